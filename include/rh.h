@@ -1,0 +1,168 @@
+/*
+ * rh.h - reduced Hessians of the power-flow balance equations on MI355X.
+ *
+ * C ABI of librh.  The operations follow the paper "Batched Second-Order
+ * Adjoint Sensitivity for Reduced Space Methods":
+ *   - the network and its balance equations g(x, p) = 0 (Sec. 3.1,
+ *     eq. (powerflow), eq. (powerflowvec));
+ *   - Newton-Raphson projection onto g = 0 (Sec. 3.2);
+ *   - the reduced gradient by the first-order adjoint (Sec. 3.3,
+ *     eq. (lagrangian), eq. (reduced_gradient));
+ *   - reduced-Hessian-vector products by the batched adjoint-adjoint
+ *     reduction (Sec. 4.1 eq. (socadjoint), eq. (hessvecprod); Sec. 4.3
+ *     Algorithm 2), and the full reduced Hessian assembled by blocks of
+ *     directions (Sec. 5.3).
+ *
+ * Conventions (all entry points):
+ *   - Every function returns an rh_status; nothing else crosses the ABI
+ *     (no exceptions, no aborts).  rh_last_error() returns a message for the
+ *     most recent failure on the calling thread.
+ *   - Host matrices are column-major; a block of k directions W is n_p x k
+ *     with leading dimension ldw >= n_p, and so is its product HW.
+ *   - The caller owns every buffer it passes.  rh_network_create copies the
+ *     description; handles returned through `out` are owned by the library
+ *     and released with the matching destroy call.
+ *   - A network handle is not re-entrant: calls on one handle must not
+ *     overlap.  Distinct handles may be used from different threads.
+ *   - State and parameter orderings (eq. (powerflowvec), parameter count of
+ *     Table 1):
+ *       x = [theta at PV buses; theta at PQ buses; v at PQ buses]
+ *       p = [Pg at PV buses; v at the reference bus; v at PV buses]
+ *     each block in ascending bus id.  rh_network_index_maps exports them.
+ *   - Units are per-unit.  The cost is f = sum over generators of
+ *     c2 Pg^2 + c1 Pg + c0, the reference generator's Pg being its bus
+ *     balance P^inj_ref + Pd_ref (the paper leaves f unspecified beyond its
+ *     dependence on the generation).
+ */
+#ifndef RH_H
+#define RH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rh_context rh_context; /* opaque; one per GPU (or host-only) */
+typedef struct rh_network rh_network; /* opaque; one network + operating point */
+
+typedef enum {
+  RH_OK = 0,
+  RH_EINVAL = -1,    /* bad argument or network description (incl. NaN/Inf) */
+  RH_ENOMEM = -2,    /* host or device allocation failed */
+  RH_ENOCONV = -3,   /* Newton did not reach the tolerance */
+  RH_ESINGULAR = -4, /* G_x is singular or numerically so (tiny pivot) */
+  RH_ESTATE = -5,    /* call out of order, e.g. a product before a solve */
+  RH_EDEVICE = -6,   /* HIP error, or a device call on a host-only context */
+  RH_EBUSY = -7      /* reserved for callers that share a handle */
+} rh_status;
+
+typedef enum {
+  RH_FP64 = 0,        /* every step in FP64 */
+  RH_FP32_REFINED = 1 /* reserved: FP32 sweeps with FP64 residual refinement */
+} rh_precision;
+
+/* Network description (Sec. 3.1).  All arrays are read-only and copied.
+ * Branch b joins br_from[b] and br_to[b] (0-based, distinct) with series
+ * impedance br_r + j br_x and total line charging br_b, half at each end.
+ * bus_type: 1 = PQ, 2 = PV, 3 = reference (exactly one).  gen_bus lists one
+ * generator per PV bus and one at the reference bus (no other buses);
+ * Pg is its active set-point (ignored for the reference generator), Vg its
+ * voltage set-point, c2/c1/c0 its cost coefficients. */
+typedef struct {
+  int32_t n_bus, n_branch, n_gen;
+  const int32_t *br_from, *br_to;
+  const double *br_r, *br_x, *br_b;
+  const int32_t *bus_type;
+  const double *Pd, *Qd;
+  const int32_t *gen_bus;
+  const double *Pg, *Vg, *c2, *c1, *c0;
+} rh_network_desc;
+
+/* Figures of the last solve and the last Hessian call on a network. */
+typedef struct {
+  int32_t n_x, n_p;
+  int64_t nnz_gx, nnz_l, nnz_u; /* G_x and its LU factors (unit diagonal of L not stored) */
+  int32_t levels_l, levels_u;   /* dependency depth of the L and U sweeps */
+  int32_t newton_iters;
+  double newton_resid;          /* ||g||_inf at the accepted state */
+  int32_t last_k;               /* directions in the last product call */
+  int32_t last_launches;        /* kernel launches since the previous report */
+  int32_t dirs_per_group;       /* directions owned by one workgroup (last launch) */
+  double last_kernel_ms;        /* summed duration of those launches when timing was
+                                   on (HIP events on the launch stream), else -1 */
+} rh_report;
+
+/* Create a context on HIP device `device`; device = -1 gives a host-only
+ * context (network set-up, Newton and gradients work; products return
+ * RH_EDEVICE). */
+rh_status rh_context_create(int32_t device, rh_context **out);
+rh_status rh_context_destroy(rh_context *ctx);
+/* Record HIP events around every kernel launch (for rh_report.last_kernel_ms). */
+rh_status rh_context_set_timing(rh_context *ctx, int32_t on);
+
+/* Validate and copy a network; builds the index maps, the sparsity pattern of
+ * G_x, a fill-reducing ordering, the symbolic LU and the level schedules.
+ * The parameters start at the description's set-points. */
+rh_status rh_network_create(rh_context *ctx, const rh_network_desc *desc, rh_network **out);
+rh_status rh_network_destroy(rh_network *net);
+rh_status rh_network_dims(const rh_network *net, int32_t *n_x, int32_t *n_p);
+/* x_bus[n_x], x_kind[n_x], p_bus[n_p], p_kind[n_p]; kind 0 = angle,
+ * 1 = voltage magnitude, 2 = generator active power.  Any pointer may be NULL. */
+rh_status rh_network_index_maps(const rh_network *net, int32_t *x_bus, int32_t *x_kind,
+                                int32_t *p_bus, int32_t *p_kind);
+
+/* Replace p (n_p values) or the loads (n_bus values each).  Both invalidate
+ * the solution: products and gradients return RH_ESTATE until the next
+ * successful rh_solve_powerflow. */
+rh_status rh_set_parameters(rh_network *net, const double *p);
+rh_status rh_get_parameters(const rh_network *net, double *p);
+rh_status rh_set_loads(rh_network *net, const double *Pd, const double *Qd);
+
+/* Starting point of the next Newton solve: x0 (n_x values, the state
+ * ordering), or NULL for a flat start (angles 0, PQ magnitudes 1).  Kept until
+ * replaced; a good guess is the previous operating point's state. */
+rh_status rh_set_initial_state(rh_network *net, const double *x0);
+
+/* Newton-Raphson from the initial state (flat start by default) until
+ * ||g||_inf <= tol or max_iter steps (Sec. 3.2).  On success it factorises
+ * G_x, forms the first-order adjoint and the per-branch second-order
+ * coefficients, and (on a device context) uploads them.  iters/resid_inf may
+ * be NULL.  Returns RH_ENOCONV or RH_ESINGULAR on failure. */
+rh_status rh_solve_powerflow(rh_network *net, double tol, int32_t max_iter, int32_t *iters,
+                             double *resid_inf);
+/* Converged state x (n_x), objective F(p) = f(x(p), p), reduced gradient (n_p). */
+rh_status rh_get_state(const rh_network *net, double *x);
+rh_status rh_objective(const rh_network *net, double *F);
+rh_status rh_reduced_gradient(rh_network *net, double *grad);
+
+/* k reduced-Hessian-vector products HW = (d2 F) W, host buffers (Algorithm 2:
+ * SpMul, batched sparse solve, batched tensor projection, transposed batched
+ * solve, SpMulAdd).  Synchronous. */
+rh_status rh_hvp(rh_network *net, int32_t k, const double *W, int64_t ldw, double *HW,
+                 int64_t ldhw, rh_precision prec);
+/* As rh_hvp on device buffers (FP64, column-major), enqueued on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  Asynchronous: the buffers must
+ * stay valid until the stream reaches this work. */
+rh_status rh_hvp_device(rh_network *net, int32_t k, const void *dW, int64_t ldw, void *dHW,
+                        int64_t ldhw, rh_precision prec, void *hip_stream);
+/* The dense reduced Hessian H (n_p x n_p, column-major, ldh >= n_p), computed
+ * in ceil(n_p / k_block) blocks of identity columns (Sec. 5.3);
+ * k_block = 0 picks the block size.  Host output, synchronous. */
+rh_status rh_reduced_hessian(rh_network *net, double *H, int64_t ldh, int32_t k_block,
+                             rh_precision prec);
+/* As rh_reduced_hessian into a device buffer, enqueued on `hip_stream`. */
+rh_status rh_reduced_hessian_device(rh_network *net, void *dH, int64_t ldh, int32_t k_block,
+                                    rh_precision prec, void *hip_stream);
+
+/* Figures of the network; waits for the timed launches since the previous
+ * report, sums their durations, then starts a new timing window. */
+rh_status rh_last_report(const rh_network *net, rh_report *out);
+const char *rh_status_string(rh_status s);
+const char *rh_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RH_H */

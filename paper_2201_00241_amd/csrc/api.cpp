@@ -1,0 +1,358 @@
+// C ABI entry points of librh (declared in include/rh.h).
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+
+#include "rh_internal.h"
+
+using namespace rh;
+
+namespace {
+
+thread_local std::string g_err;
+
+rh_status fail(rh_status s, const std::string &msg) {
+  g_err = msg;
+  return s;
+}
+
+#define GUARD_BEGIN try {
+#define GUARD_END                                             \
+  }                                                           \
+  catch (const std::bad_alloc &) {                            \
+    return fail(RH_ENOMEM, "host allocation failed");         \
+  }                                                           \
+  catch (const std::exception &ex) {                          \
+    return fail(RH_EINVAL, std::string("exception: ") + ex.what()); \
+  }                                                           \
+  catch (...) {                                               \
+    return fail(RH_EINVAL, "unknown exception");              \
+  }
+
+bool finite_n(const double *a, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+rh_status need_solved(const rh_network *net) {
+  if (!net) return fail(RH_EINVAL, "null network");
+  if (!net->n.solved) return fail(RH_ESTATE, "no converged power flow for the current parameters");
+  return RH_OK;
+}
+
+rh_status need_device(rh_network *net) {
+  if (net->n.ctx->device < 0) return fail(RH_EDEVICE, "host-only context");
+  return RH_OK;
+}
+
+void invalidate(Network &n) {
+  n.solved = false;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *rh_status_string(rh_status s) {
+  switch (s) {
+    case RH_OK: return "ok";
+    case RH_EINVAL: return "invalid argument";
+    case RH_ENOMEM: return "out of memory";
+    case RH_ENOCONV: return "Newton did not converge";
+    case RH_ESINGULAR: return "singular Jacobian";
+    case RH_ESTATE: return "call out of order";
+    case RH_EDEVICE: return "device error";
+    case RH_EBUSY: return "busy";
+  }
+  return "unknown status";
+}
+
+const char *rh_last_error(void) { return g_err.c_str(); }
+
+rh_status rh_context_create(int32_t device, rh_context **out) {
+  GUARD_BEGIN
+  if (!out) return fail(RH_EINVAL, "null out");
+  *out = nullptr;
+  if (device < -1) return fail(RH_EINVAL, "device must be >= -1");
+  if (device >= 0) {
+    std::string err;
+    rh_status s = device_set(device, err);
+    if (s != RH_OK) return fail(s, err);
+  }
+  rh_context *c = new rh_context();
+  c->c.device = device;
+  *out = c;
+  return RH_OK;
+  GUARD_END
+}
+
+rh_status rh_context_destroy(rh_context *ctx) {
+  delete ctx;
+  return RH_OK;
+}
+
+rh_status rh_context_set_timing(rh_context *ctx, int32_t on) {
+  if (!ctx) return fail(RH_EINVAL, "null context");
+  ctx->c.timing = on != 0;
+  return RH_OK;
+}
+
+rh_status rh_network_create(rh_context *ctx, const rh_network_desc *desc, rh_network **out) {
+  GUARD_BEGIN
+  if (!ctx || !desc || !out) return fail(RH_EINVAL, "null argument");
+  *out = nullptr;
+  rh_network *net = new rh_network();
+  net->n.ctx = &ctx->c;
+  std::string err;
+  rh_status s = network_build(net->n, *desc, err);
+  if (s != RH_OK) {
+    delete net;
+    return fail(s, err);
+  }
+  net->n.report.last_kernel_ms = -1.0;
+  *out = net;
+  return RH_OK;
+  GUARD_END
+}
+
+rh_status rh_network_destroy(rh_network *net) {
+  if (!net) return RH_OK;
+  device_free(net->n);
+  delete net;
+  return RH_OK;
+}
+
+rh_status rh_network_dims(const rh_network *net, int32_t *n_x, int32_t *n_p) {
+  if (!net) return fail(RH_EINVAL, "null network");
+  if (n_x) *n_x = net->n.n_x;
+  if (n_p) *n_p = net->n.n_p;
+  return RH_OK;
+}
+
+rh_status rh_network_index_maps(const rh_network *net, int32_t *x_bus, int32_t *x_kind,
+                                int32_t *p_bus, int32_t *p_kind) {
+  if (!net) return fail(RH_EINVAL, "null network");
+  const Network &n = net->n;
+  for (int32_t b = 0; b < n.n_bus; ++b) {
+    if (n.th_x[b] >= 0) {
+      if (x_bus) x_bus[n.th_x[b]] = b;
+      if (x_kind) x_kind[n.th_x[b]] = 0;
+    }
+    if (n.v_x[b] >= 0) {
+      if (x_bus) x_bus[n.v_x[b]] = b;
+      if (x_kind) x_kind[n.v_x[b]] = 1;
+    }
+    if (n.v_p[b] >= 0) {
+      if (p_bus) p_bus[n.v_p[b]] = b;
+      if (p_kind) p_kind[n.v_p[b]] = 1;
+    }
+    if (n.pg_p[b] >= 0) {
+      if (p_bus) p_bus[n.pg_p[b]] = b;
+      if (p_kind) p_kind[n.pg_p[b]] = 2;
+    }
+  }
+  return RH_OK;
+}
+
+rh_status rh_set_parameters(rh_network *net, const double *p) {
+  if (!net || !p) return fail(RH_EINVAL, "null argument");
+  if (!finite_n(p, net->n.n_p)) return fail(RH_EINVAL, "NaN or Inf in parameters");
+  net->n.p.assign(p, p + net->n.n_p);
+  invalidate(net->n);
+  return RH_OK;
+}
+
+rh_status rh_get_parameters(const rh_network *net, double *p) {
+  if (!net || !p) return fail(RH_EINVAL, "null argument");
+  std::memcpy(p, net->n.p.data(), sizeof(double) * net->n.n_p);
+  return RH_OK;
+}
+
+rh_status rh_set_loads(rh_network *net, const double *Pd, const double *Qd) {
+  if (!net || !Pd || !Qd) return fail(RH_EINVAL, "null argument");
+  if (!finite_n(Pd, net->n.n_bus) || !finite_n(Qd, net->n.n_bus))
+    return fail(RH_EINVAL, "NaN or Inf in loads");
+  net->n.Pd.assign(Pd, Pd + net->n.n_bus);
+  net->n.Qd.assign(Qd, Qd + net->n.n_bus);
+  invalidate(net->n);
+  return RH_OK;
+}
+
+rh_status rh_set_initial_state(rh_network *net, const double *x0) {
+  if (!net) return fail(RH_EINVAL, "null network");
+  if (!x0) {
+    net->n.x0.clear();
+    return RH_OK;
+  }
+  if (!finite_n(x0, net->n.n_x)) return fail(RH_EINVAL, "NaN or Inf in initial state");
+  net->n.x0.assign(x0, x0 + net->n.n_x);
+  return RH_OK;
+}
+
+rh_status rh_solve_powerflow(rh_network *net, double tol, int32_t max_iter, int32_t *iters,
+                             double *resid_inf) {
+  GUARD_BEGIN
+  if (!net) return fail(RH_EINVAL, "null network");
+  std::string err;
+  rh_status s = network_solve(net->n, tol, max_iter, err);
+  if (iters) *iters = net->n.newton_iters;
+  if (resid_inf) *resid_inf = net->n.newton_resid;
+  if (s != RH_OK) return fail(s, err);
+  if (net->n.ctx->device >= 0) {
+    s = device_upload(net->n, err);
+    if (s != RH_OK) {
+      net->n.solved = false;
+      return fail(s, err);
+    }
+  }
+  return RH_OK;
+  GUARD_END
+}
+
+rh_status rh_get_state(const rh_network *net, double *x) {
+  rh_status s = need_solved(net);
+  if (s != RH_OK) return s;
+  if (!x) return fail(RH_EINVAL, "null x");
+  std::memcpy(x, net->n.x.data(), sizeof(double) * net->n.n_x);
+  return RH_OK;
+}
+
+rh_status rh_objective(const rh_network *net, double *F) {
+  rh_status s = need_solved(net);
+  if (s != RH_OK) return s;
+  if (!F) return fail(RH_EINVAL, "null F");
+  *F = net->n.objective;
+  return RH_OK;
+}
+
+rh_status rh_reduced_gradient(rh_network *net, double *grad) {
+  GUARD_BEGIN
+  rh_status s = need_solved(net);
+  if (s != RH_OK) return s;
+  if (!grad) return fail(RH_EINVAL, "null grad");
+  std::vector<double> g;
+  reduced_gradient(net->n, g);
+  std::memcpy(grad, g.data(), sizeof(double) * net->n.n_p);
+  return RH_OK;
+  GUARD_END
+}
+
+rh_status rh_hvp_device(rh_network *net, int32_t k, const void *dW, int64_t ldw, void *dHW,
+                        int64_t ldhw, rh_precision prec, void *hip_stream) {
+  GUARD_BEGIN
+  rh_status s = need_solved(net);
+  if (s != RH_OK) return s;
+  if ((s = need_device(net)) != RH_OK) return s;
+  if (prec != RH_FP64) return fail(RH_EINVAL, "only RH_FP64 is available");
+  if (k < 0 || !dW || !dHW || ldw < net->n.n_p || ldhw < net->n.n_p)
+    return fail(RH_EINVAL, "bad product arguments");
+  net->n.report.last_k = k;
+  if (k == 0) return RH_OK;
+  std::string err;
+  s = device_hvp(net->n, k, static_cast<const double *>(dW), ldw, static_cast<double *>(dHW), ldhw,
+                 -1, hip_stream, err);
+  if (s != RH_OK) return fail(s, err);
+  return RH_OK;
+  GUARD_END
+}
+
+rh_status rh_reduced_hessian_device(rh_network *net, void *dH, int64_t ldh, int32_t k_block,
+                                    rh_precision prec, void *hip_stream) {
+  GUARD_BEGIN
+  rh_status s = need_solved(net);
+  if (s != RH_OK) return s;
+  if ((s = need_device(net)) != RH_OK) return s;
+  if (prec != RH_FP64) return fail(RH_EINVAL, "only RH_FP64 is available");
+  const int32_t n_p = net->n.n_p;
+  if (!dH || ldh < n_p || k_block < 0) return fail(RH_EINVAL, "bad Hessian arguments");
+  const int32_t k = (k_block == 0 || k_block > n_p) ? n_p : k_block;
+  net->n.report.last_k = n_p;
+  std::string err;
+  double *H = static_cast<double *>(dH);
+  for (int32_t j0 = 0; j0 < n_p; j0 += k) {
+    const int32_t kb = std::min(k, n_p - j0);
+    s = device_hvp(net->n, kb, nullptr, 0, H + (int64_t)j0 * ldh, ldh, j0, hip_stream, err);
+    if (s != RH_OK) return fail(s, err);
+  }
+  return RH_OK;
+  GUARD_END
+}
+
+rh_status rh_hvp(rh_network *net, int32_t k, const double *W, int64_t ldw, double *HW, int64_t ldhw,
+                 rh_precision prec) {
+  GUARD_BEGIN
+  rh_status s = need_solved(net);
+  if (s != RH_OK) return s;
+  if ((s = need_device(net)) != RH_OK) return s;
+  const int32_t n_p = net->n.n_p;
+  if (k < 0 || !W || !HW || ldw < n_p || ldhw < n_p) return fail(RH_EINVAL, "bad product arguments");
+  if (k == 0) return RH_OK;
+  for (int32_t j = 0; j < k; ++j)
+    if (!finite_n(W + (int64_t)j * ldw, n_p)) return fail(RH_EINVAL, "NaN or Inf in W");
+  std::string err;
+  void *dW = nullptr, *dHW = nullptr;
+  const size_t bytes = sizeof(double) * (size_t)n_p * k;
+  if ((s = device_alloc(&dW, bytes, err)) != RH_OK) return fail(s, err);
+  if ((s = device_alloc(&dHW, bytes, err)) != RH_OK) {
+    device_release(dW);
+    return fail(s, err);
+  }
+  s = device_memcpy_2d(dW, sizeof(double) * n_p, W, sizeof(double) * ldw, sizeof(double) * n_p, k, 1,
+                       err);
+  if (s == RH_OK) {
+    s = rh_hvp_device(net, k, dW, n_p, dHW, n_p, prec, nullptr);
+    if (s != RH_OK) err = g_err;
+  }
+  if (s == RH_OK) s = device_sync(nullptr, err);
+  if (s == RH_OK)
+    s = device_memcpy_2d(HW, sizeof(double) * ldhw, dHW, sizeof(double) * n_p, sizeof(double) * n_p,
+                         k, 0, err);
+  device_release(dW);
+  device_release(dHW);
+  if (s != RH_OK) return fail(s, err);
+  return RH_OK;
+  GUARD_END
+}
+
+rh_status rh_reduced_hessian(rh_network *net, double *H, int64_t ldh, int32_t k_block,
+                             rh_precision prec) {
+  GUARD_BEGIN
+  rh_status s = need_solved(net);
+  if (s != RH_OK) return s;
+  if ((s = need_device(net)) != RH_OK) return s;
+  const int32_t n_p = net->n.n_p;
+  if (!H || ldh < n_p) return fail(RH_EINVAL, "bad Hessian arguments");
+  std::string err;
+  void *dH = nullptr;
+  if ((s = device_alloc(&dH, sizeof(double) * (size_t)n_p * n_p, err)) != RH_OK) return fail(s, err);
+  s = rh_reduced_hessian_device(net, dH, n_p, k_block, prec, nullptr);
+  if (s != RH_OK) err = g_err;
+  if (s == RH_OK) s = device_sync(nullptr, err);
+  if (s == RH_OK)
+    s = device_memcpy_2d(H, sizeof(double) * ldh, dH, sizeof(double) * n_p, sizeof(double) * n_p,
+                         n_p, 0, err);
+  device_release(dH);
+  if (s != RH_OK) return fail(s, err);
+  return RH_OK;
+  GUARD_END
+}
+
+rh_status rh_last_report(const rh_network *net, rh_report *out) {
+  if (!net || !out) return fail(RH_EINVAL, "null argument");
+  rh_network *mnet = const_cast<rh_network *>(net);
+  std::string err;
+  double ms = -1.0;
+  if (mnet->n.ctx->device >= 0) {
+    rh_status s = device_kernel_ms(mnet->n, &ms, err);
+    if (s != RH_OK) return fail(s, err);
+  }
+  mnet->n.report.last_kernel_ms = ms;
+  *out = net->n.report;
+  device_take_timing(mnet->n);
+  return RH_OK;
+}
+
+}  // extern "C"

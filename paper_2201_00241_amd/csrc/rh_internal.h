@@ -1,0 +1,138 @@
+// Internal structures of librh (host planner + device path).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/rh.h"
+
+namespace rh {
+
+enum BusType : int32_t { kPQ = 1, kPV = 2, kRef = 3 };
+
+// Row-compressed sparse matrix (ascending columns within each row).
+struct Csr {
+  int32_t n_rows = 0, n_cols = 0;
+  std::vector<int32_t> ptr, col;
+  std::vector<double> val;
+  int64_t nnz() const { return static_cast<int64_t>(col.size()); }
+};
+
+// One triangular sweep, rows grouped by dependency level.  Entry `pos` of the
+// level-ordered arrays is matrix row rows[pos]; its off-diagonal entries are
+// col/val[ptr[pos] .. ptr[pos+1]); dinv[pos] is the reciprocal pivot (empty for
+// unit-diagonal factors).
+struct Sweep {
+  std::vector<int32_t> lev_ptr, rows, ptr, col;
+  std::vector<double> val, dinv;
+  int32_t n_levels() const { return static_cast<int32_t>(lev_ptr.size()) - 1; }
+};
+
+// Fixed-pattern LU of a structurally symmetric matrix, P A P^T = L U, with a
+// fill-reducing symmetric ordering and diagonal pivots.
+struct LuPlan {
+  int32_t n = 0;
+  std::vector<int32_t> perm;   // perm[k] = original index eliminated k-th
+  std::vector<int32_t> iperm;  // iperm[perm[k]] = k
+  // Patterns in permuted numbering, ascending.
+  std::vector<std::vector<int32_t>> lrow;  // strictly lower part of row i
+  std::vector<std::vector<int32_t>> urow;  // upper part of row i, diagonal first
+  // Values, aligned with the patterns.
+  std::vector<std::vector<double>> lval, uval;
+  int64_t nnz_l = 0, nnz_u = 0;
+  std::vector<int32_t> level_l, level_u;
+  int32_t n_levels_l = 0, n_levels_u = 0;
+};
+
+struct DeviceNet;  // defined by the device translation unit
+
+struct Context {
+  int32_t device = -1;  // -1: host only
+  bool timing = false;
+};
+
+// Per-bus-incidence coefficients of the branch-wise Lagrangian Hessian.
+struct Tape {
+  // incidence list by bus: branches touching bus e, other end o
+  std::vector<int32_t> inc_ptr, inc_other;
+  std::vector<double> inc_K, inc_Hps, inc_H, inc_A2, inc_vo;
+  std::vector<double> bus_v, bus_sth, bus_sv;  // voltage, slack-term coefficients
+  std::vector<int32_t> slack_bus;              // buses with a nonzero slack coefficient
+  std::vector<double> slack_gth, slack_gv;     // d P_ref / d theta_b, d v_b
+  double slack_c2x2 = 0.0;                     // 2 c2 of the reference generator
+};
+
+struct Network {
+  Context *ctx = nullptr;
+  // ---- description (copied)
+  int32_t n_bus = 0, n_br = 0, n_gen = 0;
+  std::vector<int32_t> br_f, br_t, bus_type, gen_bus;
+  std::vector<double> br_r, br_x, br_b, Pd, Qd, Pg, Vg, c2, c1, c0;
+  // ---- per-branch series admittance and shunt
+  std::vector<double> gs, bs, bsh;  // g_s, b_s, b_c / 2
+  // ---- bookkeeping (eq. (powerflowvec), Table 1 counts)
+  int32_t ref = -1, n_pv = 0, n_pq = 0, n_x = 0, n_p = 0;
+  std::vector<int32_t> pv, pq;           // ascending bus ids
+  std::vector<int32_t> gen_of_bus;       // -1 if none
+  std::vector<int32_t> th_x, v_x, v_p;   // bus -> x index of theta / v, p index of v (-1 none)
+  std::vector<int32_t> pg_p;             // bus -> p index of Pg (-1 none)
+  // ---- Jacobian patterns (original numbering) and scatter maps
+  Csr gx;                                 // G_x pattern/values, rows = x order
+  Csr gp;                                 // G_p, n_x x n_p
+  std::vector<int64_t> gx_slot, gp_slot;  // branch-gradient slot -> value position (-1: none)
+  bool islanded = false;                  // some bus is not connected to the reference
+  // ---- factorisation
+  LuPlan lu;
+  // ---- state
+  std::vector<double> p, x, lam;
+  std::vector<double> x0;  // Newton start (empty: flat start)
+  bool solved = false;
+  int32_t newton_iters = 0;
+  double newton_resid = 0.0;
+  double objective = 0.0;
+  Tape tape;
+  rh_report report{};
+  DeviceNet *dev = nullptr;
+};
+
+// ---- host planner (network.cpp)
+rh_status network_build(Network &net, const rh_network_desc &d, std::string &err);
+rh_status network_solve(Network &net, double tol, int32_t max_iter, std::string &err);
+void flows_inject(const Network &net, const std::vector<double> &th, const std::vector<double> &v,
+                  std::vector<double> &P, std::vector<double> &Q);
+void unpack_state(const Network &net, const std::vector<double> &x, const std::vector<double> &p,
+                  std::vector<double> &th, std::vector<double> &v);
+void reduced_gradient(const Network &net, std::vector<double> &grad);
+
+// ---- sparse LU (sparse_lu.cpp)
+void lu_analyse(LuPlan &lu, const Csr &pattern);
+bool lu_factor(LuPlan &lu, const Csr &a, std::string &err);
+void lu_solve(const LuPlan &lu, std::vector<double> &b);        // A x = b in place
+void lu_solve_t(const LuPlan &lu, std::vector<double> &b);      // A^T x = b in place
+void lu_sweeps(const LuPlan &lu, Sweep &sl, Sweep &su, Sweep &sut, Sweep &slt);
+
+// ---- device path (device.hip)
+rh_status device_upload(Network &net, std::string &err);
+void device_free(Network &net);
+void device_take_timing(Network &net);  // forget recorded launches
+rh_status device_kernel_ms(Network &net, double *ms, std::string &err);
+rh_status device_hvp(Network &net, int32_t k, const double *dW, int64_t ldw, double *dHW,
+                     int64_t ldhw, int32_t identity_from, void *stream, std::string &err);
+rh_status device_set(int32_t device, std::string &err);
+rh_status device_memcpy_h2d(void *dst, const void *src, size_t bytes, std::string &err);
+rh_status device_memcpy_d2h(void *dst, const void *src, size_t bytes, std::string &err);
+rh_status device_memcpy_2d(void *dst, size_t dpitch, const void *src, size_t spitch,
+                           size_t width, size_t rows, int to_device, std::string &err);
+rh_status device_alloc(void **p, size_t bytes, std::string &err);
+void device_release(void *p);
+rh_status device_sync(void *stream, std::string &err);
+
+}  // namespace rh
+
+struct rh_context {
+  rh::Context c;
+};
+struct rh_network {
+  rh::Network n;
+};

@@ -1,0 +1,271 @@
+// Fixed-pattern sparse LU of G_x with a symmetric fill-reducing ordering.
+//
+// The paper factorises G_x once on the host and re-uses the pattern for every
+// refactorisation and for the batched forward/backward solves (Sec. 5.2).
+// Here the host computes a minimum-degree ordering on the (structurally
+// symmetric) pattern of G_x, the symbolic factor by simulating the
+// elimination, and the numeric factor P A P^T = L U row by row with diagonal
+// pivots (the power-flow Jacobian has a dominant diagonal in the natural
+// pairing of angle/active-power and magnitude/reactive-power).  Rows of the
+// triangular factors are then grouped into dependency levels for the device
+// sweeps.
+#include <algorithm>
+#include <cmath>
+#include <queue>
+
+#include "rh_internal.h"
+
+namespace rh {
+
+void lu_analyse(LuPlan &lu, const Csr &pat) {
+  const int32_t n = pat.n_rows;
+  lu.n = n;
+  // adjacency of the symmetric pattern, without the diagonal
+  std::vector<std::vector<int32_t>> adj(n);
+  for (int32_t r = 0; r < n; ++r)
+    for (int32_t e = pat.ptr[r]; e < pat.ptr[r + 1]; ++e) {
+      const int32_t c = pat.col[e];
+      if (c != r) {
+        adj[r].push_back(c);
+        adj[c].push_back(r);
+      }
+    }
+  std::vector<int32_t> mark(n, -1);
+  for (int32_t r = 0; r < n; ++r) {
+    auto &a = adj[r];
+    std::sort(a.begin(), a.end());
+    a.erase(std::unique(a.begin(), a.end()), a.end());
+  }
+  // minimum degree by explicit elimination-graph updates (ties: lower index)
+  using Item = std::pair<int32_t, int32_t>;
+  std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
+  for (int32_t r = 0; r < n; ++r) heap.push({(int32_t)adj[r].size(), r});
+  std::vector<char> gone(n, 0);
+  std::vector<std::vector<int32_t>> nbrs(n);  // eliminated k-th: its neighbours
+  lu.perm.assign(n, -1);
+  lu.iperm.assign(n, -1);
+  std::vector<int32_t> merged;
+  for (int32_t k = 0; k < n; ++k) {
+    int32_t v;
+    for (;;) {
+      const Item it = heap.top();
+      heap.pop();
+      if (!gone[it.second] && (int32_t)adj[it.second].size() == it.first) {
+        v = it.second;
+        break;
+      }
+    }
+    gone[v] = 1;
+    lu.perm[k] = v;
+    lu.iperm[v] = k;
+    const std::vector<int32_t> nb = adj[v];
+    nbrs[k] = nb;
+    for (int32_t u : nb) {
+      // adj[u] <- adj[u] \ {v}  union  nb \ {u}
+      merged.clear();
+      for (int32_t w : adj[u])
+        if (w != v && mark[w] != u) {
+          mark[w] = u;
+          merged.push_back(w);
+        }
+      for (int32_t w : nb)
+        if (w != u && mark[w] != u) {
+          mark[w] = u;
+          merged.push_back(w);
+        }
+      for (int32_t w : merged) mark[w] = -1;
+      adj[u].assign(merged.begin(), merged.end());
+      heap.push({(int32_t)adj[u].size(), u});
+    }
+    adj[v].clear();
+    adj[v].shrink_to_fit();
+  }
+  // symbolic factor in permuted numbering
+  lu.urow.assign(n, {});
+  lu.lrow.assign(n, {});
+  lu.nnz_l = lu.nnz_u = 0;
+  for (int32_t k = 0; k < n; ++k) {
+    auto &u = lu.urow[k];
+    u.reserve(nbrs[k].size() + 1);
+    u.push_back(k);
+    std::vector<int32_t> cols;
+    cols.reserve(nbrs[k].size());
+    for (int32_t w : nbrs[k]) cols.push_back(lu.iperm[w]);
+    std::sort(cols.begin(), cols.end());
+    u.insert(u.end(), cols.begin(), cols.end());
+    for (int32_t c : cols) lu.lrow[c].push_back(k);  // ascending k
+    lu.nnz_u += (int64_t)u.size();
+    lu.nnz_l += (int64_t)cols.size();
+  }
+  lu.lval.assign(n, {});
+  lu.uval.assign(n, {});
+  for (int32_t i = 0; i < n; ++i) {
+    lu.lval[i].assign(lu.lrow[i].size(), 0.0);
+    lu.uval[i].assign(lu.urow[i].size(), 0.0);
+  }
+  // dependency levels: forward sweeps (L, U^T) and backward sweeps (U, L^T)
+  lu.level_l.assign(n, 0);
+  lu.n_levels_l = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    int32_t lv = 0;
+    for (int32_t k : lu.lrow[i]) lv = std::max(lv, lu.level_l[k] + 1);
+    lu.level_l[i] = lv;
+    lu.n_levels_l = std::max(lu.n_levels_l, lv + 1);
+  }
+  lu.level_u.assign(n, 0);
+  lu.n_levels_u = 0;
+  for (int32_t i = n - 1; i >= 0; --i) {
+    int32_t lv = 0;
+    for (size_t q = 1; q < lu.urow[i].size(); ++q) lv = std::max(lv, lu.level_u[lu.urow[i][q]] + 1);
+    lu.level_u[i] = lv;
+    lu.n_levels_u = std::max(lu.n_levels_u, lv + 1);
+  }
+}
+
+bool lu_factor(LuPlan &lu, const Csr &a, std::string &err) {
+  const int32_t n = lu.n;
+  std::vector<double> w(n, 0.0);
+  for (int32_t i = 0; i < n; ++i) {
+    const int32_t r = lu.perm[i];
+    double rowmax = 0.0;
+    for (int32_t e = a.ptr[r]; e < a.ptr[r + 1]; ++e) {
+      w[lu.iperm[a.col[e]]] = a.val[e];
+      rowmax = std::max(rowmax, std::fabs(a.val[e]));
+    }
+    const auto &lr = lu.lrow[i];
+    auto &lv = lu.lval[i];
+    for (size_t q = 0; q < lr.size(); ++q) {
+      const int32_t k = lr[q];
+      const double l = w[k] / lu.uval[k][0];
+      lv[q] = l;
+      w[k] = 0.0;
+      const auto &ur = lu.urow[k];
+      const auto &uv = lu.uval[k];
+      for (size_t s = 1; s < ur.size(); ++s) w[ur[s]] -= l * uv[s];
+    }
+    const auto &ur = lu.urow[i];
+    auto &uv = lu.uval[i];
+    for (size_t s = 0; s < ur.size(); ++s) {
+      uv[s] = w[ur[s]];
+      w[ur[s]] = 0.0;
+    }
+    if (!std::isfinite(uv[0]) || std::fabs(uv[0]) <= 1e-13 * rowmax || rowmax == 0.0) {
+      err = "G_x is singular to working precision (pivot " + std::to_string(i) + ")";
+      return false;
+    }
+  }
+  return true;
+}
+
+void lu_solve(const LuPlan &lu, std::vector<double> &b) {
+  const int32_t n = lu.n;
+  std::vector<double> y(n);
+  for (int32_t i = 0; i < n; ++i) y[i] = b[lu.perm[i]];
+  for (int32_t i = 0; i < n; ++i) {
+    double s = y[i];
+    const auto &lr = lu.lrow[i];
+    const auto &lv = lu.lval[i];
+    for (size_t q = 0; q < lr.size(); ++q) s -= lv[q] * y[lr[q]];
+    y[i] = s;
+  }
+  for (int32_t i = n - 1; i >= 0; --i) {
+    const auto &ur = lu.urow[i];
+    const auto &uv = lu.uval[i];
+    double s = y[i];
+    for (size_t q = 1; q < ur.size(); ++q) s -= uv[q] * y[ur[q]];
+    y[i] = s / uv[0];
+  }
+  for (int32_t i = 0; i < n; ++i) b[lu.perm[i]] = y[i];
+}
+
+void lu_solve_t(const LuPlan &lu, std::vector<double> &b) {
+  // A^T = P^T U^T L^T P
+  const int32_t n = lu.n;
+  std::vector<double> y(n);
+  for (int32_t i = 0; i < n; ++i) y[i] = b[lu.perm[i]];
+  for (int32_t k = 0; k < n; ++k) {  // U^T z = y, by columns of U^T (rows of U)
+    const auto &ur = lu.urow[k];
+    const auto &uv = lu.uval[k];
+    const double z = y[k] / uv[0];
+    y[k] = z;
+    for (size_t q = 1; q < ur.size(); ++q) y[ur[q]] -= uv[q] * z;
+  }
+  for (int32_t i = n - 1; i >= 0; --i) {  // L^T w = z, by columns of L^T (rows of L)
+    const auto &lr = lu.lrow[i];
+    const auto &lv = lu.lval[i];
+    const double z = y[i];
+    for (size_t q = 0; q < lr.size(); ++q) y[lr[q]] -= lv[q] * z;
+  }
+  for (int32_t i = 0; i < n; ++i) b[lu.perm[i]] = y[i];
+}
+
+namespace {
+
+// Group rows by level; `row_entries(i, cols, vals)` appends row i's entries.
+template <class F>
+void make_sweep(Sweep &s, int32_t n, const std::vector<int32_t> &level, int32_t n_levels,
+                F row_entries, const std::vector<double> *diag) {
+  s.lev_ptr.assign(n_levels + 1, 0);
+  for (int32_t i = 0; i < n; ++i) s.lev_ptr[level[i] + 1]++;
+  for (int32_t l = 0; l < n_levels; ++l) s.lev_ptr[l + 1] += s.lev_ptr[l];
+  s.rows.assign(n, 0);
+  std::vector<int32_t> fill(s.lev_ptr.begin(), s.lev_ptr.end() - 1);
+  for (int32_t i = 0; i < n; ++i) s.rows[fill[level[i]]++] = i;  // ascending within a level
+  s.ptr.assign(n + 1, 0);
+  s.col.clear();
+  s.val.clear();
+  s.dinv.clear();
+  for (int32_t pos = 0; pos < n; ++pos) {
+    const int32_t i = s.rows[pos];
+    row_entries(i, s.col, s.val);
+    s.ptr[pos + 1] = (int32_t)s.col.size();
+    if (diag) s.dinv.push_back(1.0 / (*diag)[i]);
+  }
+}
+
+}  // namespace
+
+void lu_sweeps(const LuPlan &lu, Sweep &sl, Sweep &su, Sweep &sut, Sweep &slt) {
+  const int32_t n = lu.n;
+  std::vector<double> d(n);
+  for (int32_t i = 0; i < n; ++i) d[i] = lu.uval[i][0];
+  // rows of U^T and L^T (the pattern is symmetric: U^T row i = L row i's columns)
+  std::vector<std::vector<int32_t>> utc(n), ltc(n);
+  std::vector<std::vector<double>> utv(n), ltv(n);
+  for (int32_t k = 0; k < n; ++k)
+    for (size_t q = 1; q < lu.urow[k].size(); ++q) {
+      utc[lu.urow[k][q]].push_back(k);
+      utv[lu.urow[k][q]].push_back(lu.uval[k][q]);
+    }
+  for (int32_t j = 0; j < n; ++j)
+    for (size_t q = 0; q < lu.lrow[j].size(); ++q) {
+      ltc[lu.lrow[j][q]].push_back(j);
+      ltv[lu.lrow[j][q]].push_back(lu.lval[j][q]);
+    }
+  make_sweep(sl, n, lu.level_l, lu.n_levels_l,
+             [&](int32_t i, std::vector<int32_t> &c, std::vector<double> &v) {
+               c.insert(c.end(), lu.lrow[i].begin(), lu.lrow[i].end());
+               v.insert(v.end(), lu.lval[i].begin(), lu.lval[i].end());
+             },
+             nullptr);
+  make_sweep(su, n, lu.level_u, lu.n_levels_u,
+             [&](int32_t i, std::vector<int32_t> &c, std::vector<double> &v) {
+               c.insert(c.end(), lu.urow[i].begin() + 1, lu.urow[i].end());
+               v.insert(v.end(), lu.uval[i].begin() + 1, lu.uval[i].end());
+             },
+             &d);
+  make_sweep(sut, n, lu.level_l, lu.n_levels_l,
+             [&](int32_t i, std::vector<int32_t> &c, std::vector<double> &v) {
+               c.insert(c.end(), utc[i].begin(), utc[i].end());
+               v.insert(v.end(), utv[i].begin(), utv[i].end());
+             },
+             &d);
+  make_sweep(slt, n, lu.level_u, lu.n_levels_u,
+             [&](int32_t i, std::vector<int32_t> &c, std::vector<double> &v) {
+               c.insert(c.end(), ltc[i].begin(), ltc[i].end());
+               v.insert(v.end(), ltv[i].begin(), ltv[i].end());
+             },
+             nullptr);
+}
+
+}  // namespace rh

@@ -1,0 +1,345 @@
+"""ctypes binding of librh (names follow include/rh.h).
+
+Argument marshalling only: every computation happens in the library.  The
+binding refuses to run without the built library (no fallback).  PyTorch is
+imported first so that the library shares PyTorch's HIP runtime (device
+pointers and streams from PyTorch are then valid in librh).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from pathlib import Path
+
+import numpy as np
+
+LIB_PATH = Path(__file__).resolve().parent / "librh.so"
+
+RH_OK, RH_EINVAL, RH_ENOMEM, RH_ENOCONV, RH_ESINGULAR, RH_ESTATE, RH_EDEVICE, RH_EBUSY = (
+    0, -1, -2, -3, -4, -5, -6, -7)
+RH_FP64, RH_FP32_REFINED = 0, 1
+
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_f64p = ctypes.POINTER(ctypes.c_double)
+
+
+class rh_network_desc(ctypes.Structure):
+    _fields_ = [
+        ("n_bus", ctypes.c_int32), ("n_branch", ctypes.c_int32), ("n_gen", ctypes.c_int32),
+        ("br_from", _i32p), ("br_to", _i32p),
+        ("br_r", _f64p), ("br_x", _f64p), ("br_b", _f64p),
+        ("bus_type", _i32p),
+        ("Pd", _f64p), ("Qd", _f64p),
+        ("gen_bus", _i32p),
+        ("Pg", _f64p), ("Vg", _f64p), ("c2", _f64p), ("c1", _f64p), ("c0", _f64p),
+    ]
+
+
+class rh_report(ctypes.Structure):
+    _fields_ = [
+        ("n_x", ctypes.c_int32), ("n_p", ctypes.c_int32),
+        ("nnz_gx", ctypes.c_int64), ("nnz_l", ctypes.c_int64), ("nnz_u", ctypes.c_int64),
+        ("levels_l", ctypes.c_int32), ("levels_u", ctypes.c_int32),
+        ("newton_iters", ctypes.c_int32),
+        ("newton_resid", ctypes.c_double),
+        ("last_k", ctypes.c_int32), ("last_launches", ctypes.c_int32),
+        ("dirs_per_group", ctypes.c_int32),
+        ("last_kernel_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class RhError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"librh status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+# symbol -> (restype, argtypes)
+_SIGS = {
+    "rh_context_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
+    "rh_context_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "rh_context_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "rh_network_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(rh_network_desc),
+                                         ctypes.POINTER(ctypes.c_void_p)]),
+    "rh_network_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "rh_network_dims": (ctypes.c_int, [ctypes.c_void_p, _i32p, _i32p]),
+    "rh_network_index_maps": (ctypes.c_int, [ctypes.c_void_p, _i32p, _i32p, _i32p, _i32p]),
+    "rh_set_parameters": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
+    "rh_get_parameters": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
+    "rh_set_loads": (ctypes.c_int, [ctypes.c_void_p, _f64p, _f64p]),
+    "rh_set_initial_state": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
+    "rh_solve_powerflow": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32,
+                                          _i32p, _f64p]),
+    "rh_get_state": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
+    "rh_objective": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
+    "rh_reduced_gradient": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
+    "rh_hvp": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _f64p, ctypes.c_int64, _f64p,
+                              ctypes.c_int64, ctypes.c_int]),
+    "rh_hvp_device": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                     ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                     ctypes.c_int, ctypes.c_void_p]),
+    "rh_reduced_hessian": (ctypes.c_int, [ctypes.c_void_p, _f64p, ctypes.c_int64,
+                                          ctypes.c_int32, ctypes.c_int]),
+    "rh_reduced_hessian_device": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
+                                                 ctypes.c_int64, ctypes.c_int32, ctypes.c_int,
+                                                 ctypes.c_void_p]),
+    "rh_last_report": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(rh_report)]),
+    "rh_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "rh_last_error": (ctypes.c_char_p, []),
+}
+
+SYMBOLS = tuple(_SIGS)
+
+
+def load(path: str | os.PathLike | None = None):
+    """Load librh (after PyTorch, so both use one HIP runtime)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (loads the HIP runtime librh links against)
+
+    p = Path(path) if path else LIB_PATH
+    if not p.exists():
+        raise RuntimeError(f"librh is not built ({p}); run __graft_entry__.build()")
+    lib = ctypes.CDLL(str(p))
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != RH_OK:
+        raise RhError(status, _lib.rh_last_error().decode())
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _p(a: np.ndarray, typ):
+    return a.ctypes.data_as(typ)
+
+
+# ---- thin wrappers with the C names -------------------------------------
+def rh_context_create(device: int) -> ctypes.c_void_p:
+    lib = load()
+    h = ctypes.c_void_p()
+    _check(lib.rh_context_create(int(device), ctypes.byref(h)))
+    return h
+
+
+def rh_context_destroy(ctx) -> None:
+    _check(load().rh_context_destroy(ctx))
+
+
+def rh_context_set_timing(ctx, on: bool) -> None:
+    _check(load().rh_context_set_timing(ctx, 1 if on else 0))
+
+
+def rh_network_create(ctx, grid):
+    """``grid`` carries the description arrays (see rh_network_desc)."""
+    lib = load()
+    keep = dict(
+        br_from=_i32(grid.br_from), br_to=_i32(grid.br_to), br_r=_f64(grid.br_r),
+        br_x=_f64(grid.br_x), br_b=_f64(grid.br_b), bus_type=_i32(grid.bus_type),
+        Pd=_f64(grid.Pd), Qd=_f64(grid.Qd), gen_bus=_i32(grid.gen_bus), Pg=_f64(grid.Pg),
+        Vg=_f64(grid.Vg), c2=_f64(grid.c2), c1=_f64(grid.c1), c0=_f64(grid.c0),
+    )
+    d = rh_network_desc()
+    d.n_bus = int(grid.n_bus)
+    d.n_branch = int(keep["br_from"].size)
+    d.n_gen = int(keep["gen_bus"].size)
+    for k, v in keep.items():
+        setattr(d, k, _p(v, _i32p if v.dtype == np.int32 else _f64p))
+    h = ctypes.c_void_p()
+    _check(lib.rh_network_create(ctx, ctypes.byref(d), ctypes.byref(h)))
+    return h
+
+
+def rh_network_destroy(net) -> None:
+    _check(load().rh_network_destroy(net))
+
+
+def rh_network_dims(net):
+    nx, np_ = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().rh_network_dims(net, ctypes.byref(nx), ctypes.byref(np_)))
+    return nx.value, np_.value
+
+
+def rh_network_index_maps(net):
+    nx, npar = rh_network_dims(net)
+    xb, xk = np.zeros(nx, np.int32), np.zeros(nx, np.int32)
+    pb, pk = np.zeros(npar, np.int32), np.zeros(npar, np.int32)
+    _check(load().rh_network_index_maps(net, _p(xb, _i32p), _p(xk, _i32p), _p(pb, _i32p),
+                                        _p(pk, _i32p)))
+    return xb, xk, pb, pk
+
+
+def rh_set_parameters(net, p) -> None:
+    p = _f64(p)
+    _check(load().rh_set_parameters(net, _p(p, _f64p)))
+
+
+def rh_get_parameters(net) -> np.ndarray:
+    _, npar = rh_network_dims(net)
+    p = np.zeros(npar)
+    _check(load().rh_get_parameters(net, _p(p, _f64p)))
+    return p
+
+
+def rh_set_loads(net, Pd, Qd) -> None:
+    Pd, Qd = _f64(Pd), _f64(Qd)
+    _check(load().rh_set_loads(net, _p(Pd, _f64p), _p(Qd, _f64p)))
+
+
+def rh_set_initial_state(net, x0=None) -> None:
+    if x0 is None:
+        _check(load().rh_set_initial_state(net, None))
+    else:
+        x0 = _f64(x0)
+        _check(load().rh_set_initial_state(net, _p(x0, _f64p)))
+
+
+def rh_solve_powerflow(net, tol=1e-13, max_iter=30):
+    it, r = ctypes.c_int32(), ctypes.c_double()
+    _check(load().rh_solve_powerflow(net, float(tol), int(max_iter), ctypes.byref(it),
+                                     ctypes.byref(r)))
+    return it.value, r.value
+
+
+def rh_get_state(net) -> np.ndarray:
+    nx, _ = rh_network_dims(net)
+    x = np.zeros(nx)
+    _check(load().rh_get_state(net, _p(x, _f64p)))
+    return x
+
+
+def rh_objective(net) -> float:
+    f = ctypes.c_double()
+    _check(load().rh_objective(net, ctypes.byref(f)))
+    return f.value
+
+
+def rh_reduced_gradient(net) -> np.ndarray:
+    _, npar = rh_network_dims(net)
+    g = np.zeros(npar)
+    _check(load().rh_reduced_gradient(net, _p(g, _f64p)))
+    return g
+
+
+def rh_hvp(net, W, prec=RH_FP64) -> np.ndarray:
+    _, npar = rh_network_dims(net)
+    W = np.asfortranarray(W, dtype=np.float64)
+    if W.ndim != 2 or W.shape[0] != npar:
+        raise ValueError("W must be n_p x k")
+    k = W.shape[1]
+    HW = np.zeros((npar, k), order="F")
+    _check(load().rh_hvp(net, k, _p(W, _f64p), npar, _p(HW, _f64p), npar, int(prec)))
+    return HW
+
+
+def rh_hvp_device(net, k, dW_ptr, ldw, dHW_ptr, ldhw, prec=RH_FP64, stream=None) -> None:
+    _check(load().rh_hvp_device(net, int(k), ctypes.c_void_p(dW_ptr), int(ldw),
+                                ctypes.c_void_p(dHW_ptr), int(ldhw), int(prec),
+                                ctypes.c_void_p(stream or 0)))
+
+
+def rh_reduced_hessian(net, k_block=0, prec=RH_FP64) -> np.ndarray:
+    _, npar = rh_network_dims(net)
+    H = np.zeros((npar, npar), order="F")
+    _check(load().rh_reduced_hessian(net, _p(H, _f64p), npar, int(k_block), int(prec)))
+    return H
+
+
+def rh_reduced_hessian_device(net, dH_ptr, ldh, k_block=0, prec=RH_FP64, stream=None) -> None:
+    _check(load().rh_reduced_hessian_device(net, ctypes.c_void_p(dH_ptr), int(ldh), int(k_block),
+                                            int(prec), ctypes.c_void_p(stream or 0)))
+
+
+def rh_last_report(net) -> dict:
+    r = rh_report()
+    _check(load().rh_last_report(net, ctypes.byref(r)))
+    return r.as_dict()
+
+
+def rh_status_string(s: int) -> str:
+    return load().rh_status_string(int(s)).decode()
+
+
+def rh_last_error() -> str:
+    return load().rh_last_error().decode()
+
+
+# ---- convenience object ---------------------------------------------------
+class Context:
+    def __init__(self, device: int = 0):
+        self.h = rh_context_create(device)
+        self.device = device
+
+    def set_timing(self, on: bool = True):
+        rh_context_set_timing(self.h, on)
+
+    def close(self):
+        if self.h:
+            rh_context_destroy(self.h)
+            self.h = None
+
+
+class Network:
+    """One network handle; methods mirror the C calls."""
+
+    def __init__(self, ctx: Context, grid):
+        self.ctx = ctx
+        self.h = rh_network_create(ctx.h, grid)
+        self.n_x, self.n_p = rh_network_dims(self.h)
+        v0 = getattr(grid, "v0", None)
+        if v0 is not None:  # Newton starts at angles 0 and the grid's magnitude guess
+            xb, xk, _, _ = rh_network_index_maps(self.h)
+            x0 = np.where(xk == 1, np.asarray(v0, dtype=np.float64)[xb], 0.0)
+            rh_set_initial_state(self.h, x0)
+
+    def close(self):
+        if self.h:
+            rh_network_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    index_maps = lambda self: rh_network_index_maps(self.h)  # noqa: E731
+    set_parameters = lambda self, p: rh_set_parameters(self.h, p)  # noqa: E731
+    get_parameters = lambda self: rh_get_parameters(self.h)  # noqa: E731
+    set_loads = lambda self, Pd, Qd: rh_set_loads(self.h, Pd, Qd)  # noqa: E731
+    set_initial_state = lambda self, x0=None: rh_set_initial_state(self.h, x0)  # noqa: E731
+    solve = lambda self, tol=1e-13, max_iter=30: rh_solve_powerflow(self.h, tol, max_iter)  # noqa
+    state = lambda self: rh_get_state(self.h)  # noqa: E731
+    objective = lambda self: rh_objective(self.h)  # noqa: E731
+    reduced_gradient = lambda self: rh_reduced_gradient(self.h)  # noqa: E731
+    hvp = lambda self, W, prec=RH_FP64: rh_hvp(self.h, W, prec)  # noqa: E731
+    reduced_hessian = lambda self, k_block=0, prec=RH_FP64: rh_reduced_hessian(self.h, k_block, prec)  # noqa
+    report = lambda self: rh_last_report(self.h)  # noqa: E731
+
+    def hvp_device(self, W, HW, stream=None, prec=RH_FP64):
+        """W, HW: torch float64 CUDA tensors of shape (k, n_p) (row j = direction j)."""
+        k = W.shape[0]
+        rh_hvp_device(self.h, k, W.data_ptr(), W.stride(0), HW.data_ptr(), HW.stride(0), prec,
+                      stream)
+
+    def reduced_hessian_device(self, H, k_block=0, stream=None, prec=RH_FP64):
+        """H: torch float64 CUDA tensor (n_p, n_p); row j receives column j of the Hessian."""
+        rh_reduced_hessian_device(self.h, H.data_ptr(), H.stride(0), k_block, prec, stream)

@@ -1,0 +1,141 @@
+"""The C ABI on the CPU: symbols, host-only error paths and the host planner.
+
+No kernel runs here: a host-only context (device -1) exercises network set-up,
+Newton, the first-order adjoint and the reduced gradient, which are compared
+with the oracle; every failure mode that can be forced from the host returns
+its documented status.
+"""
+import re
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import gridgen
+from oracle import solve
+from paper_2201_00241_amd import rh
+
+ROOT = Path(__file__).resolve().parents[1]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = rh.Context(-1)
+    yield c
+    c.close()
+
+
+def test_library_exports_every_declared_symbol():
+    lib = rh.load()
+    header = (ROOT / "include" / "rh.h").read_text()
+    declared = set(re.findall(r"^(?:rh_status|const char \*)\s*(rh_\w+)\(", header, re.M))
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(rh.SYMBOLS)
+
+
+@pytest.mark.parametrize("name", ["c0", "c1"])
+def test_host_planner_matches_oracle(ctx, name):
+    g = gridgen.config_grid(name, 0)
+    net = rh.Network(ctx, g)
+    it, r = net.solve()
+    s = solve(g)
+    assert r <= 1e-13 and it >= 1
+    assert np.max(np.abs(net.state() - s.x)) < 1e-12
+    assert abs(net.objective() - s.F) <= 1e-13 * abs(s.F)
+    gr = net.reduced_gradient()
+    assert np.max(np.abs(gr - s.grad)) <= 1e-11 * np.max(np.abs(s.grad))
+    np.testing.assert_array_equal(net.get_parameters(), s.p)
+
+
+def test_index_maps_follow_the_state_ordering(ctx):
+    g = gridgen.config_grid("c0", 1)
+    net = rh.Network(ctx, g)
+    xb, xk, pb, pk = net.index_maps()
+    pv = np.flatnonzero(g.bus_type == gridgen.PV)
+    pq = np.flatnonzero(g.bus_type == gridgen.PQ)
+    np.testing.assert_array_equal(xb, np.concatenate([pv, pq, pq]))
+    np.testing.assert_array_equal(xk, [0] * (pv.size + pq.size) + [1] * pq.size)
+    np.testing.assert_array_equal(pb, np.concatenate([pv, [g.ref_bus], pv]))
+    np.testing.assert_array_equal(pk, [2] * pv.size + [1] * (pv.size + 1))
+
+
+def _status(fn, *a):
+    with pytest.raises(rh.RhError) as e:
+        fn(*a)
+    return e.value.status
+
+
+def test_products_need_a_device(ctx):
+    net = rh.Network(ctx, gridgen.config_grid("c0", 0))
+    assert _status(net.reduced_gradient) == rh.RH_ESTATE  # before a solve
+    net.solve()
+    assert _status(net.hvp, np.ones((net.n_p, 2))) == rh.RH_EDEVICE
+    assert _status(net.reduced_hessian) == rh.RH_EDEVICE
+
+
+def test_bad_descriptions_are_rejected(ctx):
+    g = gridgen.config_grid("c0", 0)
+    bad = g.copy()
+    bad.br_to[0] = bad.br_from[0]
+    assert _status(rh.Network, ctx, bad) == rh.RH_EINVAL  # self-loop
+    bad = g.copy()
+    t = bad.bus_type.copy()
+    t[np.flatnonzero(t == gridgen.PQ)[0]] = gridgen.REF
+    bad.bus_type = t
+    assert _status(rh.Network, ctx, bad) == rh.RH_EINVAL  # two references
+    bad = g.copy()
+    bad.Pd[3] = np.nan
+    assert _status(rh.Network, ctx, bad) == rh.RH_EINVAL
+    bad = g.copy()
+    bad.br_from[1] = 99
+    assert _status(rh.Network, ctx, bad) == rh.RH_EINVAL
+
+
+def _grid(n, br, types, loads):
+    br = np.asarray(br)
+    m = br.shape[0]
+    gens = np.flatnonzero(np.asarray(types) != gridgen.PQ)
+    return gridgen.Grid(
+        n_bus=n, br_from=br[:, 0].astype(np.int32), br_to=br[:, 1].astype(np.int32),
+        br_r=np.full(m, 0.01), br_x=np.full(m, 0.1), br_b=np.zeros(m),
+        bus_type=np.asarray(types, dtype=np.int32), Pd=np.asarray(loads, dtype=float),
+        Qd=0.3 * np.asarray(loads, dtype=float), gen_bus=gens.astype(np.int32),
+        Pg=np.zeros(gens.size), Vg=np.ones(gens.size), c2=np.ones(gens.size),
+        c1=np.ones(gens.size), c0=np.zeros(gens.size))
+
+
+def test_island_is_singular_and_isolated_bus_invalid(ctx):
+    # buses 3-4 form an island without the reference bus
+    island = _grid(5, [[0, 1], [1, 2], [3, 4]], [3, 1, 1, 1, 1], [0, .1, .1, .1, .1])
+    net = rh.Network(ctx, island)
+    assert _status(net.solve) == rh.RH_ESINGULAR
+    # bus 3 has no branch at all
+    lone = _grid(4, [[0, 1], [1, 2]], [3, 1, 1, 1], [0, .1, .1, .1])
+    assert _status(rh.Network, ctx, lone) == rh.RH_EINVAL
+
+
+def test_overload_does_not_converge(ctx):
+    g = gridgen.config_grid("c0", 0)
+    heavy = g.copy()
+    heavy.Pd *= 40.0
+    heavy.Qd *= 40.0
+    net = rh.Network(ctx, heavy)
+    assert _status(net.solve, 1e-13, 20) in (rh.RH_ENOCONV, rh.RH_ESINGULAR)
+
+
+def test_parameter_changes_invalidate_the_solution(ctx):
+    g = gridgen.config_grid("c0", 0)
+    net = rh.Network(ctx, g)
+    net.solve()
+    p = net.get_parameters()
+    p[0] += 0.01
+    net.set_parameters(p)
+    assert _status(net.objective) == rh.RH_ESTATE
+    net.solve()
+    s = solve(g, p=p)
+    assert abs(net.objective() - s.F) <= 1e-12 * abs(s.F)
+    bad = p.copy()
+    bad[1] = np.inf
+    assert _status(net.set_parameters, bad) == rh.RH_EINVAL
