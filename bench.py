@@ -120,6 +120,13 @@ def main():
     ms_per_step = total_ms / args.steps
     value = n_p * args.steps / (total_ms / 1e3)
 
+    # one more step with in-kernel phase stamps (outside the timed region)
+    ctx.set_timing(2)
+    net.reduced_hessian_device(H, k_block=k, stream=sptr)
+    torch.cuda.synchronize()
+    prep = net.report()
+    ctx.set_timing(0)
+
     rep = trep
     launches = trep["last_launches"]
     avg_launch_ms = trep["last_kernel_ms"] / launches
@@ -146,7 +153,10 @@ def main():
             "dirs_per_group": rep["dirs_per_group"],
             "levels_l": rep["levels_l"], "levels_u": rep["levels_u"],
             "nnz_l": rep["nnz_l"], "nnz_u": rep["nnz_u"],
+            "steps_l": rep["steps_l"], "steps_u": rep["steps_u"],
         },
+        "phase_us": dict(zip(["spmul", "L", "U", "projection", "Ut", "Lt", "spmuladd"],
+                             [round(v, 2) for v in prep["phase_us"]])),
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)),
                        "p99": float(np.percentile(step_ms, 99)),
                        "what": "one full reduced Hessian"},

@@ -84,6 +84,8 @@ typedef struct {
   int32_t n_x, n_p;
   int64_t nnz_gx, nnz_l, nnz_u; /* G_x and its LU factors (unit diagonal of L not stored) */
   int32_t levels_l, levels_u;   /* dependency depth of the L and U sweeps */
+  int32_t steps_l, steps_u;     /* barrier-separated steps of the device sweeps
+                                   (narrow levels merged into dense-inverse blocks) */
   int32_t newton_iters;
   double newton_resid;          /* ||g||_inf at the accepted state */
   int32_t last_k;               /* directions in the last product call */
@@ -91,6 +93,9 @@ typedef struct {
   int32_t dirs_per_group;       /* directions owned by one workgroup (last launch) */
   double last_kernel_ms;        /* summed duration of those launches when timing was
                                    on (HIP events on the launch stream), else -1 */
+  double phase_us[7];           /* timing level 2: mean time per workgroup of SpMul,
+                                   L sweep, U sweep, tensor projection, U^T sweep,
+                                   L^T sweep, SpMulAdd in the last timed launch */
 } rh_report;
 
 /* Create a context on HIP device `device`; device = -1 gives a host-only
@@ -98,7 +103,9 @@ typedef struct {
  * RH_EDEVICE). */
 rh_status rh_context_create(int32_t device, rh_context **out);
 rh_status rh_context_destroy(rh_context *ctx);
-/* Record HIP events around every kernel launch (for rh_report.last_kernel_ms). */
+/* Timing: 0 off; 1 HIP events around every kernel launch
+ * (rh_report.last_kernel_ms); 2 also in-kernel phase timestamps
+ * (rh_report.phase_us), which add a little work per workgroup. */
 rh_status rh_context_set_timing(rh_context *ctx, int32_t on);
 
 /* Validate and copy a network; builds the index maps, the sparsity pattern of

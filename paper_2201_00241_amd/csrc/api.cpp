@@ -96,7 +96,8 @@ rh_status rh_context_destroy(rh_context *ctx) {
 
 rh_status rh_context_set_timing(rh_context *ctx, int32_t on) {
   if (!ctx) return fail(RH_EINVAL, "null context");
-  ctx->c.timing = on != 0;
+  if (on < 0 || on > 2) return fail(RH_EINVAL, "timing level must be 0, 1 or 2");
+  ctx->c.timing = on;
   return RH_OK;
 }
 
@@ -345,7 +346,7 @@ rh_status rh_last_report(const rh_network *net, rh_report *out) {
   rh_network *mnet = const_cast<rh_network *>(net);
   std::string err;
   double ms = -1.0;
-  if (mnet->n.ctx->device >= 0) {
+  if (mnet->n.ctx->device >= 0 && mnet->n.dev) {
     rh_status s = device_kernel_ms(mnet->n, &ms, err);
     if (s != RH_OK) return fail(s, err);
   }

@@ -45,11 +45,20 @@ struct LuPlan {
   int32_t n_levels_l = 0, n_levels_u = 0;
 };
 
+// Device sweep schedule: the sweep's rows in the same positions, with the
+// entries of merged blocks split off into dense block inverses, and per step
+// {first position, rows, log2 lanes per row, dense offset or -1}.
+struct Schedule {
+  Sweep s;
+  std::vector<int32_t> meta;
+  std::vector<double> dense;
+};
+
 struct DeviceNet;  // defined by the device translation unit
 
 struct Context {
   int32_t device = -1;  // -1: host only
-  bool timing = false;
+  int32_t timing = 0;  // 0 off, 1 launch events, 2 also in-kernel phase stamps
 };
 
 // Per-bus-incidence coefficients of the branch-wise Lagrangian Hessian.
@@ -111,6 +120,8 @@ bool lu_factor(LuPlan &lu, const Csr &a, std::string &err);
 void lu_solve(const LuPlan &lu, std::vector<double> &b);        // A x = b in place
 void lu_solve_t(const LuPlan &lu, std::vector<double> &b);      // A^T x = b in place
 void lu_sweeps(const LuPlan &lu, Sweep &sl, Sweep &su, Sweep &sut, Sweep &slt);
+int lane_log2(int32_t rows, int32_t longest, int lane_budget);
+Schedule build_schedule(const Sweep &in, int32_t n, int bmax, int block_rows, int lane_budget);
 
 // ---- device path (device.hip)
 rh_status device_upload(Network &net, std::string &err);

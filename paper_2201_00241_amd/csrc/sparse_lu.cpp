@@ -268,4 +268,79 @@ void lu_sweeps(const LuPlan &lu, Sweep &sl, Sweep &su, Sweep &sut, Sweep &slt) {
              nullptr);
 }
 
+// log2 of the lane group per row of a step: about four entries of the
+// step's longest row per lane, as long as rows x lanes stays within the
+// lane budget.
+int lane_log2(int32_t rows, int32_t longest, int lane_budget) {
+  int lg = 0;
+  while (lg < 6 && (1 << lg) * 4 < longest) ++lg;
+  while (lg > 0 && (int64_t)rows << lg > lane_budget) --lg;
+  return lg;
+}
+
+// Sweep schedule: wide levels stay single steps; runs of consecutive narrow
+// levels with at most `bmax` rows in all become blocks.  For a block each
+// row keeps only its entries to rows of earlier steps; the entries inside the
+// block and the pivots form the block's triangular matrix M (local order =
+// level order), whose inverse is stored densely (column-major).
+Schedule build_schedule(const Sweep &in, int32_t n, int bmax, int block_rows, int lane_budget) {
+  bmax = std::min(bmax, block_rows);
+  Schedule out;
+  Sweep &o = out.s;
+  const int32_t nl = in.n_levels();
+  o.rows = in.rows;
+  o.dinv = in.dinv;
+  o.ptr.assign(in.rows.size() + 1, 0);
+  std::vector<int32_t> local(n, -1);
+  auto level_rows = [&](int32_t l) { return in.lev_ptr[l + 1] - in.lev_ptr[l]; };
+  int32_t l = 0;
+  while (l < nl) {
+    int32_t l2 = l + 1, rows = level_rows(l);
+    if (bmax > 1 && rows <= bmax)
+      while (l2 < nl && rows + level_rows(l2) <= bmax) rows += level_rows(l2++);
+    const int32_t b = in.lev_ptr[l], e = in.lev_ptr[l2];
+    const bool block = (l2 - l) >= 2;
+    if (block)
+      for (int32_t p = b; p < e; ++p) local[in.rows[p]] = p - b;
+    int32_t longest = 0;
+    std::vector<long double> M;
+    if (block) M.assign((size_t)rows * rows, 0.0L);
+    for (int32_t p = b; p < e; ++p) {
+      const int32_t start = (int32_t)o.col.size();
+      for (int32_t q = in.ptr[p]; q < in.ptr[p + 1]; ++q) {
+        const int32_t c = in.col[q];
+        if (block && local[c] >= 0) {
+          M[(size_t)(p - b) + (size_t)local[c] * rows] = in.val[q];
+        } else {
+          o.col.push_back(c);
+          o.val.push_back(in.val[q]);
+        }
+      }
+      o.ptr[p + 1] = (int32_t)o.col.size();
+      longest = std::max(longest, (int32_t)o.col.size() - start);
+      if (block) M[(size_t)(p - b) * (rows + 1)] = in.dinv.empty() ? 1.0L : 1.0L / in.dinv[p];
+    }
+    int32_t off = -1;
+    if (block) {
+      // column j of M^{-1} by forward substitution on e_j (extended precision)
+      off = (int32_t)out.dense.size();
+      out.dense.resize(out.dense.size() + (size_t)rows * rows, 0.0);
+      std::vector<long double> y(rows);
+      for (int32_t j = 0; j < rows; ++j) {
+        for (int32_t a = 0; a < rows; ++a) {
+          long double acc = (a == j) ? 1.0L : 0.0L;
+          for (int32_t c = j; c < a; ++c) acc -= M[(size_t)a + (size_t)c * rows] * y[c];
+          y[a] = a < j ? 0.0L : acc / M[(size_t)a * (rows + 1)];
+        }
+        for (int32_t a = j; a < rows; ++a) out.dense[off + (size_t)a + (size_t)j * rows] = (double)y[a];
+      }
+      for (int32_t p = b; p < e; ++p) local[in.rows[p]] = -1;
+    }
+    out.meta.insert(out.meta.end(), {b, rows, lane_log2(rows, longest, lane_budget), off});
+    l = l2;
+  }
+  return out;
+}
+
+
 }  // namespace rh

@@ -40,15 +40,19 @@ class rh_report(ctypes.Structure):
         ("n_x", ctypes.c_int32), ("n_p", ctypes.c_int32),
         ("nnz_gx", ctypes.c_int64), ("nnz_l", ctypes.c_int64), ("nnz_u", ctypes.c_int64),
         ("levels_l", ctypes.c_int32), ("levels_u", ctypes.c_int32),
+        ("steps_l", ctypes.c_int32), ("steps_u", ctypes.c_int32),
         ("newton_iters", ctypes.c_int32),
         ("newton_resid", ctypes.c_double),
         ("last_k", ctypes.c_int32), ("last_launches", ctypes.c_int32),
         ("dirs_per_group", ctypes.c_int32),
         ("last_kernel_ms", ctypes.c_double),
+        ("phase_us", ctypes.c_double * 7),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["phase_us"] = list(self.phase_us)
+        return d
 
 
 class RhError(RuntimeError):
@@ -144,8 +148,9 @@ def rh_context_destroy(ctx) -> None:
     _check(load().rh_context_destroy(ctx))
 
 
-def rh_context_set_timing(ctx, on: bool) -> None:
-    _check(load().rh_context_set_timing(ctx, 1 if on else 0))
+def rh_context_set_timing(ctx, level) -> None:
+    """0 off, 1 launch events, 2 also in-kernel phase stamps."""
+    _check(load().rh_context_set_timing(ctx, int(level)))
 
 
 def rh_network_create(ctx, grid):
@@ -288,8 +293,8 @@ class Context:
         self.h = rh_context_create(device)
         self.device = device
 
-    def set_timing(self, on: bool = True):
-        rh_context_set_timing(self.h, on)
+    def set_timing(self, level=1):
+        rh_context_set_timing(self.h, int(level))
 
     def close(self):
         if self.h:

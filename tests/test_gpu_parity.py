@@ -108,22 +108,29 @@ def test_1k_device_entry_point_with_padding(c1, rhmod):
 def test_block_size_and_grouping_invariance_is_bitwise(c1):
     g, net, s = c1
     W = gridgen.directions(net.n_p, 64, 8)
-    _say("1k: k=64 vs k=1 vs k=7, one and four directions per workgroup")
+    _say("1k: k=64 vs k=1 vs k=7; 1-8 directions per workgroup; LDS and global vectors")
     ref = net.hvp(W)
     for j in (0, 31, 63):
         np.testing.assert_array_equal(net.hvp(W[:, j:j + 1])[:, 0], ref[:, j])
     np.testing.assert_array_equal(net.hvp(W[:, 10:17]), ref[:, 10:17])
-    old = os.environ.get("RH_DIRS_PER_GROUP")
+    old = {k: os.environ.get(k) for k in ("RH_DIRS_PER_GROUP", "RH_NO_LDS")}
     try:
-        for c in ("2", "4", "8"):
+        for c in ("1", "2", "4"):
+            os.environ["RH_DIRS_PER_GROUP"] = c
+            np.testing.assert_array_equal(net.hvp(W), ref)
+            assert net.report()["dirs_per_group"] == int(c)
+        # the vector in global memory instead of LDS: same arithmetic
+        os.environ["RH_NO_LDS"] = "1"
+        for c in ("1", "4", "8"):
             os.environ["RH_DIRS_PER_GROUP"] = c
             np.testing.assert_array_equal(net.hvp(W), ref)
             assert net.report()["dirs_per_group"] == int(c)
     finally:
-        if old is None:
-            os.environ.pop("RH_DIRS_PER_GROUP", None)
-        else:
-            os.environ["RH_DIRS_PER_GROUP"] = old
+        for k, v in old.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
 
 
 def test_zero_directions_is_a_no_op(c1):
