@@ -1,0 +1,178 @@
+// CPU check of the host planner of librh (compiled and run by
+// tests/test_native.py).  Reads a network from a binary file, then checks
+//  1. the fixed-pattern LU: A x = b and A^T x = b solves against a dense
+//     Gaussian elimination of the same G_x (small networks only);
+//  2. the device sweep schedules: a host emulation of the kernel's step
+//     structure (plain levels and dense-inverse blocks) against a plain
+//     row-by-row sweep, for block sizes 0, 16 and 64.
+// Prints "max_err <name> <value>" lines; exit status 0 unless it fails to run.
+#include <cmath>
+#include <cstdio>
+#include <random>
+#include <vector>
+
+#include "../../paper_2201_00241_amd/csrc/rh_internal.h"
+
+using namespace rh;
+
+template <class T>
+static std::vector<T> rd(FILE *f, size_t n) {
+  std::vector<T> v(n);
+  if (fread(v.data(), sizeof(T), n, f) != n) v.clear();
+  return v;
+}
+
+static void emulate(const Schedule &sc, std::vector<double> &X) {
+  const Sweep &s = sc.s;
+  const size_t ns = sc.meta.size() / 4;
+  for (size_t st = 0; st < ns; ++st) {
+    const int b = sc.meta[4 * st], rows = sc.meta[4 * st + 1], off = sc.meta[4 * st + 3];
+    std::vector<double> r(rows);
+    for (int a = 0; a < rows; ++a) {
+      const int p = b + a;
+      double part = 0;
+      for (int q = s.ptr[p]; q < s.ptr[p + 1]; ++q) part += s.val[q] * X[s.col[q]];
+      double v = X[s.rows[p]] - part;
+      if (off < 0) {
+        if (!s.dinv.empty()) v *= s.dinv[p];
+        X[s.rows[p]] = v;
+      } else {
+        r[a] = v;
+      }
+    }
+    if (off >= 0)
+      for (int a = 0; a < rows; ++a) {
+        double acc = 0;
+        for (int c = 0; c <= a; ++c) acc += sc.dense[off + a + (size_t)c * rows] * r[c];
+        X[s.rows[b + a]] = acc;
+      }
+  }
+}
+
+static void plain(const Sweep &s, std::vector<double> &X) {
+  for (size_t p = 0; p < s.rows.size(); ++p) {
+    double v = X[s.rows[p]];
+    for (int q = s.ptr[p]; q < s.ptr[p + 1]; ++q) v -= s.val[q] * X[s.col[q]];
+    if (!s.dinv.empty()) v *= s.dinv[p];
+    X[s.rows[p]] = v;
+  }
+}
+
+static double relerr(const std::vector<double> &a, const std::vector<double> &b) {
+  double e = 0, m = 0;
+  for (size_t i = 0; i < a.size(); ++i) {
+    e = std::max(e, std::fabs(a[i] - b[i]));
+    m = std::max(m, std::fabs(b[i]));
+  }
+  return e / m;
+}
+
+int main(int argc, char **argv) {
+  if (argc < 2) return 2;
+  FILE *f = fopen(argv[1], "rb");
+  if (!f) return 2;
+  auto hdr = rd<int32_t>(f, 3);
+  const int n = hdr[0], m = hdr[1], g = hdr[2];
+  auto bf = rd<int32_t>(f, m), bt = rd<int32_t>(f, m);
+  auto r = rd<double>(f, m), x = rd<double>(f, m), b = rd<double>(f, m);
+  auto ty = rd<int32_t>(f, n);
+  auto pd = rd<double>(f, n), qd = rd<double>(f, n);
+  auto gb = rd<int32_t>(f, g);
+  auto pg = rd<double>(f, g), vg = rd<double>(f, g), c2 = rd<double>(f, g), c1 = rd<double>(f, g),
+       c0 = rd<double>(f, g);
+  auto v0 = rd<double>(f, n);
+  fclose(f);
+  rh_network_desc d{n, m, g, bf.data(), bt.data(), r.data(), x.data(), b.data(), ty.data(), pd.data(),
+                    qd.data(), gb.data(), pg.data(), vg.data(), c2.data(), c1.data(), c0.data()};
+  Context ctx;
+  Network net;
+  net.ctx = &ctx;
+  std::string err;
+  if (network_build(net, d, err) != RH_OK) {
+    printf("build error %s\n", err.c_str());
+    return 1;
+  }
+  if (v0.size() == (size_t)n) {
+    net.x0.assign(net.n_x, 0.0);
+    for (int bb = 0; bb < n; ++bb)
+      if (net.v_x[bb] >= 0) net.x0[net.v_x[bb]] = v0[bb];
+  }
+  if (network_solve(net, 1e-13, 30, err) != RH_OK) {
+    printf("solve error %s\n", err.c_str());
+    return 1;
+  }
+  std::mt19937_64 rng(7);
+  std::normal_distribution<double> nd;
+  const int nx = net.n_x;
+  if (nx <= 400) {  // dense Gaussian elimination with partial pivoting
+    std::vector<double> A((size_t)nx * nx, 0.0);
+    for (int i = 0; i < nx; ++i)
+      for (int e = net.gx.ptr[i]; e < net.gx.ptr[i + 1]; ++e) A[(size_t)i * nx + net.gx.col[e]] = net.gx.val[e];
+    for (int trans = 0; trans < 2; ++trans) {
+      std::vector<double> M(A), rhs(nx), sol;
+      if (trans)
+        for (int i = 0; i < nx; ++i)
+          for (int j = 0; j < nx; ++j) M[(size_t)i * nx + j] = A[(size_t)j * nx + i];
+      for (auto &v : rhs) v = nd(rng);
+      sol = rhs;
+      if (trans)
+        lu_solve_t(net.lu, sol);
+      else
+        lu_solve(net.lu, sol);
+      std::vector<double> bvec(rhs);
+      for (int k = 0; k < nx; ++k) {
+        int p = k;
+        for (int i = k + 1; i < nx; ++i)
+          if (std::fabs(M[(size_t)i * nx + k]) > std::fabs(M[(size_t)p * nx + k])) p = i;
+        for (int j = 0; j < nx; ++j) std::swap(M[(size_t)k * nx + j], M[(size_t)p * nx + j]);
+        std::swap(bvec[k], bvec[p]);
+        for (int i = k + 1; i < nx; ++i) {
+          const double l = M[(size_t)i * nx + k] / M[(size_t)k * nx + k];
+          for (int j = k; j < nx; ++j) M[(size_t)i * nx + j] -= l * M[(size_t)k * nx + j];
+          bvec[i] -= l * bvec[k];
+        }
+      }
+      std::vector<double> xs(nx);
+      for (int i = nx - 1; i >= 0; --i) {
+        double s = bvec[i];
+        for (int j = i + 1; j < nx; ++j) s -= M[(size_t)i * nx + j] * xs[j];
+        xs[i] = s / M[(size_t)i * nx + i];
+      }
+      printf("max_err lu_solve%s %.3e\n", trans ? "_t" : "", relerr(sol, xs));
+    }
+  }
+  Sweep sw[4];
+  lu_sweeps(net.lu, sw[0], sw[1], sw[2], sw[3]);
+  const char *nm[4] = {"L", "U", "Ut", "Lt"};
+  for (int k = 0; k < 4; ++k)
+    for (int bmax : {0, 16, 64}) {
+      const Schedule sc = build_schedule(sw[k], nx, bmax, 64, 512);
+      std::vector<double> X(nx);
+      for (auto &v : X) v = nd(rng);
+      std::vector<double> Y = X;
+      emulate(sc, X);
+      plain(sw[k], Y);
+      printf("max_err sweep_%s_b%d %.3e steps %zu\n", nm[k], bmax, relerr(X, Y), sc.meta.size() / 4);
+    }
+  // the four sweeps compose to the two solves: U^-1 L^-1 (P b) and L^-T U^-T (P b)
+  {
+    std::vector<double> bb(nx);
+    for (auto &v : bb) v = nd(rng);
+    std::vector<double> ref = bb, X(nx);
+    lu_solve(net.lu, ref);
+    for (int i = 0; i < nx; ++i) X[net.lu.iperm[i]] = bb[i];
+    emulate(build_schedule(sw[0], nx, 64, 64, 512), X);
+    emulate(build_schedule(sw[1], nx, 64, 64, 512), X);
+    std::vector<double> sol(nx);
+    for (int i = 0; i < nx; ++i) sol[i] = X[net.lu.iperm[i]];
+    printf("max_err solve_via_sweeps %.3e\n", relerr(sol, ref));
+    ref = bb;
+    lu_solve_t(net.lu, ref);
+    for (int i = 0; i < nx; ++i) X[net.lu.iperm[i]] = bb[i];
+    emulate(build_schedule(sw[2], nx, 64, 64, 512), X);
+    emulate(build_schedule(sw[3], nx, 64, 64, 512), X);
+    for (int i = 0; i < nx; ++i) sol[i] = X[net.lu.iperm[i]];
+    printf("max_err solve_t_via_sweeps %.3e\n", relerr(sol, ref));
+  }
+  return 0;
+}
