@@ -71,6 +71,15 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--k", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="hessian",
+                    choices=["hessian", "batch", "serving"],
+                    help="hessian: full reduced Hessian (the headline metric); batch: many "
+                         "operating points of one grid in one launch; serving: Poisson "
+                         "request mix through the continuous-batching server")
+    ap.add_argument("--instances", type=int, default=32)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run a device-to-device copy of this many bytes, 10 times "
+                         "(reference for scaling HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 "
@@ -79,11 +88,26 @@ def main():
 
     import torch
 
+    if args.copy_probe:
+        n = args.copy_probe // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8,
+                          "launches": 10}), flush=True)
+        return
+
     import gridgen
     from paper_2201_00241_amd import rh
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "serving":
+        return bench_serving(args)
     g = gridgen.config_grid(args.config, 0)
     ctx = rh.Context(0)
     net = rh.Network(ctx, g)
@@ -172,6 +196,105 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, k)
     print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    """Operating points of one grid (loads perturbed by up to 10 %), each with
+    128 Gaussian directions, in one launch per step."""
+    import torch
+
+    import gridgen
+    from paper_2201_00241_amd import rh
+
+    base = gridgen.config_grid(args.config if args.config != "c2" else "c3", 0)
+    ctx = rh.Context(0)
+    nets, t0 = [], time.perf_counter()
+    for i in range(args.instances):
+        g = gridgen.perturb_loads(base, seed=5000 + i)
+        n = rh.Network(ctx, g)
+        n.solve(1e-13, 30)
+        nets.append(n)
+    setup_s = time.perf_counter() - t0
+    k = 128
+    Ws = [torch.from_numpy(np.ascontiguousarray(gridgen.directions(n.n_p, k, 7000 + i).T)).cuda()
+          for i, n in enumerate(nets)]
+    HWs = [torch.empty_like(W) for W in Ws]
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        ctx.hvp_batch_device(nets, Ws, HWs, stream=stream.cuda_stream)
+    torch.cuda.synchronize()
+    ctx.set_timing(1)
+    ctx.report()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        ctx.hvp_batch_device(nets, Ws, HWs, stream=stream.cuda_stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    rep = ctx.report()
+    ctx.set_timing(0)
+    ms = e0.elapsed_time(e1) / args.steps
+    n_x, n_p = nets[0].n_x, nets[0].n_p
+    print(json.dumps({
+        "metric": "batched instances: HVPs/sec", "value": len(nets) * k / (ms / 1e3),
+        "unit": "HVP/s", "ms_per_step": ms, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{len(nets)} operating points of a {base.n_bus}-bus grid "
+                               f"x {k} Gaussian directions, one launch",
+                   "n_x": n_x, "n_p": n_p, "launches_per_step": rep["last_launches"] // args.steps,
+                   "dirs_per_group": rep["dirs_per_group"]},
+        "avg_launch_ms": rep["last_kernel_ms"] / max(1, rep["last_launches"]),
+        "setup_s": setup_s}), flush=True)
+
+
+def bench_serving(args):
+    """Poisson arrivals over resident 1k, 10k and 70k networks (4 operating
+    points each), requests for 1, 16 or 128 directions or the full Hessian."""
+    import gridgen
+    from paper_2201_00241_amd import rh
+    from paper_2201_00241_amd.serving import Request, Server, latency_summary
+
+    ctx = rh.Context(0)
+    nets = {}
+    for name in ("c1", "c2", "c3"):
+        base = gridgen.config_grid(name, 0)
+        for i in range(4):
+            n = rh.Network(ctx, gridgen.perturb_loads(base, seed=9000 + i))
+            n.solve(1e-13, 30)
+            nets[f"{name}/{i}"] = n
+    keys = sorted(nets)
+    rng = np.random.default_rng(11)
+
+    def make(n_req, rate):
+        t, reqs = 0.0, []
+        for i in range(n_req):
+            key = keys[rng.integers(len(keys))]
+            k = int(rng.choice([1, 16, 128, 0], p=[0.3, 0.3, 0.3, 0.1]))
+            if k == 0 and key.startswith("c3"):
+                k = 128  # a full 70k-bus Hessian would dominate the mix
+            W = None if k == 0 else rng.standard_normal((nets[key].n_p, k))
+            if rate:
+                t += rng.exponential(1.0 / rate)
+            reqs.append(Request(rid=i, key=key, k=k, W=W, arrival=t))
+        return reqs
+
+    srv = Server(ctx, nets, max_inflight=3, dirs_per_launch=4096, block=256)
+    srv.run(make(20, 0))  # warm-up
+    t0 = time.perf_counter()
+    closed = srv.run(make(120, 0))
+    peak = len(closed) / (time.perf_counter() - t0)
+    reqs = make(200, 0.8 * peak)
+    t0 = time.perf_counter()
+    done = srv.run(reqs)
+    wall = time.perf_counter() - t0
+    hvps = sum((r.k if r.k else nets[r.key].n_p) for r in done)
+    print(json.dumps({
+        "metric": "served reduced-Hessian requests: p50/p99 latency", "unit": "ms",
+        "latency": latency_summary(done), "requests_per_s": len(done) / wall,
+        "hvp_per_s": hvps / wall, "peak_requests_per_s": peak, "arrival_rate": 0.8 * peak,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "Poisson mix over 1k/10k/70k-bus grids, 4 operating points "
+                               "each; k in {1,16,128} or the full Hessian (1k, 10k)"}}),
+          flush=True)
 
 
 if __name__ == "__main__":

@@ -293,12 +293,13 @@ def geometric(n_bus: int, n_branch: int, n_gen: int, seed: int, alpha: float,
 # Workload shapes.  ``alpha`` is the loading factor (loads, dispatch and line
 # charging scaled together) and ``kappa`` the loss factor of the PV dispatch.
 # Both were set with tests/golden/calibrate_grids.py: alpha is about 0.8 of
-# the smallest loading limit found over the instances used, kappa the slack's
-# loss share at light load scaled linearly to alpha.
+# the smallest loading limit found over the instances used (70k buses: the
+# limit is 0.055, so loads are light there), kappa the slack's loss share at
+# light load scaled linearly to alpha.
 CONFIGS = {
     "c1": dict(n_bus=1_000, n_branch=1_350, n_gen=100, alpha=0.30, kappa=0.0255),
     "c2": dict(n_bus=10_000, n_branch=13_500, n_gen=1_400, alpha=0.22, kappa=0.0113),
-    "c3": dict(n_bus=70_000, n_branch=95_000, n_gen=5_000, alpha=0.20, kappa=0.0),
+    "c3": dict(n_bus=70_000, n_branch=95_000, n_gen=5_000, alpha=0.044, kappa=0.0069),
 }
 CONFIG_INDEX = {"c0": 0, "c1": 1, "c2": 2, "c3": 3}
 

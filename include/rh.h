@@ -59,7 +59,11 @@ typedef enum {
 
 typedef enum {
   RH_FP64 = 0,        /* every step in FP64 */
-  RH_FP32_REFINED = 1 /* reserved: FP32 sweeps with FP64 residual refinement */
+  RH_FP32_REFINED = 1 /* triangular sweeps in FP32 with FP64 residual refinement:
+                         x = solve32(b), then `refinement` times
+                         x += solve32(b - G_x x) (G_x^T for the second solve),
+                         residuals, stored vectors, tensor projection and G_p
+                         products in FP64; LU factors computed in FP64 */
 } rh_precision;
 
 /* Network description (Sec. 3.1).  All arrays are read-only and copied.
@@ -107,6 +111,10 @@ rh_status rh_context_destroy(rh_context *ctx);
  * (rh_report.last_kernel_ms); 2 also in-kernel phase timestamps
  * (rh_report.phase_us), which add a little work per workgroup. */
 rh_status rh_context_set_timing(rh_context *ctx, int32_t on);
+
+/* Correction steps of RH_FP32_REFINED after the first FP32 solve (default 2,
+ * at most 16). */
+rh_status rh_context_set_refinement(rh_context *ctx, int32_t steps);
 
 /* Validate and copy a network; builds the index maps, the sparsity pattern of
  * G_x, a fill-reducing ordering, the symbolic LU and the level schedules.
@@ -162,9 +170,28 @@ rh_status rh_reduced_hessian(rh_network *net, double *H, int64_t ldh, int32_t k_
 rh_status rh_reduced_hessian_device(rh_network *net, void *dH, int64_t ldh, int32_t k_block,
                                     rh_precision prec, void *hip_stream);
 
+/* Batched instances (several networks, or operating points of one grid, in
+ * one kernel launch; the direction blocks of Algorithm 2 are independent
+ * across instances as they are across directions).  Item i: network nets[i]
+ * (solved, created on ctx), k[i] directions in device buffers dW[i] /
+ * dHW[i] (FP64, column-major, leading dimensions ldw[i], ldhw[i] >= its n_p).
+ * identity_from may be NULL; where identity_from[i] >= 0, item i's directions
+ * are the identity columns identity_from[i] .. + k[i] - 1 (dW[i] is not read;
+ * a block of the full reduced Hessian).  Enqueued on hip_stream.  The context
+ * keeps launch resources per stream: batched calls on different streams may
+ * run concurrently (call from one host thread at a time). */
+rh_status rh_hvp_batch_device(rh_context *ctx, int32_t n, rh_network *const *nets,
+                              const int32_t *k, const void *const *dW, const int64_t *ldw,
+                              void *const *dHW, const int64_t *ldhw,
+                              const int32_t *identity_from, rh_precision prec,
+                              void *hip_stream);
+
 /* Figures of the network; waits for the timed launches since the previous
  * report, sums their durations, then starts a new timing window. */
 rh_status rh_last_report(const rh_network *net, rh_report *out);
+/* Launch figures of the batched calls on ctx since the previous call (only
+ * the launch, timing and phase fields are filled). */
+rh_status rh_context_report(rh_context *ctx, rh_report *out);
 const char *rh_status_string(rh_status s);
 const char *rh_last_error(void);
 

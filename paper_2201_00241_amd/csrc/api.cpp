@@ -90,6 +90,8 @@ rh_status rh_context_create(int32_t device, rh_context **out) {
 }
 
 rh_status rh_context_destroy(rh_context *ctx) {
+  if (!ctx) return RH_OK;
+  device_ctx_free(ctx->c);
   delete ctx;
   return RH_OK;
 }
@@ -98,6 +100,13 @@ rh_status rh_context_set_timing(rh_context *ctx, int32_t on) {
   if (!ctx) return fail(RH_EINVAL, "null context");
   if (on < 0 || on > 2) return fail(RH_EINVAL, "timing level must be 0, 1 or 2");
   ctx->c.timing = on;
+  return RH_OK;
+}
+
+rh_status rh_context_set_refinement(rh_context *ctx, int32_t steps) {
+  if (!ctx) return fail(RH_EINVAL, "null context");
+  if (steps < 0 || steps > 16) return fail(RH_EINVAL, "refinement steps must be in 0..16");
+  ctx->c.refine = steps;
   return RH_OK;
 }
 
@@ -247,14 +256,14 @@ rh_status rh_hvp_device(rh_network *net, int32_t k, const void *dW, int64_t ldw,
   rh_status s = need_solved(net);
   if (s != RH_OK) return s;
   if ((s = need_device(net)) != RH_OK) return s;
-  if (prec != RH_FP64) return fail(RH_EINVAL, "only RH_FP64 is available");
+  if (prec != RH_FP64 && prec != RH_FP32_REFINED) return fail(RH_EINVAL, "unknown precision");
   if (k < 0 || !dW || !dHW || ldw < net->n.n_p || ldhw < net->n.n_p)
     return fail(RH_EINVAL, "bad product arguments");
   net->n.report.last_k = k;
   if (k == 0) return RH_OK;
   std::string err;
   s = device_hvp(net->n, k, static_cast<const double *>(dW), ldw, static_cast<double *>(dHW), ldhw,
-                 -1, hip_stream, err);
+                 -1, prec, hip_stream, err);
   if (s != RH_OK) return fail(s, err);
   return RH_OK;
   GUARD_END
@@ -266,7 +275,7 @@ rh_status rh_reduced_hessian_device(rh_network *net, void *dH, int64_t ldh, int3
   rh_status s = need_solved(net);
   if (s != RH_OK) return s;
   if ((s = need_device(net)) != RH_OK) return s;
-  if (prec != RH_FP64) return fail(RH_EINVAL, "only RH_FP64 is available");
+  if (prec != RH_FP64 && prec != RH_FP32_REFINED) return fail(RH_EINVAL, "unknown precision");
   const int32_t n_p = net->n.n_p;
   if (!dH || ldh < n_p || k_block < 0) return fail(RH_EINVAL, "bad Hessian arguments");
   const int32_t k = (k_block == 0 || k_block > n_p) ? n_p : k_block;
@@ -275,7 +284,7 @@ rh_status rh_reduced_hessian_device(rh_network *net, void *dH, int64_t ldh, int3
   double *H = static_cast<double *>(dH);
   for (int32_t j0 = 0; j0 < n_p; j0 += k) {
     const int32_t kb = std::min(k, n_p - j0);
-    s = device_hvp(net->n, kb, nullptr, 0, H + (int64_t)j0 * ldh, ldh, j0, hip_stream, err);
+    s = device_hvp(net->n, kb, nullptr, 0, H + (int64_t)j0 * ldh, ldh, j0, prec, hip_stream, err);
     if (s != RH_OK) return fail(s, err);
   }
   return RH_OK;
@@ -345,14 +354,54 @@ rh_status rh_last_report(const rh_network *net, rh_report *out) {
   if (!net || !out) return fail(RH_EINVAL, "null argument");
   rh_network *mnet = const_cast<rh_network *>(net);
   std::string err;
-  double ms = -1.0;
-  if (mnet->n.ctx->device >= 0 && mnet->n.dev) {
-    rh_status s = device_kernel_ms(mnet->n, &ms, err);
+  if (mnet->n.ctx->device >= 0) {
+    rh_status s = device_collect(mnet->n, err);
     if (s != RH_OK) return fail(s, err);
   }
-  mnet->n.report.last_kernel_ms = ms;
   *out = net->n.report;
-  device_take_timing(mnet->n);
+  return RH_OK;
+}
+
+rh_status rh_hvp_batch_device(rh_context *ctx, int32_t n, rh_network *const *nets, const int32_t *k,
+                              const void *const *dW, const int64_t *ldw, void *const *dHW,
+                              const int64_t *ldhw, const int32_t *identity_from, rh_precision prec,
+                              void *hip_stream) {
+  GUARD_BEGIN
+  if (!ctx) return fail(RH_EINVAL, "null context");
+  if (ctx->c.device < 0) return fail(RH_EDEVICE, "host-only context");
+  if (prec != RH_FP64 && prec != RH_FP32_REFINED) return fail(RH_EINVAL, "unknown precision");
+  if (n < 0 || (n > 0 && (!nets || !k || !dW || !ldw || !dHW || !ldhw)))
+    return fail(RH_EINVAL, "bad batch arguments");
+  std::vector<Network *> ns(n);
+  for (int32_t i = 0; i < n; ++i) {
+    if (!nets[i]) return fail(RH_EINVAL, "null network in batch");
+    Network &net = nets[i]->n;
+    if (net.ctx != &ctx->c) return fail(RH_EINVAL, "network of another context in batch");
+    if (!net.solved || !net.dev) return fail(RH_ESTATE, "unsolved network in batch");
+    const int32_t idf = identity_from ? identity_from[i] : -1;
+    if (k[i] < 0 || (k[i] > 0 && (!dHW[i] || ldhw[i] < net.n_p)))
+      return fail(RH_EINVAL, "bad batch item");
+    if (k[i] > 0 && idf < 0 && (!dW[i] || ldw[i] < net.n_p)) return fail(RH_EINVAL, "bad batch item");
+    if (idf >= 0 && (int64_t)idf + k[i] > net.n_p) return fail(RH_EINVAL, "identity block exceeds n_p");
+    ns[i] = &net;
+  }
+  std::string err;
+  rh_status s = device_hvp_batch(ctx->c, n, ns.data(), k, reinterpret_cast<const double *const *>(dW),
+                                 ldw, reinterpret_cast<double *const *>(dHW), ldhw, identity_from,
+                                 prec, hip_stream, err);
+  if (s != RH_OK) return fail(s, err);
+  return RH_OK;
+  GUARD_END
+}
+
+rh_status rh_context_report(rh_context *ctx, rh_report *out) {
+  if (!ctx || !out) return fail(RH_EINVAL, "null argument");
+  *out = rh_report{};
+  std::string err;
+  if (ctx->c.device >= 0) {
+    rh_status s = device_ctx_collect(ctx->c, *out, err);
+    if (s != RH_OK) return fail(s, err);
+  }
   return RH_OK;
 }
 

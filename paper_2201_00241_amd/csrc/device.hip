@@ -58,7 +58,27 @@ struct DevSweep {
   const int32_t *rows, *ptr, *col;
   const double *val, *dinv;  // dinv == nullptr: unit diagonal
   const double *dense;       // block inverses
+  const float *val32, *dinv32, *dense32;  // FP32 copies (refined mode)
 };
+
+template <class T>
+__device__ __forceinline__ const T *sw_val(const DevSweep &s);
+template <>
+__device__ __forceinline__ const double *sw_val<double>(const DevSweep &s) { return s.val; }
+template <>
+__device__ __forceinline__ const float *sw_val<float>(const DevSweep &s) { return s.val32; }
+template <class T>
+__device__ __forceinline__ const T *sw_dinv(const DevSweep &s);
+template <>
+__device__ __forceinline__ const double *sw_dinv<double>(const DevSweep &s) { return s.dinv; }
+template <>
+__device__ __forceinline__ const float *sw_dinv<float>(const DevSweep &s) { return s.dinv32; }
+template <class T>
+__device__ __forceinline__ const T *sw_dense(const DevSweep &s);
+template <>
+__device__ __forceinline__ const double *sw_dense<double>(const DevSweep &s) { return s.dense; }
+template <>
+__device__ __forceinline__ const float *sw_dense<float>(const DevSweep &s) { return s.dense32; }
 
 struct NetDesc {
   int32_t n_x, n_p, n_bus, n_pg, n_slack;
@@ -77,15 +97,29 @@ struct NetDesc {
   const double *slack_gth, *slack_gv;
   const int32_t *pg_idx;
   const double *pg_c2x2;
+  // G_x and G_x^T in permuted numbering (residuals of the refined mode)
+  const int32_t *gx_ptr, *gx_col, *gxt_ptr, *gxt_col;
+  const double *gx_val, *gxt_val;
 };
 
-struct BlockArgs {
-  int32_t k;              // directions in this launch
-  int32_t identity_from;  // >= 0: W is columns identity_from.. of the identity
+// One unit of work: a block of k directions of one network (column-major
+// W and HW with leading dimensions ldw, ldhw; identity_from >= 0 means W is
+// columns identity_from .. of the identity and is not read).
+struct WorkItem {
+  const NetDesc *nd;  // device copy of the network's descriptor
   const double *W;
-  int64_t ldw;
   double *HW;
-  int64_t ldhw;
+  int64_t ldw, ldhw;
+  int32_t k, identity_from;
+  int32_t chunk0;  // first chunk of C directions of this item in the launch
+  int32_t pad;
+};
+
+struct LaunchArgs {
+  const WorkItem *items;  // n_items entries in device memory; nullptr: `one`
+  WorkItem one;
+  int32_t n_items, n_chunks;
+  int32_t refine;  // refined mode: correction steps after the first FP32 solve
   double *scratch;
   int64_t scratch_stride;  // doubles per workgroup
   long long *stamps;       // kStamps wall-clock stamps per workgroup, or nullptr
@@ -93,10 +127,24 @@ struct BlockArgs {
 
 constexpr int kStamps = 8;
 
-__device__ __forceinline__ double w_at(const BlockArgs &a, int32_t q, int32_t dir) {
+__device__ __forceinline__ double w_at(const WorkItem &a, int32_t q, int32_t dir) {
   if (dir >= a.k) return 0.0;
   if (a.identity_from >= 0) return (q == a.identity_from + dir) ? 1.0 : 0.0;
   return a.W[(int64_t)dir * a.ldw + q];
+}
+
+// The work item that holds global chunk `chunk` (items sorted by chunk0).
+__device__ __forceinline__ WorkItem item_of(const LaunchArgs &la, int32_t chunk) {
+  if (!la.items) return la.one;
+  int32_t lo = 0, hi = la.n_items - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (la.items[mid].chunk0 <= chunk)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return la.items[lo];
 }
 
 // Registers holding one row of a level: its position, entry range, the first
@@ -104,28 +152,32 @@ __device__ __forceinline__ double w_at(const BlockArgs &a, int32_t q, int32_t di
 // one level ahead, so that the dependent global loads leave the critical path
 // of the sweep (they do not depend on the solution vector).
 constexpr int kPre = 4;
+template <class T>
 struct RowPre {
   int32_t pos, q0, q1, row;
   int32_t col[kPre];
-  double val[kPre];
-  double dinv;
+  T val[kPre];
+  T dinv;
 };
 
-__device__ __forceinline__ RowPre prefetch_row(const DevSweep &s, const int4 m, int32_t r, int lane,
-                                               int width) {
-  RowPre p;
+template <class T>
+__device__ __forceinline__ RowPre<T> prefetch_row(const DevSweep &s, const int4 m, int32_t r, int lane,
+                                                  int width) {
+  RowPre<T> p;
   p.pos = -1;
   if (r < m.y) {
+    const T *val = sw_val<T>(s);
+    const T *dinv = sw_dinv<T>(s);
     p.pos = m.x + r;
     p.q0 = s.ptr[p.pos];
     p.q1 = s.ptr[p.pos + 1];
     p.row = s.rows[p.pos];
-    p.dinv = s.dinv ? s.dinv[p.pos] : 1.0;
+    p.dinv = dinv ? dinv[p.pos] : T(1);
 #pragma unroll
     for (int i = 0; i < kPre; ++i) {
       const int32_t q = p.q0 + lane + i * width;
       p.col[i] = q < p.q1 ? s.col[q] : 0;
-      p.val[i] = q < p.q1 ? s.val[q] : 0.0;
+      p.val[i] = q < p.q1 ? val[q] : T(0);
     }
   }
   return p;
@@ -134,13 +186,14 @@ __device__ __forceinline__ RowPre prefetch_row(const DevSweep &s, const int4 m, 
 // One row: new value = (init - sum_j val_j X_j) * dinv, summed by a lane
 // group of `width` lanes and combined by a shuffle butterfly.  Rows of a block
 // step only form the residual (no pivot) into s_r at their place in the block.
-template <int C, int NT>
-__device__ __forceinline__ void row_update(const DevSweep &s, const RowPre &p, double *__restrict__ X,
-                                           const double *__restrict__ init, double *__restrict__ s_r,
+template <int C, int NT, class T>
+__device__ __forceinline__ void row_update(const DevSweep &s, const RowPre<T> &p, T *__restrict__ X,
+                                           const T *__restrict__ init, T *__restrict__ s_r,
                                            int32_t first, bool block, int lane, int width) {
-  double part[C];
+  const T *val = sw_val<T>(s);
+  T part[C];
 #pragma unroll
-  for (int c = 0; c < C; ++c) part[c] = 0.0;
+  for (int c = 0; c < C; ++c) part[c] = T(0);
 #pragma unroll
   for (int i = 0; i < kPre; ++i) {
     const int32_t j = p.col[i] * C;
@@ -148,7 +201,7 @@ __device__ __forceinline__ void row_update(const DevSweep &s, const RowPre &p, d
     for (int c = 0; c < C; ++c) part[c] = fma(p.val[i], X[j + c], part[c]);
   }
   for (int32_t q = p.q0 + lane + kPre * width; q < p.q1; q += width) {
-    const double v = s.val[q];
+    const T v = val[q];
     const int32_t j = s.col[q] * C;
 #pragma unroll
     for (int c = 0; c < C; ++c) part[c] = fma(v, X[j + c], part[c]);
@@ -164,10 +217,11 @@ __device__ __forceinline__ void row_update(const DevSweep &s, const RowPre &p, d
 #pragma unroll
       for (int c = 0; c < C; ++c) s_r[a + c] = (init ? init[i + c] : X[i + c]) - part[c];
     } else {
+      const bool piv = sw_dinv<T>(s) != nullptr;
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        double v = (init ? init[i + c] : X[i + c]) - part[c];
-        if (s.dinv) v *= p.dinv;
+        T v = (init ? init[i + c] : X[i + c]) - part[c];
+        if (piv) v *= p.dinv;
         X[i + c] = v;
       }
     }
@@ -183,42 +237,41 @@ __device__ __forceinline__ void row_update(const DevSweep &s, const RowPre &p, d
 // stored the dense inverse M^{-1} of the block's own triangular system
 // (column-major, kBlockRows x kBlockRows at most).  A block is then solved in
 // two parallel phases: residuals r = init - (external part), then x = M^{-1} r.
-template <int C, int NT>
-__device__ __forceinline__ void sweep(const DevSweep &s, double *__restrict__ X,
-                                      const double *__restrict__ init, double *__restrict__ s_r,
-                                      int tid) {
+template <int C, int NT, class T>
+__device__ __forceinline__ void sweep(const DevSweep &s, T *__restrict__ X, const T *__restrict__ init,
+                                      T *__restrict__ s_r, int tid) {
   const int32_t nl = s.n_levels;
   if (nl == 0) return;
   int4 m = s.lev[0];
   int lg = m.z;
-  RowPre pre = prefetch_row(s, m, tid >> lg, tid & ((1 << lg) - 1), 1 << lg);
+  RowPre<T> pre = prefetch_row<T>(s, m, tid >> lg, tid & ((1 << lg) - 1), 1 << lg);
   for (int32_t lev = 0; lev < nl; ++lev) {
     const int4 cur = m;
     const int width = 1 << lg;
     const int lane = tid & (width - 1);
-    const RowPre first = pre;
+    const RowPre<T> first = pre;
     if (lev + 1 < nl) {  // next step's first rows, issued before this step's work
       m = s.lev[lev + 1];
       lg = m.z;
-      pre = prefetch_row(s, m, tid >> lg, tid & ((1 << lg) - 1), 1 << lg);
+      pre = prefetch_row<T>(s, m, tid >> lg, tid & ((1 << lg) - 1), 1 << lg);
     }
     const bool block = cur.w >= 0;
     if (first.pos >= 0) {
-      row_update<C, NT>(s, first, X, init, s_r, cur.x, block, lane, width);
+      row_update<C, NT, T>(s, first, X, init, s_r, cur.x, block, lane, width);
       for (int32_t r = (tid >> cur.z) + (NT >> cur.z); r < cur.y; r += (NT >> cur.z)) {
-        const RowPre p = prefetch_row(s, cur, r, lane, width);
-        row_update<C, NT>(s, p, X, init, s_r, cur.x, block, lane, width);
+        const RowPre<T> p = prefetch_row<T>(s, cur, r, lane, width);
+        row_update<C, NT, T>(s, p, X, init, s_r, cur.x, block, lane, width);
       }
     }
     __syncthreads();
     if (block) {
       if (tid < cur.y) {
-        const double *__restrict__ Mi = s.dense + cur.w;
-        double acc[C];
+        const T *__restrict__ Mi = sw_dense<T>(s) + cur.w;
+        T acc[C];
 #pragma unroll
-        for (int c = 0; c < C; ++c) acc[c] = 0.0;
+        for (int c = 0; c < C; ++c) acc[c] = T(0);
         for (int32_t b = 0; b <= tid; ++b) {
-          const double v = Mi[tid + b * cur.y];
+          const T v = Mi[tid + b * cur.y];
 #pragma unroll
           for (int c = 0; c < C; ++c) acc[c] = fma(v, s_r[b * C + c], acc[c]);
         }
@@ -231,16 +284,10 @@ __device__ __forceinline__ void sweep(const DevSweep &s, double *__restrict__ X,
   }
 }
 
+// SpMul: B = -P G_p W into X (rows of C directions, FP64).
 template <int C, int NT>
-__device__ __forceinline__ void reduction(const NetDesc &nd, const BlockArgs &a, double *__restrict__ X,
-                                          double *__restrict__ Yx, double *s_slack, double *s_r,
-                                          int32_t dir0) {
-  const int tid = threadIdx.x;
-  // optional phase timestamps (first chunk of each workgroup, thread 0)
-  long long *st = (a.stamps && dir0 == (int32_t)blockIdx.x * C && tid == 0)
-                      ? a.stamps + (int64_t)blockIdx.x * kStamps : nullptr;
-  if (st) st[0] = wall_clock64();
-  // 1. B' = -P G_p W
+__device__ __forceinline__ void spmul(const NetDesc &nd, const WorkItem &a, double *__restrict__ X,
+                                      int32_t dir0, int tid) {
   for (int32_t i = tid; i < nd.n_x; i += NT) {
     double acc[C];
 #pragma unroll
@@ -254,35 +301,35 @@ __device__ __forceinline__ void reduction(const NetDesc &nd, const BlockArgs &a,
 #pragma unroll
     for (int c = 0; c < C; ++c) X[i * C + c] = -acc[c];
   }
-  __syncthreads();
-  if (st) st[1] = wall_clock64();
-  // 2. Z' = U^{-1} L^{-1} B'
-  sweep<C, NT>(nd.L, X, nullptr, s_r, tid);
-  if (st) st[2] = wall_clock64();
-  sweep<C, NT>(nd.U, X, nullptr, s_r, tid);
-  if (st) st[3] = wall_clock64();
-  // 3a. slack-cost rank-one term: s = grad P_ref . tangent
+}
+
+// Tensor projection (Sec. 4.2) with the state tangent Z: the slack-cost
+// rank-one scalar, then per bus the branch second-order terms; the x part
+// goes negated into Yx, the p part into the output.  Ends with a barrier.
+template <int C, int NT>
+__device__ __forceinline__ void projection(const NetDesc &nd, const WorkItem &a,
+                                           const double *__restrict__ Z, double *__restrict__ Yx,
+                                           double *s_slack, int32_t dir0, int tid) {
   if (tid < C) {
     const int c = tid;
     double s = 0.0;
     for (int32_t q = 0; q < nd.n_slack; ++q) {
       const int32_t tx = nd.slack_thx[q], vs = nd.slack_vs[q];
-      const double dth = tx >= 0 ? X[tx * C + c] : 0.0;
-      const double dv = vs >= 0 ? X[vs * C + c] : w_at(a, -vs - 1, dir0 + c);
+      const double dth = tx >= 0 ? Z[tx * C + c] : 0.0;
+      const double dv = vs >= 0 ? Z[vs * C + c] : w_at(a, -vs - 1, dir0 + c);
       s += nd.slack_gth[q] * dth + nd.slack_gv[q] * dv;
     }
     s_slack[c] = s;
   }
   __syncthreads();
-  // 3b. per-bus gather of the branch second-order terms
   for (int32_t e = tid; e < nd.n_bus; e += NT) {
     const int32_t tx = nd.bus_thx[e], vs = nd.bus_vs[e];
     const double ve = nd.bus_v[e], sth = nd.bus_sth[e], sv = nd.bus_sv[e];
     double dte[C], dve[C], yth[C], yv[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-      dte[c] = tx >= 0 ? X[tx * C + c] : 0.0;
-      dve[c] = vs >= 0 ? X[vs * C + c] : w_at(a, -vs - 1, dir0 + c);
+      dte[c] = tx >= 0 ? Z[tx * C + c] : 0.0;
+      dve[c] = vs >= 0 ? Z[vs * C + c] : w_at(a, -vs - 1, dir0 + c);
       yth[c] = sth * s_slack[c];
       yv[c] = sv * s_slack[c];
     }
@@ -292,8 +339,8 @@ __device__ __forceinline__ void reduction(const NetDesc &nd, const BlockArgs &a,
       const double vo = nd.inc_vo[q];
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        const double dto = ot >= 0 ? X[ot * C + c] : 0.0;
-        const double dvo = ov >= 0 ? X[ov * C + c] : w_at(a, -ov - 1, dir0 + c);
+        const double dto = ot >= 0 ? Z[ot * C + c] : 0.0;
+        const double dvo = ov >= 0 ? Z[ov * C + c] : w_at(a, -ov - 1, dir0 + c);
         const double dd = dte[c] - dto;
         yth[c] += -K * dd + hps * (vo * dve[c] + ve * dvo);
         yv[c] += hps * vo * dd + A2 * dve[c] + H * dvo;
@@ -315,13 +362,12 @@ __device__ __forceinline__ void reduction(const NetDesc &nd, const BlockArgs &a,
       if (dir0 + c < a.k) a.HW[(int64_t)(dir0 + c) * a.ldhw + q] = nd.pg_c2x2[g] * w_at(a, q, dir0 + c);
   }
   __syncthreads();
-  if (st) st[4] = wall_clock64();
-  // 4. Psi' = L^{-T} U^{-T} (-P Y_x)
-  sweep<C, NT>(nd.Ut, X, Yx, s_r, tid);
-  if (st) st[5] = wall_clock64();
-  sweep<C, NT>(nd.Lt, X, nullptr, s_r, tid);
-  if (st) st[6] = wall_clock64();
-  // 5. H W = Y_p + G_p^T Psi
+}
+
+// SpMulAdd: H W += G_p^T Psi.
+template <int C, int NT>
+__device__ __forceinline__ void spmuladd(const NetDesc &nd, const WorkItem &a,
+                                         const double *__restrict__ Psi, int32_t dir0, int tid) {
   for (int32_t q = tid; q < nd.n_p; q += NT) {
     double acc[C];
 #pragma unroll
@@ -330,59 +376,176 @@ __device__ __forceinline__ void reduction(const NetDesc &nd, const BlockArgs &a,
       const double v = nd.gpt_val[e];
       const int32_t j = nd.gpt_col[e] * C;
 #pragma unroll
-      for (int c = 0; c < C; ++c) acc[c] = fma(v, X[j + c], acc[c]);
+      for (int c = 0; c < C; ++c) acc[c] = fma(v, Psi[j + c], acc[c]);
     }
 #pragma unroll
     for (int c = 0; c < C; ++c)
       if (dir0 + c < a.k) a.HW[(int64_t)(dir0 + c) * a.ldhw + q] += acc[c];
   }
+}
+
+template <int C, int NT>
+__device__ __forceinline__ void reduction(const NetDesc &nd, const WorkItem &a, double *__restrict__ X,
+                                          double *__restrict__ Yx, double *s_slack, double *s_r,
+                                          int32_t dir0, long long *stamps) {
+  const int tid = threadIdx.x;
+  // optional phase timestamps (thread 0)
+  long long *st = (stamps && tid == 0) ? stamps : nullptr;
+  if (st) st[0] = wall_clock64();
+  // 1. B' = -P G_p W
+  spmul<C, NT>(nd, a, X, dir0, tid);
+  __syncthreads();
+  if (st) st[1] = wall_clock64();
+  // 2. Z' = U^{-1} L^{-1} B'
+  sweep<C, NT, double>(nd.L, X, nullptr, s_r, tid);
+  if (st) st[2] = wall_clock64();
+  sweep<C, NT, double>(nd.U, X, nullptr, s_r, tid);
+  if (st) st[3] = wall_clock64();
+  // 3. tensor projection: -Y_x into Yx, Y_p into the output
+  projection<C, NT>(nd, a, X, Yx, s_slack, dir0, tid);
+  if (st) st[4] = wall_clock64();
+  // 4. Psi' = L^{-T} U^{-T} (-P Y_x)
+  sweep<C, NT, double>(nd.Ut, X, Yx, s_r, tid);
+  if (st) st[5] = wall_clock64();
+  sweep<C, NT, double>(nd.Lt, X, nullptr, s_r, tid);
+  if (st) st[6] = wall_clock64();
+  // 5. H W = Y_p + G_p^T Psi
+  spmuladd<C, NT>(nd, a, X, dir0, tid);
+  __syncthreads();
+  if (st) st[7] = wall_clock64();
+}
+
+// Refined mode (FP32 sweeps, FP64 residuals).  Each of the two solves is
+//   x = solve32(b);  repeat `refine` times: x += solve32(b - A x)
+// with the residual b - A x formed in FP64 from G_x (or G_x^T) and x kept in
+// FP64; the tensor projection, G_p products and all stored vectors are FP64.
+// Scratch: V1 (right-hand sides: -G_p W, then -Y_x) and V2 (Z, then Psi),
+// both FP64 in global memory; X32 holds the FP32 correction being solved.
+template <int C, int NT, bool TRANS>
+__device__ __forceinline__ void refined_solve(const NetDesc &nd, const double *__restrict__ V1,
+                                              double *__restrict__ V2, float *__restrict__ X32,
+                                              float *s_r, int refine, int tid) {
+  const DevSweep &s1 = TRANS ? nd.Ut : nd.L;
+  const DevSweep &s2 = TRANS ? nd.Lt : nd.U;
+  const int32_t *ptr = TRANS ? nd.gxt_ptr : nd.gx_ptr;
+  const int32_t *col = TRANS ? nd.gxt_col : nd.gx_col;
+  const double *val = TRANS ? nd.gxt_val : nd.gx_val;
+  for (int it = 0; it <= refine; ++it) {
+    for (int32_t i = tid; i < nd.n_x; i += NT) {
+      double r[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) r[c] = V1[i * C + c];
+      if (it > 0)
+        for (int32_t e = ptr[i]; e < ptr[i + 1]; ++e) {
+          const double v = val[e];
+          const int32_t j = col[e] * C;
+#pragma unroll
+          for (int c = 0; c < C; ++c) r[c] = fma(-v, V2[j + c], r[c]);
+        }
+#pragma unroll
+      for (int c = 0; c < C; ++c) X32[i * C + c] = (float)r[c];
+    }
+    __syncthreads();
+    sweep<C, NT, float>(s1, X32, nullptr, s_r, tid);
+    sweep<C, NT, float>(s2, X32, nullptr, s_r, tid);
+    for (int32_t i = tid; i < nd.n_x; i += NT) {
+#pragma unroll
+      for (int c = 0; c < C; ++c)
+        V2[i * C + c] = (it ? V2[i * C + c] : 0.0) + (double)X32[i * C + c];
+    }
+    __syncthreads();
+  }
+}
+
+template <int C, int NT>
+__device__ __forceinline__ void reduction_refined(const NetDesc &nd, const WorkItem &a,
+                                                  float *__restrict__ X32, double *__restrict__ V1,
+                                                  double *__restrict__ V2, double *s_slack, float *s_r,
+                                                  int refine, int32_t dir0, long long *stamps) {
+  const int tid = threadIdx.x;
+  long long *st = (stamps && tid == 0) ? stamps : nullptr;
+  if (st) st[0] = wall_clock64();
+  spmul<C, NT>(nd, a, V1, dir0, tid);
+  __syncthreads();
+  if (st) st[1] = wall_clock64();
+  refined_solve<C, NT, false>(nd, V1, V2, X32, s_r, refine, tid);  // Z
+  if (st) st[2] = st[3] = wall_clock64();
+  projection<C, NT>(nd, a, V2, V1, s_slack, dir0, tid);  // V1 = -Y_x
+  if (st) st[4] = wall_clock64();
+  refined_solve<C, NT, true>(nd, V1, V2, X32, s_r, refine, tid);  // Psi
+  if (st) st[5] = st[6] = wall_clock64();
+  spmuladd<C, NT>(nd, a, V2, dir0, tid);
   __syncthreads();
   if (st) st[7] = wall_clock64();
 }
 
 // X in LDS (dynamic shared memory of n_x * C doubles); Y_x in global scratch.
 template <int C>
-__global__ __launch_bounds__(kThreadsLds) void block_kernel_lds(const NetDesc nd, const BlockArgs a) {
+__global__ __launch_bounds__(kThreadsLds) void block_kernel_lds(const LaunchArgs la) {
   extern __shared__ double smem[];
   __shared__ double s_slack[C];
   __shared__ double s_r[kBlockRows * C];
-  double *Yx = a.scratch + (int64_t)blockIdx.x * a.scratch_stride;
-  const int32_t n_chunks = (a.k + C - 1) / C;
-  for (int32_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x)
-    reduction<C, kThreadsLds>(nd, a, smem, Yx, s_slack, s_r, chunk * C);
+  double *Yx = la.scratch + (int64_t)blockIdx.x * la.scratch_stride;
+  for (int32_t chunk = blockIdx.x; chunk < la.n_chunks; chunk += gridDim.x) {
+    const WorkItem it = item_of(la, chunk);
+    long long *st = (la.stamps && chunk == (int32_t)blockIdx.x)
+                        ? la.stamps + (int64_t)blockIdx.x * kStamps : nullptr;
+    reduction<C, kThreadsLds>(*it.nd, it, smem, Yx, s_slack, s_r, (chunk - it.chunk0) * C, st);
+  }
 }
 
 // X and Y_x in global scratch (networks whose vector does not fit in LDS).
 template <int C>
-__global__ __launch_bounds__(kThreads) void block_kernel_global(const NetDesc nd, const BlockArgs a) {
+__global__ __launch_bounds__(kThreads) void block_kernel_global(const LaunchArgs la) {
   __shared__ double s_slack[C];
   __shared__ double s_r[kBlockRows * C];
-  double *Yx = a.scratch + (int64_t)blockIdx.x * a.scratch_stride;
-  double *X = Yx + (int64_t)nd.n_x * C;
-  const int32_t n_chunks = (a.k + C - 1) / C;
-  for (int32_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x)
-    reduction<C, kThreads>(nd, a, X, Yx, s_slack, s_r, chunk * C);
+  double *Yx = la.scratch + (int64_t)blockIdx.x * la.scratch_stride;
+  double *X = Yx + la.scratch_stride / 2;
+  for (int32_t chunk = blockIdx.x; chunk < la.n_chunks; chunk += gridDim.x) {
+    const WorkItem it = item_of(la, chunk);
+    long long *st = (la.stamps && chunk == (int32_t)blockIdx.x)
+                        ? la.stamps + (int64_t)blockIdx.x * kStamps : nullptr;
+    reduction<C, kThreads>(*it.nd, it, X, Yx, s_slack, s_r, (chunk - it.chunk0) * C, st);
+  }
+}
+
+// Refined mode, FP32 correction vector in LDS (n_x * C floats).
+template <int C>
+__global__ __launch_bounds__(kThreadsLds) void refined_kernel_lds(const LaunchArgs la) {
+  extern __shared__ float smem32[];
+  __shared__ double s_slack[C];
+  __shared__ float s_r[kBlockRows * C];
+  double *V1 = la.scratch + (int64_t)blockIdx.x * la.scratch_stride;
+  double *V2 = V1 + la.scratch_stride / 2;
+  for (int32_t chunk = blockIdx.x; chunk < la.n_chunks; chunk += gridDim.x) {
+    const WorkItem it = item_of(la, chunk);
+    long long *st = (la.stamps && chunk == (int32_t)blockIdx.x)
+                        ? la.stamps + (int64_t)blockIdx.x * kStamps : nullptr;
+    reduction_refined<C, kThreadsLds>(*it.nd, it, smem32, V1, V2, s_slack, s_r, la.refine,
+                                      (chunk - it.chunk0) * C, st);
+  }
+}
+
+// Refined mode with every vector in global scratch.
+template <int C>
+__global__ __launch_bounds__(kThreads) void refined_kernel_global(const LaunchArgs la) {
+  __shared__ double s_slack[C];
+  __shared__ float s_r[kBlockRows * C];
+  double *V1 = la.scratch + (int64_t)blockIdx.x * la.scratch_stride;
+  double *V2 = V1 + la.scratch_stride / 3;
+  float *X32 = reinterpret_cast<float *>(V1 + 2 * (la.scratch_stride / 3));
+  for (int32_t chunk = blockIdx.x; chunk < la.n_chunks; chunk += gridDim.x) {
+    const WorkItem it = item_of(la, chunk);
+    long long *st = (la.stamps && chunk == (int32_t)blockIdx.x)
+                        ? la.stamps + (int64_t)blockIdx.x * kStamps : nullptr;
+    reduction_refined<C, kThreads>(*it.nd, it, X32, V1, V2, s_slack, s_r, la.refine,
+                                   (chunk - it.chunk0) * C, st);
+  }
 }
 
 }  // namespace
 
-// ----------------------------------------------------------------- device net
-struct DeviceNet {
-  NetDesc nd{};
-  std::vector<void *> allocs;
-  double *scratch = nullptr;
-  size_t scratch_bytes = 0;
-  int32_t n_sms = 0;
-  size_t lds_max = 0;  // dynamic LDS a workgroup may use
-  // start/stop events of the launches of the current call (timing on)
-  std::vector<hipEvent_t> ev;
-  size_t ev_used = 0;
-  // in-kernel phase stamps of the last launch (timing level 2)
-  long long *stamps = nullptr;
-  int32_t stamps_cap = 0, stamps_groups = 0;
-  double wall_khz = 0.0;
-};
-
+// ----------------------------------------------------------------- runtime
 namespace {
 
 #define HIP_TRY(expr)                                                          \
@@ -393,6 +556,265 @@ namespace {
       return RH_EDEVICE;                                                       \
     }                                                                          \
   } while (0)
+
+struct DeviceInfo {
+  int device = -1;
+  int cus = 0;
+  size_t lds_max = 0;  // dynamic LDS a workgroup may use
+  double wall_khz = 0.0;
+};
+
+// Launch resources: per-workgroup scratch, timing events, phase stamps and the
+// device copy of a work list.  A network owns one (its own calls); a context
+// owns one for batched calls.
+struct Runner {
+  double *scratch = nullptr;
+  size_t scratch_bytes = 0;
+  std::vector<hipEvent_t> ev;  // start/stop pairs of the launches since the last report
+  size_t ev_used = 0;
+  long long *stamps = nullptr;
+  int32_t stamps_cap = 0, stamps_groups = 0;
+  WorkItem *items_dev = nullptr, *items_host = nullptr;
+  int32_t items_cap = 0;
+  hipEvent_t items_done = nullptr;  // the last launch that read the work list
+  int32_t launches = 0, last_c = 0;
+};
+
+rh_status query_info(int device, DeviceInfo &info, std::string &err) {
+  int cus = 0, lds_a = 0, lds_b = 0, wkhz = 0;
+  HIP_TRY(hipDeviceGetAttribute(&wkhz, hipDeviceAttributeWallClockRate, device));
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+  HIP_TRY(hipDeviceGetAttribute(&lds_a, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
+  HIP_TRY(hipDeviceGetAttribute(&lds_b, hipDeviceAttributeSharedMemPerBlockOptin, device));
+  info.device = device;
+  info.cus = cus;
+  info.wall_khz = wkhz;
+  // leave room for the kernels' static LDS (slack scalars and block residuals)
+  const size_t lds = (size_t)std::max(lds_a, lds_b);
+  const size_t fixed = (size_t)kBlockRows * 8 * sizeof(double) + 256;
+  info.lds_max = lds > fixed ? lds - fixed : 0;
+  return RH_OK;
+}
+
+void runner_free(Runner &r) {
+  if (r.scratch) (void)hipFree(r.scratch);
+  for (hipEvent_t e : r.ev) (void)hipEventDestroy(e);
+  if (r.stamps) (void)hipFree(r.stamps);
+  if (r.items_dev) (void)hipFree(r.items_dev);
+  if (r.items_host) (void)hipHostFree(r.items_host);
+  if (r.items_done) (void)hipEventDestroy(r.items_done);
+  r = Runner();
+}
+
+// Summed launch durations (and mean phase times) since the previous call.
+rh_status runner_collect(Runner &r, const DeviceInfo &info, rh_report &rep, std::string &err) {
+  rep.last_kernel_ms = -1.0;
+  rep.last_launches = r.launches;
+  rep.dirs_per_group = r.last_c;
+  if (r.stamps_groups > 0 && info.wall_khz > 0) {
+    std::vector<long long> st((size_t)r.stamps_groups * kStamps);
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(st.data(), r.stamps, st.size() * sizeof(long long), hipMemcpyDeviceToHost));
+    for (int p = 0; p < 7; ++p) {
+      double sum = 0.0;
+      for (int32_t g = 0; g < r.stamps_groups; ++g)
+        sum += (double)(st[(size_t)g * kStamps + p + 1] - st[(size_t)g * kStamps + p]);
+      rep.phase_us[p] = sum / r.stamps_groups / info.wall_khz * 1e3;
+    }
+    r.stamps_groups = 0;
+  }
+  if (r.ev_used > 0) {
+    double sum = 0.0;
+    for (size_t i = 0; i + 1 < r.ev_used; i += 2) {
+      HIP_TRY(hipEventSynchronize(r.ev[i + 1]));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, r.ev[i], r.ev[i + 1]));
+      sum += ms;
+    }
+    rep.last_kernel_ms = sum;
+  }
+  r.ev_used = 0;
+  r.launches = 0;
+  return RH_OK;
+}
+
+template <int C>
+rh_status launch(bool lds, bool refined, int32_t groups, size_t lds_bytes, hipStream_t s,
+                 const LaunchArgs &la, std::string &err) {
+  if (refined) {
+    if constexpr (C <= 4) {
+      if (lds) {
+        HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&refined_kernel_lds<C>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+        hipLaunchKernelGGL(refined_kernel_lds<C>, dim3(groups), dim3(kThreadsLds), lds_bytes, s, la);
+        HIP_TRY(hipGetLastError());
+        return RH_OK;
+      }
+    }
+    hipLaunchKernelGGL(refined_kernel_global<C>, dim3(groups), dim3(kThreads), 0, s, la);
+    HIP_TRY(hipGetLastError());
+    return RH_OK;
+  }
+  if constexpr (C <= 4) {
+    if (lds) {
+      HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&block_kernel_lds<C>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+      hipLaunchKernelGGL(block_kernel_lds<C>, dim3(groups), dim3(kThreadsLds), lds_bytes, s, la);
+      HIP_TRY(hipGetLastError());
+      return RH_OK;
+    }
+  }
+  hipLaunchKernelGGL(block_kernel_global<C>, dim3(groups), dim3(kThreads), 0, s, la);
+  HIP_TRY(hipGetLastError());
+  return RH_OK;
+}
+
+// Directions per workgroup: more share each factor entry, fewer keep the chip
+// busy.  Take the largest C (<= 8; <= 4 with the 1024-thread LDS kernel) that
+// still gives two workgroups per CU and whose vectors fit the LDS budget.
+// The choice does not change any direction's arithmetic.
+int32_t choose_c(int64_t k, int32_t cus, int64_t n_x, size_t lds_max, bool lds, size_t elem) {
+  if (const char *e = std::getenv("RH_DIRS_PER_GROUP")) {
+    const int v = std::atoi(e);
+    if ((v == 1 || v == 2 || v == 4 || (v == 8 && !lds)) && (!lds || (size_t)n_x * v * elem <= lds_max))
+      return v;
+  }
+  int32_t c = lds ? 4 : 8;
+  while (c > 1 && (k < (int64_t)c * 2 * cus || (lds && (size_t)n_x * c * elem > lds_max))) c >>= 1;
+  return c;
+}
+
+// Launch the reduction over a list of work items (host copies; their nd
+// pointers are device descriptors).  max_nx is the largest n_x among them.
+rh_status run_items(const DeviceInfo &info, Runner &r, int32_t timing, int32_t refine,
+                    std::vector<WorkItem> &items, int32_t max_nx, hipStream_t s, std::string &err) {
+  int64_t total_k = 0;
+  for (const WorkItem &it : items) total_k += it.k;
+  if (total_k <= 0) return RH_OK;
+  const bool refined = refine >= 0;
+  const size_t elem = refined ? sizeof(float) : sizeof(double);  // LDS vector element
+  const bool lds = (size_t)max_nx * elem <= info.lds_max && !std::getenv("RH_NO_LDS");
+  const int32_t C = choose_c(total_k, info.cus, max_nx, info.lds_max, lds, elem);
+  int64_t n_chunks = 0;
+  for (WorkItem &it : items) {
+    it.chunk0 = (int32_t)n_chunks;
+    n_chunks += (it.k + C - 1) / C;
+  }
+  if (n_chunks > INT32_MAX) {
+    err = "too many directions in one launch";
+    return RH_EINVAL;
+  }
+  // per-workgroup scratch, 256-byte aligned: FP64 mode Y_x (+ X when it is
+  // not in LDS); refined mode V1, V2 (+ the FP32 correction when not in LDS)
+  const int64_t parts = refined ? (lds ? 2 : 3) : (lds ? 1 : 2);
+  const int64_t stride = (parts * max_nx * C + 31) / 32 * 32 * (refined ? 1 : 1);
+  const int64_t max_groups_mem = std::max<int64_t>(1, (int64_t(8) << 30) / (stride * 8));
+  const int64_t per_cu = lds ? 1 : 4;
+  const int32_t groups = (int32_t)std::min<int64_t>({n_chunks, max_groups_mem, (int64_t)info.cus * 8 * per_cu});
+  const size_t need = (size_t)groups * stride * sizeof(double);
+  if (need > r.scratch_bytes) {
+    HIP_TRY(hipStreamSynchronize(s));  // earlier work on this stream may still use it
+    if (r.scratch) HIP_TRY(hipFree(r.scratch));
+    r.scratch = nullptr;
+    r.scratch_bytes = 0;
+    void *p = nullptr;
+    HIP_TRY(hipMalloc(&p, need));
+    r.scratch = (double *)p;
+    r.scratch_bytes = need;
+  }
+  LaunchArgs la{};
+  la.refine = refine;
+  la.n_items = (int32_t)items.size();
+  la.n_chunks = (int32_t)n_chunks;
+  la.scratch = r.scratch;
+  la.scratch_stride = stride;
+  if (items.size() == 1) {
+    la.items = nullptr;
+    la.one = items[0];
+  } else {
+    if ((int32_t)items.size() > r.items_cap) {
+      HIP_TRY(hipStreamSynchronize(s));
+      if (r.items_dev) HIP_TRY(hipFree(r.items_dev));
+      if (r.items_host) HIP_TRY(hipHostFree(r.items_host));
+      r.items_dev = r.items_host = nullptr;
+      r.items_cap = 0;
+      HIP_TRY(hipMalloc(&r.items_dev, items.size() * sizeof(WorkItem)));
+      HIP_TRY(hipHostMalloc(&r.items_host, items.size() * sizeof(WorkItem), hipHostMallocDefault));
+      r.items_cap = (int32_t)items.size();
+    }
+    if (!r.items_done) HIP_TRY(hipEventCreateWithFlags(&r.items_done, hipEventDisableTiming));
+    HIP_TRY(hipEventSynchronize(r.items_done));  // the previous list is no longer read
+    std::memcpy(r.items_host, items.data(), items.size() * sizeof(WorkItem));
+    HIP_TRY(hipMemcpyAsync(r.items_dev, r.items_host, items.size() * sizeof(WorkItem),
+                           hipMemcpyHostToDevice, s));
+    la.items = r.items_dev;
+  }
+  la.stamps = nullptr;
+  if (timing >= 2) {
+    if (r.stamps_cap < groups) {
+      HIP_TRY(hipStreamSynchronize(s));
+      if (r.stamps) HIP_TRY(hipFree(r.stamps));
+      r.stamps = nullptr;
+      r.stamps_cap = 0;
+      HIP_TRY(hipMalloc(&r.stamps, (size_t)groups * kStamps * sizeof(long long)));
+      r.stamps_cap = groups;
+    }
+    la.stamps = r.stamps;
+    r.stamps_groups = groups;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (timing >= 1) {
+    while (r.ev.size() < r.ev_used + 2) {
+      hipEvent_t e;
+      HIP_TRY(hipEventCreate(&e));
+      r.ev.push_back(e);
+    }
+    e0 = r.ev[r.ev_used];
+    e1 = r.ev[r.ev_used + 1];
+    r.ev_used += 2;
+    HIP_TRY(hipEventRecord(e0, s));
+  }
+  const size_t lds_bytes = lds ? (size_t)max_nx * C * elem : 0;
+  rh_status st;
+  switch (C) {
+    case 1: st = launch<1>(lds, refined, groups, lds_bytes, s, la, err); break;
+    case 2: st = launch<2>(lds, refined, groups, lds_bytes, s, la, err); break;
+    case 4: st = launch<4>(lds, refined, groups, lds_bytes, s, la, err); break;
+    default: st = launch<8>(lds, refined, groups, lds_bytes, s, la, err); break;
+  }
+  if (st != RH_OK) return st;
+  if (items.size() > 1) HIP_TRY(hipEventRecord(r.items_done, s));
+  if (timing >= 1) HIP_TRY(hipEventRecord(e1, s));
+  r.launches += 1;
+  r.last_c = C;
+  return RH_OK;
+}
+
+}  // namespace
+
+struct DeviceNet {
+  NetDesc nd{};               // host copy of the descriptor (device pointers)
+  NetDesc *nd_dev = nullptr;  // the same descriptor in device memory
+  std::vector<void *> allocs;
+  DeviceInfo info;
+  Runner run;
+};
+
+// A context's resources for batched launches: one runner per stream, since
+// launches on one stream are ordered and may share scratch, while launches on
+// different streams may overlap.
+struct DeviceCtx {
+  DeviceInfo info;
+  std::vector<std::pair<void *, Runner>> runs;
+  Runner &on(void *stream) {
+    for (auto &pr : runs)
+      if (pr.first == stream) return pr.second;
+    runs.emplace_back(stream, Runner());
+    return runs.back().second;
+  }
+};
+
+namespace {
 
 template <class T>
 rh_status upload(DeviceNet &dn, const std::vector<T> &v, const T **out, std::string &err) {
@@ -429,6 +851,15 @@ rh_status upload_sweep(DeviceNet *dn, const Sweep &s, int32_t n, int bmax, DevSw
   if (!sc.s.dinv.empty()) UP(sc.s.dinv, o.dinv);
   o.dense = nullptr;
   if (!sc.dense.empty()) UP(sc.dense, o.dense);
+  // FP32 copies for the refined mode
+  const std::vector<float> v32(sc.s.val.begin(), sc.s.val.end());
+  const std::vector<float> d32(sc.s.dinv.begin(), sc.s.dinv.end());
+  const std::vector<float> m32(sc.dense.begin(), sc.dense.end());
+  UP(v32, o.val32);
+  o.dinv32 = nullptr;
+  if (!d32.empty()) UP(d32, o.dinv32);
+  o.dense32 = nullptr;
+  if (!m32.empty()) UP(m32, o.dense32);
   return RH_OK;
 }
 
@@ -443,69 +874,64 @@ void device_free(Network &net) {
   if (!net.dev) return;
   (void)hipDeviceSynchronize();
   for (void *p : net.dev->allocs) (void)hipFree(p);
-  if (net.dev->scratch) (void)hipFree(net.dev->scratch);
-  for (hipEvent_t e : net.dev->ev) (void)hipEventDestroy(e);
-  if (net.dev->stamps) (void)hipFree(net.dev->stamps);
+  runner_free(net.dev->run);
   delete net.dev;
   net.dev = nullptr;
 }
 
-void device_take_timing(Network &net) {
-  if (net.dev) net.dev->ev_used = 0;
-  net.report.last_launches = 0;
+void device_ctx_free(Context &ctx) {
+  if (!ctx.dev) return;
+  (void)hipDeviceSynchronize();
+  for (auto &pr : ctx.dev->runs) runner_free(pr.second);
+  delete ctx.dev;
+  ctx.dev = nullptr;
 }
 
-rh_status device_kernel_ms(Network &net, double *ms_out, std::string &err) {
-  *ms_out = -1.0;
-  DeviceNet *dn = net.dev;
-  if (!dn) return RH_OK;
-  if (dn->stamps_groups > 0 && dn->wall_khz > 0) {
-    std::vector<long long> st((size_t)dn->stamps_groups * kStamps);
-    HIP_TRY(hipDeviceSynchronize());
-    HIP_TRY(hipMemcpy(st.data(), dn->stamps, st.size() * sizeof(long long), hipMemcpyDeviceToHost));
-    for (int p = 0; p < 7; ++p) {
-      double sum = 0.0;
-      for (int32_t g = 0; g < dn->stamps_groups; ++g)
-        sum += (double)(st[(size_t)g * kStamps + p + 1] - st[(size_t)g * kStamps + p]);
-      net.report.phase_us[p] = sum / dn->stamps_groups / dn->wall_khz * 1e3;
+rh_status device_collect(Network &net, std::string &err) {
+  if (!net.dev) return RH_OK;
+  return runner_collect(net.dev->run, net.dev->info, net.report, err);
+}
+
+rh_status device_ctx_collect(Context &ctx, rh_report &rep, std::string &err) {
+  rep.last_kernel_ms = -1.0;
+  if (!ctx.dev) return RH_OK;
+  // sum over the streams' runners
+  rh_report total = rep;
+  total.last_launches = 0;
+  double ms = 0.0;
+  bool any_ms = false;
+  for (auto &pr : ctx.dev->runs) {
+    rh_report r = rep;
+    rh_status s = runner_collect(pr.second, ctx.dev->info, r, err);
+    if (s != RH_OK) return s;
+    total.last_launches += r.last_launches;
+    if (r.last_kernel_ms >= 0) {
+      ms += r.last_kernel_ms;
+      any_ms = true;
     }
-    dn->stamps_groups = 0;
+    if (r.last_launches > 0) {
+      total.dirs_per_group = r.dirs_per_group;
+      for (int p = 0; p < 7; ++p) total.phase_us[p] = r.phase_us[p];
+    }
   }
-  if (dn->ev_used == 0) return RH_OK;
-  double sum = 0.0;
-  for (size_t i = 0; i + 1 < dn->ev_used; i += 2) {
-    HIP_TRY(hipEventSynchronize(dn->ev[i + 1]));
-    float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, dn->ev[i], dn->ev[i + 1]));
-    sum += ms;
-  }
-  *ms_out = sum;
+  total.last_kernel_ms = any_ms ? ms : -1.0;
+  rep = total;
   return RH_OK;
 }
 
 rh_status device_upload(Network &net, std::string &err) {
   HIP_TRY(hipSetDevice(net.ctx->device));
-  size_t keep_bytes = 0;
-  double *keep = nullptr;
-  if (net.dev) {  // keep the scratch buffer across operating points
-    keep = net.dev->scratch;
-    keep_bytes = net.dev->scratch_bytes;
-    net.dev->scratch = nullptr;
+  Runner keep;  // keep the launch resources across operating points
+  if (net.dev) {
+    keep = net.dev->run;
+    net.dev->run = Runner();
     device_free(net);
   }
   DeviceNet *dn = new DeviceNet();
   net.dev = dn;
-  dn->scratch = keep;
-  dn->scratch_bytes = keep_bytes;
-  int cus = 0, lds_a = 0, lds_b = 0, wkhz = 0;
-  HIP_TRY(hipDeviceGetAttribute(&wkhz, hipDeviceAttributeWallClockRate, net.ctx->device));
-  dn->wall_khz = wkhz;
-  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, net.ctx->device));
-  HIP_TRY(hipDeviceGetAttribute(&lds_a, hipDeviceAttributeMaxSharedMemoryPerBlock, net.ctx->device));
-  HIP_TRY(hipDeviceGetAttribute(&lds_b, hipDeviceAttributeSharedMemPerBlockOptin, net.ctx->device));
-  dn->n_sms = cus;
-  // leave room for the kernel's static LDS (the slack scalars)
-  dn->lds_max = (size_t)std::max(lds_a, lds_b) > 256 ? (size_t)std::max(lds_a, lds_b) - 256 : 0;
+  dn->run = keep;
+  rh_status qs = query_info(net.ctx->device, dn->info, err);
+  if (qs != RH_OK) return qs;
 
   NetDesc &nd = dn->nd;
   const LuPlan &lu = net.lu;
@@ -610,49 +1036,53 @@ rh_status device_upload(Network &net, std::string &err) {
     UP(idx, nd.pg_idx);
     UP(c2, nd.pg_c2x2);
   }
+  // G_x and G_x^T in permuted numbering (residuals of the refined mode)
+  {
+    const int32_t nx = net.n_x;
+    std::vector<std::vector<std::pair<int32_t, double>>> rows(nx), trows(nx);
+    for (int32_t r = 0; r < nx; ++r)
+      for (int32_t e = net.gx.ptr[r]; e < net.gx.ptr[r + 1]; ++e) {
+        const int32_t ip = lu.iperm[r], jp = lu.iperm[net.gx.col[e]];
+        rows[ip].push_back({jp, net.gx.val[e]});
+        trows[jp].push_back({ip, net.gx.val[e]});
+      }
+    for (int t = 0; t < 2; ++t) {
+      auto &R = t ? trows : rows;
+      std::vector<int32_t> ptr(nx + 1, 0), col;
+      std::vector<double> val;
+      for (int32_t i = 0; i < nx; ++i) {
+        std::sort(R[i].begin(), R[i].end());
+        for (auto &pr : R[i]) {
+          col.push_back(pr.first);
+          val.push_back(pr.second);
+        }
+        ptr[i + 1] = (int32_t)col.size();
+      }
+      if (t) {
+        UP(ptr, nd.gxt_ptr);
+        UP(col, nd.gxt_col);
+        UP(val, nd.gxt_val);
+      } else {
+        UP(ptr, nd.gx_ptr);
+        UP(col, nd.gx_col);
+        UP(val, nd.gx_val);
+      }
+    }
+  }
+  {
+    void *p = nullptr;
+    HIP_TRY(hipMalloc(&p, sizeof(NetDesc)));
+    dn->allocs.push_back(p);
+    HIP_TRY(hipMemcpy(p, &dn->nd, sizeof(NetDesc), hipMemcpyHostToDevice));
+    dn->nd_dev = static_cast<NetDesc *>(p);
+  }
   HIP_TRY(hipDeviceSynchronize());
   return RH_OK;
 }
 
-namespace {
-
-template <int C>
-rh_status launch(bool lds, int32_t groups, size_t lds_bytes, hipStream_t s, const NetDesc &nd,
-                 const BlockArgs &a, std::string &err) {
-  if constexpr (C <= 4) {
-    if (lds) {
-      HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&block_kernel_lds<C>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
-      hipLaunchKernelGGL(block_kernel_lds<C>, dim3(groups), dim3(kThreadsLds), lds_bytes, s, nd, a);
-      HIP_TRY(hipGetLastError());
-      return RH_OK;
-    }
-  }
-  hipLaunchKernelGGL(block_kernel_global<C>, dim3(groups), dim3(kThreads), 0, s, nd, a);
-  HIP_TRY(hipGetLastError());
-  return RH_OK;
-}
-
-// Directions per workgroup: more share each factor entry, fewer keep the chip
-// busy.  Take the largest C (<= 8) that still gives two workgroups per CU
-// and whose vector fits the LDS budget (the LDS variant).  The result does
-// not change any direction's arithmetic.
-int32_t choose_c(int32_t k, int32_t cus, int64_t n_x, size_t lds_max, bool lds) {
-  if (const char *e = std::getenv("RH_DIRS_PER_GROUP")) {
-    const int v = std::atoi(e);
-    if ((v == 1 || v == 2 || v == 4 || (v == 8 && !lds)) && (!lds || (size_t)n_x * v * 8 <= lds_max))
-      return v;
-  }
-  int32_t c = lds ? 4 : 8;  // (8 directions x 1024 threads would spill registers)
-  while (c > 1 && ((int64_t)k < (int64_t)c * 2 * cus || (lds && (size_t)n_x * c * 8 > lds_max)))
-    c >>= 1;
-  return c;
-}
-
-}  // namespace
-
 rh_status device_hvp(Network &net, int32_t k, const double *dW, int64_t ldw, double *dHW,
-                     int64_t ldhw, int32_t identity_from, void *stream, std::string &err) {
+                     int64_t ldhw, int32_t identity_from, rh_precision prec, void *stream,
+                     std::string &err) {
   DeviceNet *dn = net.dev;
   if (!dn) {
     err = "network has no device data (solve first)";
@@ -667,75 +1097,52 @@ rh_status device_hvp(Network &net, int32_t k, const double *dW, int64_t ldw, dou
     return RH_EINVAL;
   }
   HIP_TRY(hipSetDevice(net.ctx->device));
-  const bool lds = (size_t)net.n_x * 8 <= dn->lds_max && !std::getenv("RH_NO_LDS");
-  const int32_t C = choose_c(k, dn->n_sms, net.n_x, dn->lds_max, lds);
-  const int32_t n_chunks = (k + C - 1) / C;
-  // per-workgroup scratch: Y_x (and X when it is not in LDS), 256-byte aligned
-  const int64_t stride = ((lds ? 1LL : 2LL) * net.n_x * C + 31) / 32 * 32;
-  const int64_t max_groups_mem = std::max<int64_t>(1, (int64_t(8) << 30) / (stride * 8));
-  const int64_t per_cu = lds ? 1 : 4;
-  const int32_t groups = (int32_t)std::min<int64_t>({(int64_t)n_chunks, max_groups_mem,
-                                                     (int64_t)dn->n_sms * 8 * per_cu});
-  const size_t need = (size_t)groups * stride * sizeof(double);
-  if (need > dn->scratch_bytes) {
-    // the buffer may still be in use by earlier work on the same stream
-    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
-    if (dn->scratch) HIP_TRY(hipFree(dn->scratch));
-    dn->scratch = nullptr;
-    dn->scratch_bytes = 0;
-    void *p = nullptr;
-    HIP_TRY(hipMalloc(&p, need));
-    dn->scratch = (double *)p;
-    dn->scratch_bytes = need;
+  std::vector<WorkItem> items(1);
+  WorkItem &it = items[0];
+  it.nd = dn->nd_dev;
+  it.W = dW;
+  it.HW = dHW;
+  it.ldw = ldw;
+  it.ldhw = ldhw;
+  it.k = k;
+  it.identity_from = identity_from;
+  const int32_t refine = prec == RH_FP32_REFINED ? net.ctx->refine : -1;
+  rh_status s = run_items(dn->info, dn->run, net.ctx->timing, refine, items, net.n_x,
+                          (hipStream_t)stream, err);
+  net.report.dirs_per_group = dn->run.last_c;
+  return s;
+}
+
+rh_status device_hvp_batch(Context &ctx, int32_t n, Network *const *nets, const int32_t *k,
+                           const double *const *dW, const int64_t *ldw, double *const *dHW,
+                           const int64_t *ldhw, const int32_t *identity_from, rh_precision prec,
+                           void *stream, std::string &err) {
+  HIP_TRY(hipSetDevice(ctx.device));
+  if (!ctx.dev) {
+    ctx.dev = new DeviceCtx();
+    rh_status qs = query_info(ctx.device, ctx.dev->info, err);
+    if (qs != RH_OK) return qs;
   }
-  BlockArgs a;
-  a.k = k;
-  a.identity_from = identity_from;
-  a.W = dW;
-  a.ldw = ldw;
-  a.HW = dHW;
-  a.ldhw = ldhw;
-  a.scratch = dn->scratch;
-  a.scratch_stride = stride;
-  a.stamps = nullptr;
-  if (net.ctx->timing >= 2) {
-    if (dn->stamps_cap < groups) {
-      HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
-      if (dn->stamps) HIP_TRY(hipFree(dn->stamps));
-      dn->stamps = nullptr;
-      dn->stamps_cap = 0;
-      HIP_TRY(hipMalloc(&dn->stamps, (size_t)groups * kStamps * sizeof(long long)));
-      dn->stamps_cap = groups;
-    }
-    a.stamps = dn->stamps;
-    dn->stamps_groups = groups;
+  std::vector<WorkItem> items;
+  int32_t max_nx = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    Network &net = *nets[i];
+    if (k[i] == 0) continue;
+    WorkItem it{};
+    it.nd = net.dev->nd_dev;
+    it.W = dW[i];
+    it.HW = dHW[i];
+    it.ldw = ldw[i];
+    it.ldhw = ldhw[i];
+    it.k = k[i];
+    it.identity_from = identity_from ? identity_from[i] : -1;
+    items.push_back(it);
+    max_nx = std::max(max_nx, net.n_x);
   }
-  hipStream_t s = (hipStream_t)stream;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (net.ctx->timing) {
-    while (dn->ev.size() < dn->ev_used + 2) {
-      hipEvent_t e;
-      HIP_TRY(hipEventCreate(&e));
-      dn->ev.push_back(e);
-    }
-    e0 = dn->ev[dn->ev_used];
-    e1 = dn->ev[dn->ev_used + 1];
-    dn->ev_used += 2;
-    HIP_TRY(hipEventRecord(e0, s));
-  }
-  const size_t lds_bytes = lds ? (size_t)net.n_x * C * sizeof(double) : 0;
-  rh_status st;
-  switch (C) {
-    case 1: st = launch<1>(lds, groups, lds_bytes, s, dn->nd, a, err); break;
-    case 2: st = launch<2>(lds, groups, lds_bytes, s, dn->nd, a, err); break;
-    case 4: st = launch<4>(lds, groups, lds_bytes, s, dn->nd, a, err); break;
-    default: st = launch<8>(lds, groups, lds_bytes, s, dn->nd, a, err); break;
-  }
-  if (st != RH_OK) return st;
-  net.report.last_launches += 1;
-  net.report.dirs_per_group = C;
-  if (net.ctx->timing) HIP_TRY(hipEventRecord(e1, s));
-  return RH_OK;
+  if (items.empty()) return RH_OK;
+  const int32_t refine = prec == RH_FP32_REFINED ? ctx.refine : -1;
+  return run_items(ctx.dev->info, ctx.dev->on(stream), ctx.timing, refine, items, max_nx,
+                   (hipStream_t)stream, err);
 }
 
 rh_status device_alloc(void **p, size_t bytes, std::string &err) {

@@ -55,10 +55,13 @@ struct Schedule {
 };
 
 struct DeviceNet;  // defined by the device translation unit
+struct DeviceCtx;  // likewise: a context's resources for batched launches
 
 struct Context {
   int32_t device = -1;  // -1: host only
   int32_t timing = 0;  // 0 off, 1 launch events, 2 also in-kernel phase stamps
+  int32_t refine = 2;  // refined mode: correction steps after the first FP32 solve
+  DeviceCtx *dev = nullptr;
 };
 
 // Per-bus-incidence coefficients of the branch-wise Lagrangian Hessian.
@@ -126,10 +129,18 @@ Schedule build_schedule(const Sweep &in, int32_t n, int bmax, int block_rows, in
 // ---- device path (device.hip)
 rh_status device_upload(Network &net, std::string &err);
 void device_free(Network &net);
-void device_take_timing(Network &net);  // forget recorded launches
-rh_status device_kernel_ms(Network &net, double *ms, std::string &err);
+void device_ctx_free(Context &ctx);
+// Fill the report's launch count, summed kernel time and phase times of the
+// launches since the previous collection, and start a new window.
+rh_status device_collect(Network &net, std::string &err);
+rh_status device_ctx_collect(Context &ctx, rh_report &rep, std::string &err);
 rh_status device_hvp(Network &net, int32_t k, const double *dW, int64_t ldw, double *dHW,
-                     int64_t ldhw, int32_t identity_from, void *stream, std::string &err);
+                     int64_t ldhw, int32_t identity_from, rh_precision prec, void *stream,
+                     std::string &err);
+rh_status device_hvp_batch(Context &ctx, int32_t n, Network *const *nets, const int32_t *k,
+                           const double *const *dW, const int64_t *ldw, double *const *dHW,
+                           const int64_t *ldhw, const int32_t *identity_from, rh_precision prec,
+                           void *stream, std::string &err);
 rh_status device_set(int32_t device, std::string &err);
 rh_status device_memcpy_h2d(void *dst, const void *src, size_t bytes, std::string &err);
 rh_status device_memcpy_d2h(void *dst, const void *src, size_t bytes, std::string &err);

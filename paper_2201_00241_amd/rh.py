@@ -68,6 +68,7 @@ _SIGS = {
     "rh_context_create": (ctypes.c_int, [ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
     "rh_context_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "rh_context_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "rh_context_set_refinement": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "rh_network_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(rh_network_desc),
                                          ctypes.POINTER(ctypes.c_void_p)]),
     "rh_network_destroy": (ctypes.c_int, [ctypes.c_void_p]),
@@ -92,7 +93,15 @@ _SIGS = {
     "rh_reduced_hessian_device": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
                                                  ctypes.c_int64, ctypes.c_int32, ctypes.c_int,
                                                  ctypes.c_void_p]),
+    "rh_hvp_batch_device": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
+                                           ctypes.POINTER(ctypes.c_void_p), _i32p,
+                                           ctypes.POINTER(ctypes.c_void_p),
+                                           ctypes.POINTER(ctypes.c_int64),
+                                           ctypes.POINTER(ctypes.c_void_p),
+                                           ctypes.POINTER(ctypes.c_int64), _i32p,
+                                           ctypes.c_int, ctypes.c_void_p]),
     "rh_last_report": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(rh_report)]),
+    "rh_context_report": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(rh_report)]),
     "rh_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "rh_last_error": (ctypes.c_char_p, []),
 }
@@ -151,6 +160,10 @@ def rh_context_destroy(ctx) -> None:
 def rh_context_set_timing(ctx, level) -> None:
     """0 off, 1 launch events, 2 also in-kernel phase stamps."""
     _check(load().rh_context_set_timing(ctx, int(level)))
+
+
+def rh_context_set_refinement(ctx, steps: int) -> None:
+    _check(load().rh_context_set_refinement(ctx, int(steps)))
 
 
 def rh_network_create(ctx, grid):
@@ -273,6 +286,26 @@ def rh_reduced_hessian_device(net, dH_ptr, ldh, k_block=0, prec=RH_FP64, stream=
                                             int(prec), ctypes.c_void_p(stream or 0)))
 
 
+def rh_hvp_batch_device(ctx, nets, ks, dWs, ldws, dHWs, ldhws, identity_from=None,
+                        prec=RH_FP64, stream=None) -> None:
+    n = len(nets)
+    arr_v = ctypes.c_void_p * n
+    arr_l = ctypes.c_int64 * n
+    kk = np.ascontiguousarray(ks, dtype=np.int32)
+    idf = None if identity_from is None else np.ascontiguousarray(identity_from, dtype=np.int32)
+    _check(load().rh_hvp_batch_device(
+        ctx, n, arr_v(*[nn.value if isinstance(nn, ctypes.c_void_p) else nn for nn in nets]),
+        _p(kk, _i32p), arr_v(*[w or None for w in dWs]), arr_l(*ldws), arr_v(*dHWs),
+        arr_l(*ldhws), None if idf is None else _p(idf, _i32p), int(prec),
+        ctypes.c_void_p(stream or 0)))
+
+
+def rh_context_report(ctx) -> dict:
+    r = rh_report()
+    _check(load().rh_context_report(ctx, ctypes.byref(r)))
+    return r.as_dict()
+
+
 def rh_last_report(net) -> dict:
     r = rh_report()
     _check(load().rh_last_report(net, ctypes.byref(r)))
@@ -295,6 +328,19 @@ class Context:
 
     def set_timing(self, level=1):
         rh_context_set_timing(self.h, int(level))
+
+    def set_refinement(self, steps: int):
+        rh_context_set_refinement(self.h, steps)
+
+    def report(self):
+        return rh_context_report(self.h)
+
+    def hvp_batch_device(self, nets, Ws, HWs, stream=None, prec=RH_FP64):
+        """nets: Network objects; Ws/HWs: torch float64 CUDA tensors (k_i, n_p_i)."""
+        rh_hvp_batch_device(self.h, [n.h for n in nets], [W.shape[0] for W in Ws],
+                            [W.data_ptr() for W in Ws], [W.stride(0) for W in Ws],
+                            [H.data_ptr() for H in HWs], [H.stride(0) for H in HWs], None, prec,
+                            stream)
 
     def close(self):
         if self.h:

@@ -1,0 +1,187 @@
+"""Continuous-batching server for reduced-Hessian requests on one GPU.
+
+Requests ask for k Hessian-vector products of one resident network (a grid
+at an operating point whose LU factors, adjoint and branch coefficients stay
+on the device) or for its full reduced Hessian.  The server splits every
+request into work items of at most `block` directions (a full Hessian becomes
+identity blocks, Sec. 5.3) and keeps up to `max_inflight` batched launches in
+flight, each on its own stream.  Whenever a launch completes, the items that
+arrived meanwhile are admitted into the next launch, as far as the direction
+budget per launch and the device-memory budget allow; a request's blocks may
+be spread over several launches.  Every direction's arithmetic is independent
+of the launch it lands in, so a result is bitwise the same alone and in the
+mix.
+
+All computation runs in librh (rh_hvp_batch_device); this module only
+schedules, moves buffers and measures latency.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import rh
+
+
+@dataclass
+class Request:
+    rid: int
+    key: str                      # resident network
+    k: int                        # directions; 0 = the full reduced Hessian
+    W: np.ndarray | None = None   # host directions (n_p x k), None for a full Hessian
+    arrival: float = 0.0          # scheduled arrival, seconds from the start
+    # filled by the server
+    result: np.ndarray | None = None
+    t_first_launch: float = -1.0
+    t_done: float = -1.0
+    launches: int = 0
+    _dW: object = None
+    _dHW: object = None
+    _blocks_left: int = 0
+    _bytes: int = 0
+
+    @property
+    def latency(self) -> float:
+        return self.t_done - self.arrival
+
+
+@dataclass
+class _Item:
+    req: Request
+    j0: int
+    kb: int
+
+
+@dataclass
+class _Launch:
+    stream: object
+    event: object
+    items: list = field(default_factory=list)
+
+
+def footprint_bytes(n_p: int, k: int) -> int:
+    """Device bytes a request holds while admitted: its W and H W blocks."""
+    return (2 * k if k else n_p) * n_p * 8
+
+
+class Server:
+    def __init__(self, ctx: rh.Context, networks: dict, max_inflight: int = 3,
+                 dirs_per_launch: int = 4096, block: int = 256,
+                 mem_budget_bytes: int = 32 << 30):
+        import torch
+
+        self.torch = torch
+        self.ctx = ctx
+        self.nets = networks
+        self.max_inflight = max_inflight
+        self.dirs_per_launch = dirs_per_launch
+        self.block = block
+        self.mem_budget = mem_budget_bytes
+        self.streams = [torch.cuda.Stream() for _ in range(max_inflight)]
+
+    # ---- request life cycle -------------------------------------------------
+    def _admit(self, req: Request) -> bool:
+        """Allocate the request's device buffers if the memory budget allows."""
+        torch = self.torch
+        net = self.nets[req.key]
+        nbytes = footprint_bytes(net.n_p, req.k)
+        if self._mem_used + nbytes > self.mem_budget:
+            return False
+        kk = req.k if req.k else net.n_p
+        if req.k:
+            req._dW = torch.from_numpy(np.ascontiguousarray(np.asarray(req.W).T)).cuda()
+        req._dHW = torch.empty((kk, net.n_p), dtype=torch.float64, device="cuda")
+        req._bytes = nbytes
+        self._mem_used += nbytes
+        req._blocks_left = (kk + self.block - 1) // self.block
+        for j0 in range(0, kk, self.block):
+            self._items.append(_Item(req, j0, min(self.block, kk - j0)))
+        return True
+
+    def _launch(self, stream, items, now):
+        torch = self.torch
+        nets, ks, dWs, ldws, dHWs, ldhws, idf = [], [], [], [], [], [], []
+        for it in items:
+            r = it.req
+            net = self.nets[r.key]
+            nets.append(net.h)
+            ks.append(it.kb)
+            if r.k:
+                dWs.append(r._dW[it.j0].data_ptr())
+                ldws.append(r._dW.stride(0))
+                idf.append(-1)
+            else:
+                dWs.append(0)
+                ldws.append(net.n_p)
+                idf.append(it.j0)
+            dHWs.append(r._dHW[it.j0].data_ptr())
+            ldhws.append(r._dHW.stride(0))
+            if r.t_first_launch < 0:
+                r.t_first_launch = now
+            r.launches += 1
+        stream.wait_stream(torch.cuda.current_stream())  # uploads of admitted W blocks
+        with torch.cuda.stream(stream):
+            rh.rh_hvp_batch_device(self.ctx.h, nets, ks, dWs, ldws, dHWs, ldhws,
+                                   identity_from=idf, stream=stream.cuda_stream)
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        return _Launch(stream, ev, items)
+
+    def _finish(self, launch: _Launch, now: float, done: list):
+        for it in launch.items:
+            r = it.req
+            r._blocks_left -= 1
+            if r._blocks_left == 0:
+                r.t_done = now
+                r.result = r._dHW.cpu().numpy().T
+                r._dW = r._dHW = None
+                self._mem_used -= r._bytes
+                done.append(r)
+
+    # ---- event loop ---------------------------------------------------------
+    def run(self, requests: list, poll_s: float = 5e-5) -> list:
+        """Serve `requests` (arrival times relative to now); returns them completed."""
+        pending = deque(sorted(requests, key=lambda r: r.arrival))
+        waiting: deque = deque()     # arrived, not yet admitted
+        self._items: deque = deque()  # admitted blocks not yet launched
+        self._mem_used = 0
+        inflight: list = []
+        done: list = []
+        free_streams = list(self.streams)
+        t0 = time.perf_counter()
+        while pending or waiting or self._items or inflight:
+            now = time.perf_counter() - t0
+            while pending and pending[0].arrival <= now:
+                waiting.append(pending.popleft())
+            for L in list(inflight):
+                if L.event.query():
+                    inflight.remove(L)
+                    free_streams.append(L.stream)
+                    self._finish(L, time.perf_counter() - t0, done)
+            while waiting and self._admit(waiting[0]):
+                waiting.popleft()
+            if self._items and free_streams:
+                batch, dirs = [], 0
+                while self._items and dirs + self._items[0].kb <= self.dirs_per_launch:
+                    it = self._items.popleft()
+                    batch.append(it)
+                    dirs += it.kb
+                if not batch:  # one block larger than the budget: launch it alone
+                    batch.append(self._items.popleft())
+                inflight.append(self._launch(free_streams.pop(0), batch, now))
+                continue
+            if not inflight and not self._items and not waiting and pending:
+                time.sleep(max(0.0, min(pending[0].arrival - now, 1e-3)))
+            else:
+                time.sleep(poll_s)
+        self.torch.cuda.synchronize()
+        return done
+
+
+def latency_summary(reqs: list) -> dict:
+    lat = np.array([r.latency for r in reqs]) * 1e3
+    return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_ms": float(lat.mean()), "n": int(lat.size)}

@@ -187,3 +187,110 @@ def test_errors_do_not_launch(c1, rhmod):
     with pytest.raises(rhmod.RhError) as e:
         net.hvp(np.full((net.n_p, 2), np.nan))
     assert e.value.status == rhmod.RH_EINVAL
+
+
+def test_batched_instances_match_single_calls_bitwise(ctx, rhmod, c1):
+    """One launch over three networks (two operating points of the 1k grid and
+    the 9-bus grid) gives exactly the per-network results."""
+    import torch
+
+    g1, net1, s1 = c1
+    g2 = gridgen.perturb_loads(g1, seed=17)
+    net2 = rhmod.Network(ctx, g2)
+    net2.solve()
+    g3 = gridgen.config_grid("c0", 0)
+    net3 = rhmod.Network(ctx, g3)
+    net3.solve()
+    nets, ks = [net1, net2, net3], [37, 64, 5]
+    Ws = [torch.from_numpy(np.ascontiguousarray(gridgen.directions(n.n_p, k, 30 + i).T)).cuda()
+          for i, (n, k) in enumerate(zip(nets, ks))]
+    HWs = [torch.zeros_like(W) for W in Ws]
+    stream = torch.cuda.current_stream().cuda_stream
+    _say("batch: 1k + perturbed 1k + 9-bus in one launch")
+    ctx.hvp_batch_device(nets, Ws, HWs, stream=stream)
+    torch.cuda.synchronize()
+    assert ctx.report()["last_launches"] == 1
+    for n, W, HW in zip(nets, Ws, HWs):
+        ref = torch.zeros_like(W)
+        n.hvp_device(W, ref, stream=stream)
+        torch.cuda.synchronize()
+        assert torch.equal(HW, ref)
+    s2 = solve(g2)
+    assert _relerr(HWs[1].cpu().numpy().T, s2.hvp(Ws[1].cpu().numpy().T)) <= TOL
+
+
+def test_served_results_equal_solo_results(ctx, rhmod, c1):
+    """Continuous batching: each request's result is bitwise its solo result,
+    whatever it shared its launches with; full Hessians match the oracle."""
+    import torch
+
+    from paper_2201_00241_amd.serving import Request, Server
+
+    g1, net1, s1 = c1
+    g2 = gridgen.perturb_loads(g1, seed=23)
+    net2 = rhmod.Network(ctx, g2)
+    net2.solve()
+    g3 = gridgen.config_grid("c0", 1)
+    net3 = rhmod.Network(ctx, g3)
+    net3.solve()
+    nets = {"a": net1, "b": net2, "c": net3}
+    rng = np.random.default_rng(3)
+    reqs = []
+    for i in range(14):
+        key = "abc"[i % 3]
+        k = [1, 16, 0, 40][i % 4]
+        W = None if k == 0 else gridgen.directions(nets[key].n_p, k, 100 + i)
+        reqs.append(Request(rid=i, key=key, k=k, W=W, arrival=float(rng.exponential(2e-4) * i)))
+    _say("serving: 14 mixed requests over 3 resident networks")
+    srv = Server(ctx, nets, max_inflight=3, dirs_per_launch=300, block=64)
+    done = srv.run(reqs)
+    assert len(done) == len(reqs)
+    assert max(r.launches for r in done) >= 2  # some request spanned launches
+    stream = torch.cuda.current_stream().cuda_stream
+    for r in done:
+        net = nets[r.key]
+        if r.k:
+            W = torch.from_numpy(np.ascontiguousarray(r.W.T)).cuda()
+            solo = torch.zeros_like(W)
+            net.hvp_device(W, solo, stream=stream)
+        else:
+            solo = torch.zeros((net.n_p, net.n_p), dtype=torch.float64, device="cuda")
+            net.reduced_hessian_device(solo, k_block=64, stream=stream)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(r.result, solo.cpu().numpy().T)
+    full_a = [r for r in done if r.key == "a" and r.k == 0][0]
+    assert _relerr(full_a.result, s1.reduced_hessian()) <= TOL
+
+
+@pytest.mark.parametrize("steps", [0, 1, 2, 3])
+def test_refined_fp32_1k(ctx, rhmod, c1, steps):
+    """FP32 sweeps with FP64 residual refinement; the error against the oracle
+    is stated per result (column); two correction steps reach 1e-8."""
+    g, net, s = c1
+    ctx.set_refinement(steps)
+    try:
+        W = gridgen.directions(net.n_p, 48, 40)
+        HW = net.hvp(W, prec=rhmod.RH_FP32_REFINED)
+    finally:
+        ctx.set_refinement(2)
+    ref = s.hvp(W)
+    per_col = np.max(np.abs(HW - ref), axis=0) / np.max(np.abs(ref), axis=0)
+    _say(f"refined 1k, {steps} correction steps: per-result error max {per_col.max():.2e} "
+         f"median {np.median(per_col):.2e}")
+    if steps >= 2:
+        assert per_col.max() <= 1e-8
+
+
+def test_refined_fp32_10k_block_and_full_hessian_columns(ctx, rhmod, c2):
+    g, net, s = c2
+    W = gridgen.directions(net.n_p, 128, 41)
+    HW = net.hvp(W, prec=rhmod.RH_FP32_REFINED)
+    ref = s.hvp(W)
+    per_col = np.max(np.abs(HW - ref), axis=0) / np.max(np.abs(ref), axis=0)
+    _say(f"refined 10k: per-result error max {per_col.max():.2e} median {np.median(per_col):.2e}")
+    assert per_col.max() <= 1e-8
+    H = net.reduced_hessian(k_block=256, prec=rhmod.RH_FP32_REFINED)
+    cols = np.array([0, 1, 700, 1399, 1400, 2000, net.n_p - 1])
+    E = np.zeros((net.n_p, cols.size))
+    E[cols, np.arange(cols.size)] = 1.0
+    assert _relerr(H[:, cols], s.hvp(E)) <= 1e-8
