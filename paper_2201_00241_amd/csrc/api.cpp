@@ -379,10 +379,14 @@ rh_status rh_hvp_batch_device(rh_context *ctx, int32_t n, rh_network *const *net
     if (net.ctx != &ctx->c) return fail(RH_EINVAL, "network of another context in batch");
     if (!net.solved || !net.dev) return fail(RH_ESTATE, "unsolved network in batch");
     const int32_t idf = identity_from ? identity_from[i] : -1;
+    const std::string where = "batch item " + std::to_string(i) + " (k " + std::to_string(k[i]) +
+                              ", n_p " + std::to_string(net.n_p) + ", ldw " + std::to_string(ldw[i]) +
+                              ", ldhw " + std::to_string(ldhw[i]) + ", identity_from " +
+                              std::to_string(idf) + ")";
     if (k[i] < 0 || (k[i] > 0 && (!dHW[i] || ldhw[i] < net.n_p)))
-      return fail(RH_EINVAL, "bad batch item");
-    if (k[i] > 0 && idf < 0 && (!dW[i] || ldw[i] < net.n_p)) return fail(RH_EINVAL, "bad batch item");
-    if (idf >= 0 && (int64_t)idf + k[i] > net.n_p) return fail(RH_EINVAL, "identity block exceeds n_p");
+      return fail(RH_EINVAL, "bad output of " + where);
+    if (k[i] > 0 && idf < 0 && (!dW[i] || ldw[i] < net.n_p)) return fail(RH_EINVAL, "bad input of " + where);
+    if (idf >= 0 && (int64_t)idf + k[i] > net.n_p) return fail(RH_EINVAL, "identity block exceeds n_p in " + where);
     ns[i] = &net;
   }
   std::string err;

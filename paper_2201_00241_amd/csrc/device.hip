@@ -42,8 +42,11 @@ namespace rh {
 
 namespace {
 
-constexpr int kThreads = 512;      // global-vector variant (several workgroups per CU)
-constexpr int kThreadsLds = 1024;  // LDS variant (one workgroup per CU at 10k buses)
+// One workgroup size for every variant: the sweep schedules (lane groups,
+// wave steps) are built for it, so all variants do the same arithmetic.
+constexpr int kThreads = 1024;
+constexpr int kThreadsLds = kThreads;
+constexpr int kWaves = kThreads / 64;
 // lanes x rows budget used to pick a level's lane-group size (fixed, so the
 // schedule never depends on the launch shape)
 constexpr int kLaneBudget = 512;
@@ -59,6 +62,8 @@ struct DevSweep {
   const double *val, *dinv;  // dinv == nullptr: unit diagonal
   const double *dense;       // block inverses
   const float *val32, *dinv32, *dense32;  // FP32 copies (refined mode)
+  const int32_t *wdir;       // wave steps: per wave, range of its wave levels
+  const int4 *wlev;          // wave level: first position, rows, log2 lanes per row
 };
 
 template <class T>
@@ -253,7 +258,30 @@ __device__ __forceinline__ void sweep(const DevSweep &s, T *__restrict__ X, cons
     if (lev + 1 < nl) {  // next step's first rows, issued before this step's work
       m = s.lev[lev + 1];
       lg = m.z;
-      pre = prefetch_row<T>(s, m, tid >> lg, tid & ((1 << lg) - 1), 1 << lg);
+      pre = prefetch_row<T>(s, m, m.w >= -1 ? tid >> lg : INT32_MAX, tid & ((1 << lg) - 1), 1 << lg);
+    }
+    if (cur.w <= -2) {
+      // wave step: each wave walks its own subtrees level by level; rows of a
+      // wave level only read rows of earlier wave levels of the same wave (or
+      // of earlier steps), so wave-local program order is the only ordering
+      const int32_t *dir = s.wdir + (-2 - cur.w);
+      const int wv = tid >> 6, l64 = tid & 63;
+      const int32_t j1 = dir[wv + 1];
+      for (int32_t j = dir[wv]; j < j1; ++j) {
+        const int4 wm = s.wlev[j];
+        const int wwidth = 1 << wm.z;
+        const int wlane = l64 & (wwidth - 1);
+        for (int32_t r = l64 >> wm.z; r < wm.y; r += (64 >> wm.z)) {
+          const RowPre<T> p = prefetch_row<T>(s, wm, r, wlane, wwidth);
+          row_update<C, NT, T>(s, p, X, init, s_r, wm.x, false, wlane, wwidth);
+        }
+        // this wave's writes before its next level's reads
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      }
+      __syncthreads();
+      continue;
     }
     const bool block = cur.w >= 0;
     if (first.pos >= 0) {
@@ -670,13 +698,13 @@ rh_status launch(bool lds, bool refined, int32_t groups, size_t lds_bytes, hipSt
 }
 
 // Directions per workgroup: more share each factor entry, fewer keep the chip
-// busy.  Take the largest C (<= 8; <= 4 with the 1024-thread LDS kernel) that
-// still gives two workgroups per CU and whose vectors fit the LDS budget.
+// busy.  Take the largest C (<= 2) that still gives two workgroups per CU and
+// whose vectors fit the LDS budget.
 // The choice does not change any direction's arithmetic.
 int32_t choose_c(int64_t k, int32_t cus, int64_t n_x, size_t lds_max, bool lds, size_t elem) {
   if (const char *e = std::getenv("RH_DIRS_PER_GROUP")) {
     const int v = std::atoi(e);
-    if ((v == 1 || v == 2 || v == 4 || (v == 8 && !lds)) && (!lds || (size_t)n_x * v * elem <= lds_max))
+    if ((v == 1 || v == 2 || v == 4) && (!lds || (size_t)n_x * v * elem <= lds_max))
       return v;
   }
   int32_t c = lds ? 4 : 8;
@@ -709,7 +737,7 @@ rh_status run_items(const DeviceInfo &info, Runner &r, int32_t timing, int32_t r
   const int64_t parts = refined ? (lds ? 2 : 3) : (lds ? 1 : 2);
   const int64_t stride = (parts * max_nx * C + 31) / 32 * 32 * (refined ? 1 : 1);
   const int64_t max_groups_mem = std::max<int64_t>(1, (int64_t(8) << 30) / (stride * 8));
-  const int64_t per_cu = lds ? 1 : 4;
+  const int64_t per_cu = lds ? 1 : 2;
   const int32_t groups = (int32_t)std::min<int64_t>({n_chunks, max_groups_mem, (int64_t)info.cus * 8 * per_cu});
   const size_t need = (size_t)groups * stride * sizeof(double);
   if (need > r.scratch_bytes) {
@@ -780,7 +808,7 @@ rh_status run_items(const DeviceInfo &info, Runner &r, int32_t timing, int32_t r
     case 1: st = launch<1>(lds, refined, groups, lds_bytes, s, la, err); break;
     case 2: st = launch<2>(lds, refined, groups, lds_bytes, s, la, err); break;
     case 4: st = launch<4>(lds, refined, groups, lds_bytes, s, la, err); break;
-    default: st = launch<8>(lds, refined, groups, lds_bytes, s, la, err); break;
+    default: st = launch<4>(lds, refined, groups, lds_bytes, s, la, err); break;
   }
   if (st != RH_OK) return st;
   if (items.size() > 1) HIP_TRY(hipEventRecord(r.items_done, s));
@@ -836,9 +864,9 @@ rh_status upload(DeviceNet &dn, const std::vector<T> &v, const T **out, std::str
     if (s_ != RH_OK) return s_;                                 \
   } while (0)
 
-rh_status upload_sweep(DeviceNet *dn, const Sweep &s, int32_t n, int bmax, DevSweep &o,
-                       std::string &err) {
-  const Schedule sc = build_schedule(s, n, bmax, kBlockRows, kLaneBudget);
+rh_status upload_sweep(DeviceNet *dn, const Sweep &s, int32_t n, const std::vector<int32_t> &parent,
+                       bool forward, const ScheduleParams &prm, DevSweep &o, std::string &err) {
+  const Schedule sc = build_schedule(s, n, parent, forward, prm);
   o.n_levels = (int32_t)(sc.meta.size() / 4);
   const int32_t *mp = nullptr;
   UP(sc.meta, mp);
@@ -860,6 +888,14 @@ rh_status upload_sweep(DeviceNet *dn, const Sweep &s, int32_t n, int bmax, DevSw
   if (!d32.empty()) UP(d32, o.dinv32);
   o.dense32 = nullptr;
   if (!m32.empty()) UP(m32, o.dense32);
+  o.wdir = nullptr;
+  o.wlev = nullptr;
+  if (!sc.wdir.empty()) {
+    UP(sc.wdir, o.wdir);
+    const int32_t *wp = nullptr;
+    UP(sc.wlev, wp);
+    o.wlev = reinterpret_cast<const int4 *>(wp);
+  }
   return RH_OK;
 }
 
@@ -941,13 +977,19 @@ rh_status device_upload(Network &net, std::string &err) {
 
   Sweep sl, su, sut, slt;
   lu_sweeps(lu, sl, su, sut, slt);
-  int bmax = kBlockRows;
-  if (const char *e = std::getenv("RH_BLOCK_ROWS")) bmax = std::min(kBlockRows, std::max(0, std::atoi(e)));
+  ScheduleParams prm;
+  prm.bmax = kBlockRows;
+  prm.block_rows = kBlockRows;
+  prm.lane_budget = kLaneBudget;
+  prm.n_waves = kWaves;
+  if (const char *e = std::getenv("RH_BLOCK_ROWS")) prm.bmax = std::min(kBlockRows, std::max(0, std::atoi(e)));
+  if (const char *e = std::getenv("RH_WAVE_STEPS")) prm.wave_mode = std::atoi(e) != 0;
   const int32_t n = net.n_x;
-  if (upload_sweep(dn, sl, n, bmax, nd.L, err) != RH_OK ||
-      upload_sweep(dn, su, n, bmax, nd.U, err) != RH_OK ||
-      upload_sweep(dn, sut, n, bmax, nd.Ut, err) != RH_OK ||
-      upload_sweep(dn, slt, n, bmax, nd.Lt, err) != RH_OK)
+  const std::vector<int32_t> parent = etree_parent(lu);
+  if (upload_sweep(dn, sl, n, parent, true, prm, nd.L, err) != RH_OK ||
+      upload_sweep(dn, su, n, parent, false, prm, nd.U, err) != RH_OK ||
+      upload_sweep(dn, sut, n, parent, true, prm, nd.Ut, err) != RH_OK ||
+      upload_sweep(dn, slt, n, parent, false, prm, nd.Lt, err) != RH_OK)
     return RH_EDEVICE;
   net.report.steps_l = nd.L.n_levels;
   net.report.steps_u = nd.U.n_levels;

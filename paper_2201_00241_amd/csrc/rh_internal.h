@@ -45,13 +45,25 @@ struct LuPlan {
   int32_t n_levels_l = 0, n_levels_u = 0;
 };
 
-// Device sweep schedule: the sweep's rows in the same positions, with the
-// entries of merged blocks split off into dense block inverses, and per step
-// {first position, rows, log2 lanes per row, dense offset or -1}.
+// Device sweep schedule: the sweep's rows in step order, with the entries of
+// merged blocks split off into dense block inverses; per step
+// {first position, rows, log2 lanes per row, kind}, kind = dense offset of a
+// block, -1 for a plain level, or -2 - d for a wave step whose waves' level
+// lists are wlev[wdir[d + w] .. wdir[d + w + 1]) (4 ints per wave level:
+// first position, rows, log2 lanes per row, 0).
 struct Schedule {
-  Sweep s;
+  Sweep s;  // rows, ptr, col, val, dinv (lev_ptr unused)
   std::vector<int32_t> meta;
   std::vector<double> dense;
+  std::vector<int32_t> wdir, wlev;
+};
+
+struct ScheduleParams {
+  int bmax = 64;          // rows of a merged block (0: no blocks)
+  int block_rows = 64;    // the kernel's block capacity
+  int lane_budget = 512;  // rows x lanes of a level step
+  int n_waves = 16;       // waves of the kernel's workgroup
+  int wave_mode = 1;      // 0: no wave step
 };
 
 struct DeviceNet;  // defined by the device translation unit
@@ -124,7 +136,9 @@ void lu_solve(const LuPlan &lu, std::vector<double> &b);        // A x = b in pl
 void lu_solve_t(const LuPlan &lu, std::vector<double> &b);      // A^T x = b in place
 void lu_sweeps(const LuPlan &lu, Sweep &sl, Sweep &su, Sweep &sut, Sweep &slt);
 int lane_log2(int32_t rows, int32_t longest, int lane_budget);
-Schedule build_schedule(const Sweep &in, int32_t n, int bmax, int block_rows, int lane_budget);
+Schedule build_schedule(const Sweep &in, int32_t n, const std::vector<int32_t> &parent, bool forward,
+                        const ScheduleParams &prm);
+std::vector<int32_t> etree_parent(const LuPlan &lu);
 
 // ---- device path (device.hip)
 rh_status device_upload(Network &net, std::string &err);

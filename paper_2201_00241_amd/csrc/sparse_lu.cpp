@@ -278,69 +278,276 @@ int lane_log2(int32_t rows, int32_t longest, int lane_budget) {
   return lg;
 }
 
-// Sweep schedule: wide levels stay single steps; runs of consecutive narrow
-// levels with at most `bmax` rows in all become blocks.  For a block each
-// row keeps only its entries to rows of earlier steps; the entries inside the
-// block and the pivots form the block's triangular matrix M (local order =
-// level order), whose inverse is stored densely (column-major).
-Schedule build_schedule(const Sweep &in, int32_t n, int bmax, int block_rows, int lane_budget) {
-  bmax = std::min(bmax, block_rows);
-  Schedule out;
+namespace {
+
+// Append rows (positions of `in`) as one step of the output: a plain level,
+// or (block = true) a block with its internal entries folded into the dense
+// inverse of its triangular system.
+void emit_rows(const Sweep &in, const std::vector<int32_t> &pos, bool block, int lane_budget,
+               std::vector<int32_t> &local, Schedule &out) {
   Sweep &o = out.s;
-  const int32_t nl = in.n_levels();
-  o.rows = in.rows;
-  o.dinv = in.dinv;
-  o.ptr.assign(in.rows.size() + 1, 0);
-  std::vector<int32_t> local(n, -1);
-  auto level_rows = [&](int32_t l) { return in.lev_ptr[l + 1] - in.lev_ptr[l]; };
-  int32_t l = 0;
+  const int32_t b = (int32_t)o.rows.size(), rows = (int32_t)pos.size();
+  if (block)
+    for (int32_t a = 0; a < rows; ++a) local[in.rows[pos[a]]] = a;
+  int32_t longest = 0;
+  std::vector<long double> M;
+  if (block) M.assign((size_t)rows * rows, 0.0L);
+  for (int32_t a = 0; a < rows; ++a) {
+    const int32_t p = pos[a];
+    o.rows.push_back(in.rows[p]);
+    if (!in.dinv.empty()) o.dinv.push_back(in.dinv[p]);
+    const int32_t start = (int32_t)o.col.size();
+    for (int32_t q = in.ptr[p]; q < in.ptr[p + 1]; ++q) {
+      const int32_t c = in.col[q];
+      if (block && local[c] >= 0) {
+        M[(size_t)a + (size_t)local[c] * rows] = in.val[q];
+      } else {
+        o.col.push_back(c);
+        o.val.push_back(in.val[q]);
+      }
+    }
+    o.ptr.push_back((int32_t)o.col.size());
+    longest = std::max(longest, (int32_t)o.col.size() - start);
+    if (block) M[(size_t)a * (rows + 1)] = in.dinv.empty() ? 1.0L : 1.0L / in.dinv[p];
+  }
+  int32_t off = -1;
+  if (block) {
+    // column j of M^{-1} by forward substitution on e_j (extended precision)
+    off = (int32_t)out.dense.size();
+    out.dense.resize(out.dense.size() + (size_t)rows * rows, 0.0);
+    std::vector<long double> y(rows);
+    for (int32_t j = 0; j < rows; ++j) {
+      for (int32_t a = 0; a < rows; ++a) {
+        long double acc = (a == j) ? 1.0L : 0.0L;
+        for (int32_t c = j; c < a; ++c) acc -= M[(size_t)a + (size_t)c * rows] * y[c];
+        y[a] = a < j ? 0.0L : acc / M[(size_t)a * (rows + 1)];
+      }
+      for (int32_t a = j; a < rows; ++a) out.dense[off + (size_t)a + (size_t)j * rows] = (double)y[a];
+    }
+    for (int32_t a = 0; a < rows; ++a) local[in.rows[pos[a]]] = -1;
+  }
+  out.meta.insert(out.meta.end(), {b, rows, lane_log2(rows, longest, lane_budget), off});
+}
+
+// Level steps for the rows `order` (positions of `in`, a valid sweep order),
+// levels counted among these rows only; runs of narrow levels with at most
+// `bmax` rows in all become blocks.  Returns the number of steps.
+int32_t emit_levels(const Sweep &in, const std::vector<int32_t> &order, std::vector<int32_t> &lvl_of_row,
+                    int bmax, int lane_budget, std::vector<int32_t> &local, Schedule *out) {
+  // level among `order` rows (dependencies outside are already solved)
+  int32_t nl = 0;
+  for (int32_t p : order) lvl_of_row[in.rows[p]] = 0;
+  for (int32_t p : order) {
+    int32_t lv = 0;
+    for (int32_t q = in.ptr[p]; q < in.ptr[p + 1]; ++q) {
+      const int32_t d = lvl_of_row[in.col[q]];
+      if (d >= 0) lv = std::max(lv, d + 1);
+    }
+    lvl_of_row[in.rows[p]] = lv;
+    nl = std::max(nl, lv + 1);
+  }
+  std::vector<std::vector<int32_t>> levels(nl);
+  for (int32_t p : order) levels[lvl_of_row[in.rows[p]]].push_back(p);
+  for (int32_t p : order) lvl_of_row[in.rows[p]] = -1;
+  int32_t steps = 0, l = 0;
   while (l < nl) {
-    int32_t l2 = l + 1, rows = level_rows(l);
+    int32_t l2 = l + 1, rows = (int32_t)levels[l].size();
     if (bmax > 1 && rows <= bmax)
-      while (l2 < nl && rows + level_rows(l2) <= bmax) rows += level_rows(l2++);
-    const int32_t b = in.lev_ptr[l], e = in.lev_ptr[l2];
+      while (l2 < nl && rows + (int32_t)levels[l2].size() <= bmax) rows += (int32_t)levels[l2++].size();
     const bool block = (l2 - l) >= 2;
-    if (block)
-      for (int32_t p = b; p < e; ++p) local[in.rows[p]] = p - b;
-    int32_t longest = 0;
-    std::vector<long double> M;
-    if (block) M.assign((size_t)rows * rows, 0.0L);
-    for (int32_t p = b; p < e; ++p) {
-      const int32_t start = (int32_t)o.col.size();
+    std::vector<int32_t> pos;
+    for (int32_t k = l; k < l2; ++k) pos.insert(pos.end(), levels[k].begin(), levels[k].end());
+    if (out) emit_rows(in, pos, block, lane_budget, local, *out);
+    ++steps;
+    l = l2;
+  }
+  return steps;
+}
+
+}  // namespace
+
+// Sweep schedule.  Steps are plain levels, dense-inverse blocks of merged
+// narrow levels, or one wave step: the elimination tree is cut into disjoint
+// subtrees (each subtree's rows depend only on the subtree and on rows outside
+// it that are solved before), the subtrees are assigned to the workgroup's
+// waves by longest-processing-time-first, and every wave walks its subtrees
+// level by level with wave-local ordering only.  The cut is chosen by a small
+// cost model (a workgroup barrier step ~ 4 wave levels); the wave step comes
+// first in forward sweeps (leaves first) and last in backward sweeps.
+Schedule build_schedule(const Sweep &in, int32_t n, const std::vector<int32_t> &parent, bool forward,
+                        const ScheduleParams &prm) {
+  const int bmax = std::min(prm.bmax, prm.block_rows);
+  Schedule out;
+  std::vector<int32_t> local(n, -1), lvl(n, -1);
+  const int32_t npos = (int32_t)in.rows.size();
+  std::vector<int32_t> pos_of(n, -1);
+  for (int32_t p = 0; p < npos; ++p) pos_of[in.rows[p]] = p;
+  std::vector<int32_t> all(npos);
+  for (int32_t p = 0; p < npos; ++p) all[p] = p;
+
+  out.s.ptr.assign(1, 0);
+  const int nw = prm.n_waves;
+  if (prm.wave_mode == 0 || nw < 2 || (int32_t)parent.size() != n) {
+    emit_levels(in, all, lvl, bmax, prm.lane_budget, local, &out);
+    return out;
+  }
+  // subtree work (rows + entries) in the elimination tree (parent > child)
+  std::vector<double> wk(n, 0.0), sub(n, 0.0);
+  double total = 0.0;
+  for (int32_t p = 0; p < npos; ++p) {
+    wk[in.rows[p]] = 1.0 + (in.ptr[p + 1] - in.ptr[p]);
+    total += wk[in.rows[p]];
+  }
+  std::vector<std::vector<int32_t>> kids(n);
+  std::vector<int32_t> roots;
+  for (int32_t v = 0; v < n; ++v) {
+    sub[v] += wk[v];
+    if (parent[v] >= 0) {
+      sub[parent[v]] += sub[v];
+      kids[parent[v]].push_back(v);
+    } else {
+      roots.push_back(v);
+    }
+  }
+  const double kBarrier = 4.0, kLevel = 1.0, kEntry = 1.0 / 16.0;
+  const double plain_cost = kBarrier * emit_levels(in, all, lvl, bmax, prm.lane_budget, local, nullptr);
+  double best = plain_cost;
+  int best_f = 0;
+  std::vector<int32_t> owner(n, -1);  // wave of a subtree row, -1 = top part
+  std::vector<int32_t> best_owner;
+  for (int f : {1, 2, 4, 8, 16, 32}) {
+    const double target = total / (nw * f);
+    std::vector<int32_t> stack(roots), subroots;
+    std::vector<char> top(n, 0);
+    while (!stack.empty()) {
+      const int32_t v = stack.back();
+      stack.pop_back();
+      if (sub[v] <= target) {
+        subroots.push_back(v);
+      } else {
+        top[v] = 1;
+        stack.insert(stack.end(), kids[v].begin(), kids[v].end());
+      }
+    }
+    std::sort(subroots.begin(), subroots.end(),
+              [&](int32_t a, int32_t b) { return sub[a] > sub[b] || (sub[a] == sub[b] && a < b); });
+    std::vector<double> load(nw, 0.0);
+    std::fill(owner.begin(), owner.end(), -1);
+    for (int32_t r : subroots) {
+      const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[w] += sub[r];
+      std::vector<int32_t> st{r};
+      while (!st.empty()) {
+        const int32_t v = st.back();
+        st.pop_back();
+        owner[v] = w;
+        st.insert(st.end(), kids[v].begin(), kids[v].end());
+      }
+    }
+    // wave makespan: per wave level a latency plus its entries over 64 lanes
+    std::vector<int32_t> wl(n, -1);
+    std::vector<std::vector<double>> lvl_entries(nw), lvl_longest(nw);
+    for (int32_t p = 0; p < npos; ++p) {
+      const int32_t r = in.rows[p];
+      if (owner[r] < 0) continue;
+      int32_t lv = 0;
       for (int32_t q = in.ptr[p]; q < in.ptr[p + 1]; ++q) {
         const int32_t c = in.col[q];
-        if (block && local[c] >= 0) {
-          M[(size_t)(p - b) + (size_t)local[c] * rows] = in.val[q];
-        } else {
-          o.col.push_back(c);
-          o.val.push_back(in.val[q]);
-        }
+        if (owner[c] == owner[r]) lv = std::max(lv, wl[c] + 1);
       }
-      o.ptr[p + 1] = (int32_t)o.col.size();
-      longest = std::max(longest, (int32_t)o.col.size() - start);
-      if (block) M[(size_t)(p - b) * (rows + 1)] = in.dinv.empty() ? 1.0L : 1.0L / in.dinv[p];
-    }
-    int32_t off = -1;
-    if (block) {
-      // column j of M^{-1} by forward substitution on e_j (extended precision)
-      off = (int32_t)out.dense.size();
-      out.dense.resize(out.dense.size() + (size_t)rows * rows, 0.0);
-      std::vector<long double> y(rows);
-      for (int32_t j = 0; j < rows; ++j) {
-        for (int32_t a = 0; a < rows; ++a) {
-          long double acc = (a == j) ? 1.0L : 0.0L;
-          for (int32_t c = j; c < a; ++c) acc -= M[(size_t)a + (size_t)c * rows] * y[c];
-          y[a] = a < j ? 0.0L : acc / M[(size_t)a * (rows + 1)];
-        }
-        for (int32_t a = j; a < rows; ++a) out.dense[off + (size_t)a + (size_t)j * rows] = (double)y[a];
+      wl[r] = lv;
+      auto &E = lvl_entries[owner[r]];
+      auto &Lg = lvl_longest[owner[r]];
+      if ((int32_t)E.size() <= lv) {
+        E.resize(lv + 1, 0.0);
+        Lg.resize(lv + 1, 0.0);
       }
-      for (int32_t p = b; p < e; ++p) local[in.rows[p]] = -1;
+      E[lv] += wk[r];
+      Lg[lv] = std::max(Lg[lv], wk[r]);
     }
-    out.meta.insert(out.meta.end(), {b, rows, lane_log2(rows, longest, lane_budget), off});
-    l = l2;
+    double makespan = 0.0;
+    for (int w = 0; w < nw; ++w) {
+      double t = 0.0;
+      for (size_t l = 0; l < lvl_entries[w].size(); ++l)
+        t += kLevel + kEntry * std::max(lvl_entries[w][l] / 64.0, lvl_longest[w][l] / 16.0);
+      makespan = std::max(makespan, t);
+    }
+    std::vector<int32_t> order;
+    for (int32_t p = 0; p < npos; ++p)
+      if (owner[in.rows[p]] < 0) order.push_back(p);
+    const double cost =
+        kBarrier * (1 + emit_levels(in, order, lvl, bmax, prm.lane_budget, local, nullptr)) + makespan;
+    if (cost < best) {
+      best = cost;
+      best_f = f;
+      best_owner = owner;
+    }
+  }
+  if (best_f == 0) {
+    emit_levels(in, all, lvl, bmax, prm.lane_budget, local, &out);
+    return out;
+  }
+  owner = best_owner;
+  std::vector<int32_t> top_order;
+  for (int32_t p = 0; p < npos; ++p)
+    if (owner[in.rows[p]] < 0) top_order.push_back(p);
+  auto emit_wave_step = [&]() {
+    // wave levels within each wave (dependencies inside the same wave only)
+    std::vector<int32_t> wl(n, -1);
+    std::vector<std::vector<std::vector<int32_t>>> W(nw);
+    for (int32_t p = 0; p < npos; ++p) {
+      const int32_t r = in.rows[p];
+      const int32_t w = owner[r];
+      if (w < 0) continue;
+      int32_t lv = 0;
+      for (int32_t q = in.ptr[p]; q < in.ptr[p + 1]; ++q)
+        if (owner[in.col[q]] == w) lv = std::max(lv, wl[in.col[q]] + 1);
+      wl[r] = lv;
+      if ((int32_t)W[w].size() <= lv) W[w].resize(lv + 1);
+      W[w][lv].push_back(p);
+    }
+    const int32_t dir0 = (int32_t)out.wdir.size();
+    const int32_t b = (int32_t)out.s.rows.size();
+    int32_t rows_total = 0;
+    for (int w = 0; w < nw; ++w) {
+      out.wdir.push_back((int32_t)(out.wlev.size() / 4));
+      for (auto &lv : W[w]) {
+        // rows of one wave level, as a plain level step of the wave
+        const int32_t first = (int32_t)out.s.rows.size();
+        int32_t longest = 0;
+        for (int32_t p : lv) {
+          out.s.rows.push_back(in.rows[p]);
+          if (!in.dinv.empty()) out.s.dinv.push_back(in.dinv[p]);
+          for (int32_t q = in.ptr[p]; q < in.ptr[p + 1]; ++q) {
+            out.s.col.push_back(in.col[q]);
+            out.s.val.push_back(in.val[q]);
+          }
+          out.s.ptr.push_back((int32_t)out.s.col.size());
+          longest = std::max(longest, in.ptr[p + 1] - in.ptr[p]);
+        }
+        out.wlev.insert(out.wlev.end(),
+                        {first, (int32_t)lv.size(), lane_log2((int32_t)lv.size(), longest, 64), 0});
+        rows_total += (int32_t)lv.size();
+      }
+    }
+    out.wdir.push_back((int32_t)(out.wlev.size() / 4));
+    out.meta.insert(out.meta.end(), {b, rows_total, 0, -2 - dir0});
+  };
+  if (forward) {
+    emit_wave_step();
+    emit_levels(in, top_order, lvl, bmax, prm.lane_budget, local, &out);
+  } else {
+    emit_levels(in, top_order, lvl, bmax, prm.lane_budget, local, &out);
+    emit_wave_step();
   }
   return out;
 }
 
+std::vector<int32_t> etree_parent(const LuPlan &lu) {
+  std::vector<int32_t> parent(lu.n, -1);
+  for (int32_t k = 0; k < lu.n; ++k)
+    if (lu.urow[k].size() > 1) parent[k] = lu.urow[k][1];
+  return parent;
+}
 
 }  // namespace rh

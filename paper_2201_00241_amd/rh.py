@@ -145,6 +145,12 @@ def _p(a: np.ndarray, typ):
     return a.ctypes.data_as(typ)
 
 
+def _ld(t) -> int:
+    """Leading dimension of a row-major (k, ld) device tensor (PyTorch reports
+    an arbitrary stride for a dimension of size one)."""
+    return max(int(t.stride(0)), int(t.shape[1])) if t.shape[0] == 1 else int(t.stride(0))
+
+
 # ---- thin wrappers with the C names -------------------------------------
 def rh_context_create(device: int) -> ctypes.c_void_p:
     lib = load()
@@ -338,8 +344,8 @@ class Context:
     def hvp_batch_device(self, nets, Ws, HWs, stream=None, prec=RH_FP64):
         """nets: Network objects; Ws/HWs: torch float64 CUDA tensors (k_i, n_p_i)."""
         rh_hvp_batch_device(self.h, [n.h for n in nets], [W.shape[0] for W in Ws],
-                            [W.data_ptr() for W in Ws], [W.stride(0) for W in Ws],
-                            [H.data_ptr() for H in HWs], [H.stride(0) for H in HWs], None, prec,
+                            [W.data_ptr() for W in Ws], [_ld(W) for W in Ws],
+                            [H.data_ptr() for H in HWs], [_ld(H) for H in HWs], None, prec,
                             stream)
 
     def close(self):
@@ -388,9 +394,8 @@ class Network:
     def hvp_device(self, W, HW, stream=None, prec=RH_FP64):
         """W, HW: torch float64 CUDA tensors of shape (k, n_p) (row j = direction j)."""
         k = W.shape[0]
-        rh_hvp_device(self.h, k, W.data_ptr(), W.stride(0), HW.data_ptr(), HW.stride(0), prec,
-                      stream)
+        rh_hvp_device(self.h, k, W.data_ptr(), _ld(W), HW.data_ptr(), _ld(HW), prec, stream)
 
     def reduced_hessian_device(self, H, k_block=0, stream=None, prec=RH_FP64):
         """H: torch float64 CUDA tensor (n_p, n_p); row j receives column j of the Hessian."""
-        rh_reduced_hessian_device(self.h, H.data_ptr(), H.stride(0), k_block, prec, stream)
+        rh_reduced_hessian_device(self.h, H.data_ptr(), _ld(H), k_block, prec, stream)

@@ -92,7 +92,7 @@ class Server:
             return False
         kk = req.k if req.k else net.n_p
         if req.k:
-            req._dW = torch.from_numpy(np.ascontiguousarray(np.asarray(req.W).T)).cuda()
+            req._dW = torch.from_numpy(np.ascontiguousarray(np.asarray(req.W).T)).cuda().contiguous()
         req._dHW = torch.empty((kk, net.n_p), dtype=torch.float64, device="cuda")
         req._bytes = nbytes
         self._mem_used += nbytes
@@ -109,16 +109,16 @@ class Server:
             net = self.nets[r.key]
             nets.append(net.h)
             ks.append(it.kb)
+            # both buffers are contiguous (rows, n_p): leading dimension n_p
             if r.k:
                 dWs.append(r._dW[it.j0].data_ptr())
-                ldws.append(r._dW.stride(0))
                 idf.append(-1)
             else:
                 dWs.append(0)
-                ldws.append(net.n_p)
                 idf.append(it.j0)
+            ldws.append(net.n_p)
             dHWs.append(r._dHW[it.j0].data_ptr())
-            ldhws.append(r._dHW.stride(0))
+            ldhws.append(net.n_p)
             if r.t_first_launch < 0:
                 r.t_first_launch = now
             r.launches += 1

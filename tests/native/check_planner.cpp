@@ -22,20 +22,57 @@ static std::vector<T> rd(FILE *f, size_t n) {
   return v;
 }
 
-static void emulate(const Schedule &sc, std::vector<double> &X) {
+// Emulates the kernel's step structure.  In a wave step the waves run one
+// after the other in reverse order, each level by level, and every row first
+// checks that the rows it reads are final (solved in an earlier step, or
+// earlier in its own wave); `ok` turns false otherwise.
+static void emulate(const Schedule &sc, std::vector<double> &X, bool &ok) {
   const Sweep &s = sc.s;
   const size_t ns = sc.meta.size() / 4;
+  std::vector<char> done(X.size(), 0);
+  for (size_t p = 0; p < s.rows.size(); ++p) done[s.rows[p]] = 0;
+  std::vector<char> pending(X.size(), 0);
+  for (size_t p = 0; p < s.rows.size(); ++p) pending[s.rows[p]] = 1;
+  auto row = [&](int p) {
+    double part = 0;
+    for (int q = s.ptr[p]; q < s.ptr[p + 1]; ++q) {
+      if (pending[s.col[q]]) ok = false;
+      part += s.val[q] * X[s.col[q]];
+    }
+    double v = X[s.rows[p]] - part;
+    if (!s.dinv.empty()) v *= s.dinv[p];
+    X[s.rows[p]] = v;
+    pending[s.rows[p]] = 0;
+  };
   for (size_t st = 0; st < ns; ++st) {
     const int b = sc.meta[4 * st], rows = sc.meta[4 * st + 1], off = sc.meta[4 * st + 3];
+    if (off <= -2) {
+      const int d = -2 - off;
+      const int nw = 16;
+      for (int w = nw - 1; w >= 0; --w)
+        for (int j = sc.wdir[d + w]; j < sc.wdir[d + w + 1]; ++j)
+          for (int r = 0; r < sc.wlev[4 * j + 1]; ++r) row(sc.wlev[4 * j] + r);
+      continue;
+    }
+    if (off < 0) {
+      // rows of a level are independent: all read before any is written
+      for (int a = 0; a < rows; ++a)
+        for (int q = s.ptr[b + a]; q < s.ptr[b + a + 1]; ++q)
+          if (pending[s.col[q]]) ok = false;
+    }
     std::vector<double> r(rows);
     for (int a = 0; a < rows; ++a) {
       const int p = b + a;
       double part = 0;
-      for (int q = s.ptr[p]; q < s.ptr[p + 1]; ++q) part += s.val[q] * X[s.col[q]];
+      for (int q = s.ptr[p]; q < s.ptr[p + 1]; ++q) {
+        if (off >= 0 && pending[s.col[q]]) ok = false;  // external entries only
+        part += s.val[q] * X[s.col[q]];
+      }
       double v = X[s.rows[p]] - part;
       if (off < 0) {
         if (!s.dinv.empty()) v *= s.dinv[p];
         X[s.rows[p]] = v;
+        pending[s.rows[p]] = 0;
       } else {
         r[a] = v;
       }
@@ -45,8 +82,12 @@ static void emulate(const Schedule &sc, std::vector<double> &X) {
         double acc = 0;
         for (int c = 0; c <= a; ++c) acc += sc.dense[off + a + (size_t)c * rows] * r[c];
         X[s.rows[b + a]] = acc;
+        pending[s.rows[b + a]] = 0;
       }
   }
+  for (size_t i = 0; i < X.size(); ++i)
+    if (pending[i]) ok = false;
+  (void)done;
 }
 
 static void plain(const Sweep &s, std::vector<double> &X) {
@@ -144,16 +185,29 @@ int main(int argc, char **argv) {
   Sweep sw[4];
   lu_sweeps(net.lu, sw[0], sw[1], sw[2], sw[3]);
   const char *nm[4] = {"L", "U", "Ut", "Lt"};
+  const bool fwd[4] = {true, false, true, false};
+  const std::vector<int32_t> parent = etree_parent(net.lu);
+  int bad = 0;
   for (int k = 0; k < 4; ++k)
-    for (int bmax : {0, 16, 64}) {
-      const Schedule sc = build_schedule(sw[k], nx, bmax, 64, 512);
-      std::vector<double> X(nx);
-      for (auto &v : X) v = nd(rng);
-      std::vector<double> Y = X;
-      emulate(sc, X);
-      plain(sw[k], Y);
-      printf("max_err sweep_%s_b%d %.3e steps %zu\n", nm[k], bmax, relerr(X, Y), sc.meta.size() / 4);
-    }
+    for (int wave : {0, 1})
+      for (int bmax : {0, 16, 64}) {
+        ScheduleParams prm;
+        prm.bmax = bmax;
+        prm.wave_mode = wave;
+        const Schedule sc = build_schedule(sw[k], nx, parent, fwd[k], prm);
+        std::vector<double> X(nx);
+        for (auto &v : X) v = nd(rng);
+        std::vector<double> Y = X;
+        bool ok = true;
+        emulate(sc, X, ok);
+        plain(sw[k], Y);
+        if (!ok) ++bad;
+        int waves = 0;
+        for (size_t q = 0; q < sc.meta.size() / 4; ++q) waves += sc.meta[4 * q + 3] <= -2;
+        printf("max_err sweep_%s_w%d_b%d %.3e steps %zu wave_steps %d order_ok %d\n", nm[k], wave, bmax,
+               relerr(X, Y), sc.meta.size() / 4, waves, ok ? 1 : 0);
+      }
+  printf("order_violations %d\n", bad);
   // the four sweeps compose to the two solves: U^-1 L^-1 (P b) and L^-T U^-T (P b)
   {
     std::vector<double> bb(nx);
@@ -161,16 +215,19 @@ int main(int argc, char **argv) {
     std::vector<double> ref = bb, X(nx);
     lu_solve(net.lu, ref);
     for (int i = 0; i < nx; ++i) X[net.lu.iperm[i]] = bb[i];
-    emulate(build_schedule(sw[0], nx, 64, 64, 512), X);
-    emulate(build_schedule(sw[1], nx, 64, 64, 512), X);
+    ScheduleParams prm;
+    bool ok = true;
+    emulate(build_schedule(sw[0], nx, parent, true, prm), X, ok);
+    emulate(build_schedule(sw[1], nx, parent, false, prm), X, ok);
     std::vector<double> sol(nx);
     for (int i = 0; i < nx; ++i) sol[i] = X[net.lu.iperm[i]];
     printf("max_err solve_via_sweeps %.3e\n", relerr(sol, ref));
     ref = bb;
     lu_solve_t(net.lu, ref);
     for (int i = 0; i < nx; ++i) X[net.lu.iperm[i]] = bb[i];
-    emulate(build_schedule(sw[2], nx, 64, 64, 512), X);
-    emulate(build_schedule(sw[3], nx, 64, 64, 512), X);
+    emulate(build_schedule(sw[2], nx, parent, true, prm), X, ok);
+    emulate(build_schedule(sw[3], nx, parent, false, prm), X, ok);
+    if (!ok) printf("order_violations_composed 1\n");
     for (int i = 0; i < nx; ++i) sol[i] = X[net.lu.iperm[i]];
     printf("max_err solve_t_via_sweeps %.3e\n", relerr(sol, ref));
   }
