@@ -44,46 +44,49 @@ namespace {
 
 // One workgroup size for every variant: the sweep schedules (lane groups,
 // wave steps) are built for it, so all variants do the same arithmetic.
+// Read-only descriptors are read through the constant address space, so the
+// compiler keeps their fields in scalar registers across global stores.
+#define AS4 __attribute__((address_space(4)))
+
 constexpr int kThreads = 1024;
 constexpr int kThreadsLds = kThreads;
 constexpr int kWaves = kThreads / 64;
 // lanes x rows budget used to pick a level's lane-group size (fixed, so the
 // schedule never depends on the launch shape)
-constexpr int kLaneBudget = 512;
+constexpr int kLaneBudget = 1024;
 
 constexpr int kBlockRows = 64;  // rows of a merged block of narrow levels (one wave)
 
+// A triangular sweep in device form (see Packed in the host planner): steps,
+// units with per-lane entry slots, row info and dense block inverses.
 struct DevSweep {
-  int32_t n_levels;  // steps
-  // per step: first position, row count, log2 lanes per row, offset of the
-  // block's dense inverse (-1: a plain level)
-  const int4 *lev;
-  const int32_t *rows, *ptr, *col;
-  const double *val, *dinv;  // dinv == nullptr: unit diagonal
-  const double *dense;       // block inverses
-  const float *val32, *dinv32, *dense32;  // FP32 copies (refined mode)
-  const int32_t *wdir;       // wave steps: per wave, range of its wave levels
-  const int4 *wlev;          // wave level: first position, rows, log2 lanes per row
+  int32_t n_steps;
+  const int4 *steps;  // {unit or wave directory offset, 0, kind, dense offset}
+  const int4 *units;  // 2 x int4: {slot_base, info_base, rows, groups}, {lg, E, lanes, 0}
+  const int32_t *wdir;
+  const int32_t *scol, *irow;
+  const double *sval, *idinv, *dense;          // idinv == nullptr: unit diagonal
+  const float *sval32, *idinv32, *dense32;     // FP32 copies (refined mode)
 };
 
 template <class T>
-__device__ __forceinline__ const T *sw_val(const DevSweep &s);
+__device__ __forceinline__ const T *sw_val(const DevSweep AS4 &s);
 template <>
-__device__ __forceinline__ const double *sw_val<double>(const DevSweep &s) { return s.val; }
+__device__ __forceinline__ const double *sw_val<double>(const DevSweep AS4 &s) { return s.sval; }
 template <>
-__device__ __forceinline__ const float *sw_val<float>(const DevSweep &s) { return s.val32; }
+__device__ __forceinline__ const float *sw_val<float>(const DevSweep AS4 &s) { return s.sval32; }
 template <class T>
-__device__ __forceinline__ const T *sw_dinv(const DevSweep &s);
+__device__ __forceinline__ const T *sw_dinv(const DevSweep AS4 &s);
 template <>
-__device__ __forceinline__ const double *sw_dinv<double>(const DevSweep &s) { return s.dinv; }
+__device__ __forceinline__ const double *sw_dinv<double>(const DevSweep AS4 &s) { return s.idinv; }
 template <>
-__device__ __forceinline__ const float *sw_dinv<float>(const DevSweep &s) { return s.dinv32; }
+__device__ __forceinline__ const float *sw_dinv<float>(const DevSweep AS4 &s) { return s.idinv32; }
 template <class T>
-__device__ __forceinline__ const T *sw_dense(const DevSweep &s);
+__device__ __forceinline__ const T *sw_dense(const DevSweep AS4 &s);
 template <>
-__device__ __forceinline__ const double *sw_dense<double>(const DevSweep &s) { return s.dense; }
+__device__ __forceinline__ const double *sw_dense<double>(const DevSweep AS4 &s) { return s.dense; }
 template <>
-__device__ __forceinline__ const float *sw_dense<float>(const DevSweep &s) { return s.dense32; }
+__device__ __forceinline__ const float *sw_dense<float>(const DevSweep AS4 &s) { return s.dense32; }
 
 struct NetDesc {
   int32_t n_x, n_p, n_bus, n_pg, n_slack;
@@ -128,7 +131,10 @@ struct LaunchArgs {
   double *scratch;
   int64_t scratch_stride;  // doubles per workgroup
   long long *stamps;       // kStamps wall-clock stamps per workgroup, or nullptr
+  long long *step_stamps;  // debug: workgroup 0 stamps every sweep step (4 x kMaxStepStamps)
 };
+
+constexpr int kMaxStepStamps = 128;
 
 constexpr int kStamps = 8;
 
@@ -152,169 +158,206 @@ __device__ __forceinline__ WorkItem item_of(const LaunchArgs &la, int32_t chunk)
   return la.items[lo];
 }
 
-// Registers holding one row of a level: its position, entry range, the first
-// kPre entries of this lane, the matrix row and the reciprocal pivot.  Loaded
-// one level ahead, so that the dependent global loads leave the critical path
-// of the sweep (they do not depend on the solution vector).
+// A unit of a sweep (see DevSweep): its slot layout.
+struct Unit {
+  int32_t slot_base, info_base, rows, groups, lg, E, lanes;
+};
+
+__device__ __forceinline__ Unit unit_at(const DevSweep AS4 &s, int32_t u) {
+  const int4 a = s.units[2 * u], b = s.units[2 * u + 1];
+  return Unit{a.x, a.y, a.z, a.w, b.x, b.y, b.z};
+}
+
+// The first kPre entry slots of one lane in one pass of a unit.  They do not
+// depend on the solution vector, so they are loaded a unit or two ahead and
+// the only dependent access left on the critical path is the LDS gather.
 constexpr int kPre = 4;
 template <class T>
-struct RowPre {
-  int32_t pos, q0, q1, row;
+struct Slots {
   int32_t col[kPre];
   T val[kPre];
-  T dinv;
 };
 
 template <class T>
-__device__ __forceinline__ RowPre<T> prefetch_row(const DevSweep &s, const int4 m, int32_t r, int lane,
-                                                  int width) {
-  RowPre<T> p;
-  p.pos = -1;
-  if (r < m.y) {
-    const T *val = sw_val<T>(s);
-    const T *dinv = sw_dinv<T>(s);
-    p.pos = m.x + r;
-    p.q0 = s.ptr[p.pos];
-    p.q1 = s.ptr[p.pos + 1];
-    p.row = s.rows[p.pos];
-    p.dinv = dinv ? dinv[p.pos] : T(1);
+__device__ __forceinline__ Slots<T> load_slots(const DevSweep AS4 &s, const Unit &U, int32_t pass, int lane) {
+  Slots<T> L;
+  const T *val = sw_val<T>(s);
+  const bool act = lane < U.lanes && pass * U.groups + (lane >> U.lg) < U.rows;
 #pragma unroll
-    for (int i = 0; i < kPre; ++i) {
-      const int32_t q = p.q0 + lane + i * width;
-      p.col[i] = q < p.q1 ? s.col[q] : 0;
-      p.val[i] = q < p.q1 ? val[q] : T(0);
-    }
+  for (int e = 0; e < kPre; ++e) {
+    const bool ok = act && e < U.E;
+    const int64_t at = (int64_t)U.slot_base + ((int64_t)pass * U.E + e) * U.lanes + lane;
+    L.col[e] = ok ? s.scol[at] : 0;
+    L.val[e] = ok ? val[at] : T(0);
   }
-  return p;
+  return L;
 }
 
-// One row: new value = (init - sum_j val_j X_j) * dinv, summed by a lane
-// group of `width` lanes and combined by a shuffle butterfly.  Rows of a block
-// step only form the residual (no pivot) into s_r at their place in the block.
-template <int C, int NT, class T>
-__device__ __forceinline__ void row_update(const DevSweep &s, const RowPre<T> &p, T *__restrict__ X,
-                                           const T *__restrict__ init, T *__restrict__ s_r,
-                                           int32_t first, bool block, int lane, int width) {
+// One lane's share of one pass of a unit: partial dot product of its slots
+// with X, butterfly over the lane group, and the group's first lane writes the
+// row (or, in a block, its residual into s_r).  Padding slots are (0, 0).
+template <int C, class T>
+__device__ __forceinline__ void lane_update(const DevSweep AS4 &s, const Unit &U, int32_t pass, int lane,
+                                            const Slots<T> &L, T *__restrict__ X,
+                                            const T *__restrict__ init, T *__restrict__ s_r,
+                                            bool block) {
+  const int width = 1 << U.lg;
+  const int32_t r = pass * U.groups + (lane >> U.lg);
+  if (lane >= U.lanes || r >= U.rows) return;  // whole lane groups only
   const T *val = sw_val<T>(s);
   T part[C];
 #pragma unroll
   for (int c = 0; c < C; ++c) part[c] = T(0);
 #pragma unroll
-  for (int i = 0; i < kPre; ++i) {
-    const int32_t j = p.col[i] * C;
+  for (int e = 0; e < kPre; ++e) {
+    const int32_t j = L.col[e] * C;
 #pragma unroll
-    for (int c = 0; c < C; ++c) part[c] = fma(p.val[i], X[j + c], part[c]);
+    for (int c = 0; c < C; ++c) part[c] = fma(L.val[e], X[j + c], part[c]);
   }
-  for (int32_t q = p.q0 + lane + kPre * width; q < p.q1; q += width) {
-    const T v = val[q];
-    const int32_t j = s.col[q] * C;
+  // remaining slots, four at a time so their loads are in flight together
+  for (int32_t e0 = kPre; e0 < U.E; e0 += 4) {
+    int32_t jj[4];
+    T vv[4];
 #pragma unroll
-    for (int c = 0; c < C; ++c) part[c] = fma(v, X[j + c], part[c]);
+    for (int e = 0; e < 4; ++e) {
+      const bool ok = e0 + e < U.E;
+      const int64_t at = (int64_t)U.slot_base + ((int64_t)pass * U.E + (ok ? e0 + e : e0)) * U.lanes + lane;
+      vv[e] = ok ? val[at] : T(0);
+      jj[e] = ok ? s.scol[at] * C : 0;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) part[c] = fma(vv[e], X[jj[e] + c], part[c]);
+    }
   }
   for (int off = width >> 1; off > 0; off >>= 1) {
 #pragma unroll
     for (int c = 0; c < C; ++c) part[c] += __shfl_xor(part[c], off);
   }
-  if (lane == 0) {
-    const int32_t i = p.row * C;
+  if ((lane & (width - 1)) == 0) {
+    const int32_t i = s.irow[U.info_base + r] * C;
     if (block) {
-      const int32_t a = (p.pos - first) * C;
 #pragma unroll
-      for (int c = 0; c < C; ++c) s_r[a + c] = (init ? init[i + c] : X[i + c]) - part[c];
+      for (int c = 0; c < C; ++c) s_r[r * C + c] = (init ? init[i + c] : X[i + c]) - part[c];
     } else {
-      const bool piv = sw_dinv<T>(s) != nullptr;
+      const T *dinv = sw_dinv<T>(s);
+      const T dv = dinv ? dinv[U.info_base + r] : T(1);
 #pragma unroll
       for (int c = 0; c < C; ++c) {
         T v = (init ? init[i + c] : X[i + c]) - part[c];
-        if (piv) v *= p.dinv;
+        if (dinv) v *= dv;
         X[i + c] = v;
       }
     }
   }
 }
 
+// Synchronisation inside a sweep.  With X in LDS the sweep's threads only
+// communicate through LDS (the right-hand side and the factors are read-only
+// in global memory), so the barriers fence LDS only and leave the prefetch
+// loads in flight; within one wave, LDS operations are performed in order, so
+// a wave level only needs a compiler barrier.  With X in global memory both
+// wait for the vector-memory counter.
+template <bool LDSX>
+__device__ __forceinline__ void step_barrier() {
+  if constexpr (LDSX) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+  } else {
+    __syncthreads();
+  }
+}
+
+template <bool LDSX>
+__device__ __forceinline__ void wave_sync() {
+  if constexpr (LDSX) {
+    __builtin_amdgcn_wave_barrier();
+  } else {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+  }
+}
+
 // Level-scheduled triangular sweep on X (rows of C directions).
 //
-// A step is either one dependency level (its rows are independent) or a block
-// of consecutive narrow levels (at most kBlockRows rows in all).  For a block
-// the host has split each row's entries into those reaching rows solved in
-// earlier steps (kept in the CSR arrays) and those inside the block, and
-// stored the dense inverse M^{-1} of the block's own triangular system
-// (column-major, kBlockRows x kBlockRows at most).  A block is then solved in
-// two parallel phases: residuals r = init - (external part), then x = M^{-1} r.
-template <int C, int NT, class T>
-__device__ __forceinline__ void sweep(const DevSweep &s, T *__restrict__ X, const T *__restrict__ init,
-                                      T *__restrict__ s_r, int tid) {
-  const int32_t nl = s.n_levels;
-  if (nl == 0) return;
-  int4 m = s.lev[0];
-  int lg = m.z;
-  RowPre<T> pre = prefetch_row<T>(s, m, tid >> lg, tid & ((1 << lg) - 1), 1 << lg);
-  for (int32_t lev = 0; lev < nl; ++lev) {
-    const int4 cur = m;
-    const int width = 1 << lg;
-    const int lane = tid & (width - 1);
-    const RowPre<T> first = pre;
-    if (lev + 1 < nl) {  // next step's first rows, issued before this step's work
-      m = s.lev[lev + 1];
-      lg = m.z;
-      pre = prefetch_row<T>(s, m, m.w >= -1 ? tid >> lg : INT32_MAX, tid & ((1 << lg) - 1), 1 << lg);
+// Steps: a plain level (independent rows); a block of consecutive narrow
+// levels, whose rows first form residuals r = init - (entries to earlier
+// steps) and then x = M^{-1} r with the block's dense inverse (the host split
+// off the entries inside the block); or a wave step, in which every wave walks
+// its own elimination subtrees level by level with wave-local ordering only.
+// A workgroup barrier separates steps.
+template <int C, int NT, class T, bool LDSX>
+__device__ __forceinline__ void sweep(const DevSweep AS4 &s, T *__restrict__ X, const T *__restrict__ init,
+                                      T *__restrict__ s_r, int tid, long long *ss = nullptr) {
+  const int32_t ns = s.n_steps;
+  if (ns == 0) return;
+  if (ss && tid == 0) ss[0] = wall_clock64();
+  int4 st = s.steps[0];
+  Slots<T> pre;  // first pass of the next level/block step
+  if (st.z != 2) pre = load_slots<T>(s, unit_at(s, st.x), 0, tid);
+  for (int32_t k = 0; k < ns; ++k) {
+    const int4 cur = st;
+    const Slots<T> first = pre;
+    if (k + 1 < ns) {
+      st = s.steps[k + 1];
+      if (st.z != 2) pre = load_slots<T>(s, unit_at(s, st.x), 0, tid);
     }
-    if (cur.w <= -2) {
-      // wave step: each wave walks its own subtrees level by level; rows of a
-      // wave level only read rows of earlier wave levels of the same wave (or
-      // of earlier steps), so wave-local program order is the only ordering
-      const int32_t *dir = s.wdir + (-2 - cur.w);
+    if (cur.z == 2) {
+      // wave step: the wave's units in order, entries loaded a unit ahead
       const int wv = tid >> 6, l64 = tid & 63;
-      const int32_t j1 = dir[wv + 1];
-      for (int32_t j = dir[wv]; j < j1; ++j) {
-        const int4 wm = s.wlev[j];
-        const int wwidth = 1 << wm.z;
-        const int wlane = l64 & (wwidth - 1);
-        for (int32_t r = l64 >> wm.z; r < wm.y; r += (64 >> wm.z)) {
-          const RowPre<T> p = prefetch_row<T>(s, wm, r, wlane, wwidth);
-          row_update<C, NT, T>(s, p, X, init, s_r, wm.x, false, wlane, wwidth);
-        }
-        // this wave's writes before its next level's reads
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      const int32_t u0 = s.wdir[cur.x + wv], u1 = s.wdir[cur.x + wv + 1];
+      Slots<T> a;
+      if (u0 < u1) a = load_slots<T>(s, unit_at(s, u0), 0, l64);
+      for (int32_t u = u0; u < u1; ++u) {
+        const Unit U = unit_at(s, u);
+        Slots<T> b;
+        if (u + 1 < u1) b = load_slots<T>(s, unit_at(s, u + 1), 0, l64);
+        lane_update<C, T>(s, U, 0, l64, a, X, init, s_r, false);
+        const int32_t passes = (U.rows + U.groups - 1) / U.groups;
+        for (int32_t p = 1; p < passes; ++p)
+          lane_update<C, T>(s, U, p, l64, load_slots<T>(s, U, p, l64), X, init, s_r, false);
+        wave_sync<LDSX>();  // this wave's writes before its next unit's reads
+        a = b;
       }
-      __syncthreads();
+      step_barrier<LDSX>();
+      if (ss && tid == 0 && k + 1 < kMaxStepStamps) ss[k + 1] = wall_clock64();
       continue;
     }
-    const bool block = cur.w >= 0;
-    if (first.pos >= 0) {
-      row_update<C, NT, T>(s, first, X, init, s_r, cur.x, block, lane, width);
-      for (int32_t r = (tid >> cur.z) + (NT >> cur.z); r < cur.y; r += (NT >> cur.z)) {
-        const RowPre<T> p = prefetch_row<T>(s, cur, r, lane, width);
-        row_update<C, NT, T>(s, p, X, init, s_r, cur.x, block, lane, width);
-      }
-    }
-    __syncthreads();
+    const Unit U = unit_at(s, cur.x);
+    const bool block = cur.z == 1;
+    lane_update<C, T>(s, U, 0, tid, first, X, init, s_r, block);
+    const int32_t passes = (U.rows + U.groups - 1) / U.groups;
+    for (int32_t p = 1; p < passes; ++p)
+      lane_update<C, T>(s, U, p, tid, load_slots<T>(s, U, p, tid), X, init, s_r, block);
+    step_barrier<LDSX>();
     if (block) {
-      if (tid < cur.y) {
+      if (tid < U.rows) {
         const T *__restrict__ Mi = sw_dense<T>(s) + cur.w;
         T acc[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) acc[c] = T(0);
         for (int32_t b = 0; b <= tid; ++b) {
-          const T v = Mi[tid + b * cur.y];
+          const T v = Mi[tid + b * U.rows];
 #pragma unroll
           for (int c = 0; c < C; ++c) acc[c] = fma(v, s_r[b * C + c], acc[c]);
         }
-        const int32_t i = s.rows[cur.x + tid] * C;
+        const int32_t i = s.irow[U.info_base + tid] * C;
 #pragma unroll
         for (int c = 0; c < C; ++c) X[i + c] = acc[c];
       }
-      __syncthreads();
+      step_barrier<LDSX>();
     }
+    if (ss && tid == 0 && k + 1 < kMaxStepStamps) ss[k + 1] = wall_clock64();
   }
+  __syncthreads();  // full barrier at the end of the sweep
 }
 
 // SpMul: B = -P G_p W into X (rows of C directions, FP64).
 template <int C, int NT>
-__device__ __forceinline__ void spmul(const NetDesc &nd, const WorkItem &a, double *__restrict__ X,
+__device__ __forceinline__ void spmul(const NetDesc AS4 &nd, const WorkItem &a, double *__restrict__ X,
                                       int32_t dir0, int tid) {
   for (int32_t i = tid; i < nd.n_x; i += NT) {
     double acc[C];
@@ -335,7 +378,7 @@ __device__ __forceinline__ void spmul(const NetDesc &nd, const WorkItem &a, doub
 // rank-one scalar, then per bus the branch second-order terms; the x part
 // goes negated into Yx, the p part into the output.  Ends with a barrier.
 template <int C, int NT>
-__device__ __forceinline__ void projection(const NetDesc &nd, const WorkItem &a,
+__device__ __forceinline__ void projection(const NetDesc AS4 &nd, const WorkItem &a,
                                            const double *__restrict__ Z, double *__restrict__ Yx,
                                            double *s_slack, int32_t dir0, int tid) {
   if (tid < C) {
@@ -394,7 +437,7 @@ __device__ __forceinline__ void projection(const NetDesc &nd, const WorkItem &a,
 
 // SpMulAdd: H W += G_p^T Psi.
 template <int C, int NT>
-__device__ __forceinline__ void spmuladd(const NetDesc &nd, const WorkItem &a,
+__device__ __forceinline__ void spmuladd(const NetDesc AS4 &nd, const WorkItem &a,
                                          const double *__restrict__ Psi, int32_t dir0, int tid) {
   for (int32_t q = tid; q < nd.n_p; q += NT) {
     double acc[C];
@@ -412,10 +455,10 @@ __device__ __forceinline__ void spmuladd(const NetDesc &nd, const WorkItem &a,
   }
 }
 
-template <int C, int NT>
-__device__ __forceinline__ void reduction(const NetDesc &nd, const WorkItem &a, double *__restrict__ X,
+template <int C, int NT, bool LDSX>
+__device__ __forceinline__ void reduction(const NetDesc AS4 &nd, const WorkItem &a, double *__restrict__ X,
                                           double *__restrict__ Yx, double *s_slack, double *s_r,
-                                          int32_t dir0, long long *stamps) {
+                                          int32_t dir0, long long *stamps, long long *ss = nullptr) {
   const int tid = threadIdx.x;
   // optional phase timestamps (thread 0)
   long long *st = (stamps && tid == 0) ? stamps : nullptr;
@@ -425,17 +468,17 @@ __device__ __forceinline__ void reduction(const NetDesc &nd, const WorkItem &a, 
   __syncthreads();
   if (st) st[1] = wall_clock64();
   // 2. Z' = U^{-1} L^{-1} B'
-  sweep<C, NT, double>(nd.L, X, nullptr, s_r, tid);
+  sweep<C, NT, double, LDSX>(nd.L, X, nullptr, s_r, tid, ss);
   if (st) st[2] = wall_clock64();
-  sweep<C, NT, double>(nd.U, X, nullptr, s_r, tid);
+  sweep<C, NT, double, LDSX>(nd.U, X, nullptr, s_r, tid, ss ? ss + kMaxStepStamps : nullptr);
   if (st) st[3] = wall_clock64();
   // 3. tensor projection: -Y_x into Yx, Y_p into the output
   projection<C, NT>(nd, a, X, Yx, s_slack, dir0, tid);
   if (st) st[4] = wall_clock64();
   // 4. Psi' = L^{-T} U^{-T} (-P Y_x)
-  sweep<C, NT, double>(nd.Ut, X, Yx, s_r, tid);
+  sweep<C, NT, double, LDSX>(nd.Ut, X, Yx, s_r, tid, ss ? ss + 2 * kMaxStepStamps : nullptr);
   if (st) st[5] = wall_clock64();
-  sweep<C, NT, double>(nd.Lt, X, nullptr, s_r, tid);
+  sweep<C, NT, double, LDSX>(nd.Lt, X, nullptr, s_r, tid, ss ? ss + 3 * kMaxStepStamps : nullptr);
   if (st) st[6] = wall_clock64();
   // 5. H W = Y_p + G_p^T Psi
   spmuladd<C, NT>(nd, a, X, dir0, tid);
@@ -449,12 +492,12 @@ __device__ __forceinline__ void reduction(const NetDesc &nd, const WorkItem &a, 
 // FP64; the tensor projection, G_p products and all stored vectors are FP64.
 // Scratch: V1 (right-hand sides: -G_p W, then -Y_x) and V2 (Z, then Psi),
 // both FP64 in global memory; X32 holds the FP32 correction being solved.
-template <int C, int NT, bool TRANS>
-__device__ __forceinline__ void refined_solve(const NetDesc &nd, const double *__restrict__ V1,
+template <int C, int NT, bool TRANS, bool LDSX>
+__device__ __forceinline__ void refined_solve(const NetDesc AS4 &nd, const double *__restrict__ V1,
                                               double *__restrict__ V2, float *__restrict__ X32,
                                               float *s_r, int refine, int tid) {
-  const DevSweep &s1 = TRANS ? nd.Ut : nd.L;
-  const DevSweep &s2 = TRANS ? nd.Lt : nd.U;
+  const DevSweep AS4 &s1 = TRANS ? nd.Ut : nd.L;
+  const DevSweep AS4 &s2 = TRANS ? nd.Lt : nd.U;
   const int32_t *ptr = TRANS ? nd.gxt_ptr : nd.gx_ptr;
   const int32_t *col = TRANS ? nd.gxt_col : nd.gx_col;
   const double *val = TRANS ? nd.gxt_val : nd.gx_val;
@@ -474,8 +517,8 @@ __device__ __forceinline__ void refined_solve(const NetDesc &nd, const double *_
       for (int c = 0; c < C; ++c) X32[i * C + c] = (float)r[c];
     }
     __syncthreads();
-    sweep<C, NT, float>(s1, X32, nullptr, s_r, tid);
-    sweep<C, NT, float>(s2, X32, nullptr, s_r, tid);
+    sweep<C, NT, float, LDSX>(s1, X32, nullptr, s_r, tid);
+    sweep<C, NT, float, LDSX>(s2, X32, nullptr, s_r, tid);
     for (int32_t i = tid; i < nd.n_x; i += NT) {
 #pragma unroll
       for (int c = 0; c < C; ++c)
@@ -485,8 +528,8 @@ __device__ __forceinline__ void refined_solve(const NetDesc &nd, const double *_
   }
 }
 
-template <int C, int NT>
-__device__ __forceinline__ void reduction_refined(const NetDesc &nd, const WorkItem &a,
+template <int C, int NT, bool LDSX>
+__device__ __forceinline__ void reduction_refined(const NetDesc AS4 &nd, const WorkItem &a,
                                                   float *__restrict__ X32, double *__restrict__ V1,
                                                   double *__restrict__ V2, double *s_slack, float *s_r,
                                                   int refine, int32_t dir0, long long *stamps) {
@@ -496,11 +539,11 @@ __device__ __forceinline__ void reduction_refined(const NetDesc &nd, const WorkI
   spmul<C, NT>(nd, a, V1, dir0, tid);
   __syncthreads();
   if (st) st[1] = wall_clock64();
-  refined_solve<C, NT, false>(nd, V1, V2, X32, s_r, refine, tid);  // Z
+  refined_solve<C, NT, false, LDSX>(nd, V1, V2, X32, s_r, refine, tid);  // Z
   if (st) st[2] = st[3] = wall_clock64();
   projection<C, NT>(nd, a, V2, V1, s_slack, dir0, tid);  // V1 = -Y_x
   if (st) st[4] = wall_clock64();
-  refined_solve<C, NT, true>(nd, V1, V2, X32, s_r, refine, tid);  // Psi
+  refined_solve<C, NT, true, LDSX>(nd, V1, V2, X32, s_r, refine, tid);  // Psi
   if (st) st[5] = st[6] = wall_clock64();
   spmuladd<C, NT>(nd, a, V2, dir0, tid);
   __syncthreads();
@@ -518,7 +561,9 @@ __global__ __launch_bounds__(kThreadsLds) void block_kernel_lds(const LaunchArgs
     const WorkItem it = item_of(la, chunk);
     long long *st = (la.stamps && chunk == (int32_t)blockIdx.x)
                         ? la.stamps + (int64_t)blockIdx.x * kStamps : nullptr;
-    reduction<C, kThreadsLds>(*it.nd, it, smem, Yx, s_slack, s_r, (chunk - it.chunk0) * C, st);
+    reduction<C, kThreadsLds, true>(*(const NetDesc AS4 *)it.nd, it, smem, Yx, s_slack, s_r,
+                                    (chunk - it.chunk0) * C, st,
+                                    (blockIdx.x == 0 && chunk == 0) ? la.step_stamps : nullptr);
   }
 }
 
@@ -533,7 +578,9 @@ __global__ __launch_bounds__(kThreads) void block_kernel_global(const LaunchArgs
     const WorkItem it = item_of(la, chunk);
     long long *st = (la.stamps && chunk == (int32_t)blockIdx.x)
                         ? la.stamps + (int64_t)blockIdx.x * kStamps : nullptr;
-    reduction<C, kThreads>(*it.nd, it, X, Yx, s_slack, s_r, (chunk - it.chunk0) * C, st);
+    reduction<C, kThreads, false>(*(const NetDesc AS4 *)it.nd, it, X, Yx, s_slack, s_r,
+                                  (chunk - it.chunk0) * C, st,
+                                  (blockIdx.x == 0 && chunk == 0) ? la.step_stamps : nullptr);
   }
 }
 
@@ -549,7 +596,7 @@ __global__ __launch_bounds__(kThreadsLds) void refined_kernel_lds(const LaunchAr
     const WorkItem it = item_of(la, chunk);
     long long *st = (la.stamps && chunk == (int32_t)blockIdx.x)
                         ? la.stamps + (int64_t)blockIdx.x * kStamps : nullptr;
-    reduction_refined<C, kThreadsLds>(*it.nd, it, smem32, V1, V2, s_slack, s_r, la.refine,
+    reduction_refined<C, kThreadsLds, true>(*(const NetDesc AS4 *)it.nd, it, smem32, V1, V2, s_slack, s_r, la.refine,
                                       (chunk - it.chunk0) * C, st);
   }
 }
@@ -566,7 +613,7 @@ __global__ __launch_bounds__(kThreads) void refined_kernel_global(const LaunchAr
     const WorkItem it = item_of(la, chunk);
     long long *st = (la.stamps && chunk == (int32_t)blockIdx.x)
                         ? la.stamps + (int64_t)blockIdx.x * kStamps : nullptr;
-    reduction_refined<C, kThreads>(*it.nd, it, X32, V1, V2, s_slack, s_r, la.refine,
+    reduction_refined<C, kThreads, false>(*(const NetDesc AS4 *)it.nd, it, X32, V1, V2, s_slack, s_r, la.refine,
                                    (chunk - it.chunk0) * C, st);
   }
 }
@@ -606,6 +653,8 @@ struct Runner {
   int32_t items_cap = 0;
   hipEvent_t items_done = nullptr;  // the last launch that read the work list
   int32_t launches = 0, last_c = 0;
+  long long *step_stamps = nullptr;  // debug (RH_STEP_STAMPS)
+  bool step_stamps_pending = false;
 };
 
 rh_status query_info(int device, DeviceInfo &info, std::string &err) {
@@ -631,6 +680,7 @@ void runner_free(Runner &r) {
   if (r.items_dev) (void)hipFree(r.items_dev);
   if (r.items_host) (void)hipHostFree(r.items_host);
   if (r.items_done) (void)hipEventDestroy(r.items_done);
+  if (r.step_stamps) (void)hipFree(r.step_stamps);
   r = Runner();
 }
 
@@ -650,6 +700,20 @@ rh_status runner_collect(Runner &r, const DeviceInfo &info, rh_report &rep, std:
       rep.phase_us[p] = sum / r.stamps_groups / info.wall_khz * 1e3;
     }
     r.stamps_groups = 0;
+  }
+  if (r.step_stamps_pending && info.wall_khz > 0) {
+    std::vector<long long> st(4 * kMaxStepStamps);
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(st.data(), r.step_stamps, st.size() * sizeof(long long), hipMemcpyDeviceToHost));
+    const char *nm[4] = {"L", "U", "Ut", "Lt"};
+    for (int w = 0; w < 4; ++w) {
+      fprintf(stderr, "steps %s (us):", nm[w]);
+      for (int k = 1; k < kMaxStepStamps && st[w * kMaxStepStamps + k] != 0; ++k)
+        fprintf(stderr, " %.2f",
+                (st[w * kMaxStepStamps + k] - st[w * kMaxStepStamps + k - 1]) / info.wall_khz * 1e3);
+      fprintf(stderr, "\n");
+    }
+    r.step_stamps_pending = false;
   }
   if (r.ev_used > 0) {
     double sum = 0.0;
@@ -777,6 +841,13 @@ rh_status run_items(const DeviceInfo &info, Runner &r, int32_t timing, int32_t r
                            hipMemcpyHostToDevice, s));
     la.items = r.items_dev;
   }
+  la.step_stamps = nullptr;
+  if (std::getenv("RH_STEP_STAMPS")) {
+    if (!r.step_stamps) HIP_TRY(hipMalloc(&r.step_stamps, 4 * kMaxStepStamps * sizeof(long long)));
+    HIP_TRY(hipMemsetAsync(r.step_stamps, 0, 4 * kMaxStepStamps * sizeof(long long), s));
+    la.step_stamps = r.step_stamps;
+    r.step_stamps_pending = true;
+  }
   la.stamps = nullptr;
   if (timing >= 2) {
     if (r.stamps_cap < groups) {
@@ -821,6 +892,7 @@ rh_status run_items(const DeviceInfo &info, Runner &r, int32_t timing, int32_t r
 }  // namespace
 
 struct DeviceNet {
+  std::vector<int32_t> sweep_steps;  // barrier steps of the L, U, U^T, L^T sweeps
   NetDesc nd{};               // host copy of the descriptor (device pointers)
   NetDesc *nd_dev = nullptr;  // the same descriptor in device memory
   std::vector<void *> allocs;
@@ -867,35 +939,32 @@ rh_status upload(DeviceNet &dn, const std::vector<T> &v, const T **out, std::str
 rh_status upload_sweep(DeviceNet *dn, const Sweep &s, int32_t n, const std::vector<int32_t> &parent,
                        bool forward, const ScheduleParams &prm, DevSweep &o, std::string &err) {
   const Schedule sc = build_schedule(s, n, parent, forward, prm);
-  o.n_levels = (int32_t)(sc.meta.size() / 4);
-  const int32_t *mp = nullptr;
-  UP(sc.meta, mp);
-  o.lev = reinterpret_cast<const int4 *>(mp);
-  UP(sc.s.rows, o.rows);
-  UP(sc.s.ptr, o.ptr);
-  UP(sc.s.col, o.col);
-  UP(sc.s.val, o.val);
-  o.dinv = nullptr;
-  if (!sc.s.dinv.empty()) UP(sc.s.dinv, o.dinv);
+  const Packed pk = pack_schedule(sc, kThreads);
+  o.n_steps = (int32_t)(pk.steps.size() / 4);
+  const int32_t *p = nullptr;
+  UP(pk.steps, p);
+  o.steps = reinterpret_cast<const int4 *>(p);
+  UP(pk.units, p);
+  o.units = reinterpret_cast<const int4 *>(p);
+  o.wdir = nullptr;
+  if (!pk.wdir.empty()) UP(pk.wdir, o.wdir);
+  UP(pk.scol, o.scol);
+  UP(pk.irow, o.irow);
+  UP(pk.sval, o.sval);
+  o.idinv = nullptr;
+  if (!pk.idinv.empty()) UP(pk.idinv, o.idinv);
   o.dense = nullptr;
-  if (!sc.dense.empty()) UP(sc.dense, o.dense);
+  if (!pk.dense.empty()) UP(pk.dense, o.dense);
   // FP32 copies for the refined mode
-  const std::vector<float> v32(sc.s.val.begin(), sc.s.val.end());
-  const std::vector<float> d32(sc.s.dinv.begin(), sc.s.dinv.end());
-  const std::vector<float> m32(sc.dense.begin(), sc.dense.end());
-  UP(v32, o.val32);
-  o.dinv32 = nullptr;
-  if (!d32.empty()) UP(d32, o.dinv32);
+  const std::vector<float> v32(pk.sval.begin(), pk.sval.end());
+  const std::vector<float> d32(pk.idinv.begin(), pk.idinv.end());
+  const std::vector<float> m32(pk.dense.begin(), pk.dense.end());
+  UP(v32, o.sval32);
+  o.idinv32 = nullptr;
+  if (!d32.empty()) UP(d32, o.idinv32);
   o.dense32 = nullptr;
   if (!m32.empty()) UP(m32, o.dense32);
-  o.wdir = nullptr;
-  o.wlev = nullptr;
-  if (!sc.wdir.empty()) {
-    UP(sc.wdir, o.wdir);
-    const int32_t *wp = nullptr;
-    UP(sc.wlev, wp);
-    o.wlev = reinterpret_cast<const int4 *>(wp);
-  }
+  dn->sweep_steps.push_back(o.n_steps);
   return RH_OK;
 }
 
@@ -991,8 +1060,8 @@ rh_status device_upload(Network &net, std::string &err) {
       upload_sweep(dn, sut, n, parent, true, prm, nd.Ut, err) != RH_OK ||
       upload_sweep(dn, slt, n, parent, false, prm, nd.Lt, err) != RH_OK)
     return RH_EDEVICE;
-  net.report.steps_l = nd.L.n_levels;
-  net.report.steps_u = nd.U.n_levels;
+  net.report.steps_l = nd.L.n_steps;
+  net.report.steps_u = nd.U.n_steps;
 
   // G_p with rows in permuted order, and G_p^T with permuted columns
   {

@@ -58,10 +58,27 @@ struct Schedule {
   std::vector<int32_t> wdir, wlev;
 };
 
+// Device form of a schedule.  Every unit (a level step, the rows of a block,
+// or one wave level of a wave step) stores its entries in per-lane slots:
+// rows are spread over groups of 2^lg lanes, `groups` rows per pass, and lane
+// j of a group holds entries j, j + 2^lg, ... of its row, `E` slots per lane
+// and pass, padded with (column 0, value 0).  Slot (pass, e, lane) sits at
+// slot_base + (pass * E + e) * lanes + lane, so a lane needs no row pointer.
+// units: 8 ints each {slot_base, info_base, rows, groups, lg, E, lanes, 0};
+// irow/idinv give each row's matrix row and reciprocal pivot (unit order).
+// steps: 4 ints each {unit or wave directory offset, 0, kind, dense offset},
+// kind 0 = level, 1 = block (dense inverse at the offset), 2 = wave step
+// (its waves' unit ranges are wdir[off + w] .. wdir[off + w + 1]).
+struct Packed {
+  std::vector<int32_t> steps, units, wdir;
+  std::vector<int32_t> scol, irow;
+  std::vector<double> sval, idinv, dense;
+};
+
 struct ScheduleParams {
   int bmax = 64;          // rows of a merged block (0: no blocks)
   int block_rows = 64;    // the kernel's block capacity
-  int lane_budget = 512;  // rows x lanes of a level step
+  int lane_budget = 1024;  // rows x lanes of a level step
   int n_waves = 16;       // waves of the kernel's workgroup
   int wave_mode = 1;      // 0: no wave step
 };
@@ -139,6 +156,9 @@ int lane_log2(int32_t rows, int32_t longest, int lane_budget);
 Schedule build_schedule(const Sweep &in, int32_t n, const std::vector<int32_t> &parent, bool forward,
                         const ScheduleParams &prm);
 std::vector<int32_t> etree_parent(const LuPlan &lu);
+// Pack a schedule into per-lane slots; `lanes` = workgroup size, wave steps use
+// 64 lanes per wave.
+Packed pack_schedule(const Schedule &sc, int lanes);
 
 // ---- device path (device.hip)
 rh_status device_upload(Network &net, std::string &err);

@@ -550,4 +550,66 @@ std::vector<int32_t> etree_parent(const LuPlan &lu) {
   return parent;
 }
 
+namespace {
+
+// One unit: rows at positions [b, b + rows) of sc.s with lane groups of 2^lg.
+int32_t pack_unit(const Schedule &sc, int32_t b, int32_t rows, int lg, int max_lanes, Packed &pk) {
+  const Sweep &s = sc.s;
+  const int32_t w = 1 << lg;
+  const int32_t groups = std::max<int32_t>(1, std::min<int32_t>(rows, max_lanes / w));
+  const int32_t lanes = groups * w;
+  const int32_t passes = rows > 0 ? (rows + groups - 1) / groups : 0;
+  int32_t longest = 0;
+  for (int32_t r = 0; r < rows; ++r) longest = std::max(longest, s.ptr[b + r + 1] - s.ptr[b + r]);
+  const int32_t E = (longest + w - 1) / w;
+  const int32_t slot_base = (int32_t)pk.scol.size(), info_base = (int32_t)pk.irow.size();
+  pk.scol.resize(pk.scol.size() + (size_t)passes * E * lanes, 0);
+  pk.sval.resize(pk.sval.size() + (size_t)passes * E * lanes, 0.0);
+  for (int32_t r = 0; r < rows; ++r) {
+    const int32_t p = r / groups, g = r % groups, pos = b + r;
+    const int32_t q0 = s.ptr[pos], len = s.ptr[pos + 1] - q0;
+    for (int32_t j = 0; j < w; ++j)
+      for (int32_t e = 0; e < E; ++e) {
+        const int32_t q = j + e * w;
+        if (q >= len) continue;
+        const size_t at = (size_t)slot_base + ((size_t)p * E + e) * lanes + (size_t)g * w + j;
+        pk.scol[at] = s.col[q0 + q];
+        pk.sval[at] = s.val[q0 + q];
+      }
+    pk.irow.push_back(s.rows[pos]);
+    if (!s.dinv.empty()) pk.idinv.push_back(s.dinv[pos]);
+  }
+  const int32_t u = (int32_t)(pk.units.size() / 8);
+  pk.units.insert(pk.units.end(), {slot_base, info_base, rows, groups, lg, E, lanes, 0});
+  return u;
+}
+
+}  // namespace
+
+Packed pack_schedule(const Schedule &sc, int lanes) {
+  Packed pk;
+  pk.dense = sc.dense;
+  const size_t ns = sc.meta.size() / 4;
+  for (size_t st = 0; st < ns; ++st) {
+    const int32_t b = sc.meta[4 * st], rows = sc.meta[4 * st + 1], lg = sc.meta[4 * st + 2];
+    const int32_t kind = sc.meta[4 * st + 3];
+    if (kind <= -2) {
+      const int32_t d = -2 - kind;
+      const int32_t off = (int32_t)pk.wdir.size();
+      const int32_t nw = lanes / 64;
+      for (int32_t w = 0; w < nw; ++w) {
+        pk.wdir.push_back((int32_t)(pk.units.size() / 8));
+        for (int32_t j = sc.wdir[d + w]; j < sc.wdir[d + w + 1]; ++j)
+          pack_unit(sc, sc.wlev[4 * j], sc.wlev[4 * j + 1], sc.wlev[4 * j + 2], 64, pk);
+      }
+      pk.wdir.push_back((int32_t)(pk.units.size() / 8));
+      pk.steps.insert(pk.steps.end(), {off, 0, 2, 0});
+    } else {
+      const int32_t u = pack_unit(sc, b, rows, lg, lanes, pk);
+      pk.steps.insert(pk.steps.end(), {u, 0, kind >= 0 ? 1 : 0, kind >= 0 ? kind : 0});
+    }
+  }
+  return pk;
+}
+
 }  // namespace rh

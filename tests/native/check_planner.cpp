@@ -90,6 +90,65 @@ static void emulate(const Schedule &sc, std::vector<double> &X, bool &ok) {
   (void)done;
 }
 
+// Emulates the kernel on the packed (per-lane slot) form: every lane sums its
+// slots, lane groups combine, the group's row is written.  Wave steps run
+// waves in reverse order; reads of rows not yet final clear `ok`.
+static void emulate_packed(const Packed &pk, std::vector<double> &X, std::vector<char> pending, bool &ok) {
+  auto unit = [&](int u, bool block, std::vector<double> &r) {
+    const int *U = &pk.units[8 * u];
+    const int slot_base = U[0], info_base = U[1], rows = U[2], groups = U[3], lg = U[4], E = U[5],
+              lanes = U[6];
+    const int w = 1 << lg;
+    r.assign(rows, 0.0);
+    std::vector<double> part(rows, 0.0);
+    const int passes = rows ? (rows + groups - 1) / groups : 0;
+    for (int p = 0; p < passes; ++p)
+      for (int lane = 0; lane < lanes; ++lane) {
+        const int row = p * groups + lane / w;
+        if (row >= rows) continue;
+        for (int e = 0; e < E; ++e) {
+          const size_t at = (size_t)slot_base + ((size_t)p * E + e) * lanes + lane;
+          if (pk.sval[at] != 0.0 && pending[pk.scol[at]]) ok = false;
+          part[row] += pk.sval[at] * X[pk.scol[at]];
+        }
+      }
+    for (int a = 0; a < rows; ++a) {
+      const int i = pk.irow[info_base + a];
+      double v = X[i] - part[a];
+      if (block) {
+        r[a] = v;
+      } else {
+        if (!pk.idinv.empty()) v *= pk.idinv[info_base + a];
+        X[i] = v;
+        pending[i] = 0;
+      }
+    }
+  };
+  std::vector<double> r;
+  for (size_t st = 0; st < pk.steps.size() / 4; ++st) {
+    const int a = pk.steps[4 * st], kind = pk.steps[4 * st + 2], off = pk.steps[4 * st + 3];
+    if (kind == 2) {
+      const int nw = 16;
+      for (int w = nw - 1; w >= 0; --w)
+        for (int u = pk.wdir[a + w]; u < pk.wdir[a + w + 1]; ++u) unit(u, false, r);
+    } else if (kind == 0) {
+      unit(a, false, r);
+    } else {
+      unit(a, true, r);
+      const int *U = &pk.units[8 * a];
+      const int rows = U[2], info_base = U[1];
+      for (int x = 0; x < rows; ++x) {
+        double acc = 0;
+        for (int c = 0; c <= x; ++c) acc += pk.dense[off + x + (size_t)c * rows] * r[c];
+        X[pk.irow[info_base + x]] = acc;
+        pending[pk.irow[info_base + x]] = 0;
+      }
+    }
+  }
+  for (char c : pending)
+    if (c) ok = false;
+}
+
 static void plain(const Sweep &s, std::vector<double> &X) {
   for (size_t p = 0; p < s.rows.size(); ++p) {
     double v = X[s.rows[p]];
@@ -204,6 +263,24 @@ int main(int argc, char **argv) {
         if (!ok) ++bad;
         int waves = 0;
         for (size_t q = 0; q < sc.meta.size() / 4; ++q) waves += sc.meta[4 * q + 3] <= -2;
+        // the packed form the kernel reads
+        {
+          const Packed pk = pack_schedule(sc, 1024);
+          std::vector<double> Xp = Y;
+          for (size_t p = 0; p < Xp.size(); ++p) Xp[p] = 0;
+          std::vector<double> X0(nx);
+          std::mt19937_64 r2(99 + k);
+          for (auto &v : X0) v = nd(r2);
+          std::vector<double> Xa = X0, Xb = X0;
+          std::vector<char> pend(nx, 0);
+          for (int32_t rr : sw[k].rows) pend[rr] = 1;
+          bool okp = true;
+          emulate_packed(pk, Xa, pend, okp);
+          plain(sw[k], Xb);
+          if (!okp) ++bad;
+          printf("max_err packed_%s_w%d_b%d %.3e order_ok %d slots %zu\n", nm[k], wave, bmax,
+                 relerr(Xa, Xb), okp ? 1 : 0, pk.scol.size());
+        }
         printf("max_err sweep_%s_w%d_b%d %.3e steps %zu wave_steps %d order_ok %d\n", nm[k], wave, bmax,
                relerr(X, Y), sc.meta.size() / 4, waves, ok ? 1 : 0);
       }
