@@ -5,14 +5,15 @@
 // every step of the reduction for its directions ("direction-owned" scheme):
 //
 //   1. SpMul            B' = -P G_p W                        (row-parallel)
-//   2. BatchSparseSolve Z' = U^{-1} L^{-1} B'                (level-scheduled)
+//   2. BatchSparseSolve Z' = Uh^{-1} D^{-1} L^{-1} B'        (level-scheduled;
+//      U = D Uh, so every sweep has a unit diagonal)
 //   3. BatchTensorProjection (Sec. 4.2, forward-over-reverse of the branch
 //      flows): every bus sums the second-order terms of its incident branches
 //      (gather form of the "edges, then nodes" accumulation: no atomics), plus
 //      the slack-cost rank-one term and the 2 c2 diagonal of the generator
 //      costs.  The x part is written negated as the right-hand side of
 //      step 4, the p part straight into the output.
-//   4. BatchSparseSolve (transposed)  Psi' = L^{-T} U^{-T} (-P Y_x)
+//   4. BatchSparseSolve (transposed)  Psi' = L^{-T} D^{-1} Uh^{-T} (-P Y_x)
 //   5. SpMulAdd         H W = Y_p + G_p^T Psi
 //
 // The working vector X (n_x x C, the C directions of a row contiguous) lives in
@@ -65,8 +66,12 @@ struct DevSweep {
   const int4 *units;  // 2 x int4: {slot_base, info_base, rows, groups}, {lg, E, lanes, 0}
   const int32_t *wdir;
   const int32_t *scol, *irow;
-  const double *sval, *idinv, *dense;          // idinv == nullptr: unit diagonal
-  const float *sval32, *idinv32, *dense32;     // FP32 copies (refined mode)
+  const double *sval, *dense;   // unit diagonal (pivots are applied between sweeps)
+  const float *sval32, *dense32;  // FP32 copies (refined mode)
+  // the sweep's arrays as byte ranges of one allocation: read in both
+  // precisions, FP64 only, FP32 only (see l2_warm)
+  const char *warm_common, *warm64, *warm32;
+  int64_t warm_common_bytes, warm64_bytes, warm32_bytes;
 };
 
 template <class T>
@@ -76,12 +81,6 @@ __device__ __forceinline__ const double *sw_val<double>(const DevSweep AS4 &s) {
 template <>
 __device__ __forceinline__ const float *sw_val<float>(const DevSweep AS4 &s) { return s.sval32; }
 template <class T>
-__device__ __forceinline__ const T *sw_dinv(const DevSweep AS4 &s);
-template <>
-__device__ __forceinline__ const double *sw_dinv<double>(const DevSweep AS4 &s) { return s.idinv; }
-template <>
-__device__ __forceinline__ const float *sw_dinv<float>(const DevSweep AS4 &s) { return s.idinv32; }
-template <class T>
 __device__ __forceinline__ const T *sw_dense(const DevSweep AS4 &s);
 template <>
 __device__ __forceinline__ const double *sw_dense<double>(const DevSweep AS4 &s) { return s.dense; }
@@ -90,7 +89,9 @@ __device__ __forceinline__ const float *sw_dense<float>(const DevSweep AS4 &s) {
 
 struct NetDesc {
   int32_t n_x, n_p, n_bus, n_pg, n_slack;
-  DevSweep L, U, Ut, Lt;
+  DevSweep L, U, Ut, Lt;  // U and Ut hold the unit factor D^{-1} U
+  const double *pivinv;   // D^{-1}, applied between the two sweeps of a solve
+  const float *pivinv32;
   const int32_t *gp_ptr, *gp_col;  // G_p, rows in permuted x order
   const double *gp_val;
   const int32_t *gpt_ptr, *gpt_col;  // G_p^T, columns in permuted x order
@@ -168,21 +169,52 @@ __device__ __forceinline__ Unit unit_at(const DevSweep AS4 &s, int32_t u) {
   return Unit{a.x, a.y, a.z, a.w, b.x, b.y, b.z};
 }
 
-// The first kPre entry slots of one lane in one pass of a unit.  They do not
-// depend on the solution vector, so they are loaded a unit or two ahead and
-// the only dependent access left on the critical path is the LDS gather.
+// Per-lane table of a wave's unit descriptors: lane i holds the slot base,
+// row-info base and compact word of unit tb + i (compact = rows | lg << 16 |
+// E << 19; groups = min(rows, 64 >> lg)).
+constexpr int kWaveAhead = 2;  // units whose slots a wave has in flight
+struct WaveTable {
+  int32_t slot_base, info_base, compact;
+};
+
+__device__ __forceinline__ WaveTable wave_table(const DevSweep AS4 &s, int32_t tb, int32_t u1, int l64) {
+  WaveTable t{0, 0, 0};
+  if (tb + l64 < u1) {
+    const int32_t *e = reinterpret_cast<const int32_t *>(s.units) + 8 * (int64_t)(tb + l64);
+    t.slot_base = e[0];
+    t.info_base = e[1];
+    t.compact = e[7];
+  }
+  return t;
+}
+
+__device__ __forceinline__ Unit wave_unit(const WaveTable &t, int32_t i) {
+  const int32_t sb = __builtin_amdgcn_readlane(t.slot_base, i);
+  const int32_t ib = __builtin_amdgcn_readlane(t.info_base, i);
+  const int32_t cw = __builtin_amdgcn_readlane(t.compact, i);
+  const int32_t rows = cw & 0xFFFF, lg = (cw >> 16) & 7, E = (int32_t)((uint32_t)cw >> 19);
+  const int32_t groups = max(1, min(rows, 64 >> lg));
+  return Unit{sb, ib, rows, groups, lg, E, groups << lg};
+}
+
+// The first kPre entry slots of one lane in one pass of a unit, with its
+// row's matrix row.  None of it depends on the solution
+// vector, so it is loaded a unit (or a step) ahead and the only dependent
+// accesses left on the critical path are LDS gathers and wave shuffles.
 constexpr int kPre = 4;
 template <class T>
 struct Slots {
   int32_t col[kPre];
   T val[kPre];
+  int32_t row;
 };
 
 template <class T>
 __device__ __forceinline__ Slots<T> load_slots(const DevSweep AS4 &s, const Unit &U, int32_t pass, int lane) {
   Slots<T> L;
   const T *val = sw_val<T>(s);
-  const bool act = lane < U.lanes && pass * U.groups + (lane >> U.lg) < U.rows;
+  const int32_t r = pass * U.groups + (lane >> U.lg);
+  const bool act = lane < U.lanes && r < U.rows;
 #pragma unroll
   for (int e = 0; e < kPre; ++e) {
     const bool ok = act && e < U.E;
@@ -190,17 +222,104 @@ __device__ __forceinline__ Slots<T> load_slots(const DevSweep AS4 &s, const Unit
     L.col[e] = ok ? s.scol[at] : 0;
     L.val[e] = ok ? val[at] : T(0);
   }
+  L.row = act ? s.irow[U.info_base + r] : 0;
   return L;
 }
 
+// The dense inverse of a block (rows <= kBlockRows, column-major) is applied
+// by all NT threads: NT / kBlockRows lanes per row, each with E entries
+// (columns j, j + lanes, ...) that it loads a step ahead, then a butterfly.
+template <int NT>
+struct DenseShape {
+  static constexpr int lanes = NT / kBlockRows;
+  static constexpr int E = kBlockRows / lanes;
+  static_assert(lanes * E == kBlockRows && (lanes & (lanes - 1)) == 0 && lanes <= 64, "dense block shape");
+};
+
+template <class T, int NT>
+struct DenseRow {
+  T m[DenseShape<NT>::E];
+  int32_t row;
+};
+
+template <class T, int NT>
+__device__ __forceinline__ DenseRow<T, NT> load_dense(const DevSweep AS4 &s, int32_t off, const Unit &U, int tid) {
+  using D = DenseShape<NT>;
+  DenseRow<T, NT> R;
+  const T *Mi = sw_dense<T>(s) + off;
+  const int32_t a = tid / D::lanes, j = tid % D::lanes;
+#pragma unroll
+  for (int e = 0; e < D::E; ++e) {
+    const int32_t b = j + e * D::lanes;
+    R.m[e] = (a < U.rows && b <= a) ? Mi[a + b * U.rows] : T(0);
+  }
+  R.row = (j == 0 && a < U.rows) ? s.irow[U.info_base + a] : 0;
+  return R;
+}
+
+// x = M^{-1} r for a block's rows: r in s_r (rows of C), x to X[row].
+template <int C, int NT, class T>
+__device__ __forceinline__ void dense_apply(const Unit &U, const DenseRow<T, NT> &R, T *__restrict__ X,
+                                            const T *__restrict__ s_r, int tid) {
+  using D = DenseShape<NT>;
+  const int32_t a = tid / D::lanes, j = tid % D::lanes;
+  T acc[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) acc[c] = T(0);
+#pragma unroll
+  for (int e = 0; e < D::E; ++e) {
+    const int32_t b = j + e * D::lanes;
+    const bool ok = a < U.rows && b <= a;
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = fma(R.m[e], ok ? s_r[b * C + c] : T(0), acc[c]);
+  }
+#pragma unroll
+  for (int off = D::lanes >> 1; off > 0; off >>= 1) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] += __shfl_xor(acc[c], off);
+  }
+  if (j == 0 && a < U.rows) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) X[R.row * C + c] = acc[c];
+  }
+}
+
+// Cross-lane moves within a row of 16 lanes (DPP, no LDS round trip).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)u, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+// Sum over aligned groups of 2^lg lanes (lg uniform, 0..6); the group's first
+// lane receives the total.  Pairs within a quad (lane ^ 1, lane ^ 2), then
+// the mirror within 8 and within 16 lanes (every lane of the smaller group
+// holds its total by then), then lane ^ 16 and lane ^ 32 by permute.
+template <class T>
+__device__ __forceinline__ T group_sum(T v, int lg) {
+  if (lg >= 1) v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+  if (lg >= 2) v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+  if (lg >= 3) v += dpp_move<0x141>(v);  // row_half_mirror
+  if (lg >= 4) v += dpp_move<0x140>(v);  // row_mirror
+  if (lg >= 5) v += __shfl_xor(v, 16);
+  if (lg >= 6) v += __shfl_xor(v, 32);
+  return v;
+}
+
 // One lane's share of one pass of a unit: partial dot product of its slots
-// with X, butterfly over the lane group, and the group's first lane writes the
-// row (or, in a block, its residual into s_r).  Padding slots are (0, 0).
+// with X (the prefetched ones, then any further ones), sum over the lane
+// group, and the group's first lane writes the row (or, in a block, its
+// residual into s_r).  Padding slots are (0, 0).
 template <int C, class T>
 __device__ __forceinline__ void lane_update(const DevSweep AS4 &s, const Unit &U, int32_t pass, int lane,
-                                            const Slots<T> &L, T *__restrict__ X,
-                                            const T *__restrict__ init, T *__restrict__ s_r,
-                                            bool block) {
+                                            const Slots<T> &L, T *__restrict__ X, const T *__restrict__ init,
+                                            T *__restrict__ s_r, bool block) {
   const int width = 1 << U.lg;
   const int32_t r = pass * U.groups + (lane >> U.lg);
   if (lane >= U.lanes || r >= U.rows) return;  // whole lane groups only
@@ -231,26 +350,40 @@ __device__ __forceinline__ void lane_update(const DevSweep AS4 &s, const Unit &U
       for (int c = 0; c < C; ++c) part[c] = fma(vv[e], X[jj[e] + c], part[c]);
     }
   }
-  for (int off = width >> 1; off > 0; off >>= 1) {
 #pragma unroll
-    for (int c = 0; c < C; ++c) part[c] += __shfl_xor(part[c], off);
-  }
+  for (int c = 0; c < C; ++c) part[c] = group_sum(part[c], U.lg);
   if ((lane & (width - 1)) == 0) {
-    const int32_t i = s.irow[U.info_base + r] * C;
+    const int32_t i = L.row * C;
     if (block) {
 #pragma unroll
       for (int c = 0; c < C; ++c) s_r[r * C + c] = (init ? init[i + c] : X[i + c]) - part[c];
     } else {
-      const T *dinv = sw_dinv<T>(s);
-      const T dv = dinv ? dinv[U.info_base + r] : T(1);
 #pragma unroll
-      for (int c = 0; c < C; ++c) {
-        T v = (init ? init[i + c] : X[i + c]) - part[c];
-        if (dinv) v *= dv;
-        X[i + c] = v;
-      }
+      for (int c = 0; c < C; ++c) X[i + c] = (init ? init[i + c] : X[i + c]) - part[c];
     }
   }
+}
+
+// Bring a sweep's arrays into the L2 of this workgroup's XCD before its
+// dependent steps reach them.  Every workgroup runs the same sweep at about
+// the same time, so otherwise each step's lines miss in all of them at once
+// and every step waits for HBM.  Consecutive workgroup ids are dispatched
+// round-robin over the XCDs; the workgroups of one XCD split the range and
+// touch one dword per 128-byte line.  The words are folded into the return
+// value, which the caller consumes at the end of the sweep, so the loads are
+// kept and nothing waits for them early.
+constexpr int kXcds = 8;
+
+template <int NT>
+__device__ __forceinline__ uint32_t l2_warm(const char *p, int64_t bytes, int tid) {
+  if (!p || bytes <= 0) return 0u;
+  const int64_t lines = (bytes + 127) >> 7;  // ranges are multiples of 4 bytes
+  const int32_t xcd = (int32_t)(blockIdx.x % kXcds), j = (int32_t)(blockIdx.x / kXcds);
+  const int32_t nwg = ((int32_t)gridDim.x - xcd + kXcds - 1) / kXcds;
+  const int64_t l0 = lines * j / nwg, l1 = lines * (j + 1) / nwg;
+  uint32_t acc = 0u;
+  for (int64_t l = l0 + tid; l < l1; l += NT) acc ^= *reinterpret_cast<const uint32_t *>(p + (l << 7));
+  return acc;
 }
 
 // Synchronisation inside a sweep.  With X in LDS the sweep's threads only
@@ -295,64 +428,98 @@ __device__ __forceinline__ void sweep(const DevSweep AS4 &s, T *__restrict__ X, 
   const int32_t ns = s.n_steps;
   if (ns == 0) return;
   if (ss && tid == 0) ss[0] = wall_clock64();
+  const uint32_t warm = l2_warm<NT>(s.warm_common, s.warm_common_bytes, tid) ^
+                        (sizeof(T) == 8 ? l2_warm<NT>(s.warm64, s.warm64_bytes, tid)
+                                        : l2_warm<NT>(s.warm32, s.warm32_bytes, tid));
   int4 st = s.steps[0];
-  Slots<T> pre;  // first pass of the next level/block step
-  if (st.z != 2) pre = load_slots<T>(s, unit_at(s, st.x), 0, tid);
+  Slots<T> pre;          // first pass of the next level/block step
+  DenseRow<T, NT> preD;  // and its dense inverse entries if it is a block
+  if (st.z != 2) {
+    const Unit U = unit_at(s, st.x);
+    pre = load_slots<T>(s, U, 0, tid);
+    if (st.z == 1) preD = load_dense<T, NT>(s, st.w, U, tid);
+  }
   for (int32_t k = 0; k < ns; ++k) {
     const int4 cur = st;
     const Slots<T> first = pre;
-    if (k + 1 < ns) {
-      st = s.steps[k + 1];
-      if (st.z != 2) pre = load_slots<T>(s, unit_at(s, st.x), 0, tid);
-    }
+    const DenseRow<T, NT> dense = preD;
     if (cur.z == 2) {
-      // wave step: the wave's units in order, entries loaded a unit ahead
+      // wave step: the wave's units in order.  The wave keeps the compact
+      // descriptors of up to 64 of its units in a per-lane table (read by
+      // readlane, no scalar memory round trip per unit) and loads each
+      // unit's slots kWaveAhead units ahead; the next step's prefetch is
+      // issued once the wave is done.
       const int wv = tid >> 6, l64 = tid & 63;
       const int32_t u0 = s.wdir[cur.x + wv], u1 = s.wdir[cur.x + wv + 1];
-      Slots<T> a;
-      if (u0 < u1) a = load_slots<T>(s, unit_at(s, u0), 0, l64);
+      int32_t tb = u0;
+      WaveTable tab = wave_table(s, tb, u1, l64);
+      Slots<T> ring[kWaveAhead];
+#pragma unroll
+      for (int d = 0; d < kWaveAhead; ++d)
+        if (u0 + d < u1) ring[d] = load_slots<T>(s, wave_unit(tab, d), 0, l64);
       for (int32_t u = u0; u < u1; ++u) {
-        const Unit U = unit_at(s, u);
-        Slots<T> b;
-        if (u + 1 < u1) b = load_slots<T>(s, unit_at(s, u + 1), 0, l64);
-        lane_update<C, T>(s, U, 0, l64, a, X, init, s_r, false);
+        if (u + kWaveAhead >= tb + 64) {  // uniform: refill the table from u
+          tb = u;
+          tab = wave_table(s, tb, u1, l64);
+        }
+        const Unit U = wave_unit(tab, u - tb);
+        const Slots<T> cur_slots = ring[0];
+#pragma unroll
+        for (int d = 0; d + 1 < kWaveAhead; ++d) ring[d] = ring[d + 1];
+        if (u + kWaveAhead < u1) ring[kWaveAhead - 1] = load_slots<T>(s, wave_unit(tab, u + kWaveAhead - tb), 0, l64);
+        lane_update<C, T>(s, U, 0, l64, cur_slots, X, init, s_r, false);
         const int32_t passes = (U.rows + U.groups - 1) / U.groups;
         for (int32_t p = 1; p < passes; ++p)
           lane_update<C, T>(s, U, p, l64, load_slots<T>(s, U, p, l64), X, init, s_r, false);
         wave_sync<LDSX>();  // this wave's writes before its next unit's reads
-        a = b;
+      }
+      if (k + 1 < ns) {
+        st = s.steps[k + 1];
+        if (st.z != 2) {
+          const Unit Un = unit_at(s, st.x);
+          pre = load_slots<T>(s, Un, 0, tid);
+          if (st.z == 1) preD = load_dense<T, NT>(s, st.w, Un, tid);
+        }
       }
       step_barrier<LDSX>();
       if (ss && tid == 0 && k + 1 < kMaxStepStamps) ss[k + 1] = wall_clock64();
       continue;
     }
+    // level or block step: the next step's prefetch, then the arithmetic
     const Unit U = unit_at(s, cur.x);
     const bool block = cur.z == 1;
+    if (k + 1 < ns) {
+      st = s.steps[k + 1];
+      if (st.z != 2) {
+        const Unit Un = unit_at(s, st.x);
+        pre = load_slots<T>(s, Un, 0, tid);
+        if (st.z == 1) preD = load_dense<T, NT>(s, st.w, Un, tid);
+      }
+    }
     lane_update<C, T>(s, U, 0, tid, first, X, init, s_r, block);
     const int32_t passes = (U.rows + U.groups - 1) / U.groups;
     for (int32_t p = 1; p < passes; ++p)
       lane_update<C, T>(s, U, p, tid, load_slots<T>(s, U, p, tid), X, init, s_r, block);
     step_barrier<LDSX>();
     if (block) {
-      if (tid < U.rows) {
-        const T *__restrict__ Mi = sw_dense<T>(s) + cur.w;
-        T acc[C];
-#pragma unroll
-        for (int c = 0; c < C; ++c) acc[c] = T(0);
-        for (int32_t b = 0; b <= tid; ++b) {
-          const T v = Mi[tid + b * U.rows];
-#pragma unroll
-          for (int c = 0; c < C; ++c) acc[c] = fma(v, s_r[b * C + c], acc[c]);
-        }
-        const int32_t i = s.irow[U.info_base + tid] * C;
-#pragma unroll
-        for (int c = 0; c < C; ++c) X[i + c] = acc[c];
-      }
+      dense_apply<C, NT, T>(U, dense, X, s_r, tid);
       step_barrier<LDSX>();
     }
     if (ss && tid == 0 && k + 1 < kMaxStepStamps) ss[k + 1] = wall_clock64();
   }
-  __syncthreads();  // full barrier at the end of the sweep
+  asm volatile("" ::"v"(warm));  // the warming loads are complete by now
+  __syncthreads();                // full barrier at the end of the sweep
+}
+
+// X <- D^{-1} X between the two sweeps of a solve, then a barrier.
+template <int C, int NT, class T>
+__device__ __forceinline__ void pivot_scale(const T *__restrict__ d, T *__restrict__ X, int32_t n, int tid) {
+  for (int32_t i = tid; i < n; i += NT) {
+    const T v = d[i];
+#pragma unroll
+    for (int c = 0; c < C; ++c) X[i * C + c] *= v;
+  }
+  __syncthreads();
 }
 
 // SpMul: B = -P G_p W into X (rows of C directions, FP64).
@@ -467,16 +634,18 @@ __device__ __forceinline__ void reduction(const NetDesc AS4 &nd, const WorkItem 
   spmul<C, NT>(nd, a, X, dir0, tid);
   __syncthreads();
   if (st) st[1] = wall_clock64();
-  // 2. Z' = U^{-1} L^{-1} B'
+  // 2. Z' = Uh^{-1} D^{-1} L^{-1} B'
   sweep<C, NT, double, LDSX>(nd.L, X, nullptr, s_r, tid, ss);
+  pivot_scale<C, NT, double>(nd.pivinv, X, nd.n_x, tid);
   if (st) st[2] = wall_clock64();
   sweep<C, NT, double, LDSX>(nd.U, X, nullptr, s_r, tid, ss ? ss + kMaxStepStamps : nullptr);
   if (st) st[3] = wall_clock64();
   // 3. tensor projection: -Y_x into Yx, Y_p into the output
   projection<C, NT>(nd, a, X, Yx, s_slack, dir0, tid);
   if (st) st[4] = wall_clock64();
-  // 4. Psi' = L^{-T} U^{-T} (-P Y_x)
+  // 4. Psi' = L^{-T} D^{-1} Uh^{-T} (-P Y_x)
   sweep<C, NT, double, LDSX>(nd.Ut, X, Yx, s_r, tid, ss ? ss + 2 * kMaxStepStamps : nullptr);
+  pivot_scale<C, NT, double>(nd.pivinv, X, nd.n_x, tid);
   if (st) st[5] = wall_clock64();
   sweep<C, NT, double, LDSX>(nd.Lt, X, nullptr, s_r, tid, ss ? ss + 3 * kMaxStepStamps : nullptr);
   if (st) st[6] = wall_clock64();
@@ -518,6 +687,7 @@ __device__ __forceinline__ void refined_solve(const NetDesc AS4 &nd, const doubl
     }
     __syncthreads();
     sweep<C, NT, float, LDSX>(s1, X32, nullptr, s_r, tid);
+    pivot_scale<C, NT, float>(nd.pivinv32, X32, nd.n_x, tid);
     sweep<C, NT, float, LDSX>(s2, X32, nullptr, s_r, tid);
     for (int32_t i = tid; i < nd.n_x; i += NT) {
 #pragma unroll
@@ -936,34 +1106,64 @@ rh_status upload(DeviceNet &dn, const std::vector<T> &v, const T **out, std::str
     if (s_ != RH_OK) return s_;                                 \
   } while (0)
 
+// Arrays appended to one host staging buffer at 256-byte aligned offsets and
+// uploaded as one allocation.
+struct Blob {
+  std::vector<char> h;
+  template <class T>
+  int64_t add(const std::vector<T> &v) {
+    if (v.empty()) return -1;
+    const size_t off = (h.size() + 255) & ~size_t(255);
+    h.resize(off + v.size() * sizeof(T));
+    std::memcpy(h.data() + off, v.data(), v.size() * sizeof(T));
+    return (int64_t)off;
+  }
+  size_t mark() const { return (h.size() + 255) & ~size_t(255); }
+};
+
+template <class T>
+const T *at_off(const char *base, int64_t off) {
+  return off < 0 ? nullptr : reinterpret_cast<const T *>(base + off);
+}
+
+// One sweep in one allocation: the layout and entry columns first (read in
+// both precisions), then the FP64 values and block inverses, then their FP32
+// copies, so that each precision's working set is two contiguous ranges.
 rh_status upload_sweep(DeviceNet *dn, const Sweep &s, int32_t n, const std::vector<int32_t> &parent,
                        bool forward, const ScheduleParams &prm, DevSweep &o, std::string &err) {
   const Schedule sc = build_schedule(s, n, parent, forward, prm);
   const Packed pk = pack_schedule(sc, kThreads);
+  if (!pk.idinv.empty()) {
+    err = "internal: device sweeps must have a unit diagonal";
+    return RH_EDEVICE;
+  }
+  Blob bl;
+  const int64_t o_steps = bl.add(pk.steps), o_units = bl.add(pk.units), o_wdir = bl.add(pk.wdir);
+  const int64_t o_scol = bl.add(pk.scol), o_irow = bl.add(pk.irow);
+  const size_t m1 = bl.mark();
+  const int64_t o_sval = bl.add(pk.sval), o_dense = bl.add(pk.dense);
+  const size_t m2 = bl.mark();
+  const int64_t o_sval32 = bl.add(std::vector<float>(pk.sval.begin(), pk.sval.end()));
+  const int64_t o_dense32 = bl.add(std::vector<float>(pk.dense.begin(), pk.dense.end()));
+  const size_t m3 = bl.h.size();
+  const char *base = nullptr;
+  UP(bl.h, base);
   o.n_steps = (int32_t)(pk.steps.size() / 4);
-  const int32_t *p = nullptr;
-  UP(pk.steps, p);
-  o.steps = reinterpret_cast<const int4 *>(p);
-  UP(pk.units, p);
-  o.units = reinterpret_cast<const int4 *>(p);
-  o.wdir = nullptr;
-  if (!pk.wdir.empty()) UP(pk.wdir, o.wdir);
-  UP(pk.scol, o.scol);
-  UP(pk.irow, o.irow);
-  UP(pk.sval, o.sval);
-  o.idinv = nullptr;
-  if (!pk.idinv.empty()) UP(pk.idinv, o.idinv);
-  o.dense = nullptr;
-  if (!pk.dense.empty()) UP(pk.dense, o.dense);
-  // FP32 copies for the refined mode
-  const std::vector<float> v32(pk.sval.begin(), pk.sval.end());
-  const std::vector<float> d32(pk.idinv.begin(), pk.idinv.end());
-  const std::vector<float> m32(pk.dense.begin(), pk.dense.end());
-  UP(v32, o.sval32);
-  o.idinv32 = nullptr;
-  if (!d32.empty()) UP(d32, o.idinv32);
-  o.dense32 = nullptr;
-  if (!m32.empty()) UP(m32, o.dense32);
+  o.steps = at_off<int4>(base, o_steps);
+  o.units = at_off<int4>(base, o_units);
+  o.wdir = at_off<int32_t>(base, o_wdir);
+  o.scol = at_off<int32_t>(base, o_scol);
+  o.irow = at_off<int32_t>(base, o_irow);
+  o.sval = at_off<double>(base, o_sval);
+  o.dense = at_off<double>(base, o_dense);
+  o.sval32 = at_off<float>(base, o_sval32);
+  o.dense32 = at_off<float>(base, o_dense32);
+  o.warm_common = base;
+  o.warm_common_bytes = (int64_t)m1;
+  o.warm64 = base + m1;
+  o.warm64_bytes = (int64_t)(m2 - m1);
+  o.warm32 = base + m2;
+  o.warm32_bytes = (int64_t)(m3 - m2);
   dn->sweep_steps.push_back(o.n_steps);
   return RH_OK;
 }
@@ -1045,7 +1245,13 @@ rh_status device_upload(Network &net, std::string &err) {
   nd.n_bus = net.n_bus;
 
   Sweep sl, su, sut, slt;
-  lu_sweeps(lu, sl, su, sut, slt);
+  std::vector<double> pivinv;
+  lu_sweeps(lu, sl, su, sut, slt, pivinv);
+  UP(pivinv, nd.pivinv);
+  {
+    const std::vector<float> p32(pivinv.begin(), pivinv.end());
+    UP(p32, nd.pivinv32);
+  }
   ScheduleParams prm;
   prm.bmax = kBlockRows;
   prm.block_rows = kBlockRows;

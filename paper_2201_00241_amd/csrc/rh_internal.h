@@ -64,7 +64,9 @@ struct Schedule {
 // j of a group holds entries j, j + 2^lg, ... of its row, `E` slots per lane
 // and pass, padded with (column 0, value 0).  Slot (pass, e, lane) sits at
 // slot_base + (pass * E + e) * lanes + lane, so a lane needs no row pointer.
-// units: 8 ints each {slot_base, info_base, rows, groups, lg, E, lanes, 0};
+// units: 8 ints each {slot_base, info_base, rows, groups, lg, E, lanes,
+// compact}; for wave-step units compact = rows | lg << 16 | E << 19 (their
+// groups = min(rows, 64 >> lg)), else -1.
 // irow/idinv give each row's matrix row and reciprocal pivot (unit order).
 // steps: 4 ints each {unit or wave directory offset, 0, kind, dense offset},
 // kind 0 = level, 1 = block (dense inverse at the offset), 2 = wave step
@@ -151,7 +153,10 @@ void lu_analyse(LuPlan &lu, const Csr &pattern);
 bool lu_factor(LuPlan &lu, const Csr &a, std::string &err);
 void lu_solve(const LuPlan &lu, std::vector<double> &b);        // A x = b in place
 void lu_solve_t(const LuPlan &lu, std::vector<double> &b);      // A^T x = b in place
-void lu_sweeps(const LuPlan &lu, Sweep &sl, Sweep &su, Sweep &sut, Sweep &slt);
+// The four unit-diagonal sweeps of the two solves with A = P^T L D Uh P:
+// A^{-1} b = P^T Uh^{-1} D^{-1} L^{-1} P b and A^{-T} b = P^T L^{-T} D^{-1}
+// Uh^{-T} P b; pivinv = D^{-1} (reciprocal pivots, factor numbering).
+void lu_sweeps(const LuPlan &lu, Sweep &sl, Sweep &su, Sweep &sut, Sweep &slt, std::vector<double> &pivinv);
 int lane_log2(int32_t rows, int32_t longest, int lane_budget);
 Schedule build_schedule(const Sweep &in, int32_t n, const std::vector<int32_t> &parent, bool forward,
                         const ScheduleParams &prm);

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <queue>
+#include <stdexcept>
 
 #include "rh_internal.h"
 
@@ -225,17 +226,25 @@ void make_sweep(Sweep &s, int32_t n, const std::vector<int32_t> &level, int32_t 
 
 }  // namespace
 
-void lu_sweeps(const LuPlan &lu, Sweep &sl, Sweep &su, Sweep &sut, Sweep &slt) {
+void lu_sweeps(const LuPlan &lu, Sweep &sl, Sweep &su, Sweep &sut, Sweep &slt, std::vector<double> &pivinv) {
   const int32_t n = lu.n;
-  std::vector<double> d(n);
-  for (int32_t i = 0; i < n; ++i) d[i] = lu.uval[i][0];
+  // U = D Uh with Uh unit upper triangular: U^{-1} = Uh^{-1} D^{-1} and
+  // U^{-T} = D^{-1} Uh^{-T}, so every sweep has a unit diagonal and each solve
+  // scales by D^{-1} between its two sweeps.
+  pivinv.assign(n, 0.0);
+  std::vector<std::vector<double>> uh(n);
+  for (int32_t k = 0; k < n; ++k) {
+    pivinv[k] = 1.0 / lu.uval[k][0];
+    uh[k].resize(lu.uval[k].size());
+    for (size_t q = 1; q < lu.uval[k].size(); ++q) uh[k][q] = lu.uval[k][q] / lu.uval[k][0];
+  }
   // rows of U^T and L^T (the pattern is symmetric: U^T row i = L row i's columns)
   std::vector<std::vector<int32_t>> utc(n), ltc(n);
   std::vector<std::vector<double>> utv(n), ltv(n);
   for (int32_t k = 0; k < n; ++k)
     for (size_t q = 1; q < lu.urow[k].size(); ++q) {
       utc[lu.urow[k][q]].push_back(k);
-      utv[lu.urow[k][q]].push_back(lu.uval[k][q]);
+      utv[lu.urow[k][q]].push_back(uh[k][q]);
     }
   for (int32_t j = 0; j < n; ++j)
     for (size_t q = 0; q < lu.lrow[j].size(); ++q) {
@@ -251,15 +260,15 @@ void lu_sweeps(const LuPlan &lu, Sweep &sl, Sweep &su, Sweep &sut, Sweep &slt) {
   make_sweep(su, n, lu.level_u, lu.n_levels_u,
              [&](int32_t i, std::vector<int32_t> &c, std::vector<double> &v) {
                c.insert(c.end(), lu.urow[i].begin() + 1, lu.urow[i].end());
-               v.insert(v.end(), lu.uval[i].begin() + 1, lu.uval[i].end());
+               v.insert(v.end(), uh[i].begin() + 1, uh[i].end());
              },
-             &d);
+             nullptr);
   make_sweep(sut, n, lu.level_l, lu.n_levels_l,
              [&](int32_t i, std::vector<int32_t> &c, std::vector<double> &v) {
                c.insert(c.end(), utc[i].begin(), utc[i].end());
                v.insert(v.end(), utv[i].begin(), utv[i].end());
              },
-             &d);
+             nullptr);
   make_sweep(slt, n, lu.level_u, lu.n_levels_u,
              [&](int32_t i, std::vector<int32_t> &c, std::vector<double> &v) {
                c.insert(c.end(), ltc[i].begin(), ltc[i].end());
@@ -580,7 +589,9 @@ int32_t pack_unit(const Schedule &sc, int32_t b, int32_t rows, int lg, int max_l
     if (!s.dinv.empty()) pk.idinv.push_back(s.dinv[pos]);
   }
   const int32_t u = (int32_t)(pk.units.size() / 8);
-  pk.units.insert(pk.units.end(), {slot_base, info_base, rows, groups, lg, E, lanes, 0});
+  // compact form for the per-lane unit tables of wave steps (64 lanes)
+  const int32_t compact = (max_lanes == 64 && rows < (1 << 16) && E < (1 << 13)) ? (rows | lg << 16 | E << 19) : -1;
+  pk.units.insert(pk.units.end(), {slot_base, info_base, rows, groups, lg, E, lanes, compact});
   return u;
 }
 
@@ -600,7 +611,8 @@ Packed pack_schedule(const Schedule &sc, int lanes) {
       for (int32_t w = 0; w < nw; ++w) {
         pk.wdir.push_back((int32_t)(pk.units.size() / 8));
         for (int32_t j = sc.wdir[d + w]; j < sc.wdir[d + w + 1]; ++j)
-          pack_unit(sc, sc.wlev[4 * j], sc.wlev[4 * j + 1], sc.wlev[4 * j + 2], 64, pk);
+          if (pk.units[8 * pack_unit(sc, sc.wlev[4 * j], sc.wlev[4 * j + 1], sc.wlev[4 * j + 2], 64, pk) + 7] < 0)
+            throw std::runtime_error("wave level too large for the compact unit form");
       }
       pk.wdir.push_back((int32_t)(pk.units.size() / 8));
       pk.steps.insert(pk.steps.end(), {off, 0, 2, 0});

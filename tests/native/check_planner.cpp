@@ -242,7 +242,8 @@ int main(int argc, char **argv) {
     }
   }
   Sweep sw[4];
-  lu_sweeps(net.lu, sw[0], sw[1], sw[2], sw[3]);
+  std::vector<double> pivinv;
+  lu_sweeps(net.lu, sw[0], sw[1], sw[2], sw[3], pivinv);
   const char *nm[4] = {"L", "U", "Ut", "Lt"};
   const bool fwd[4] = {true, false, true, false};
   const std::vector<int32_t> parent = etree_parent(net.lu);
@@ -295,6 +296,7 @@ int main(int argc, char **argv) {
     ScheduleParams prm;
     bool ok = true;
     emulate(build_schedule(sw[0], nx, parent, true, prm), X, ok);
+    for (int i = 0; i < nx; ++i) X[i] *= pivinv[i];
     emulate(build_schedule(sw[1], nx, parent, false, prm), X, ok);
     std::vector<double> sol(nx);
     for (int i = 0; i < nx; ++i) sol[i] = X[net.lu.iperm[i]];
@@ -303,6 +305,7 @@ int main(int argc, char **argv) {
     lu_solve_t(net.lu, ref);
     for (int i = 0; i < nx; ++i) X[net.lu.iperm[i]] = bb[i];
     emulate(build_schedule(sw[2], nx, parent, true, prm), X, ok);
+    for (int i = 0; i < nx; ++i) X[i] *= pivinv[i];
     emulate(build_schedule(sw[3], nx, parent, false, prm), X, ok);
     if (!ok) printf("order_violations_composed 1\n");
     for (int i = 0; i < nx; ++i) sol[i] = X[net.lu.iperm[i]];
