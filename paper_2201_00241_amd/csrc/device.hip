@@ -63,9 +63,10 @@ constexpr int kBlockRows = 64;  // rows of a merged block of narrow levels (one 
 struct DevSweep {
   int32_t n_steps;
   const int4 *steps;  // {unit or wave directory offset, 0, kind, dense offset}
-  const int4 *units;  // 2 x int4: {slot_base, info_base, rows, groups}, {lg, E, lanes, 0}
+  const int4 *units;  // 2 x int4: {slot_base, info_base, rows, groups}, {lg, E, lanes, compact}
   const int32_t *wdir;
   const int32_t *scol, *irow;
+  int32_t n_slots, n_irow;  // lengths of the slot and row arrays
   const double *sval, *dense;   // unit diagonal (pivots are applied between sweeps)
   const float *sval32, *dense32;  // FP32 copies (refined mode)
   // the sweep's arrays as byte ranges of one allocation: read in both
@@ -132,10 +133,12 @@ struct LaunchArgs {
   double *scratch;
   int64_t scratch_stride;  // doubles per workgroup
   long long *stamps;       // kStamps wall-clock stamps per workgroup, or nullptr
-  long long *step_stamps;  // debug: workgroup 0 stamps every sweep step (4 x kMaxStepStamps)
+  long long *step_stamps;  // debug: workgroup 0 stamps sweep steps and wave units (4 x kSweepStamps)
 };
 
 constexpr int kMaxStepStamps = 128;
+constexpr int kUnitStamps = 64;  // per wave: the end of its first 64 units
+constexpr int kSweepStamps = kMaxStepStamps + kWaves * kUnitStamps;
 
 constexpr int kStamps = 8;
 
@@ -162,40 +165,65 @@ __device__ __forceinline__ WorkItem item_of(const LaunchArgs &la, int32_t chunk)
 // A unit of a sweep (see DevSweep): its slot layout.
 struct Unit {
   int32_t slot_base, info_base, rows, groups, lg, E, lanes;
+  bool assign;  // x_i = sum (second half of a wave block) instead of x_i - sum
 };
 
 __device__ __forceinline__ Unit unit_at(const DevSweep AS4 &s, int32_t u) {
   const int4 a = s.units[2 * u], b = s.units[2 * u + 1];
-  return Unit{a.x, a.y, a.z, a.w, b.x, b.y, b.z};
+  return Unit{a.x, a.y, a.z, a.w, b.x, b.y, b.z, false};
 }
 
-// Per-lane table of a wave's unit descriptors: lane i holds the slot base,
-// row-info base and compact word of unit tb + i (compact = rows | lg << 16 |
-// E << 19; groups = min(rows, 64 >> lg)).
-constexpr int kWaveAhead = 2;  // units whose slots a wave has in flight
-struct WaveTable {
-  int32_t slot_base, info_base, compact;
+// A wave's units in a wave step, read without memory round trips per unit:
+// lane i of cw[q] holds the compact word of unit u0 + 64 q + i (compact =
+// rows | lg << 15 | assign << 18 | E << 19; groups = min(rows, 64 >> lg)),
+// loaded once when the wave step starts; the slot base and row-info base are
+// running sums, since a wave's units are packed one after the other.  Units
+// beyond 64 kTableWords read their compact word from memory.
+constexpr int kWaveAhead = 2;   // units whose slots a wave has in flight
+constexpr int kTableWords = 4;  // per-lane table registers (256 units)
+
+struct WaveWalk {
+  int32_t cw[kTableWords];
+  int32_t u0;
 };
 
-__device__ __forceinline__ WaveTable wave_table(const DevSweep AS4 &s, int32_t tb, int32_t u1, int l64) {
-  WaveTable t{0, 0, 0};
-  if (tb + l64 < u1) {
-    const int32_t *e = reinterpret_cast<const int32_t *>(s.units) + 8 * (int64_t)(tb + l64);
-    t.slot_base = e[0];
-    t.info_base = e[1];
-    t.compact = e[7];
+__device__ __forceinline__ WaveWalk wave_walk(const DevSweep AS4 &s, int32_t u0, int32_t u1, int l64) {
+  WaveWalk w;
+  w.u0 = u0;
+  const int32_t *units = reinterpret_cast<const int32_t *>(s.units);
+#pragma unroll
+  for (int q = 0; q < kTableWords; ++q) {
+    const int32_t u = u0 + 64 * q + l64;
+    w.cw[q] = u < u1 ? units[8 * (int64_t)u + 7] : 0;
   }
-  return t;
+  // consume the table here, so that no later wait covers these loads
+  int32_t any = 0;
+#pragma unroll
+  for (int q = 0; q < kTableWords; ++q) any |= __builtin_amdgcn_readfirstlane(w.cw[q]);
+  asm volatile("" ::"s"(any));
+  return w;
 }
 
-__device__ __forceinline__ Unit wave_unit(const WaveTable &t, int32_t i) {
-  const int32_t sb = __builtin_amdgcn_readlane(t.slot_base, i);
-  const int32_t ib = __builtin_amdgcn_readlane(t.info_base, i);
-  const int32_t cw = __builtin_amdgcn_readlane(t.compact, i);
-  const int32_t rows = cw & 0xFFFF, lg = (cw >> 16) & 7, E = (int32_t)((uint32_t)cw >> 19);
-  const int32_t groups = max(1, min(rows, 64 >> lg));
-  return Unit{sb, ib, rows, groups, lg, E, groups << lg};
+__device__ __forceinline__ int32_t walk_word(const DevSweep AS4 &s, const WaveWalk &w, int32_t u) {
+  const int32_t i = u - w.u0;
+  if (i < 64 * kTableWords) {
+    const int32_t q = i >> 6, l = i & 63;
+    int32_t v = __builtin_amdgcn_readlane(w.cw[0], l);
+#pragma unroll
+    for (int qq = 1; qq < kTableWords; ++qq)
+      if (q == qq) v = __builtin_amdgcn_readlane(w.cw[qq], l);
+    return v;
+  }
+  return ((const int32_t AS4 *)s.units)[8 * (int64_t)u + 7];  // scalar load
 }
+
+// The unit with compact word cw at (slot_base, info_base).
+__device__ __forceinline__ Unit unit_of(int32_t cw, int32_t sb, int32_t ib) {
+  const int32_t rows = cw & 0x7FFF, lg = (cw >> 15) & 7, E = (int32_t)((uint32_t)cw >> 19);
+  const int32_t groups = min(rows, 64 >> lg);  // an empty unit (cw = 0) has no lanes
+  return Unit{sb, ib, rows, groups, lg, E, groups << lg, ((cw >> 18) & 1) != 0};
+}
+
 
 // The first kPre entry slots of one lane in one pass of a unit, with its
 // row's matrix row.  None of it depends on the solution
@@ -211,6 +239,10 @@ struct Slots {
 
 template <class T>
 __device__ __forceinline__ Slots<T> load_slots(const DevSweep AS4 &s, const Unit &U, int32_t pass, int lane) {
+  // Every lane issues the same loads, lanes without an entry from the zero
+  // slot 0, so the number of loads in flight is the same on every path and
+  // no loaded value is used before the unit needs it.  The row of a lane
+  // without one is never written.
   Slots<T> L;
   const T *val = sw_val<T>(s);
   const int32_t r = pass * U.groups + (lane >> U.lg);
@@ -218,11 +250,11 @@ __device__ __forceinline__ Slots<T> load_slots(const DevSweep AS4 &s, const Unit
 #pragma unroll
   for (int e = 0; e < kPre; ++e) {
     const bool ok = act && e < U.E;
-    const int64_t at = (int64_t)U.slot_base + ((int64_t)pass * U.E + e) * U.lanes + lane;
-    L.col[e] = ok ? s.scol[at] : 0;
-    L.val[e] = ok ? val[at] : T(0);
+    const int64_t at = ok ? (int64_t)U.slot_base + ((int64_t)pass * U.E + e) * U.lanes + lane : 0;
+    L.col[e] = s.scol[at];
+    L.val[e] = val[at];
   }
-  L.row = act ? s.irow[U.info_base + r] : 0;
+  L.row = s.irow[act ? U.info_base + r : 0];
   return L;
 }
 
@@ -246,14 +278,15 @@ template <class T, int NT>
 __device__ __forceinline__ DenseRow<T, NT> load_dense(const DevSweep AS4 &s, int32_t off, const Unit &U, int tid) {
   using D = DenseShape<NT>;
   DenseRow<T, NT> R;
-  const T *Mi = sw_dense<T>(s) + off;
+  const T *Dz = sw_dense<T>(s);  // Dz[0] is a zero
   const int32_t a = tid / D::lanes, j = tid % D::lanes;
 #pragma unroll
   for (int e = 0; e < D::E; ++e) {
     const int32_t b = j + e * D::lanes;
-    R.m[e] = (a < U.rows && b <= a) ? Mi[a + b * U.rows] : T(0);
+    const bool ok = a < U.rows && b <= a;
+    R.m[e] = Dz[ok ? off + a + b * U.rows : 0];
   }
-  R.row = (j == 0 && a < U.rows) ? s.irow[U.info_base + a] : 0;
+  R.row = s.irow[a < U.rows ? U.info_base + a : 0];  // written only by j == 0, a < rows
   return R;
 }
 
@@ -312,56 +345,79 @@ __device__ __forceinline__ T group_sum(T v, int lg) {
   return v;
 }
 
-// One lane's share of one pass of a unit: partial dot product of its slots
-// with X (the prefetched ones, then any further ones), sum over the lane
-// group, and the group's first lane writes the row (or, in a block, its
-// residual into s_r).  Padding slots are (0, 0).
+// One lane's share of one pass of a unit, in two halves so that a caller can
+// reuse the slot registers in between: lane_dot forms the partial dot product
+// of the lane's slots with X (the X values of the prefetched slots gathered
+// first, then any further slots), lane_finish sums over the lane group and
+// the group's first lane writes the row (or, in a block, its residual into
+// s_r; in an assigning unit, the sum itself).  Padding slots are (0, 0).  An
+// assigning unit has one pass, so all its lanes read X before any lane of the
+// wave writes.  Every lane of the wave takes part (the group sum needs them).
 template <int C, class T>
-__device__ __forceinline__ void lane_update(const DevSweep AS4 &s, const Unit &U, int32_t pass, int lane,
-                                            const Slots<T> &L, T *__restrict__ X, const T *__restrict__ init,
-                                            T *__restrict__ s_r, bool block) {
-  const int width = 1 << U.lg;
-  const int32_t r = pass * U.groups + (lane >> U.lg);
-  if (lane >= U.lanes || r >= U.rows) return;  // whole lane groups only
+struct Part {
+  T v[C];
+};
+
+template <int C, class T>
+__device__ __forceinline__ Part<C, T> lane_dot(const DevSweep AS4 &s, const Unit &U, int32_t pass, int lane,
+                                               const Slots<T> &L, const T *__restrict__ X) {
   const T *val = sw_val<T>(s);
-  T part[C];
+  Part<C, T> P;
+  T xv[kPre][C];
 #pragma unroll
-  for (int c = 0; c < C; ++c) part[c] = T(0);
+  for (int e = 0; e < kPre; ++e)
 #pragma unroll
-  for (int e = 0; e < kPre; ++e) {
-    const int32_t j = L.col[e] * C;
+    for (int c = 0; c < C; ++c) xv[e][c] = X[L.col[e] * C + c];
 #pragma unroll
-    for (int c = 0; c < C; ++c) part[c] = fma(L.val[e], X[j + c], part[c]);
-  }
+  for (int c = 0; c < C; ++c) P.v[c] = T(0);
+#pragma unroll
+  for (int e = 0; e < kPre; ++e)
+#pragma unroll
+    for (int c = 0; c < C; ++c) P.v[c] = fma(L.val[e], xv[e][c], P.v[c]);
   // remaining slots, four at a time so their loads are in flight together
+  const bool act = lane < U.lanes && pass * U.groups + (lane >> U.lg) < U.rows;
   for (int32_t e0 = kPre; e0 < U.E; e0 += 4) {
     int32_t jj[4];
     T vv[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const bool ok = e0 + e < U.E;
-      const int64_t at = (int64_t)U.slot_base + ((int64_t)pass * U.E + (ok ? e0 + e : e0)) * U.lanes + lane;
-      vv[e] = ok ? val[at] : T(0);
-      jj[e] = ok ? s.scol[at] * C : 0;
+      const bool ok = act && e0 + e < U.E;
+      const int64_t at = ok ? (int64_t)U.slot_base + ((int64_t)pass * U.E + e0 + e) * U.lanes + lane : 0;
+      vv[e] = val[at];
+      jj[e] = s.scol[at] * C;
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < 4; ++e)
 #pragma unroll
-      for (int c = 0; c < C; ++c) part[c] = fma(vv[e], X[jj[e] + c], part[c]);
-    }
+      for (int c = 0; c < C; ++c) P.v[c] = fma(vv[e], X[jj[e] + c], P.v[c]);
   }
+  return P;
+}
+
+template <int C, class T>
+__device__ __forceinline__ void lane_finish(const Unit &U, int32_t pass, int lane, int32_t row, Part<C, T> P,
+                                            T *__restrict__ X, T *__restrict__ s_r,
+                                            bool block) {
 #pragma unroll
-  for (int c = 0; c < C; ++c) part[c] = group_sum(part[c], U.lg);
-  if ((lane & (width - 1)) == 0) {
-    const int32_t i = L.row * C;
+  for (int c = 0; c < C; ++c) P.v[c] = group_sum(P.v[c], U.lg);
+  const int32_t r = pass * U.groups + (lane >> U.lg);
+  if (lane < U.lanes && r < U.rows && (lane & ((1 << U.lg) - 1)) == 0) {
+    const int32_t i = row * C;
     if (block) {
 #pragma unroll
-      for (int c = 0; c < C; ++c) s_r[r * C + c] = (init ? init[i + c] : X[i + c]) - part[c];
+      for (int c = 0; c < C; ++c) s_r[r * C + c] = X[i + c] - P.v[c];
     } else {
 #pragma unroll
-      for (int c = 0; c < C; ++c) X[i + c] = (init ? init[i + c] : X[i + c]) - part[c];
+      for (int c = 0; c < C; ++c) X[i + c] = U.assign ? P.v[c] : X[i + c] - P.v[c];
     }
   }
+}
+
+template <int C, class T>
+__device__ __forceinline__ void lane_update(const DevSweep AS4 &s, const Unit &U, int32_t pass, int lane,
+                                            const Slots<T> &L, T *__restrict__ X,
+                                            T *__restrict__ s_r, bool block) {
+  lane_finish<C, T>(U, pass, lane, L.row, lane_dot<C, T>(s, U, pass, lane, L, X), X, s_r, block);
 }
 
 // Bring a sweep's arrays into the L2 of this workgroup's XCD before its
@@ -414,6 +470,161 @@ __device__ __forceinline__ void wave_sync() {
   }
 }
 
+// One wave's walk through its units of a wave step.  Every wave unit has one
+// pass and at least kPre slots per lane (kPre exactly, except for rows longer
+// than 64 kPre entries), its lanes are rows << lg, and the slot and row arrays
+// end with a zero tail, so each lane loads its kPre slots and its row index
+// from a uniform base plus its lane offset, with no per-lane bounds tests:
+// lanes past the unit's rows read the next unit's data (or the tail) and form
+// whole lane groups whose sums are never written.  Units are loaded
+// kWaveAhead ahead into rotating buffers (the loop is unrolled over them, so no
+// buffer with loads in flight is copied), and the loads are issued on every
+// iteration (past the end, from the tail) so that the number in flight is the
+// same on every path.
+constexpr int kWavePre = kSlotsAhead;  // slots per lane of a wave unit
+
+template <class T>
+struct WSlots {
+  int32_t col[kWavePre];
+  T val[kWavePre];
+  int32_t row;
+};
+
+// Buffer resources of a sweep's slot and row arrays: loads take a uniform
+// byte offset in a scalar register and the lane's offset in a vector
+// register, so a unit's loads need no per-lane address arithmetic (and reads
+// past the end return 0).
+struct WaveBufs {
+  __amdgpu_buffer_rsrc_t col, val, row;
+};
+
+constexpr int kBufWord3 = 0x00020000;  // raw (untyped) buffer access on gfx9-family targets
+
+template <class T>
+__device__ __forceinline__ WaveBufs wave_bufs(const DevSweep AS4 &s) {
+  WaveBufs b;
+  b.col = __builtin_amdgcn_make_buffer_rsrc((void *)s.scol, 0, s.n_slots * 4, kBufWord3);
+  b.val = __builtin_amdgcn_make_buffer_rsrc((void *)sw_val<T>(s), 0, s.n_slots * (int)sizeof(T), kBufWord3);
+  b.row = __builtin_amdgcn_make_buffer_rsrc((void *)s.irow, 0, s.n_irow * 4, kBufWord3);
+  return b;
+}
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+template <class T>
+__device__ __forceinline__ T buf_load_val(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <>
+__device__ __forceinline__ double buf_load_val<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ float buf_load_val<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+// Lanes past the unit's rows use a lane offset beyond every buffer's range:
+// their loads return 0 (column 0, value 0) without touching memory, so their
+// gathers all hit one LDS word.
+constexpr int kOffRange = 0x40000000;
+
+template <class T>
+__device__ __forceinline__ WSlots<T> wave_load(const WaveBufs &B, int32_t sb, int32_t ib, int32_t lanes, int32_t lg,
+                                               int l64) {
+  WSlots<T> L;
+  const bool act = l64 < lanes;
+  const int vc = act ? l64 * 4 : kOffRange;
+  const int vv = act ? l64 * (int)sizeof(T) : kOffRange;
+  const int vr = act ? (l64 >> lg) * 4 : kOffRange;
+#pragma unroll
+  for (int e = 0; e < kWavePre; ++e) {
+    // uniform offsets: say so, or the compiler may keep them in vector
+    // registers and loop over their distinct values
+    const int32_t at = __builtin_amdgcn_readfirstlane(sb + e * lanes);
+    L.col[e] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(B.col, vc, at * 4, 0);
+    L.val[e] = buf_load_val<T>(B.val, vv, at * (int)sizeof(T));
+  }
+  L.row = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(B.row, vr, __builtin_amdgcn_readfirstlane(ib) * 4, 0);
+  return L;
+}
+
+template <int C, class T, bool LDSX>
+__device__ __forceinline__ void wave_walk_units(const DevSweep AS4 &s, int32_t u0, int32_t u1, int wv, int l64,
+                                                T *__restrict__ X, long long *ss) {
+  const WaveWalk walk = wave_walk(s, u0, u1, l64);
+  const WaveBufs B = wave_bufs<T>(s);
+  int32_t sb_cur = 0, ib_cur = 0;  // bases of unit u
+  if (u0 < u1) {
+    const int32_t AS4 *h = (const int32_t AS4 *)s.units + 8 * (int64_t)u0;
+    sb_cur = h[0];
+    ib_cur = h[1];
+  }
+  int32_t sb_pre = sb_cur, ib_pre = ib_cur;  // bases of the next unit to load
+  WSlots<T> ring[kWaveAhead];
+#pragma unroll
+  for (int d = 0; d < kWaveAhead; ++d) {
+    const Unit Up = unit_of(u0 + d < u1 ? walk_word(s, walk, u0 + d) : 0, sb_pre, ib_pre);
+    ring[d] = wave_load<T>(B, sb_pre, ib_pre, Up.lanes, Up.lg, l64);
+    sb_pre += Up.E * Up.lanes;  // wave units have one pass
+    ib_pre += Up.rows;
+  }
+  const T *val = sw_val<T>(s);
+  // every unrolled step runs (a step past the end is an empty unit), so the
+  // same loads are in flight on every path through the loop
+  for (int32_t u = u0; u < u1; u += kWaveAhead) {
+#pragma unroll
+    for (int d = 0; d < kWaveAhead; ++d) {
+      const int32_t uu = u + d;
+      const Unit U = unit_of(uu < u1 ? walk_word(s, walk, uu) : 0, sb_cur, ib_cur);
+      const WSlots<T> &L = ring[d];
+      // gathers: the kWavePre entries and the row's own value
+      T xv[kWavePre][C], xr[C];
+#pragma unroll
+      for (int e = 0; e < kWavePre; ++e)
+#pragma unroll
+        for (int c = 0; c < C; ++c) xv[e][c] = X[L.col[e] * C + c];
+      const int32_t row = L.row;
+#pragma unroll
+      for (int c = 0; c < C; ++c) xr[c] = X[row * C + c];
+      T part[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) part[c] = T(0);
+#pragma unroll
+      for (int e = 0; e < kWavePre; ++e)
+#pragma unroll
+        for (int c = 0; c < C; ++c) part[c] = fma(L.val[e], xv[e][c], part[c]);
+      {
+        const Unit Up = unit_of(uu + kWaveAhead < u1 ? walk_word(s, walk, uu + kWaveAhead) : 0, sb_pre, ib_pre);
+        ring[d] = wave_load<T>(B, sb_pre, ib_pre, Up.lanes, Up.lg, l64);
+        sb_pre += Up.E * Up.lanes;
+        ib_pre += Up.rows;
+      }
+      // rows longer than 64 kWavePre entries (rare): the remaining slots
+      for (int32_t e0 = kWavePre; e0 < U.E; e0 += 4) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const bool ok = e0 + e < U.E;
+          const int64_t at = (int64_t)U.slot_base + (int64_t)(ok ? e0 + e : 0) * U.lanes + l64;
+          const T v = val[at];
+          const int32_t j = s.scol[at];
+#pragma unroll
+          for (int c = 0; c < C; ++c) part[c] = fma(ok ? v : T(0), X[j * C + c], part[c]);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < C; ++c) part[c] = group_sum(part[c], U.lg);
+      if ((l64 & ((1 << U.lg) - 1)) == 0 && l64 < U.lanes) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) X[row * C + c] = U.assign ? part[c] : xr[c] - part[c];
+      }
+      wave_sync<LDSX>();  // this wave's writes before its next unit's reads
+      if (ss && l64 == 0 && uu < u1 && uu - u0 < kUnitStamps)
+        ss[kMaxStepStamps + wv * kUnitStamps + (uu - u0)] = wall_clock64();
+      sb_cur += U.E * U.lanes;
+      ib_cur += U.rows;
+    }
+  }
+}
+
 // Level-scheduled triangular sweep on X (rows of C directions).
 //
 // Steps: a plain level (independent rows); a block of consecutive narrow
@@ -423,7 +634,7 @@ __device__ __forceinline__ void wave_sync() {
 // its own elimination subtrees level by level with wave-local ordering only.
 // A workgroup barrier separates steps.
 template <int C, int NT, class T, bool LDSX>
-__device__ __forceinline__ void sweep(const DevSweep AS4 &s, T *__restrict__ X, const T *__restrict__ init,
+__device__ __forceinline__ void sweep(const DevSweep AS4 &s, T *__restrict__ X,
                                       T *__restrict__ s_r, int tid, long long *ss = nullptr) {
   const int32_t ns = s.n_steps;
   if (ns == 0) return;
@@ -449,30 +660,11 @@ __device__ __forceinline__ void sweep(const DevSweep AS4 &s, T *__restrict__ X, 
       // readlane, no scalar memory round trip per unit) and loads each
       // unit's slots kWaveAhead units ahead; the next step's prefetch is
       // issued once the wave is done.
-      const int wv = tid >> 6, l64 = tid & 63;
+      // the wave index is uniform in a wave: tell the compiler, so that the
+      // walk's control flow and descriptors stay scalar
+      const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), l64 = tid & 63;
       const int32_t u0 = s.wdir[cur.x + wv], u1 = s.wdir[cur.x + wv + 1];
-      int32_t tb = u0;
-      WaveTable tab = wave_table(s, tb, u1, l64);
-      Slots<T> ring[kWaveAhead];
-#pragma unroll
-      for (int d = 0; d < kWaveAhead; ++d)
-        if (u0 + d < u1) ring[d] = load_slots<T>(s, wave_unit(tab, d), 0, l64);
-      for (int32_t u = u0; u < u1; ++u) {
-        if (u + kWaveAhead >= tb + 64) {  // uniform: refill the table from u
-          tb = u;
-          tab = wave_table(s, tb, u1, l64);
-        }
-        const Unit U = wave_unit(tab, u - tb);
-        const Slots<T> cur_slots = ring[0];
-#pragma unroll
-        for (int d = 0; d + 1 < kWaveAhead; ++d) ring[d] = ring[d + 1];
-        if (u + kWaveAhead < u1) ring[kWaveAhead - 1] = load_slots<T>(s, wave_unit(tab, u + kWaveAhead - tb), 0, l64);
-        lane_update<C, T>(s, U, 0, l64, cur_slots, X, init, s_r, false);
-        const int32_t passes = (U.rows + U.groups - 1) / U.groups;
-        for (int32_t p = 1; p < passes; ++p)
-          lane_update<C, T>(s, U, p, l64, load_slots<T>(s, U, p, l64), X, init, s_r, false);
-        wave_sync<LDSX>();  // this wave's writes before its next unit's reads
-      }
+      wave_walk_units<C, T, LDSX>(s, u0, u1, wv, l64, X, ss);
       if (k + 1 < ns) {
         st = s.steps[k + 1];
         if (st.z != 2) {
@@ -496,10 +688,10 @@ __device__ __forceinline__ void sweep(const DevSweep AS4 &s, T *__restrict__ X, 
         if (st.z == 1) preD = load_dense<T, NT>(s, st.w, Un, tid);
       }
     }
-    lane_update<C, T>(s, U, 0, tid, first, X, init, s_r, block);
+    lane_update<C, T>(s, U, 0, tid, first, X, s_r, block);
     const int32_t passes = (U.rows + U.groups - 1) / U.groups;
     for (int32_t p = 1; p < passes; ++p)
-      lane_update<C, T>(s, U, p, tid, load_slots<T>(s, U, p, tid), X, init, s_r, block);
+      lane_update<C, T>(s, U, p, tid, load_slots<T>(s, U, p, tid), X, s_r, block);
     step_barrier<LDSX>();
     if (block) {
       dense_apply<C, NT, T>(U, dense, X, s_r, tid);
@@ -635,22 +827,31 @@ __device__ __forceinline__ void reduction(const NetDesc AS4 &nd, const WorkItem 
   __syncthreads();
   if (st) st[1] = wall_clock64();
   // 2. Z' = Uh^{-1} D^{-1} L^{-1} B'
-  sweep<C, NT, double, LDSX>(nd.L, X, nullptr, s_r, tid, ss);
+  sweep<C, NT, double, LDSX>(nd.L, X, s_r, tid, ss);
   pivot_scale<C, NT, double>(nd.pivinv, X, nd.n_x, tid);
   if (st) st[2] = wall_clock64();
-  sweep<C, NT, double, LDSX>(nd.U, X, nullptr, s_r, tid, ss ? ss + kMaxStepStamps : nullptr);
+  sweep<C, NT, double, LDSX>(nd.U, X, s_r, tid, ss ? ss + kSweepStamps : nullptr);
   if (st) st[3] = wall_clock64();
   // 3. tensor projection: -Y_x into Yx, Y_p into the output
   projection<C, NT>(nd, a, X, Yx, s_slack, dir0, tid);
   if (st) st[4] = wall_clock64();
-  // 4. Psi' = L^{-T} D^{-1} Uh^{-T} (-P Y_x)
-  sweep<C, NT, double, LDSX>(nd.Ut, X, Yx, s_r, tid, ss ? ss + 2 * kMaxStepStamps : nullptr);
-  pivot_scale<C, NT, double>(nd.pivinv, X, nd.n_x, tid);
+  // 4. Psi' = L^{-T} D^{-1} Uh^{-T} (-P Y_x), in place on the working vector
+  // V: X in LDS takes a copy of -P Y_x (Z is no longer needed); with X in
+  // global memory the solve runs on Yx itself
+  double *V = X;
+  if constexpr (LDSX) {
+    for (int32_t i = tid; i < nd.n_x * C; i += NT) X[i] = Yx[i];
+    __syncthreads();
+  } else {
+    V = Yx;
+  }
+  sweep<C, NT, double, LDSX>(nd.Ut, V, s_r, tid, ss ? ss + 2 * kSweepStamps : nullptr);
+  pivot_scale<C, NT, double>(nd.pivinv, V, nd.n_x, tid);
   if (st) st[5] = wall_clock64();
-  sweep<C, NT, double, LDSX>(nd.Lt, X, nullptr, s_r, tid, ss ? ss + 3 * kMaxStepStamps : nullptr);
+  sweep<C, NT, double, LDSX>(nd.Lt, V, s_r, tid, ss ? ss + 3 * kSweepStamps : nullptr);
   if (st) st[6] = wall_clock64();
   // 5. H W = Y_p + G_p^T Psi
-  spmuladd<C, NT>(nd, a, X, dir0, tid);
+  spmuladd<C, NT>(nd, a, V, dir0, tid);
   __syncthreads();
   if (st) st[7] = wall_clock64();
 }
@@ -686,9 +887,9 @@ __device__ __forceinline__ void refined_solve(const NetDesc AS4 &nd, const doubl
       for (int c = 0; c < C; ++c) X32[i * C + c] = (float)r[c];
     }
     __syncthreads();
-    sweep<C, NT, float, LDSX>(s1, X32, nullptr, s_r, tid);
+    sweep<C, NT, float, LDSX>(s1, X32, s_r, tid);
     pivot_scale<C, NT, float>(nd.pivinv32, X32, nd.n_x, tid);
-    sweep<C, NT, float, LDSX>(s2, X32, nullptr, s_r, tid);
+    sweep<C, NT, float, LDSX>(s2, X32, s_r, tid);
     for (int32_t i = tid; i < nd.n_x; i += NT) {
 #pragma unroll
       for (int c = 0; c < C; ++c)
@@ -872,15 +1073,40 @@ rh_status runner_collect(Runner &r, const DeviceInfo &info, rh_report &rep, std:
     r.stamps_groups = 0;
   }
   if (r.step_stamps_pending && info.wall_khz > 0) {
-    std::vector<long long> st(4 * kMaxStepStamps);
+    std::vector<long long> st(4 * kSweepStamps);
     HIP_TRY(hipDeviceSynchronize());
     HIP_TRY(hipMemcpy(st.data(), r.step_stamps, st.size() * sizeof(long long), hipMemcpyDeviceToHost));
     const char *nm[4] = {"L", "U", "Ut", "Lt"};
+    const double us = 1e3 / info.wall_khz;
     for (int w = 0; w < 4; ++w) {
+      const long long *S = st.data() + (size_t)w * kSweepStamps;
       fprintf(stderr, "steps %s (us):", nm[w]);
-      for (int k = 1; k < kMaxStepStamps && st[w * kMaxStepStamps + k] != 0; ++k)
-        fprintf(stderr, " %.2f",
-                (st[w * kMaxStepStamps + k] - st[w * kMaxStepStamps + k - 1]) / info.wall_khz * 1e3);
+      int wave_k = -1;
+      for (int k = 1; k < kMaxStepStamps && S[k] != 0; ++k) {
+        fprintf(stderr, " %.2f", (S[k] - S[k - 1]) * us);
+        // a wave step's units stamp inside (S[k-1], S[k]]
+        for (int v = 0; v < kWaves && wave_k < 0; ++v)
+          if (S[kMaxStepStamps + v * kUnitStamps] > S[k - 1] && S[kMaxStepStamps + v * kUnitStamps] <= S[k])
+            wave_k = k;
+      }
+      fprintf(stderr, "\n");
+      if (wave_k < 0) continue;
+      // the wave that finished last: its unit durations
+      int last = 0;
+      long long end_last = 0;
+      for (int v = 0; v < kWaves; ++v) {
+        long long e = 0;
+        for (int u = 0; u < kUnitStamps; ++u) e = std::max(e, S[kMaxStepStamps + v * kUnitStamps + u]);
+        if (e > end_last) { end_last = e; last = v; }
+      }
+      fprintf(stderr, "units %s wave %d (us):", nm[w], last);
+      long long prev = S[wave_k - 1];
+      for (int u = 0; u < kUnitStamps; ++u) {
+        const long long t = S[kMaxStepStamps + last * kUnitStamps + u];
+        if (t == 0) break;
+        fprintf(stderr, " %.2f", (t - prev) * us);
+        prev = t;
+      }
       fprintf(stderr, "\n");
     }
     r.step_stamps_pending = false;
@@ -1013,8 +1239,8 @@ rh_status run_items(const DeviceInfo &info, Runner &r, int32_t timing, int32_t r
   }
   la.step_stamps = nullptr;
   if (std::getenv("RH_STEP_STAMPS")) {
-    if (!r.step_stamps) HIP_TRY(hipMalloc(&r.step_stamps, 4 * kMaxStepStamps * sizeof(long long)));
-    HIP_TRY(hipMemsetAsync(r.step_stamps, 0, 4 * kMaxStepStamps * sizeof(long long), s));
+    if (!r.step_stamps) HIP_TRY(hipMalloc(&r.step_stamps, 4 * kSweepStamps * sizeof(long long)));
+    HIP_TRY(hipMemsetAsync(r.step_stamps, 0, 4 * kSweepStamps * sizeof(long long), s));
     la.step_stamps = r.step_stamps;
     r.step_stamps_pending = true;
   }
@@ -1132,7 +1358,8 @@ const T *at_off(const char *base, int64_t off) {
 rh_status upload_sweep(DeviceNet *dn, const Sweep &s, int32_t n, const std::vector<int32_t> &parent,
                        bool forward, const ScheduleParams &prm, DevSweep &o, std::string &err) {
   const Schedule sc = build_schedule(s, n, parent, forward, prm);
-  const Packed pk = pack_schedule(sc, kThreads);
+  Packed pk = pack_schedule(sc, kThreads);
+  if (pk.irow.empty()) pk.irow.push_back(0);  // lanes without a row read element 0
   if (!pk.idinv.empty()) {
     err = "internal: device sweeps must have a unit diagonal";
     return RH_EDEVICE;
@@ -1164,6 +1391,8 @@ rh_status upload_sweep(DeviceNet *dn, const Sweep &s, int32_t n, const std::vect
   o.warm64_bytes = (int64_t)(m2 - m1);
   o.warm32 = base + m2;
   o.warm32_bytes = (int64_t)(m3 - m2);
+  o.n_slots = (int32_t)pk.scol.size();
+  o.n_irow = (int32_t)pk.irow.size();
   dn->sweep_steps.push_back(o.n_steps);
   return RH_OK;
 }

@@ -49,14 +49,21 @@ struct LuPlan {
 // merged blocks split off into dense block inverses; per step
 // {first position, rows, log2 lanes per row, kind}, kind = dense offset of a
 // block, -1 for a plain level, or -2 - d for a wave step whose waves' level
-// lists are wlev[wdir[d + w] .. wdir[d + w + 1]) (4 ints per wave level:
-// first position, rows, log2 lanes per row, 0).
+// lists are wlev[wdir[d + w] .. wdir[d + w + 1]) (4 ints per wave unit:
+// first position, rows, log2 lanes per row, assign).  A wave unit is one wave
+// level, or one half of a wave block (see kWaveBlockRows): its residual unit
+// (assign 0, entries to rows outside the block) followed by the assigning
+// unit (assign 1) whose entries are the rows of the block's inverse.
 struct Schedule {
   Sweep s;  // rows, ptr, col, val, dinv (lev_ptr unused)
   std::vector<int32_t> meta;
   std::vector<double> dense;
   std::vector<int32_t> wdir, wlev;
 };
+
+// Rows of a wave block: a run of narrow wave levels solved with the inverse of
+// its unit lower-triangular block (one lane group of 4 per row, one pass).
+constexpr int32_t kWaveBlockRows = 16;
 
 // Device form of a schedule.  Every unit (a level step, the rows of a block,
 // or one wave level of a wave step) stores its entries in per-lane slots:
@@ -65,12 +72,21 @@ struct Schedule {
 // and pass, padded with (column 0, value 0).  Slot (pass, e, lane) sits at
 // slot_base + (pass * E + e) * lanes + lane, so a lane needs no row pointer.
 // units: 8 ints each {slot_base, info_base, rows, groups, lg, E, lanes,
-// compact}; for wave-step units compact = rows | lg << 16 | E << 19 (their
-// groups = min(rows, 64 >> lg)), else -1.
+// compact}; for wave-step units compact = rows | lg << 15 | assign << 18 |
+// E << 19 (their groups = min(rows, 64 >> lg)), else -1.  An assigning unit
+// writes its rows' dot products (x_i = sum) instead of x_i - sum; it is the
+// second half of a wave block and reads only rows of that block.
 // irow/idinv give each row's matrix row and reciprocal pivot (unit order).
+// Slot 0 and dense[0] are a zero padding entry (offsets start at 1); the
+// slot arrays end with a zero tail of 64 x kSlotsAhead slots and irow with 64
+// rows.  Wave units have one pass and at least kSlotsAhead slots per lane.
 // steps: 4 ints each {unit or wave directory offset, 0, kind, dense offset},
 // kind 0 = level, 1 = block (dense inverse at the offset), 2 = wave step
 // (its waves' unit ranges are wdir[off + w] .. wdir[off + w + 1]).
+// Entry slots per lane that the kernel loads ahead of a unit; wave units are
+// packed to fit in them where 64 lanes allow.
+constexpr int kSlotsAhead = 4;
+
 struct Packed {
   std::vector<int32_t> steps, units, wdir;
   std::vector<int32_t> scol, irow;

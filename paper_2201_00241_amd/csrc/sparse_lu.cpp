@@ -518,25 +518,80 @@ Schedule build_schedule(const Sweep &in, int32_t n, const std::vector<int32_t> &
     const int32_t dir0 = (int32_t)out.wdir.size();
     const int32_t b = (int32_t)out.s.rows.size();
     int32_t rows_total = 0;
-    for (int w = 0; w < nw; ++w) {
-      out.wdir.push_back((int32_t)(out.wlev.size() / 4));
-      for (auto &lv : W[w]) {
-        // rows of one wave level, as a plain level step of the wave
-        const int32_t first = (int32_t)out.s.rows.size();
-        int32_t longest = 0;
-        for (int32_t p : lv) {
-          out.s.rows.push_back(in.rows[p]);
-          if (!in.dinv.empty()) out.s.dinv.push_back(in.dinv[p]);
-          for (int32_t q = in.ptr[p]; q < in.ptr[p + 1]; ++q) {
+    // rows at positions `ps` of `in` as one wave unit; entries to columns with
+    // local[c] >= 0 (inside a wave block) are left out
+    auto emit_unit = [&](const std::vector<int32_t> &ps) {
+      const int32_t first = (int32_t)out.s.rows.size();
+      int32_t longest = 0;
+      for (int32_t p : ps) {
+        out.s.rows.push_back(in.rows[p]);
+        if (!in.dinv.empty()) out.s.dinv.push_back(in.dinv[p]);
+        const int32_t start = (int32_t)out.s.col.size();
+        for (int32_t q = in.ptr[p]; q < in.ptr[p + 1]; ++q)
+          if (local[in.col[q]] < 0) {
             out.s.col.push_back(in.col[q]);
             out.s.val.push_back(in.val[q]);
           }
-          out.s.ptr.push_back((int32_t)out.s.col.size());
-          longest = std::max(longest, in.ptr[p + 1] - in.ptr[p]);
+        out.s.ptr.push_back((int32_t)out.s.col.size());
+        longest = std::max(longest, (int32_t)out.s.col.size() - start);
+      }
+      out.wlev.insert(out.wlev.end(), {first, (int32_t)ps.size(), lane_log2((int32_t)ps.size(), longest, 64), 0});
+      rows_total += (int32_t)ps.size();
+    };
+    // a run of narrow wave levels with at most kWaveBlockRows rows in all:
+    // a residual unit (entries to earlier rows) and an assigning unit that
+    // applies the inverse of the run's unit lower-triangular block, whose
+    // "entries" are the inverse's row (columns = the run's rows, diagonal 1)
+    auto emit_wave_block = [&](const std::vector<int32_t> &ps) {
+      const int32_t R = (int32_t)ps.size();
+      for (int32_t a = 0; a < R; ++a) local[in.rows[ps[a]]] = a;
+      std::vector<long double> M((size_t)R * R, 0.0L);  // column-major
+      for (int32_t a = 0; a < R; ++a) {
+        M[(size_t)a * (R + 1)] = 1.0L;
+        for (int32_t q = in.ptr[ps[a]]; q < in.ptr[ps[a] + 1]; ++q)
+          if (local[in.col[q]] >= 0) M[(size_t)a + (size_t)local[in.col[q]] * R] = in.val[q];
+      }
+      emit_unit(ps);
+      // inverse by forward substitution on the unit vectors (extended precision)
+      std::vector<long double> inv((size_t)R * R, 0.0L), y(R);
+      for (int32_t j = 0; j < R; ++j) {
+        for (int32_t a = 0; a < R; ++a) {
+          long double acc = (a == j) ? 1.0L : 0.0L;
+          for (int32_t c = j; c < a; ++c) acc -= M[(size_t)a + (size_t)c * R] * y[c];
+          y[a] = a < j ? 0.0L : acc;
         }
-        out.wlev.insert(out.wlev.end(),
-                        {first, (int32_t)lv.size(), lane_log2((int32_t)lv.size(), longest, 64), 0});
-        rows_total += (int32_t)lv.size();
+        for (int32_t a = j; a < R; ++a) inv[(size_t)a + (size_t)j * R] = y[a];
+      }
+      const int32_t first = (int32_t)out.s.rows.size();
+      for (int32_t a = 0; a < R; ++a) {
+        out.s.rows.push_back(in.rows[ps[a]]);
+        for (int32_t c = 0; c <= a; ++c) {
+          out.s.col.push_back(in.rows[ps[c]]);
+          out.s.val.push_back((double)inv[(size_t)a + (size_t)c * R]);
+        }
+        out.s.ptr.push_back((int32_t)out.s.col.size());
+      }
+      out.wlev.insert(out.wlev.end(), {first, R, lane_log2(R, R, 64), 1});
+      for (int32_t a = 0; a < R; ++a) local[in.rows[ps[a]]] = -1;
+    };
+    for (int w = 0; w < nw; ++w) {
+      out.wdir.push_back((int32_t)(out.wlev.size() / 4));
+      const size_t L = W[w].size();
+      size_t l = 0;
+      while (l < L) {
+        size_t l2 = l;
+        int32_t rows = 0;
+        if (in.dinv.empty())
+          while (l2 < L && rows + (int32_t)W[w][l2].size() <= kWaveBlockRows) rows += (int32_t)W[w][l2++].size();
+        if (l2 - l >= 3) {
+          std::vector<int32_t> ps;
+          for (size_t x = l; x < l2; ++x) ps.insert(ps.end(), W[w][x].begin(), W[w][x].end());
+          emit_wave_block(ps);
+          l = l2;
+        } else {
+          emit_unit(W[w][l]);
+          ++l;
+        }
       }
     }
     out.wdir.push_back((int32_t)(out.wlev.size() / 4));
@@ -562,7 +617,8 @@ std::vector<int32_t> etree_parent(const LuPlan &lu) {
 namespace {
 
 // One unit: rows at positions [b, b + rows) of sc.s with lane groups of 2^lg.
-int32_t pack_unit(const Schedule &sc, int32_t b, int32_t rows, int lg, int max_lanes, Packed &pk) {
+int32_t pack_unit(const Schedule &sc, int32_t b, int32_t rows, int lg, int max_lanes, int assign, int32_t min_E,
+                  Packed &pk) {
   const Sweep &s = sc.s;
   const int32_t w = 1 << lg;
   const int32_t groups = std::max<int32_t>(1, std::min<int32_t>(rows, max_lanes / w));
@@ -570,7 +626,7 @@ int32_t pack_unit(const Schedule &sc, int32_t b, int32_t rows, int lg, int max_l
   const int32_t passes = rows > 0 ? (rows + groups - 1) / groups : 0;
   int32_t longest = 0;
   for (int32_t r = 0; r < rows; ++r) longest = std::max(longest, s.ptr[b + r + 1] - s.ptr[b + r]);
-  const int32_t E = (longest + w - 1) / w;
+  const int32_t E = std::max(min_E, (longest + w - 1) / w);
   const int32_t slot_base = (int32_t)pk.scol.size(), info_base = (int32_t)pk.irow.size();
   pk.scol.resize(pk.scol.size() + (size_t)passes * E * lanes, 0);
   pk.sval.resize(pk.sval.size() + (size_t)passes * E * lanes, 0.0);
@@ -590,7 +646,8 @@ int32_t pack_unit(const Schedule &sc, int32_t b, int32_t rows, int lg, int max_l
   }
   const int32_t u = (int32_t)(pk.units.size() / 8);
   // compact form for the per-lane unit tables of wave steps (64 lanes)
-  const int32_t compact = (max_lanes == 64 && rows < (1 << 16) && E < (1 << 13)) ? (rows | lg << 16 | E << 19) : -1;
+  const int32_t compact =
+      (max_lanes == 64 && rows < (1 << 15) && E < (1 << 13)) ? (rows | lg << 15 | assign << 18 | E << 19) : -1;
   pk.units.insert(pk.units.end(), {slot_base, info_base, rows, groups, lg, E, lanes, compact});
   return u;
 }
@@ -599,7 +656,12 @@ int32_t pack_unit(const Schedule &sc, int32_t b, int32_t rows, int lg, int max_l
 
 Packed pack_schedule(const Schedule &sc, int lanes) {
   Packed pk;
-  pk.dense = sc.dense;
+  // element 0 of the slots and of the block inverses is a zero that lanes
+  // without an entry read
+  pk.scol.assign(1, 0);
+  pk.sval.assign(1, 0.0);
+  pk.dense.assign(1, 0.0);
+  pk.dense.insert(pk.dense.end(), sc.dense.begin(), sc.dense.end());
   const size_t ns = sc.meta.size() / 4;
   for (size_t st = 0; st < ns; ++st) {
     const int32_t b = sc.meta[4 * st], rows = sc.meta[4 * st + 1], lg = sc.meta[4 * st + 2];
@@ -610,17 +672,38 @@ Packed pack_schedule(const Schedule &sc, int lanes) {
       const int32_t nw = lanes / 64;
       for (int32_t w = 0; w < nw; ++w) {
         pk.wdir.push_back((int32_t)(pk.units.size() / 8));
-        for (int32_t j = sc.wdir[d + w]; j < sc.wdir[d + w + 1]; ++j)
-          if (pk.units[8 * pack_unit(sc, sc.wlev[4 * j], sc.wlev[4 * j + 1], sc.wlev[4 * j + 2], 64, pk) + 7] < 0)
-            throw std::runtime_error("wave level too large for the compact unit form");
+        for (int32_t j = sc.wdir[d + w]; j < sc.wdir[d + w + 1]; ++j) {
+          const int32_t b = sc.wlev[4 * j], rows = sc.wlev[4 * j + 1], assign = sc.wlev[4 * j + 3];
+          // a plain (subtracting) wave unit's rows are independent: split it
+          // into one-pass units with lane groups wide enough that every row
+          // fits in the slots the kernel loads ahead (as far as 64 lanes allow)
+          int32_t per = rows, lg = sc.wlev[4 * j + 2];
+          if (!assign) {
+            int32_t longest = 0;
+            for (int32_t r = 0; r < rows; ++r) longest = std::max(longest, sc.s.ptr[b + r + 1] - sc.s.ptr[b + r]);
+            lg = 0;
+            while (lg < 6 && (1 << lg) * kSlotsAhead < longest) ++lg;
+            per = std::max(1, 64 >> lg);
+          }
+          // one pass, padded to kSlotsAhead slots per lane (the kernel's
+          // fixed-shape fast path)
+          for (int32_t r0 = 0; r0 < rows; r0 += per)
+            if (pk.units[8 * pack_unit(sc, b + r0, std::min(per, rows - r0), lg, 64, assign, kSlotsAhead, pk) + 7] < 0)
+              throw std::runtime_error("wave level too large for the compact unit form");
+        }
       }
       pk.wdir.push_back((int32_t)(pk.units.size() / 8));
       pk.steps.insert(pk.steps.end(), {off, 0, 2, 0});
     } else {
-      const int32_t u = pack_unit(sc, b, rows, lg, lanes, pk);
-      pk.steps.insert(pk.steps.end(), {u, 0, kind >= 0 ? 1 : 0, kind >= 0 ? kind : 0});
+      const int32_t u = pack_unit(sc, b, rows, lg, lanes, 0, 0, pk);
+      pk.steps.insert(pk.steps.end(), {u, 0, kind >= 0 ? 1 : 0, kind >= 0 ? kind + 1 : 0});
     }
   }
+  // zero tail: a wave unit's lanes beyond its rows read up to 64 x
+  // kSlotsAhead slots and 64 row indices past its start
+  pk.scol.resize(pk.scol.size() + 64 * kSlotsAhead, 0);
+  pk.sval.resize(pk.sval.size() + 64 * kSlotsAhead, 0.0);
+  pk.irow.resize(pk.irow.size() + 64, 0);
   return pk;
 }
 

@@ -6,6 +6,7 @@
 //     structure (plain levels and dense-inverse blocks) against a plain
 //     row-by-row sweep, for block sizes 0, 16 and 64.
 // Prints "max_err <name> <value>" lines; exit status 0 unless it fails to run.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <random>
@@ -50,8 +51,21 @@ static void emulate(const Schedule &sc, std::vector<double> &X, bool &ok) {
       const int d = -2 - off;
       const int nw = 16;
       for (int w = nw - 1; w >= 0; --w)
-        for (int j = sc.wdir[d + w]; j < sc.wdir[d + w + 1]; ++j)
-          for (int r = 0; r < sc.wlev[4 * j + 1]; ++r) row(sc.wlev[4 * j] + r);
+        for (int j = sc.wdir[d + w]; j < sc.wdir[d + w + 1]; ++j) {
+          const int first = sc.wlev[4 * j], nr = sc.wlev[4 * j + 1];
+          if (sc.wlev[4 * j + 3] == 0) {
+            for (int r = 0; r < nr; ++r) row(first + r);
+          } else {
+            // assigning unit of a wave block: all reads, then all writes
+            std::vector<double> v(nr, 0.0);
+            for (int r = 0; r < nr; ++r)
+              for (int q = s.ptr[first + r]; q < s.ptr[first + r + 1]; ++q) {
+                if (pending[s.col[q]]) ok = false;
+                v[r] += s.val[q] * X[s.col[q]];
+              }
+            for (int r = 0; r < nr; ++r) X[s.rows[first + r]] = v[r];
+          }
+        }
       continue;
     }
     if (off < 0) {
@@ -90,6 +104,37 @@ static void emulate(const Schedule &sc, std::vector<double> &X, bool &ok) {
   (void)done;
 }
 
+// The kernel walks a wave's units from the compact words alone: the slot
+// base and row-info base of each unit are running sums from the wave's first
+// unit, and lanes/groups/passes follow from rows and lg.  Returns false if
+// any wave unit disagrees with its stored descriptor.
+static bool check_wave_walk(const Packed &pk) {
+  for (size_t st = 0; st < pk.steps.size() / 4; ++st) {
+    if (pk.steps[4 * st + 2] != 2) continue;
+    const int a = pk.steps[4 * st];
+    for (int w = 0; w < 16; ++w) {
+      const int u0 = pk.wdir[a + w], u1 = pk.wdir[a + w + 1];
+      if (u0 >= u1) continue;
+      long sb = pk.units[8 * u0], ib = pk.units[8 * u0 + 1];
+      for (int u = u0; u < u1; ++u) {
+        const int *U = &pk.units[8 * u];
+        const int cw = U[7];
+        if (cw < 0) return false;
+        const int rows = cw & 0x7FFF, lg = (cw >> 15) & 7, E = (int)((unsigned)cw >> 19);
+        const int groups = std::max(1, std::min(rows, 64 >> lg)), lanes = groups << lg;
+        if (U[0] != sb || U[1] != ib || U[2] != rows || U[3] != groups || U[4] != lg || U[5] != E || U[6] != lanes)
+          return false;
+        const int passes = (rows + (64 >> lg) - 1) >> (6 - lg);
+        if (passes != (rows + groups - 1) / groups && rows > 0) return false;
+        if (sb + (long)passes * E * lanes > (long)pk.scol.size() || ib + rows > (long)pk.irow.size()) return false;
+        sb += (long)passes * E * lanes;
+        ib += rows;
+      }
+    }
+  }
+  return true;
+}
+
 // Emulates the kernel on the packed (per-lane slot) form: every lane sums its
 // slots, lane groups combine, the group's row is written.  Wave steps run
 // waves in reverse order; reads of rows not yet final clear `ok`.
@@ -98,6 +143,7 @@ static void emulate_packed(const Packed &pk, std::vector<double> &X, std::vector
     const int *U = &pk.units[8 * u];
     const int slot_base = U[0], info_base = U[1], rows = U[2], groups = U[3], lg = U[4], E = U[5],
               lanes = U[6];
+    const bool assign = U[7] >= 0 && ((U[7] >> 18) & 1);
     const int w = 1 << lg;
     r.assign(rows, 0.0);
     std::vector<double> part(rows, 0.0);
@@ -114,7 +160,7 @@ static void emulate_packed(const Packed &pk, std::vector<double> &X, std::vector
       }
     for (int a = 0; a < rows; ++a) {
       const int i = pk.irow[info_base + a];
-      double v = X[i] - part[a];
+      double v = assign ? part[a] : X[i] - part[a];
       if (block) {
         r[a] = v;
       } else {
@@ -277,6 +323,10 @@ int main(int argc, char **argv) {
           for (int32_t rr : sw[k].rows) pend[rr] = 1;
           bool okp = true;
           emulate_packed(pk, Xa, pend, okp);
+          if (!check_wave_walk(pk)) {
+            printf("wave_walk_mismatch %s_w%d_b%d\n", nm[k], wave, bmax);
+            okp = false;
+          }
           plain(sw[k], Xb);
           if (!okp) ++bad;
           printf("max_err packed_%s_w%d_b%d %.3e order_ok %d slots %zu\n", nm[k], wave, bmax,
