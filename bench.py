@@ -16,6 +16,7 @@ The CPU baseline runs the FP64 oracle (single-threaded SuperLU solves and
 sparse products) on the same grid for a bounded sample of identity blocks.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -28,6 +29,35 @@ sys.path.insert(0, str(ROOT))
 import numpy as np  # noqa: E402
 
 PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = ROOT / "profiles" / "block_kernel_10k_hbm_traffic.txt"
+
+
+def sources_digest():
+    """SHA-256 over the library sources (kernels, planner, ABI), in name order."""
+    h = hashlib.sha256()
+    for f in sorted((ROOT / "paper_2201_00241_amd" / "csrc").iterdir()):
+        if f.suffix in (".hip", ".cpp", ".h"):
+            h.update(f.name.encode())
+            h.update(f.read_bytes())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the block kernel from the committed counter
+    summary, or None if the kernel sources changed since it was measured."""
+    if not TRAFFIC_FILE.exists():
+        return None
+    kv = {}
+    for line in TRAFFIC_FILE.read_text().splitlines():
+        if ":" in line and not line.startswith(("#", " ", "|")):
+            key, val = line.split(":", 1)
+            kv[key.strip()] = val.strip()
+    if kv.get("sources_sha256") != sources_digest():
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def algorithmic_bytes_per_launch(rep, g, k):
@@ -144,6 +174,20 @@ def main():
     ms_per_step = total_ms / args.steps
     value = n_p * args.steps / (total_ms / 1e3)
 
+    # the refined FP32 mode on the same workload ("vs plain"), after the timed region
+    H64 = H.clone()
+    for _ in range(args.warmup):
+        net.reduced_hessian_device(H, k_block=k, stream=sptr, prec=rh.RH_FP32_REFINED)
+    r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    r0.record(stream)
+    for _ in range(args.steps):
+        net.reduced_hessian_device(H, k_block=k, stream=sptr, prec=rh.RH_FP32_REFINED)
+    r1.record(stream)
+    torch.cuda.synchronize()
+    refined_ms = r0.elapsed_time(r1) / args.steps
+    refined_dev = float((H - H64).abs().max() / H64.abs().max())
+    H.copy_(H64)
+
     # one more step with in-kernel phase stamps (outside the timed region)
     ctx.set_timing(2)
     net.reduced_hessian_device(H, k_block=k, stream=sptr)
@@ -156,6 +200,7 @@ def main():
     avg_launch_ms = trep["last_kernel_ms"] / launches
     bytes_launch = algorithmic_bytes_per_launch(rep, g, k)
     achieved = bytes_launch / (avg_launch_ms / 1e3) / 1e9
+    traffic = measured_traffic()
     out = {
         "metric": "reduced-Hessian HVPs/sec at 10k buses (k=256) vs plain; p50/p99 latency",
         "value": value,
@@ -186,10 +231,14 @@ def main():
                        "what": "one full reduced Hessian"},
         "roofline": {
             "bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+            "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
             "kernel": "block_kernel", "avg_launch_ms": avg_launch_ms,
             "algorithmic_bytes_per_launch": bytes_launch,
         },
+        "refined_fp32": {"value": n_p / (refined_ms / 1e3), "unit": "HVP/s", "ms_per_step": refined_ms,
+                         "max_rel_dev_from_fp64": refined_dev,
+                         "what": "same workload, FP32 sweeps with two FP64 refinement steps"},
         "setup_s": setup_s,
         "wall_s": wall,
     }

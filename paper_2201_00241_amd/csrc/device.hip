@@ -1167,7 +1167,7 @@ int32_t choose_c(int64_t k, int32_t cus, int64_t n_x, size_t lds_max, bool lds, 
     if ((v == 1 || v == 2 || v == 4) && (!lds || (size_t)n_x * v * elem <= lds_max))
       return v;
   }
-  int32_t c = lds ? 4 : 8;
+  int32_t c = 4;  // the largest group the kernels are instantiated for
   while (c > 1 && (k < (int64_t)c * 2 * cus || (lds && (size_t)n_x * c * elem > lds_max))) c >>= 1;
   return c;
 }
@@ -1275,7 +1275,9 @@ rh_status run_items(const DeviceInfo &info, Runner &r, int32_t timing, int32_t r
     case 1: st = launch<1>(lds, refined, groups, lds_bytes, s, la, err); break;
     case 2: st = launch<2>(lds, refined, groups, lds_bytes, s, la, err); break;
     case 4: st = launch<4>(lds, refined, groups, lds_bytes, s, la, err); break;
-    default: st = launch<4>(lds, refined, groups, lds_bytes, s, la, err); break;
+    default:
+      err = "internal: no kernel for " + std::to_string(C) + " directions per workgroup";
+      return RH_EDEVICE;
   }
   if (st != RH_OK) return st;
   if (items.size() > 1) HIP_TRY(hipEventRecord(r.items_done, s));

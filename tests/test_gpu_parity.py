@@ -219,6 +219,35 @@ def test_batched_instances_match_single_calls_bitwise(ctx, rhmod, c1):
     assert _relerr(HWs[1].cpu().numpy().T, s2.hvp(Ws[1].cpu().numpy().T)) <= TOL
 
 
+@pytest.mark.parametrize("global_x", [False, True])
+def test_large_batch_uses_four_directions_per_group_bitwise(ctx, rhmod, c1, global_x, monkeypatch):
+    """A launch with enough directions for groups of four (the largest
+    instantiated kernel), with the working vector in LDS and in global
+    memory: every direction equals its solo result bitwise."""
+    import torch
+
+    g1, net1, s1 = c1
+    if global_x:
+        monkeypatch.setenv("RH_NO_LDS", "1")
+    n_items, k = 12, net1.n_p
+    Ws = [torch.from_numpy(np.ascontiguousarray(gridgen.directions(net1.n_p, k, 300 + i).T)).cuda()
+          for i in range(n_items)]
+    HWs = [torch.zeros_like(W) for W in Ws]
+    stream = torch.cuda.current_stream().cuda_stream
+    _say(f"batch: {n_items} x {k} directions of the 1k grid, global X = {global_x}")
+    ctx.hvp_batch_device([net1] * n_items, Ws, HWs, stream=stream)
+    torch.cuda.synchronize()
+    rep = ctx.report()
+    assert rep["last_launches"] == 1 and rep["dirs_per_group"] == 4
+    monkeypatch.delenv("RH_NO_LDS", raising=False)
+    for i in (0, n_items // 2, n_items - 1):
+        ref = torch.zeros_like(Ws[i])
+        net1.hvp_device(Ws[i], ref, stream=stream)
+        torch.cuda.synchronize()
+        assert torch.equal(HWs[i], ref)
+    assert _relerr(HWs[-1].cpu().numpy().T, s1.hvp(Ws[-1].cpu().numpy().T)) <= TOL
+
+
 def test_served_results_equal_solo_results(ctx, rhmod, c1):
     """Continuous batching: each request's result is bitwise its solo result,
     whatever it shared its launches with; full Hessians match the oracle."""
