@@ -113,7 +113,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 "
-                                   "(direction blocks would shard across GPUs, see DESIGN.md)"}))
+                                   "(direction blocks are independent and would shard across "
+                                   "GPUs by block, which is not implemented)"}))
         sys.exit(2)
 
     import torch
