@@ -36,6 +36,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 
 #include "rh_internal.h"
 
@@ -88,8 +89,23 @@ __device__ __forceinline__ const double *sw_dense<double>(const DevSweep AS4 &s)
 template <>
 __device__ __forceinline__ const float *sw_dense<float>(const DevSweep AS4 &s) { return s.dense32; }
 
+// Tensor projection records.  Buses are taken in passes of kThreads (ordered
+// by decreasing degree, so a pass's lanes have similar incidence counts); lane
+// t of pass p holds bus p * kThreads + t of that order, and its incidence e
+// is slot pass.x + e * kThreads + t for e < pass.y (the pass's largest
+// degree), padded with slots whose ot is kPadInc.  Every record of a pass is
+// addressed without reading another one, so a lane issues all its loads at
+// once.  Records are planes of 16-byte words (a wave's load of one plane is
+// 1 KB contiguous):
+//   bus b:  {bits(tx, vs), ve}, {sth, sv}          planes of passes x kThreads words
+//   slot k: {K, Hps}, {H, A2}, {vo, bits(ot, ov)}  planes of proj_slots words
+// bits(a, b) holds two int32 (a in the low half) in the bytes of a double.
+constexpr int32_t kPadInc = -2;
+// record arrays stay below the out-of-range offset (see kOffRange)
+constexpr int64_t kProjMaxBytes = 0x3f000000;
+
 struct NetDesc {
-  int32_t n_x, n_p, n_bus, n_pg, n_slack;
+  int32_t n_x, n_p, n_bus, n_slack, n_proj_pass;
   DevSweep L, U, Ut, Lt;  // U and Ut hold the unit factor D^{-1} U
   const double *pivinv;   // D^{-1}, applied between the two sweeps of a solve
   const float *pivinv32;
@@ -97,16 +113,20 @@ struct NetDesc {
   const double *gp_val;
   const int32_t *gpt_ptr, *gpt_col;  // G_p^T, columns in permuted x order
   const double *gpt_val;
-  // bus tangent sources: theta from X[thx] (-1: reference, zero tangent);
+  // bus tangent sources: theta from X[tx] (-1: reference, zero tangent);
   // v from X[vs] if vs >= 0, else from W[-vs - 1] (generator magnitude)
-  const int32_t *bus_thx, *bus_vs;
-  const int32_t *inc_ptr, *inc_othx, *inc_ovs;  // incidences, other end's sources
-  const double *inc_K, *inc_Hps, *inc_H, *inc_A2, *inc_vo;
-  const double *bus_v, *bus_sth, *bus_sv;
+  const double2 *proj_bus, *proj_inc;
+  const int2 *proj_pass;  // {first slot, slots per lane}
+  int32_t proj_slots;
+  // byte ranges warmed into L2 by the sweep before the phase that reads them:
+  // the projection records, and G_p^T with p_c2x2
+  const char *proj_warm, *gpt_warm;
+  int64_t proj_warm_bytes, gpt_warm_bytes;
   const int32_t *slack_thx, *slack_vs;
   const double *slack_gth, *slack_gv;
-  const int32_t *pg_idx;
-  const double *pg_c2x2;
+  // 2 c2 of the generator whose output is parameter q; NaN where parameter q
+  // is a voltage magnitude (its Y_p comes from the projection)
+  const double *p_c2x2;
   // G_x and G_x^T in permuted numbering (residuals of the refined mode)
   const int32_t *gx_ptr, *gx_col, *gxt_ptr, *gxt_col;
   const double *gx_val, *gxt_val;
@@ -168,9 +188,17 @@ struct Unit {
   bool assign;  // x_i = sum (second half of a wave block) instead of x_i - sum
 };
 
+// Descriptors are read through the constant address space: scalar loads,
+// which wait on their own counter instead of behind the vector loads in
+// flight (the arrays are never written while a kernel runs).
 __device__ __forceinline__ Unit unit_at(const DevSweep AS4 &s, int32_t u) {
-  const int4 a = s.units[2 * u], b = s.units[2 * u + 1];
-  return Unit{a.x, a.y, a.z, a.w, b.x, b.y, b.z, false};
+  const int32_t AS4 *w = (const int32_t AS4 *)(s.units + 2 * u);
+  return Unit{w[0], w[1], w[2], w[3], w[4], w[5], w[6], false};
+}
+
+__device__ __forceinline__ int4 step_at(const DevSweep AS4 &s, int32_t k) {
+  const int32_t AS4 *w = (const int32_t AS4 *)(s.steps + k);
+  return make_int4(w[0], w[1], w[2], w[3]);
 }
 
 // A wave's units in a wave step, read without memory round trips per unit:
@@ -258,9 +286,37 @@ __device__ __forceinline__ Slots<T> load_slots(const DevSweep AS4 &s, const Unit
   return L;
 }
 
+// Cross-lane moves within a row of 16 lanes (DPP, no LDS round trip).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)u, CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, true);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+// Sum over aligned groups of 2^lg lanes (lg uniform, 0..6); the group's first
+// lane receives the total.  Pairs within a quad (lane ^ 1, lane ^ 2), then
+// the mirror within 8 and within 16 lanes (every lane of the smaller group
+// holds its total by then), then lane ^ 16 and lane ^ 32 by permute.
+template <class T>
+__device__ __forceinline__ T group_sum(T v, int lg) {
+  if (lg >= 1) v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+  if (lg >= 2) v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+  if (lg >= 3) v += dpp_move<0x141>(v);  // row_half_mirror
+  if (lg >= 4) v += dpp_move<0x140>(v);  // row_mirror
+  if (lg >= 5) v += __shfl_xor(v, 16);
+  if (lg >= 6) v += __shfl_xor(v, 32);
+  return v;
+}
+
 // The dense inverse of a block (rows <= kBlockRows, column-major) is applied
 // by all NT threads: NT / kBlockRows lanes per row, each with E entries
-// (columns j, j + lanes, ...) that it loads a step ahead, then a butterfly.
+// (columns j, j + lanes, ...) that it loads a step ahead, then a group sum.
 template <int NT>
 struct DenseShape {
   static constexpr int lanes = NT / kBlockRows;
@@ -307,42 +363,11 @@ __device__ __forceinline__ void dense_apply(const Unit &U, const DenseRow<T, NT>
     for (int c = 0; c < C; ++c) acc[c] = fma(R.m[e], ok ? s_r[b * C + c] : T(0), acc[c]);
   }
 #pragma unroll
-  for (int off = D::lanes >> 1; off > 0; off >>= 1) {
-#pragma unroll
-    for (int c = 0; c < C; ++c) acc[c] += __shfl_xor(acc[c], off);
-  }
+  for (int c = 0; c < C; ++c) acc[c] = group_sum(acc[c], __builtin_ctz(D::lanes));  // to lane j == 0
   if (j == 0 && a < U.rows) {
 #pragma unroll
     for (int c = 0; c < C; ++c) X[R.row * C + c] = acc[c];
   }
-}
-
-// Cross-lane moves within a row of 16 lanes (DPP, no LDS round trip).
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double v) {
-  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
-  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned)u, CTRL, 0xF, 0xF, true);
-  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(u >> 32), CTRL, 0xF, 0xF, true);
-  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
-}
-template <int CTRL>
-__device__ __forceinline__ float dpp_move(float v) {
-  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
-}
-
-// Sum over aligned groups of 2^lg lanes (lg uniform, 0..6); the group's first
-// lane receives the total.  Pairs within a quad (lane ^ 1, lane ^ 2), then
-// the mirror within 8 and within 16 lanes (every lane of the smaller group
-// holds its total by then), then lane ^ 16 and lane ^ 32 by permute.
-template <class T>
-__device__ __forceinline__ T group_sum(T v, int lg) {
-  if (lg >= 1) v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
-  if (lg >= 2) v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
-  if (lg >= 3) v += dpp_move<0x141>(v);  // row_half_mirror
-  if (lg >= 4) v += dpp_move<0x140>(v);  // row_mirror
-  if (lg >= 5) v += __shfl_xor(v, 16);
-  if (lg >= 6) v += __shfl_xor(v, 32);
-  return v;
 }
 
 // One lane's share of one pass of a unit, in two halves so that a caller can
@@ -374,20 +399,21 @@ __device__ __forceinline__ Part<C, T> lane_dot(const DevSweep AS4 &s, const Unit
   for (int e = 0; e < kPre; ++e)
 #pragma unroll
     for (int c = 0; c < C; ++c) P.v[c] = fma(L.val[e], xv[e][c], P.v[c]);
-  // remaining slots, four at a time so their loads are in flight together
+  // remaining slots, M at a time so their loads are in flight together
+  constexpr int M = 4;
   const bool act = lane < U.lanes && pass * U.groups + (lane >> U.lg) < U.rows;
-  for (int32_t e0 = kPre; e0 < U.E; e0 += 4) {
-    int32_t jj[4];
-    T vv[4];
+  for (int32_t e0 = kPre; e0 < U.E; e0 += M) {
+    int32_t jj[M];
+    T vv[M];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < M; ++e) {
       const bool ok = act && e0 + e < U.E;
       const int64_t at = ok ? (int64_t)U.slot_base + ((int64_t)pass * U.E + e0 + e) * U.lanes + lane : 0;
       vv[e] = val[at];
       jj[e] = s.scol[at] * C;
     }
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
+    for (int e = 0; e < M; ++e)
 #pragma unroll
       for (int c = 0; c < C; ++c) P.v[c] = fma(vv[e], X[jj[e] + c], P.v[c]);
   }
@@ -635,14 +661,17 @@ __device__ __forceinline__ void wave_walk_units(const DevSweep AS4 &s, int32_t u
 // A workgroup barrier separates steps.
 template <int C, int NT, class T, bool LDSX>
 __device__ __forceinline__ void sweep(const DevSweep AS4 &s, T *__restrict__ X,
-                                      T *__restrict__ s_r, int tid, long long *ss = nullptr) {
+                                      T *__restrict__ s_r, int tid, long long *ss = nullptr,
+                                      const char *next = nullptr, int64_t next_bytes = 0) {
   const int32_t ns = s.n_steps;
   if (ns == 0) return;
   if (ss && tid == 0) ss[0] = wall_clock64();
-  const uint32_t warm = l2_warm<NT>(s.warm_common, s.warm_common_bytes, tid) ^
+  // the sweep's own arrays, and those of the phase after it (`next`)
+  const uint32_t warm = l2_warm<NT>(next, next_bytes, tid) ^
+                        l2_warm<NT>(s.warm_common, s.warm_common_bytes, tid) ^
                         (sizeof(T) == 8 ? l2_warm<NT>(s.warm64, s.warm64_bytes, tid)
                                         : l2_warm<NT>(s.warm32, s.warm32_bytes, tid));
-  int4 st = s.steps[0];
+  int4 st = step_at(s, 0);
   Slots<T> pre;          // first pass of the next level/block step
   DenseRow<T, NT> preD;  // and its dense inverse entries if it is a block
   if (st.z != 2) {
@@ -663,10 +692,11 @@ __device__ __forceinline__ void sweep(const DevSweep AS4 &s, T *__restrict__ X,
       // the wave index is uniform in a wave: tell the compiler, so that the
       // walk's control flow and descriptors stay scalar
       const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), l64 = tid & 63;
-      const int32_t u0 = s.wdir[cur.x + wv], u1 = s.wdir[cur.x + wv + 1];
+      const int32_t AS4 *wd = (const int32_t AS4 *)s.wdir;
+      const int32_t u0 = wd[cur.x + wv], u1 = wd[cur.x + wv + 1];
       wave_walk_units<C, T, LDSX>(s, u0, u1, wv, l64, X, ss);
       if (k + 1 < ns) {
-        st = s.steps[k + 1];
+        st = step_at(s, k + 1);
         if (st.z != 2) {
           const Unit Un = unit_at(s, st.x);
           pre = load_slots<T>(s, Un, 0, tid);
@@ -681,7 +711,7 @@ __device__ __forceinline__ void sweep(const DevSweep AS4 &s, T *__restrict__ X,
     const Unit U = unit_at(s, cur.x);
     const bool block = cur.z == 1;
     if (k + 1 < ns) {
-      st = s.steps[k + 1];
+      st = step_at(s, k + 1);
       if (st.z != 2) {
         const Unit Un = unit_at(s, st.x);
         pre = load_slots<T>(s, Un, 0, tid);
@@ -718,6 +748,19 @@ __device__ __forceinline__ void pivot_scale(const T *__restrict__ d, T *__restri
 template <int C, int NT>
 __device__ __forceinline__ void spmul(const NetDesc AS4 &nd, const WorkItem &a, double *__restrict__ X,
                                       int32_t dir0, int tid) {
+  if (a.identity_from >= 0) {
+    // W = columns of the identity: B is a column of G_p, negated, and -0 in
+    // every other row (the values the row products give)
+    for (int32_t i = tid; i < nd.n_x * C; i += NT) X[i] = -0.0;
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      if (dir0 + c >= a.k) continue;
+      const int32_t q = a.identity_from + dir0 + c;
+      for (int32_t e = nd.gpt_ptr[q] + tid; e < nd.gpt_ptr[q + 1]; e += NT) X[nd.gpt_col[e] * C + c] = -nd.gpt_val[e];
+    }
+    return;
+  }
   for (int32_t i = tid; i < nd.n_x; i += NT) {
     double acc[C];
 #pragma unroll
@@ -733,72 +776,150 @@ __device__ __forceinline__ void spmul(const NetDesc AS4 &nd, const WorkItem &a, 
   }
 }
 
+// The projection records through buffer resources: uniform byte offsets in
+// scalar registers, the lane's offset in a vector register, and reads past
+// the end return 0 (slots past a pass's slot count read at kOffRange).
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+struct ProjBufs {
+  __amdgpu_buffer_rsrc_t bus, inc;
+  int32_t bus_plane, inc_plane;  // plane sizes in bytes
+};
+
+__device__ __forceinline__ f64x2 proj_word(__amdgpu_buffer_rsrc_t r, int voff, int32_t soff) {
+  return __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, __builtin_amdgcn_readfirstlane(soff), 0));
+}
+
+// Incidence slots e0 .. e0 + M - 1 of a lane in a projection pass.
+template <int NT, int M>
+__device__ __forceinline__ void proj_load_chunk(const ProjBufs &B, int2 pm, int32_t e0, int tid, f64x2 (&r0)[M],
+                                                f64x2 (&r1)[M], f64x2 (&r2)[M]) {
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    const int32_t at = e0 + j < pm.y ? (pm.x + (e0 + j) * NT) * 16 : kOffRange;
+    r0[j] = proj_word(B.inc, tid * 16, at);
+    r1[j] = proj_word(B.inc, tid * 16, at + B.inc_plane);
+    r2[j] = proj_word(B.inc, tid * 16, at + 2 * B.inc_plane);
+  }
+}
+
 // Tensor projection (Sec. 4.2) with the state tangent Z: the slack-cost
 // rank-one scalar, then per bus the branch second-order terms; the x part
-// goes negated into Yx, the p part into the output.  Ends with a barrier.
+// goes negated into Yx, the p part of the voltage parameters into the output
+// (the generator parameters' 2 c2 w term is added by spmuladd).  Ends with a
+// barrier.
 template <int C, int NT>
 __device__ __forceinline__ void projection(const NetDesc AS4 &nd, const WorkItem &a,
                                            const double *__restrict__ Z, double *__restrict__ Yx,
                                            double *s_slack, int32_t dir0, int tid) {
-  if (tid < C) {
-    const int c = tid;
-    double s = 0.0;
-    for (int32_t q = 0; q < nd.n_slack; ++q) {
-      const int32_t tx = nd.slack_thx[q], vs = nd.slack_vs[q];
-      const double dth = tx >= 0 ? Z[tx * C + c] : 0.0;
-      const double dv = vs >= 0 ? Z[vs * C + c] : w_at(a, -vs - 1, dir0 + c);
-      s += nd.slack_gth[q] * dth + nd.slack_gv[q] * dv;
+  // slack scalar: wave 0 evaluates 64 terms at a time, then every lane adds
+  // them in order (the same sum as a serial loop)
+  if (tid < 64) {
+    double s[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) s[c] = 0.0;
+    for (int32_t q0 = 0; q0 < nd.n_slack; q0 += 64) {
+      const int32_t q = q0 + tid;
+      double term[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) term[c] = 0.0;
+      if (q < nd.n_slack) {
+        const int32_t tx = nd.slack_thx[q], vs = nd.slack_vs[q];
+        const double gth = nd.slack_gth[q], gv = nd.slack_gv[q];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const double dth = tx >= 0 ? Z[tx * C + c] : 0.0;
+          const double dv = vs >= 0 ? Z[vs * C + c] : w_at(a, -vs - 1, dir0 + c);
+          term[c] = gth * dth + gv * dv;
+        }
+      }
+      const int32_t m = min(64, nd.n_slack - q0);
+      for (int32_t j = 0; j < m; ++j) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) s[c] += __shfl(term[c], j);
+      }
     }
-    s_slack[c] = s;
+    if (tid == 0) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) s_slack[c] = s[c];
+    }
   }
   __syncthreads();
-  for (int32_t e = tid; e < nd.n_bus; e += NT) {
-    const int32_t tx = nd.bus_thx[e], vs = nd.bus_vs[e];
-    const double ve = nd.bus_v[e], sth = nd.bus_sth[e], sv = nd.bus_sv[e];
+  double sl[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) sl[c] = s_slack[c];
+  constexpr int M = C == 1 ? 4 : 2;  // incidences whose loads are in flight together
+  const int32_t AS4 *passes = (const int32_t AS4 *)nd.proj_pass;  // scalar loads
+  ProjBufs B;
+  B.bus_plane = nd.n_proj_pass * NT * 16;
+  B.inc_plane = nd.proj_slots * 16;
+  B.bus = __builtin_amdgcn_make_buffer_rsrc((void *)nd.proj_bus, 0, 2 * B.bus_plane, kBufWord3);
+  B.inc = __builtin_amdgcn_make_buffer_rsrc((void *)nd.proj_inc, 0, 3 * B.inc_plane, kBufWord3);
+  int2 pm_next = make_int2(0, 0);
+  if (nd.n_proj_pass > 0) pm_next = make_int2(passes[0], passes[1]);
+  for (int32_t p = 0; p < nd.n_proj_pass; ++p) {
+    const int2 pm = pm_next;  // loaded a pass ahead
+    if (p + 1 < nd.n_proj_pass) pm_next = make_int2(passes[2 * p + 2], passes[2 * p + 3]);
+    // lanes past the last bus read padding records (tx = vs = -1, padded
+    // incidences) and store nothing: no divergent exit, so the pass index
+    // stays uniform
+    const bool act = p * NT + tid < nd.n_bus;
+    // every load of the bus and of its first M incidences is issued before
+    // any of them is used
+    const f64x2 b0 = proj_word(B.bus, tid * 16, p * NT * 16);
+    const f64x2 b1 = proj_word(B.bus, tid * 16, p * NT * 16 + B.bus_plane);
+    f64x2 r0[M], r1[M], r2[M];
+    proj_load_chunk<NT, M>(B, pm, 0, tid, r0, r1, r2);
+    const int32_t tx = __double2loint(b0.x), vs = __double2hiint(b0.x);
+    const double ve = b0.y, sth = b1.x, sv = b1.y;
     double dte[C], dve[C], yth[C], yv[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       dte[c] = tx >= 0 ? Z[tx * C + c] : 0.0;
       dve[c] = vs >= 0 ? Z[vs * C + c] : w_at(a, -vs - 1, dir0 + c);
-      yth[c] = sth * s_slack[c];
-      yv[c] = sv * s_slack[c];
+      yth[c] = sth * sl[c];
+      yv[c] = sv * sl[c];
     }
-    for (int32_t q = nd.inc_ptr[e]; q < nd.inc_ptr[e + 1]; ++q) {
-      const int32_t ot = nd.inc_othx[q], ov = nd.inc_ovs[q];
-      const double K = nd.inc_K[q], hps = nd.inc_Hps[q], H = nd.inc_H[q], A2 = nd.inc_A2[q];
-      const double vo = nd.inc_vo[q];
+    for (int32_t e0 = 0;;) {
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        const int32_t ot = __double2loint(r2[j].y), ov = __double2hiint(r2[j].y);
+        if (e0 + j >= pm.y || ot == kPadInc) continue;
+        const double K = r0[j].x, Hps = r0[j].y, H = r1[j].x, A2 = r1[j].y, vo = r2[j].x;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          const double dto = ot >= 0 ? Z[ot * C + c] : 0.0;
+          const double dvo = ov >= 0 ? Z[ov * C + c] : w_at(a, -ov - 1, dir0 + c);
+          const double dd = dte[c] - dto;
+          yth[c] += -K * dd + Hps * (vo * dve[c] + ve * dvo);
+          yv[c] += Hps * vo * dd + A2 * dve[c] + H * dvo;
+        }
+      }
+      e0 += M;
+      if (e0 >= pm.y) break;
+      proj_load_chunk<NT, M>(B, pm, e0, tid, r0, r1, r2);
+    }
+    if (act) {
 #pragma unroll
       for (int c = 0; c < C; ++c) {
-        const double dto = ot >= 0 ? Z[ot * C + c] : 0.0;
-        const double dvo = ov >= 0 ? Z[ov * C + c] : w_at(a, -ov - 1, dir0 + c);
-        const double dd = dte[c] - dto;
-        yth[c] += -K * dd + hps * (vo * dve[c] + ve * dvo);
-        yv[c] += hps * vo * dd + A2 * dve[c] + H * dvo;
+        if (tx >= 0) Yx[tx * C + c] = -yth[c];
+        if (vs >= 0)
+          Yx[vs * C + c] = -yv[c];
+        else if (dir0 + c < a.k)
+          a.HW[(int64_t)(dir0 + c) * a.ldhw + (-vs - 1)] = yv[c];
       }
     }
-#pragma unroll
-    for (int c = 0; c < C; ++c) {
-      if (tx >= 0) Yx[tx * C + c] = -yth[c];
-      if (vs >= 0)
-        Yx[vs * C + c] = -yv[c];
-      else if (dir0 + c < a.k)
-        a.HW[(int64_t)(dir0 + c) * a.ldhw + (-vs - 1)] = yv[c];
-    }
-  }
-  for (int32_t g = tid; g < nd.n_pg; g += NT) {
-    const int32_t q = nd.pg_idx[g];
-#pragma unroll
-    for (int c = 0; c < C; ++c)
-      if (dir0 + c < a.k) a.HW[(int64_t)(dir0 + c) * a.ldhw + q] = nd.pg_c2x2[g] * w_at(a, q, dir0 + c);
   }
   __syncthreads();
 }
 
-// SpMulAdd: H W += G_p^T Psi.
+// SpMulAdd: H W = Y_p + G_p^T Psi, Y_p of a generator parameter being its
+// 2 c2 w term and that of a voltage parameter the projection's output.
 template <int C, int NT>
 __device__ __forceinline__ void spmuladd(const NetDesc AS4 &nd, const WorkItem &a,
                                          const double *__restrict__ Psi, int32_t dir0, int tid) {
   for (int32_t q = tid; q < nd.n_p; q += NT) {
+    const double c2x2 = nd.p_c2x2[q];
     double acc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = 0.0;
@@ -809,9 +930,32 @@ __device__ __forceinline__ void spmuladd(const NetDesc AS4 &nd, const WorkItem &
       for (int c = 0; c < C; ++c) acc[c] = fma(v, Psi[j + c], acc[c]);
     }
 #pragma unroll
-    for (int c = 0; c < C; ++c)
-      if (dir0 + c < a.k) a.HW[(int64_t)(dir0 + c) * a.ldhw + q] += acc[c];
+    for (int c = 0; c < C; ++c) {
+      if (dir0 + c >= a.k) continue;
+      double *h = a.HW + (int64_t)(dir0 + c) * a.ldhw + q;
+      const double yp = __builtin_isnan(c2x2) ? *h : __dmul_rn(c2x2, w_at(a, q, dir0 + c));
+      *h = yp + acc[c];
+    }
   }
+}
+
+// dst[0 .. n) = src[0 .. n) with 16-byte accesses, eight per thread in flight
+// (src and dst 16-byte aligned).
+template <int NT>
+__device__ __forceinline__ void copy_to_lds(const double *__restrict__ src, double *__restrict__ dst, int32_t n,
+                                            int tid) {
+  const int32_t n2 = n / 2;
+  const double2 *s2 = reinterpret_cast<const double2 *>(src);
+  double2 *d2 = reinterpret_cast<double2 *>(dst);
+  for (int32_t b = 0; b < n2; b += 8 * NT) {
+    double2 v[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) v[m] = b + m * NT + tid < n2 ? s2[b + m * NT + tid] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int m = 0; m < 8; ++m)
+      if (b + m * NT + tid < n2) d2[b + m * NT + tid] = v[m];
+  }
+  if ((n & 1) && tid == 0) dst[n - 1] = src[n - 1];
 }
 
 template <int C, int NT, bool LDSX>
@@ -830,7 +974,8 @@ __device__ __forceinline__ void reduction(const NetDesc AS4 &nd, const WorkItem 
   sweep<C, NT, double, LDSX>(nd.L, X, s_r, tid, ss);
   pivot_scale<C, NT, double>(nd.pivinv, X, nd.n_x, tid);
   if (st) st[2] = wall_clock64();
-  sweep<C, NT, double, LDSX>(nd.U, X, s_r, tid, ss ? ss + kSweepStamps : nullptr);
+  sweep<C, NT, double, LDSX>(nd.U, X, s_r, tid, ss ? ss + kSweepStamps : nullptr, nd.proj_warm,
+                             nd.proj_warm_bytes);
   if (st) st[3] = wall_clock64();
   // 3. tensor projection: -Y_x into Yx, Y_p into the output
   projection<C, NT>(nd, a, X, Yx, s_slack, dir0, tid);
@@ -840,7 +985,7 @@ __device__ __forceinline__ void reduction(const NetDesc AS4 &nd, const WorkItem 
   // global memory the solve runs on Yx itself
   double *V = X;
   if constexpr (LDSX) {
-    for (int32_t i = tid; i < nd.n_x * C; i += NT) X[i] = Yx[i];
+    copy_to_lds<NT>(Yx, X, nd.n_x * C, tid);
     __syncthreads();
   } else {
     V = Yx;
@@ -848,7 +993,8 @@ __device__ __forceinline__ void reduction(const NetDesc AS4 &nd, const WorkItem 
   sweep<C, NT, double, LDSX>(nd.Ut, V, s_r, tid, ss ? ss + 2 * kSweepStamps : nullptr);
   pivot_scale<C, NT, double>(nd.pivinv, V, nd.n_x, tid);
   if (st) st[5] = wall_clock64();
-  sweep<C, NT, double, LDSX>(nd.Lt, V, s_r, tid, ss ? ss + 3 * kSweepStamps : nullptr);
+  sweep<C, NT, double, LDSX>(nd.Lt, V, s_r, tid, ss ? ss + 3 * kSweepStamps : nullptr, nd.gpt_warm,
+                             nd.gpt_warm_bytes);
   if (st) st[6] = wall_clock64();
   // 5. H W = Y_p + G_p^T Psi
   spmuladd<C, NT>(nd, a, V, dir0, tid);
@@ -889,7 +1035,8 @@ __device__ __forceinline__ void refined_solve(const NetDesc AS4 &nd, const doubl
     __syncthreads();
     sweep<C, NT, float, LDSX>(s1, X32, s_r, tid);
     pivot_scale<C, NT, float>(nd.pivinv32, X32, nd.n_x, tid);
-    sweep<C, NT, float, LDSX>(s2, X32, s_r, tid);
+    sweep<C, NT, float, LDSX>(s2, X32, s_r, tid, nullptr, TRANS ? nd.gpt_warm : nd.proj_warm,
+                              TRANS ? nd.gpt_warm_bytes : nd.proj_warm_bytes);
     for (int32_t i = tid; i < nd.n_x; i += NT) {
 #pragma unroll
       for (int c = 0; c < C; ++c)
@@ -1529,9 +1676,18 @@ rh_status device_upload(Network &net, std::string &err) {
       }
       tptr[q + 1] = (int32_t)tcol.size();
     }
-    UP(tptr, nd.gpt_ptr);
-    UP(tcol, nd.gpt_col);
-    UP(tval, nd.gpt_val);
+    std::vector<double> c2(net.n_p, std::numeric_limits<double>::quiet_NaN());
+    for (int32_t b : net.pv) c2[net.pg_p[b]] = 2.0 * net.c2[net.gen_of_bus[b]];
+    Blob bl;
+    const int64_t o_ptr = bl.add(tptr), o_col = bl.add(tcol), o_val = bl.add(tval), o_c2 = bl.add(c2);
+    const char *base = nullptr;
+    UP(bl.h, base);
+    nd.gpt_ptr = at_off<int32_t>(base, o_ptr);
+    nd.gpt_col = at_off<int32_t>(base, o_col);
+    nd.gpt_val = at_off<double>(base, o_val);
+    nd.p_c2x2 = at_off<double>(base, o_c2);
+    nd.gpt_warm = base;
+    nd.gpt_warm_bytes = (int64_t)bl.h.size();
   }
   // tangent sources per bus in permuted numbering: theta from X[thx] (-1 at
   // the reference bus); v from X[vs] at PQ buses, else from W[-vs - 1]
@@ -1540,27 +1696,76 @@ rh_status device_upload(Network &net, std::string &err) {
     thx[b] = net.th_x[b] >= 0 ? lu.iperm[net.th_x[b]] : -1;
     vs[b] = net.v_x[b] >= 0 ? lu.iperm[net.v_x[b]] : -net.v_p[b] - 1;
   }
-  UP(thx, nd.bus_thx);
-  UP(vs, nd.bus_vs);
   const Tape &tp = net.tape;
+  // tensor projection records: buses by decreasing degree (ties by index),
+  // kThreads per pass, incidences in tape order
   {
-    std::vector<int32_t> oth(tp.inc_other.size()), ovs(tp.inc_other.size());
-    for (size_t q = 0; q < tp.inc_other.size(); ++q) {
-      oth[q] = thx[tp.inc_other[q]];
-      ovs[q] = vs[tp.inc_other[q]];
+    const int32_t nb = net.n_bus;
+    std::vector<int32_t> order(nb);
+    for (int32_t b = 0; b < nb; ++b) order[b] = b;
+    auto deg = [&](int32_t b) { return tp.inc_ptr[b + 1] - tp.inc_ptr[b]; };
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return deg(x) > deg(y); });
+    const int32_t npass = (nb + kThreads - 1) / kThreads;
+    // the two int32 halves of a record word
+    auto bits = [](int32_t lo, int32_t hi) {
+      const uint64_t u = (uint64_t)(uint32_t)lo | ((uint64_t)(uint32_t)hi << 32);
+      double d;
+      std::memcpy(&d, &u, sizeof d);
+      return d;
+    };
+    std::vector<int2> pm(npass);
+    int64_t slots = 0;
+    for (int32_t p = 0; p < npass; ++p) {
+      const int32_t E = deg(order[p * kThreads]);
+      pm[p] = make_int2((int32_t)slots, E);
+      slots += (int64_t)E * kThreads;
+      if (slots * 3 * 16 >= kProjMaxBytes) {
+        err = "network too large for the projection records";
+        return RH_EINVAL;
+      }
     }
-    UP(oth, nd.inc_othx);
-    UP(ovs, nd.inc_ovs);
+    const size_t S = (size_t)slots;
+    const size_t NB = (size_t)npass * kThreads;  // bus planes padded to whole passes
+    if ((int64_t)NB * 2 * 16 >= kProjMaxBytes) {
+      err = "network too large for the projection records";
+      return RH_EINVAL;
+    }
+    std::vector<double> pb(4 * NB, 0.0), pi(6 * S, 0.0);  // double2 planes
+    for (size_t i = 0; i < NB; ++i) pb[2 * i] = bits(-1, -1);
+    for (size_t k = 0; k < S; ++k) pi[2 * (2 * S + k) + 1] = bits(kPadInc, 0);
+    for (int32_t p = 0; p < npass; ++p) {
+      const int32_t first = p * kThreads;
+      for (int32_t t = 0; t < kThreads && first + t < nb; ++t) {
+        const int32_t b = order[first + t];
+        const size_t i = (size_t)(first + t);
+        pb[2 * i] = bits(thx[b], vs[b]);
+        pb[2 * i + 1] = tp.bus_v[b];
+        pb[2 * (NB + i)] = tp.bus_sth[b];
+        pb[2 * (NB + i) + 1] = tp.bus_sv[b];
+        for (int32_t e = 0; e < deg(b); ++e) {
+          const int32_t q = tp.inc_ptr[b] + e, o = tp.inc_other[q];
+          const size_t k = (size_t)pm[p].x + (size_t)e * kThreads + t;
+          pi[2 * k] = tp.inc_K[q];
+          pi[2 * k + 1] = tp.inc_Hps[q];
+          pi[2 * (S + k)] = tp.inc_H[q];
+          pi[2 * (S + k) + 1] = tp.inc_A2[q];
+          pi[2 * (2 * S + k)] = tp.inc_vo[q];
+          pi[2 * (2 * S + k) + 1] = bits(thx[o], vs[o]);
+        }
+      }
+    }
+    nd.n_proj_pass = npass;
+    nd.proj_slots = (int32_t)S;
+    Blob bl;
+    const int64_t o_pass = bl.add(pm), o_bus = bl.add(pb), o_inc = bl.add(pi);
+    const char *base = nullptr;
+    UP(bl.h, base);
+    nd.proj_pass = at_off<int2>(base, o_pass);
+    nd.proj_bus = at_off<double2>(base, o_bus);
+    nd.proj_inc = at_off<double2>(base, o_inc);
+    nd.proj_warm = base;
+    nd.proj_warm_bytes = (int64_t)bl.h.size();
   }
-  UP(tp.inc_ptr, nd.inc_ptr);
-  UP(tp.inc_K, nd.inc_K);
-  UP(tp.inc_Hps, nd.inc_Hps);
-  UP(tp.inc_H, nd.inc_H);
-  UP(tp.inc_A2, nd.inc_A2);
-  UP(tp.inc_vo, nd.inc_vo);
-  UP(tp.bus_v, nd.bus_v);
-  UP(tp.bus_sth, nd.bus_sth);
-  UP(tp.bus_sv, nd.bus_sv);
   nd.n_slack = (int32_t)tp.slack_bus.size();
   {
     std::vector<int32_t> sth(tp.slack_bus.size()), svs(tp.slack_bus.size());
@@ -1573,17 +1778,6 @@ rh_status device_upload(Network &net, std::string &err) {
   }
   UP(tp.slack_gth, nd.slack_gth);
   UP(tp.slack_gv, nd.slack_gv);
-  {
-    std::vector<int32_t> idx;
-    std::vector<double> c2;
-    for (int32_t b : net.pv) {
-      idx.push_back(net.pg_p[b]);
-      c2.push_back(2.0 * net.c2[net.gen_of_bus[b]]);
-    }
-    nd.n_pg = (int32_t)idx.size();
-    UP(idx, nd.pg_idx);
-    UP(c2, nd.pg_c2x2);
-  }
   // G_x and G_x^T in permuted numbering (residuals of the refined mode)
   {
     const int32_t nx = net.n_x;
