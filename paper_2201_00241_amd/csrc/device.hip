@@ -153,12 +153,11 @@ struct LaunchArgs {
   double *scratch;
   int64_t scratch_stride;  // doubles per workgroup
   long long *stamps;       // kStamps wall-clock stamps per workgroup, or nullptr
-  long long *step_stamps;  // debug: workgroup 0 stamps sweep steps and wave units (4 x kSweepStamps)
+  long long *step_stamps;  // debug: workgroup 0 stamps the steps of its sweeps (4 x kSweepStamps)
 };
 
 constexpr int kMaxStepStamps = 128;
-constexpr int kUnitStamps = 64;  // per wave: the end of its first 64 units
-constexpr int kSweepStamps = kMaxStepStamps + kWaves * kUnitStamps;
+constexpr int kSweepStamps = kMaxStepStamps;
 
 constexpr int kStamps = 8;
 
@@ -199,50 +198,6 @@ __device__ __forceinline__ Unit unit_at(const DevSweep AS4 &s, int32_t u) {
 __device__ __forceinline__ int4 step_at(const DevSweep AS4 &s, int32_t k) {
   const int32_t AS4 *w = (const int32_t AS4 *)(s.steps + k);
   return make_int4(w[0], w[1], w[2], w[3]);
-}
-
-// A wave's units in a wave step, read without memory round trips per unit:
-// lane i of cw[q] holds the compact word of unit u0 + 64 q + i (compact =
-// rows | lg << 15 | assign << 18 | E << 19; groups = min(rows, 64 >> lg)),
-// loaded once when the wave step starts; the slot base and row-info base are
-// running sums, since a wave's units are packed one after the other.  Units
-// beyond 64 kTableWords read their compact word from memory.
-constexpr int kWaveAhead = 2;   // units whose slots a wave has in flight
-constexpr int kTableWords = 4;  // per-lane table registers (256 units)
-
-struct WaveWalk {
-  int32_t cw[kTableWords];
-  int32_t u0;
-};
-
-__device__ __forceinline__ WaveWalk wave_walk(const DevSweep AS4 &s, int32_t u0, int32_t u1, int l64) {
-  WaveWalk w;
-  w.u0 = u0;
-  const int32_t *units = reinterpret_cast<const int32_t *>(s.units);
-#pragma unroll
-  for (int q = 0; q < kTableWords; ++q) {
-    const int32_t u = u0 + 64 * q + l64;
-    w.cw[q] = u < u1 ? units[8 * (int64_t)u + 7] : 0;
-  }
-  // consume the table here, so that no later wait covers these loads
-  int32_t any = 0;
-#pragma unroll
-  for (int q = 0; q < kTableWords; ++q) any |= __builtin_amdgcn_readfirstlane(w.cw[q]);
-  asm volatile("" ::"s"(any));
-  return w;
-}
-
-__device__ __forceinline__ int32_t walk_word(const DevSweep AS4 &s, const WaveWalk &w, int32_t u) {
-  const int32_t i = u - w.u0;
-  if (i < 64 * kTableWords) {
-    const int32_t q = i >> 6, l = i & 63;
-    int32_t v = __builtin_amdgcn_readlane(w.cw[0], l);
-#pragma unroll
-    for (int qq = 1; qq < kTableWords; ++qq)
-      if (q == qq) v = __builtin_amdgcn_readlane(w.cw[qq], l);
-    return v;
-  }
-  return ((const int32_t AS4 *)s.units)[8 * (int64_t)u + 7];  // scalar load
 }
 
 // The unit with compact word cw at (slot_base, info_base).
@@ -573,80 +528,123 @@ __device__ __forceinline__ WSlots<T> wave_load(const WaveBufs &B, int32_t sb, in
   return L;
 }
 
+// A wave's walk through its units of a wave step.  Unit u0 + j runs at step
+// j while the slots of unit u0 + j + kWaveAhead are loaded, so a unit's
+// compact word is needed once, when its loads are issued, and travels with
+// its slots in the rotating buffer.  Lane i of table word q holds the compact
+// word of unit u0 + kWaveAhead + 64 q + i (0 past the wave's last unit: an
+// empty unit, with no lanes, that loads and writes nothing); the walk reads
+// it by readlane with the step's index in its chunk of 64 steps and shifts
+// the table by one word per chunk, so no per-unit branch picks the word and
+// no per-unit memory access reads it.  Slot and row-info bases are running
+// sums, since a wave's units are packed one after the other.  Scalar
+// instructions are the walk's bottleneck (one scalar unit serves all waves of
+// a CU), so the per-unit work is kept to one decode and a few additions.
+constexpr int kWaveAhead = 2;   // units whose slots a wave has in flight
+constexpr int kTableWords = 4;  // per-lane table registers (256 units)
+
+template <class T>
+struct WRing {
+  WSlots<T> L;
+  int32_t cw;  // the unit's compact word
+};
+
+// Issue the loads of the unit with compact word cw at the running bases (sb,
+// ib), which it then advances past the unit.
+template <class T>
+__device__ __forceinline__ void ring_load(const WaveBufs &B, int32_t cw, int32_t &sb, int32_t &ib, int l64,
+                                          WRing<T> &R) {
+  const Unit U = unit_of(cw, sb, ib);
+  R.L = wave_load<T>(B, sb, ib, U.lanes, U.lg, l64);
+  R.cw = cw;
+  sb += U.E * U.lanes;  // wave units have one pass
+  ib += U.rows;
+}
+
 template <int C, class T, bool LDSX>
-__device__ __forceinline__ void wave_walk_units(const DevSweep AS4 &s, int32_t u0, int32_t u1, int wv, int l64,
-                                                T *__restrict__ X, long long *ss) {
-  const WaveWalk walk = wave_walk(s, u0, u1, l64);
+__device__ __forceinline__ void wave_walk_units(const DevSweep AS4 &s, int32_t u0, int32_t u1, int l64,
+                                                T *__restrict__ X) {
+  const int32_t n = u1 - u0;
+  if (n <= 0) return;
+  const int32_t *units = reinterpret_cast<const int32_t *>(s.units);
+  int32_t tab[kTableWords];
+#pragma unroll
+  for (int q = 0; q < kTableWords; ++q) {
+    const int32_t u = u0 + kWaveAhead + 64 * q + l64;
+    tab[q] = u < u1 ? units[8 * (int64_t)u + 7] : 0;
+  }
+  {
+    // consume the table here, so that no later wait covers these loads
+    int32_t any = 0;
+#pragma unroll
+    for (int q = 0; q < kTableWords; ++q) any |= __builtin_amdgcn_readfirstlane(tab[q]);
+    asm volatile("" ::"s"(any));
+  }
   const WaveBufs B = wave_bufs<T>(s);
-  int32_t sb_cur = 0, ib_cur = 0;  // bases of unit u
-  if (u0 < u1) {
-    const int32_t AS4 *h = (const int32_t AS4 *)s.units + 8 * (int64_t)u0;
-    sb_cur = h[0];
-    ib_cur = h[1];
-  }
-  int32_t sb_pre = sb_cur, ib_pre = ib_cur;  // bases of the next unit to load
-  WSlots<T> ring[kWaveAhead];
+  const int32_t AS4 *hu = (const int32_t AS4 *)s.units;  // scalar loads
+  int32_t sb_cur = hu[8 * (int64_t)u0];                   // slot base of the running unit
+  int32_t sb_pre = sb_cur, ib_pre = hu[8 * (int64_t)u0 + 1];  // bases of the next unit to load
+  WRing<T> ring[kWaveAhead];
 #pragma unroll
-  for (int d = 0; d < kWaveAhead; ++d) {
-    const Unit Up = unit_of(u0 + d < u1 ? walk_word(s, walk, u0 + d) : 0, sb_pre, ib_pre);
-    ring[d] = wave_load<T>(B, sb_pre, ib_pre, Up.lanes, Up.lg, l64);
-    sb_pre += Up.E * Up.lanes;  // wave units have one pass
-    ib_pre += Up.rows;
-  }
+  for (int d = 0; d < kWaveAhead; ++d)
+    ring_load<T>(B, d < n ? hu[8 * (int64_t)(u0 + d) + 7] : 0, sb_pre, ib_pre, l64, ring[d]);
   const T *val = sw_val<T>(s);
-  // every unrolled step runs (a step past the end is an empty unit), so the
-  // same loads are in flight on every path through the loop
-  for (int32_t u = u0; u < u1; u += kWaveAhead) {
+  for (int32_t c0 = 0; c0 < n; c0 += 64) {
+    // every unrolled step runs (a step past the end is an empty unit), so the
+    // same loads are in flight on every path through the loop
+    for (int32_t i = 0; i < 64 && c0 + i < n; i += kWaveAhead) {
 #pragma unroll
-    for (int d = 0; d < kWaveAhead; ++d) {
-      const int32_t uu = u + d;
-      const Unit U = unit_of(uu < u1 ? walk_word(s, walk, uu) : 0, sb_cur, ib_cur);
-      const WSlots<T> &L = ring[d];
-      // gathers: the kWavePre entries and the row's own value
-      T xv[kWavePre][C], xr[C];
+      for (int d = 0; d < kWaveAhead; ++d) {
+        const WSlots<T> &L = ring[d].L;
+        const Unit U = unit_of(ring[d].cw, sb_cur, 0);
+        // gathers: the kWavePre entries and the row's own value
+        T xv[kWavePre][C], xr[C];
 #pragma unroll
-      for (int e = 0; e < kWavePre; ++e)
+        for (int e = 0; e < kWavePre; ++e)
 #pragma unroll
-        for (int c = 0; c < C; ++c) xv[e][c] = X[L.col[e] * C + c];
-      const int32_t row = L.row;
+          for (int c = 0; c < C; ++c) xv[e][c] = X[L.col[e] * C + c];
+        const int32_t row = L.row;
 #pragma unroll
-      for (int c = 0; c < C; ++c) xr[c] = X[row * C + c];
-      T part[C];
+        for (int c = 0; c < C; ++c) xr[c] = X[row * C + c];
+        T part[C];
 #pragma unroll
-      for (int c = 0; c < C; ++c) part[c] = T(0);
+        for (int c = 0; c < C; ++c) part[c] = T(0);
 #pragma unroll
-      for (int e = 0; e < kWavePre; ++e)
+        for (int e = 0; e < kWavePre; ++e)
 #pragma unroll
-        for (int c = 0; c < C; ++c) part[c] = fma(L.val[e], xv[e][c], part[c]);
-      {
-        const Unit Up = unit_of(uu + kWaveAhead < u1 ? walk_word(s, walk, uu + kWaveAhead) : 0, sb_pre, ib_pre);
-        ring[d] = wave_load<T>(B, sb_pre, ib_pre, Up.lanes, Up.lg, l64);
-        sb_pre += Up.E * Up.lanes;
-        ib_pre += Up.rows;
-      }
-      // rows longer than 64 kWavePre entries (rare): the remaining slots
-      for (int32_t e0 = kWavePre; e0 < U.E; e0 += 4) {
+          for (int c = 0; c < C; ++c) part[c] = fma(L.val[e], xv[e][c], part[c]);
+        ring_load<T>(B, __builtin_amdgcn_readlane(tab[0], i + d), sb_pre, ib_pre, l64, ring[d]);
+        // rows longer than 64 kWavePre entries (rare): the remaining slots
+        for (int32_t e0 = kWavePre; e0 < U.E; e0 += 4) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const bool ok = e0 + e < U.E;
-          const int64_t at = (int64_t)U.slot_base + (int64_t)(ok ? e0 + e : 0) * U.lanes + l64;
-          const T v = val[at];
-          const int32_t j = s.scol[at];
+          for (int e = 0; e < 4; ++e) {
+            const bool ok = e0 + e < U.E;
+            const int64_t at = (int64_t)U.slot_base + (int64_t)(ok ? e0 + e : 0) * U.lanes + l64;
+            const T v = val[at];
+            const int32_t j = s.scol[at];
 #pragma unroll
-          for (int c = 0; c < C; ++c) part[c] = fma(ok ? v : T(0), X[j * C + c], part[c]);
+            for (int c = 0; c < C; ++c) part[c] = fma(ok ? v : T(0), X[j * C + c], part[c]);
+          }
         }
-      }
 #pragma unroll
-      for (int c = 0; c < C; ++c) part[c] = group_sum(part[c], U.lg);
-      if ((l64 & ((1 << U.lg) - 1)) == 0 && l64 < U.lanes) {
+        for (int c = 0; c < C; ++c) part[c] = group_sum(part[c], U.lg);
+        if ((l64 & ((1 << U.lg) - 1)) == 0 && l64 < U.lanes) {
 #pragma unroll
-        for (int c = 0; c < C; ++c) X[row * C + c] = U.assign ? part[c] : xr[c] - part[c];
+          for (int c = 0; c < C; ++c) X[row * C + c] = U.assign ? part[c] : xr[c] - part[c];
+        }
+        wave_sync<LDSX>();  // this wave's writes before its next unit's reads
+        sb_cur += U.E * U.lanes;
       }
-      wave_sync<LDSX>();  // this wave's writes before its next unit's reads
-      if (ss && l64 == 0 && uu < u1 && uu - u0 < kUnitStamps)
-        ss[kMaxStepStamps + wv * kUnitStamps + (uu - u0)] = wall_clock64();
-      sb_cur += U.E * U.lanes;
-      ib_cur += U.rows;
+    }
+    // next chunk: shift the table (a wave with more than 64 kTableWords
+    // units reads further words here)
+#pragma unroll
+    for (int q = 0; q + 1 < kTableWords; ++q) tab[q] = tab[q + 1];
+    tab[kTableWords - 1] = 0;
+    if (c0 + 64 * kTableWords + kWaveAhead < n) {
+      const int32_t u = u0 + kWaveAhead + c0 + 64 * kTableWords + l64;
+      tab[kTableWords - 1] = u < u1 ? units[8 * (int64_t)u + 7] : 0;
+      asm volatile("" ::"s"(__builtin_amdgcn_readfirstlane(tab[kTableWords - 1])));
     }
   }
 }
@@ -684,17 +682,14 @@ __device__ __forceinline__ void sweep(const DevSweep AS4 &s, T *__restrict__ X,
     const Slots<T> first = pre;
     const DenseRow<T, NT> dense = preD;
     if (cur.z == 2) {
-      // wave step: the wave's units in order.  The wave keeps the compact
-      // descriptors of up to 64 of its units in a per-lane table (read by
-      // readlane, no scalar memory round trip per unit) and loads each
-      // unit's slots kWaveAhead units ahead; the next step's prefetch is
-      // issued once the wave is done.
+      // wave step: the wave's units in order (see wave_walk_units); the next
+      // step's prefetch is issued once the wave is done.
       // the wave index is uniform in a wave: tell the compiler, so that the
       // walk's control flow and descriptors stay scalar
       const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), l64 = tid & 63;
       const int32_t AS4 *wd = (const int32_t AS4 *)s.wdir;
       const int32_t u0 = wd[cur.x + wv], u1 = wd[cur.x + wv + 1];
-      wave_walk_units<C, T, LDSX>(s, u0, u1, wv, l64, X, ss);
+      wave_walk_units<C, T, LDSX>(s, u0, u1, l64, X);
       if (k + 1 < ns) {
         st = step_at(s, k + 1);
         if (st.z != 2) {
@@ -1228,32 +1223,7 @@ rh_status runner_collect(Runner &r, const DeviceInfo &info, rh_report &rep, std:
     for (int w = 0; w < 4; ++w) {
       const long long *S = st.data() + (size_t)w * kSweepStamps;
       fprintf(stderr, "steps %s (us):", nm[w]);
-      int wave_k = -1;
-      for (int k = 1; k < kMaxStepStamps && S[k] != 0; ++k) {
-        fprintf(stderr, " %.2f", (S[k] - S[k - 1]) * us);
-        // a wave step's units stamp inside (S[k-1], S[k]]
-        for (int v = 0; v < kWaves && wave_k < 0; ++v)
-          if (S[kMaxStepStamps + v * kUnitStamps] > S[k - 1] && S[kMaxStepStamps + v * kUnitStamps] <= S[k])
-            wave_k = k;
-      }
-      fprintf(stderr, "\n");
-      if (wave_k < 0) continue;
-      // the wave that finished last: its unit durations
-      int last = 0;
-      long long end_last = 0;
-      for (int v = 0; v < kWaves; ++v) {
-        long long e = 0;
-        for (int u = 0; u < kUnitStamps; ++u) e = std::max(e, S[kMaxStepStamps + v * kUnitStamps + u]);
-        if (e > end_last) { end_last = e; last = v; }
-      }
-      fprintf(stderr, "units %s wave %d (us):", nm[w], last);
-      long long prev = S[wave_k - 1];
-      for (int u = 0; u < kUnitStamps; ++u) {
-        const long long t = S[kMaxStepStamps + last * kUnitStamps + u];
-        if (t == 0) break;
-        fprintf(stderr, " %.2f", (t - prev) * us);
-        prev = t;
-      }
+      for (int k = 1; k < kMaxStepStamps && S[k] != 0; ++k) fprintf(stderr, " %.2f", (S[k] - S[k - 1]) * us);
       fprintf(stderr, "\n");
     }
     r.step_stamps_pending = false;
