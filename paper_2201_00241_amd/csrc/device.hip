@@ -451,17 +451,13 @@ __device__ __forceinline__ void wave_sync() {
   }
 }
 
-// One wave's walk through its units of a wave step.  Every wave unit has one
-// pass and at least kPre slots per lane (kPre exactly, except for rows longer
-// than 64 kPre entries), its lanes are rows << lg, and the slot and row arrays
-// end with a zero tail, so each lane loads its kPre slots and its row index
-// from a uniform base plus its lane offset, with no per-lane bounds tests:
-// lanes past the unit's rows read the next unit's data (or the tail) and form
-// whole lane groups whose sums are never written.  Units are loaded
-// kWaveAhead ahead into rotating buffers (the loop is unrolled over them, so no
-// buffer with loads in flight is copied), and the loads are issued on every
-// iteration (past the end, from the tail) so that the number in flight is the
-// same on every path.
+// Slots of a wave unit: every wave unit has one pass and an even number of
+// slots per lane, kWavePre except for rows longer than 64 kWavePre entries;
+// its lanes are groups << lg (whole lane groups), and a lane's slots are
+// stored in pairs (see Packed), so each lane loads its first kWavePre slots
+// and its row index with four accesses from a uniform base plus its lane
+// offset.  Lanes past the unit's rows read nothing (out-of-range offsets,
+// see kOffRange) and form whole lane groups whose sums are never written.
 constexpr int kWavePre = kSlotsAhead;  // slots per lane of a wave unit
 
 template <class T>
@@ -508,22 +504,48 @@ __device__ __forceinline__ float buf_load_val<float>(__amdgpu_buffer_rsrc_t r, i
 // gathers all hit one LDS word.
 constexpr int kOffRange = 0x40000000;
 
+// Two values of a lane's slot pair with one access.
+template <class T>
+__device__ __forceinline__ void buf_load_pair(__amdgpu_buffer_rsrc_t r, int voff, int soff, T &a, T &b);
+template <>
+__device__ __forceinline__ void buf_load_pair<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff, double &a,
+                                                      double &b) {
+  typedef double f64x2_t __attribute__((ext_vector_type(2)));
+  const f64x2_t v = __builtin_bit_cast(f64x2_t, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+  a = v.x;
+  b = v.y;
+}
+template <>
+__device__ __forceinline__ void buf_load_pair<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff, float &a,
+                                                     float &b) {
+  typedef float f32x2_t __attribute__((ext_vector_type(2)));
+  const f32x2_t v = __builtin_bit_cast(f32x2_t, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  a = v.x;
+  b = v.y;
+}
+
+// A wave unit's first two slot pairs and the row of each lane: pair p of the
+// unit's lanes starts at slot sb + 2 p lanes, lane l's pair at 2 l within it.
 template <class T>
 __device__ __forceinline__ WSlots<T> wave_load(const WaveBufs &B, int32_t sb, int32_t ib, int32_t lanes, int32_t lg,
                                                int l64) {
+  static_assert(kWavePre == 4, "two slot pairs per lane");
   WSlots<T> L;
   const bool act = l64 < lanes;
-  const int vc = act ? l64 * 4 : kOffRange;
-  const int vv = act ? l64 * (int)sizeof(T) : kOffRange;
+  const int vc = act ? l64 * 8 : kOffRange;
+  const int vv = act ? l64 * 2 * (int)sizeof(T) : kOffRange;
   const int vr = act ? (l64 >> lg) * 4 : kOffRange;
-#pragma unroll
-  for (int e = 0; e < kWavePre; ++e) {
-    // uniform offsets: say so, or the compiler may keep them in vector
-    // registers and loop over their distinct values
-    const int32_t at = __builtin_amdgcn_readfirstlane(sb + e * lanes);
-    L.col[e] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(B.col, vc, at * 4, 0);
-    L.val[e] = buf_load_val<T>(B.val, vv, at * (int)sizeof(T));
-  }
+  // uniform offsets: say so, or the compiler may keep them in vector
+  // registers and loop over their distinct values
+  const int32_t s0 = __builtin_amdgcn_readfirstlane(sb), s1 = __builtin_amdgcn_readfirstlane(sb + 2 * lanes);
+  const u32x2 c0 = __builtin_amdgcn_raw_buffer_load_b64(B.col, vc, s0 * 4, 0);
+  const u32x2 c1 = __builtin_amdgcn_raw_buffer_load_b64(B.col, vc, s1 * 4, 0);
+  buf_load_pair<T>(B.val, vv, s0 * (int)sizeof(T), L.val[0], L.val[1]);
+  buf_load_pair<T>(B.val, vv, s1 * (int)sizeof(T), L.val[2], L.val[3]);
+  L.col[0] = (int32_t)c0.x;
+  L.col[1] = (int32_t)c0.y;
+  L.col[2] = (int32_t)c1.x;
+  L.col[3] = (int32_t)c1.y;
   L.row = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(B.row, vr, __builtin_amdgcn_readfirstlane(ib) * 4, 0);
   return L;
 }
@@ -614,16 +636,18 @@ __device__ __forceinline__ void wave_walk_units(const DevSweep AS4 &s, int32_t u
 #pragma unroll
           for (int c = 0; c < C; ++c) part[c] = fma(L.val[e], xv[e][c], part[c]);
         ring_load<T>(B, __builtin_amdgcn_readlane(tab[0], i + d), sb_pre, ib_pre, l64, ring[d]);
-        // rows longer than 64 kWavePre entries (rare): the remaining slots
+        // rows longer than 64 kWavePre entries (rare): the remaining slot
+        // pairs, two at a time
         for (int32_t e0 = kWavePre; e0 < U.E; e0 += 4) {
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            const bool ok = e0 + e < U.E;
-            const int64_t at = (int64_t)U.slot_base + (int64_t)(ok ? e0 + e : 0) * U.lanes + l64;
+            const bool ok = e0 + e < U.E && l64 < U.lanes;
+            const int64_t at =
+                ok ? (int64_t)U.slot_base + (int64_t)((e0 + e) >> 1) * 2 * U.lanes + 2 * l64 + (e & 1) : 0;
             const T v = val[at];
             const int32_t j = s.scol[at];
 #pragma unroll
-            for (int c = 0; c < C; ++c) part[c] = fma(ok ? v : T(0), X[j * C + c], part[c]);
+            for (int c = 0; c < C; ++c) part[c] = fma(v, X[j * C + c], part[c]);
           }
         }
 #pragma unroll

@@ -618,15 +618,17 @@ namespace {
 
 // One unit: rows at positions [b, b + rows) of sc.s with lane groups of 2^lg.
 int32_t pack_unit(const Schedule &sc, int32_t b, int32_t rows, int lg, int max_lanes, int assign, int32_t min_E,
-                  Packed &pk) {
+                  bool wave, Packed &pk) {
   const Sweep &s = sc.s;
   const int32_t w = 1 << lg;
   const int32_t groups = std::max<int32_t>(1, std::min<int32_t>(rows, max_lanes / w));
   const int32_t lanes = groups * w;
   const int32_t passes = rows > 0 ? (rows + groups - 1) / groups : 0;
+  if (wave && passes > 1) throw std::runtime_error("internal: a wave unit has one pass");
   int32_t longest = 0;
   for (int32_t r = 0; r < rows; ++r) longest = std::max(longest, s.ptr[b + r + 1] - s.ptr[b + r]);
-  const int32_t E = std::max(min_E, (longest + w - 1) / w);
+  const int32_t E0 = std::max(min_E, (longest + w - 1) / w);
+  const int32_t E = wave ? (E0 + 1) & ~1 : E0;  // wave units: whole slot pairs
   const int32_t slot_base = (int32_t)pk.scol.size(), info_base = (int32_t)pk.irow.size();
   pk.scol.resize(pk.scol.size() + (size_t)passes * E * lanes, 0);
   pk.sval.resize(pk.sval.size() + (size_t)passes * E * lanes, 0.0);
@@ -637,7 +639,9 @@ int32_t pack_unit(const Schedule &sc, int32_t b, int32_t rows, int lg, int max_l
       for (int32_t e = 0; e < E; ++e) {
         const int32_t q = j + e * w;
         if (q >= len) continue;
-        const size_t at = (size_t)slot_base + ((size_t)p * E + e) * lanes + (size_t)g * w + j;
+        const size_t lane = (size_t)g * w + j;
+        const size_t at = wave ? (size_t)slot_base + (size_t)(e >> 1) * 2 * lanes + 2 * lane + (e & 1)
+                               : (size_t)slot_base + ((size_t)p * E + e) * lanes + lane;
         pk.scol[at] = s.col[q0 + q];
         pk.sval[at] = s.val[q0 + q];
       }
@@ -646,8 +650,7 @@ int32_t pack_unit(const Schedule &sc, int32_t b, int32_t rows, int lg, int max_l
   }
   const int32_t u = (int32_t)(pk.units.size() / 8);
   // compact form for the per-lane unit tables of wave steps (64 lanes)
-  const int32_t compact =
-      (max_lanes == 64 && rows < (1 << 15) && E < (1 << 13)) ? (rows | lg << 15 | assign << 18 | E << 19) : -1;
+  const int32_t compact = !wave ? -1 : (rows < (1 << 15) && E < (1 << 13)) ? (rows | lg << 15 | assign << 18 | E << 19) : -2;
   pk.units.insert(pk.units.end(), {slot_base, info_base, rows, groups, lg, E, lanes, compact});
   return u;
 }
@@ -688,14 +691,14 @@ Packed pack_schedule(const Schedule &sc, int lanes) {
           // one pass, padded to kSlotsAhead slots per lane (the kernel's
           // fixed-shape fast path)
           for (int32_t r0 = 0; r0 < rows; r0 += per)
-            if (pk.units[8 * pack_unit(sc, b + r0, std::min(per, rows - r0), lg, 64, assign, kSlotsAhead, pk) + 7] < 0)
+            if (pk.units[8 * pack_unit(sc, b + r0, std::min(per, rows - r0), lg, 64, assign, kSlotsAhead, true, pk) + 7] < 0)
               throw std::runtime_error("wave level too large for the compact unit form");
         }
       }
       pk.wdir.push_back((int32_t)(pk.units.size() / 8));
       pk.steps.insert(pk.steps.end(), {off, 0, 2, 0});
     } else {
-      const int32_t u = pack_unit(sc, b, rows, lg, lanes, 0, 0, pk);
+      const int32_t u = pack_unit(sc, b, rows, lg, lanes, 0, 0, false, pk);
       pk.steps.insert(pk.steps.end(), {u, 0, kind >= 0 ? 1 : 0, kind >= 0 ? kind + 1 : 0});
     }
   }
