@@ -451,12 +451,12 @@ __device__ __forceinline__ void wave_sync() {
   }
 }
 
-// Slots of a wave unit: every wave unit has one pass and an even number of
+// Slots of a wave unit: every wave unit has one pass and a multiple of four
 // slots per lane, kWavePre except for rows longer than 64 kWavePre entries;
-// its lanes are groups << lg (whole lane groups), and a lane's slots are
-// stored in pairs (see Packed), so each lane loads its first kWavePre slots
-// and its row index with four accesses from a uniform base plus its lane
-// offset.  Lanes past the unit's rows read nothing (out-of-range offsets,
+// its lanes are groups << lg (whole lane groups), and a lane's columns are
+// stored in quads and its values in pairs (see Packed), so each lane loads
+// its first kWavePre slots and its row index with four accesses from a
+// uniform base plus its lane offset.  Lanes past the unit's rows read nothing (out-of-range offsets,
 // see kOffRange) and form whole lane groups whose sums are never written.
 constexpr int kWavePre = kSlotsAhead;  // slots per lane of a wave unit
 
@@ -486,7 +486,7 @@ __device__ __forceinline__ WaveBufs wave_bufs(const DevSweep AS4 &s) {
   return b;
 }
 
-typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 template <class T>
 __device__ __forceinline__ T buf_load_val(__amdgpu_buffer_rsrc_t r, int voff, int soff);
@@ -524,28 +524,28 @@ __device__ __forceinline__ void buf_load_pair<float>(__amdgpu_buffer_rsrc_t r, i
   b = v.y;
 }
 
-// A wave unit's first two slot pairs and the row of each lane: pair p of the
-// unit's lanes starts at slot sb + 2 p lanes, lane l's pair at 2 l within it.
+// A wave unit's first kWavePre slots and the row of each lane: the lane's
+// first column quad at sb + 4 l, its value pairs at sb + 2 l and
+// sb + 2 lanes + 2 l (see Packed).
 template <class T>
 __device__ __forceinline__ WSlots<T> wave_load(const WaveBufs &B, int32_t sb, int32_t ib, int32_t lanes, int32_t lg,
                                                int l64) {
   static_assert(kWavePre == 4, "two slot pairs per lane");
   WSlots<T> L;
   const bool act = l64 < lanes;
-  const int vc = act ? l64 * 8 : kOffRange;
+  const int vc = act ? l64 * 16 : kOffRange;
   const int vv = act ? l64 * 2 * (int)sizeof(T) : kOffRange;
   const int vr = act ? (l64 >> lg) * 4 : kOffRange;
   // uniform offsets: say so, or the compiler may keep them in vector
   // registers and loop over their distinct values
   const int32_t s0 = __builtin_amdgcn_readfirstlane(sb), s1 = __builtin_amdgcn_readfirstlane(sb + 2 * lanes);
-  const u32x2 c0 = __builtin_amdgcn_raw_buffer_load_b64(B.col, vc, s0 * 4, 0);
-  const u32x2 c1 = __builtin_amdgcn_raw_buffer_load_b64(B.col, vc, s1 * 4, 0);
+  const u32x4 c = __builtin_amdgcn_raw_buffer_load_b128(B.col, vc, s0 * 4, 0);
   buf_load_pair<T>(B.val, vv, s0 * (int)sizeof(T), L.val[0], L.val[1]);
   buf_load_pair<T>(B.val, vv, s1 * (int)sizeof(T), L.val[2], L.val[3]);
-  L.col[0] = (int32_t)c0.x;
-  L.col[1] = (int32_t)c0.y;
-  L.col[2] = (int32_t)c1.x;
-  L.col[3] = (int32_t)c1.y;
+  L.col[0] = (int32_t)c.x;
+  L.col[1] = (int32_t)c.y;
+  L.col[2] = (int32_t)c.z;
+  L.col[3] = (int32_t)c.w;
   L.row = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(B.row, vr, __builtin_amdgcn_readfirstlane(ib) * 4, 0);
   return L;
 }
@@ -636,16 +636,17 @@ __device__ __forceinline__ void wave_walk_units(const DevSweep AS4 &s, int32_t u
 #pragma unroll
           for (int c = 0; c < C; ++c) part[c] = fma(L.val[e], xv[e][c], part[c]);
         ring_load<T>(B, __builtin_amdgcn_readlane(tab[0], i + d), sb_pre, ib_pre, l64, ring[d]);
-        // rows longer than 64 kWavePre entries (rare): the remaining slot
-        // pairs, two at a time
+        // rows longer than 64 kWavePre entries (rare): the remaining slots,
+        // a column quad at a time
         for (int32_t e0 = kWavePre; e0 < U.E; e0 += 4) {
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            const bool ok = e0 + e < U.E && l64 < U.lanes;
-            const int64_t at =
+            const bool ok = l64 < U.lanes;
+            const int64_t ac = ok ? (int64_t)U.slot_base + (int64_t)(e0 >> 2) * 4 * U.lanes + 4 * l64 + e : 0;
+            const int64_t av =
                 ok ? (int64_t)U.slot_base + (int64_t)((e0 + e) >> 1) * 2 * U.lanes + 2 * l64 + (e & 1) : 0;
-            const T v = val[at];
-            const int32_t j = s.scol[at];
+            const T v = val[av];
+            const int32_t j = s.scol[ac];
 #pragma unroll
             for (int c = 0; c < C; ++c) part[c] = fma(v, X[j * C + c], part[c]);
           }

@@ -71,10 +71,12 @@ constexpr int32_t kWaveBlockRows = 16;
 // j of a group holds entries j, j + 2^lg, ... of its row, `E` slots per lane
 // and pass, padded with (column 0, value 0).  Slot (pass, e, lane) sits at
 // slot_base + (pass * E + e) * lanes + lane, so a lane needs no row pointer.
-// Wave-step units have one pass and an even E, and keep a lane's slots in
-// pairs: slot (e, lane) sits at slot_base + (e >> 1) * 2 lanes + 2 lane +
-// (e & 1), so a lane reads two columns, or two values, with one access, and
-// the pairs of a unit's lanes are contiguous.
+// Wave-step units have one pass and E a multiple of 4, and keep a lane's
+// columns in quads and its values in pairs: the column of slot (e, lane)
+// sits at slot_base + (e >> 2) * 4 lanes + 4 lane + (e & 3), its value at
+// slot_base + (e >> 1) * 2 lanes + 2 lane + (e & 1), so a lane reads four
+// columns, or two values, with one access, and the quads (pairs) of a unit's
+// lanes are contiguous.
 // units: 8 ints each {slot_base, info_base, rows, groups, lg, E, lanes,
 // compact}; for wave-step units compact = rows | lg << 15 | assign << 18 |
 // E << 19 (their groups = min(rows, 64 >> lg)), else -1.  An assigning unit

@@ -124,7 +124,7 @@ static bool check_wave_walk(const Packed &pk) {
         const int groups = std::max(1, std::min(rows, 64 >> lg)), lanes = groups << lg;
         if (U[0] != sb || U[1] != ib || U[2] != rows || U[3] != groups || U[4] != lg || U[5] != E || U[6] != lanes)
           return false;
-        if (E % 2 != 0 || rows > groups) return false;  // slot pairs, one pass
+        if (E % 4 != 0 || rows > groups) return false;  // column quads, one pass
         const int passes = (rows + (64 >> lg) - 1) >> (6 - lg);
         if (passes != (rows + groups - 1) / groups && rows > 0) return false;
         if (sb + (long)passes * E * lanes > (long)pk.scol.size() || ib + rows > (long)pk.irow.size()) return false;
@@ -154,11 +154,14 @@ static void emulate_packed(const Packed &pk, std::vector<double> &X, std::vector
         const int row = p * groups + lane / w;
         if (row >= rows) continue;
         for (int e = 0; e < E; ++e) {
-          // wave units (compact word present) keep a lane's slots in pairs
-          const size_t at = U[7] >= 0 ? (size_t)slot_base + (size_t)(e / 2) * 2 * lanes + 2 * (size_t)lane + e % 2
-                                      : (size_t)slot_base + ((size_t)p * E + e) * lanes + lane;
-          if (pk.sval[at] != 0.0 && pending[pk.scol[at]]) ok = false;
-          part[row] += pk.sval[at] * X[pk.scol[at]];
+          // wave units (compact word present) keep a lane's columns in quads
+          // and its values in pairs
+          const bool wv = U[7] >= 0;
+          const size_t at = (size_t)slot_base + ((size_t)p * E + e) * lanes + lane;
+          const size_t ac = wv ? (size_t)slot_base + (size_t)(e / 4) * 4 * lanes + 4 * (size_t)lane + e % 4 : at;
+          const size_t av = wv ? (size_t)slot_base + (size_t)(e / 2) * 2 * lanes + 2 * (size_t)lane + e % 2 : at;
+          if (pk.sval[av] != 0.0 && pending[pk.scol[ac]]) ok = false;
+          part[row] += pk.sval[av] * X[pk.scol[ac]];
         }
       }
     for (int a = 0; a < rows; ++a) {
