@@ -200,11 +200,13 @@ __device__ __forceinline__ int4 step_at(const DevSweep AS4 &s, int32_t k) {
   return make_int4(w[0], w[1], w[2], w[3]);
 }
 
-// The unit with compact word cw at (slot_base, info_base).
+// The wave unit with compact word cw (lanes | lg << 7 | assign << 10 |
+// E << 11; one pass, so rows = groups = lanes >> lg) at (slot_base,
+// info_base).  An empty unit (cw = 0) has no lanes.
 __device__ __forceinline__ Unit unit_of(int32_t cw, int32_t sb, int32_t ib) {
-  const int32_t rows = cw & 0x7FFF, lg = (cw >> 15) & 7, E = (int32_t)((uint32_t)cw >> 19);
-  const int32_t groups = min(rows, 64 >> lg);  // an empty unit (cw = 0) has no lanes
-  return Unit{sb, ib, rows, groups, lg, E, groups << lg, ((cw >> 18) & 1) != 0};
+  const int32_t lanes = cw & 127, lg = (cw >> 7) & 7, E = (int32_t)((uint32_t)cw >> 11);
+  const int32_t rows = lanes >> lg;
+  return Unit{sb, ib, rows, rows, lg, E, lanes, ((cw >> 10) & 1) != 0};
 }
 
 
@@ -257,15 +259,27 @@ __device__ __forceinline__ float dpp_move(float v) {
 // Sum over aligned groups of 2^lg lanes (lg uniform, 0..6); the group's first
 // lane receives the total.  Pairs within a quad (lane ^ 1, lane ^ 2), then
 // the mirror within 8 and within 16 lanes (every lane of the smaller group
-// holds its total by then), then lane ^ 16 and lane ^ 32 by permute.
+// holds its total by then), then lane ^ 16 and lane ^ 32 by permute.  The
+// tests are nested so that the common sizes (4 and 8 lanes) take two or
+// three uniform branches.
 template <class T>
 __device__ __forceinline__ T group_sum(T v, int lg) {
-  if (lg >= 1) v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
-  if (lg >= 2) v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
-  if (lg >= 3) v += dpp_move<0x141>(v);  // row_half_mirror
-  if (lg >= 4) v += dpp_move<0x140>(v);  // row_mirror
-  if (lg >= 5) v += __shfl_xor(v, 16);
-  if (lg >= 6) v += __shfl_xor(v, 32);
+  if (lg >= 2) {
+    v += dpp_move<0xB1>(v);  // quad_perm [1,0,3,2]
+    v += dpp_move<0x4E>(v);  // quad_perm [2,3,0,1]
+    if (lg >= 3) {
+      v += dpp_move<0x141>(v);  // row_half_mirror
+      if (lg >= 4) {
+        v += dpp_move<0x140>(v);  // row_mirror
+        if (lg >= 5) {
+          v += __shfl_xor(v, 16);
+          if (lg >= 6) v += __shfl_xor(v, 32);
+        }
+      }
+    }
+  } else if (lg == 1) {
+    v += dpp_move<0xB1>(v);
+  }
   return v;
 }
 

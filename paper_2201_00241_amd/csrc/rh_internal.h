@@ -78,8 +78,8 @@ constexpr int32_t kWaveBlockRows = 16;
 // columns, or two values, with one access, and the quads (pairs) of a unit's
 // lanes are contiguous.
 // units: 8 ints each {slot_base, info_base, rows, groups, lg, E, lanes,
-// compact}; for wave-step units compact = rows | lg << 15 | assign << 18 |
-// E << 19 (their groups = min(rows, 64 >> lg)), else -1.  An assigning unit
+// compact}; for wave-step units compact = lanes | lg << 7 | assign << 10 |
+// E << 11 (their rows = groups = lanes >> lg), else -1.  An assigning unit
 // writes its rows' dot products (x_i = sum) instead of x_i - sum; it is the
 // second half of a wave block and reads only rows of that block.
 // irow/idinv give each row's matrix row and reciprocal pivot (unit order).

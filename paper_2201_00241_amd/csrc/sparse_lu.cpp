@@ -652,7 +652,8 @@ int32_t pack_unit(const Schedule &sc, int32_t b, int32_t rows, int lg, int max_l
   }
   const int32_t u = (int32_t)(pk.units.size() / 8);
   // compact form for the per-lane unit tables of wave steps (64 lanes)
-  const int32_t compact = !wave ? -1 : (rows < (1 << 15) && E < (1 << 13)) ? (rows | lg << 15 | assign << 18 | E << 19) : -2;
+  // wave units have one pass, so rows = lanes >> lg and lanes <= 64
+  const int32_t compact = !wave ? -1 : (lanes <= 64 && E < (1 << 20)) ? (lanes | lg << 7 | assign << 10 | E << 11) : -2;
   pk.units.insert(pk.units.end(), {slot_base, info_base, rows, groups, lg, E, lanes, compact});
   return u;
 }

@@ -120,8 +120,8 @@ static bool check_wave_walk(const Packed &pk) {
         const int *U = &pk.units[8 * u];
         const int cw = U[7];
         if (cw < 0) return false;
-        const int rows = cw & 0x7FFF, lg = (cw >> 15) & 7, E = (int)((unsigned)cw >> 19);
-        const int groups = std::max(1, std::min(rows, 64 >> lg)), lanes = groups << lg;
+        const int lanes = cw & 127, lg = (cw >> 7) & 7, E = (int)((unsigned)cw >> 11);
+        const int rows = lanes >> lg, groups = rows;
         if (U[0] != sb || U[1] != ib || U[2] != rows || U[3] != groups || U[4] != lg || U[5] != E || U[6] != lanes)
           return false;
         if (E % 4 != 0 || rows > groups) return false;  // column quads, one pass
@@ -144,7 +144,7 @@ static void emulate_packed(const Packed &pk, std::vector<double> &X, std::vector
     const int *U = &pk.units[8 * u];
     const int slot_base = U[0], info_base = U[1], rows = U[2], groups = U[3], lg = U[4], E = U[5],
               lanes = U[6];
-    const bool assign = U[7] >= 0 && ((U[7] >> 18) & 1);
+    const bool assign = U[7] >= 0 && ((U[7] >> 10) & 1);
     const int w = 1 << lg;
     r.assign(rows, 0.0);
     std::vector<double> part(rows, 0.0);
