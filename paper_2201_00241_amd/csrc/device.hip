@@ -222,26 +222,106 @@ struct Slots {
   int32_t row;
 };
 
+// Buffer resources of a sweep's slot and row arrays: loads take a uniform
+// byte offset in a scalar register and the lane's offset in a vector
+// register, so a unit's loads need no per-lane address arithmetic (and reads
+// past the end return 0).
+struct WaveBufs {
+  __amdgpu_buffer_rsrc_t col, val, row;
+};
+
+constexpr int kBufWord3 = 0x00020000;  // raw (untyped) buffer access on gfx9-family targets
+
 template <class T>
-__device__ __forceinline__ Slots<T> load_slots(const DevSweep AS4 &s, const Unit &U, int32_t pass, int lane) {
-  // Every lane issues the same loads, lanes without an entry from the zero
-  // slot 0, so the number of loads in flight is the same on every path and
-  // no loaded value is used before the unit needs it.  The row of a lane
-  // without one is never written.
+__device__ __forceinline__ WaveBufs wave_bufs(const DevSweep AS4 &s) {
+  WaveBufs b;
+  b.col = __builtin_amdgcn_make_buffer_rsrc((void *)s.scol, 0, s.n_slots * 4, kBufWord3);
+  b.val = __builtin_amdgcn_make_buffer_rsrc((void *)sw_val<T>(s), 0, s.n_slots * (int)sizeof(T), kBufWord3);
+  b.row = __builtin_amdgcn_make_buffer_rsrc((void *)s.irow, 0, s.n_irow * 4, kBufWord3);
+  return b;
+}
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <class T>
+__device__ __forceinline__ T buf_load_val(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <>
+__device__ __forceinline__ double buf_load_val<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ float buf_load_val<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+// Lanes past the unit's rows use a lane offset beyond every buffer's range:
+// their loads return 0 (column 0, value 0) without touching memory, so their
+// gathers all hit one LDS word.
+constexpr int kOffRange = 0x40000000;
+
+// Two values of a lane's slot pair with one access.
+template <class T>
+__device__ __forceinline__ void buf_load_pair(__amdgpu_buffer_rsrc_t r, int voff, int soff, T &a, T &b);
+template <>
+__device__ __forceinline__ void buf_load_pair<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff, double &a,
+                                                      double &b) {
+  typedef double f64x2_t __attribute__((ext_vector_type(2)));
+  const f64x2_t v = __builtin_bit_cast(f64x2_t, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+  a = v.x;
+  b = v.y;
+}
+template <>
+__device__ __forceinline__ void buf_load_pair<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff, float &a,
+                                                     float &b) {
+  typedef float f32x2_t __attribute__((ext_vector_type(2)));
+  const f32x2_t v = __builtin_bit_cast(f32x2_t, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  a = v.x;
+  b = v.y;
+}
+
+// The first kPre slots of one pass of a unit for one lane, and the lane's
+// row (see Packed): base is the pass's first slot, rbase the row-info index
+// of its first row; the lane's column quad sits at base + 4 lane, its value
+// pairs at base + 2 lane and base + 2 lanes + 2 lane.  A lane without a row
+// (act false), or a pass without slots, reads nothing: out-of-range offsets
+// return zeros.  Every call issues the same four loads.
+template <class T>
+__device__ __forceinline__ Slots<T> unit_load(const WaveBufs &B, int32_t base, int32_t rbase, int32_t lanes,
+                                              int32_t lg, int lane, bool act, bool slots) {
+  static_assert(kPre == 4, "one column quad and two value pairs per lane");
   Slots<T> L;
-  const T *val = sw_val<T>(s);
-  const int32_t r = pass * U.groups + (lane >> U.lg);
-  const bool act = lane < U.lanes && r < U.rows;
-#pragma unroll
-  for (int e = 0; e < kPre; ++e) {
-    const bool ok = act && e < U.E;
-    const int64_t at = ok ? (int64_t)U.slot_base + ((int64_t)pass * U.E + e) * U.lanes + lane : 0;
-    L.col[e] = s.scol[at];
-    L.val[e] = val[at];
-  }
-  L.row = s.irow[act ? U.info_base + r : 0];
+  const int vc = act && slots ? lane * 16 : kOffRange;
+  const int vv = act && slots ? lane * 2 * (int)sizeof(T) : kOffRange;
+  const int vr = act ? (lane >> lg) * 4 : kOffRange;
+  // uniform offsets: say so, or the compiler may keep them in vector
+  // registers and loop over their distinct values
+  const int32_t s0 = __builtin_amdgcn_readfirstlane(base), s1 = __builtin_amdgcn_readfirstlane(base + 2 * lanes);
+  const u32x4 c = __builtin_amdgcn_raw_buffer_load_b128(B.col, vc, s0 * 4, 0);
+  buf_load_pair<T>(B.val, vv, s0 * (int)sizeof(T), L.val[0], L.val[1]);
+  buf_load_pair<T>(B.val, vv, s1 * (int)sizeof(T), L.val[2], L.val[3]);
+  L.col[0] = (int32_t)c.x;
+  L.col[1] = (int32_t)c.y;
+  L.col[2] = (int32_t)c.z;
+  L.col[3] = (int32_t)c.w;
+  L.row = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(B.row, vr, __builtin_amdgcn_readfirstlane(rbase) * 4, 0);
   return L;
 }
+
+// A wave unit (one pass) at slot base sb and row-info base ib.
+template <class T>
+__device__ __forceinline__ Slots<T> wave_load(const WaveBufs &B, int32_t sb, int32_t ib, int32_t lanes, int32_t lg,
+                                              int l64) {
+  return unit_load<T>(B, sb, ib, lanes, lg, l64, l64 < lanes, true);
+}
+
+// Pass `pass` of a level or block unit.
+template <class T>
+__device__ __forceinline__ Slots<T> load_slots(const WaveBufs &B, const Unit &U, int32_t pass, int lane) {
+  const bool act = lane < U.lanes && pass * U.groups + (lane >> U.lg) < U.rows;
+  return unit_load<T>(B, U.slot_base + pass * U.E * U.lanes, U.info_base + pass * U.groups, U.lanes, U.lg, lane,
+                      act, U.E > 0);
+}
+
 
 // Cross-lane moves within a row of 16 lanes (DPP, no LDS round trip).
 template <int CTRL>
@@ -353,9 +433,8 @@ struct Part {
 };
 
 template <int C, class T>
-__device__ __forceinline__ Part<C, T> lane_dot(const DevSweep AS4 &s, const Unit &U, int32_t pass, int lane,
+__device__ __forceinline__ Part<C, T> lane_dot(const WaveBufs &B, const Unit &U, int32_t pass, int lane,
                                                const Slots<T> &L, const T *__restrict__ X) {
-  const T *val = sw_val<T>(s);
   Part<C, T> P;
   T xv[kPre][C];
 #pragma unroll
@@ -368,23 +447,25 @@ __device__ __forceinline__ Part<C, T> lane_dot(const DevSweep AS4 &s, const Unit
   for (int e = 0; e < kPre; ++e)
 #pragma unroll
     for (int c = 0; c < C; ++c) P.v[c] = fma(L.val[e], xv[e][c], P.v[c]);
-  // remaining slots, M at a time so their loads are in flight together
-  constexpr int M = 4;
-  const bool act = lane < U.lanes && pass * U.groups + (lane >> U.lg) < U.rows;
-  for (int32_t e0 = kPre; e0 < U.E; e0 += M) {
-    int32_t jj[M];
-    T vv[M];
+  // remaining slots, a column quad and two value pairs at a time
+  if (U.E > kPre) {
+    const bool act = lane < U.lanes && pass * U.groups + (lane >> U.lg) < U.rows;
+    const int vc = act ? lane * 16 : kOffRange;
+    const int vv = act ? lane * 2 * (int)sizeof(T) : kOffRange;
+    const int32_t base = U.slot_base + pass * U.E * U.lanes;
+    for (int32_t e0 = kPre; e0 < U.E; e0 += 4) {
+      const int32_t s0 = __builtin_amdgcn_readfirstlane(base + e0 * U.lanes);
+      const int32_t s1 = __builtin_amdgcn_readfirstlane(base + (e0 + 2) * U.lanes);
+      const u32x4 cq = __builtin_amdgcn_raw_buffer_load_b128(B.col, vc, s0 * 4, 0);
+      T v[4];
+      buf_load_pair<T>(B.val, vv, s0 * (int)sizeof(T), v[0], v[1]);
+      buf_load_pair<T>(B.val, vv, s1 * (int)sizeof(T), v[2], v[3]);
+      const int32_t j[4] = {(int32_t)cq.x, (int32_t)cq.y, (int32_t)cq.z, (int32_t)cq.w};
 #pragma unroll
-    for (int e = 0; e < M; ++e) {
-      const bool ok = act && e0 + e < U.E;
-      const int64_t at = ok ? (int64_t)U.slot_base + ((int64_t)pass * U.E + e0 + e) * U.lanes + lane : 0;
-      vv[e] = val[at];
-      jj[e] = s.scol[at] * C;
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int c = 0; c < C; ++c) P.v[c] = fma(v[e], X[j[e] * C + c], P.v[c]);
     }
-#pragma unroll
-    for (int e = 0; e < M; ++e)
-#pragma unroll
-      for (int c = 0; c < C; ++c) P.v[c] = fma(vv[e], X[jj[e] + c], P.v[c]);
   }
   return P;
 }
@@ -409,10 +490,10 @@ __device__ __forceinline__ void lane_finish(const Unit &U, int32_t pass, int lan
 }
 
 template <int C, class T>
-__device__ __forceinline__ void lane_update(const DevSweep AS4 &s, const Unit &U, int32_t pass, int lane,
+__device__ __forceinline__ void lane_update(const WaveBufs &B, const Unit &U, int32_t pass, int lane,
                                             const Slots<T> &L, T *__restrict__ X,
                                             T *__restrict__ s_r, bool block) {
-  lane_finish<C, T>(U, pass, lane, L.row, lane_dot<C, T>(s, U, pass, lane, L, X), X, s_r, block);
+  lane_finish<C, T>(U, pass, lane, L.row, lane_dot<C, T>(B, U, pass, lane, L, X), X, s_r, block);
 }
 
 // Bring a sweep's arrays into the L2 of this workgroup's XCD before its
@@ -474,95 +555,7 @@ __device__ __forceinline__ void wave_sync() {
 // see kOffRange) and form whole lane groups whose sums are never written.
 constexpr int kWavePre = kSlotsAhead;  // slots per lane of a wave unit
 
-template <class T>
-struct WSlots {
-  int32_t col[kWavePre];
-  T val[kWavePre];
-  int32_t row;
-};
 
-// Buffer resources of a sweep's slot and row arrays: loads take a uniform
-// byte offset in a scalar register and the lane's offset in a vector
-// register, so a unit's loads need no per-lane address arithmetic (and reads
-// past the end return 0).
-struct WaveBufs {
-  __amdgpu_buffer_rsrc_t col, val, row;
-};
-
-constexpr int kBufWord3 = 0x00020000;  // raw (untyped) buffer access on gfx9-family targets
-
-template <class T>
-__device__ __forceinline__ WaveBufs wave_bufs(const DevSweep AS4 &s) {
-  WaveBufs b;
-  b.col = __builtin_amdgcn_make_buffer_rsrc((void *)s.scol, 0, s.n_slots * 4, kBufWord3);
-  b.val = __builtin_amdgcn_make_buffer_rsrc((void *)sw_val<T>(s), 0, s.n_slots * (int)sizeof(T), kBufWord3);
-  b.row = __builtin_amdgcn_make_buffer_rsrc((void *)s.irow, 0, s.n_irow * 4, kBufWord3);
-  return b;
-}
-
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-
-template <class T>
-__device__ __forceinline__ T buf_load_val(__amdgpu_buffer_rsrc_t r, int voff, int soff);
-template <>
-__device__ __forceinline__ double buf_load_val<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
-}
-template <>
-__device__ __forceinline__ float buf_load_val<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
-}
-
-// Lanes past the unit's rows use a lane offset beyond every buffer's range:
-// their loads return 0 (column 0, value 0) without touching memory, so their
-// gathers all hit one LDS word.
-constexpr int kOffRange = 0x40000000;
-
-// Two values of a lane's slot pair with one access.
-template <class T>
-__device__ __forceinline__ void buf_load_pair(__amdgpu_buffer_rsrc_t r, int voff, int soff, T &a, T &b);
-template <>
-__device__ __forceinline__ void buf_load_pair<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff, double &a,
-                                                      double &b) {
-  typedef double f64x2_t __attribute__((ext_vector_type(2)));
-  const f64x2_t v = __builtin_bit_cast(f64x2_t, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
-  a = v.x;
-  b = v.y;
-}
-template <>
-__device__ __forceinline__ void buf_load_pair<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff, float &a,
-                                                     float &b) {
-  typedef float f32x2_t __attribute__((ext_vector_type(2)));
-  const f32x2_t v = __builtin_bit_cast(f32x2_t, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
-  a = v.x;
-  b = v.y;
-}
-
-// A wave unit's first kWavePre slots and the row of each lane: the lane's
-// first column quad at sb + 4 l, its value pairs at sb + 2 l and
-// sb + 2 lanes + 2 l (see Packed).
-template <class T>
-__device__ __forceinline__ WSlots<T> wave_load(const WaveBufs &B, int32_t sb, int32_t ib, int32_t lanes, int32_t lg,
-                                               int l64) {
-  static_assert(kWavePre == 4, "two slot pairs per lane");
-  WSlots<T> L;
-  const bool act = l64 < lanes;
-  const int vc = act ? l64 * 16 : kOffRange;
-  const int vv = act ? l64 * 2 * (int)sizeof(T) : kOffRange;
-  const int vr = act ? (l64 >> lg) * 4 : kOffRange;
-  // uniform offsets: say so, or the compiler may keep them in vector
-  // registers and loop over their distinct values
-  const int32_t s0 = __builtin_amdgcn_readfirstlane(sb), s1 = __builtin_amdgcn_readfirstlane(sb + 2 * lanes);
-  const u32x4 c = __builtin_amdgcn_raw_buffer_load_b128(B.col, vc, s0 * 4, 0);
-  buf_load_pair<T>(B.val, vv, s0 * (int)sizeof(T), L.val[0], L.val[1]);
-  buf_load_pair<T>(B.val, vv, s1 * (int)sizeof(T), L.val[2], L.val[3]);
-  L.col[0] = (int32_t)c.x;
-  L.col[1] = (int32_t)c.y;
-  L.col[2] = (int32_t)c.z;
-  L.col[3] = (int32_t)c.w;
-  L.row = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(B.row, vr, __builtin_amdgcn_readfirstlane(ib) * 4, 0);
-  return L;
-}
 
 // A wave's walk through its units of a wave step.  Unit u0 + j runs at step
 // j while the slots of unit u0 + j + kWaveAhead are loaded, so a unit's
@@ -581,7 +574,7 @@ constexpr int kTableWords = 4;  // per-lane table registers (256 units)
 
 template <class T>
 struct WRing {
-  WSlots<T> L;
+  Slots<T> L;
   int32_t cw;  // the unit's compact word
 };
 
@@ -624,14 +617,13 @@ __device__ __forceinline__ void wave_walk_units(const DevSweep AS4 &s, int32_t u
 #pragma unroll
   for (int d = 0; d < kWaveAhead; ++d)
     ring_load<T>(B, d < n ? hu[8 * (int64_t)(u0 + d) + 7] : 0, sb_pre, ib_pre, l64, ring[d]);
-  const T *val = sw_val<T>(s);
   for (int32_t c0 = 0; c0 < n; c0 += 64) {
     // every unrolled step runs (a step past the end is an empty unit), so the
     // same loads are in flight on every path through the loop
     for (int32_t i = 0; i < 64 && c0 + i < n; i += kWaveAhead) {
 #pragma unroll
       for (int d = 0; d < kWaveAhead; ++d) {
-        const WSlots<T> &L = ring[d].L;
+        const Slots<T> &L = ring[d].L;
         const Unit U = unit_of(ring[d].cw, sb_cur, 0);
         // gathers: the kWavePre entries and the row's own value
         T xv[kWavePre][C], xr[C];
@@ -650,19 +642,22 @@ __device__ __forceinline__ void wave_walk_units(const DevSweep AS4 &s, int32_t u
 #pragma unroll
           for (int c = 0; c < C; ++c) part[c] = fma(L.val[e], xv[e][c], part[c]);
         ring_load<T>(B, __builtin_amdgcn_readlane(tab[0], i + d), sb_pre, ib_pre, l64, ring[d]);
-        // rows longer than 64 kWavePre entries (rare): the remaining slots,
-        // a column quad at a time
-        for (int32_t e0 = kWavePre; e0 < U.E; e0 += 4) {
+        // rows longer than 64 kWavePre entries (rare): the remaining slots
+        if (U.E > kWavePre) {
+          const int vc = l64 < U.lanes ? l64 * 16 : kOffRange;
+          const int vv = l64 < U.lanes ? l64 * 2 * (int)sizeof(T) : kOffRange;
+          for (int32_t e0 = kWavePre; e0 < U.E; e0 += 4) {
+            const int32_t s0 = __builtin_amdgcn_readfirstlane(U.slot_base + e0 * U.lanes);
+            const int32_t s1 = __builtin_amdgcn_readfirstlane(U.slot_base + (e0 + 2) * U.lanes);
+            const u32x4 cq = __builtin_amdgcn_raw_buffer_load_b128(B.col, vc, s0 * 4, 0);
+            T v[4];
+            buf_load_pair<T>(B.val, vv, s0 * (int)sizeof(T), v[0], v[1]);
+            buf_load_pair<T>(B.val, vv, s1 * (int)sizeof(T), v[2], v[3]);
+            const int32_t j[4] = {(int32_t)cq.x, (int32_t)cq.y, (int32_t)cq.z, (int32_t)cq.w};
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const bool ok = l64 < U.lanes;
-            const int64_t ac = ok ? (int64_t)U.slot_base + (int64_t)(e0 >> 2) * 4 * U.lanes + 4 * l64 + e : 0;
-            const int64_t av =
-                ok ? (int64_t)U.slot_base + (int64_t)((e0 + e) >> 1) * 2 * U.lanes + 2 * l64 + (e & 1) : 0;
-            const T v = val[av];
-            const int32_t j = s.scol[ac];
+            for (int e = 0; e < 4; ++e)
 #pragma unroll
-            for (int c = 0; c < C; ++c) part[c] = fma(v, X[j * C + c], part[c]);
+              for (int c = 0; c < C; ++c) part[c] = fma(v[e], X[j[e] * C + c], part[c]);
           }
         }
 #pragma unroll
@@ -708,18 +703,27 @@ __device__ __forceinline__ void sweep(const DevSweep AS4 &s, T *__restrict__ X,
                         l2_warm<NT>(s.warm_common, s.warm_common_bytes, tid) ^
                         (sizeof(T) == 8 ? l2_warm<NT>(s.warm64, s.warm64_bytes, tid)
                                         : l2_warm<NT>(s.warm32, s.warm32_bytes, tid));
+  const WaveBufs B = wave_bufs<T>(s);
+  // The next level or block step's first slots and, for a block, its dense
+  // inverse entries are loaded a step ahead.  The same loads are issued
+  // whatever the next step is (with no rows when it is a wave step, or past
+  // the end), so the compiler's wait counts never cover a prefetch early.
+  Slots<T> pre;
+  DenseRow<T, NT> preD;
+  auto prefetch = [&](const int4 nx, bool valid) {
+    const bool use = valid && nx.z != 2;
+    const Unit Un = use ? unit_at(s, nx.x) : Unit{0, 0, 0, 1, 0, 0, 0, false};
+    pre = load_slots<T>(B, Un, 0, tid);
+    const Unit Ud = (use && nx.z == 1) ? Un : Unit{0, 0, 0, 1, 0, 0, 0, false};
+    preD = load_dense<T, NT>(s, (use && nx.z == 1) ? nx.w : 0, Ud, tid);
+  };
   int4 st = step_at(s, 0);
-  Slots<T> pre;          // first pass of the next level/block step
-  DenseRow<T, NT> preD;  // and its dense inverse entries if it is a block
-  if (st.z != 2) {
-    const Unit U = unit_at(s, st.x);
-    pre = load_slots<T>(s, U, 0, tid);
-    if (st.z == 1) preD = load_dense<T, NT>(s, st.w, U, tid);
-  }
+  prefetch(st, true);
   for (int32_t k = 0; k < ns; ++k) {
     const int4 cur = st;
     const Slots<T> first = pre;
     const DenseRow<T, NT> dense = preD;
+    if (k + 1 < ns) st = step_at(s, k + 1);
     if (cur.z == 2) {
       // wave step: the wave's units in order (see wave_walk_units); the next
       // step's prefetch is issued once the wave is done.
@@ -729,33 +733,21 @@ __device__ __forceinline__ void sweep(const DevSweep AS4 &s, T *__restrict__ X,
       const int32_t AS4 *wd = (const int32_t AS4 *)s.wdir;
       const int32_t u0 = wd[cur.x + wv], u1 = wd[cur.x + wv + 1];
       wave_walk_units<C, T, LDSX>(s, u0, u1, l64, X);
-      if (k + 1 < ns) {
-        st = step_at(s, k + 1);
-        if (st.z != 2) {
-          const Unit Un = unit_at(s, st.x);
-          pre = load_slots<T>(s, Un, 0, tid);
-          if (st.z == 1) preD = load_dense<T, NT>(s, st.w, Un, tid);
-        }
-      }
+      prefetch(st, k + 1 < ns);
       step_barrier<LDSX>();
       if (ss && tid == 0 && k + 1 < kMaxStepStamps) ss[k + 1] = wall_clock64();
       continue;
     }
-    // level or block step: the next step's prefetch, then the arithmetic
+    // level or block step: the arithmetic, then the next step's prefetch
+    // (issued after this step's own loads, so waiting for those never waits
+    // for it), then the barrier
     const Unit U = unit_at(s, cur.x);
     const bool block = cur.z == 1;
-    if (k + 1 < ns) {
-      st = step_at(s, k + 1);
-      if (st.z != 2) {
-        const Unit Un = unit_at(s, st.x);
-        pre = load_slots<T>(s, Un, 0, tid);
-        if (st.z == 1) preD = load_dense<T, NT>(s, st.w, Un, tid);
-      }
-    }
-    lane_update<C, T>(s, U, 0, tid, first, X, s_r, block);
+    lane_update<C, T>(B, U, 0, tid, first, X, s_r, block);
     const int32_t passes = (U.rows + U.groups - 1) / U.groups;
     for (int32_t p = 1; p < passes; ++p)
-      lane_update<C, T>(s, U, p, tid, load_slots<T>(s, U, p, tid), X, s_r, block);
+      lane_update<C, T>(B, U, p, tid, load_slots<T>(B, U, p, tid), X, s_r, block);
+    prefetch(st, k + 1 < ns);
     step_barrier<LDSX>();
     if (block) {
       dense_apply<C, NT, T>(U, dense, X, s_r, tid);

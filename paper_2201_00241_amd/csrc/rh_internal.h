@@ -69,14 +69,13 @@ constexpr int32_t kWaveBlockRows = 16;
 // or one wave level of a wave step) stores its entries in per-lane slots:
 // rows are spread over groups of 2^lg lanes, `groups` rows per pass, and lane
 // j of a group holds entries j, j + 2^lg, ... of its row, `E` slots per lane
-// and pass, padded with (column 0, value 0).  Slot (pass, e, lane) sits at
-// slot_base + (pass * E + e) * lanes + lane, so a lane needs no row pointer.
-// Wave-step units have one pass and E a multiple of 4, and keep a lane's
-// columns in quads and its values in pairs: the column of slot (e, lane)
-// sits at slot_base + (e >> 2) * 4 lanes + 4 lane + (e & 3), its value at
-// slot_base + (e >> 1) * 2 lanes + 2 lane + (e & 1), so a lane reads four
-// columns, or two values, with one access, and the quads (pairs) of a unit's
-// lanes are contiguous.
+// and pass (E a multiple of 4), padded with (column 0, value 0).  A pass
+// occupies slots slot_base + pass * E * lanes onwards and keeps a lane's
+// columns in quads and its values in pairs: the column of slot (e, lane) sits
+// at + (e >> 2) * 4 lanes + 4 lane + (e & 3), its value at + (e >> 1) * 2
+// lanes + 2 lane + (e & 1), so a lane reads four columns, or two values, with
+// one access, the quads (pairs) of a pass's lanes are contiguous, and a lane
+// needs no row pointer.  Wave-step units have one pass.
 // units: 8 ints each {slot_base, info_base, rows, groups, lg, E, lanes,
 // compact}; for wave-step units compact = lanes | lg << 7 | assign << 10 |
 // E << 11 (their rows = groups = lanes >> lg), else -1.  An assigning unit

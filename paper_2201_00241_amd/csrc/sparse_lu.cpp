@@ -628,7 +628,7 @@ int32_t pack_unit(const Schedule &sc, int32_t b, int32_t rows, int lg, int max_l
   int32_t longest = 0;
   for (int32_t r = 0; r < rows; ++r) longest = std::max(longest, s.ptr[b + r + 1] - s.ptr[b + r]);
   const int32_t E0 = std::max(min_E, (longest + w - 1) / w);
-  const int32_t E = wave ? (E0 + 3) & ~3 : E0;  // wave units: whole column quads
+  const int32_t E = (E0 + 3) & ~3;  // whole column quads
   const int32_t slot_base = (int32_t)pk.scol.size(), info_base = (int32_t)pk.irow.size();
   pk.scol.resize(pk.scol.size() + (size_t)passes * E * lanes, 0);
   pk.sval.resize(pk.sval.size() + (size_t)passes * E * lanes, 0.0);
@@ -639,11 +639,10 @@ int32_t pack_unit(const Schedule &sc, int32_t b, int32_t rows, int lg, int max_l
       for (int32_t e = 0; e < E; ++e) {
         const int32_t q = j + e * w;
         if (q >= len) continue;
-        const size_t lane = (size_t)g * w + j;
-        const size_t at = (size_t)slot_base + ((size_t)p * E + e) * lanes + lane;
-        // wave units: a lane's columns in quads, its values in pairs
-        const size_t ac = wave ? (size_t)slot_base + (size_t)(e >> 2) * 4 * lanes + 4 * lane + (e & 3) : at;
-        const size_t av = wave ? (size_t)slot_base + (size_t)(e >> 1) * 2 * lanes + 2 * lane + (e & 1) : at;
+        // a lane's columns in quads, its values in pairs, pass after pass
+        const size_t lane = (size_t)g * w + j, base = (size_t)slot_base + (size_t)p * E * lanes;
+        const size_t ac = base + (size_t)(e >> 2) * 4 * lanes + 4 * lane + (e & 3);
+        const size_t av = base + (size_t)(e >> 1) * 2 * lanes + 2 * lane + (e & 1);
         pk.scol[ac] = s.col[q0 + q];
         pk.sval[av] = s.val[q0 + q];
       }

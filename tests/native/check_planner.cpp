@@ -154,12 +154,10 @@ static void emulate_packed(const Packed &pk, std::vector<double> &X, std::vector
         const int row = p * groups + lane / w;
         if (row >= rows) continue;
         for (int e = 0; e < E; ++e) {
-          // wave units (compact word present) keep a lane's columns in quads
-          // and its values in pairs
-          const bool wv = U[7] >= 0;
-          const size_t at = (size_t)slot_base + ((size_t)p * E + e) * lanes + lane;
-          const size_t ac = wv ? (size_t)slot_base + (size_t)(e / 4) * 4 * lanes + 4 * (size_t)lane + e % 4 : at;
-          const size_t av = wv ? (size_t)slot_base + (size_t)(e / 2) * 2 * lanes + 2 * (size_t)lane + e % 2 : at;
+          // a lane's columns in quads and its values in pairs, pass by pass
+          const size_t base = (size_t)slot_base + (size_t)p * E * lanes;
+          const size_t ac = base + (size_t)(e / 4) * 4 * lanes + 4 * (size_t)lane + e % 4;
+          const size_t av = base + (size_t)(e / 2) * 2 * lanes + 2 * (size_t)lane + e % 2;
           if (pk.sval[av] != 0.0 && pending[pk.scol[ac]]) ok = false;
           part[row] += pk.sval[av] * X[pk.scol[ac]];
         }
