@@ -379,10 +379,12 @@ int32_t emit_levels(const Sweep &in, const std::vector<int32_t> &order, std::vec
 // narrow levels, or one wave step: the elimination tree is cut into disjoint
 // subtrees (each subtree's rows depend only on the subtree and on rows outside
 // it that are solved before), the subtrees are assigned to the workgroup's
-// waves by longest-processing-time-first, and every wave walks its subtrees
-// level by level with wave-local ordering only.  The cut is chosen by a small
-// cost model (a workgroup barrier step ~ 4 wave levels); the wave step comes
-// first in forward sweeps (leaves first) and last in backward sweeps.
+// waves (longest-processing-time-first, then single-subtree moves that lower
+// the largest number of units on one wave), and every wave walks its
+// subtrees level by level with wave-local ordering only.  The cut is chosen
+// by a small cost model (a workgroup barrier step ~ 5 wave units); the wave
+// step comes first in forward sweeps (leaves first) and last in backward
+// sweeps.
 Schedule build_schedule(const Sweep &in, int32_t n, const std::vector<int32_t> &parent, bool forward,
                         const ScheduleParams &prm) {
   const int bmax = std::min(prm.bmax, prm.block_rows);
@@ -418,7 +420,8 @@ Schedule build_schedule(const Sweep &in, int32_t n, const std::vector<int32_t> &
       roots.push_back(v);
     }
   }
-  const double kBarrier = 4.0, kLevel = 1.0, kEntry = 1.0 / 16.0;
+  // costs in wave-unit times: a workgroup barrier step ~ 5 units
+  const double kBarrier = 5.0, kUnit = 1.0;
   const double plain_cost = kBarrier * emit_levels(in, all, lvl, bmax, prm.lane_budget, local, nullptr);
   double best = plain_cost;
   int best_f = 0;
@@ -440,47 +443,129 @@ Schedule build_schedule(const Sweep &in, int32_t n, const std::vector<int32_t> &
     }
     std::sort(subroots.begin(), subroots.end(),
               [&](int32_t a, int32_t b) { return sub[a] > sub[b] || (sub[a] == sub[b] && a < b); });
-    std::vector<double> load(nw, 0.0);
-    std::fill(owner.begin(), owner.end(), -1);
-    for (int32_t r : subroots) {
-      const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-      load[w] += sub[r];
-      std::vector<int32_t> st{r};
+    // subtree of every row below the cut, and the level of each row within
+    // its subtree (subtrees are independent, so a wave's levels are the
+    // union of its subtrees' levels)
+    const int32_t ns = (int32_t)subroots.size();
+    std::vector<int32_t> sid(n, -1);
+    for (int32_t i = 0; i < ns; ++i) {
+      std::vector<int32_t> st{subroots[i]};
       while (!st.empty()) {
         const int32_t v = st.back();
         st.pop_back();
-        owner[v] = w;
+        sid[v] = i;
         st.insert(st.end(), kids[v].begin(), kids[v].end());
       }
     }
-    // wave makespan: per wave level a latency plus its entries over 64 lanes
-    std::vector<int32_t> wl(n, -1);
-    std::vector<std::vector<double>> lvl_entries(nw), lvl_longest(nw);
-    for (int32_t p = 0; p < npos; ++p) {
-      const int32_t r = in.rows[p];
-      if (owner[r] < 0) continue;
-      int32_t lv = 0;
-      for (int32_t q = in.ptr[p]; q < in.ptr[p + 1]; ++q) {
-        const int32_t c = in.col[q];
-        if (owner[c] == owner[r]) lv = std::max(lv, wl[c] + 1);
+    // per subtree and level: rows and longest row
+    std::vector<std::vector<std::pair<int32_t, int32_t>>> prof(ns);
+    {
+      std::vector<int32_t> wl(n, -1);
+      for (int32_t p = 0; p < npos; ++p) {
+        const int32_t r = in.rows[p];
+        if (sid[r] < 0) continue;
+        int32_t lv = 0;
+        for (int32_t q = in.ptr[p]; q < in.ptr[p + 1]; ++q)
+          if (sid[in.col[q]] == sid[r]) lv = std::max(lv, wl[in.col[q]] + 1);
+        wl[r] = lv;
+        auto &P = prof[sid[r]];
+        if ((int32_t)P.size() <= lv) P.resize(lv + 1, {0, 0});
+        P[lv].first += 1;
+        P[lv].second = std::max(P[lv].second, in.ptr[p + 1] - in.ptr[p]);
       }
-      wl[r] = lv;
-      auto &E = lvl_entries[owner[r]];
-      auto &Lg = lvl_longest[owner[r]];
-      if ((int32_t)E.size() <= lv) {
-        E.resize(lv + 1, 0.0);
-        Lg.resize(lv + 1, 0.0);
+    }
+    // units a wave emits for a set of subtrees: merged levels, runs of
+    // narrow levels as wave blocks (two units), others split into units
+    // of 64 >> lg rows (lg: lanes per row so the longest fits in
+    // kSlotsAhead slots), as emit_wave_step and pack_schedule do
+    auto wave_units = [&](const std::vector<int32_t> &set) {
+      std::vector<std::pair<int32_t, int32_t>> M;
+      for (int32_t i : set) {
+        if (M.size() < prof[i].size()) M.resize(prof[i].size(), {0, 0});
+        for (size_t l = 0; l < prof[i].size(); ++l) {
+          M[l].first += prof[i][l].first;
+          M[l].second = std::max(M[l].second, prof[i][l].second);
+        }
       }
-      E[lv] += wk[r];
-      Lg[lv] = std::max(Lg[lv], wk[r]);
+      auto split = [](int32_t rows, int32_t longest) {
+        int lg = 0;
+        while (lg < 6 && (1 << lg) * kSlotsAhead < longest) ++lg;
+        const int32_t per = std::max(1, 64 >> lg);
+        return (rows + per - 1) / per;
+      };
+      int64_t units = 0;
+      for (size_t l = 0, L = M.size(); l < L;) {
+        size_t l2 = l;
+        int32_t rows = 0, longest = 0;
+        if (in.dinv.empty())
+          while (l2 < L && rows + M[l2].first <= kWaveBlockRows) {
+            rows += M[l2].first;
+            longest = std::max(longest, M[l2].second);
+            ++l2;
+          }
+        if (l2 - l >= 3) {
+          units += 1 + split(rows, longest);
+          l = l2;
+        } else {
+          units += split(M[l].first, M[l].second);
+          ++l;
+        }
+      }
+      return units;
+    };
+    // longest-processing-time-first by subtree work, then moves of single
+    // subtrees off the wave with the most units while that lowers the most
+    std::vector<double> load(nw, 0.0);
+    std::vector<std::vector<int32_t>> sets(nw);
+    for (int32_t i = 0; i < ns; ++i) {
+      const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[w] += sub[subroots[i]];
+      sets[w].push_back(i);
     }
-    double makespan = 0.0;
-    for (int w = 0; w < nw; ++w) {
-      double t = 0.0;
-      for (size_t l = 0; l < lvl_entries[w].size(); ++l)
-        t += kLevel + kEntry * std::max(lvl_entries[w][l] / 64.0, lvl_longest[w][l] / 16.0);
-      makespan = std::max(makespan, t);
+    std::vector<int64_t> units(nw);
+    for (int w = 0; w < nw; ++w) units[w] = wave_units(sets[w]);
+    for (int it = 0; it < 4 * ns; ++it) {
+      const int wm = (int)(std::max_element(units.begin(), units.end()) - units.begin());
+      int64_t best_m = units[wm], best_a = 0, best_b = 0;
+      int best_j = -1, best_w = -1;
+      for (size_t j = 0; j < sets[wm].size(); ++j) {
+        std::vector<int32_t> rest = sets[wm];
+        rest.erase(rest.begin() + (long)j);
+        const int64_t a = wave_units(rest);
+        if (a >= best_m) continue;
+        for (int w2 = 0; w2 < nw; ++w2) {
+          if (w2 == wm) continue;
+          std::vector<int32_t> more = sets[w2];
+          more.push_back(sets[wm][j]);
+          const int64_t b = wave_units(more);
+          if (std::max(a, b) < best_m) {
+            best_m = std::max(a, b);
+            best_a = a;
+            best_b = b;
+            best_j = (int)j;
+            best_w = w2;
+          }
+        }
+      }
+      if (best_j < 0) break;
+      sets[best_w].push_back(sets[wm][best_j]);
+      sets[wm].erase(sets[wm].begin() + best_j);
+      units[wm] = best_a;
+      units[best_w] = best_b;
     }
+    std::fill(owner.begin(), owner.end(), -1);
+    for (int w = 0; w < nw; ++w)
+      for (int32_t i : sets[w]) {
+        std::vector<int32_t> st{subroots[i]};
+        while (!st.empty()) {
+          const int32_t v = st.back();
+          st.pop_back();
+          owner[v] = w;
+          st.insert(st.end(), kids[v].begin(), kids[v].end());
+        }
+      }
+    // wave makespan: the most units on one wave
+    const double makespan = kUnit * (double)*std::max_element(units.begin(), units.end());
     std::vector<int32_t> order;
     for (int32_t p = 0; p < npos; ++p)
       if (owner[in.rows[p]] < 0) order.push_back(p);
