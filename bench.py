@@ -285,6 +285,19 @@ def bench_batch(args):
     ctx.set_timing(0)
     ms = e0.elapsed_time(e1) / args.steps
     n_x, n_p = nets[0].n_x, nets[0].n_p
+    # the same batch with FP32 sweeps and FP64 refinement, after the timed
+    # region: its rate and its largest deviation from the FP64 results
+    HW64 = [h.clone() for h in HWs]
+    ctx.hvp_batch_device(nets, Ws, HWs, stream=stream.cuda_stream, prec=rh.RH_FP32_REFINED)
+    torch.cuda.synchronize()
+    r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    r0.record(stream)
+    for _ in range(args.steps):
+        ctx.hvp_batch_device(nets, Ws, HWs, stream=stream.cuda_stream, prec=rh.RH_FP32_REFINED)
+    r1.record(stream)
+    torch.cuda.synchronize()
+    refined_ms = r0.elapsed_time(r1) / args.steps
+    refined_dev = max(float((h - g).abs().max() / g.abs().max()) for h, g in zip(HWs, HW64))
     print(json.dumps({
         "metric": "batched instances: HVPs/sec", "value": len(nets) * k / (ms / 1e3),
         "unit": "HVP/s", "ms_per_step": ms, "dtype": "f64", "data": "synthetic",
@@ -293,6 +306,9 @@ def bench_batch(args):
                    "n_x": n_x, "n_p": n_p, "launches_per_step": rep["last_launches"] // args.steps,
                    "dirs_per_group": rep["dirs_per_group"]},
         "avg_launch_ms": rep["last_kernel_ms"] / max(1, rep["last_launches"]),
+        "refined_fp32": {"value": len(nets) * k / (refined_ms / 1e3), "unit": "HVP/s",
+                         "ms_per_step": refined_ms, "max_rel_dev_from_fp64": refined_dev,
+                         "what": "same batch, FP32 sweeps with two FP64 refinement steps"},
         "setup_s": setup_s}), flush=True)
 
 
