@@ -163,10 +163,15 @@ rh_status rh_hvp_device(rh_network *net, int32_t k, const void *dW, int64_t ldw,
                         int64_t ldhw, rh_precision prec, void *hip_stream);
 /* The dense reduced Hessian H (n_p x n_p, column-major, ldh >= n_p), computed
  * in ceil(n_p / k_block) blocks of identity columns (Sec. 5.3);
- * k_block = 0 picks the block size.  Host output, synchronous. */
+ * k_block = 0 lets the library choose: on the first such call for the
+ * network and precision it times one block of each candidate size (64 to
+ * 2048 in powers of two below n_p, and n_p itself when at most 2048) and
+ * keeps the size with the smallest estimated total; rh_report.last_k then
+ * gives the block size used.  Host output, synchronous. */
 rh_status rh_reduced_hessian(rh_network *net, double *H, int64_t ldh, int32_t k_block,
                              rh_precision prec);
-/* As rh_reduced_hessian into a device buffer, enqueued on `hip_stream`. */
+/* As rh_reduced_hessian into a device buffer, enqueued on `hip_stream` (the
+ * first call with k_block = 0 synchronises the stream while it tunes). */
 rh_status rh_reduced_hessian_device(rh_network *net, void *dH, int64_t ldh, int32_t k_block,
                                     rh_precision prec, void *hip_stream);
 

@@ -1,4 +1,5 @@
 // C ABI entry points of librh (declared in include/rh.h).
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <exception>
@@ -269,6 +270,38 @@ rh_status rh_hvp_device(rh_network *net, int32_t k, const void *dW, int64_t ldw,
   GUARD_END
 }
 
+// Block size of the full Hessian when the caller leaves it to the library:
+// one block of each candidate size (identity columns 0 .. k - 1, written
+// into H and overwritten by the real run) is timed by the wall clock around
+// a synchronised launch, after one untimed launch, and the size with the
+// smallest estimated total (time per block x blocks) is kept for the network
+// and precision.  Candidates: 64 .. 2048 in powers of two up to n_p, and n_p
+// itself when smaller than 2048 (one launch).
+static rh_status tune_block(Network &n, double *H, int64_t ldh, rh_precision prec, void *stream,
+                            int32_t &k_out, std::string &err) {
+  const int32_t n_p = n.n_p;
+  std::vector<int32_t> cand;
+  for (int32_t k = 64; k <= 2048 && k < n_p; k *= 2) cand.push_back(k);
+  if (n_p <= 2048) cand.push_back(n_p);
+  rh_status s = device_hvp(n, cand[0], nullptr, 0, H, ldh, 0, prec, stream, err);
+  if (s == RH_OK) s = device_sync(stream, err);
+  double best = 0.0;
+  k_out = cand.back();
+  for (int32_t k : cand) {
+    if (s != RH_OK) break;
+    const auto t0 = std::chrono::steady_clock::now();
+    s = device_hvp(n, k, nullptr, 0, H, ldh, 0, prec, stream, err);
+    if (s == RH_OK) s = device_sync(stream, err);
+    const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    const double total = t * ((n_p + k - 1) / k);
+    if (k == cand[0] || total < best) {
+      best = total;
+      k_out = k;
+    }
+  }
+  return s;
+}
+
 rh_status rh_reduced_hessian_device(rh_network *net, void *dH, int64_t ldh, int32_t k_block,
                                     rh_precision prec, void *hip_stream) {
   GUARD_BEGIN
@@ -278,10 +311,15 @@ rh_status rh_reduced_hessian_device(rh_network *net, void *dH, int64_t ldh, int3
   if (prec != RH_FP64 && prec != RH_FP32_REFINED) return fail(RH_EINVAL, "unknown precision");
   const int32_t n_p = net->n.n_p;
   if (!dH || ldh < n_p || k_block < 0) return fail(RH_EINVAL, "bad Hessian arguments");
-  const int32_t k = (k_block == 0 || k_block > n_p) ? n_p : k_block;
-  net->n.report.last_k = n_p;
   std::string err;
   double *H = static_cast<double *>(dH);
+  int32_t k = k_block > n_p ? n_p : k_block;
+  if (k_block == 0) {
+    int32_t &tk = net->n.tuned_k[prec == RH_FP64 ? 0 : 1];
+    if (tk == 0 && (s = tune_block(net->n, H, ldh, prec, hip_stream, tk, err)) != RH_OK) return fail(s, err);
+    k = tk;
+  }
+  net->n.report.last_k = k;
   for (int32_t j0 = 0; j0 < n_p; j0 += k) {
     const int32_t kb = std::min(k, n_p - j0);
     s = device_hvp(net->n, kb, nullptr, 0, H + (int64_t)j0 * ldh, ldh, j0, prec, hip_stream, err);

@@ -158,6 +158,7 @@ struct Network {
   Tape tape;
   rh_report report{};
   DeviceNet *dev = nullptr;
+  int32_t tuned_k[2] = {0, 0};  // full-Hessian block size chosen per precision (0: not yet)
 };
 
 // ---- host planner (network.cpp)

@@ -79,6 +79,22 @@ def test_1k_full_hessian_ragged_blocks(c1):
     assert np.max(np.abs(H - H.T)) / np.max(np.abs(H)) < 1e-11
 
 
+def test_1k_full_hessian_tuned_block(c1):
+    """k_block = 0: the library times its candidate block sizes once and keeps
+    one; the result is bitwise that of an explicit block size (a direction's
+    arithmetic does not depend on k) and matches the oracle."""
+    g, net, s = c1
+    _say(f"1k: full H with the tuned block size (n_p={net.n_p})")
+    H0 = net.reduced_hessian(k_block=0)
+    k = net.report()["last_k"]
+    assert k in (64, 128, net.n_p), k
+    H1 = net.reduced_hessian(k_block=0)  # tuned size kept
+    assert net.report()["last_k"] == k
+    H64 = net.reduced_hessian(k_block=64)
+    assert np.array_equal(H0, H64) and np.array_equal(H1, H64)
+    assert _relerr(H0, s.reduced_hessian(64)) <= TOL
+
+
 def test_1k_random_directions(c1):
     g, net, s = c1
     W = gridgen.directions(net.n_p, 37, 5)
