@@ -242,6 +242,8 @@ __device__ __forceinline__ WaveBufs wave_bufs(const DevSweep AS4 &s) {
 }
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 template <class T>
 __device__ __forceinline__ T buf_load_val(__amdgpu_buffer_rsrc_t r, int voff, int soff);
@@ -265,16 +267,14 @@ __device__ __forceinline__ void buf_load_pair(__amdgpu_buffer_rsrc_t r, int voff
 template <>
 __device__ __forceinline__ void buf_load_pair<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff, double &a,
                                                       double &b) {
-  typedef double f64x2_t __attribute__((ext_vector_type(2)));
-  const f64x2_t v = __builtin_bit_cast(f64x2_t, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+  const f64x2 v = __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
   a = v.x;
   b = v.y;
 }
 template <>
 __device__ __forceinline__ void buf_load_pair<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff, float &a,
                                                      float &b) {
-  typedef float f32x2_t __attribute__((ext_vector_type(2)));
-  const f32x2_t v = __builtin_bit_cast(f32x2_t, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  const f32x2 v = __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
   a = v.x;
   b = v.y;
 }
@@ -805,8 +805,6 @@ __device__ __forceinline__ void spmul(const NetDesc AS4 &nd, const WorkItem &a, 
 // The projection records through buffer resources: uniform byte offsets in
 // scalar registers, the lane's offset in a vector register, and reads past
 // the end return 0 (slots past a pass's slot count read at kOffRange).
-typedef double f64x2 __attribute__((ext_vector_type(2)));
-
 struct ProjBufs {
   __amdgpu_buffer_rsrc_t bus, inc;
   int32_t bus_plane, inc_plane;  // plane sizes in bytes

@@ -82,9 +82,9 @@ constexpr int32_t kWaveBlockRows = 16;
 // writes its rows' dot products (x_i = sum) instead of x_i - sum; it is the
 // second half of a wave block and reads only rows of that block.
 // irow/idinv give each row's matrix row and reciprocal pivot (unit order).
-// Slot 0 and dense[0] are a zero padding entry (offsets start at 1); the
-// slot arrays end with a zero tail of 64 x kSlotsAhead slots and irow with 64
-// rows.  Wave units have one pass and at least kSlotsAhead slots per lane.
+// Slot 0 and dense[0] are a zero padding entry (offsets start at 1) that
+// lanes without an entry read.  Wave units have one pass and at least
+// kSlotsAhead slots per lane.
 // steps: 4 ints each {unit or wave directory offset, 0, kind, dense offset},
 // kind 0 = level, 1 = block (dense inverse at the offset), 2 = wave step
 // (its waves' unit ranges are wdir[off + w] .. wdir[off + w + 1]).

@@ -789,11 +789,6 @@ Packed pack_schedule(const Schedule &sc, int lanes) {
       pk.steps.insert(pk.steps.end(), {u, 0, kind >= 0 ? 1 : 0, kind >= 0 ? kind + 1 : 0});
     }
   }
-  // zero tail: a wave unit's lanes beyond its rows read up to 64 x
-  // kSlotsAhead slots and 64 row indices past its start
-  pk.scol.resize(pk.scol.size() + 64 * kSlotsAhead, 0);
-  pk.sval.resize(pk.sval.size() + 64 * kSlotsAhead, 0.0);
-  pk.irow.resize(pk.irow.size() + 64, 0);
   return pk;
 }
 
