@@ -103,6 +103,18 @@ def test_1k_random_directions(c1):
     assert _relerr(HW, s.hvp(W)) <= TOL
 
 
+@pytest.mark.parametrize("n_bus", [1024, 2049])
+def test_projection_pass_edges(ctx, rhmod, n_bus):
+    """The projection takes buses 1,024 per pass: a grid that fills its passes
+    exactly, and one whose last pass holds a single bus."""
+    g = gridgen.geometric(n_bus, int(1.35 * n_bus), n_bus // 10, seed=4242 + n_bus, alpha=0.3, kappa=0.0255)
+    net = rhmod.Network(ctx, g)
+    net.solve()
+    W = gridgen.directions(net.n_p, 16, 11)
+    _say(f"{n_bus}-bus geometric grid: 16 Gaussian directions")
+    assert _relerr(net.hvp(W), solve(g).hvp(W)) <= TOL
+
+
 def test_1k_device_entry_point_with_padding(c1, rhmod):
     import torch
 
