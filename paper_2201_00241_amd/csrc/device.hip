@@ -503,7 +503,9 @@ __device__ __forceinline__ void lane_update(const WaveBufs &B, const Unit &U, in
 // round-robin over the XCDs; the workgroups of one XCD split the range and
 // touch one dword per 128-byte line.  The words are folded into the return
 // value, which the caller consumes at the end of the sweep, so the loads are
-// kept and nothing waits for them early.
+// kept.  Folding a word waits for its load, so a thread has one warming load
+// in flight at a time; that paces the warm (issuing all of a thread's lines
+// before the first wait measured slower).
 constexpr int kXcds = 8;
 
 template <int NT>
