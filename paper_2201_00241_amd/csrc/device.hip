@@ -105,11 +105,14 @@ constexpr int32_t kPadInc = -2;
 constexpr int64_t kProjMaxBytes = 0x3f000000;
 
 struct NetDesc {
-  int32_t n_x, n_p, n_bus, n_slack, n_proj_pass;
+  int32_t n_x, n_p, n_bus, n_slack, n_proj_pass, n_gp_rows;
   DevSweep L, U, Ut, Lt;  // U and Ut hold the unit factor D^{-1} U
   const double *pivinv;   // D^{-1}, applied between the two sweeps of a solve
   const float *pivinv32;
-  const int32_t *gp_ptr, *gp_col;  // G_p, rows in permuted x order
+  // G_p, rows in permuted x order: one record {row, first entry, end, 0}
+  // per row with entries, in row order, and the entries' columns and values
+  const int4 *gp_rows;
+  const int32_t *gp_col;
   const double *gp_val;
   const int32_t *gpt_ptr, *gpt_col;  // G_p^T, columns in permuted x order
   const double *gpt_val;
@@ -789,18 +792,24 @@ __device__ __forceinline__ void spmul(const NetDesc AS4 &nd, const WorkItem &a, 
     }
     return;
   }
-  for (int32_t i = tid; i < nd.n_x; i += NT) {
+  // -0 in every row (what the product of a row without entries gives), then
+  // the rows with entries, each from its record: most rows of G_p are empty,
+  // and a thread's rows are chains of dependent loads
+  for (int32_t i = tid; i < nd.n_x * C; i += NT) X[i] = -0.0;
+  __syncthreads();
+  for (int32_t j = tid; j < nd.n_gp_rows; j += NT) {
+    const int4 r = nd.gp_rows[j];
     double acc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = 0.0;
-    for (int32_t e = nd.gp_ptr[i]; e < nd.gp_ptr[i + 1]; ++e) {
+    for (int32_t e = r.y; e < r.z; ++e) {
       const double v = nd.gp_val[e];
       const int32_t q = nd.gp_col[e];
 #pragma unroll
       for (int c = 0; c < C; ++c) acc[c] = fma(v, w_at(a, q, dir0 + c), acc[c]);
     }
 #pragma unroll
-    for (int c = 0; c < C; ++c) X[i * C + c] = -acc[c];
+    for (int c = 0; c < C; ++c) X[r.x * C + c] = -acc[c];
   }
 }
 
@@ -1650,17 +1659,19 @@ rh_status device_upload(Network &net, std::string &err) {
 
   // G_p with rows in permuted order, and G_p^T with permuted columns
   {
-    std::vector<int32_t> ptr(net.n_x + 1, 0), col;
+    std::vector<int4> grows;
+    std::vector<int32_t> col;
     std::vector<double> val;
     for (int32_t ip = 0; ip < net.n_x; ++ip) {
-      const int32_t r = lu.perm[ip];
+      const int32_t r = lu.perm[ip], e0 = (int32_t)col.size();
       for (int32_t e = net.gp.ptr[r]; e < net.gp.ptr[r + 1]; ++e) {
         col.push_back(net.gp.col[e]);
         val.push_back(net.gp.val[e]);
       }
-      ptr[ip + 1] = (int32_t)col.size();
+      if ((int32_t)col.size() > e0) grows.push_back(make_int4(ip, e0, (int32_t)col.size(), 0));
     }
-    UP(ptr, nd.gp_ptr);
+    nd.n_gp_rows = (int32_t)grows.size();
+    UP(grows, nd.gp_rows);
     UP(col, nd.gp_col);
     UP(val, nd.gp_val);
     std::vector<std::vector<std::pair<int32_t, double>>> rows(net.n_p);
