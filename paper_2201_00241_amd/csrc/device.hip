@@ -764,13 +764,24 @@ __device__ __forceinline__ void sweep(const DevSweep AS4 &s, T *__restrict__ X,
   __syncthreads();                // full barrier at the end of the sweep
 }
 
-// X <- D^{-1} X between the two sweeps of a solve, then a barrier.
+// X <- D^{-1} X between the two sweeps of a solve, then a barrier.  A thread
+// loads the pivots of several of its rows before it scales any of them (one
+// row at a time, each row would wait a full load latency).
 template <int C, int NT, class T>
 __device__ __forceinline__ void pivot_scale(const T *__restrict__ d, T *__restrict__ X, int32_t n, int tid) {
-  for (int32_t i = tid; i < n; i += NT) {
-    const T v = d[i];
+  constexpr int kRows = C == 4 ? 4 : 8;  // fewer at four directions, where registers are tight
+  for (int32_t b = tid; b < n; b += kRows * NT) {
+    T v[kRows];
 #pragma unroll
-    for (int c = 0; c < C; ++c) X[i * C + c] *= v;
+    for (int m = 0; m < kRows; ++m) v[m] = b + m * NT < n ? d[b + m * NT] : T(0);
+#pragma unroll
+    for (int m = 0; m < kRows; ++m) {
+      const int32_t i = b + m * NT;
+      if (i < n) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) X[i * C + c] *= v[m];
+      }
+    }
   }
   __syncthreads();
 }
