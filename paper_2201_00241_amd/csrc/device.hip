@@ -964,23 +964,38 @@ __device__ __forceinline__ void projection(const NetDesc AS4 &nd, const WorkItem
 template <int C, int NT>
 __device__ __forceinline__ void spmuladd(const NetDesc AS4 &nd, const WorkItem &a,
                                          const double *__restrict__ Psi, int32_t dir0, int tid) {
+  // A thread issues the loads of four entries of its row of G_p^T, and its
+  // Y_p words, before it waits for any of them; the sum keeps entry order.
   for (int32_t q = tid; q < nd.n_p; q += NT) {
     const double c2x2 = nd.p_c2x2[q];
+    double hv[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) hv[c] = dir0 + c < a.k ? a.HW[(int64_t)(dir0 + c) * a.ldhw + q] : 0.0;
     double acc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = 0.0;
-    for (int32_t e = nd.gpt_ptr[q]; e < nd.gpt_ptr[q + 1]; ++e) {
-      const double v = nd.gpt_val[e];
-      const int32_t j = nd.gpt_col[e] * C;
+    const int32_t e1 = nd.gpt_ptr[q + 1];
+    for (int32_t e = nd.gpt_ptr[q]; e < e1; e += 4) {
+      double v[4];
+      int32_t j[4];
 #pragma unroll
-      for (int c = 0; c < C; ++c) acc[c] = fma(v, Psi[j + c], acc[c]);
+      for (int m = 0; m < 4; ++m) {
+        v[m] = e + m < e1 ? nd.gpt_val[e + m] : 0.0;
+        j[m] = e + m < e1 ? nd.gpt_col[e + m] * C : 0;
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        if (e + m < e1) {
+#pragma unroll
+          for (int c = 0; c < C; ++c) acc[c] = fma(v[m], Psi[j[m] + c], acc[c]);
+        }
+      }
     }
 #pragma unroll
     for (int c = 0; c < C; ++c) {
       if (dir0 + c >= a.k) continue;
-      double *h = a.HW + (int64_t)(dir0 + c) * a.ldhw + q;
-      const double yp = __builtin_isnan(c2x2) ? *h : __dmul_rn(c2x2, w_at(a, q, dir0 + c));
-      *h = yp + acc[c];
+      const double yp = __builtin_isnan(c2x2) ? hv[c] : __dmul_rn(c2x2, w_at(a, q, dir0 + c));
+      a.HW[(int64_t)(dir0 + c) * a.ldhw + q] = yp + acc[c];
     }
   }
 }
