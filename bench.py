@@ -12,8 +12,9 @@ the four triangular sweeps (12 bytes each), the per-incidence coefficients and
 G_p; achieved GB/s = those bytes / the average launch duration from HIP events
 recorded on the launch stream.  Peak: 8 TB/s (MI355X HBM3E).
 
-The CPU baseline runs the FP64 oracle (single-threaded SuperLU solves and
-sparse products) on the same grid for a bounded sample of identity blocks.
+The CPU baseline runs the FP64 oracle (SuperLU solves and sparse products)
+on the same grid: the whole Hessian split over every host core, one process
+per core, with the one-core rate beside it.
 """
 import argparse
 import hashlib
@@ -60,17 +61,68 @@ def measured_traffic():
         return None
 
 
-def algorithmic_bytes_per_launch(rep, g, k):
+def algorithmic_bytes_per_launch(rep, g, kb):
+    """Algorithmic HBM bytes of one launch over kb directions (FP64)."""
     n_x, n_p = rep["n_x"], rep["n_p"]
     per_dir = (10 * n_x + 5 * n_p) * 8
     factors = 2 * (rep["nnz_l"] + rep["nnz_u"]) * 12  # L, U, U^T, L^T sweeps
     tape = 2 * g.n_branch * (5 * 8 + 4) + g.n_bus * 8 * 3
     gp = 2 * (n_x + 2 * g.n_branch * 2) * 12
-    return per_dir * k + factors + tape + gp
+    return per_dir * kb + factors + tape + gp
 
 
-def cpu_baseline(g, k, budget_s=12.0):
-    """Oracle on blocks of k identity columns until the time budget is spent."""
+def mean_bytes_per_launch(rep, g, n_p, k):
+    """Average of algorithmic_bytes_per_launch over the ceil(n_p / k) launches
+    of a full Hessian (the last one carries n_p mod k directions)."""
+    kbs = [min(k, n_p - j0) for j0 in range(0, n_p, k)]
+    return sum(algorithmic_bytes_per_launch(rep, g, kb) for kb in kbs) / len(kbs)
+
+
+def host_cpu():
+    """CPU model and the number of cores this process may use (at most 16,
+    the host share of one GPU on a shared box)."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return model, max(1, min(n, 16))
+
+
+def _oracle_worker(config, k, lo, hi, barrier, out):
+    """One process of the multi-core baseline: its own oracle set-up (Newton,
+    SuperLU, lambda), then identity blocks [lo, hi) of the full Hessian,
+    timed from a barrier shared with the other workers."""
+    os.environ["OMP_NUM_THREADS"] = "1"
+    sys.path.insert(0, str(ROOT))
+    import gridgen
+    from oracle import solve
+
+    s = solve(gridgen.config_grid(config, 0))
+    n_p = s.o.n_p
+    barrier.wait()
+    t0 = time.perf_counter()
+    for j0 in range(lo, hi, k):
+        kb = min(k, hi - j0)
+        W = np.zeros((n_p, kb))
+        W[np.arange(j0, j0 + kb), np.arange(kb)] = 1.0
+        s.hvp(W)
+    out.put((hi - lo, time.perf_counter() - t0))
+
+
+def cpu_baseline(config, g, k, budget_s=12.0):
+    """The oracle on the same workload: one core for up to budget_s, then the
+    whole Hessian split over every host core (one process per core, each with
+    its own SuperLU); the headline figure is the multi-core rate."""
+    import multiprocessing as mp
+
     from oracle import solve
 
     t0 = time.perf_counter()
@@ -86,10 +138,241 @@ def cpu_baseline(g, k, budget_s=12.0):
         s.hvp(W)
         done += kb
     el = time.perf_counter() - t1
+    one_core = done / el
+    model, cores = host_cpu()
+    # contiguous column ranges, one per process, rounded to whole blocks of 16
+    step = max(16, -(-n_p // cores // 16) * 16)
+    ranges = [(lo, min(n_p, lo + step)) for lo in range(0, n_p, step)]
+    ctx = mp.get_context("spawn")
+    barrier = ctx.Barrier(len(ranges))
+    q = ctx.Queue()
+    procs = [ctx.Process(target=_oracle_worker, args=(config, 16, lo, hi, barrier, q))
+             for lo, hi in ranges]
+    for p in procs:
+        p.start()
+    res = [q.get(timeout=600) for _ in procs]
+    for p in procs:
+        p.join()
+    cols = sum(r[0] for r in res)
+    wall = max(r[1] for r in res)
     return {
-        "value": done / el, "unit": "HVP/s", "cores": 1, "kind": "oracle",
-        "sample": f"{done} of {n_p} identity directions in k={k} blocks ({el:.1f} s); "
-                  f"Newton+LU+lambda set-up {setup:.1f} s not included",
+        "value": cols / wall, "unit": "HVP/s", "cores": len(ranges), "kind": "oracle",
+        "cpu_model": model,
+        "one_core": {"value": one_core, "unit": "HVP/s", "cores": 1,
+                     "sample": f"{done} of {n_p} identity directions in k={k} blocks ({el:.1f} s)"},
+        "sample": f"all {n_p} identity directions of the full Hessian, split into {len(ranges)} "
+                  f"contiguous column ranges over {len(ranges)} processes (SciPy SuperLU, one "
+                  f"thread each, k=16 blocks), {wall:.2f} s from a common start; each process's "
+                  f"Newton+LU+lambda set-up ({setup:.1f} s on one core) not included",
+    }
+
+
+def refined_bytes_per_direction(n_x, n_p, passes_z, passes_psi):
+    """Algorithmic bytes of one direction in the refined mode, counting every
+    pass made: per FP32 pass (the first solve or a correction) the FP32
+    intermediate of the first sweep and the FP32 correction written and read
+    (2 x 2 x 4 n_x), the FP64 residual and the FP64 solution read and written
+    (2 x 2 x 8 n_x); outside the passes the right-hand side B and Z, -Y_x, Psi
+    (8 n_x each) and W twice, Y_p, H (5 n_p x 8)."""
+    per_pass = (2 * 2 * 4 + 2 * 2 * 8) * n_x
+    return (passes_z + passes_psi) * per_pass + 4 * 8 * n_x + 5 * 8 * n_p
+
+
+def refined_launch_bytes(rep, g, kb, passes_z, passes_psi, nnz_gx):
+    """Per launch: the directions' bytes plus, per pass, the FP32 factor
+    entries of both sweeps (8 bytes) and the FP64 residual matrix (12 bytes),
+    and once the tape and G_p."""
+    n_x, n_p = rep["n_x"], rep["n_p"]
+    per_pass_factors = (rep["nnz_l"] + rep["nnz_u"]) * 8 + nnz_gx * 12
+    tape = 2 * g.n_branch * (5 * 8 + 4) + g.n_bus * 8 * 3
+    gp = 2 * (n_x + 2 * g.n_branch * 2) * 12
+    return (kb * refined_bytes_per_direction(n_x, n_p, passes_z, passes_psi)
+            + (passes_z + passes_psi) * per_pass_factors + tape + gp)
+
+
+def _parallel_networks(ctx, grids):
+    """Create and solve one network per grid on a few host threads (the C ABI
+    allows distinct handles on different threads)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from paper_2201_00241_amd import rh
+
+    def make(g):
+        n = rh.Network(ctx, g)
+        n.solve(1e-13, 30)
+        return n
+
+    with ThreadPoolExecutor(max_workers=min(8, len(grids))) as ex:
+        return list(ex.map(make, grids))
+
+
+def run_refined(net, g, H, k, steps, warmup, stream):
+    """The refined FP32 mode on the headline workload: HVP/s, per-column
+    refinement figures and the roofline fraction over every pass made."""
+    import torch
+
+    from paper_2201_00241_amd import rh
+
+    n_p = net.n_p
+    sptr = stream.cuda_stream
+    H64 = H.clone()
+    for _ in range(warmup):
+        net.reduced_hessian_device(H, k_block=k, stream=sptr, prec=rh.RH_FP32_REFINED)
+    torch.cuda.synchronize()
+    net.ctx.set_timing(1)
+    net.report()
+    r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    r0.record(stream)
+    for _ in range(steps):
+        net.reduced_hessian_device(H, k_block=k, stream=sptr, prec=rh.RH_FP32_REFINED)
+    r1.record(stream)
+    torch.cuda.synchronize()
+    rep = net.report()
+    net.ctx.set_timing(0)
+    ms = r0.elapsed_time(r1) / steps
+    fig = net.refinement_report(n_p)
+    pz = 1.0 + float(np.mean(fig["steps_z"]))
+    pp = 1.0 + float(np.mean(fig["steps_psi"]))
+    kbs = [min(k, n_p - j0) for j0 in range(0, n_p, k)]
+    bytes_launch = sum(refined_launch_bytes(rep, g, kb, pz, pp, rep["nnz_gx"]) for kb in kbs) / len(kbs)
+    avg_launch_ms = rep["last_kernel_ms"] / rep["last_launches"]
+    achieved = bytes_launch / (avg_launch_ms / 1e3) / 1e9
+    dev = float((H - H64).abs().max() / H64.abs().max())
+    H.copy_(H64)
+    return {
+        "value": n_p / (ms / 1e3), "unit": "HVP/s", "ms_per_step": ms, "k": k,
+        "dirs_per_group": rep["dirs_per_group"], "max_rel_dev_from_fp64": dev,
+        "passes_per_solve": {"z": pz, "psi": pp},
+        "corrections_histogram": {"z": np.bincount(fig["steps_z"]).tolist(),
+                                  "psi": np.bincount(fig["steps_psi"]).tolist()},
+        "max_backward_error": {"z": float(fig["berr_z"].max()), "psi": float(fig["berr_psi"].max())},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "kernel": "refined_kernel",
+                     "avg_launch_ms": avg_launch_ms, "algorithmic_bytes_per_launch": bytes_launch},
+        "what": "same workload, FP32 sweeps with FP64 residual refinement (each direction stops "
+                "at a backward error of 1e-13 or after 4 corrections)",
+    }
+
+
+def run_batch(instances, steps, warmup, config="c3"):
+    """Operating points of one grid (loads perturbed by up to 10 %), each with
+    128 Gaussian directions, in one launch per step; FP64 and refined."""
+    import torch
+
+    import gridgen
+    from paper_2201_00241_amd import rh
+
+    base = gridgen.config_grid(config, 0)
+    ctx = rh.Context(0)
+    t0 = time.perf_counter()
+    nets = _parallel_networks(ctx, [gridgen.perturb_loads(base, seed=5000 + i) for i in range(instances)])
+    setup_s = time.perf_counter() - t0
+    k = 128
+    Ws = [torch.from_numpy(np.ascontiguousarray(gridgen.directions(n.n_p, k, 7000 + i).T)).cuda()
+          for i, n in enumerate(nets)]
+    HWs = [torch.empty_like(W) for W in Ws]
+    stream = torch.cuda.current_stream()
+    out = {}
+    HW64 = None
+    for name, prec in (("fp64", rh.RH_FP64), ("refined_fp32", rh.RH_FP32_REFINED)):
+        for _ in range(warmup):
+            ctx.hvp_batch_device(nets, Ws, HWs, stream=stream.cuda_stream, prec=prec)
+        torch.cuda.synchronize()
+        ctx.set_timing(1)
+        ctx.report()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            ctx.hvp_batch_device(nets, Ws, HWs, stream=stream.cuda_stream, prec=prec)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        rep = ctx.report()
+        ctx.set_timing(0)
+        ms = e0.elapsed_time(e1) / steps
+        out[name] = {"value": len(nets) * k / (ms / 1e3), "unit": "HVP/s", "ms_per_step": ms,
+                     "launches_per_step": rep["last_launches"] / steps,
+                     "dirs_per_group": rep["dirs_per_group"],
+                     "avg_launch_ms": rep["last_kernel_ms"] / max(1, rep["last_launches"])}
+        if HW64 is None:
+            HW64 = [h.clone() for h in HWs]
+        else:
+            out[name]["max_rel_dev_from_fp64"] = max(
+                float((h - g).abs().max() / g.abs().max()) for h, g in zip(HWs, HW64))
+    for n in nets:
+        n.close()
+    ctx.close()
+    out.update({
+        "workload": f"{len(nets)} operating points of a {base.n_bus}-bus grid (loads x U(0.9, 1.1)) "
+                    f"x {k} Gaussian directions, one launch per step",
+        "n_x": nets[0].n_x, "n_p": nets[0].n_p, "setup_s": setup_s,
+    })
+    return out
+
+
+def run_serving(n_peak=120, n_run=300, seed=11):
+    """Poisson arrivals over resident 1k, 10k and 70k networks (4 operating
+    points each); requests for 1, 16 or 128 directions or the full Hessian,
+    FP64 or refined.  The peak is the closed-loop rate of the same mix; the
+    arrival times are scaled so that the offered rate (requests / last
+    arrival) is exactly 0.8 x peak."""
+    import gridgen
+    from paper_2201_00241_amd import rh
+    from paper_2201_00241_amd.serving import Request, Server, latency_summary
+
+    ctx = rh.Context(0)
+    grids, keys = [], []
+    for name in ("c1", "c2", "c3"):
+        base = gridgen.config_grid(name, 0)
+        for i in range(4):
+            grids.append(gridgen.perturb_loads(base, seed=9000 + i))
+            keys.append(f"{name}/{i}")
+    t0 = time.perf_counter()
+    nets = dict(zip(keys, _parallel_networks(ctx, grids)))
+    setup_s = time.perf_counter() - t0
+    rng = np.random.default_rng(seed)
+
+    def make(n_req):
+        reqs = []
+        for i in range(n_req):
+            key = keys[rng.integers(len(keys))]
+            k = int(rng.choice([1, 16, 128, 0], p=[0.3, 0.3, 0.3, 0.1]))
+            prec = rh.RH_FP64 if rng.random() < 0.5 else rh.RH_FP32_REFINED
+            W = None if k == 0 else rng.standard_normal((nets[key].n_p, k))
+            reqs.append(Request(rid=i, key=key, k=k, W=W, prec=prec))
+        return reqs
+
+    srv = Server(ctx, nets, max_inflight=3, dirs_per_launch=4096, block=256,
+                 mem_budget_bytes=128 << 30, keep_results=False)
+    srv.run(make(12))  # warm-up
+    t0 = time.perf_counter()
+    closed = srv.run(make(n_peak))
+    peak = len(closed) / (time.perf_counter() - t0)
+    reqs = make(n_run)
+    gaps = rng.exponential(1.0, n_run)
+    arr = np.cumsum(gaps)
+    arr *= n_run / (0.8 * peak) / arr[-1]  # offered rate n_run / arr[-1] = 0.8 peak
+    for r, a in zip(reqs, arr):
+        r.arrival = float(a)
+    t0 = time.perf_counter()
+    done = srv.run(reqs)
+    wall = time.perf_counter() - t0
+    ok = [r for r in done if r.error is None]
+    hvps = sum((r.k if r.k else nets[r.key].n_p) for r in ok)
+    lat = latency_summary(ok)
+    for n in nets.values():
+        n.close()
+    ctx.close()
+    return {
+        "p50_ms": lat["p50_ms"], "p99_ms": lat["p99_ms"], "mean_ms": lat["mean_ms"],
+        "requests": len(done), "failed": len(done) - len(ok),
+        "offered_rate_req_s": n_run / float(arr[-1]), "peak_req_s": peak,
+        "offered_fraction_of_peak": n_run / float(arr[-1]) / peak,
+        "served_req_s": len(ok) / wall, "served_hvp_s": hvps / wall,
+        "latency": "scheduled arrival to the completion event of the request's last block",
+        "workload": "Poisson arrivals over 1k/10k/70k-bus grids, 4 load-perturbed operating points "
+                    "each; k in {1,16,128} (0.3 each) or the full Hessian (0.1); FP64 or refined "
+                    "FP32 (0.5 each)",
+        "setup_s": setup_s,
     }
 
 
@@ -101,11 +384,14 @@ def main():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--k", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-refined", action="store_true")
     ap.add_argument("--workload", default="hessian",
                     choices=["hessian", "batch", "serving"],
-                    help="hessian: full reduced Hessian (the headline metric); batch: many "
-                         "operating points of one grid in one launch; serving: Poisson "
-                         "request mix through the continuous-batching server")
+                    help="hessian: full reduced Hessian (the headline metric, with the batched "
+                         "and serving figures attached); batch: only the operating points of "
+                         "one grid in one launch; serving: only the Poisson request mix")
     ap.add_argument("--instances", type=int, default=32)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a device-to-device copy of this many bytes, 10 times "
@@ -136,9 +422,11 @@ def main():
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
     if args.workload == "batch":
-        return bench_batch(args)
+        print(json.dumps(run_batch(args.instances, args.steps, args.warmup)), flush=True)
+        return
     if args.workload == "serving":
-        return bench_serving(args)
+        print(json.dumps(run_serving()), flush=True)
+        return
     g = gridgen.config_grid(args.config, 0)
     ctx = rh.Context(0)
     net = rh.Network(ctx, g)
@@ -174,20 +462,7 @@ def main():
     total_ms = ev[0].elapsed_time(ev[-1])
     ms_per_step = total_ms / args.steps
     value = n_p * args.steps / (total_ms / 1e3)
-
-    # the refined FP32 mode on the same workload ("vs plain"), after the timed region
-    H64 = H.clone()
-    for _ in range(args.warmup):
-        net.reduced_hessian_device(H, k_block=k, stream=sptr, prec=rh.RH_FP32_REFINED)
-    r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    r0.record(stream)
-    for _ in range(args.steps):
-        net.reduced_hessian_device(H, k_block=k, stream=sptr, prec=rh.RH_FP32_REFINED)
-    r1.record(stream)
-    torch.cuda.synchronize()
-    refined_ms = r0.elapsed_time(r1) / args.steps
-    refined_dev = float((H - H64).abs().max() / H64.abs().max())
-    H.copy_(H64)
+    print(f"# headline: {value:.0f} HVP/s, {ms_per_step:.3f} ms per Hessian", file=sys.stderr, flush=True)
 
     # one more step with in-kernel phase stamps (outside the timed region)
     ctx.set_timing(2)
@@ -199,9 +474,10 @@ def main():
     rep = trep
     launches = trep["last_launches"]
     avg_launch_ms = trep["last_kernel_ms"] / launches
-    bytes_launch = algorithmic_bytes_per_launch(rep, g, k)
+    bytes_launch = mean_bytes_per_launch(rep, g, n_p, k)
     achieved = bytes_launch / (avg_launch_ms / 1e3) / 1e9
     traffic = measured_traffic()
+    phase_names = ["spmul", "L", "U", "projection", "Ut", "Lt", "spmuladd"]
     out = {
         "metric": "reduced-Hessian HVPs/sec at 10k buses (k=256) vs plain; p50/p99 latency",
         "value": value,
@@ -219,14 +495,15 @@ def main():
             "workload": f"full reduced Hessian of a {g.n_bus}-bus synthetic grid "
                         f"({g.n_branch} branches, {g.n_gen} generators) in k={k} blocks",
             "n_x": rep["n_x"], "n_p": n_p, "k": k,
+            "loading_factor": g.meta.get("alpha"),
+            "mean_pq_load_pu": float(np.mean(g.Pd[g.bus_type == gridgen.PQ])),
             "launches_per_step": launches // args.steps,
             "dirs_per_group": rep["dirs_per_group"],
             "levels_l": rep["levels_l"], "levels_u": rep["levels_u"],
             "nnz_l": rep["nnz_l"], "nnz_u": rep["nnz_u"],
             "steps_l": rep["steps_l"], "steps_u": rep["steps_u"],
         },
-        "phase_us": dict(zip(["spmul", "L", "U", "projection", "Ut", "Lt", "spmuladd"],
-                             [round(v, 2) for v in prep["phase_us"]])),
+        "phase_us": dict(zip(phase_names, [round(v, 2) for v in prep["phase_us"]])),
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)),
                        "p99": float(np.percentile(step_ms, 99)),
                        "what": "one full reduced Hessian"},
@@ -237,130 +514,33 @@ def main():
             "kernel": "block_kernel", "avg_launch_ms": avg_launch_ms,
             "algorithmic_bytes_per_launch": bytes_launch,
         },
-        "refined_fp32": {"value": n_p / (refined_ms / 1e3), "unit": "HVP/s", "ms_per_step": refined_ms,
-                         "max_rel_dev_from_fp64": refined_dev,
-                         "what": "same workload, FP32 sweeps with two FP64 refinement steps"},
         "setup_s": setup_s,
         "wall_s": wall,
     }
+    # per-phase roofline fractions: each phase's algorithmic bytes (k directions)
+    # over its mean time per workgroup
+    n_x = rep["n_x"]
+    ph_bytes = {"L": 2 * n_x * k * 8 + rep["nnz_l"] * 12, "U": 2 * n_x * k * 8 + rep["nnz_u"] * 12,
+                "Ut": 2 * n_x * k * 8 + rep["nnz_u"] * 12, "Lt": 2 * n_x * k * 8 + rep["nnz_l"] * 12,
+                "projection": 2 * (n_x + n_p) * k * 8}
+    out["phase_roofline_frac"] = {
+        p: round(b / (out["phase_us"][p] * 1e-6) / 1e9 / PEAK_HBM_GBS, 4)
+        for p, b in ph_bytes.items() if out["phase_us"].get(p, 0) > 0}
+    if not args.no_refined:
+        out["refined_fp32"] = run_refined(net, g, H, k, args.steps, args.warmup, stream)
+        print(f"# refined: {out['refined_fp32']['value']:.0f} HVP/s", file=sys.stderr, flush=True)
+    net.close()
+    ctx.close()
+    if not args.no_batch:
+        out["batch"] = run_batch(args.instances, max(2, args.steps // 4), 1)
+        print(f"# batch: {out['batch']['fp64']['value']:.0f} HVP/s", file=sys.stderr, flush=True)
+    if not args.no_serving:
+        out["serving"] = run_serving()
+        print(f"# serving: p50 {out['serving']['p50_ms']:.1f} ms p99 {out['serving']['p99_ms']:.1f} ms",
+              file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(g, k)
+        out["cpu_baseline"] = cpu_baseline(args.config, g, k)
     print(json.dumps(out), flush=True)
-
-
-def bench_batch(args):
-    """Operating points of one grid (loads perturbed by up to 10 %), each with
-    128 Gaussian directions, in one launch per step."""
-    import torch
-
-    import gridgen
-    from paper_2201_00241_amd import rh
-
-    base = gridgen.config_grid(args.config if args.config != "c2" else "c3", 0)
-    ctx = rh.Context(0)
-    nets, t0 = [], time.perf_counter()
-    for i in range(args.instances):
-        g = gridgen.perturb_loads(base, seed=5000 + i)
-        n = rh.Network(ctx, g)
-        n.solve(1e-13, 30)
-        nets.append(n)
-    setup_s = time.perf_counter() - t0
-    k = 128
-    Ws = [torch.from_numpy(np.ascontiguousarray(gridgen.directions(n.n_p, k, 7000 + i).T)).cuda()
-          for i, n in enumerate(nets)]
-    HWs = [torch.empty_like(W) for W in Ws]
-    stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        ctx.hvp_batch_device(nets, Ws, HWs, stream=stream.cuda_stream)
-    torch.cuda.synchronize()
-    ctx.set_timing(1)
-    ctx.report()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(args.steps):
-        ctx.hvp_batch_device(nets, Ws, HWs, stream=stream.cuda_stream)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    rep = ctx.report()
-    ctx.set_timing(0)
-    ms = e0.elapsed_time(e1) / args.steps
-    n_x, n_p = nets[0].n_x, nets[0].n_p
-    # the same batch with FP32 sweeps and FP64 refinement, after the timed
-    # region: its rate and its largest deviation from the FP64 results
-    HW64 = [h.clone() for h in HWs]
-    ctx.hvp_batch_device(nets, Ws, HWs, stream=stream.cuda_stream, prec=rh.RH_FP32_REFINED)
-    torch.cuda.synchronize()
-    r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    r0.record(stream)
-    for _ in range(args.steps):
-        ctx.hvp_batch_device(nets, Ws, HWs, stream=stream.cuda_stream, prec=rh.RH_FP32_REFINED)
-    r1.record(stream)
-    torch.cuda.synchronize()
-    refined_ms = r0.elapsed_time(r1) / args.steps
-    refined_dev = max(float((h - g).abs().max() / g.abs().max()) for h, g in zip(HWs, HW64))
-    print(json.dumps({
-        "metric": "batched instances: HVPs/sec", "value": len(nets) * k / (ms / 1e3),
-        "unit": "HVP/s", "ms_per_step": ms, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{len(nets)} operating points of a {base.n_bus}-bus grid "
-                               f"x {k} Gaussian directions, one launch",
-                   "n_x": n_x, "n_p": n_p, "launches_per_step": rep["last_launches"] // args.steps,
-                   "dirs_per_group": rep["dirs_per_group"]},
-        "avg_launch_ms": rep["last_kernel_ms"] / max(1, rep["last_launches"]),
-        "refined_fp32": {"value": len(nets) * k / (refined_ms / 1e3), "unit": "HVP/s",
-                         "ms_per_step": refined_ms, "max_rel_dev_from_fp64": refined_dev,
-                         "what": "same batch, FP32 sweeps with two FP64 refinement steps"},
-        "setup_s": setup_s}), flush=True)
-
-
-def bench_serving(args):
-    """Poisson arrivals over resident 1k, 10k and 70k networks (4 operating
-    points each), requests for 1, 16 or 128 directions or the full Hessian."""
-    import gridgen
-    from paper_2201_00241_amd import rh
-    from paper_2201_00241_amd.serving import Request, Server, latency_summary
-
-    ctx = rh.Context(0)
-    nets = {}
-    for name in ("c1", "c2", "c3"):
-        base = gridgen.config_grid(name, 0)
-        for i in range(4):
-            n = rh.Network(ctx, gridgen.perturb_loads(base, seed=9000 + i))
-            n.solve(1e-13, 30)
-            nets[f"{name}/{i}"] = n
-    keys = sorted(nets)
-    rng = np.random.default_rng(11)
-
-    def make(n_req, rate):
-        t, reqs = 0.0, []
-        for i in range(n_req):
-            key = keys[rng.integers(len(keys))]
-            k = int(rng.choice([1, 16, 128, 0], p=[0.3, 0.3, 0.3, 0.1]))
-            if k == 0 and key.startswith("c3"):
-                k = 128  # a full 70k-bus Hessian would dominate the mix
-            W = None if k == 0 else rng.standard_normal((nets[key].n_p, k))
-            if rate:
-                t += rng.exponential(1.0 / rate)
-            reqs.append(Request(rid=i, key=key, k=k, W=W, arrival=t))
-        return reqs
-
-    srv = Server(ctx, nets, max_inflight=3, dirs_per_launch=4096, block=256)
-    srv.run(make(20, 0))  # warm-up
-    t0 = time.perf_counter()
-    closed = srv.run(make(120, 0))
-    peak = len(closed) / (time.perf_counter() - t0)
-    reqs = make(200, 0.8 * peak)
-    t0 = time.perf_counter()
-    done = srv.run(reqs)
-    wall = time.perf_counter() - t0
-    hvps = sum((r.k if r.k else nets[r.key].n_p) for r in done)
-    print(json.dumps({
-        "metric": "served reduced-Hessian requests: p50/p99 latency", "unit": "ms",
-        "latency": latency_summary(done), "requests_per_s": len(done) / wall,
-        "hvp_per_s": hvps / wall, "peak_requests_per_s": peak, "arrival_rate": 0.8 * peak,
-        "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "Poisson mix over 1k/10k/70k-bus grids, 4 operating points "
-                               "each; k in {1,16,128} or the full Hessian (1k, 10k)"}}),
-          flush=True)
 
 
 if __name__ == "__main__":

@@ -59,11 +59,10 @@ typedef enum {
 
 typedef enum {
   RH_FP64 = 0,        /* every step in FP64 */
-  RH_FP32_REFINED = 1 /* triangular sweeps in FP32 with FP64 residual refinement:
-                         x = solve32(b), then `refinement` times
-                         x += solve32(b - G_x x) (G_x^T for the second solve),
-                         residuals, stored vectors, tensor projection and G_p
-                         products in FP64; LU factors computed in FP64 */
+  RH_FP32_REFINED = 1 /* triangular sweeps in FP32 with FP64 residual refinement
+                         (see rh_context_set_refinement): residuals, stored
+                         vectors, tensor projection and G_p products in FP64;
+                         LU factors computed in FP64 */
 } rh_precision;
 
 /* Network description (Sec. 3.1).  All arrays are read-only and copied.
@@ -112,9 +111,14 @@ rh_status rh_context_destroy(rh_context *ctx);
  * (rh_report.phase_us), which add a little work per workgroup. */
 rh_status rh_context_set_timing(rh_context *ctx, int32_t on);
 
-/* Correction steps of RH_FP32_REFINED after the first FP32 solve (default 2,
- * at most 16). */
-rh_status rh_context_set_refinement(rh_context *ctx, int32_t steps);
+/* Refined mode (RH_FP32_REFINED): each of the two sparse solves of a direction
+ * (G_x z = b and G_x^T psi = b') is x = solve32(b), then corrections
+ * x += solve32(r) with the FP64 residual r = b - A x, until
+ * ||r||_inf <= tol ||A||_inf ||x||_inf (a backward-error test) or `steps`
+ * corrections were made.  Each direction stops on its own.  Defaults: at most
+ * 4 corrections, tol 1e-13; tol 0 makes every direction take all `steps`. */
+rh_status rh_context_set_refinement(rh_context *ctx, int32_t steps);     /* 0 .. 16 */
+rh_status rh_context_set_refinement_tol(rh_context *ctx, double tol);   /* finite, >= 0 */
 
 /* Validate and copy a network; builds the index maps, the sparsity pattern of
  * G_x, a fill-reducing ordering, the symbolic LU and the level schedules.
@@ -190,6 +194,27 @@ rh_status rh_hvp_batch_device(rh_context *ctx, int32_t n, rh_network *const *net
                               void *const *dHW, const int64_t *ldhw,
                               const int32_t *identity_from, rh_precision prec,
                               void *hip_stream);
+
+/* Per-column figures of the last RH_FP32_REFINED call of rh_hvp,
+ * rh_hvp_device, rh_reduced_hessian or rh_reduced_hessian_device on the
+ * network (batched calls record none).  For columns j < n (n at most that
+ * call's column count, n_p for a full Hessian): the backward error of each
+ * solve after its last correction, ||r||_inf / (||A||_inf ||x||_inf) with the
+ * residual in FP64 (A = G_x for the state tangent z, G_x^T for the
+ * second-order adjoint psi), and the corrections each solve took.  Any output
+ * may be NULL.  Waits for the device.  RH_ESTATE before any refined call. */
+rh_status rh_refinement_report(const rh_network *net, int32_t n, double *berr_z, int32_t *steps_z,
+                               double *berr_psi, int32_t *steps_psi);
+
+/* Device memory of a network, for admission control by callers that keep
+ * several networks resident: `resident` = bytes the network holds now (LU
+ * factors and sweep schedules in both precisions, branch coefficients, G_p,
+ * G_x, descriptors, and its own launch scratch), `scratch_per_direction` =
+ * launch scratch one direction of this network may take in precision `prec`
+ * (a launch holds it for each direction it runs at once, up to the
+ * workgroups it keeps resident).  Either output may be NULL. */
+rh_status rh_network_device_bytes(const rh_network *net, rh_precision prec, int64_t *resident,
+                                  int64_t *scratch_per_direction);
 
 /* Figures of the network; waits for the timed launches since the previous
  * report, sums their durations, then starts a new timing window. */

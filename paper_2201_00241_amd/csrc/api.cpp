@@ -111,6 +111,13 @@ rh_status rh_context_set_refinement(rh_context *ctx, int32_t steps) {
   return RH_OK;
 }
 
+rh_status rh_context_set_refinement_tol(rh_context *ctx, double tol) {
+  if (!ctx) return fail(RH_EINVAL, "null context");
+  if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(RH_EINVAL, "tolerance must be finite and >= 0");
+  ctx->c.refine_tol = tol;
+  return RH_OK;
+}
+
 rh_status rh_network_create(rh_context *ctx, const rh_network_desc *desc, rh_network **out) {
   GUARD_BEGIN
   if (!ctx || !desc || !out) return fail(RH_EINVAL, "null argument");
@@ -266,6 +273,7 @@ rh_status rh_hvp_device(rh_network *net, int32_t k, const void *dW, int64_t ldw,
   s = device_hvp(net->n, k, static_cast<const double *>(dW), ldw, static_cast<double *>(dHW), ldhw,
                  -1, prec, hip_stream, err);
   if (s != RH_OK) return fail(s, err);
+  if (prec == RH_FP32_REFINED) net->n.refined_cols = k;
   return RH_OK;
   GUARD_END
 }
@@ -325,6 +333,7 @@ rh_status rh_reduced_hessian_device(rh_network *net, void *dH, int64_t ldh, int3
     s = device_hvp(net->n, kb, nullptr, 0, H + (int64_t)j0 * ldh, ldh, j0, prec, hip_stream, err);
     if (s != RH_OK) return fail(s, err);
   }
+  if (prec == RH_FP32_REFINED) net->n.refined_cols = n_p;
   return RH_OK;
   GUARD_END
 }
@@ -398,6 +407,37 @@ rh_status rh_last_report(const rh_network *net, rh_report *out) {
   }
   *out = net->n.report;
   return RH_OK;
+}
+
+rh_status rh_network_device_bytes(const rh_network *net, rh_precision prec, int64_t *resident,
+                                  int64_t *scratch_per_direction) {
+  if (!net) return fail(RH_EINVAL, "null network");
+  if (prec != RH_FP64 && prec != RH_FP32_REFINED) return fail(RH_EINVAL, "unknown precision");
+  if (resident) *resident = device_network_bytes(net->n);
+  if (scratch_per_direction) *scratch_per_direction = device_scratch_per_direction(net->n.n_x, prec);
+  return RH_OK;
+}
+
+rh_status rh_refinement_report(const rh_network *net, int32_t n, double *berr_z, int32_t *steps_z,
+                               double *berr_psi, int32_t *steps_psi) {
+  GUARD_BEGIN
+  if (!net) return fail(RH_EINVAL, "null network");
+  rh_network *mnet = const_cast<rh_network *>(net);
+  if (mnet->n.refined_cols < 0) return fail(RH_ESTATE, "no refined product call on this network");
+  if (n < 0 || n > mnet->n.refined_cols)
+    return fail(RH_EINVAL, "column count exceeds that of the last refined call");
+  std::vector<double> v;
+  std::string err;
+  rh_status s = device_refinement_report(mnet->n, n, v, err);
+  if (s != RH_OK) return fail(s, err);
+  for (int32_t j = 0; j < n; ++j) {
+    if (berr_z) berr_z[j] = v[4 * (size_t)j];
+    if (steps_z) steps_z[j] = (int32_t)v[4 * (size_t)j + 1];
+    if (berr_psi) berr_psi[j] = v[4 * (size_t)j + 2];
+    if (steps_psi) steps_psi[j] = (int32_t)v[4 * (size_t)j + 3];
+  }
+  return RH_OK;
+  GUARD_END
 }
 
 rh_status rh_hvp_batch_device(rh_context *ctx, int32_t n, rh_network *const *nets, const int32_t *k,

@@ -33,6 +33,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -104,6 +105,22 @@ constexpr int32_t kPadInc = -2;
 // record arrays stay below the out-of-range offset (see kOffRange)
 constexpr int64_t kProjMaxBytes = 0x3f000000;
 
+// A sparse matrix for row-parallel products with a vector in LDS (the
+// residuals of the refined mode).  Rows are taken kThreads per pass in order
+// of decreasing length; lane t of pass p owns row rows[p * kThreads + t] (-1:
+// none), and its entry e sits in slot pass_first[p] + e * kThreads + t of the
+// column and value planes (padding: column 0, value 0).  A pass is read in
+// chunks of kEllChunk entries; chunk c is {first slot, pass, flags}, flags
+// bit 0 = first chunk of its pass, bit 1 = last.  norm = max row sum of |a|.
+constexpr int kEllChunk = 8;
+struct EllMat {
+  int32_t n_chunks, n_slots;
+  const int4 *chunks;
+  const int32_t *rows, *col;
+  const double *val;
+  double norm;
+};
+
 struct NetDesc {
   int32_t n_x, n_p, n_bus, n_slack, n_proj_pass, n_gp_rows;
   DevSweep L, U, Ut, Lt;  // U and Ut hold the unit factor D^{-1} U
@@ -131,8 +148,7 @@ struct NetDesc {
   // is a voltage magnitude (its Y_p comes from the projection)
   const double *p_c2x2;
   // G_x and G_x^T in permuted numbering (residuals of the refined mode)
-  const int32_t *gx_ptr, *gx_col, *gxt_ptr, *gxt_col;
-  const double *gx_val, *gxt_val;
+  EllMat gx, gxt;
 };
 
 // One unit of work: a block of k directions of one network (column-major
@@ -146,13 +162,17 @@ struct WorkItem {
   int32_t k, identity_from;
   int32_t chunk0;  // first chunk of C directions of this item in the launch
   int32_t pad;
+  // refined mode: per direction {backward error of Z, corrections of Z,
+  // backward error of Psi, corrections of Psi} (4 doubles), or nullptr
+  double *rinfo;
 };
 
 struct LaunchArgs {
   const WorkItem *items;  // n_items entries in device memory; nullptr: `one`
   WorkItem one;
   int32_t n_items, n_chunks;
-  int32_t refine;  // refined mode: correction steps after the first FP32 solve
+  int32_t refine;  // refined mode: at most this many correction steps after the first FP32 solve
+  double refine_tol;  // refined mode: stop a direction once ||r|| <= tol ||A|| ||x|| (inf-norms)
   double *scratch;
   int64_t scratch_stride;  // doubles per workgroup
   long long *stamps;       // kStamps wall-clock stamps per workgroup, or nullptr
@@ -1063,47 +1083,174 @@ __device__ __forceinline__ void reduction(const NetDesc AS4 &nd, const WorkItem 
   if (st) st[7] = wall_clock64();
 }
 
-// Refined mode (FP32 sweeps, FP64 residuals).  Each of the two solves is
-//   x = solve32(b);  repeat `refine` times: x += solve32(b - A x)
-// with the residual b - A x formed in FP64 from G_x (or G_x^T) and x kept in
-// FP64; the tensor projection, G_p products and all stored vectors are FP64.
-// Scratch: V1 (right-hand sides: -G_p W, then -Y_x) and V2 (Z, then Psi),
-// both FP64 in global memory; X32 holds the FP32 correction being solved.
+// Workgroup maxima of two non-negative vectors of C values (s_red: kWaves *
+// 2 C doubles); every thread receives them.  Ends with a barrier.
+template <int C, int NT>
+__device__ __forceinline__ void block_max2(double (&a)[C], double (&b)[C], double *s_red, int tid) {
+#pragma unroll
+  for (int c = 0; c < C; ++c)
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      a[c] = fmax(a[c], __shfl_xor(a[c], off));
+      b[c] = fmax(b[c], __shfl_xor(b[c], off));
+    }
+  if ((tid & 63) == 0) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      s_red[(tid >> 6) * 2 * C + c] = a[c];
+      s_red[(tid >> 6) * 2 * C + C + c] = b[c];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < C; ++c) {
+    double ma = 0.0, mb = 0.0;
+    for (int w = 0; w < NT / 64; ++w) {
+      ma = fmax(ma, s_red[w * 2 * C + c]);
+      mb = fmax(mb, s_red[w * 2 * C + C + c]);
+    }
+    a[c] = ma;
+    b[c] = mb;
+  }
+  __syncthreads();
+}
+
+// One chunk of kEllChunk entries of a lane's row.
+struct EllChunkRegs {
+  int32_t col[kEllChunk];
+  double val[kEllChunk];
+};
+
+__device__ __forceinline__ void ell_load(__amdgpu_buffer_rsrc_t bc, __amdgpu_buffer_rsrc_t bv, int32_t first,
+                                         int tid, EllChunkRegs &r) {
+#pragma unroll
+  for (int e = 0; e < kEllChunk; ++e) {
+    const int32_t slot = __builtin_amdgcn_readfirstlane(first + e * kThreads);
+    r.col[e] = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(bc, tid * 4, slot * 4, 0);
+    r.val[e] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(bv, tid * 8, slot * 8, 0));
+  }
+}
+
+// R <- R - A D for the directions with act[c] (rows of C directions; D is the
+// FP32 correction just solved for, in LDS or global memory; R the FP64
+// residual in global memory), and rmax[c] = max |R_i| over this thread's rows.
+// The next chunk's loads are issued before the current one is used.  A row's
+// products are summed in slot order, the same for every launch shape.
+template <int C, int NT, class T32>
+__device__ __forceinline__ void ell_residual(const EllMat AS4 &m, const T32 *__restrict__ D, double *__restrict__ R,
+                                             const bool (&act)[C], double (&rmax)[C], int tid) {
+  static_assert(NT == kThreads, "row passes are built for the kernel's workgroup");
+  const int32_t n = m.n_chunks;
+  if (n == 0) return;
+  const __amdgpu_buffer_rsrc_t bc = __builtin_amdgcn_make_buffer_rsrc((void *)m.col, 0, m.n_slots * 4, kBufWord3);
+  const __amdgpu_buffer_rsrc_t bv = __builtin_amdgcn_make_buffer_rsrc((void *)m.val, 0, m.n_slots * 8, kBufWord3);
+  const int32_t AS4 *ch = (const int32_t AS4 *)m.chunks;  // scalar loads
+  EllChunkRegs cur, nxt;
+  int32_t c_first = ch[0], c_pass = ch[1], c_flags = ch[2];
+  ell_load(bc, bv, c_first, tid, cur);
+  int32_t row = -1;
+  double rv[C], acc[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) rv[c] = acc[c] = 0.0;
+  for (int32_t k = 0; k < n; ++k) {
+    int32_t n_first = 0, n_pass = 0, n_flags = 0;
+    if (k + 1 < n) {
+      n_first = ch[4 * (k + 1)];
+      n_pass = ch[4 * (k + 1) + 1];
+      n_flags = ch[4 * (k + 1) + 2];
+      ell_load(bc, bv, n_first, tid, nxt);
+    }
+    if (c_flags & 1) {  // first chunk of a pass: the lane's row and its residual
+      row = m.rows[c_pass * NT + tid];
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        acc[c] = 0.0;
+        rv[c] = row >= 0 ? R[row * C + c] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < kEllChunk; ++e)
+#pragma unroll
+      for (int c = 0; c < C; ++c) acc[c] = fma(cur.val[e], (double)D[cur.col[e] * C + c], acc[c]);
+    if ((c_flags & 2) && row >= 0) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        if (!act[c]) continue;
+        const double r = rv[c] - acc[c];
+        R[row * C + c] = r;
+        rmax[c] = fmax(rmax[c], fabs(r));
+      }
+    }
+    cur = nxt;
+    c_first = n_first;
+    c_pass = n_pass;
+    c_flags = n_flags;
+  }
+}
+
+// Refined mode (FP32 sweeps, FP64 residuals).  Each of the two solves A x = b
+// (A = G_x for Z, G_x^T for Psi) runs
+//   d_0 = solve32(b), x = d_0, r = b - A d_0;
+//   while the direction is not converged and fewer than `refine` corrections
+//   were made:  d = solve32(r), x += d, r -= A d
+// with x and r in FP64 (global memory) and A d formed in FP64 from the FP32
+// correction d where it sits (LDS, or global memory).  A direction has
+// converged once ||r||_inf <= tol ||A||_inf ||x||_inf; it then takes no further
+// updates, so its result does not depend on the directions it shares the
+// workgroup with.  berr[c] = ||r|| / (||A|| ||x||) of the final x, steps[c]
+// the corrections made.  V1 holds b on entry (overwritten by r), V2 receives x.
 template <int C, int NT, bool TRANS, bool LDSX>
-__device__ __forceinline__ void refined_solve(const NetDesc AS4 &nd, const double *__restrict__ V1,
+__device__ __forceinline__ void refined_solve(const NetDesc AS4 &nd, double *__restrict__ V1,
                                               double *__restrict__ V2, float *__restrict__ X32,
-                                              float *s_r, int refine, int tid) {
+                                              float *s_r, double *s_red, int refine, double tol, int tid,
+                                              double (&berr)[C], int32_t (&steps)[C]) {
   const DevSweep AS4 &s1 = TRANS ? nd.Ut : nd.L;
   const DevSweep AS4 &s2 = TRANS ? nd.Lt : nd.U;
-  const int32_t *ptr = TRANS ? nd.gxt_ptr : nd.gx_ptr;
-  const int32_t *col = TRANS ? nd.gxt_col : nd.gx_col;
-  const double *val = TRANS ? nd.gxt_val : nd.gx_val;
-  for (int it = 0; it <= refine; ++it) {
-    for (int32_t i = tid; i < nd.n_x; i += NT) {
-      double r[C];
+  const EllMat AS4 &A = TRANS ? nd.gxt : nd.gx;
+  const int32_t n = nd.n_x;
+  bool act[C];
 #pragma unroll
-      for (int c = 0; c < C; ++c) r[c] = V1[i * C + c];
-      if (it > 0)
-        for (int32_t e = ptr[i]; e < ptr[i + 1]; ++e) {
-          const double v = val[e];
-          const int32_t j = col[e] * C;
+  for (int c = 0; c < C; ++c) {
+    act[c] = true;
+    steps[c] = 0;
+    berr[c] = 0.0;
+  }
+  for (int it = 0;; ++it) {
+    // right-hand side in FP32: b, then the residual
+    for (int32_t i = tid; i < n; i += NT) {
 #pragma unroll
-          for (int c = 0; c < C; ++c) r[c] = fma(-v, V2[j + c], r[c]);
-        }
-#pragma unroll
-      for (int c = 0; c < C; ++c) X32[i * C + c] = (float)r[c];
+      for (int c = 0; c < C; ++c) X32[i * C + c] = (float)V1[i * C + c];
     }
     __syncthreads();
     sweep<C, NT, float, LDSX>(s1, X32, s_r, tid);
-    pivot_scale<C, NT, float>(nd.pivinv32, X32, nd.n_x, tid);
+    pivot_scale<C, NT, float>(nd.pivinv32, X32, n, tid);
     sweep<C, NT, float, LDSX>(s2, X32, s_r, tid, nullptr, TRANS ? nd.gpt_warm : nd.proj_warm,
                               TRANS ? nd.gpt_warm_bytes : nd.proj_warm_bytes);
-    for (int32_t i = tid; i < nd.n_x; i += NT) {
+    double xmax[C], rmax[C];
 #pragma unroll
-      for (int c = 0; c < C; ++c)
-        V2[i * C + c] = (it ? V2[i * C + c] : 0.0) + (double)X32[i * C + c];
+    for (int c = 0; c < C; ++c) xmax[c] = rmax[c] = 0.0;
+    for (int32_t i = tid; i < n; i += NT) {
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        if (!act[c]) continue;
+        const double x = (it ? V2[i * C + c] : 0.0) + (double)X32[i * C + c];
+        V2[i * C + c] = x;
+        xmax[c] = fmax(xmax[c], fabs(x));
+      }
     }
-    __syncthreads();
+    ell_residual<C, NT, float>(A, X32, V1, act, rmax, tid);
+    block_max2<C, NT>(rmax, xmax, s_red, tid);
+    bool any = false;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      if (!act[c]) continue;
+      const double scale = A.norm * xmax[c];
+      berr[c] = rmax[c] == 0.0 ? 0.0 : rmax[c] / scale;
+      steps[c] = it;
+      act[c] = !(rmax[c] <= tol * scale) && it < refine;
+      any = any || act[c];
+    }
+    if (!any) break;
   }
 }
 
@@ -1111,20 +1258,34 @@ template <int C, int NT, bool LDSX>
 __device__ __forceinline__ void reduction_refined(const NetDesc AS4 &nd, const WorkItem &a,
                                                   float *__restrict__ X32, double *__restrict__ V1,
                                                   double *__restrict__ V2, double *s_slack, float *s_r,
-                                                  int refine, int32_t dir0, long long *stamps) {
+                                                  double *s_red, int refine, double tol, int32_t dir0,
+                                                  long long *stamps) {
   const int tid = threadIdx.x;
   long long *st = (stamps && tid == 0) ? stamps : nullptr;
   if (st) st[0] = wall_clock64();
   spmul<C, NT>(nd, a, V1, dir0, tid);
   __syncthreads();
   if (st) st[1] = wall_clock64();
-  refined_solve<C, NT, false, LDSX>(nd, V1, V2, X32, s_r, refine, tid);  // Z
+  double bz[C], bp[C];
+  int32_t kz[C], kp[C];
+  refined_solve<C, NT, false, LDSX>(nd, V1, V2, X32, s_r, s_red, refine, tol, tid, bz, kz);  // Z
   if (st) st[2] = st[3] = wall_clock64();
   projection<C, NT>(nd, a, V2, V1, s_slack, dir0, tid);  // V1 = -Y_x
   if (st) st[4] = wall_clock64();
-  refined_solve<C, NT, true, LDSX>(nd, V1, V2, X32, s_r, refine, tid);  // Psi
+  refined_solve<C, NT, true, LDSX>(nd, V1, V2, X32, s_r, s_red, refine, tol, tid, bp, kp);  // Psi
   if (st) st[5] = st[6] = wall_clock64();
   spmuladd<C, NT>(nd, a, V2, dir0, tid);
+  if (a.rinfo && tid == 0) {
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      if (dir0 + c >= a.k) continue;
+      double *o = a.rinfo + 4 * (int64_t)(dir0 + c);
+      o[0] = bz[c];
+      o[1] = (double)kz[c];
+      o[2] = bp[c];
+      o[3] = (double)kp[c];
+    }
+  }
   __syncthreads();
   if (st) st[7] = wall_clock64();
 }
@@ -1169,14 +1330,15 @@ __global__ __launch_bounds__(kThreadsLds) void refined_kernel_lds(const LaunchAr
   extern __shared__ float smem32[];
   __shared__ double s_slack[C];
   __shared__ float s_r[kBlockRows * C];
+  __shared__ double s_red[kWaves * 2 * C];
   double *V1 = la.scratch + (int64_t)blockIdx.x * la.scratch_stride;
   double *V2 = V1 + la.scratch_stride / 2;
   for (int32_t chunk = blockIdx.x; chunk < la.n_chunks; chunk += gridDim.x) {
     const WorkItem it = item_of(la, chunk);
     long long *st = (la.stamps && chunk == (int32_t)blockIdx.x)
                         ? la.stamps + (int64_t)blockIdx.x * kStamps : nullptr;
-    reduction_refined<C, kThreadsLds, true>(*(const NetDesc AS4 *)it.nd, it, smem32, V1, V2, s_slack, s_r, la.refine,
-                                      (chunk - it.chunk0) * C, st);
+    reduction_refined<C, kThreadsLds, true>(*(const NetDesc AS4 *)it.nd, it, smem32, V1, V2, s_slack, s_r, s_red,
+                                            la.refine, la.refine_tol, (chunk - it.chunk0) * C, st);
   }
 }
 
@@ -1185,6 +1347,7 @@ template <int C>
 __global__ __launch_bounds__(kThreads) void refined_kernel_global(const LaunchArgs la) {
   __shared__ double s_slack[C];
   __shared__ float s_r[kBlockRows * C];
+  __shared__ double s_red[kWaves * 2 * C];
   double *V1 = la.scratch + (int64_t)blockIdx.x * la.scratch_stride;
   double *V2 = V1 + la.scratch_stride / 3;
   float *X32 = reinterpret_cast<float *>(V1 + 2 * (la.scratch_stride / 3));
@@ -1192,8 +1355,8 @@ __global__ __launch_bounds__(kThreads) void refined_kernel_global(const LaunchAr
     const WorkItem it = item_of(la, chunk);
     long long *st = (la.stamps && chunk == (int32_t)blockIdx.x)
                         ? la.stamps + (int64_t)blockIdx.x * kStamps : nullptr;
-    reduction_refined<C, kThreads, false>(*(const NetDesc AS4 *)it.nd, it, X32, V1, V2, s_slack, s_r, la.refine,
-                                   (chunk - it.chunk0) * C, st);
+    reduction_refined<C, kThreads, false>(*(const NetDesc AS4 *)it.nd, it, X32, V1, V2, s_slack, s_r, s_red,
+                                          la.refine, la.refine_tol, (chunk - it.chunk0) * C, st);
   }
 }
 
@@ -1247,7 +1410,7 @@ rh_status query_info(int device, DeviceInfo &info, std::string &err) {
   info.wall_khz = wkhz;
   // leave room for the kernels' static LDS (slack scalars and block residuals)
   const size_t lds = (size_t)std::max(lds_a, lds_b);
-  const size_t fixed = (size_t)kBlockRows * 8 * sizeof(double) + 256;
+  const size_t fixed = (size_t)kBlockRows * 8 * sizeof(double) + (size_t)kWaves * 8 * sizeof(double) + 256;
   info.lds_max = lds > fixed ? lds - fixed : 0;
   return RH_OK;
 }
@@ -1357,7 +1520,7 @@ int32_t choose_c(int64_t k, int32_t cus, int64_t n_x, size_t lds_max, bool lds, 
 
 // Launch the reduction over a list of work items (host copies; their nd
 // pointers are device descriptors).  max_nx is the largest n_x among them.
-rh_status run_items(const DeviceInfo &info, Runner &r, int32_t timing, int32_t refine,
+rh_status run_items(const DeviceInfo &info, Runner &r, int32_t timing, int32_t refine, double refine_tol,
                     std::vector<WorkItem> &items, int32_t max_nx, hipStream_t s, std::string &err) {
   int64_t total_k = 0;
   for (const WorkItem &it : items) total_k += it.k;
@@ -1395,6 +1558,7 @@ rh_status run_items(const DeviceInfo &info, Runner &r, int32_t timing, int32_t r
   }
   LaunchArgs la{};
   la.refine = refine;
+  la.refine_tol = refine_tol;
   la.n_items = (int32_t)items.size();
   la.n_chunks = (int32_t)n_chunks;
   la.scratch = r.scratch;
@@ -1474,6 +1638,9 @@ rh_status run_items(const DeviceInfo &info, Runner &r, int32_t timing, int32_t r
 
 struct DeviceNet {
   std::vector<int32_t> sweep_steps;  // barrier steps of the L, U, U^T, L^T sweeps
+  double *rinfo = nullptr;           // per-column refinement figures (4 doubles per column)
+  int64_t rinfo_cols = 0;
+  int64_t bytes = 0;                 // device bytes of the network's own arrays (allocs)
   NetDesc nd{};               // host copy of the descriptor (device pointers)
   NetDesc *nd_dev = nullptr;  // the same descriptor in device memory
   std::vector<void *> allocs;
@@ -1506,6 +1673,7 @@ rh_status upload(DeviceNet &dn, const std::vector<T> &v, const T **out, std::str
   void *p = nullptr;
   HIP_TRY(hipMalloc(&p, v.size() * sizeof(T)));
   dn.allocs.push_back(p);
+  dn.bytes += (int64_t)(v.size() * sizeof(T));
   HIP_TRY(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
   *out = static_cast<const T *>(p);
   return RH_OK;
@@ -1582,6 +1750,69 @@ rh_status upload_sweep(DeviceNet *dn, const Sweep &s, int32_t n, const std::vect
   return RH_OK;
 }
 
+// A matrix in the row-pass layout of EllMat: rows by decreasing length,
+// kThreads per pass, every pass padded to a multiple of kEllChunk entries.
+rh_status upload_ell(DeviceNet *dn, std::vector<std::vector<std::pair<int32_t, double>>> &R, EllMat &m,
+                     std::string &err) {
+  const int32_t n = (int32_t)R.size();
+  std::vector<int32_t> order(n);
+  double norm = 0.0;
+  for (int32_t i = 0; i < n; ++i) {
+    order[i] = i;
+    std::sort(R[i].begin(), R[i].end());
+    double s = 0.0;
+    for (auto &pr : R[i]) s += std::fabs(pr.second);
+    norm = std::max(norm, s);
+  }
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t b) { return R[a].size() > R[b].size(); });
+  const int32_t npass = (n + kThreads - 1) / kThreads;
+  std::vector<int32_t> rows((size_t)npass * kThreads, -1), chunks;
+  std::vector<int32_t> first(npass), width(npass);
+  int64_t slots = 0;
+  for (int32_t p = 0; p < npass; ++p) {
+    const int32_t longest = (int32_t)R[order[(size_t)p * kThreads]].size();
+    const int32_t E = std::max(kEllChunk, (longest + kEllChunk - 1) / kEllChunk * kEllChunk);
+    first[p] = (int32_t)slots;
+    width[p] = E;
+    for (int32_t e0 = 0; e0 < E; e0 += kEllChunk) {
+      chunks.push_back((int32_t)(slots + (int64_t)e0 * kThreads));
+      chunks.push_back(p);
+      chunks.push_back((e0 == 0 ? 1 : 0) | (e0 + kEllChunk >= E ? 2 : 0));
+      chunks.push_back(0);
+    }
+    slots += (int64_t)E * kThreads;
+  }
+  if (slots * 8 >= 0x7fffffff) {
+    err = "network too large for the residual layout";
+    return RH_EINVAL;
+  }
+  std::vector<int32_t> col((size_t)slots, 0);
+  std::vector<double> val((size_t)slots, 0.0);
+  for (int32_t p = 0; p < npass; ++p)
+    for (int32_t t = 0; t < kThreads && (int64_t)p * kThreads + t < n; ++t) {
+      const int32_t i = order[(size_t)p * kThreads + t];
+      rows[(size_t)p * kThreads + t] = i;
+      for (size_t e = 0; e < R[i].size(); ++e) {
+        const size_t k = (size_t)first[p] + e * kThreads + t;
+        col[k] = R[i][e].first;
+        val[k] = R[i][e].second;
+      }
+    }
+  Blob bl;
+  const int64_t o_ch = bl.add(chunks), o_rows = bl.add(rows), o_col = bl.add(col), o_val = bl.add(val);
+  const char *base = nullptr;
+  UP(bl.h, base);
+  m.n_chunks = (int32_t)(chunks.size() / 4);
+  m.n_slots = (int32_t)slots;
+  m.chunks = at_off<int4>(base, o_ch);
+  m.rows = at_off<int32_t>(base, o_rows);
+  m.col = at_off<int32_t>(base, o_col);
+  m.val = at_off<double>(base, o_val);
+  m.norm = norm;
+  return RH_OK;
+}
+
 }  // namespace
 
 rh_status device_set(int32_t device, std::string &err) {
@@ -1593,6 +1824,7 @@ void device_free(Network &net) {
   if (!net.dev) return;
   (void)hipDeviceSynchronize();
   for (void *p : net.dev->allocs) (void)hipFree(p);
+  if (net.dev->rinfo) (void)hipFree(net.dev->rinfo);
   runner_free(net.dev->run);
   delete net.dev;
   net.dev = nullptr;
@@ -1641,14 +1873,21 @@ rh_status device_ctx_collect(Context &ctx, rh_report &rep, std::string &err) {
 rh_status device_upload(Network &net, std::string &err) {
   HIP_TRY(hipSetDevice(net.ctx->device));
   Runner keep;  // keep the launch resources across operating points
+  double *keep_rinfo = nullptr;
+  int64_t keep_cols = 0;
   if (net.dev) {
     keep = net.dev->run;
     net.dev->run = Runner();
+    keep_rinfo = net.dev->rinfo;
+    keep_cols = net.dev->rinfo_cols;
+    net.dev->rinfo = nullptr;
     device_free(net);
   }
   DeviceNet *dn = new DeviceNet();
   net.dev = dn;
   dn->run = keep;
+  dn->rinfo = keep_rinfo;
+  dn->rinfo_cols = keep_cols;
   rh_status qs = query_info(net.ctx->device, dn->info, err);
   if (qs != RH_OK) return qs;
 
@@ -1826,33 +2065,14 @@ rh_status device_upload(Network &net, std::string &err) {
         rows[ip].push_back({jp, net.gx.val[e]});
         trows[jp].push_back({ip, net.gx.val[e]});
       }
-    for (int t = 0; t < 2; ++t) {
-      auto &R = t ? trows : rows;
-      std::vector<int32_t> ptr(nx + 1, 0), col;
-      std::vector<double> val;
-      for (int32_t i = 0; i < nx; ++i) {
-        std::sort(R[i].begin(), R[i].end());
-        for (auto &pr : R[i]) {
-          col.push_back(pr.first);
-          val.push_back(pr.second);
-        }
-        ptr[i + 1] = (int32_t)col.size();
-      }
-      if (t) {
-        UP(ptr, nd.gxt_ptr);
-        UP(col, nd.gxt_col);
-        UP(val, nd.gxt_val);
-      } else {
-        UP(ptr, nd.gx_ptr);
-        UP(col, nd.gx_col);
-        UP(val, nd.gx_val);
-      }
-    }
+    if (upload_ell(dn, rows, nd.gx, err) != RH_OK || upload_ell(dn, trows, nd.gxt, err) != RH_OK)
+      return RH_EDEVICE;
   }
   {
     void *p = nullptr;
     HIP_TRY(hipMalloc(&p, sizeof(NetDesc)));
     dn->allocs.push_back(p);
+    dn->bytes += (int64_t)sizeof(NetDesc);
     HIP_TRY(hipMemcpy(p, &dn->nd, sizeof(NetDesc), hipMemcpyHostToDevice));
     dn->nd_dev = static_cast<NetDesc *>(p);
   }
@@ -1886,8 +2106,23 @@ rh_status device_hvp(Network &net, int32_t k, const double *dW, int64_t ldw, dou
   it.ldhw = ldhw;
   it.k = k;
   it.identity_from = identity_from;
+  it.rinfo = nullptr;
   const int32_t refine = prec == RH_FP32_REFINED ? net.ctx->refine : -1;
-  rh_status s = run_items(dn->info, dn->run, net.ctx->timing, refine, items, net.n_x,
+  if (refine >= 0) {
+    // per-column refinement figures: columns 0 .. k - 1 of the call, or the
+    // identity block's own columns of the full Hessian
+    const int64_t cols = identity_from >= 0 ? (int64_t)net.n_p : (int64_t)k;
+    if (cols > dn->rinfo_cols) {
+      HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+      if (dn->rinfo) HIP_TRY(hipFree(dn->rinfo));
+      dn->rinfo = nullptr;
+      dn->rinfo_cols = 0;
+      HIP_TRY(hipMalloc(&dn->rinfo, (size_t)cols * 4 * sizeof(double)));
+      dn->rinfo_cols = cols;
+    }
+    it.rinfo = dn->rinfo + 4 * (int64_t)(identity_from >= 0 ? identity_from : 0);
+  }
+  rh_status s = run_items(dn->info, dn->run, net.ctx->timing, refine, net.ctx->refine_tol, items, net.n_x,
                           (hipStream_t)stream, err);
   net.report.dirs_per_group = dn->run.last_c;
   return s;
@@ -1916,13 +2151,40 @@ rh_status device_hvp_batch(Context &ctx, int32_t n, Network *const *nets, const 
     it.ldhw = ldhw[i];
     it.k = k[i];
     it.identity_from = identity_from ? identity_from[i] : -1;
+    it.rinfo = nullptr;  // batched calls record no per-column refinement figures
     items.push_back(it);
     max_nx = std::max(max_nx, net.n_x);
   }
   if (items.empty()) return RH_OK;
   const int32_t refine = prec == RH_FP32_REFINED ? ctx.refine : -1;
-  return run_items(ctx.dev->info, ctx.dev->on(stream), ctx.timing, refine, items, max_nx,
+  return run_items(ctx.dev->info, ctx.dev->on(stream), ctx.timing, refine, ctx.refine_tol, items, max_nx,
                    (hipStream_t)stream, err);
+}
+
+rh_status device_refinement_report(Network &net, int32_t n, std::vector<double> &out, std::string &err) {
+  DeviceNet *dn = net.dev;
+  if (!dn || !dn->rinfo || n > dn->rinfo_cols) {
+    err = "no refined product recorded for these columns";
+    return RH_ESTATE;
+  }
+  out.assign((size_t)n * 4, 0.0);
+  if (n == 0) return RH_OK;
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(out.data(), dn->rinfo, out.size() * sizeof(double), hipMemcpyDeviceToHost));
+  return RH_OK;
+}
+
+int64_t device_network_bytes(const Network &net) {
+  const DeviceNet *dn = net.dev;
+  if (!dn) return 0;
+  return dn->bytes + dn->rinfo_cols * 4 * (int64_t)sizeof(double) + (int64_t)dn->run.scratch_bytes;
+}
+
+int64_t device_scratch_per_direction(int32_t n_x, rh_precision prec) {
+  // per-workgroup scratch of run_items, per direction it owns, with the
+  // vector in global memory (the larger case): FP64 Y_x and X; refined V1,
+  // V2 and the FP32 correction
+  return (prec == RH_FP32_REFINED ? 2 * 8 + 4 : 2 * 8) * (int64_t)n_x;
 }
 
 rh_status device_alloc(void **p, size_t bytes, std::string &err) {

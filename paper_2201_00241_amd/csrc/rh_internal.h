@@ -112,7 +112,8 @@ struct DeviceCtx;  // likewise: a context's resources for batched launches
 struct Context {
   int32_t device = -1;  // -1: host only
   int32_t timing = 0;  // 0 off, 1 launch events, 2 also in-kernel phase stamps
-  int32_t refine = 2;  // refined mode: correction steps after the first FP32 solve
+  int32_t refine = 4;  // refined mode: at most this many corrections after the first FP32 solve
+  double refine_tol = 1e-13;  // refined mode: a direction stops once its backward error is <= this
   DeviceCtx *dev = nullptr;
 };
 
@@ -159,6 +160,7 @@ struct Network {
   rh_report report{};
   DeviceNet *dev = nullptr;
   int32_t tuned_k[2] = {0, 0};  // full-Hessian block size chosen per precision (0: not yet)
+  int32_t refined_cols = -1;    // columns of the last refined product call (-1: none)
 };
 
 // ---- host planner (network.cpp)
@@ -207,6 +209,14 @@ rh_status device_memcpy_h2d(void *dst, const void *src, size_t bytes, std::strin
 rh_status device_memcpy_d2h(void *dst, const void *src, size_t bytes, std::string &err);
 rh_status device_memcpy_2d(void *dst, size_t dpitch, const void *src, size_t spitch,
                            size_t width, size_t rows, int to_device, std::string &err);
+// Per-column figures of the last refined product call: 4 doubles per column
+// {backward error of Z, corrections of Z, backward error of Psi, corrections of Psi}.
+rh_status device_refinement_report(Network &net, int32_t n, std::vector<double> &out, std::string &err);
+// Device bytes held by the network (factors, schedules, coefficients,
+// descriptors, its launch scratch and report buffers), and the launch
+// scratch a direction of a network with n_x states may take.
+int64_t device_network_bytes(const Network &net);
+int64_t device_scratch_per_direction(int32_t n_x, rh_precision prec);
 rh_status device_alloc(void **p, size_t bytes, std::string &err);
 void device_release(void *p);
 rh_status device_sync(void *stream, std::string &err);

@@ -69,6 +69,7 @@ _SIGS = {
     "rh_context_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "rh_context_set_timing": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "rh_context_set_refinement": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "rh_context_set_refinement_tol": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double]),
     "rh_network_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(rh_network_desc),
                                          ctypes.POINTER(ctypes.c_void_p)]),
     "rh_network_destroy": (ctypes.c_int, [ctypes.c_void_p]),
@@ -101,6 +102,11 @@ _SIGS = {
                                            ctypes.POINTER(ctypes.c_int64), _i32p,
                                            ctypes.c_int, ctypes.c_void_p]),
     "rh_last_report": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(rh_report)]),
+    "rh_network_device_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
+                                               ctypes.POINTER(ctypes.c_int64),
+                                               ctypes.POINTER(ctypes.c_int64)]),
+    "rh_refinement_report": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _f64p, _i32p, _f64p,
+                                            _i32p]),
     "rh_context_report": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(rh_report)]),
     "rh_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "rh_last_error": (ctypes.c_char_p, []),
@@ -170,6 +176,10 @@ def rh_context_set_timing(ctx, level) -> None:
 
 def rh_context_set_refinement(ctx, steps: int) -> None:
     _check(load().rh_context_set_refinement(ctx, int(steps)))
+
+
+def rh_context_set_refinement_tol(ctx, tol: float) -> None:
+    _check(load().rh_context_set_refinement_tol(ctx, float(tol)))
 
 
 def rh_network_create(ctx, grid):
@@ -318,6 +328,22 @@ def rh_last_report(net) -> dict:
     return r.as_dict()
 
 
+def rh_network_device_bytes(net, prec=RH_FP64):
+    """(resident bytes, launch scratch bytes per direction) of a network."""
+    r, d = ctypes.c_int64(), ctypes.c_int64()
+    _check(load().rh_network_device_bytes(net, int(prec), ctypes.byref(r), ctypes.byref(d)))
+    return r.value, d.value
+
+
+def rh_refinement_report(net, n: int) -> dict:
+    """Per-column backward errors and correction counts of the last refined call."""
+    bz, bp = np.zeros(n), np.zeros(n)
+    kz, kp = np.zeros(n, np.int32), np.zeros(n, np.int32)
+    _check(load().rh_refinement_report(net, int(n), _p(bz, _f64p), _p(kz, _i32p), _p(bp, _f64p),
+                                       _p(kp, _i32p)))
+    return {"berr_z": bz, "steps_z": kz, "berr_psi": bp, "steps_psi": kp}
+
+
 def rh_status_string(s: int) -> str:
     return load().rh_status_string(int(s)).decode()
 
@@ -337,6 +363,9 @@ class Context:
 
     def set_refinement(self, steps: int):
         rh_context_set_refinement(self.h, steps)
+
+    def set_refinement_tol(self, tol: float):
+        rh_context_set_refinement_tol(self.h, tol)
 
     def report(self):
         return rh_context_report(self.h)
@@ -390,6 +419,8 @@ class Network:
     hvp = lambda self, W, prec=RH_FP64: rh_hvp(self.h, W, prec)  # noqa: E731
     reduced_hessian = lambda self, k_block=0, prec=RH_FP64: rh_reduced_hessian(self.h, k_block, prec)  # noqa
     report = lambda self: rh_last_report(self.h)  # noqa: E731
+    refinement_report = lambda self, n: rh_refinement_report(self.h, n)  # noqa: E731
+    device_bytes = lambda self, prec=RH_FP64: rh_network_device_bytes(self.h, prec)  # noqa: E731
 
     def hvp_device(self, W, HW, stream=None, prec=RH_FP64):
         """W, HW: torch float64 CUDA tensors of shape (k, n_p) (row j = direction j)."""

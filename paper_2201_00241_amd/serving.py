@@ -2,15 +2,25 @@
 
 Requests ask for k Hessian-vector products of one resident network (a grid
 at an operating point whose LU factors, adjoint and branch coefficients stay
-on the device) or for its full reduced Hessian.  The server splits every
-request into work items of at most `block` directions (a full Hessian becomes
-identity blocks, Sec. 5.3) and keeps up to `max_inflight` batched launches in
-flight, each on its own stream.  Whenever a launch completes, the items that
-arrived meanwhile are admitted into the next launch, as far as the direction
-budget per launch and the device-memory budget allow; a request's blocks may
-be spread over several launches.  Every direction's arithmetic is independent
-of the launch it lands in, so a result is bitwise the same alone and in the
-mix.
+on the device) or for its full reduced Hessian, in FP64 or in the refined
+FP32 mode.  The server splits every request into work items of at most
+`block` directions (a full Hessian becomes identity blocks, Sec. 5.3) and
+keeps up to `max_inflight` batched launches in flight, each on its own
+stream.  Whenever a launch completes, the items that arrived meanwhile are
+admitted into the next launch, as far as the direction budget per launch and
+the device-memory budget allow; a request's blocks may be spread over several
+launches.  A launch carries one precision.  Every direction's arithmetic is
+independent of the launch it lands in, so a result is bitwise the same alone
+and in the mix.
+
+Admission counts device memory: the resident bytes of every network (held
+for the server's lifetime) are taken off the budget at start; a request then
+needs its W and H W buffers plus the launch scratch of its directions.
+
+Failures: a request whose directions are not finite is rejected at arrival.
+If a batched launch fails, each request in it is retried alone; a request that
+fails alone is evicted (its buffers released, `error` set) and the others
+continue.
 
 All computation runs in librh (rh_hvp_batch_device); this module only
 schedules, moves buffers and measures latency.
@@ -33,11 +43,14 @@ class Request:
     k: int                        # directions; 0 = the full reduced Hessian
     W: np.ndarray | None = None   # host directions (n_p x k), None for a full Hessian
     arrival: float = 0.0          # scheduled arrival, seconds from the start
+    prec: int = rh.RH_FP64
     # filled by the server
     result: np.ndarray | None = None
+    error: str | None = None
     t_first_launch: float = -1.0
     t_done: float = -1.0
     launches: int = 0
+    retried: bool = False
     _dW: object = None
     _dHW: object = None
     _blocks_left: int = 0
@@ -62,15 +75,10 @@ class _Launch:
     items: list = field(default_factory=list)
 
 
-def footprint_bytes(n_p: int, k: int) -> int:
-    """Device bytes a request holds while admitted: its W and H W blocks."""
-    return (2 * k if k else n_p) * n_p * 8
-
-
 class Server:
     def __init__(self, ctx: rh.Context, networks: dict, max_inflight: int = 3,
                  dirs_per_launch: int = 4096, block: int = 256,
-                 mem_budget_bytes: int = 32 << 30):
+                 mem_budget_bytes: int = 64 << 30, keep_results: bool = True):
         import torch
 
         self.torch = torch
@@ -79,16 +87,30 @@ class Server:
         self.max_inflight = max_inflight
         self.dirs_per_launch = dirs_per_launch
         self.block = block
-        self.mem_budget = mem_budget_bytes
+        self.keep_results = keep_results
         self.streams = [torch.cuda.Stream() for _ in range(max_inflight)]
+        self.resident = {key: n.device_bytes()[0] for key, n in networks.items()}
+        self.mem_budget = mem_budget_bytes
+        self.budget_left = mem_budget_bytes - sum(self.resident.values())
+        if self.budget_left <= 0:
+            raise ValueError("resident networks exceed the device-memory budget")
+
+    def footprint_bytes(self, req: Request) -> int:
+        """Device bytes a request holds while admitted: W and H W, and the launch
+        scratch of as many of its directions as one launch may run."""
+        net = self.nets[req.key]
+        kk = req.k if req.k else net.n_p
+        _, per_dir = net.device_bytes(req.prec)
+        bufs = (2 * req.k if req.k else net.n_p) * net.n_p * 8
+        return bufs + min(kk, self.dirs_per_launch) * per_dir
 
     # ---- request life cycle -------------------------------------------------
     def _admit(self, req: Request) -> bool:
         """Allocate the request's device buffers if the memory budget allows."""
         torch = self.torch
         net = self.nets[req.key]
-        nbytes = footprint_bytes(net.n_p, req.k)
-        if self._mem_used + nbytes > self.mem_budget:
+        nbytes = self.footprint_bytes(req)
+        if self._mem_used + nbytes > self.budget_left:
             return False
         kk = req.k if req.k else net.n_p
         if req.k:
@@ -101,7 +123,12 @@ class Server:
             self._items.append(_Item(req, j0, min(self.block, kk - j0)))
         return True
 
-    def _launch(self, stream, items, now):
+    def _release(self, req: Request):
+        req._dW = req._dHW = None
+        self._mem_used -= req._bytes
+        req._bytes = 0
+
+    def _enqueue(self, stream, items, prec):
         torch = self.torch
         nets, ks, dWs, ldws, dHWs, ldhws, idf = [], [], [], [], [], [], []
         for it in items:
@@ -119,26 +146,57 @@ class Server:
             ldws.append(net.n_p)
             dHWs.append(r._dHW[it.j0].data_ptr())
             ldhws.append(net.n_p)
-            if r.t_first_launch < 0:
-                r.t_first_launch = now
-            r.launches += 1
         stream.wait_stream(torch.cuda.current_stream())  # uploads of admitted W blocks
         with torch.cuda.stream(stream):
             rh.rh_hvp_batch_device(self.ctx.h, nets, ks, dWs, ldws, dHWs, ldhws,
-                                   identity_from=idf, stream=stream.cuda_stream)
+                                   identity_from=idf, prec=prec, stream=stream.cuda_stream)
             ev = torch.cuda.Event()
             ev.record(stream)
-        return _Launch(stream, ev, items)
+        return ev
+
+    def _launch(self, stream, items, now, done):
+        prec = items[0].req.prec
+        for it in items:
+            if it.req.t_first_launch < 0:
+                it.req.t_first_launch = now
+            it.req.launches += 1
+        try:
+            return _Launch(stream, self._enqueue(stream, items, prec), items)
+        except rh.RhError:
+            pass
+        # the batched launch failed: retry each request alone; a request that
+        # fails alone is evicted
+        ok = []
+        by_req = {}
+        for it in items:
+            by_req.setdefault(it.req.rid, []).append(it)
+        for its in by_req.values():
+            r = its[0].req
+            r.retried = True
+            try:
+                self._enqueue(stream, its, prec)
+                ok.extend(its)
+            except rh.RhError as e:
+                r.error = str(e)
+                r.t_done = time.perf_counter() - self._t0
+                self._items = deque(x for x in self._items if x.req is not r)
+                self._release(r)
+                done.append(r)
+        ev = self.torch.cuda.Event()
+        ev.record(stream)
+        return _Launch(stream, ev, ok)
 
     def _finish(self, launch: _Launch, now: float, done: list):
         for it in launch.items:
             r = it.req
+            if r.error is not None:  # evicted after this launch was enqueued
+                continue
             r._blocks_left -= 1
             if r._blocks_left == 0:
                 r.t_done = now
-                r.result = r._dHW.cpu().numpy().T
-                r._dW = r._dHW = None
-                self._mem_used -= r._bytes
+                if self.keep_results:
+                    r.result = r._dHW.cpu().numpy().T
+                self._release(r)
                 done.append(r)
 
     # ---- event loop ---------------------------------------------------------
@@ -151,11 +209,20 @@ class Server:
         inflight: list = []
         done: list = []
         free_streams = list(self.streams)
-        t0 = time.perf_counter()
+        self._t0 = t0 = time.perf_counter()
         while pending or waiting or self._items or inflight:
             now = time.perf_counter() - t0
             while pending and pending[0].arrival <= now:
-                waiting.append(pending.popleft())
+                r = pending.popleft()
+                if r.k and not np.all(np.isfinite(r.W)):
+                    r.error = "directions are not finite"
+                elif self.footprint_bytes(r) > self.budget_left:
+                    r.error = "request exceeds the device-memory budget"
+                if r.error is not None:
+                    r.t_done = now
+                    done.append(r)
+                    continue
+                waiting.append(r)
             for L in list(inflight):
                 if L.event.query():
                     inflight.remove(L)
@@ -164,14 +231,22 @@ class Server:
             while waiting and self._admit(waiting[0]):
                 waiting.popleft()
             if self._items and free_streams:
-                batch, dirs = [], 0
-                while self._items and dirs + self._items[0].kb <= self.dirs_per_launch:
+                # the next launch: blocks of the head item's precision, in order
+                prec = self._items[0].req.prec
+                batch, dirs, rest = [], 0, deque()
+                while self._items:
                     it = self._items.popleft()
-                    batch.append(it)
-                    dirs += it.kb
-                if not batch:  # one block larger than the budget: launch it alone
-                    batch.append(self._items.popleft())
-                inflight.append(self._launch(free_streams.pop(0), batch, now))
+                    if it.req.prec == prec and dirs + it.kb <= self.dirs_per_launch:
+                        batch.append(it)
+                        dirs += it.kb
+                    elif it.req.prec == prec and not batch:
+                        batch.append(it)  # one block larger than the budget: alone
+                        dirs += it.kb
+                    else:
+                        rest.append(it)
+                self._items = rest
+                L = self._launch(free_streams.pop(0), batch, now, done)
+                inflight.append(L)
                 continue
             if not inflight and not self._items and not waiting and pending:
                 time.sleep(max(0.0, min(pending[0].arrival - now, 1e-3)))
@@ -182,6 +257,6 @@ class Server:
 
 
 def latency_summary(reqs: list) -> dict:
-    lat = np.array([r.latency for r in reqs]) * 1e3
+    lat = np.array([r.latency for r in reqs if r.error is None]) * 1e3
     return {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "mean_ms": float(lat.mean()), "n": int(lat.size)}

@@ -139,3 +139,16 @@ def test_parameter_changes_invalidate_the_solution(ctx):
     bad = p.copy()
     bad[1] = np.inf
     assert _status(net.set_parameters, bad) == rh.RH_EINVAL
+
+
+def test_refinement_figures_need_a_refined_call(ctx):
+    net = rh.Network(ctx, gridgen.config_grid("c0", 0))
+    net.solve()
+    assert _status(net.refinement_report, 1) == rh.RH_ESTATE
+    assert _status(ctx.set_refinement_tol, -1.0) == rh.RH_EINVAL
+    assert _status(ctx.set_refinement_tol, float("nan")) == rh.RH_EINVAL
+    assert _status(ctx.set_refinement, 17) == rh.RH_EINVAL
+    ctx.set_refinement_tol(1e-13)
+    resident, per_dir = net.device_bytes(rh.RH_FP32_REFINED)
+    assert resident == 0  # host-only context: nothing on a device
+    assert per_dir == 20 * net.n_x
