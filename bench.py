@@ -79,8 +79,9 @@ def mean_bytes_per_launch(rep, g, n_p, k):
 
 
 def host_cpu():
-    """CPU model and the number of cores this process may use (at most 16,
-    the host share of one GPU on a shared box)."""
+    """CPU model and the number of cores this process may use: the affinity
+    set, capped by the cgroup CPU quota when one is set, and at 16 (the host
+    share of one GPU on a shared box)."""
     model = "unknown"
     try:
         for line in open("/proc/cpuinfo"):
@@ -93,28 +94,37 @@ def host_cpu():
         n = len(os.sched_getaffinity(0))
     except AttributeError:
         n = os.cpu_count() or 1
-    return model, max(1, min(n, 16))
+    quota = None
+    try:
+        q, period = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        if q != "max":
+            quota = float(q) / float(period)
+    except (OSError, ValueError):
+        pass
+    if quota is not None:
+        n = min(n, max(1, int(quota)))
+    return model, max(1, min(n, 16)), quota
 
 
-def _oracle_worker(config, k, lo, hi, barrier, out):
+def _oracle_worker(config, lo, hi, barrier, out):
     """One process of the multi-core baseline: its own oracle set-up (Newton,
-    SuperLU, lambda), then identity blocks [lo, hi) of the full Hessian,
-    timed from a barrier shared with the other workers."""
-    os.environ["OMP_NUM_THREADS"] = "1"
+    SuperLU, lambda), then identity columns [lo, hi) of the full Hessian as
+    one block, timed from a barrier shared with the other workers."""
     sys.path.insert(0, str(ROOT))
     import gridgen
     from oracle import solve
 
     s = solve(gridgen.config_grid(config, 0))
     n_p = s.o.n_p
+    W = np.zeros((n_p, hi - lo))
+    W[np.arange(lo, hi), np.arange(hi - lo)] = 1.0
     barrier.wait()
     t0 = time.perf_counter()
-    for j0 in range(lo, hi, k):
-        kb = min(k, hi - j0)
-        W = np.zeros((n_p, kb))
-        W[np.arange(j0, j0 + kb), np.arange(kb)] = 1.0
-        s.hvp(W)
+    s.hvp(W)
     out.put((hi - lo, time.perf_counter() - t0))
+
+
+_THREAD_VARS = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS", "BLIS_NUM_THREADS")
 
 
 def cpu_baseline(config, g, k, budget_s=12.0):
@@ -139,31 +149,42 @@ def cpu_baseline(config, g, k, budget_s=12.0):
         done += kb
     el = time.perf_counter() - t1
     one_core = done / el
-    model, cores = host_cpu()
-    # contiguous column ranges, one per process, rounded to whole blocks of 16
-    step = max(16, -(-n_p // cores // 16) * 16)
+    model, cores, quota = host_cpu()
+    # contiguous column ranges, one per process; every process runs one
+    # thread (the variables are set before the children import numpy)
+    step = -(-n_p // cores)
     ranges = [(lo, min(n_p, lo + step)) for lo in range(0, n_p, step)]
     ctx = mp.get_context("spawn")
     barrier = ctx.Barrier(len(ranges))
     q = ctx.Queue()
-    procs = [ctx.Process(target=_oracle_worker, args=(config, 16, lo, hi, barrier, q))
-             for lo, hi in ranges]
-    for p in procs:
-        p.start()
-    res = [q.get(timeout=600) for _ in procs]
-    for p in procs:
-        p.join()
+    saved = {v: os.environ.get(v) for v in _THREAD_VARS}
+    for v in _THREAD_VARS:
+        os.environ[v] = "1"
+    try:
+        procs = [ctx.Process(target=_oracle_worker, args=(config, lo, hi, barrier, q))
+                 for lo, hi in ranges]
+        for p in procs:
+            p.start()
+        res = [q.get(timeout=600) for _ in procs]
+        for p in procs:
+            p.join()
+    finally:
+        for v, val in saved.items():
+            if val is None:
+                os.environ.pop(v, None)
+            else:
+                os.environ[v] = val
     cols = sum(r[0] for r in res)
     wall = max(r[1] for r in res)
     return {
         "value": cols / wall, "unit": "HVP/s", "cores": len(ranges), "kind": "oracle",
-        "cpu_model": model,
+        "cpu_model": model, "cgroup_cpu_quota": quota,
         "one_core": {"value": one_core, "unit": "HVP/s", "cores": 1,
                      "sample": f"{done} of {n_p} identity directions in k={k} blocks ({el:.1f} s)"},
         "sample": f"all {n_p} identity directions of the full Hessian, split into {len(ranges)} "
-                  f"contiguous column ranges over {len(ranges)} processes (SciPy SuperLU, one "
-                  f"thread each, k=16 blocks), {wall:.2f} s from a common start; each process's "
-                  f"Newton+LU+lambda set-up ({setup:.1f} s on one core) not included",
+                  f"contiguous column ranges of up to {step}, one per process (SciPy SuperLU, one "
+                  f"thread each, each range one block), {wall:.2f} s from a common start; each "
+                  f"process's Newton+LU+lambda set-up ({setup:.1f} s on one core) not included",
     }
 
 
