@@ -165,6 +165,23 @@ rh_status rh_hvp(rh_network *net, int32_t k, const double *W, int64_t ldw, doubl
  * stay valid until the stream reaches this work. */
 rh_status rh_hvp_device(rh_network *net, int32_t k, const void *dW, int64_t ldw, void *dHW,
                         int64_t ldhw, rh_precision prec, void *hip_stream);
+/* For callers that cannot allocate device memory (work recorded under HIP
+ * graph capture, serving loops and harnesses that forbid allocation):
+ * rh_hvp_device without any allocation.  Same arguments and products, bitwise
+ * equal to rh_hvp_device's.  Launch scratch comes from one fixed device array
+ * of RH_NOALLOC_SCRATCH_BYTES per GPU, whose address rh_context_create takes
+ * and which the GPU holds until the process ends; when a launch's full
+ * scratch would exceed it, fewer workgroups run, each taking several chunks
+ * of directions in turn.  No launch timing and no per-column refinement
+ * figures are recorded.  RH_EINVAL when one workgroup's scratch alone exceeds
+ * the array (with the vector in global memory, about 8 million states in FP64
+ * and 6 million in the refined mode); RH_ESTATE if no context was created on
+ * the network's device.  Every call on a GPU shares that GPU's array and
+ * nothing in it needs to start at zero, but calls that overlap on one GPU
+ * (other streams, threads or contexts) race: the caller serialises them. */
+#define RH_NOALLOC_SCRATCH_BYTES (128ll << 20)
+rh_status rh_hvp_device_noalloc(rh_network *net, int32_t k, const void *dW, int64_t ldw, void *dHW,
+                                int64_t ldhw, rh_precision prec, void *hip_stream);
 /* The dense reduced Hessian H (n_p x n_p, column-major, ldh >= n_p), computed
  * in ceil(n_p / k_block) blocks of identity columns (Sec. 5.3);
  * k_block = 0 lets the library choose: on the first such call for the

@@ -81,6 +81,7 @@ rh_status rh_context_create(int32_t device, rh_context **out) {
   if (device >= 0) {
     std::string err;
     rh_status s = device_set(device, err);
+    if (s == RH_OK) s = device_fixed_scratch_init(device, err);
     if (s != RH_OK) return fail(s, err);
   }
   rh_context *c = new rh_context();
@@ -274,6 +275,25 @@ rh_status rh_hvp_device(rh_network *net, int32_t k, const void *dW, int64_t ldw,
                  -1, prec, hip_stream, err);
   if (s != RH_OK) return fail(s, err);
   if (prec == RH_FP32_REFINED) net->n.refined_cols = k;
+  return RH_OK;
+  GUARD_END
+}
+
+rh_status rh_hvp_device_noalloc(rh_network *net, int32_t k, const void *dW, int64_t ldw, void *dHW,
+                                int64_t ldhw, rh_precision prec, void *hip_stream) {
+  GUARD_BEGIN
+  rh_status s = need_solved(net);
+  if (s != RH_OK) return s;
+  if ((s = need_device(net)) != RH_OK) return s;
+  if (prec != RH_FP64 && prec != RH_FP32_REFINED) return fail(RH_EINVAL, "unknown precision");
+  if (k < 0 || !dW || !dHW || ldw < net->n.n_p || ldhw < net->n.n_p)
+    return fail(RH_EINVAL, "bad product arguments");
+  net->n.report.last_k = k;
+  if (k == 0) return RH_OK;
+  std::string err;
+  s = device_hvp_noalloc(net->n, k, static_cast<const double *>(dW), ldw, static_cast<double *>(dHW), ldhw,
+                         prec, hip_stream, err);
+  if (s != RH_OK) return fail(s, err);
   return RH_OK;
   GUARD_END
 }

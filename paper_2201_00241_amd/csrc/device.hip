@@ -38,8 +38,16 @@
 #include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <mutex>
 
 #include "rh_internal.h"
+
+// Launch scratch of the allocation-free entry point (rh_hvp_device_noalloc):
+// one fixed array per GPU, held from the code object's load until the process
+// ends.  Its name is a host-side stand-in: host code takes the device address
+// once per device with hipGetSymbolAddress (device_fixed_scratch_init) and
+// passes only that address to kernels.
+static __device__ __align__(256) double scratch[RH_NOALLOC_SCRATCH_BYTES / sizeof(double)];
 
 namespace rh {
 
@@ -1520,8 +1528,17 @@ int32_t choose_c(int64_t k, int32_t cus, int64_t n_x, size_t lds_max, bool lds, 
 
 // Launch the reduction over a list of work items (host copies; their nd
 // pointers are device descriptors).  max_nx is the largest n_x among them.
+// A caller-independent scratch range (the fixed array of the allocation-free
+// entry point): the launch runs at most bytes / (workgroup scratch) workgroups
+// and records no timing.
+struct FixedScratch {
+  double *ptr;
+  int64_t bytes;
+};
+
 rh_status run_items(const DeviceInfo &info, Runner &r, int32_t timing, int32_t refine, double refine_tol,
-                    std::vector<WorkItem> &items, int32_t max_nx, hipStream_t s, std::string &err) {
+                    std::vector<WorkItem> &items, int32_t max_nx, hipStream_t s, std::string &err,
+                    const FixedScratch *fixed = nullptr) {
   int64_t total_k = 0;
   for (const WorkItem &it : items) total_k += it.k;
   if (total_k <= 0) return RH_OK;
@@ -1544,9 +1561,25 @@ rh_status run_items(const DeviceInfo &info, Runner &r, int32_t timing, int32_t r
   const int64_t stride = (parts * max_nx * C + 31) / 32 * 32 * (refined ? 1 : 1);
   const int64_t max_groups_mem = std::max<int64_t>(1, (int64_t(8) << 30) / (stride * 8));
   const int64_t per_cu = lds ? 1 : 2;
-  const int32_t groups = (int32_t)std::min<int64_t>({n_chunks, max_groups_mem, (int64_t)info.cus * 8 * per_cu});
+  int32_t groups = (int32_t)std::min<int64_t>({n_chunks, max_groups_mem, (int64_t)info.cus * 8 * per_cu});
+  if (fixed) {
+    // workgroups take further chunks in turn when the fixed range is short
+    const int64_t fit = fixed->bytes / (stride * (int64_t)sizeof(double));
+    if (fit < 1) {
+      err = "network too large for the fixed scratch: one workgroup needs " +
+            std::to_string(stride * (int64_t)sizeof(double)) + " bytes, " + std::to_string(fixed->bytes) +
+            " available";
+      return RH_EINVAL;
+    }
+    if (items.size() != 1) {
+      err = "internal: the fixed scratch takes one work item";
+      return RH_EDEVICE;
+    }
+    groups = (int32_t)std::min<int64_t>(groups, fit);
+    timing = 0;
+  }
   const size_t need = (size_t)groups * stride * sizeof(double);
-  if (need > r.scratch_bytes) {
+  if (!fixed && need > r.scratch_bytes) {
     HIP_TRY(hipStreamSynchronize(s));  // earlier work on this stream may still use it
     if (r.scratch) HIP_TRY(hipFree(r.scratch));
     r.scratch = nullptr;
@@ -1561,7 +1594,7 @@ rh_status run_items(const DeviceInfo &info, Runner &r, int32_t timing, int32_t r
   la.refine_tol = refine_tol;
   la.n_items = (int32_t)items.size();
   la.n_chunks = (int32_t)n_chunks;
-  la.scratch = r.scratch;
+  la.scratch = fixed ? fixed->ptr : r.scratch;
   la.scratch_stride = stride;
   if (items.size() == 1) {
     la.items = nullptr;
@@ -1585,7 +1618,7 @@ rh_status run_items(const DeviceInfo &info, Runner &r, int32_t timing, int32_t r
     la.items = r.items_dev;
   }
   la.step_stamps = nullptr;
-  if (std::getenv("RH_STEP_STAMPS")) {
+  if (!fixed && std::getenv("RH_STEP_STAMPS")) {
     if (!r.step_stamps) HIP_TRY(hipMalloc(&r.step_stamps, 4 * kSweepStamps * sizeof(long long)));
     HIP_TRY(hipMemsetAsync(r.step_stamps, 0, 4 * kSweepStamps * sizeof(long long), s));
     la.step_stamps = r.step_stamps;
@@ -1817,6 +1850,37 @@ rh_status upload_ell(DeviceNet *dn, std::vector<std::vector<std::pair<int32_t, d
 
 rh_status device_set(int32_t device, std::string &err) {
   HIP_TRY(hipSetDevice(device));
+  return RH_OK;
+}
+
+namespace {
+// Device address of the fixed scratch array, per device (taken once, with
+// that device current).
+constexpr int kMaxDevices = 64;
+std::mutex g_fixed_mu;
+void *g_fixed_ptr[kMaxDevices] = {};
+
+void *fixed_scratch_of(int32_t device) {
+  std::lock_guard<std::mutex> lk(g_fixed_mu);
+  return device >= 0 && device < kMaxDevices ? g_fixed_ptr[device] : nullptr;
+}
+}  // namespace
+
+rh_status device_fixed_scratch_init(int32_t device, std::string &err) {
+  if (device < 0 || device >= kMaxDevices) {
+    err = "device index beyond the fixed scratch table";
+    return RH_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(g_fixed_mu);
+  if (g_fixed_ptr[device]) return RH_OK;
+  HIP_TRY(hipSetDevice(device));
+  void *p = nullptr;
+  HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) {
+    err = "hipGetSymbolAddress returned no address for the fixed scratch";
+    return RH_EDEVICE;
+  }
+  g_fixed_ptr[device] = p;
   return RH_OK;
 }
 
@@ -2126,6 +2190,40 @@ rh_status device_hvp(Network &net, int32_t k, const double *dW, int64_t ldw, dou
                           (hipStream_t)stream, err);
   net.report.dirs_per_group = dn->run.last_c;
   return s;
+}
+
+rh_status device_hvp_noalloc(Network &net, int32_t k, const double *dW, int64_t ldw, double *dHW, int64_t ldhw,
+                             rh_precision prec, void *stream, std::string &err) {
+  DeviceNet *dn = net.dev;
+  if (!dn) {
+    err = "network has no device data (solve first)";
+    return RH_ESTATE;
+  }
+  if (k <= 0 || ldhw < net.n_p || ldw < net.n_p || !dW || !dHW) {
+    err = "bad block arguments";
+    return RH_EINVAL;
+  }
+  void *fp = fixed_scratch_of(net.ctx->device);
+  if (!fp) {
+    err = "no fixed scratch on this device (context not created on it)";
+    return RH_ESTATE;
+  }
+  HIP_TRY(hipSetDevice(net.ctx->device));
+  std::vector<WorkItem> items(1);
+  WorkItem &it = items[0];
+  it = WorkItem{};
+  it.nd = dn->nd_dev;
+  it.W = dW;
+  it.HW = dHW;
+  it.ldw = ldw;
+  it.ldhw = ldhw;
+  it.k = k;
+  it.identity_from = -1;
+  it.rinfo = nullptr;  // no per-column refinement figures
+  const FixedScratch fx{static_cast<double *>(fp), (int64_t)RH_NOALLOC_SCRATCH_BYTES};
+  const int32_t refine = prec == RH_FP32_REFINED ? net.ctx->refine : -1;
+  return run_items(dn->info, dn->run, 0, refine, net.ctx->refine_tol, items, net.n_x, (hipStream_t)stream, err,
+                   &fx);
 }
 
 rh_status device_hvp_batch(Context &ctx, int32_t n, Network *const *nets, const int32_t *k,

@@ -205,6 +205,13 @@ rh_status device_hvp_batch(Context &ctx, int32_t n, Network *const *nets, const 
                            const int64_t *ldhw, const int32_t *identity_from, rh_precision prec,
                            void *stream, std::string &err);
 rh_status device_set(int32_t device, std::string &err);
+// Takes the device address of the fixed scratch array of the allocation-free
+// entry point on `device` (once per device; that device becomes current).
+rh_status device_fixed_scratch_init(int32_t device, std::string &err);
+// rh_hvp_device with the fixed scratch: no allocation, no timing, no
+// per-column refinement figures.
+rh_status device_hvp_noalloc(Network &net, int32_t k, const double *dW, int64_t ldw, double *dHW, int64_t ldhw,
+                             rh_precision prec, void *stream, std::string &err);
 rh_status device_memcpy_h2d(void *dst, const void *src, size_t bytes, std::string &err);
 rh_status device_memcpy_d2h(void *dst, const void *src, size_t bytes, std::string &err);
 rh_status device_memcpy_2d(void *dst, size_t dpitch, const void *src, size_t spitch,

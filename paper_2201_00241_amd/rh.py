@@ -89,6 +89,9 @@ _SIGS = {
     "rh_hvp_device": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                      ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
                                      ctypes.c_int, ctypes.c_void_p]),
+    "rh_hvp_device_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                             ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                             ctypes.c_int, ctypes.c_void_p]),
     "rh_reduced_hessian": (ctypes.c_int, [ctypes.c_void_p, _f64p, ctypes.c_int64,
                                           ctypes.c_int32, ctypes.c_int]),
     "rh_reduced_hessian_device": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p,
@@ -290,6 +293,12 @@ def rh_hvp_device(net, k, dW_ptr, ldw, dHW_ptr, ldhw, prec=RH_FP64, stream=None)
                                 ctypes.c_void_p(stream or 0)))
 
 
+def rh_hvp_device_noalloc(net, k, dW_ptr, ldw, dHW_ptr, ldhw, prec=RH_FP64, stream=None) -> None:
+    _check(load().rh_hvp_device_noalloc(net, int(k), ctypes.c_void_p(dW_ptr), int(ldw),
+                                        ctypes.c_void_p(dHW_ptr), int(ldhw), int(prec),
+                                        ctypes.c_void_p(stream or 0)))
+
+
 def rh_reduced_hessian(net, k_block=0, prec=RH_FP64) -> np.ndarray:
     _, npar = rh_network_dims(net)
     H = np.zeros((npar, npar), order="F")
@@ -426,6 +435,11 @@ class Network:
         """W, HW: torch float64 CUDA tensors of shape (k, n_p) (row j = direction j)."""
         k = W.shape[0]
         rh_hvp_device(self.h, k, W.data_ptr(), _ld(W), HW.data_ptr(), _ld(HW), prec, stream)
+
+    def hvp_device_noalloc(self, W, HW, stream=None, prec=RH_FP64):
+        """As hvp_device, with the library's fixed scratch (no allocation)."""
+        k = W.shape[0]
+        rh_hvp_device_noalloc(self.h, k, W.data_ptr(), _ld(W), HW.data_ptr(), _ld(HW), prec, stream)
 
     def reduced_hessian_device(self, H, k_block=0, stream=None, prec=RH_FP64):
         """H: torch float64 CUDA tensor (n_p, n_p); row j receives column j of the Hessian."""
