@@ -73,16 +73,15 @@ constexpr int kBlockRows = 64;  // rows of a merged block of narrow levels (one 
 struct DevSweep {
   int32_t n_steps;
   const int4 *steps;  // {unit or wave directory offset, 0, kind, dense offset}
-  const int4 *units;  // 2 x int4: {slot_base, info_base, rows, groups}, {lg, E, lanes, compact}
+  const int4 *units;  // level and block units, 2 x int4: {slot_base, info_base, rows, groups}, {lg, E, lanes, -1}
   const int32_t *wdir;
   const int32_t *scol, *irow;
   int32_t n_slots, n_irow;  // lengths of the slot and row arrays
   const double *sval, *dense;   // unit diagonal (pivots are applied between sweeps)
   const float *sval32, *dense32;  // FP32 copies (refined mode)
-  // the sweep's arrays as byte ranges of one allocation: read in both
-  // precisions, FP64 only, FP32 only (see l2_warm)
-  const char *warm_common, *warm64, *warm32;
-  int64_t warm_common_bytes, warm64_bytes, warm32_bytes;
+  // wave units (see Packed): the FP64 and FP32 records
+  int32_t n_wunits;
+  const char *wrec, *wrec32;
 };
 
 template <class T>
@@ -146,10 +145,6 @@ struct NetDesc {
   const double2 *proj_bus, *proj_inc;
   const int2 *proj_pass;  // {first slot, slots per lane}
   int32_t proj_slots;
-  // byte ranges warmed into L2 by the sweep before the phase that reads them:
-  // the projection records, and G_p^T with p_c2x2
-  const char *proj_warm, *gpt_warm;
-  int64_t proj_warm_bytes, gpt_warm_bytes;
   const int32_t *slack_thx, *slack_vs;
   const double *slack_gth, *slack_gv;
   // 2 c2 of the generator whose output is parameter q; NaN where parameter q
@@ -183,6 +178,7 @@ struct LaunchArgs {
   double refine_tol;  // refined mode: stop a direction once ||r|| <= tol ||A|| ||x|| (inf-norms)
   double *scratch;
   int64_t scratch_stride;  // doubles per workgroup
+  int32_t pad_rows;        // rows of the padded working vector: the largest n_x + kWavePadRows
   long long *stamps;       // kStamps wall-clock stamps per workgroup, or nullptr
   long long *step_stamps;  // debug: workgroup 0 stamps the steps of its sweeps (4 x kSweepStamps)
 };
@@ -230,16 +226,6 @@ __device__ __forceinline__ int4 step_at(const DevSweep AS4 &s, int32_t k) {
   const int32_t AS4 *w = (const int32_t AS4 *)(s.steps + k);
   return make_int4(w[0], w[1], w[2], w[3]);
 }
-
-// The wave unit with compact word cw (lanes | lg << 7 | assign << 10 |
-// E << 11; one pass, so rows = groups = lanes >> lg) at (slot_base,
-// info_base).  An empty unit (cw = 0) has no lanes.
-__device__ __forceinline__ Unit unit_of(int32_t cw, int32_t sb, int32_t ib) {
-  const int32_t lanes = cw & 127, lg = (cw >> 7) & 7, E = (int32_t)((uint32_t)cw >> 11);
-  const int32_t rows = lanes >> lg;
-  return Unit{sb, ib, rows, rows, lg, E, lanes, ((cw >> 10) & 1) != 0};
-}
-
 
 // The first kPre entry slots of one lane in one pass of a unit, with its
 // row's matrix row.  None of it depends on the solution
@@ -336,13 +322,6 @@ __device__ __forceinline__ Slots<T> unit_load(const WaveBufs &B, int32_t base, i
   L.col[3] = (int32_t)c.w;
   L.row = (int32_t)__builtin_amdgcn_raw_buffer_load_b32(B.row, vr, __builtin_amdgcn_readfirstlane(rbase) * 4, 0);
   return L;
-}
-
-// A wave unit (one pass) at slot base sb and row-info base ib.
-template <class T>
-__device__ __forceinline__ Slots<T> wave_load(const WaveBufs &B, int32_t sb, int32_t ib, int32_t lanes, int32_t lg,
-                                              int l64) {
-  return unit_load<T>(B, sb, ib, lanes, lg, l64, l64 < lanes, true);
 }
 
 // Pass `pass` of a level or block unit.
@@ -527,30 +506,6 @@ __device__ __forceinline__ void lane_update(const WaveBufs &B, const Unit &U, in
   lane_finish<C, T>(U, pass, lane, L.row, lane_dot<C, T>(B, U, pass, lane, L, X), X, s_r, block);
 }
 
-// Bring a sweep's arrays into the L2 of this workgroup's XCD before its
-// dependent steps reach them.  Every workgroup runs the same sweep at about
-// the same time, so otherwise each step's lines miss in all of them at once
-// and every step waits for HBM.  Consecutive workgroup ids are dispatched
-// round-robin over the XCDs; the workgroups of one XCD split the range and
-// touch one dword per 128-byte line.  The words are folded into the return
-// value, which the caller consumes at the end of the sweep, so the loads are
-// kept.  Folding a word waits for its load, so a thread has one warming load
-// in flight at a time; that paces the warm (issuing all of a thread's lines
-// before the first wait measured slower).
-constexpr int kXcds = 8;
-
-template <int NT>
-__device__ __forceinline__ uint32_t l2_warm(const char *p, int64_t bytes, int tid) {
-  if (!p || bytes <= 0) return 0u;
-  const int64_t lines = (bytes + 127) >> 7;  // ranges are multiples of 4 bytes
-  const int32_t xcd = (int32_t)(blockIdx.x % kXcds), j = (int32_t)(blockIdx.x / kXcds);
-  const int32_t nwg = ((int32_t)gridDim.x - xcd + kXcds - 1) / kXcds;
-  const int64_t l0 = lines * j / nwg, l1 = lines * (j + 1) / nwg;
-  uint32_t acc = 0u;
-  for (int64_t l = l0 + tid; l < l1; l += NT) acc ^= *reinterpret_cast<const uint32_t *>(p + (l << 7));
-  return acc;
-}
-
 // Synchronisation inside a sweep.  With X in LDS the sweep's threads only
 // communicate through LDS (the right-hand side and the factors are read-only
 // in global memory), so the barriers fence LDS only and leave the prefetch
@@ -579,139 +534,161 @@ __device__ __forceinline__ void wave_sync() {
   }
 }
 
-// Slots of a wave unit: every wave unit has one pass and a multiple of four
-// slots per lane, kWavePre except for rows longer than 64 kWavePre entries;
-// its lanes are groups << lg (whole lane groups), and a lane's columns are
-// stored in quads and its values in pairs (see Packed), so each lane loads
-// its first kWavePre slots and its row index with four accesses from a
-// uniform base plus its lane offset.  Lanes past the unit's rows read nothing (out-of-range offsets,
-// see kOffRange) and form whole lane groups whose sums are never written.
-constexpr int kWavePre = kSlotsAhead;  // slots per lane of a wave unit
+// Wave units (see Packed) are fixed-shape records of 64 lanes, one record
+// per unit, interleaved: the lane's four column offsets (16 bytes at 16 l),
+// its start and write row offsets (8 bytes at 1024 + 8 l), its four values
+// (FP64: two pairs at 1536 + 16 l and 2560 + 16 l; FP32: one quad at
+// 1536 + 16 l).  The offsets address the padded vector: zero row, 64 dummy
+// rows, then the solution (kWavePadRows); they are for 8-byte rows and are
+// scaled for the row size of C directions of T.  With the vector in LDS the
+// padded vector starts at LDS address 0 (the LDS kernels have no static LDS),
+// so an offset is an LDS address and a gather needs no address arithmetic.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+#define AS3 __attribute__((address_space(3)))
 
+template <class T>
+struct WaveRec;
+template <>
+struct WaveRec<double> {
+  static constexpr int bytes = 3584;
+};
+template <>
+struct WaveRec<float> {
+  static constexpr int bytes = 2560;
+};
 
+template <class T>
+__device__ __forceinline__ const char *sw_wrec(const DevSweep AS4 &s);
+template <>
+__device__ __forceinline__ const char *sw_wrec<double>(const DevSweep AS4 &s) { return s.wrec; }
+template <>
+__device__ __forceinline__ const char *sw_wrec<float>(const DevSweep AS4 &s) { return s.wrec32; }
 
-// A wave's walk through its units of a wave step.  Unit u0 + j runs at step
-// j while the slots of unit u0 + j + kWaveAhead are loaded, so a unit's
-// compact word is needed once, when its loads are issued, and travels with
-// its slots in the rotating buffer.  Lane i of table word q holds the compact
-// word of unit u0 + kWaveAhead + 64 q + i (0 past the wave's last unit: an
-// empty unit, with no lanes, that loads and writes nothing); the walk reads
-// it by readlane with the step's index in its chunk of 64 steps and shifts
-// the table by one word per chunk, so no per-unit branch picks the word and
-// no per-unit memory access reads it.  Slot and row-info bases are running
-// sums, since a wave's units are packed one after the other.  Scalar
-// instructions are the walk's bottleneck (one scalar unit serves all waves of
-// a CU), so the per-unit work is kept to one decode and a few additions.
-constexpr int kWaveAhead = 2;   // units whose slots a wave has in flight
-constexpr int kTableWords = 4;  // per-lane table registers (256 units)
+// Byte offset of an 8-byte-row offset in a vector whose rows are C values of T.
+template <int C, class T>
+__device__ __forceinline__ uint32_t row_bytes(uint32_t off) {
+  constexpr int rb = C * (int)sizeof(T);
+  static_assert(rb == 4 || rb == 8 || rb == 16 || rb == 32, "row size");
+  if constexpr (rb == 4) return off >> 1;
+  else if constexpr (rb == 8) return off;
+  else if constexpr (rb == 16) return off << 1;
+  else return off << 2;
+}
+
+// Element c of the padded-vector row at 8-byte-row offset off: in LDS the
+// padded vector starts at address 0; in global memory at Xpad.
+template <int C, class T, bool LDSX>
+__device__ __forceinline__ T xget(const T *Xpad, uint32_t off, int c) {
+  const uint32_t b = row_bytes<C, T>(off) + (uint32_t)(c * sizeof(T));
+  if constexpr (LDSX) return *(const AS3 T *)(size_t)b;
+  else return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(Xpad) + b);
+}
+template <int C, class T, bool LDSX>
+__device__ __forceinline__ void xput(T *Xpad, uint32_t off, int c, T v) {
+  const uint32_t b = row_bytes<C, T>(off) + (uint32_t)(c * sizeof(T));
+  if constexpr (LDSX) *(AS3 T *)(size_t)b = v;
+  else *reinterpret_cast<T *>(reinterpret_cast<char *>(Xpad) + b) = v;
+}
 
 template <class T>
 struct WRing {
-  Slots<T> L;
-  int32_t cw;  // the unit's compact word
+  u32x4 col;
+  u32x2 row;  // start row, write row
+  T val[4];
 };
 
-// Issue the loads of the unit with compact word cw at the running bases (sb,
-// ib), which it then advances past the unit.
+// The record at byte soff of the buffer R (uniform), with per-lane byte
+// offsets of the column quad (vc), the row words (vr) and the value pairs
+// (vv0, vv1; FP32 reads its quad at vv0).  An out-of-range offset reads
+// zeros without a memory access, and so does the whole record past the
+// buffer's end: a unit that reads and writes +0 at the zero row.
 template <class T>
-__device__ __forceinline__ void ring_load(const WaveBufs &B, int32_t cw, int32_t &sb, int32_t &ib, int l64,
-                                          WRing<T> &R) {
-  const Unit U = unit_of(cw, sb, ib);
-  R.L = wave_load<T>(B, sb, ib, U.lanes, U.lg, l64);
-  R.cw = cw;
-  sb += U.E * U.lanes;  // wave units have one pass
-  ib += U.rows;
+__device__ __forceinline__ void wrec_load(__amdgpu_buffer_rsrc_t R, int32_t soff, int vc, int vr, int vv0, int vv1,
+                                          WRing<T> &W) {
+  const int32_t so = __builtin_amdgcn_readfirstlane(soff);
+  W.col = __builtin_amdgcn_raw_buffer_load_b128(R, vc, so, 0);
+  W.row = __builtin_bit_cast(u32x2, __builtin_amdgcn_raw_buffer_load_b64(R, vr, so, 0));
+  if constexpr (sizeof(T) == 8) {
+    const f64x2 a = __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(R, vv0, so, 0));
+    const f64x2 b = __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(R, vv1, so, 0));
+    W.val[0] = a.x;
+    W.val[1] = a.y;
+    W.val[2] = b.x;
+    W.val[3] = b.y;
+  } else {
+    (void)vv1;
+    const f32x4 a = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(R, vv0, so, 0));
+    W.val[0] = a.x;
+    W.val[1] = a.y;
+    W.val[2] = a.z;
+    W.val[3] = a.w;
+  }
 }
 
+// A wave's walk through its units of a wave step, units u0 .. u1 - 1.  Unit
+// j runs at step j while the records of units j + 1 .. j + kWaveAhead - 1 are
+// in flight, and issues the load of unit j + kWaveAhead's record when it is
+// done with its own (so the new record takes the registers of the old).
+// Every unit is the same few instructions: five gathers, four FMAs, the group
+// sum (its width, lg, is the one per-unit choice, from the write words), one
+// subtraction and one write per lane (lanes that own no row write their dummy
+// rows).  A unit's start words say which lanes of the unit kWaveAhead on have
+// entries, and which have a second value pair: the other lanes skip those
+// loads (the vector memory path, not the arithmetic, bounds a wave step, and
+// most lanes hold at most two entries).  The buffer resource covers this
+// wave's records only, so records past its last unit read as zeros.
 template <int C, class T, bool LDSX>
-__device__ __forceinline__ void wave_walk_units(const DevSweep AS4 &s, int32_t u0, int32_t u1, int l64,
-                                                T *__restrict__ X) {
+__device__ __forceinline__ void wave_walk(const DevSweep AS4 &s, int32_t u0, int32_t u1, int l64, T *Xpad) {
   const int32_t n = u1 - u0;
   if (n <= 0) return;
-  const int32_t *units = reinterpret_cast<const int32_t *>(s.units);
-  int32_t tab[kTableWords];
-#pragma unroll
-  for (int q = 0; q < kTableWords; ++q) {
-    const int32_t u = u0 + kWaveAhead + 64 * q + l64;
-    tab[q] = u < u1 ? units[8 * (int64_t)u + 7] : 0;
-  }
-  {
-    // consume the table here, so that no later wait covers these loads
-    int32_t any = 0;
-#pragma unroll
-    for (int q = 0; q < kTableWords; ++q) any |= __builtin_amdgcn_readfirstlane(tab[q]);
-    asm volatile("" ::"s"(any));
-  }
-  const WaveBufs B = wave_bufs<T>(s);
-  const int32_t AS4 *hu = (const int32_t AS4 *)s.units;  // scalar loads
-  int32_t sb_cur = hu[8 * (int64_t)u0];                   // slot base of the running unit
-  int32_t sb_pre = sb_cur, ib_pre = hu[8 * (int64_t)u0 + 1];  // bases of the next unit to load
+  constexpr int RB = WaveRec<T>::bytes;
+  const __amdgpu_buffer_rsrc_t R = __builtin_amdgcn_make_buffer_rsrc(
+      (void *)(sw_wrec<T>(s) + (int64_t)u0 * RB), 0, n * RB, kBufWord3);
+  const int vc = l64 * 16, vr = l64 * 8 + 1024, vv0 = l64 * 16 + 1536, vv1 = l64 * 16 + 2560;
   WRing<T> ring[kWaveAhead];
+  // the first records in full, issued in ring order (the loop's wait counts
+  // assume the oldest record is the next one used, also on entry)
 #pragma unroll
-  for (int d = 0; d < kWaveAhead; ++d)
-    ring_load<T>(B, d < n ? hu[8 * (int64_t)(u0 + d) + 7] : 0, sb_pre, ib_pre, l64, ring[d]);
-  for (int32_t c0 = 0; c0 < n; c0 += 64) {
-    // every unrolled step runs (a step past the end is an empty unit), so the
-    // same loads are in flight on every path through the loop
-    for (int32_t i = 0; i < 64 && c0 + i < n; i += kWaveAhead) {
+  for (int d = 0; d < kWaveAhead; ++d) {
+    wrec_load<T>(R, d * RB, vc, vr, vv0, vv1, ring[d]);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  int32_t soff = kWaveAhead * RB;
+  // every unrolled step runs (a step past the end is the zero unit), so the
+  // same loads are in flight on every path through the loop
+  for (int32_t j = 0; j < n; j += kWaveAhead) {
 #pragma unroll
-      for (int d = 0; d < kWaveAhead; ++d) {
-        const Slots<T> &L = ring[d].L;
-        const Unit U = unit_of(ring[d].cw, sb_cur, 0);
-        // gathers: the kWavePre entries and the row's own value
-        T xv[kWavePre][C], xr[C];
+    for (int d = 0; d < kWaveAhead; ++d) {
+      const u32x4 cq = ring[d].col;
+      const uint32_t rx = ring[d].row.x, ry = ring[d].row.y;
+      const int lg = (int)((uint32_t)__builtin_amdgcn_readfirstlane(ry) >> kWaveLgShift);
+      const uint32_t rs = rx & kWaveOffMask, rw = ry & kWaveOffMask;
+      // loads of the unit kWaveAhead on
+      const bool nact = (rx >> kWaveActBit) & 1u, ntwo = (rx >> kWaveTwoBit) & 1u;
+      const int nc = nact ? vc : kOffRange, nv0 = nact ? vv0 : kOffRange, nv1 = ntwo ? vv1 : kOffRange;
+      T xv[4][C], xr[C];
 #pragma unroll
-        for (int e = 0; e < kWavePre; ++e)
-#pragma unroll
-          for (int c = 0; c < C; ++c) xv[e][c] = X[L.col[e] * C + c];
-        const int32_t row = L.row;
-#pragma unroll
-        for (int c = 0; c < C; ++c) xr[c] = X[row * C + c];
-        T part[C];
-#pragma unroll
-        for (int c = 0; c < C; ++c) part[c] = T(0);
-#pragma unroll
-        for (int e = 0; e < kWavePre; ++e)
-#pragma unroll
-          for (int c = 0; c < C; ++c) part[c] = fma(L.val[e], xv[e][c], part[c]);
-        ring_load<T>(B, __builtin_amdgcn_readlane(tab[0], i + d), sb_pre, ib_pre, l64, ring[d]);
-        // rows longer than 64 kWavePre entries (rare): the remaining slots
-        if (U.E > kWavePre) {
-          const int vc = l64 < U.lanes ? l64 * 16 : kOffRange;
-          const int vv = l64 < U.lanes ? l64 * 2 * (int)sizeof(T) : kOffRange;
-          for (int32_t e0 = kWavePre; e0 < U.E; e0 += 4) {
-            const int32_t s0 = __builtin_amdgcn_readfirstlane(U.slot_base + e0 * U.lanes);
-            const int32_t s1 = __builtin_amdgcn_readfirstlane(U.slot_base + (e0 + 2) * U.lanes);
-            const u32x4 cq = __builtin_amdgcn_raw_buffer_load_b128(B.col, vc, s0 * 4, 0);
-            T v[4];
-            buf_load_pair<T>(B.val, vv, s0 * (int)sizeof(T), v[0], v[1]);
-            buf_load_pair<T>(B.val, vv, s1 * (int)sizeof(T), v[2], v[3]);
-            const int32_t j[4] = {(int32_t)cq.x, (int32_t)cq.y, (int32_t)cq.z, (int32_t)cq.w};
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-#pragma unroll
-              for (int c = 0; c < C; ++c) part[c] = fma(v[e], X[j[e] * C + c], part[c]);
-          }
-        }
-#pragma unroll
-        for (int c = 0; c < C; ++c) part[c] = group_sum(part[c], U.lg);
-        if ((l64 & ((1 << U.lg) - 1)) == 0 && l64 < U.lanes) {
-#pragma unroll
-          for (int c = 0; c < C; ++c) X[row * C + c] = U.assign ? part[c] : xr[c] - part[c];
-        }
-        wave_sync<LDSX>();  // this wave's writes before its next unit's reads
-        sb_cur += U.E * U.lanes;
+      for (int c = 0; c < C; ++c) {
+        xv[0][c] = xget<C, T, LDSX>(Xpad, cq.x, c);
+        xv[1][c] = xget<C, T, LDSX>(Xpad, cq.y, c);
+        xv[2][c] = xget<C, T, LDSX>(Xpad, cq.z, c);
+        xv[3][c] = xget<C, T, LDSX>(Xpad, cq.w, c);
+        xr[c] = xget<C, T, LDSX>(Xpad, rs, c);
       }
-    }
-    // next chunk: shift the table (a wave with more than 64 kTableWords
-    // units reads further words here)
+      T part[C];
 #pragma unroll
-    for (int q = 0; q + 1 < kTableWords; ++q) tab[q] = tab[q + 1];
-    tab[kTableWords - 1] = 0;
-    if (c0 + 64 * kTableWords + kWaveAhead < n) {
-      const int32_t u = u0 + kWaveAhead + c0 + 64 * kTableWords + l64;
-      tab[kTableWords - 1] = u < u1 ? units[8 * (int64_t)u + 7] : 0;
-      asm volatile("" ::"s"(__builtin_amdgcn_readfirstlane(tab[kTableWords - 1])));
+      for (int c = 0; c < C; ++c) part[c] = T(0);
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int c = 0; c < C; ++c) part[c] = fma(ring[d].val[e], xv[e][c], part[c]);
+#pragma unroll
+      for (int c = 0; c < C; ++c) xput<C, T, LDSX>(Xpad, rw, c, xr[c] - group_sum(part[c], lg));
+      wave_sync<LDSX>();  // this wave's writes before its next unit's reads
+      // the record kWaveAhead units on, into the registers this one held
+      wrec_load<T>(R, soff, nc, vr, nv0, nv1, ring[d]);
+      soff += RB;
     }
   }
 }
@@ -726,16 +703,10 @@ __device__ __forceinline__ void wave_walk_units(const DevSweep AS4 &s, int32_t u
 // A workgroup barrier separates steps.
 template <int C, int NT, class T, bool LDSX>
 __device__ __forceinline__ void sweep(const DevSweep AS4 &s, T *__restrict__ X,
-                                      T *__restrict__ s_r, int tid, long long *ss = nullptr,
-                                      const char *next = nullptr, int64_t next_bytes = 0) {
+                                      T *__restrict__ s_r, int tid, long long *ss = nullptr) {
   const int32_t ns = s.n_steps;
   if (ns == 0) return;
   if (ss && tid == 0) ss[0] = wall_clock64();
-  // the sweep's own arrays, and those of the phase after it (`next`)
-  const uint32_t warm = l2_warm<NT>(next, next_bytes, tid) ^
-                        l2_warm<NT>(s.warm_common, s.warm_common_bytes, tid) ^
-                        (sizeof(T) == 8 ? l2_warm<NT>(s.warm64, s.warm64_bytes, tid)
-                                        : l2_warm<NT>(s.warm32, s.warm32_bytes, tid));
   const WaveBufs B = wave_bufs<T>(s);
   // The next level or block step's first slots and, for a block, its dense
   // inverse entries are loaded a step ahead.  The same loads are issued
@@ -765,7 +736,7 @@ __device__ __forceinline__ void sweep(const DevSweep AS4 &s, T *__restrict__ X,
       const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), l64 = tid & 63;
       const int32_t AS4 *wd = (const int32_t AS4 *)s.wdir;
       const int32_t u0 = wd[cur.x + wv], u1 = wd[cur.x + wv + 1];
-      wave_walk_units<C, T, LDSX>(s, u0, u1, l64, X);
+      wave_walk<C, T, LDSX>(s, u0, u1, l64, X - kWavePadRows * C);
       prefetch(st, k + 1 < ns);
       step_barrier<LDSX>();
       if (ss && tid == 0 && k + 1 < kMaxStepStamps) ss[k + 1] = wall_clock64();
@@ -788,8 +759,7 @@ __device__ __forceinline__ void sweep(const DevSweep AS4 &s, T *__restrict__ X,
     }
     if (ss && tid == 0 && k + 1 < kMaxStepStamps) ss[k + 1] = wall_clock64();
   }
-  asm volatile("" ::"v"(warm));  // the warming loads are complete by now
-  __syncthreads();                // full barrier at the end of the sweep
+  __syncthreads();  // full barrier at the end of the sweep
 }
 
 // X <- D^{-1} X between the two sweeps of a solve, then a barrier.  A thread
@@ -1063,15 +1033,16 @@ __device__ __forceinline__ void reduction(const NetDesc AS4 &nd, const WorkItem 
   sweep<C, NT, double, LDSX>(nd.L, X, s_r, tid, ss);
   pivot_scale<C, NT, double>(nd.pivinv, X, nd.n_x, tid);
   if (st) st[2] = wall_clock64();
-  sweep<C, NT, double, LDSX>(nd.U, X, s_r, tid, ss ? ss + kSweepStamps : nullptr, nd.proj_warm,
-                             nd.proj_warm_bytes);
+  sweep<C, NT, double, LDSX>(nd.U, X, s_r, tid, ss ? ss + kSweepStamps : nullptr);
   if (st) st[3] = wall_clock64();
   // 3. tensor projection: -Y_x into Yx, Y_p into the output
   projection<C, NT>(nd, a, X, Yx, s_slack, dir0, tid);
   if (st) st[4] = wall_clock64();
   // 4. Psi' = L^{-T} D^{-1} Uh^{-T} (-P Y_x), in place on the working vector
   // V: X in LDS takes a copy of -P Y_x (Z is no longer needed); with X in
-  // global memory the solve runs on Yx itself
+  // global memory the solve runs on Yx itself (so Yx, like X, is the solution
+  // part of a padded vector: the wave walk reads its zero row and writes its
+  // dummy rows)
   double *V = X;
   if constexpr (LDSX) {
     copy_to_lds<NT>(Yx, X, nd.n_x * C, tid);
@@ -1082,8 +1053,7 @@ __device__ __forceinline__ void reduction(const NetDesc AS4 &nd, const WorkItem 
   sweep<C, NT, double, LDSX>(nd.Ut, V, s_r, tid, ss ? ss + 2 * kSweepStamps : nullptr);
   pivot_scale<C, NT, double>(nd.pivinv, V, nd.n_x, tid);
   if (st) st[5] = wall_clock64();
-  sweep<C, NT, double, LDSX>(nd.Lt, V, s_r, tid, ss ? ss + 3 * kSweepStamps : nullptr, nd.gpt_warm,
-                             nd.gpt_warm_bytes);
+  sweep<C, NT, double, LDSX>(nd.Lt, V, s_r, tid, ss ? ss + 3 * kSweepStamps : nullptr);
   if (st) st[6] = wall_clock64();
   // 5. H W = Y_p + G_p^T Psi
   spmuladd<C, NT>(nd, a, V, dir0, tid);
@@ -1232,8 +1202,7 @@ __device__ __forceinline__ void refined_solve(const NetDesc AS4 &nd, double *__r
     __syncthreads();
     sweep<C, NT, float, LDSX>(s1, X32, s_r, tid);
     pivot_scale<C, NT, float>(nd.pivinv32, X32, n, tid);
-    sweep<C, NT, float, LDSX>(s2, X32, s_r, tid, nullptr, TRANS ? nd.gpt_warm : nd.proj_warm,
-                              TRANS ? nd.gpt_warm_bytes : nd.proj_warm_bytes);
+    sweep<C, NT, float, LDSX>(s2, X32, s_r, tid);
     double xmax[C], rmax[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) xmax[c] = rmax[c] = 0.0;
@@ -1298,30 +1267,42 @@ __device__ __forceinline__ void reduction_refined(const NetDesc AS4 &nd, const W
   if (st) st[7] = wall_clock64();
 }
 
-// X in LDS (dynamic shared memory of n_x * C doubles); Y_x in global scratch.
+// X in LDS, Y_x in global scratch.  The kernel uses dynamic LDS only, so
+// that the padded vector (zero row, dummy rows, X; pad_rows x C doubles)
+// starts at LDS address 0 as the wave walk assumes; the block residuals and
+// the slack scalars follow it.
 template <int C>
 __global__ __launch_bounds__(kThreadsLds) void block_kernel_lds(const LaunchArgs la) {
   extern __shared__ double smem[];
-  __shared__ double s_slack[C];
-  __shared__ double s_r[kBlockRows * C];
+  double *s_r = smem + (int64_t)la.pad_rows * C;
+  double *s_slack = s_r + kBlockRows * C;
+  double *X = smem + kWavePadRows * C;
+  if (threadIdx.x < C) smem[threadIdx.x] = 0.0;  // the zero row (ordered by spmul's barrier)
   double *Yx = la.scratch + (int64_t)blockIdx.x * la.scratch_stride;
   for (int32_t chunk = blockIdx.x; chunk < la.n_chunks; chunk += gridDim.x) {
     const WorkItem it = item_of(la, chunk);
     long long *st = (la.stamps && chunk == (int32_t)blockIdx.x)
                         ? la.stamps + (int64_t)blockIdx.x * kStamps : nullptr;
-    reduction<C, kThreadsLds, true>(*(const NetDesc AS4 *)it.nd, it, smem, Yx, s_slack, s_r,
+    reduction<C, kThreadsLds, true>(*(const NetDesc AS4 *)it.nd, it, X, Yx, s_slack, s_r,
                                     (chunk - it.chunk0) * C, st,
                                     (blockIdx.x == 0 && chunk == 0) ? la.step_stamps : nullptr);
   }
 }
 
-// X and Y_x in global scratch (networks whose vector does not fit in LDS).
+// X and Y_x in global scratch (networks whose vector does not fit in LDS):
+// padded Y_x (the transposed solve runs on it in place), then the padded X.
 template <int C>
 __global__ __launch_bounds__(kThreads) void block_kernel_global(const LaunchArgs la) {
   __shared__ double s_slack[C];
   __shared__ double s_r[kBlockRows * C];
-  double *Yx = la.scratch + (int64_t)blockIdx.x * la.scratch_stride;
-  double *X = Yx + la.scratch_stride / 2;
+  double *Ypad = la.scratch + (int64_t)blockIdx.x * la.scratch_stride;
+  double *Xpad = Ypad + la.scratch_stride / 2;
+  double *Yx = Ypad + kWavePadRows * C;
+  double *X = Xpad + kWavePadRows * C;
+  if (threadIdx.x < C) {  // the zero rows
+    Ypad[threadIdx.x] = 0.0;
+    Xpad[threadIdx.x] = 0.0;
+  }
   for (int32_t chunk = blockIdx.x; chunk < la.n_chunks; chunk += gridDim.x) {
     const WorkItem it = item_of(la, chunk);
     long long *st = (la.stamps && chunk == (int32_t)blockIdx.x)
@@ -1332,25 +1313,30 @@ __global__ __launch_bounds__(kThreads) void block_kernel_global(const LaunchArgs
   }
 }
 
-// Refined mode, FP32 correction vector in LDS (n_x * C floats).
+// Refined mode, padded FP32 correction vector at LDS address 0 (dynamic LDS
+// only, as block_kernel_lds), then the block residuals, the slack scalars and
+// the workgroup reduction buffer.
 template <int C>
 __global__ __launch_bounds__(kThreadsLds) void refined_kernel_lds(const LaunchArgs la) {
   extern __shared__ float smem32[];
-  __shared__ double s_slack[C];
-  __shared__ float s_r[kBlockRows * C];
-  __shared__ double s_red[kWaves * 2 * C];
+  float *s_r = smem32 + (int64_t)la.pad_rows * C;
+  double *s_slack = reinterpret_cast<double *>(smem32 + (((int64_t)la.pad_rows * C + kBlockRows * C + 1) & ~int64_t(1)));
+  double *s_red = s_slack + C;
+  float *X32 = smem32 + kWavePadRows * C;
+  if (threadIdx.x < C) smem32[threadIdx.x] = 0.f;  // the zero row
   double *V1 = la.scratch + (int64_t)blockIdx.x * la.scratch_stride;
   double *V2 = V1 + la.scratch_stride / 2;
   for (int32_t chunk = blockIdx.x; chunk < la.n_chunks; chunk += gridDim.x) {
     const WorkItem it = item_of(la, chunk);
     long long *st = (la.stamps && chunk == (int32_t)blockIdx.x)
                         ? la.stamps + (int64_t)blockIdx.x * kStamps : nullptr;
-    reduction_refined<C, kThreadsLds, true>(*(const NetDesc AS4 *)it.nd, it, smem32, V1, V2, s_slack, s_r, s_red,
+    reduction_refined<C, kThreadsLds, true>(*(const NetDesc AS4 *)it.nd, it, X32, V1, V2, s_slack, s_r, s_red,
                                             la.refine, la.refine_tol, (chunk - it.chunk0) * C, st);
   }
 }
 
-// Refined mode with every vector in global scratch.
+// Refined mode with every vector in global scratch: V1, V2, the padded FP32
+// correction.
 template <int C>
 __global__ __launch_bounds__(kThreads) void refined_kernel_global(const LaunchArgs la) {
   __shared__ double s_slack[C];
@@ -1358,7 +1344,9 @@ __global__ __launch_bounds__(kThreads) void refined_kernel_global(const LaunchAr
   __shared__ double s_red[kWaves * 2 * C];
   double *V1 = la.scratch + (int64_t)blockIdx.x * la.scratch_stride;
   double *V2 = V1 + la.scratch_stride / 3;
-  float *X32 = reinterpret_cast<float *>(V1 + 2 * (la.scratch_stride / 3));
+  float *X32pad = reinterpret_cast<float *>(V1 + 2 * (la.scratch_stride / 3));
+  float *X32 = X32pad + kWavePadRows * C;
+  if (threadIdx.x < C) X32pad[threadIdx.x] = 0.f;  // the zero row
   for (int32_t chunk = blockIdx.x; chunk < la.n_chunks; chunk += gridDim.x) {
     const WorkItem it = item_of(la, chunk);
     long long *st = (la.stamps && chunk == (int32_t)blockIdx.x)
@@ -1480,12 +1468,30 @@ rh_status runner_collect(Runner &r, const DeviceInfo &info, rh_report &rep, std:
   return RH_OK;
 }
 
+// The LDS kernels address the padded vector from LDS address 0, which holds
+// only if they have no static LDS (checked once per kernel).
+rh_status no_static_lds(const void *kernel, int &checked, std::string &err) {
+  if (checked == 0) {
+    hipFuncAttributes fa{};
+    HIP_TRY(hipFuncGetAttributes(&fa, kernel));
+    checked = fa.sharedSizeBytes == 0 ? 1 : -1;
+  }
+  if (checked < 0) {
+    err = "internal: an LDS kernel has static LDS";
+    return RH_EDEVICE;
+  }
+  return RH_OK;
+}
+
 template <int C>
 rh_status launch(bool lds, bool refined, int32_t groups, size_t lds_bytes, hipStream_t s,
                  const LaunchArgs &la, std::string &err) {
+  static int checked_b = 0, checked_r = 0;
   if (refined) {
     if constexpr (C <= 4) {
       if (lds) {
+        rh_status st = no_static_lds(reinterpret_cast<const void *>(&refined_kernel_lds<C>), checked_r, err);
+        if (st != RH_OK) return st;
         HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&refined_kernel_lds<C>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
         hipLaunchKernelGGL(refined_kernel_lds<C>, dim3(groups), dim3(kThreadsLds), lds_bytes, s, la);
@@ -1499,6 +1505,8 @@ rh_status launch(bool lds, bool refined, int32_t groups, size_t lds_bytes, hipSt
   }
   if constexpr (C <= 4) {
     if (lds) {
+      rh_status st = no_static_lds(reinterpret_cast<const void *>(&block_kernel_lds<C>), checked_b, err);
+      if (st != RH_OK) return st;
       HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&block_kernel_lds<C>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
       hipLaunchKernelGGL(block_kernel_lds<C>, dim3(groups), dim3(kThreadsLds), lds_bytes, s, la);
@@ -1544,8 +1552,9 @@ rh_status run_items(const DeviceInfo &info, Runner &r, int32_t timing, int32_t r
   if (total_k <= 0) return RH_OK;
   const bool refined = refine >= 0;
   const size_t elem = refined ? sizeof(float) : sizeof(double);  // LDS vector element
-  const bool lds = (size_t)max_nx * elem <= info.lds_max && !std::getenv("RH_NO_LDS");
-  const int32_t C = choose_c(total_k, info.cus, max_nx, info.lds_max, lds, elem);
+  const int32_t pad_rows = max_nx + kWavePadRows;                 // padded working vector
+  const bool lds = (size_t)pad_rows * elem <= info.lds_max && !std::getenv("RH_NO_LDS");
+  const int32_t C = choose_c(total_k, info.cus, pad_rows, info.lds_max, lds, elem);
   int64_t n_chunks = 0;
   for (WorkItem &it : items) {
     it.chunk0 = (int32_t)n_chunks;
@@ -1558,7 +1567,7 @@ rh_status run_items(const DeviceInfo &info, Runner &r, int32_t timing, int32_t r
   // per-workgroup scratch, 256-byte aligned: FP64 mode Y_x (+ X when it is
   // not in LDS); refined mode V1, V2 (+ the FP32 correction when not in LDS)
   const int64_t parts = refined ? (lds ? 2 : 3) : (lds ? 1 : 2);
-  const int64_t stride = (parts * max_nx * C + 31) / 32 * 32 * (refined ? 1 : 1);
+  const int64_t stride = (parts * (int64_t)pad_rows * C + 31) / 32 * 32;
   const int64_t max_groups_mem = std::max<int64_t>(1, (int64_t(8) << 30) / (stride * 8));
   const int64_t per_cu = lds ? 1 : 2;
   int32_t groups = (int32_t)std::min<int64_t>({n_chunks, max_groups_mem, (int64_t)info.cus * 8 * per_cu});
@@ -1596,6 +1605,7 @@ rh_status run_items(const DeviceInfo &info, Runner &r, int32_t timing, int32_t r
   la.n_chunks = (int32_t)n_chunks;
   la.scratch = fixed ? fixed->ptr : r.scratch;
   la.scratch_stride = stride;
+  la.pad_rows = pad_rows;
   if (items.size() == 1) {
     la.items = nullptr;
     la.one = items[0];
@@ -1649,7 +1659,16 @@ rh_status run_items(const DeviceInfo &info, Runner &r, int32_t timing, int32_t r
     r.ev_used += 2;
     HIP_TRY(hipEventRecord(e0, s));
   }
-  const size_t lds_bytes = lds ? (size_t)max_nx * C * elem : 0;
+  // dynamic LDS: the padded vector, then the kernels' small buffers (block
+  // residuals, slack scalars; the refined kernel's reduction buffer)
+  size_t lds_bytes = 0;
+  if (lds) {
+    if (refined)
+      lds_bytes = (((size_t)pad_rows * C + kBlockRows * C + 1) & ~size_t(1)) * sizeof(float) +
+                  (size_t)(C + kWaves * 2 * C) * sizeof(double);
+    else
+      lds_bytes = ((size_t)pad_rows * C + kBlockRows * C + C) * sizeof(double);
+  }
   rh_status st;
   switch (C) {
     case 1: st = launch<1>(lds, refined, groups, lds_bytes, s, la, err); break;
@@ -1730,7 +1749,6 @@ struct Blob {
     std::memcpy(h.data() + off, v.data(), v.size() * sizeof(T));
     return (int64_t)off;
   }
-  size_t mark() const { return (h.size() + 255) & ~size_t(255); }
 };
 
 template <class T>
@@ -1750,15 +1768,30 @@ rh_status upload_sweep(DeviceNet *dn, const Sweep &s, int32_t n, const std::vect
     err = "internal: device sweeps must have a unit diagonal";
     return RH_EDEVICE;
   }
+  // wave-unit records in both precisions (layout: see WaveRec)
+  const size_t nwu = pk.wlg.size();
+  std::vector<char> rec64(nwu * WaveRec<double>::bytes), rec32(nwu * WaveRec<float>::bytes);
+  for (size_t u = 0; u < nwu; ++u) {
+    char *r64 = rec64.data() + u * WaveRec<double>::bytes, *r32 = rec32.data() + u * WaveRec<float>::bytes;
+    std::memcpy(r64, pk.wcol.data() + 256 * u, 1024);
+    std::memcpy(r64 + 1024, pk.wrow.data() + 128 * u, 512);
+    std::memcpy(r64 + 1536, pk.wval.data() + 256 * u, 2048);
+    std::memcpy(r32, r64, 1536);
+    float *v32 = reinterpret_cast<float *>(r32 + 1536);
+    for (int l = 0; l < 64; ++l)
+      for (int e = 0; e < 4; ++e) v32[4 * l + e] = (float)pk.wval[256 * u + 128 * (e >> 1) + 2 * l + (e & 1)];
+  }
   Blob bl;
   const int64_t o_steps = bl.add(pk.steps), o_units = bl.add(pk.units), o_wdir = bl.add(pk.wdir);
   const int64_t o_scol = bl.add(pk.scol), o_irow = bl.add(pk.irow);
-  const size_t m1 = bl.mark();
-  const int64_t o_sval = bl.add(pk.sval), o_dense = bl.add(pk.dense);
-  const size_t m2 = bl.mark();
+  const int64_t o_sval = bl.add(pk.sval), o_dense = bl.add(pk.dense), o_wrec = bl.add(rec64);
   const int64_t o_sval32 = bl.add(std::vector<float>(pk.sval.begin(), pk.sval.end()));
   const int64_t o_dense32 = bl.add(std::vector<float>(pk.dense.begin(), pk.dense.end()));
-  const size_t m3 = bl.h.size();
+  const int64_t o_wrec32 = bl.add(rec32);
+  if (nwu * WaveRec<double>::bytes >= (size_t)kOffRange) {
+    err = "network too large for the wave-unit records";
+    return RH_EINVAL;
+  }
   const char *base = nullptr;
   UP(bl.h, base);
   o.n_steps = (int32_t)(pk.steps.size() / 4);
@@ -1771,12 +1804,9 @@ rh_status upload_sweep(DeviceNet *dn, const Sweep &s, int32_t n, const std::vect
   o.dense = at_off<double>(base, o_dense);
   o.sval32 = at_off<float>(base, o_sval32);
   o.dense32 = at_off<float>(base, o_dense32);
-  o.warm_common = base;
-  o.warm_common_bytes = (int64_t)m1;
-  o.warm64 = base + m1;
-  o.warm64_bytes = (int64_t)(m2 - m1);
-  o.warm32 = base + m2;
-  o.warm32_bytes = (int64_t)(m3 - m2);
+  o.n_wunits = (int32_t)nwu;
+  o.wrec = at_off<char>(base, o_wrec);
+  o.wrec32 = at_off<char>(base, o_wrec32);
   o.n_slots = (int32_t)pk.scol.size();
   o.n_irow = (int32_t)pk.irow.size();
   dn->sweep_steps.push_back(o.n_steps);
@@ -2027,8 +2057,6 @@ rh_status device_upload(Network &net, std::string &err) {
     nd.gpt_col = at_off<int32_t>(base, o_col);
     nd.gpt_val = at_off<double>(base, o_val);
     nd.p_c2x2 = at_off<double>(base, o_c2);
-    nd.gpt_warm = base;
-    nd.gpt_warm_bytes = (int64_t)bl.h.size();
   }
   // tangent sources per bus in permuted numbering: theta from X[thx] (-1 at
   // the reference bus); v from X[vs] at PQ buses, else from W[-vs - 1]
@@ -2104,8 +2132,6 @@ rh_status device_upload(Network &net, std::string &err) {
     nd.proj_pass = at_off<int2>(base, o_pass);
     nd.proj_bus = at_off<double2>(base, o_bus);
     nd.proj_inc = at_off<double2>(base, o_inc);
-    nd.proj_warm = base;
-    nd.proj_warm_bytes = (int64_t)bl.h.size();
   }
   nd.n_slack = (int32_t)tp.slack_bus.size();
   {
@@ -2282,7 +2308,7 @@ int64_t device_scratch_per_direction(int32_t n_x, rh_precision prec) {
   // per-workgroup scratch of run_items, per direction it owns, with the
   // vector in global memory (the larger case): FP64 Y_x and X; refined V1,
   // V2 and the FP32 correction
-  return (prec == RH_FP32_REFINED ? 2 * 8 + 4 : 2 * 8) * (int64_t)n_x;
+  return (prec == RH_FP32_REFINED ? 3 * 8 : 2 * 8) * ((int64_t)n_x + kWavePadRows);
 }
 
 rh_status device_alloc(void **p, size_t bytes, std::string &err) {

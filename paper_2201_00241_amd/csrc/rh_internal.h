@@ -65,37 +65,69 @@ struct Schedule {
 // its unit lower-triangular block (one lane group of 4 per row, one pass).
 constexpr int32_t kWaveBlockRows = 16;
 
-// Device form of a schedule.  Every unit (a level step, the rows of a block,
-// or one wave level of a wave step) stores its entries in per-lane slots:
-// rows are spread over groups of 2^lg lanes, `groups` rows per pass, and lane
-// j of a group holds entries j, j + 2^lg, ... of its row, `E` slots per lane
-// and pass (E a multiple of 4), padded with (column 0, value 0).  A pass
-// occupies slots slot_base + pass * E * lanes onwards and keeps a lane's
-// columns in quads and its values in pairs: the column of slot (e, lane) sits
-// at + (e >> 2) * 4 lanes + 4 lane + (e & 3), its value at + (e >> 1) * 2
-// lanes + 2 lane + (e & 1), so a lane reads four columns, or two values, with
-// one access, the quads (pairs) of a pass's lanes are contiguous, and a lane
-// needs no row pointer.  Wave-step units have one pass.
-// units: 8 ints each {slot_base, info_base, rows, groups, lg, E, lanes,
-// compact}; for wave-step units compact = lanes | lg << 7 | assign << 10 |
-// E << 11 (their rows = groups = lanes >> lg), else -1.  An assigning unit
-// writes its rows' dot products (x_i = sum) instead of x_i - sum; it is the
-// second half of a wave block and reads only rows of that block.
+// Device form of a schedule.
+//
+// Level and block steps: every unit (a level step or the rows of a block)
+// stores its entries in per-lane slots: rows are spread over groups of 2^lg
+// lanes, `groups` rows per pass, and lane j of a group holds entries j,
+// j + 2^lg, ... of its row, `E` slots per lane and pass (E a multiple of 4),
+// padded with (column 0, value 0).  A pass occupies slots slot_base + pass *
+// E * lanes onwards and keeps a lane's columns in quads and its values in
+// pairs: the column of slot (e, lane) sits at + (e >> 2) * 4 lanes + 4 lane +
+// (e & 3), its value at + (e >> 1) * 2 lanes + 2 lane + (e & 1), so a lane
+// reads four columns, or two values, with one access, and the quads (pairs)
+// of a pass's lanes are contiguous.
+// units: 8 ints each {slot_base, info_base, rows, groups, lg, E, lanes, -1};
 // irow/idinv give each row's matrix row and reciprocal pivot (unit order).
 // Slot 0 and dense[0] are a zero padding entry (offsets start at 1) that
-// lanes without an entry read.  Wave units have one pass and at least
-// kSlotsAhead slots per lane.
+// lanes without an entry read.
 // steps: 4 ints each {unit or wave directory offset, 0, kind, dense offset},
 // kind 0 = level, 1 = block (dense inverse at the offset), 2 = wave step
-// (its waves' unit ranges are wdir[off + w] .. wdir[off + w + 1]).
-// Entry slots per lane that the kernel loads ahead of a unit; wave units are
-// packed to fit in them where 64 lanes allow.
+// (its waves' wave-unit ranges are wdir[off + w] .. wdir[off + w + 1]).
+//
+// Wave steps: fixed-shape wave units (one wave, one pass, 64 lanes, four
+// entry slots per lane), so that a wave walks them with no per-unit decode:
+// rows of 2^wlg[u] lanes each; lane j of a row's group holds entries j,
+// j + 2^lg, j + 2 * 2^lg, j + 3 * 2^lg.  Every position is a byte offset into
+// a padded vector whose first kWavePadRows rows are not the solution's: row 0
+// is a zero that is never changed (padding reads it), rows 1 .. 64 take the
+// writes of lanes that own no row (lane l writes row 1 + l), and solution row
+// i sits at row i + kWavePadRows; offsets are for 8-byte rows (the kernel
+// scales them for other row sizes).  Record of unit u, per lane l:
+//   wcol[256 u + 4 l + e]  offset of entry e's column (padding: row 0)
+//   wrow[128 u + 2 l]      offset of the row the lane's update starts from:
+//                          its own row, or row 0 (the second unit of a
+//                          wave block, and lanes without a row); bit
+//                          kWaveActBit: lane l has entries in the unit
+//                          kWaveAhead units later on the same wave (its
+//                          column quad and first value pair are loaded),
+//                          bit kWaveTwoBit: it has entries 2 or 3 there (its
+//                          second value pair is loaded); lanes whose loads
+//                          are skipped read zeros (column row 0, value 0)
+//   wrow[128 u + 2 l + 1]  offset the lane writes: its row for the first lane
+//                          of a group, else its dummy row 1 + l; bits
+//                          kWaveLgShift and up hold the unit's lg
+//   wval[256 u + 128 (e >> 1) + 2 l + (e & 1)]  entry e's value (negated in the
+//                          second unit of a wave block, so that every lane
+//                          computes x = X[start] - sum of value * X[column])
+// A row of a wave level with more than 256 entries is continued by further
+// units right after the level's first (each adds 256 more entries of the
+// row to its partial value).
 constexpr int kSlotsAhead = 4;
+constexpr int32_t kWavePadRows = 65;
+constexpr int kWaveLgShift = 29;
+constexpr int kWaveActBit = 30, kWaveTwoBit = 31;
+constexpr uint32_t kWaveOffMask = (1u << kWaveLgShift) - 1;
+// Records a wave has in flight while it walks its units (the distance of
+// the load flags above).
+constexpr int kWaveAhead = 2;
 
 struct Packed {
   std::vector<int32_t> steps, units, wdir;
   std::vector<int32_t> scol, irow;
   std::vector<double> sval, idinv, dense;
+  std::vector<int32_t> wlg, wcol, wrow;
+  std::vector<double> wval;
 };
 
 struct ScheduleParams {

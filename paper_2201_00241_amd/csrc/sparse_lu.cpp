@@ -701,18 +701,17 @@ std::vector<int32_t> etree_parent(const LuPlan &lu) {
 
 namespace {
 
-// One unit: rows at positions [b, b + rows) of sc.s with lane groups of 2^lg.
-int32_t pack_unit(const Schedule &sc, int32_t b, int32_t rows, int lg, int max_lanes, int assign, int32_t min_E,
-                  bool wave, Packed &pk) {
+// One level or block unit: rows at positions [b, b + rows) of sc.s with lane
+// groups of 2^lg.
+int32_t pack_unit(const Schedule &sc, int32_t b, int32_t rows, int lg, int max_lanes, Packed &pk) {
   const Sweep &s = sc.s;
   const int32_t w = 1 << lg;
   const int32_t groups = std::max<int32_t>(1, std::min<int32_t>(rows, max_lanes / w));
   const int32_t lanes = groups * w;
   const int32_t passes = rows > 0 ? (rows + groups - 1) / groups : 0;
-  if (wave && passes > 1) throw std::runtime_error("internal: a wave unit has one pass");
   int32_t longest = 0;
   for (int32_t r = 0; r < rows; ++r) longest = std::max(longest, s.ptr[b + r + 1] - s.ptr[b + r]);
-  const int32_t E0 = std::max(min_E, (longest + w - 1) / w);
+  const int32_t E0 = (longest + w - 1) / w;
   const int32_t E = (E0 + 3) & ~3;  // whole column quads
   const int32_t slot_base = (int32_t)pk.scol.size(), info_base = (int32_t)pk.irow.size();
   pk.scol.resize(pk.scol.size() + (size_t)passes * E * lanes, 0);
@@ -735,11 +734,76 @@ int32_t pack_unit(const Schedule &sc, int32_t b, int32_t rows, int lg, int max_l
     if (!s.dinv.empty()) pk.idinv.push_back(s.dinv[pos]);
   }
   const int32_t u = (int32_t)(pk.units.size() / 8);
-  // compact form for the per-lane unit tables of wave steps (64 lanes)
-  // wave units have one pass, so rows = lanes >> lg and lanes <= 64
-  const int32_t compact = !wave ? -1 : (lanes <= 64 && E < (1 << 20)) ? (lanes | lg << 7 | assign << 10 | E << 11) : -2;
-  pk.units.insert(pk.units.end(), {slot_base, info_base, rows, groups, lg, E, lanes, compact});
+  pk.units.insert(pk.units.end(), {slot_base, info_base, rows, groups, lg, E, lanes, -1});
   return u;
+}
+
+// Byte offset of padded-vector row r (8-byte rows), see Packed.
+int32_t wave_off(int32_t r) { return r * 8; }
+
+// One fixed-shape wave unit (see Packed): part k of each listed row (entries
+// 256 k .. 256 k + 255 of its entries at positions `pos` of sc.s), lane
+// groups of 2^lg.
+struct WaveRow {
+  int32_t pos, first, end;  // position in sc.s and the entry range of this part
+};
+
+// Returns the entry count of each lane in `cnt` (64 per unit).
+void pack_wave_unit(const Schedule &sc, const std::vector<WaveRow> &rows, int lg, bool assign, Packed &pk,
+                    std::vector<uint8_t> &cnt) {
+  const Sweep &s = sc.s;
+  const int32_t w = 1 << lg;
+  if ((int32_t)rows.size() * w > 64) throw std::runtime_error("internal: wave unit wider than a wave");
+  const size_t c0 = pk.wcol.size(), r0 = pk.wrow.size(), v0 = pk.wval.size();
+  pk.wcol.resize(c0 + 256, wave_off(0));
+  pk.wrow.resize(r0 + 128, wave_off(0));
+  pk.wval.resize(v0 + 256, 0.0);
+  for (int32_t l = 0; l < 64; ++l) pk.wrow[r0 + 2 * l + 1] = wave_off(1 + l);  // dummy rows
+  const int32_t lgbits = (int32_t)((uint32_t)lg << kWaveLgShift);
+  const size_t k0 = cnt.size();
+  cnt.resize(k0 + 64, 0);
+  for (size_t r = 0; r < rows.size(); ++r) {
+    const WaveRow &R = rows[r];
+    const int32_t row = s.rows[R.pos] + kWavePadRows, len = R.end - R.first;
+    if (len > 4 * w) throw std::runtime_error("internal: wave row part longer than its lanes' slots");
+    for (int32_t j = 0; j < w; ++j) {
+      const int32_t l = (int32_t)r * w + j;
+      pk.wrow[r0 + 2 * l] = assign ? wave_off(0) : wave_off(row);
+      if ((uint32_t)wave_off(row) > kWaveOffMask) throw std::runtime_error("network too large for wave offsets");
+      if (j == 0) pk.wrow[r0 + 2 * l + 1] = wave_off(row);
+      for (int32_t e = 0; e < 4; ++e) {
+        const int32_t q = j + e * w;
+        if (q >= len) continue;
+        pk.wcol[c0 + 4 * l + e] = wave_off(s.col[R.first + q] + kWavePadRows);
+        const double v = s.val[R.first + q];
+        pk.wval[v0 + 128 * (e >> 1) + 2 * l + (e & 1)] = assign ? -v : v;
+        cnt[k0 + l] = (uint8_t)(e + 1);
+      }
+    }
+  }
+  for (int32_t l = 0; l < 64; ++l) pk.wrow[r0 + 2 * l + 1] |= lgbits;
+  pk.wlg.push_back(lg);
+}
+
+// Load flags of a wave's units u0 .. u1 - 1 (see Packed): unit u carries in
+// its start words which lanes of unit u + kWaveAhead have entries, and which
+// have entries 2 or 3.
+void set_wave_flags(Packed &pk, const std::vector<uint8_t> &cnt, int32_t u0, int32_t u1) {
+  for (int32_t u = u0; u + kWaveAhead < u1; ++u)
+    for (int32_t l = 0; l < 64; ++l) {
+      const uint8_t c = cnt[64 * (size_t)(u + kWaveAhead) + l];
+      uint32_t w = (uint32_t)pk.wrow[128 * (size_t)u + 2 * l];
+      if (c >= 1) w |= 1u << kWaveActBit;
+      if (c >= 3) w |= 1u << kWaveTwoBit;
+      pk.wrow[128 * (size_t)u + 2 * l] = (int32_t)w;
+    }
+}
+
+// Lanes per row (log2) so that `longest` entries fit in four slots per lane.
+int wave_lg(int32_t longest) {
+  int lg = 0;
+  while (lg < 6 && (1 << lg) * kSlotsAhead < longest) ++lg;
+  return lg;
 }
 
 }  // namespace
@@ -752,40 +816,66 @@ Packed pack_schedule(const Schedule &sc, int lanes) {
   pk.sval.assign(1, 0.0);
   pk.dense.assign(1, 0.0);
   pk.dense.insert(pk.dense.end(), sc.dense.begin(), sc.dense.end());
+  constexpr int32_t kPart = 64 * kSlotsAhead;  // entries of one row in one wave unit
   const size_t ns = sc.meta.size() / 4;
   for (size_t st = 0; st < ns; ++st) {
     const int32_t b = sc.meta[4 * st], rows = sc.meta[4 * st + 1], lg = sc.meta[4 * st + 2];
     const int32_t kind = sc.meta[4 * st + 3];
     if (kind <= -2) {
+      if (!sc.s.dinv.empty()) throw std::runtime_error("internal: wave steps need a unit diagonal");
       const int32_t d = -2 - kind;
       const int32_t off = (int32_t)pk.wdir.size();
       const int32_t nw = lanes / 64;
+      std::vector<uint8_t> cnt;  // entries per lane of every wave unit
       for (int32_t w = 0; w < nw; ++w) {
-        pk.wdir.push_back((int32_t)(pk.units.size() / 8));
+        const int32_t wu0 = (int32_t)pk.wlg.size();
+        cnt.resize(64 * (size_t)wu0, 0);
+        pk.wdir.push_back(wu0);
         for (int32_t j = sc.wdir[d + w]; j < sc.wdir[d + w + 1]; ++j) {
           const int32_t b = sc.wlev[4 * j], rows = sc.wlev[4 * j + 1], assign = sc.wlev[4 * j + 3];
-          // a plain (subtracting) wave unit's rows are independent: split it
-          // into one-pass units with lane groups wide enough that every row
-          // fits in the slots the kernel loads ahead (as far as 64 lanes allow)
-          int32_t per = rows, lg = sc.wlev[4 * j + 2];
-          if (!assign) {
+          if (assign) {
+            // the second unit of a wave block reads all its rows before it
+            // writes any: one unit
             int32_t longest = 0;
-            for (int32_t r = 0; r < rows; ++r) longest = std::max(longest, sc.s.ptr[b + r + 1] - sc.s.ptr[b + r]);
-            lg = 0;
-            while (lg < 6 && (1 << lg) * kSlotsAhead < longest) ++lg;
-            per = std::max(1, 64 >> lg);
+            std::vector<WaveRow> rs;
+            for (int32_t r = 0; r < rows; ++r) {
+              rs.push_back({b + r, sc.s.ptr[b + r], sc.s.ptr[b + r + 1]});
+              longest = std::max(longest, sc.s.ptr[b + r + 1] - sc.s.ptr[b + r]);
+            }
+            pack_wave_unit(sc, rs, wave_lg(longest), true, pk, cnt);
+            continue;
           }
-          // one pass, padded to kSlotsAhead slots per lane (the kernel's
-          // fixed-shape fast path)
-          for (int32_t r0 = 0; r0 < rows; r0 += per)
-            if (pk.units[8 * pack_unit(sc, b + r0, std::min(per, rows - r0), lg, 64, assign, kSlotsAhead, true, pk) + 7] < 0)
-              throw std::runtime_error("wave level too large for the compact unit form");
+          // a subtracting unit's rows are independent: split it into units
+          // of 64 >> lg rows with lanes enough for each row's first 256
+          // entries; longer rows continue in further units
+          int32_t longest = 0, parts = 1;
+          for (int32_t r = 0; r < rows; ++r) {
+            const int32_t len = sc.s.ptr[b + r + 1] - sc.s.ptr[b + r];
+            longest = std::max(longest, std::min(len, kPart));
+            parts = std::max(parts, (len + kPart - 1) / kPart);
+          }
+          for (int32_t k = 0; k < parts; ++k) {
+            std::vector<WaveRow> rs;
+            int32_t lk = 0;
+            for (int32_t r = 0; r < rows; ++r) {
+              const int32_t q0 = sc.s.ptr[b + r] + k * kPart, q1 = std::min(sc.s.ptr[b + r + 1], q0 + kPart);
+              if (k > 0 && q0 >= q1) continue;
+              rs.push_back({b + r, q0, std::max(q0, q1)});
+              lk = std::max(lk, q1 - q0);
+            }
+            const int ul = wave_lg(k == 0 ? longest : lk);
+            const size_t per = (size_t)std::max(1, 64 >> ul);
+            for (size_t r0 = 0; r0 < rs.size(); r0 += per)
+              pack_wave_unit(sc, std::vector<WaveRow>(rs.begin() + r0, rs.begin() + std::min(rs.size(), r0 + per)),
+                             ul, false, pk, cnt);
+          }
         }
+        set_wave_flags(pk, cnt, wu0, (int32_t)pk.wlg.size());
       }
-      pk.wdir.push_back((int32_t)(pk.units.size() / 8));
+      pk.wdir.push_back((int32_t)pk.wlg.size());
       pk.steps.insert(pk.steps.end(), {off, 0, 2, 0});
     } else {
-      const int32_t u = pack_unit(sc, b, rows, lg, lanes, 0, 0, false, pk);
+      const int32_t u = pack_unit(sc, b, rows, lg, lanes, pk);
       pk.steps.insert(pk.steps.end(), {u, 0, kind >= 0 ? 1 : 0, kind >= 0 ? kind + 1 : 0});
     }
   }

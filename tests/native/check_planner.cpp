@@ -104,36 +104,76 @@ static void emulate(const Schedule &sc, std::vector<double> &X, bool &ok) {
   (void)done;
 }
 
-// The kernel walks a wave's units from the compact words alone: the slot
-// base and row-info base of each unit are running sums from the wave's first
-// unit, and lanes/groups/passes follow from rows and lg.  Returns false if
-// any wave unit disagrees with its stored descriptor.
-static bool check_wave_walk(const Packed &pk) {
+// The wave-unit arrays the kernel walks: whole 64-lane records, unit ranges
+// of the waves in order, every offset a whole 8-byte row of the padded
+// vector (n rows behind kWavePadRows) and lg within a wave.  Returns false
+// on any inconsistency.
+static bool check_wave_walk(const Packed &pk, int n) {
+  const size_t nu = pk.wlg.size();
+  if (pk.wcol.size() != 256 * nu || pk.wrow.size() != 128 * nu || pk.wval.size() != 256 * nu) return false;
+  const long lim = 8L * (n + kWavePadRows);
+  for (int32_t o : pk.wcol)
+    if (o < 0 || o % 8 || o >= lim) return false;
+  for (size_t k = 0; k < pk.wrow.size(); ++k) {
+    const long o = (long)((uint32_t)pk.wrow[k] & kWaveOffMask);
+    if (o % 8 || o >= lim) return false;
+    if (k % 2 == 1 && (int)((uint32_t)pk.wrow[k] >> kWaveLgShift) != pk.wlg[k / 128]) return false;
+    if (k % 2 == 0 && ((uint32_t)pk.wrow[k] >> kWaveLgShift & 1u)) return false;  // unused bit
+  }
+  for (int32_t lg : pk.wlg)
+    if (lg < 0 || lg > 6) return false;
+  int prev = 0;
   for (size_t st = 0; st < pk.steps.size() / 4; ++st) {
     if (pk.steps[4 * st + 2] != 2) continue;
     const int a = pk.steps[4 * st];
-    for (int w = 0; w < 16; ++w) {
-      const int u0 = pk.wdir[a + w], u1 = pk.wdir[a + w + 1];
-      if (u0 >= u1) continue;
-      long sb = pk.units[8 * u0], ib = pk.units[8 * u0 + 1];
-      for (int u = u0; u < u1; ++u) {
-        const int *U = &pk.units[8 * u];
-        const int cw = U[7];
-        if (cw < 0) return false;
-        const int lanes = cw & 127, lg = (cw >> 7) & 7, E = (int)((unsigned)cw >> 11);
-        const int rows = lanes >> lg, groups = rows;
-        if (U[0] != sb || U[1] != ib || U[2] != rows || U[3] != groups || U[4] != lg || U[5] != E || U[6] != lanes)
-          return false;
-        if (E % 4 != 0 || rows > groups) return false;  // column quads, one pass
-        const int passes = (rows + (64 >> lg) - 1) >> (6 - lg);
-        if (passes != (rows + groups - 1) / groups && rows > 0) return false;
-        if (sb + (long)passes * E * lanes > (long)pk.scol.size() || ib + rows > (long)pk.irow.size()) return false;
-        sb += (long)passes * E * lanes;
-        ib += rows;
-      }
+    for (int w = 0; w <= 16; ++w) {
+      const int u = pk.wdir[a + w];
+      if (u < prev || u > (int)nu) return false;
+      prev = u;
     }
   }
   return true;
+}
+
+// One fixed-shape wave unit on the padded vector Xp: every lane sums its four
+// slots, lane groups combine, and every lane writes X[start] - sum to its
+// write row (all reads before any write, as in one wave).  Reads of rows not
+// yet final clear `ok`; so does a change of the zero row, or a row written
+// by more than one lane.
+// `act`/`two`: which lanes load their column quad and first value pair, and
+// their second value pair (the flags carried kWaveAhead units earlier; all
+// for a wave's first units); a skipped load reads zeros.  A lane with an
+// entry its flags skip clears `ok`.
+static void wave_unit(const Packed &pk, int u, const bool *act, const bool *two, std::vector<double> &Xp,
+                      std::vector<char> &pend, bool &ok) {
+  const int w = 1 << pk.wlg[u];
+  double part[64], nv[64];
+  for (int l = 0; l < 64; ++l) {
+    part[l] = 0.0;
+    for (int e = 0; e < 4; ++e) {
+      const bool loaded = act[l] && (e < 2 || two[l]);
+      const double v0 = pk.wval[256 * u + 128 * (e >> 1) + 2 * l + (e & 1)];
+      if (!loaded && v0 != 0.0) ok = false;
+      const int c = loaded ? pk.wcol[256 * u + 4 * l + e] / 8 : 0;
+      const double v = loaded ? v0 : 0.0;
+      if (v != 0.0 && pend[c]) ok = false;
+      part[l] += v * Xp[c];
+    }
+  }
+  for (int l = 0; l < 64; ++l) {
+    double t = 0.0;
+    for (int j = (l / w) * w; j < (l / w + 1) * w; ++j) t += part[j];
+    nv[l] = Xp[(pk.wrow[128 * u + 2 * l] & kWaveOffMask) / 8] - t;
+  }
+  std::vector<int> hits(Xp.size(), 0);
+  for (int l = 0; l < 64; ++l) {
+    const int r = (int)(((uint32_t)pk.wrow[128 * u + 2 * l + 1] & kWaveOffMask) / 8);
+    if (r == 0 && nv[l] != 0.0) ok = false;
+    if (r >= kWavePadRows && ++hits[r] > 1) ok = false;
+    Xp[r] = nv[l];
+    if (r >= kWavePadRows) pend[r] = 0;
+  }
+  if (Xp[0] != 0.0) ok = false;
 }
 
 // Emulates the kernel on the packed (per-lane slot) form: every lane sums its
@@ -144,7 +184,7 @@ static void emulate_packed(const Packed &pk, std::vector<double> &X, std::vector
     const int *U = &pk.units[8 * u];
     const int slot_base = U[0], info_base = U[1], rows = U[2], groups = U[3], lg = U[4], E = U[5],
               lanes = U[6];
-    const bool assign = U[7] >= 0 && ((U[7] >> 10) & 1);
+    const bool assign = false;
     const int w = 1 << lg;
     r.assign(rows, 0.0);
     std::vector<double> part(rows, 0.0);
@@ -175,12 +215,32 @@ static void emulate_packed(const Packed &pk, std::vector<double> &X, std::vector
     }
   };
   std::vector<double> r;
+  // the padded vector of the wave units: zero row, dummy rows, then X
+  const size_t n = X.size();
+  std::vector<double> Xp(n + kWavePadRows, 0.0);
+  std::vector<char> pp(n + kWavePadRows, 0);
   for (size_t st = 0; st < pk.steps.size() / 4; ++st) {
     const int a = pk.steps[4 * st], kind = pk.steps[4 * st + 2], off = pk.steps[4 * st + 3];
     if (kind == 2) {
+      for (size_t i = 0; i < n; ++i) {
+        Xp[i + kWavePadRows] = X[i];
+        pp[i + kWavePadRows] = pending[i];
+      }
       const int nw = 16;
       for (int w = nw - 1; w >= 0; --w)
-        for (int u = pk.wdir[a + w]; u < pk.wdir[a + w + 1]; ++u) unit(u, false, r);
+        for (int u = pk.wdir[a + w]; u < pk.wdir[a + w + 1]; ++u) {
+          bool act[64], two[64];
+          for (int l = 0; l < 64; ++l) {
+            const uint32_t f = u - kWaveAhead >= pk.wdir[a + w] ? (uint32_t)pk.wrow[128 * (u - kWaveAhead) + 2 * l] : ~0u;
+            act[l] = (f >> kWaveActBit) & 1u;
+            two[l] = (f >> kWaveTwoBit) & 1u;
+          }
+          wave_unit(pk, u, act, two, Xp, pp, ok);
+        }
+      for (size_t i = 0; i < n; ++i) {
+        X[i] = Xp[i + kWavePadRows];
+        pending[i] = pp[i + kWavePadRows];
+      }
     } else if (kind == 0) {
       unit(a, false, r);
     } else {
@@ -327,7 +387,7 @@ int main(int argc, char **argv) {
           for (int32_t rr : sw[k].rows) pend[rr] = 1;
           bool okp = true;
           emulate_packed(pk, Xa, pend, okp);
-          if (!check_wave_walk(pk)) {
+          if (!check_wave_walk(pk, nx)) {
             printf("wave_walk_mismatch %s_w%d_b%d\n", nm[k], wave, bmax);
             okp = false;
           }

@@ -151,4 +151,5 @@ def test_refinement_figures_need_a_refined_call(ctx):
     ctx.set_refinement_tol(1e-13)
     resident, per_dir = net.device_bytes(rh.RH_FP32_REFINED)
     assert resident == 0  # host-only context: nothing on a device
-    assert per_dir == 20 * net.n_x
+    # V1, V2 (FP64) and the FP32 correction, each padded by the zero and dummy rows
+    assert per_dir == 24 * (net.n_x + 65)
