@@ -1,4 +1,5 @@
 // C ABI entry points of librh (declared in include/rh.h).
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -348,8 +349,13 @@ rh_status rh_reduced_hessian_device(rh_network *net, void *dH, int64_t ldh, int3
     k = tk;
   }
   net->n.report.last_k = k;
-  for (int32_t j0 = 0; j0 < n_p; j0 += k) {
-    const int32_t kb = std::min(k, n_p - j0);
+  // consecutive blocks share a launch when one block leaves CUs idle at the
+  // directions per workgroup the network allows (a direction's product does
+  // not depend on the launch it runs in)
+  const int32_t want = device_launch_dirs(net->n, prec);
+  const int32_t group = std::max(1, std::min((want + k - 1) / k, (n_p + k - 1) / k));
+  for (int32_t j0 = 0; j0 < n_p; j0 += group * k) {
+    const int32_t kb = std::min(group * k, n_p - j0);
     s = device_hvp(net->n, kb, nullptr, 0, H + (int64_t)j0 * ldh, ldh, j0, prec, hip_stream, err);
     if (s != RH_OK) return fail(s, err);
   }

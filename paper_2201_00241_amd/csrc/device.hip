@@ -1519,18 +1519,25 @@ rh_status launch(bool lds, bool refined, int32_t groups, size_t lds_bytes, hipSt
   return RH_OK;
 }
 
-// Directions per workgroup: more share each factor entry, fewer keep the chip
-// busy.  Take the largest C (<= 2) that still gives two workgroups per CU and
-// whose vectors fit the LDS budget.
-// The choice does not change any direction's arithmetic.
+// Directions per workgroup: more share each record load, fewer keep the chip
+// busy.  Every kernel runs one 1,024-thread workgroup per CU (its registers
+// allow no second one), so take the largest C that still gives every CU a
+// workgroup and whose vectors fit the LDS budget.  The choice does not change
+// any direction's arithmetic.
+int32_t lds_max_c(int64_t n_x, size_t lds_max, bool lds, size_t elem) {
+  int32_t c = 4;  // the largest group the kernels are instantiated for
+  while (c > 1 && lds && (size_t)n_x * c * elem > lds_max) c >>= 1;
+  return c;
+}
+
 int32_t choose_c(int64_t k, int32_t cus, int64_t n_x, size_t lds_max, bool lds, size_t elem) {
   if (const char *e = std::getenv("RH_DIRS_PER_GROUP")) {
     const int v = std::atoi(e);
     if ((v == 1 || v == 2 || v == 4) && (!lds || (size_t)n_x * v * elem <= lds_max))
       return v;
   }
-  int32_t c = 4;  // the largest group the kernels are instantiated for
-  while (c > 1 && (k < (int64_t)c * 2 * cus || (lds && (size_t)n_x * c * elem > lds_max))) c >>= 1;
+  int32_t c = lds_max_c(n_x, lds_max, lds, elem);
+  while (c > 1 && k < (int64_t)c * cus) c >>= 1;
   return c;
 }
 
@@ -2283,6 +2290,16 @@ rh_status device_hvp_batch(Context &ctx, int32_t n, Network *const *nets, const 
   const int32_t refine = prec == RH_FP32_REFINED ? ctx.refine : -1;
   return run_items(ctx.dev->info, ctx.dev->on(stream), ctx.timing, refine, ctx.refine_tol, items, max_nx,
                    (hipStream_t)stream, err);
+}
+
+int32_t device_launch_dirs(const Network &net, rh_precision prec) {
+  const DeviceNet *dn = net.dev;
+  if (!dn) return 1;
+  const bool refined = prec == RH_FP32_REFINED;
+  const size_t elem = refined ? sizeof(float) : sizeof(double);
+  const int64_t pad_rows = (int64_t)net.n_x + kWavePadRows;
+  const bool lds = (size_t)pad_rows * elem <= dn->info.lds_max && !std::getenv("RH_NO_LDS");
+  return lds_max_c(pad_rows, dn->info.lds_max, lds, elem) * dn->info.cus;
 }
 
 rh_status device_refinement_report(Network &net, int32_t n, std::vector<double> &out, std::string &err) {

@@ -248,6 +248,9 @@ rh_status device_memcpy_h2d(void *dst, const void *src, size_t bytes, std::strin
 rh_status device_memcpy_d2h(void *dst, const void *src, size_t bytes, std::string &err);
 rh_status device_memcpy_2d(void *dst, size_t dpitch, const void *src, size_t spitch,
                            size_t width, size_t rows, int to_device, std::string &err);
+// Directions one launch needs to give every CU a workgroup at the largest
+// number of directions per workgroup that the network's vectors allow.
+int32_t device_launch_dirs(const Network &net, rh_precision prec);
 // Per-column figures of the last refined product call: 4 doubles per column
 // {backward error of Z, corrections of Z, backward error of Psi, corrections of Psi}.
 rh_status device_refinement_report(Network &net, int32_t n, std::vector<double> &out, std::string &err);
