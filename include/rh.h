@@ -212,6 +212,27 @@ rh_status rh_hvp_batch_device(rh_context *ctx, int32_t n, rh_network *const *net
                               const int32_t *identity_from, rh_precision prec,
                               void *hip_stream);
 
+/* A batched launch recorded once and replayed (Sec. 4.3: the direction
+ * blocks of Algorithm 2 are independent, across instances as across
+ * directions; Sec. 6: many operating points of one grid).  rh_batch_create
+ * takes the arguments of rh_hvp_batch_device, uploads the work list,
+ * allocates the launch scratch and records the single batched kernel launch
+ * as a HIP graph; rh_batch_launch replays it on hip_stream (one graph launch,
+ * no host-side work list and no allocation).  The device buffers dW/dHW are
+ * bound at creation: every replay reads their current contents and overwrites
+ * the products.  A network re-solved or given new loads or parameters since
+ * creation makes rh_batch_launch return RH_ESTATE (its device data moved);
+ * create a new batch then.  No per-column refinement figures are recorded.
+ * rh_batch_info gives the launch shape (directions per workgroup,
+ * workgroups, directions).  rh_batch_destroy waits for the device. */
+typedef struct rh_batch rh_batch; /* opaque, library-owned */
+rh_status rh_batch_create(rh_context *ctx, int32_t n, rh_network *const *nets, const int32_t *k,
+                          const void *const *dW, const int64_t *ldw, void *const *dHW, const int64_t *ldhw,
+                          const int32_t *identity_from, rh_precision prec, rh_batch **out);
+rh_status rh_batch_launch(rh_batch *b, void *hip_stream);
+rh_status rh_batch_info(const rh_batch *b, int32_t *dirs_per_group, int32_t *workgroups, int32_t *directions);
+rh_status rh_batch_destroy(rh_batch *b);
+
 /* Per-column figures of the last RH_FP32_REFINED call of rh_hvp,
  * rh_hvp_device, rh_reduced_hessian or rh_reduced_hessian_device on the
  * network (batched calls record none).  For columns j < n (n at most that

@@ -466,17 +466,19 @@ rh_status rh_refinement_report(const rh_network *net, int32_t n, double *berr_z,
   GUARD_END
 }
 
-rh_status rh_hvp_batch_device(rh_context *ctx, int32_t n, rh_network *const *nets, const int32_t *k,
-                              const void *const *dW, const int64_t *ldw, void *const *dHW,
-                              const int64_t *ldhw, const int32_t *identity_from, rh_precision prec,
-                              void *hip_stream) {
-  GUARD_BEGIN
+}  // extern "C"
+
+namespace {
+// Checks of a batch (rh_hvp_batch_device, rh_batch_create); fills ns.
+rh_status check_batch(rh_context *ctx, int32_t n, rh_network *const *nets, const int32_t *k, const void *const *dW,
+                      const int64_t *ldw, void *const *dHW, const int64_t *ldhw, const int32_t *identity_from,
+                      rh_precision prec, std::vector<Network *> &ns) {
   if (!ctx) return fail(RH_EINVAL, "null context");
   if (ctx->c.device < 0) return fail(RH_EDEVICE, "host-only context");
   if (prec != RH_FP64 && prec != RH_FP32_REFINED) return fail(RH_EINVAL, "unknown precision");
   if (n < 0 || (n > 0 && (!nets || !k || !dW || !ldw || !dHW || !ldhw)))
     return fail(RH_EINVAL, "bad batch arguments");
-  std::vector<Network *> ns(n);
+  ns.assign(n, nullptr);
   for (int32_t i = 0; i < n; ++i) {
     if (!nets[i]) return fail(RH_EINVAL, "null network in batch");
     Network &net = nets[i]->n;
@@ -493,13 +495,74 @@ rh_status rh_hvp_batch_device(rh_context *ctx, int32_t n, rh_network *const *net
     if (idf >= 0 && (int64_t)idf + k[i] > net.n_p) return fail(RH_EINVAL, "identity block exceeds n_p in " + where);
     ns[i] = &net;
   }
+  return RH_OK;
+}
+}  // namespace
+
+struct rh_batch {
+  DeviceBatch *b = nullptr;
+};
+
+extern "C" {
+
+rh_status rh_hvp_batch_device(rh_context *ctx, int32_t n, rh_network *const *nets, const int32_t *k,
+                              const void *const *dW, const int64_t *ldw, void *const *dHW,
+                              const int64_t *ldhw, const int32_t *identity_from, rh_precision prec,
+                              void *hip_stream) {
+  GUARD_BEGIN
+  std::vector<Network *> ns;
+  rh_status s = check_batch(ctx, n, nets, k, dW, ldw, dHW, ldhw, identity_from, prec, ns);
+  if (s != RH_OK) return s;
   std::string err;
-  rh_status s = device_hvp_batch(ctx->c, n, ns.data(), k, reinterpret_cast<const double *const *>(dW),
-                                 ldw, reinterpret_cast<double *const *>(dHW), ldhw, identity_from,
-                                 prec, hip_stream, err);
+  s = device_hvp_batch(ctx->c, n, ns.data(), k, reinterpret_cast<const double *const *>(dW), ldw,
+                       reinterpret_cast<double *const *>(dHW), ldhw, identity_from, prec, hip_stream, err);
   if (s != RH_OK) return fail(s, err);
   return RH_OK;
   GUARD_END
+}
+
+rh_status rh_batch_create(rh_context *ctx, int32_t n, rh_network *const *nets, const int32_t *k,
+                          const void *const *dW, const int64_t *ldw, void *const *dHW, const int64_t *ldhw,
+                          const int32_t *identity_from, rh_precision prec, rh_batch **out) {
+  GUARD_BEGIN
+  if (!out) return fail(RH_EINVAL, "null out");
+  *out = nullptr;
+  std::vector<Network *> ns;
+  rh_status s = check_batch(ctx, n, nets, k, dW, ldw, dHW, ldhw, identity_from, prec, ns);
+  if (s != RH_OK) return s;
+  std::string err;
+  DeviceBatch *db = nullptr;
+  s = device_batch_create(ctx->c, n, ns.data(), k, reinterpret_cast<const double *const *>(dW), ldw,
+                          reinterpret_cast<double *const *>(dHW), ldhw, identity_from, prec, &db, err);
+  if (s != RH_OK) return fail(s, err);
+  rh_batch *b = new rh_batch();
+  b->b = db;
+  *out = b;
+  return RH_OK;
+  GUARD_END
+}
+
+rh_status rh_batch_launch(rh_batch *b, void *hip_stream) {
+  GUARD_BEGIN
+  if (!b || !b->b) return fail(RH_EINVAL, "null batch");
+  std::string err;
+  rh_status s = device_batch_launch(b->b, hip_stream, err);
+  if (s != RH_OK) return fail(s, err);
+  return RH_OK;
+  GUARD_END
+}
+
+rh_status rh_batch_info(const rh_batch *b, int32_t *dirs_per_group, int32_t *workgroups, int32_t *directions) {
+  if (!b || !b->b) return fail(RH_EINVAL, "null batch");
+  device_batch_info(b->b, dirs_per_group, workgroups, directions);
+  return RH_OK;
+}
+
+rh_status rh_batch_destroy(rh_batch *b) {
+  if (!b) return RH_OK;
+  device_batch_free(b->b);
+  delete b;
+  return RH_OK;
 }
 
 rh_status rh_context_report(rh_context *ctx, rh_report *out) {

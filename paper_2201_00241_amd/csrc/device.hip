@@ -683,8 +683,19 @@ __device__ __forceinline__ void wave_walk(const DevSweep AS4 &s, int32_t u0, int
       for (int e = 0; e < 4; ++e)
 #pragma unroll
         for (int c = 0; c < C; ++c) part[c] = fma(ring[d].val[e], xv[e][c], part[c]);
+      T nv[C];
 #pragma unroll
-      for (int c = 0; c < C; ++c) xput<C, T, LDSX>(Xpad, rw, c, xr[c] - group_sum(part[c], lg));
+      for (int c = 0; c < C; ++c) nv[c] = xr[c] - group_sum(part[c], lg);
+      if constexpr (LDSX) {
+        // every lane writes (lanes without a row to their dummy rows): no
+        // mask, and LDS writes of distinct rows cost little
+#pragma unroll
+        for (int c = 0; c < C; ++c) xput<C, T, LDSX>(Xpad, rw, c, nv[c]);
+      } else if (rw >= (uint32_t)kWavePadRows * 8u) {
+        // in global memory only the lanes that own a row store
+#pragma unroll
+        for (int c = 0; c < C; ++c) xput<C, T, LDSX>(Xpad, rw, c, nv[c]);
+      }
       wave_sync<LDSX>();  // this wave's writes before its next unit's reads
       // the record kWaveAhead units on, into the registers this one held
       wrec_load<T>(R, soff, nc, vr, nv0, nv1, ring[d]);
@@ -1483,17 +1494,36 @@ rh_status no_static_lds(const void *kernel, int &checked, std::string &err) {
   return RH_OK;
 }
 
+// Launch the kernel for C directions per workgroup.  The per-kernel attribute
+// calls come first; a launch recorded into a graph makes them beforehand
+// (mode kAttrsOnly) and records the launch alone (kLaunchOnly).
+enum LaunchMode { kAttrsAndLaunch, kAttrsOnly, kLaunchOnly };
+
 template <int C>
 rh_status launch(bool lds, bool refined, int32_t groups, size_t lds_bytes, hipStream_t s,
-                 const LaunchArgs &la, std::string &err) {
+                 const LaunchArgs &la, std::string &err, LaunchMode mode = kAttrsAndLaunch) {
   static int checked_b = 0, checked_r = 0;
+  const bool attrs = mode != kLaunchOnly;
+  if (mode == kAttrsOnly) {
+    if (!lds) return RH_OK;
+    if constexpr (C <= 4) {
+      const void *k = refined ? reinterpret_cast<const void *>(&refined_kernel_lds<C>)
+                              : reinterpret_cast<const void *>(&block_kernel_lds<C>);
+      rh_status st = no_static_lds(k, refined ? checked_r : checked_b, err);
+      if (st != RH_OK) return st;
+      HIP_TRY(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+    }
+    return RH_OK;
+  }
   if (refined) {
     if constexpr (C <= 4) {
       if (lds) {
-        rh_status st = no_static_lds(reinterpret_cast<const void *>(&refined_kernel_lds<C>), checked_r, err);
-        if (st != RH_OK) return st;
-        HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&refined_kernel_lds<C>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+        if (attrs) {
+          rh_status st = no_static_lds(reinterpret_cast<const void *>(&refined_kernel_lds<C>), checked_r, err);
+          if (st != RH_OK) return st;
+          HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&refined_kernel_lds<C>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+        }
         hipLaunchKernelGGL(refined_kernel_lds<C>, dim3(groups), dim3(kThreadsLds), lds_bytes, s, la);
         HIP_TRY(hipGetLastError());
         return RH_OK;
@@ -1505,10 +1535,12 @@ rh_status launch(bool lds, bool refined, int32_t groups, size_t lds_bytes, hipSt
   }
   if constexpr (C <= 4) {
     if (lds) {
-      rh_status st = no_static_lds(reinterpret_cast<const void *>(&block_kernel_lds<C>), checked_b, err);
-      if (st != RH_OK) return st;
-      HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&block_kernel_lds<C>),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+      if (attrs) {
+        rh_status st = no_static_lds(reinterpret_cast<const void *>(&block_kernel_lds<C>), checked_b, err);
+        if (st != RH_OK) return st;
+        HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&block_kernel_lds<C>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+      }
       hipLaunchKernelGGL(block_kernel_lds<C>, dim3(groups), dim3(kThreadsLds), lds_bytes, s, la);
       HIP_TRY(hipGetLastError());
       return RH_OK;
@@ -1551,33 +1583,76 @@ struct FixedScratch {
   int64_t bytes;
 };
 
-rh_status run_items(const DeviceInfo &info, Runner &r, int32_t timing, int32_t refine, double refine_tol,
-                    std::vector<WorkItem> &items, int32_t max_nx, hipStream_t s, std::string &err,
-                    const FixedScratch *fixed = nullptr) {
+// Shape of one batched launch: directions per workgroup, where the working
+// vector lives, workgroups and their scratch, dynamic LDS.  Sets the items'
+// first chunks.
+struct LaunchPlan {
+  bool refined = false, lds = false;
+  int32_t C = 1, pad_rows = 0, groups = 0;
+  int64_t n_chunks = 0, stride = 0;  // stride: doubles of scratch per workgroup
+  size_t lds_bytes = 0;
+};
+
+rh_status plan_launch(const DeviceInfo &info, int32_t refine, std::vector<WorkItem> &items, int32_t max_nx,
+                      LaunchPlan &pl, std::string &err) {
   int64_t total_k = 0;
   for (const WorkItem &it : items) total_k += it.k;
+  pl = LaunchPlan();
   if (total_k <= 0) return RH_OK;
-  const bool refined = refine >= 0;
-  const size_t elem = refined ? sizeof(float) : sizeof(double);  // LDS vector element
-  const int32_t pad_rows = max_nx + kWavePadRows;                 // padded working vector
-  const bool lds = (size_t)pad_rows * elem <= info.lds_max && !std::getenv("RH_NO_LDS");
-  const int32_t C = choose_c(total_k, info.cus, pad_rows, info.lds_max, lds, elem);
-  int64_t n_chunks = 0;
+  pl.refined = refine >= 0;
+  const size_t elem = pl.refined ? sizeof(float) : sizeof(double);  // LDS vector element
+  pl.pad_rows = max_nx + kWavePadRows;                               // padded working vector
+  pl.lds = (size_t)pl.pad_rows * elem <= info.lds_max && !std::getenv("RH_NO_LDS");
+  const int32_t C = pl.C = choose_c(total_k, info.cus, pl.pad_rows, info.lds_max, pl.lds, elem);
   for (WorkItem &it : items) {
-    it.chunk0 = (int32_t)n_chunks;
-    n_chunks += (it.k + C - 1) / C;
+    it.chunk0 = (int32_t)pl.n_chunks;
+    pl.n_chunks += (it.k + C - 1) / C;
   }
-  if (n_chunks > INT32_MAX) {
+  if (pl.n_chunks > INT32_MAX) {
     err = "too many directions in one launch";
     return RH_EINVAL;
   }
   // per-workgroup scratch, 256-byte aligned: FP64 mode Y_x (+ X when it is
   // not in LDS); refined mode V1, V2 (+ the FP32 correction when not in LDS)
-  const int64_t parts = refined ? (lds ? 2 : 3) : (lds ? 1 : 2);
-  const int64_t stride = (parts * (int64_t)pad_rows * C + 31) / 32 * 32;
-  const int64_t max_groups_mem = std::max<int64_t>(1, (int64_t(8) << 30) / (stride * 8));
-  const int64_t per_cu = lds ? 1 : 2;
-  int32_t groups = (int32_t)std::min<int64_t>({n_chunks, max_groups_mem, (int64_t)info.cus * 8 * per_cu});
+  const int64_t parts = pl.refined ? (pl.lds ? 2 : 3) : (pl.lds ? 1 : 2);
+  pl.stride = (parts * (int64_t)pl.pad_rows * C + 31) / 32 * 32;
+  const int64_t max_groups_mem = std::max<int64_t>(1, (int64_t(8) << 30) / (pl.stride * 8));
+  const int64_t per_cu = pl.lds ? 1 : 2;
+  pl.groups = (int32_t)std::min<int64_t>({pl.n_chunks, max_groups_mem, (int64_t)info.cus * 8 * per_cu});
+  // dynamic LDS: the padded vector, then the kernels' small buffers (block
+  // residuals, slack scalars; the refined kernel's reduction buffer)
+  if (pl.lds) {
+    if (pl.refined)
+      pl.lds_bytes = (((size_t)pl.pad_rows * C + kBlockRows * C + 1) & ~size_t(1)) * sizeof(float) +
+                     (size_t)(C + kWaves * 2 * C) * sizeof(double);
+    else
+      pl.lds_bytes = ((size_t)pl.pad_rows * C + kBlockRows * C + C) * sizeof(double);
+  }
+  return RH_OK;
+}
+
+rh_status launch_plan(const LaunchPlan &pl, int32_t groups, hipStream_t s, const LaunchArgs &la, std::string &err,
+                      LaunchMode mode = kAttrsAndLaunch) {
+  switch (pl.C) {
+    case 1: return launch<1>(pl.lds, pl.refined, groups, pl.lds_bytes, s, la, err, mode);
+    case 2: return launch<2>(pl.lds, pl.refined, groups, pl.lds_bytes, s, la, err, mode);
+    case 4: return launch<4>(pl.lds, pl.refined, groups, pl.lds_bytes, s, la, err, mode);
+    default:
+      err = "internal: no kernel for " + std::to_string(pl.C) + " directions per workgroup";
+      return RH_EDEVICE;
+  }
+}
+
+rh_status run_items(const DeviceInfo &info, Runner &r, int32_t timing, int32_t refine, double refine_tol,
+                    std::vector<WorkItem> &items, int32_t max_nx, hipStream_t s, std::string &err,
+                    const FixedScratch *fixed = nullptr) {
+  LaunchPlan pl;
+  rh_status ps = plan_launch(info, refine, items, max_nx, pl, err);
+  if (ps != RH_OK || pl.n_chunks == 0) return ps;
+  const int32_t C = pl.C;
+  const int64_t n_chunks = pl.n_chunks, stride = pl.stride;
+  const int32_t pad_rows = pl.pad_rows;
+  int32_t groups = pl.groups;
   if (fixed) {
     // workgroups take further chunks in turn when the fixed range is short
     const int64_t fit = fixed->bytes / (stride * (int64_t)sizeof(double));
@@ -1666,25 +1741,7 @@ rh_status run_items(const DeviceInfo &info, Runner &r, int32_t timing, int32_t r
     r.ev_used += 2;
     HIP_TRY(hipEventRecord(e0, s));
   }
-  // dynamic LDS: the padded vector, then the kernels' small buffers (block
-  // residuals, slack scalars; the refined kernel's reduction buffer)
-  size_t lds_bytes = 0;
-  if (lds) {
-    if (refined)
-      lds_bytes = (((size_t)pad_rows * C + kBlockRows * C + 1) & ~size_t(1)) * sizeof(float) +
-                  (size_t)(C + kWaves * 2 * C) * sizeof(double);
-    else
-      lds_bytes = ((size_t)pad_rows * C + kBlockRows * C + C) * sizeof(double);
-  }
-  rh_status st;
-  switch (C) {
-    case 1: st = launch<1>(lds, refined, groups, lds_bytes, s, la, err); break;
-    case 2: st = launch<2>(lds, refined, groups, lds_bytes, s, la, err); break;
-    case 4: st = launch<4>(lds, refined, groups, lds_bytes, s, la, err); break;
-    default:
-      err = "internal: no kernel for " + std::to_string(C) + " directions per workgroup";
-      return RH_EDEVICE;
-  }
+  const rh_status st = launch_plan(pl, groups, s, la, err);
   if (st != RH_OK) return st;
   if (items.size() > 1) HIP_TRY(hipEventRecord(r.items_done, s));
   if (timing >= 1) HIP_TRY(hipEventRecord(e1, s));
@@ -1986,6 +2043,7 @@ rh_status device_upload(Network &net, std::string &err) {
   }
   DeviceNet *dn = new DeviceNet();
   net.dev = dn;
+  ++net.dev_gen;
   dn->run = keep;
   dn->rinfo = keep_rinfo;
   dn->rinfo_cols = keep_cols;
@@ -2300,6 +2358,138 @@ int32_t device_launch_dirs(const Network &net, rh_precision prec) {
   const int64_t pad_rows = (int64_t)net.n_x + kWavePadRows;
   const bool lds = (size_t)pad_rows * elem <= dn->info.lds_max && !std::getenv("RH_NO_LDS");
   return lds_max_c(pad_rows, dn->info.lds_max, lds, elem) * dn->info.cus;
+}
+
+struct DeviceBatch {
+  int device = -1;
+  std::vector<const Network *> nets;
+  std::vector<uint64_t> gens;
+  WorkItem *items_dev = nullptr;
+  double *scratch = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int32_t C = 0, groups = 0, dirs = 0;
+};
+
+void device_batch_free(DeviceBatch *b) {
+  if (!b) return;
+  if (b->device >= 0) {
+    (void)hipSetDevice(b->device);
+    (void)hipDeviceSynchronize();  // replays may still be in flight on the callers' streams
+  }
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  if (b->items_dev) (void)hipFree(b->items_dev);
+  if (b->scratch) (void)hipFree(b->scratch);
+  delete b;
+}
+
+namespace {
+rh_status batch_build(DeviceBatch &b, const DeviceInfo &info, int32_t refine, double refine_tol,
+                      std::vector<WorkItem> &items, int32_t max_nx, std::string &err) {
+  LaunchPlan pl;
+  rh_status ps = plan_launch(info, refine, items, max_nx, pl, err);
+  if (ps != RH_OK) return ps;
+  b.C = pl.C;
+  b.groups = pl.groups;
+  HIP_TRY(hipMalloc(&b.scratch, std::max<size_t>(256, (size_t)pl.groups * pl.stride * sizeof(double))));
+  LaunchArgs la{};
+  la.refine = refine;
+  la.refine_tol = refine_tol;
+  la.n_items = (int32_t)items.size();
+  la.n_chunks = (int32_t)pl.n_chunks;
+  la.scratch = b.scratch;
+  la.scratch_stride = pl.stride;
+  la.pad_rows = pl.pad_rows;
+  if (items.size() == 1) {
+    la.one = items[0];
+  } else {
+    HIP_TRY(hipMalloc(&b.items_dev, items.size() * sizeof(WorkItem)));
+    HIP_TRY(hipMemcpy(b.items_dev, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice));
+    la.items = b.items_dev;
+  }
+  if (pl.n_chunks == 0) return RH_OK;  // nothing to record: replays do nothing
+  // kernel attributes first (not stream work), then the launch alone in the graph
+  std::string e2;
+  rh_status as = launch_plan(pl, pl.groups, nullptr, la, err, kAttrsOnly);
+  if (as != RH_OK) return as;
+  HIP_TRY(hipStreamCreateWithFlags(&b.cap, hipStreamNonBlocking));
+  HIP_TRY(hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal));
+  rh_status ls = launch_plan(pl, pl.groups, b.cap, la, e2, kLaunchOnly);
+  hipGraph_t g = nullptr;
+  const hipError_t ce = hipStreamEndCapture(b.cap, &g);
+  b.graph = g;
+  if (ls != RH_OK) {
+    err = e2;
+    return ls;
+  }
+  HIP_TRY(ce);
+  HIP_TRY(hipGraphInstantiate(&b.exec, b.graph, nullptr, nullptr, 0));
+  return RH_OK;
+}
+}  // namespace
+
+rh_status device_batch_create(Context &ctx, int32_t n, Network *const *nets, const int32_t *k,
+                              const double *const *dW, const int64_t *ldw, double *const *dHW,
+                              const int64_t *ldhw, const int32_t *identity_from, rh_precision prec,
+                              DeviceBatch **out, std::string &err) {
+  *out = nullptr;
+  HIP_TRY(hipSetDevice(ctx.device));
+  if (!ctx.dev) {
+    ctx.dev = new DeviceCtx();
+    rh_status qs = query_info(ctx.device, ctx.dev->info, err);
+    if (qs != RH_OK) return qs;
+  }
+  DeviceBatch *b = new DeviceBatch();
+  b->device = ctx.device;
+  std::vector<WorkItem> items;
+  int32_t max_nx = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    Network &net = *nets[i];
+    b->nets.push_back(&net);
+    b->gens.push_back(net.dev_gen);
+    if (k[i] == 0) continue;
+    WorkItem it{};
+    it.nd = net.dev->nd_dev;
+    it.W = dW[i];
+    it.HW = dHW[i];
+    it.ldw = ldw[i];
+    it.ldhw = ldhw[i];
+    it.k = k[i];
+    it.identity_from = identity_from ? identity_from[i] : -1;
+    it.rinfo = nullptr;
+    items.push_back(it);
+    b->dirs += k[i];
+    max_nx = std::max(max_nx, net.n_x);
+  }
+  const int32_t refine = prec == RH_FP32_REFINED ? ctx.refine : -1;
+  rh_status s = batch_build(*b, ctx.dev->info, refine, ctx.refine_tol, items, max_nx, err);
+  if (s != RH_OK) {
+    device_batch_free(b);
+    return s;
+  }
+  *out = b;
+  return RH_OK;
+}
+
+rh_status device_batch_launch(DeviceBatch *b, void *stream, std::string &err) {
+  for (size_t i = 0; i < b->nets.size(); ++i)
+    if (!b->nets[i]->dev || b->nets[i]->dev_gen != b->gens[i] || !b->nets[i]->solved) {
+      err = "batch item " + std::to_string(i) + ": the network was re-uploaded or invalidated since the batch was recorded";
+      return RH_ESTATE;
+    }
+  if (!b->exec) return RH_OK;
+  HIP_TRY(hipSetDevice(b->device));
+  HIP_TRY(hipGraphLaunch(b->exec, (hipStream_t)stream));
+  return RH_OK;
+}
+
+void device_batch_info(const DeviceBatch *b, int32_t *dirs_per_group, int32_t *workgroups, int32_t *directions) {
+  if (dirs_per_group) *dirs_per_group = b->C;
+  if (workgroups) *workgroups = b->groups;
+  if (directions) *directions = b->dirs;
 }
 
 rh_status device_refinement_report(Network &net, int32_t n, std::vector<double> &out, std::string &err) {

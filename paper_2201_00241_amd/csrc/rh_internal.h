@@ -140,6 +140,7 @@ struct ScheduleParams {
 
 struct DeviceNet;  // defined by the device translation unit
 struct DeviceCtx;  // likewise: a context's resources for batched launches
+struct DeviceBatch;  // likewise: a batched launch recorded as a graph
 
 struct Context {
   int32_t device = -1;  // -1: host only
@@ -191,6 +192,7 @@ struct Network {
   Tape tape;
   rh_report report{};
   DeviceNet *dev = nullptr;
+  uint64_t dev_gen = 0;  // device uploads so far (a recorded launch checks it is unchanged)
   int32_t tuned_k[2] = {0, 0};  // full-Hessian block size chosen per precision (0: not yet)
   int32_t refined_cols = -1;    // columns of the last refined product call (-1: none)
 };
@@ -248,6 +250,17 @@ rh_status device_memcpy_h2d(void *dst, const void *src, size_t bytes, std::strin
 rh_status device_memcpy_d2h(void *dst, const void *src, size_t bytes, std::string &err);
 rh_status device_memcpy_2d(void *dst, size_t dpitch, const void *src, size_t spitch,
                            size_t width, size_t rows, int to_device, std::string &err);
+// A batched launch (as device_hvp_batch) recorded once as a HIP graph: the
+// work list is uploaded and the launch scratch allocated at creation, then
+// every replay is one graph launch.  The batch keeps the networks' upload
+// generations and refuses to replay once one has changed.
+rh_status device_batch_create(Context &ctx, int32_t n, Network *const *nets, const int32_t *k,
+                              const double *const *dW, const int64_t *ldw, double *const *dHW,
+                              const int64_t *ldhw, const int32_t *identity_from, rh_precision prec,
+                              DeviceBatch **out, std::string &err);
+rh_status device_batch_launch(DeviceBatch *b, void *stream, std::string &err);
+void device_batch_info(const DeviceBatch *b, int32_t *dirs_per_group, int32_t *workgroups, int32_t *directions);
+void device_batch_free(DeviceBatch *b);
 // Directions one launch needs to give every CU a workgroup at the largest
 // number of directions per workgroup that the network's vectors allow.
 int32_t device_launch_dirs(const Network &net, rh_precision prec);

@@ -104,6 +104,16 @@ _SIGS = {
                                            ctypes.POINTER(ctypes.c_void_p),
                                            ctypes.POINTER(ctypes.c_int64), _i32p,
                                            ctypes.c_int, ctypes.c_void_p]),
+    "rh_batch_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_void_p), _i32p,
+                                       ctypes.POINTER(ctypes.c_void_p),
+                                       ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_void_p),
+                                       ctypes.POINTER(ctypes.c_int64), _i32p, ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_void_p)]),
+    "rh_batch_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "rh_batch_info": (ctypes.c_int, [ctypes.c_void_p, _i32p, _i32p, _i32p]),
+    "rh_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "rh_last_report": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(rh_report)]),
     "rh_network_device_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
                                                ctypes.POINTER(ctypes.c_int64),
@@ -325,6 +335,34 @@ def rh_hvp_batch_device(ctx, nets, ks, dWs, ldws, dHWs, ldhws, identity_from=Non
         ctypes.c_void_p(stream or 0)))
 
 
+def rh_batch_create(ctx, nets, ks, dWs, ldws, dHWs, ldhws, identity_from=None, prec=RH_FP64):
+    n = len(nets)
+    arr_v = ctypes.c_void_p * n
+    arr_l = ctypes.c_int64 * n
+    kk = np.ascontiguousarray(ks, dtype=np.int32)
+    idf = None if identity_from is None else np.ascontiguousarray(identity_from, dtype=np.int32)
+    h = ctypes.c_void_p()
+    _check(load().rh_batch_create(
+        ctx, n, arr_v(*[nn.value if isinstance(nn, ctypes.c_void_p) else nn for nn in nets]),
+        _p(kk, _i32p), arr_v(*[w or None for w in dWs]), arr_l(*ldws), arr_v(*dHWs), arr_l(*ldhws),
+        None if idf is None else _p(idf, _i32p), int(prec), ctypes.byref(h)))
+    return h
+
+
+def rh_batch_launch(batch, stream=None) -> None:
+    _check(load().rh_batch_launch(batch, ctypes.c_void_p(stream or 0)))
+
+
+def rh_batch_info(batch):
+    c, g, d = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load().rh_batch_info(batch, ctypes.byref(c), ctypes.byref(g), ctypes.byref(d)))
+    return {"dirs_per_group": c.value, "workgroups": g.value, "directions": d.value}
+
+
+def rh_batch_destroy(batch) -> None:
+    _check(load().rh_batch_destroy(batch))
+
+
 def rh_context_report(ctx) -> dict:
     r = rh_report()
     _check(load().rh_context_report(ctx, ctypes.byref(r)))
@@ -386,10 +424,41 @@ class Context:
                             [H.data_ptr() for H in HWs], [_ld(H) for H in HWs], None, prec,
                             stream)
 
+    def batch(self, nets, Ws, HWs, prec=RH_FP64):
+        """A recorded batched launch over torch float64 CUDA tensors (k_i, n_p_i)."""
+        return Batch(self, nets, Ws, HWs, prec)
+
     def close(self):
         if self.h:
             rh_context_destroy(self.h)
             self.h = None
+
+
+class Batch:
+    """rh_batch: the batched launch recorded once, replayed by launch()."""
+
+    def __init__(self, ctx, nets, Ws, HWs, prec=RH_FP64):
+        self.keep = (list(nets), list(Ws), list(HWs))  # the bound buffers stay alive
+        self.h = rh_batch_create(ctx.h, [n.h for n in nets], [W.shape[0] for W in Ws],
+                                 [W.data_ptr() for W in Ws], [_ld(W) for W in Ws],
+                                 [H.data_ptr() for H in HWs], [_ld(H) for H in HWs], None, prec)
+
+    def launch(self, stream=None):
+        rh_batch_launch(self.h, stream)
+
+    def info(self):
+        return rh_batch_info(self.h)
+
+    def close(self):
+        if self.h:
+            rh_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Network:

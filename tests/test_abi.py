@@ -153,3 +153,12 @@ def test_refinement_figures_need_a_refined_call(ctx):
     assert resident == 0  # host-only context: nothing on a device
     # V1, V2 (FP64) and the FP32 correction, each padded by the zero and dummy rows
     assert per_dir == 24 * (net.n_x + 65)
+
+
+def test_batch_recording_needs_a_device(ctx):
+    net = rh.Network(ctx, gridgen.config_grid("c0", 0))
+    net.solve()
+    with pytest.raises(rh.RhError) as ei:
+        rh.rh_batch_create(ctx.h, [net.h], [1], [None], [net.n_p], [None], [net.n_p])
+    assert ei.value.status == rh.RH_EDEVICE
+    assert rh.load().rh_batch_destroy(None) == rh.RH_OK
