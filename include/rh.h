@@ -82,6 +82,21 @@ typedef struct {
   const double *Pg, *Vg, *c2, *c1, *c0;
 } rh_network_desc;
 
+/* Launch shape of a network's products in one precision, chosen by
+ * rh_autotune: the full Hessian's launch size (k directions per launch, the
+ * block of Sec. 5.3), the directions one workgroup owns, and the two
+ * parameters of the triangular-sweep schedule (the largest dense block of
+ * merged narrow levels, and whether elimination-tree subtrees are walked by
+ * single waves).  k = 0: not chosen yet (library defaults). */
+typedef struct {
+  int32_t k;
+  int32_t dirs_per_group;  /* 1, 2 or 4 */
+  int32_t block_rows;      /* 0 (no merged blocks) .. 64 */
+  int32_t wave_steps;      /* 0 or 1 */
+  double ms_per_hessian;   /* the tuner's estimate for the full Hessian */
+  int32_t source;          /* 0 defaults, 1 measured, 2 read from the cache */
+} rh_tile;
+
 /* Figures of the last solve and the last Hessian call on a network. */
 typedef struct {
   int32_t n_x, n_p;
@@ -99,6 +114,7 @@ typedef struct {
   double phase_us[7];           /* timing level 2: mean time per workgroup of SpMul,
                                    L sweep, U sweep, tensor projection, U^T sweep,
                                    L^T sweep, SpMulAdd in the last timed launch */
+  rh_tile tile[2];              /* launch shapes chosen so far, FP64 and refined */
 } rh_report;
 
 /* Create a context on HIP device `device`; device = -1 gives a host-only
@@ -182,13 +198,35 @@ rh_status rh_hvp_device(rh_network *net, int32_t k, const void *dW, int64_t ldw,
 #define RH_NOALLOC_SCRATCH_BYTES (128ll << 20)
 rh_status rh_hvp_device_noalloc(rh_network *net, int32_t k, const void *dW, int64_t ldw, void *dHW,
                                 int64_t ldhw, rh_precision prec, void *hip_stream);
+/* Choose the launch shape (rh_tile) of the network's products in precision
+ * `prec` and apply it.  Unless flags has RH_TUNE_MEASURE, a shape cached for
+ * the same grid topology (which fixes the LU pattern and the sweep
+ * schedules), device and precision is taken from the cache file; otherwise
+ * every candidate is timed on the device: sweep schedules with merged blocks
+ * of at most 16, 32 or 64 rows and with or without wave steps (the
+ * network's sweeps are re-planned and uploaded for each, so device data of
+ * the network moves and recorded batches of it must be re-created), every
+ * directions-per-workgroup count whose vectors fit, and launch sizes of 128,
+ * 256, 512 and 1,024 directions (and n_p when smaller); one launch of
+ * identity columns is timed per candidate (the best of two after one
+ * untimed) and the full Hessian estimated as that time x the launches it
+ * needs.  The fastest shape is applied, reported in rh_report.tile, and
+ * (unless RH_TUNE_NO_CACHE) appended to the cache file: $RH_TUNE_CACHE, else
+ * $HOME/.cache/librh/tiles.txt (a text file, one shape per line).  `out` may
+ * be NULL.  The network must be solved; synchronises the device. */
+#define RH_TUNE_MEASURE 1
+#define RH_TUNE_NO_CACHE 2
+rh_status rh_autotune(rh_network *net, rh_precision prec, int32_t flags, rh_tile *out);
+/* The network's current shape in precision prec (k = 0: none chosen). */
+rh_status rh_get_tile(const rh_network *net, rh_precision prec, rh_tile *out);
+
 /* The dense reduced Hessian H (n_p x n_p, column-major, ldh >= n_p), computed
- * in ceil(n_p / k_block) blocks of identity columns (Sec. 5.3);
- * k_block = 0 lets the library choose: on the first such call for the
- * network and precision it times one block of each candidate size (64 to
- * 2048 in powers of two below n_p, and n_p itself when at most 2048) and
- * keeps the size with the smallest estimated total; rh_report.last_k then
- * gives the block size used.  Host output, synchronous. */
+ * in ceil(n_p / k_block) blocks of identity columns (Sec. 5.3), consecutive
+ * blocks sharing a launch when one block would leave CUs idle;
+ * k_block = 0 lets the library choose: the network's tuned shape
+ * (rh_autotune, run on the first such call, from the cache when it holds
+ * one), whose k is then the number of directions per launch;
+ * rh_report.last_k gives the size used.  Host output, synchronous. */
 rh_status rh_reduced_hessian(rh_network *net, double *H, int64_t ldh, int32_t k_block,
                              rh_precision prec);
 /* As rh_reduced_hessian into a device buffer, enqueued on `hip_stream` (the

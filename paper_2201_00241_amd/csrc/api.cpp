@@ -299,36 +299,27 @@ rh_status rh_hvp_device_noalloc(rh_network *net, int32_t k, const void *dW, int6
   GUARD_END
 }
 
-// Block size of the full Hessian when the caller leaves it to the library:
-// one block of each candidate size (identity columns 0 .. k - 1, written
-// into H and overwritten by the real run) is timed by the wall clock around
-// a synchronised launch, after one untimed launch, and the size with the
-// smallest estimated total (time per block x blocks) is kept for the network
-// and precision.  Candidates: 64 .. 2048 in powers of two up to n_p, and n_p
-// itself when smaller than 2048 (one launch).
-static rh_status tune_block(Network &n, double *H, int64_t ldh, rh_precision prec, void *stream,
-                            int32_t &k_out, std::string &err) {
-  const int32_t n_p = n.n_p;
-  std::vector<int32_t> cand;
-  for (int32_t k = 64; k <= 2048 && k < n_p; k *= 2) cand.push_back(k);
-  if (n_p <= 2048) cand.push_back(n_p);
-  rh_status s = device_hvp(n, cand[0], nullptr, 0, H, ldh, 0, prec, stream, err);
-  if (s == RH_OK) s = device_sync(stream, err);
-  double best = 0.0;
-  k_out = cand.back();
-  for (int32_t k : cand) {
-    if (s != RH_OK) break;
-    const auto t0 = std::chrono::steady_clock::now();
-    s = device_hvp(n, k, nullptr, 0, H, ldh, 0, prec, stream, err);
-    if (s == RH_OK) s = device_sync(stream, err);
-    const double t = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    const double total = t * ((n_p + k - 1) / k);
-    if (k == cand[0] || total < best) {
-      best = total;
-      k_out = k;
-    }
-  }
-  return s;
+rh_status rh_autotune(rh_network *net, rh_precision prec, int32_t flags, rh_tile *out) {
+  GUARD_BEGIN
+  rh_status s = need_solved(net);
+  if (s != RH_OK) return s;
+  if ((s = need_device(net)) != RH_OK) return s;
+  if (prec != RH_FP64 && prec != RH_FP32_REFINED) return fail(RH_EINVAL, "unknown precision");
+  if (flags & ~(RH_TUNE_MEASURE | RH_TUNE_NO_CACHE)) return fail(RH_EINVAL, "unknown tuner flags");
+  std::string err;
+  rh_tile t{};
+  s = autotune(net->n, prec, flags, t, err);
+  if (s != RH_OK) return fail(s, err);
+  if (out) *out = t;
+  return RH_OK;
+  GUARD_END
+}
+
+rh_status rh_get_tile(const rh_network *net, rh_precision prec, rh_tile *out) {
+  if (!net || !out) return fail(RH_EINVAL, "null argument");
+  if (prec != RH_FP64 && prec != RH_FP32_REFINED) return fail(RH_EINVAL, "unknown precision");
+  *out = net->n.tile[prec == RH_FP32_REFINED ? 1 : 0];
+  return RH_OK;
 }
 
 rh_status rh_reduced_hessian_device(rh_network *net, void *dH, int64_t ldh, int32_t k_block,
@@ -343,17 +334,23 @@ rh_status rh_reduced_hessian_device(rh_network *net, void *dH, int64_t ldh, int3
   std::string err;
   double *H = static_cast<double *>(dH);
   int32_t k = k_block > n_p ? n_p : k_block;
+  int32_t group = 1;
   if (k_block == 0) {
-    int32_t &tk = net->n.tuned_k[prec == RH_FP64 ? 0 : 1];
-    if (tk == 0 && (s = tune_block(net->n, H, ldh, prec, hip_stream, tk, err)) != RH_OK) return fail(s, err);
-    k = tk;
+    // the tuned shape: its k is the launch size
+    rh_tile &t = net->n.tile[prec == RH_FP64 ? 0 : 1];
+    if (t.k == 0) {
+      rh_tile tt{};
+      if ((s = autotune(net->n, prec, 0, tt, err)) != RH_OK) return fail(s, err);
+    }
+    k = std::min(t.k, n_p);
+  } else {
+    // consecutive blocks share a launch when one block leaves CUs idle at
+    // the directions per workgroup the network allows (a direction's product
+    // does not depend on the launch it runs in)
+    const int32_t want = device_launch_dirs(net->n, prec);
+    group = std::max(1, std::min((want + k - 1) / k, (n_p + k - 1) / k));
   }
   net->n.report.last_k = k;
-  // consecutive blocks share a launch when one block leaves CUs idle at the
-  // directions per workgroup the network allows (a direction's product does
-  // not depend on the launch it runs in)
-  const int32_t want = device_launch_dirs(net->n, prec);
-  const int32_t group = std::max(1, std::min((want + k - 1) / k, (n_p + k - 1) / k));
   for (int32_t j0 = 0; j0 < n_p; j0 += group * k) {
     const int32_t kb = std::min(group * k, n_p - j0);
     s = device_hvp(net->n, kb, nullptr, 0, H + (int64_t)j0 * ldh, ldh, j0, prec, hip_stream, err);
@@ -432,6 +429,8 @@ rh_status rh_last_report(const rh_network *net, rh_report *out) {
     if (s != RH_OK) return fail(s, err);
   }
   *out = net->n.report;
+  out->tile[0] = net->n.tile[0];
+  out->tile[1] = net->n.tile[1];
   return RH_OK;
 }
 

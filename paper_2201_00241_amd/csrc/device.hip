@@ -1562,12 +1562,14 @@ int32_t lds_max_c(int64_t n_x, size_t lds_max, bool lds, size_t elem) {
   return c;
 }
 
-int32_t choose_c(int64_t k, int32_t cus, int64_t n_x, size_t lds_max, bool lds, size_t elem) {
+// force: a count chosen by the tuner (0: none), taken when it fits.
+int32_t choose_c(int64_t k, int32_t cus, int64_t n_x, size_t lds_max, bool lds, size_t elem, int32_t force = 0) {
   if (const char *e = std::getenv("RH_DIRS_PER_GROUP")) {
     const int v = std::atoi(e);
     if ((v == 1 || v == 2 || v == 4) && (!lds || (size_t)n_x * v * elem <= lds_max))
       return v;
   }
+  if ((force == 1 || force == 2 || force == 4) && (!lds || (size_t)n_x * force * elem <= lds_max)) return force;
   int32_t c = lds_max_c(n_x, lds_max, lds, elem);
   while (c > 1 && k < (int64_t)c * cus) c >>= 1;
   return c;
@@ -1594,7 +1596,7 @@ struct LaunchPlan {
 };
 
 rh_status plan_launch(const DeviceInfo &info, int32_t refine, std::vector<WorkItem> &items, int32_t max_nx,
-                      LaunchPlan &pl, std::string &err) {
+                      LaunchPlan &pl, std::string &err, int32_t force_c = 0) {
   int64_t total_k = 0;
   for (const WorkItem &it : items) total_k += it.k;
   pl = LaunchPlan();
@@ -1603,7 +1605,7 @@ rh_status plan_launch(const DeviceInfo &info, int32_t refine, std::vector<WorkIt
   const size_t elem = pl.refined ? sizeof(float) : sizeof(double);  // LDS vector element
   pl.pad_rows = max_nx + kWavePadRows;                               // padded working vector
   pl.lds = (size_t)pl.pad_rows * elem <= info.lds_max && !std::getenv("RH_NO_LDS");
-  const int32_t C = pl.C = choose_c(total_k, info.cus, pl.pad_rows, info.lds_max, pl.lds, elem);
+  const int32_t C = pl.C = choose_c(total_k, info.cus, pl.pad_rows, info.lds_max, pl.lds, elem, force_c);
   for (WorkItem &it : items) {
     it.chunk0 = (int32_t)pl.n_chunks;
     pl.n_chunks += (it.k + C - 1) / C;
@@ -1645,9 +1647,9 @@ rh_status launch_plan(const LaunchPlan &pl, int32_t groups, hipStream_t s, const
 
 rh_status run_items(const DeviceInfo &info, Runner &r, int32_t timing, int32_t refine, double refine_tol,
                     std::vector<WorkItem> &items, int32_t max_nx, hipStream_t s, std::string &err,
-                    const FixedScratch *fixed = nullptr) {
+                    const FixedScratch *fixed = nullptr, int32_t force_c = 0) {
   LaunchPlan pl;
-  rh_status ps = plan_launch(info, refine, items, max_nx, pl, err);
+  rh_status ps = plan_launch(info, refine, items, max_nx, pl, err, force_c);
   if (ps != RH_OK || pl.n_chunks == 0) return ps;
   const int32_t C = pl.C;
   const int64_t n_chunks = pl.n_chunks, stride = pl.stride;
@@ -2071,6 +2073,8 @@ rh_status device_upload(Network &net, std::string &err) {
   prm.n_waves = kWaves;
   if (const char *e = std::getenv("RH_BLOCK_ROWS")) prm.bmax = std::min(kBlockRows, std::max(0, std::atoi(e)));
   if (const char *e = std::getenv("RH_WAVE_STEPS")) prm.wave_mode = std::atoi(e) != 0;
+  if (net.sched_bmax >= 0) prm.bmax = std::min(kBlockRows, net.sched_bmax);  // the tuner's choice
+  if (net.sched_wave >= 0) prm.wave_mode = net.sched_wave != 0;
   const int32_t n = net.n_x;
   const std::vector<int32_t> parent = etree_parent(lu);
   if (upload_sweep(dn, sl, n, parent, true, prm, nd.L, err) != RH_OK ||
@@ -2277,8 +2281,9 @@ rh_status device_hvp(Network &net, int32_t k, const double *dW, int64_t ldw, dou
     }
     it.rinfo = dn->rinfo + 4 * (int64_t)(identity_from >= 0 ? identity_from : 0);
   }
+  const rh_tile &t = net.tile[prec == RH_FP32_REFINED ? 1 : 0];
   rh_status s = run_items(dn->info, dn->run, net.ctx->timing, refine, net.ctx->refine_tol, items, net.n_x,
-                          (hipStream_t)stream, err);
+                          (hipStream_t)stream, err, nullptr, t.k > 0 ? t.dirs_per_group : 0);
   net.report.dirs_per_group = dn->run.last_c;
   return s;
 }
@@ -2313,8 +2318,9 @@ rh_status device_hvp_noalloc(Network &net, int32_t k, const double *dW, int64_t 
   it.rinfo = nullptr;  // no per-column refinement figures
   const FixedScratch fx{static_cast<double *>(fp), (int64_t)RH_NOALLOC_SCRATCH_BYTES};
   const int32_t refine = prec == RH_FP32_REFINED ? net.ctx->refine : -1;
+  const rh_tile &t = net.tile[prec == RH_FP32_REFINED ? 1 : 0];
   return run_items(dn->info, dn->run, 0, refine, net.ctx->refine_tol, items, net.n_x, (hipStream_t)stream, err,
-                   &fx);
+                   &fx, t.k > 0 ? t.dirs_per_group : 0);
 }
 
 rh_status device_hvp_batch(Context &ctx, int32_t n, Network *const *nets, const int32_t *k,
@@ -2350,9 +2356,29 @@ rh_status device_hvp_batch(Context &ctx, int32_t n, Network *const *nets, const 
                    (hipStream_t)stream, err);
 }
 
+int32_t device_max_c(const Network &net, rh_precision prec) {
+  const DeviceNet *dn = net.dev;
+  if (!dn) return 1;
+  const size_t elem = prec == RH_FP32_REFINED ? sizeof(float) : sizeof(double);
+  const int64_t pad_rows = (int64_t)net.n_x + kWavePadRows;
+  const bool lds = (size_t)pad_rows * elem <= dn->info.lds_max && !std::getenv("RH_NO_LDS");
+  return lds_max_c(pad_rows, dn->info.lds_max, lds, elem);
+}
+
+std::string device_key(int32_t device) {
+  hipDeviceProp_t p{};
+  if (hipGetDeviceProperties(&p, device) != hipSuccess) return "unknown";
+  std::string k = std::string(p.gcnArchName) + "/" + std::to_string(p.multiProcessorCount) + "cu";
+  for (char &c : k)
+    if (c == ' ' || c == '|' || c == '\n') c = '_';
+  return k;
+}
+
 int32_t device_launch_dirs(const Network &net, rh_precision prec) {
   const DeviceNet *dn = net.dev;
   if (!dn) return 1;
+  const rh_tile &t = net.tile[prec == RH_FP32_REFINED ? 1 : 0];
+  if (t.k > 0) return t.dirs_per_group * dn->info.cus;  // the tuner's count
   const bool refined = prec == RH_FP32_REFINED;
   const size_t elem = refined ? sizeof(float) : sizeof(double);
   const int64_t pad_rows = (int64_t)net.n_x + kWavePadRows;

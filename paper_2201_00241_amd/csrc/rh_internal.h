@@ -193,7 +193,11 @@ struct Network {
   rh_report report{};
   DeviceNet *dev = nullptr;
   uint64_t dev_gen = 0;  // device uploads so far (a recorded launch checks it is unchanged)
-  int32_t tuned_k[2] = {0, 0};  // full-Hessian block size chosen per precision (0: not yet)
+  // launch shape per precision (0 FP64, 1 refined) chosen by the tuner
+  // (tune.cpp); k == 0: not chosen, the library's defaults apply
+  rh_tile tile[2] = {};
+  // schedule parameters of the uploaded sweeps (-1: the defaults)
+  int32_t sched_bmax = -1, sched_wave = -1;
   int32_t refined_cols = -1;    // columns of the last refined product call (-1: none)
 };
 
@@ -261,6 +265,12 @@ rh_status device_batch_create(Context &ctx, int32_t n, Network *const *nets, con
 rh_status device_batch_launch(DeviceBatch *b, void *stream, std::string &err);
 void device_batch_info(const DeviceBatch *b, int32_t *dirs_per_group, int32_t *workgroups, int32_t *directions);
 void device_batch_free(DeviceBatch *b);
+// The most directions per workgroup the network's vectors allow (LDS), and
+// a name of the device for the tuner's cache.
+int32_t device_max_c(const Network &net, rh_precision prec);
+std::string device_key(int32_t device);
+// ---- launch-shape tuner (tune.cpp): rh_autotune on a solved network
+rh_status autotune(Network &net, rh_precision prec, int32_t flags, rh_tile &out, std::string &err);
 // Directions one launch needs to give every CU a workgroup at the largest
 // number of directions per workgroup that the network's vectors allow.
 int32_t device_launch_dirs(const Network &net, rh_precision prec);

@@ -35,6 +35,20 @@ class rh_network_desc(ctypes.Structure):
     ]
 
 
+class rh_tile(ctypes.Structure):
+    _fields_ = [
+        ("k", ctypes.c_int32), ("dirs_per_group", ctypes.c_int32),
+        ("block_rows", ctypes.c_int32), ("wave_steps", ctypes.c_int32),
+        ("ms_per_hessian", ctypes.c_double), ("source", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+RH_TUNE_MEASURE, RH_TUNE_NO_CACHE = 1, 2
+
+
 class rh_report(ctypes.Structure):
     _fields_ = [
         ("n_x", ctypes.c_int32), ("n_p", ctypes.c_int32),
@@ -47,11 +61,13 @@ class rh_report(ctypes.Structure):
         ("dirs_per_group", ctypes.c_int32),
         ("last_kernel_ms", ctypes.c_double),
         ("phase_us", ctypes.c_double * 7),
+        ("tile", rh_tile * 2),
     ]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
         d["phase_us"] = list(self.phase_us)
+        d["tile"] = [t.as_dict() for t in self.tile]
         return d
 
 
@@ -114,6 +130,9 @@ _SIGS = {
     "rh_batch_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "rh_batch_info": (ctypes.c_int, [ctypes.c_void_p, _i32p, _i32p, _i32p]),
     "rh_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "rh_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int32,
+                                   ctypes.POINTER(rh_tile)]),
+    "rh_get_tile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(rh_tile)]),
     "rh_last_report": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(rh_report)]),
     "rh_network_device_bytes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int,
                                                ctypes.POINTER(ctypes.c_int64),
@@ -363,6 +382,18 @@ def rh_batch_destroy(batch) -> None:
     _check(load().rh_batch_destroy(batch))
 
 
+def rh_autotune(net, prec=RH_FP64, flags=0) -> dict:
+    t = rh_tile()
+    _check(load().rh_autotune(net, int(prec), int(flags), ctypes.byref(t)))
+    return t.as_dict()
+
+
+def rh_get_tile(net, prec=RH_FP64) -> dict:
+    t = rh_tile()
+    _check(load().rh_get_tile(net, int(prec), ctypes.byref(t)))
+    return t.as_dict()
+
+
 def rh_context_report(ctx) -> dict:
     r = rh_report()
     _check(load().rh_context_report(ctx, ctypes.byref(r)))
@@ -499,6 +530,8 @@ class Network:
     report = lambda self: rh_last_report(self.h)  # noqa: E731
     refinement_report = lambda self, n: rh_refinement_report(self.h, n)  # noqa: E731
     device_bytes = lambda self, prec=RH_FP64: rh_network_device_bytes(self.h, prec)  # noqa: E731
+    autotune = lambda self, prec=RH_FP64, flags=0: rh_autotune(self.h, prec, flags)  # noqa: E731
+    tile = lambda self, prec=RH_FP64: rh_get_tile(self.h, prec)  # noqa: E731
 
     def hvp_device(self, W, HW, stream=None, prec=RH_FP64):
         """W, HW: torch float64 CUDA tensors of shape (k, n_p) (row j = direction j)."""

@@ -79,20 +79,26 @@ def test_1k_full_hessian_ragged_blocks(c1):
     assert np.max(np.abs(H - H.T)) / np.max(np.abs(H)) < 1e-11
 
 
-def test_1k_full_hessian_tuned_block(c1):
-    """k_block = 0: the library times its candidate block sizes once and keeps
-    one; the result is bitwise that of an explicit block size (a direction's
-    arithmetic does not depend on k) and matches the oracle."""
-    g, net, s = c1
-    _say(f"1k: full H with the tuned block size (n_p={net.n_p})")
+def test_1k_full_hessian_tuned_block(ctx, rhmod, tmp_path, monkeypatch):
+    """k_block = 0: the library tunes the launch shape once (here measured:
+    the cache file is empty) and keeps it; the result is bitwise that of an
+    explicit block size with the same shape (a direction's arithmetic does not
+    depend on k) and matches the oracle."""
+    monkeypatch.setenv("RH_TUNE_CACHE", str(tmp_path / "tiles.txt"))
+    g = gridgen.config_grid("c1", 0)
+    net = rhmod.Network(ctx, g)
+    net.solve()
+    _say(f"1k: full H with the tuned launch shape (n_p={net.n_p})")
     H0 = net.reduced_hessian(k_block=0)
     k = net.report()["last_k"]
-    assert k in (64, 128, net.n_p), k
-    H1 = net.reduced_hessian(k_block=0)  # tuned size kept
+    t = net.tile()
+    assert k == t["k"] and k in (128, net.n_p), k
+    H1 = net.reduced_hessian(k_block=0)  # tuned shape kept
     assert net.report()["last_k"] == k
     H64 = net.reduced_hessian(k_block=64)
     assert np.array_equal(H0, H64) and np.array_equal(H1, H64)
-    assert _relerr(H0, s.reduced_hessian(64)) <= TOL
+    assert _relerr(H0, solve(g).reduced_hessian(64)) <= TOL
+    net.close()
 
 
 def test_1k_random_directions(c1):
