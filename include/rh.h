@@ -166,6 +166,23 @@ rh_status rh_set_initial_state(rh_network *net, const double *x0);
  * be NULL.  Returns RH_ENOCONV or RH_ESINGULAR on failure. */
 rh_status rh_solve_powerflow(rh_network *net, double tol, int32_t max_iter, int32_t *iters,
                              double *resid_inf);
+/* As rh_solve_powerflow, with Newton on the device (Sec. 3.2) and the
+ * numeric LU factorisation of G_x repeated on the device on the fixed pattern
+ * and ordering analysed at rh_network_create (Sec. 5.2): per step the GPU
+ * evaluates the mismatch and G_x on its pattern, refactorises and solves for
+ * the step, and the host reads back only max |g|.  At convergence the state
+ * and the factors are copied to the host, which forms the adjoint and the
+ * branch coefficients from them without factorising, and the product path is
+ * uploaded as after rh_solve_powerflow.  Needs a device context; rows of the
+ * LU pattern wider than about 1,200 entries give RH_EINVAL.  Same statuses
+ * as rh_solve_powerflow. */
+rh_status rh_solve_powerflow_device(rh_network *net, double tol, int32_t max_iter, int32_t *iters,
+                                    double *resid_inf);
+/* Values of the LU factors of the solved operating point, P G_x P^T = L U
+ * (Sec. 5.2), in the fixed pattern's row order: l receives nnz_l values (row
+ * by row, the strictly lower entries in ascending column order), u nnz_u
+ * values (row by row, diagonal first).  Either may be NULL. */
+rh_status rh_get_factors(const rh_network *net, double *l, double *u);
 /* Converged state x (n_x), objective F(p) = f(x(p), p), reduced gradient (n_p). */
 rh_status rh_get_state(const rh_network *net, double *x);
 rh_status rh_objective(const rh_network *net, double *F);

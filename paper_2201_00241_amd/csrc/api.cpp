@@ -140,6 +140,7 @@ rh_status rh_network_create(rh_context *ctx, const rh_network_desc *desc, rh_net
 
 rh_status rh_network_destroy(rh_network *net) {
   if (!net) return RH_OK;
+  device_newton_free(net->n);
   device_free(net->n);
   delete net;
   return RH_OK;
@@ -230,6 +231,46 @@ rh_status rh_solve_powerflow(rh_network *net, double tol, int32_t max_iter, int3
   }
   return RH_OK;
   GUARD_END
+}
+
+rh_status rh_solve_powerflow_device(rh_network *net, double tol, int32_t max_iter, int32_t *iters,
+                                    double *resid_inf) {
+  GUARD_BEGIN
+  if (!net) return fail(RH_EINVAL, "null network");
+  if (net->n.ctx->device < 0) return fail(RH_EDEVICE, "host-only context");
+  Network &n = net->n;
+  n.solved = false;
+  if (n.islanded) return fail(RH_ESINGULAR, "some bus is not connected to the reference bus: G_x is singular");
+  if (!(tol > 0.0) || max_iter < 0) return fail(RH_EINVAL, "tol must be > 0 and max_iter >= 0");
+  std::string err;
+  NewtonResult res;
+  rh_status s = device_newton(n, tol, max_iter, res, err);
+  if (iters) *iters = res.iters;
+  if (resid_inf) *resid_inf = res.resid;
+  n.newton_iters = res.iters;
+  n.newton_resid = res.resid;
+  if (s != RH_OK) return fail(s, err);
+  if ((s = network_accept(n, res.x, res.iters, res.resid, true, err)) != RH_OK) return fail(s, err);
+  if ((s = device_upload(n, err)) != RH_OK) {
+    n.solved = false;
+    return fail(s, err);
+  }
+  return RH_OK;
+  GUARD_END
+}
+
+rh_status rh_get_factors(const rh_network *net, double *l, double *u) {
+  if (!net) return fail(RH_EINVAL, "null network");
+  if (!net->n.solved) return fail(RH_ESTATE, "no converged power flow for the current parameters");
+  const LuPlan &lu = net->n.lu;
+  int64_t ql = 0, qu = 0;
+  for (int32_t i = 0; i < lu.n; ++i) {
+    if (l)
+      for (double v : lu.lval[i]) l[ql++] = v;
+    if (u)
+      for (double v : lu.uval[i]) u[qu++] = v;
+  }
+  return RH_OK;
 }
 
 rh_status rh_get_state(const rh_network *net, double *x) {

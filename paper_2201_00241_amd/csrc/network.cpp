@@ -577,12 +577,20 @@ rh_status network_solve(Network &net, double tol, int32_t max_iter, std::string 
     lu_solve(net.lu, g);
     for (int32_t i = 0; i < net.n_x; ++i) x[i] -= g[i];
   }
+  return network_accept(net, x, it, r, false, err);
+}
+
+rh_status network_accept(Network &net, const std::vector<double> &x, int32_t it, double r, bool factors_given,
+                         std::string &err) {
+  net.solved = false;
+  std::vector<double> th, v;
+  unpack_state(net, x, net.p, th, v);
   net.x = x;
   net.newton_iters = it;
   net.newton_resid = r;
   // Jacobians and factors at the accepted state
   assemble_jacobians(net, th, v, net.gx_slot, net.gp_slot);
-  if (!lu_factor(net.lu, net.gx, err)) return RH_ESINGULAR;
+  if (!factors_given && !lu_factor(net.lu, net.gx, err)) return RH_ESINGULAR;
   // first-order adjoint: G_x^T lambda = -grad_x f^T
   std::vector<double> fx, fp;
   cost_gradient(net, th, v, fx, fp);

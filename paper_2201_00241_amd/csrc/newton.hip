@@ -1,0 +1,498 @@
+// Device-resident Newton-Raphson on g(x, p) = 0 (Sec. 3.2) with a
+// fixed-pattern numeric LU refactorisation of G_x on the GPU (Sec. 5.2: the
+// pattern and the ordering are analysed once on the host; only the numeric
+// factorisation is repeated for every operating point).
+//
+// Per Newton step, on the device:
+//   1. bus voltages from x and p; per branch the four end flows of eq.
+//      (powerflow) and their 16 partial derivatives w.r.t. (theta_f, theta_t,
+//      v_f, v_t);
+//   2. the mismatch g (per bus, its incident branches summed in branch
+//      order) and max |g|, the one number the host reads per step;
+//   3. the values of G_x on its fixed pattern (per entry, its branch
+//      partials summed in branch order: no atomics);
+//   4. P G_x P^T = L U, row by row with static diagonal pivots, the rows of
+//      one elimination level at a time (one wave per row, the row's values
+//      in LDS);
+//   5. the Newton step from the two triangular solves, and x -= step.
+// After convergence the state and the factors are copied to the host, which
+// forms the first-order adjoint and the branch coefficients from them (it
+// does not factorise) and uploads the product path as after a host solve.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "rh_internal.h"
+
+namespace rh {
+
+namespace {
+
+#define HIP_TRY(expr)                                                          \
+  do {                                                                         \
+    hipError_t e_ = (expr);                                                    \
+    if (e_ != hipSuccess) {                                                    \
+      err = std::string(#expr) + ": " + hipGetErrorString(e_);                 \
+      return RH_EDEVICE;                                                       \
+    }                                                                          \
+  } while (0)
+
+constexpr int kNtThreads = 1024;
+constexpr int kNtWaves = kNtThreads / 64;
+
+// Device arrays of one network (pattern and topology: built once).
+struct NtArrays {
+  int32_t n_bus, n_br, n_x, n_p, nnz_gx, nnz_lu, maxpat;
+  int32_t n_lev_l, n_lev_u;
+  // branches
+  const int32_t *br_f, *br_t;
+  const double *gs, *bs, *bsh;
+  // buses: state maps and incidences (branch order)
+  const int32_t *th_x, *v_x, *v_p, *pg_p;
+  const int32_t *inc_ptr, *inc_code;  // code = 4 * branch + 2 * end (end 0 from, 1 to)
+  // G_x: contributions of branch partials per pattern entry, in branch order
+  const int32_t *gxc_ptr, *gxc_src;  // src = 16 * branch + 4 * flow + variable
+  // LU (permuted numbering): row i holds its L part (|lrow|) then its U part
+  // (diagonal first); lucol = column of every position
+  const int32_t *row_ptr, *nl, *lucol, *perm;
+  const int32_t *a_ptr, *a_src;  // G_x entries of permuted row i: G_x value index
+  const uint16_t *a_dst;         // ... and position in the row
+  const int64_t *upd_ptr;        // per row: first target of its updates
+  const uint16_t *tgt;           // targets (position in the row) of every update, row by row
+  const int32_t *lev_ptr_l, *lev_rows_l, *lev_ptr_u, *lev_rows_u;
+};
+
+// Per-solve device vectors.
+struct NtVectors {
+  double *x, *p, *Pd, *Qd, *th, *v, *flows, *dG, *g, *gx, *lu, *y;
+  double *stat;  // [0] max |g|, [1] non-finite flag, [2] singular pivot row + 1
+};
+
+struct NtArgs {
+  NtArrays a;
+  NtVectors w;
+};
+
+// ---- kernels: states, flows, residual, Jacobian values -----------------
+
+__global__ void nt_state(const NtArgs A) {
+  const int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= A.a.n_bus) return;
+  const int32_t tx = A.a.th_x[b], vx = A.a.v_x[b], vp = A.a.v_p[b];
+  A.w.th[b] = tx >= 0 ? A.w.x[tx] : 0.0;
+  A.w.v[b] = vx >= 0 ? A.w.x[vx] : (vp >= 0 ? A.w.p[vp] : 0.0);
+}
+
+// End flows alpha v_e^2 + v_f v_t h(a) of one branch and their partials.
+__global__ void nt_flows(const NtArgs A, int want_grad) {
+  const int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= A.a.n_br) return;
+  const int32_t f = A.a.br_f[b], t = A.a.br_t[b];
+  const double gs = A.a.gs[b], bs = A.a.bs[b], bh = A.a.bsh[b];
+  const double a = A.w.th[f] - A.w.th[t];
+  double s, c;
+  sincos(a, &s, &c);
+  const double alpha[4] = {gs, -(bs + bh), gs, -(bs + bh)};
+  const double h[4] = {-(gs * c + bs * s), -(gs * s - bs * c), -(gs * c - bs * s), gs * s + bs * c};
+  const double hp[4] = {gs * s - bs * c, -(gs * c + bs * s), gs * s + bs * c, gs * c - bs * s};
+  const double vf = A.w.v[f], vt = A.w.v[t], K = vf * vt;
+  A.w.flows[4 * b + 0] = alpha[0] * vf * vf + K * h[0];
+  A.w.flows[4 * b + 1] = alpha[1] * vf * vf + K * h[1];
+  A.w.flows[4 * b + 2] = alpha[2] * vt * vt + K * h[2];
+  A.w.flows[4 * b + 3] = alpha[3] * vt * vt + K * h[3];
+  if (!want_grad) return;
+  for (int k = 0; k < 4; ++k) {
+    double *d = A.w.dG + 16 * (int64_t)b + 4 * k;
+    d[0] = K * hp[k];
+    d[1] = -K * hp[k];
+    d[2] = vt * h[k] + (k < 2 ? 2.0 * alpha[k] * vf : 0.0);
+    d[3] = vf * h[k] + (k >= 2 ? 2.0 * alpha[k] * vt : 0.0);
+  }
+}
+
+// g at the x rows of every bus: P (theta rows) and Q (v rows) mismatch.
+__global__ void nt_residual(const NtArgs A) {
+  const int32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= A.a.n_bus) return;
+  double P = 0.0, Q = 0.0;
+  for (int32_t e = A.a.inc_ptr[b]; e < A.a.inc_ptr[b + 1]; ++e) {
+    const int32_t code = A.a.inc_code[e];
+    P += A.w.flows[code];
+    Q += A.w.flows[code + 1];
+  }
+  const int32_t tx = A.a.th_x[b], vx = A.a.v_x[b], pg = A.a.pg_p[b];
+  if (tx >= 0) {
+    double r = P + A.w.Pd[b];
+    if (pg >= 0) r -= A.w.p[pg];
+    A.w.g[tx] = r;
+  }
+  if (vx >= 0) A.w.g[vx] = Q + A.w.Qd[b];
+}
+
+// max |g| and a non-finite flag (one workgroup); clears the pivot status.
+__global__ __launch_bounds__(kNtThreads) void nt_norm(const NtArgs A) {
+  __shared__ double s_max[kNtWaves];
+  __shared__ int s_bad[kNtWaves];
+  double m = 0.0;
+  int bad = 0;
+  for (int32_t i = threadIdx.x; i < A.a.n_x; i += kNtThreads) {
+    const double gi = A.w.g[i];
+    if (!isfinite(gi)) bad = 1;
+    m = fmax(m, fabs(gi));
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    m = fmax(m, __shfl_xor(m, off));
+    bad |= __shfl_xor(bad, off);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s_max[threadIdx.x >> 6] = m;
+    s_bad[threadIdx.x >> 6] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double mm = 0.0;
+    int bb = 0;
+    for (int w = 0; w < kNtWaves; ++w) {
+      mm = fmax(mm, s_max[w]);
+      bb |= s_bad[w];
+    }
+    A.w.stat[0] = mm;
+    A.w.stat[1] = bb;
+    A.w.stat[2] = 0.0;
+  }
+}
+
+// Values of G_x: every pattern entry sums its branch partials in branch order.
+__global__ void nt_gx(const NtArgs A) {
+  const int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= A.a.nnz_gx) return;
+  double acc = 0.0;
+  for (int32_t e = A.a.gxc_ptr[s]; e < A.a.gxc_ptr[s + 1]; ++e) acc += A.w.dG[A.a.gxc_src[e]];
+  A.w.gx[s] = acc;
+}
+
+// ---- refactorisation ----------------------------------------------------
+
+// P G_x P^T = L U, one elimination level of rows at a time (rows of a level
+// depend only on rows of earlier levels), one wave per row.  A row is
+// scattered into its wave's LDS buffer, then for every entry k of its L part
+// in ascending order: l = w_k / u_kk, and the U part of row k (final: an
+// earlier level) is subtracted, l times, at precomputed positions; then the
+// row is written back.  The next entry's column, the pivot and the U values
+// and targets of the next step are loaded one step ahead.  A pivot below
+// 1e-13 times the row's largest entry (or not finite) marks the row.
+__global__ __launch_bounds__(kNtThreads) void nt_refactor(const NtArgs A) {
+  extern __shared__ double s_w[];
+  const int wv = threadIdx.x >> 6, l64 = threadIdx.x & 63;
+  double *W = s_w + (int64_t)wv * A.a.maxpat;
+  const NtArrays &a = A.a;
+  double *LU = A.w.lu;
+  for (int32_t lev = 0; lev < a.n_lev_l; ++lev) {
+    const int32_t r0 = a.lev_ptr_l[lev], r1 = a.lev_ptr_l[lev + 1];
+    for (int32_t idx = r0 + wv; idx < r1; idx += kNtWaves) {
+      const int32_t i = a.lev_rows_l[idx];
+      const int32_t base = a.row_ptr[i], len = a.row_ptr[i + 1] - base, nl = a.nl[i];
+      for (int32_t t = l64; t < len; t += 64) W[t] = 0.0;
+      double amax = 0.0;
+      for (int32_t t = a.a_ptr[i] + l64; t < a.a_ptr[i + 1]; t += 64) {
+        const double val = A.w.gx[a.a_src[t]];
+        W[a.a_dst[t]] = val;
+        amax = fmax(amax, fabs(val));
+      }
+      for (int off = 32; off >= 1; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off));
+      __builtin_amdgcn_wave_barrier();
+      int64_t u = a.upd_ptr[i];
+      // step q's operands, loaded one step ahead
+      int32_t kb = 0, ul = 0;
+      double ukk = 1.0, uv = 0.0;
+      int32_t tg = 0;
+      auto fetch = [&](int32_t q, int64_t uq, int32_t &kb_, int32_t &ul_, double &ukk_, double &uv_, int32_t &tg_) {
+        if (q >= nl) return;
+        const int32_t k = a.lucol[base + q];
+        kb_ = a.row_ptr[k] + a.nl[k];
+        ul_ = a.row_ptr[k + 1] - kb_;
+        ukk_ = LU[kb_];
+        const int32_t s = 1 + l64;
+        uv_ = s < ul_ ? LU[kb_ + s] : 0.0;
+        tg_ = s < ul_ ? (int32_t)a.tgt[uq + s - 1] : 0;
+      };
+      fetch(0, u, kb, ul, ukk, uv, tg);
+      for (int32_t q = 0; q < nl; ++q) {
+        int32_t kb2 = 0, ul2 = 0, tg2 = 0;
+        double ukk2 = 1.0, uv2 = 0.0;
+        fetch(q + 1, u + (ul - 1), kb2, ul2, ukk2, uv2, tg2);
+        const double l = W[q] / ukk;
+        __builtin_amdgcn_wave_barrier();  // every lane has read w_q
+        if (l64 == 0) W[q] = l;
+        if (1 + l64 < ul) W[tg] -= l * uv;
+        for (int32_t s = 65 + l64; s < ul; s += 64) W[a.tgt[u + s - 1]] -= l * LU[kb + s];  // rows longer than 65
+        __builtin_amdgcn_wave_barrier();  // this step's writes before the next step's reads
+        u += ul - 1;
+        kb = kb2;
+        ul = ul2;
+        ukk = ukk2;
+        uv = uv2;
+        tg = tg2;
+      }
+      for (int32_t t = l64; t < len; t += 64) LU[base + t] = W[t];
+      if (l64 == 0) {
+        const double d = W[nl];
+        if (!isfinite(d) || !(fabs(d) > 1e-13 * amax) || amax == 0.0) A.w.stat[2] = (double)(i + 1);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---- Newton step: y = P g; L y; U y; x -= P^T y ---------------------------
+__global__ __launch_bounds__(kNtThreads) void nt_solve(const NtArgs A) {
+  const NtArrays &a = A.a;
+  const double *LU = A.w.lu;
+  double *y = A.w.y;
+  for (int32_t i = threadIdx.x; i < a.n_x; i += kNtThreads) y[i] = A.w.g[a.perm[i]];
+  __syncthreads();
+  // forward sweep with the unit lower factor, level by level
+  for (int32_t lev = 0; lev < a.n_lev_l; ++lev) {
+    for (int32_t idx = a.lev_ptr_l[lev] + threadIdx.x; idx < a.lev_ptr_l[lev + 1]; idx += kNtThreads) {
+      const int32_t i = a.lev_rows_l[idx], base = a.row_ptr[i], nl = a.nl[i];
+      double s = y[i];
+      for (int32_t q = 0; q < nl; ++q) s -= LU[base + q] * y[a.lucol[base + q]];
+      y[i] = s;
+    }
+    __syncthreads();
+  }
+  // backward sweep with U (diagonal first in each row)
+  for (int32_t lev = 0; lev < a.n_lev_u; ++lev) {
+    for (int32_t idx = a.lev_ptr_u[lev] + threadIdx.x; idx < a.lev_ptr_u[lev + 1]; idx += kNtThreads) {
+      const int32_t i = a.lev_rows_u[idx], ub = a.row_ptr[i] + a.nl[i], ue = a.row_ptr[i + 1];
+      double s = y[i];
+      for (int32_t q = ub + 1; q < ue; ++q) s -= LU[q] * y[a.lucol[q]];
+      y[i] = s / LU[ub];
+    }
+    __syncthreads();
+  }
+  for (int32_t i = threadIdx.x; i < a.n_x; i += kNtThreads) A.w.x[a.perm[i]] -= y[i];
+}
+
+}  // namespace
+
+// ---- host side --------------------------------------------------------------
+
+struct DevNewton {
+  int device = -1;
+  std::vector<void *> allocs;
+  NtArgs args{};
+  size_t lds_bytes = 0;
+  std::vector<int32_t> row_ptr;  // host copy (unpacking the factors)
+};
+
+namespace {
+
+template <class T>
+rh_status nt_up(DevNewton &d, const std::vector<T> &v, const T **out, std::string &err) {
+  void *p = nullptr;
+  HIP_TRY(hipMalloc(&p, std::max<size_t>(sizeof(T), v.size() * sizeof(T))));
+  d.allocs.push_back(p);
+  if (!v.empty()) HIP_TRY(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  *out = static_cast<const T *>(p);
+  return RH_OK;
+}
+
+rh_status nt_alloc(DevNewton &d, size_t n, double **out, std::string &err) {
+  void *p = nullptr;
+  HIP_TRY(hipMalloc(&p, std::max<size_t>(8, n * sizeof(double))));
+  d.allocs.push_back(p);
+  *out = static_cast<double *>(p);
+  return RH_OK;
+}
+
+#define NT_UP(vec, dst)                                  \
+  do {                                                   \
+    rh_status s_ = nt_up(d, vec, &(dst), err);           \
+    if (s_ != RH_OK) return s_;                          \
+  } while (0)
+
+rh_status nt_build(Network &net, DevNewton &d, std::string &err) {
+  const LuPlan &lu = net.lu;
+  const int32_t n = lu.n, m = net.n_br, nb = net.n_bus;
+  NtArrays &a = d.args.a;
+  a.n_bus = nb;
+  a.n_br = m;
+  a.n_x = net.n_x;
+  a.n_p = net.n_p;
+  a.nnz_gx = (int32_t)net.gx.nnz();
+  NT_UP(net.br_f, a.br_f);
+  NT_UP(net.br_t, a.br_t);
+  NT_UP(net.gs, a.gs);
+  NT_UP(net.bs, a.bs);
+  NT_UP(net.bsh, a.bsh);
+  NT_UP(net.th_x, a.th_x);
+  NT_UP(net.v_x, a.v_x);
+  NT_UP(net.v_p, a.v_p);
+  NT_UP(net.pg_p, a.pg_p);
+  {
+    std::vector<int32_t> ptr(nb + 1, 0), code(2 * (size_t)m);
+    for (int32_t b = 0; b < m; ++b) {
+      ptr[net.br_f[b] + 1]++;
+      ptr[net.br_t[b] + 1]++;
+    }
+    for (int32_t b = 0; b < nb; ++b) ptr[b + 1] += ptr[b];
+    std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+    for (int32_t b = 0; b < m; ++b) {
+      code[fill[net.br_f[b]]++] = 4 * b;
+      code[fill[net.br_t[b]]++] = 4 * b + 2;
+    }
+    NT_UP(ptr, a.inc_ptr);
+    NT_UP(code, a.inc_code);
+  }
+  {
+    // contributions of branch partials to G_x entries, in branch order
+    const int64_t nnz = net.gx.nnz();
+    std::vector<int32_t> cnt(nnz + 1, 0), src;
+    for (size_t q = 0; q < net.gx_slot.size(); ++q)
+      if (net.gx_slot[q] >= 0) cnt[net.gx_slot[q] + 1]++;
+    for (int64_t s = 0; s < nnz; ++s) cnt[s + 1] += cnt[s];
+    src.assign(cnt[nnz], 0);
+    std::vector<int32_t> fill(cnt.begin(), cnt.end() - 1);
+    for (size_t q = 0; q < net.gx_slot.size(); ++q)  // q = 16 b + 4 k + var: branch order
+      if (net.gx_slot[q] >= 0) src[fill[net.gx_slot[q]]++] = (int32_t)q;
+    NT_UP(cnt, a.gxc_ptr);
+    NT_UP(src, a.gxc_src);
+  }
+  {
+    LuMaps mp;
+    if (!lu_device_maps(lu, net.gx, mp, err)) return RH_EDEVICE;
+    if ((size_t)mp.maxpat * sizeof(double) * kNtWaves > 150 * 1024) {
+      err = "LU row pattern too wide for the device refactorisation (" + std::to_string(mp.maxpat) + ")";
+      return RH_EINVAL;
+    }
+    a.maxpat = mp.maxpat;
+    a.nnz_lu = mp.row_ptr[n];
+    NT_UP(mp.row_ptr, a.row_ptr);
+    NT_UP(mp.nl, a.nl);
+    NT_UP(mp.lucol, a.lucol);
+    NT_UP(lu.perm, a.perm);
+    NT_UP(mp.a_ptr, a.a_ptr);
+    NT_UP(mp.a_src, a.a_src);
+    NT_UP(mp.a_dst, a.a_dst);
+    NT_UP(mp.upd_ptr, a.upd_ptr);
+    NT_UP(mp.tgt, a.tgt);
+    d.row_ptr = mp.row_ptr;
+    a.n_lev_l = lu.n_levels_l;
+    a.n_lev_u = lu.n_levels_u;
+    NT_UP(mp.lev_ptr_l, a.lev_ptr_l);
+    NT_UP(mp.lev_rows_l, a.lev_rows_l);
+    NT_UP(mp.lev_ptr_u, a.lev_ptr_u);
+    NT_UP(mp.lev_rows_u, a.lev_rows_u);
+    d.lds_bytes = (size_t)mp.maxpat * sizeof(double) * kNtWaves;
+  }
+  NtVectors &w = d.args.w;
+  rh_status s;
+  if ((s = nt_alloc(d, net.n_x, &w.x, err)) != RH_OK || (s = nt_alloc(d, net.n_p, &w.p, err)) != RH_OK ||
+      (s = nt_alloc(d, nb, &w.Pd, err)) != RH_OK || (s = nt_alloc(d, nb, &w.Qd, err)) != RH_OK ||
+      (s = nt_alloc(d, nb, &w.th, err)) != RH_OK || (s = nt_alloc(d, nb, &w.v, err)) != RH_OK ||
+      (s = nt_alloc(d, 4 * (size_t)m, &w.flows, err)) != RH_OK ||
+      (s = nt_alloc(d, 16 * (size_t)m, &w.dG, err)) != RH_OK || (s = nt_alloc(d, net.n_x, &w.g, err)) != RH_OK ||
+      (s = nt_alloc(d, a.nnz_gx, &w.gx, err)) != RH_OK || (s = nt_alloc(d, a.nnz_lu, &w.lu, err)) != RH_OK ||
+      (s = nt_alloc(d, net.n_x, &w.y, err)) != RH_OK || (s = nt_alloc(d, 4, &w.stat, err)) != RH_OK)
+    return s;
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&nt_refactor),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)d.lds_bytes));
+  return RH_OK;
+}
+
+rh_status nt_step_kernels(DevNewton &d, int32_t m, int32_t nb, int32_t nnz_gx, bool jacobian, std::string &err) {
+  const int T = 256;
+  hipLaunchKernelGGL(nt_state, dim3((nb + T - 1) / T), dim3(T), 0, nullptr, d.args);
+  hipLaunchKernelGGL(nt_flows, dim3((m + T - 1) / T), dim3(T), 0, nullptr, d.args, jacobian ? 1 : 0);
+  hipLaunchKernelGGL(nt_residual, dim3((nb + T - 1) / T), dim3(T), 0, nullptr, d.args);
+  hipLaunchKernelGGL(nt_norm, dim3(1), dim3(kNtThreads), 0, nullptr, d.args);
+  if (jacobian) {
+    hipLaunchKernelGGL(nt_gx, dim3((nnz_gx + T - 1) / T), dim3(T), 0, nullptr, d.args);
+    hipLaunchKernelGGL(nt_refactor, dim3(1), dim3(kNtThreads), d.lds_bytes, nullptr, d.args);
+  }
+  HIP_TRY(hipGetLastError());
+  return RH_OK;
+}
+
+}  // namespace
+
+void device_newton_free(Network &net) {
+  DevNewton *d = net.dnewton;
+  if (!d) return;
+  (void)hipSetDevice(d->device);
+  (void)hipDeviceSynchronize();
+  for (void *p : d->allocs) (void)hipFree(p);
+  delete d;
+  net.dnewton = nullptr;
+}
+
+rh_status device_newton(Network &net, double tol, int32_t max_iter, NewtonResult &res, std::string &err) {
+  HIP_TRY(hipSetDevice(net.ctx->device));
+  if (!net.dnewton) {
+    DevNewton *d = new DevNewton();
+    d->device = net.ctx->device;
+    net.dnewton = d;
+    rh_status s = nt_build(net, *d, err);
+    if (s != RH_OK) {
+      device_newton_free(net);
+      return s;
+    }
+  }
+  DevNewton &d = *net.dnewton;
+  NtVectors &w = d.args.w;
+  std::vector<double> x(net.n_x, 0.0);
+  if ((int32_t)net.x0.size() == net.n_x)
+    x = net.x0;
+  else
+    for (int32_t b : net.pq) x[net.v_x[b]] = 1.0;
+  HIP_TRY(hipMemcpy(w.x, x.data(), x.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(w.p, net.p.data(), net.p.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(w.Pd, net.Pd.data(), net.Pd.size() * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(w.Qd, net.Qd.data(), net.Qd.size() * sizeof(double), hipMemcpyHostToDevice));
+  const int32_t m = net.n_br, nb = net.n_bus, nnz_gx = (int32_t)net.gx.nnz();
+  double stat[3] = {0.0, 0.0, 0.0};
+  int32_t it = 0;
+  for (;; ++it) {
+    // mismatch at x; with the Jacobian and its factors unless this is the end
+    rh_status s = nt_step_kernels(d, m, nb, nnz_gx, true, err);
+    if (s != RH_OK) return s;
+    HIP_TRY(hipMemcpy(stat, w.stat, sizeof stat, hipMemcpyDeviceToHost));
+    res.iters = it;
+    res.resid = stat[0];
+    if (stat[1] != 0.0) {
+      err = "Newton produced a non-finite residual";
+      return RH_ENOCONV;
+    }
+    if (stat[2] != 0.0) {
+      err = "G_x is singular to working precision (pivot " + std::to_string((int64_t)stat[2] - 1) + ")";
+      return RH_ESINGULAR;
+    }
+    if (stat[0] <= tol) break;
+    if (it >= max_iter) {
+      err = "Newton did not reach the tolerance in max_iter steps";
+      return RH_ENOCONV;
+    }
+    hipLaunchKernelGGL(nt_solve, dim3(1), dim3(kNtThreads), 0, nullptr, d.args);
+    HIP_TRY(hipGetLastError());
+  }
+  // the accepted state and the factors of G_x there (from the last step's
+  // kernels, which ran at this x)
+  res.x.resize(net.n_x);
+  HIP_TRY(hipMemcpy(res.x.data(), w.x, net.n_x * sizeof(double), hipMemcpyDeviceToHost));
+  std::vector<double> luv(d.row_ptr.back());
+  HIP_TRY(hipMemcpy(luv.data(), w.lu, luv.size() * sizeof(double), hipMemcpyDeviceToHost));
+  LuPlan &lu = net.lu;
+  for (int32_t i = 0; i < lu.n; ++i) {
+    const double *r = luv.data() + d.row_ptr[i];
+    const size_t nl = lu.lrow[i].size();
+    lu.lval[i].assign(r, r + nl);
+    lu.uval[i].assign(r + nl, r + nl + lu.urow[i].size());
+  }
+  return RH_OK;
+}
+
+}  // namespace rh

@@ -141,6 +141,7 @@ struct ScheduleParams {
 struct DeviceNet;  // defined by the device translation unit
 struct DeviceCtx;  // likewise: a context's resources for batched launches
 struct DeviceBatch;  // likewise: a batched launch recorded as a graph
+struct DevNewton;    // the device Newton's arrays (newton.hip)
 
 struct Context {
   int32_t device = -1;  // -1: host only
@@ -192,6 +193,7 @@ struct Network {
   Tape tape;
   rh_report report{};
   DeviceNet *dev = nullptr;
+  DevNewton *dnewton = nullptr;  // device Newton arrays (rh_solve_powerflow_device)
   uint64_t dev_gen = 0;  // device uploads so far (a recorded launch checks it is unchanged)
   // launch shape per precision (0 FP64, 1 refined) chosen by the tuner
   // (tune.cpp); k == 0: not chosen, the library's defaults apply
@@ -204,6 +206,37 @@ struct Network {
 // ---- host planner (network.cpp)
 rh_status network_build(Network &net, const rh_network_desc &d, std::string &err);
 rh_status network_solve(Network &net, double tol, int32_t max_iter, std::string &err);
+// The state x is accepted after `it` Newton steps with residual r: the
+// Jacobians at x, the factors of G_x (factored here unless factors_given:
+// net.lu already holds them), the first-order adjoint, the objective and the
+// branch coefficients.
+rh_status network_accept(Network &net, const std::vector<double> &x, int32_t it, double r, bool factors_given,
+                         std::string &err);
+// Maps of the device refactorisation (P G_x P^T = L U on the fixed pattern):
+// row i of the factors occupies row_ptr[i] .. row_ptr[i + 1] - 1, its L part
+// (nl[i] entries) then its U part (diagonal first), with column lucol[] of
+// every position; the G_x entries a_src[a_ptr[i] ..] of permuted row i go to
+// positions a_dst[..] of the row; eliminating with row k (every entry of row
+// i's L part in turn) updates the positions tgt[upd_ptr[i] ..] of row i, one
+// per entry of row k's U part after its diagonal; rows grouped by level of
+// the L (and U) sweep.
+struct LuMaps {
+  std::vector<int32_t> row_ptr, nl, lucol, a_ptr, a_src;
+  std::vector<uint16_t> a_dst, tgt;
+  std::vector<int64_t> upd_ptr;
+  std::vector<int32_t> lev_ptr_l, lev_rows_l, lev_ptr_u, lev_rows_u;
+  int32_t maxpat = 0;
+};
+bool lu_device_maps(const LuPlan &lu, const Csr &gx, LuMaps &mp, std::string &err);
+// Newton on the device (newton.hip): the state and the factors of G_x at it
+// are returned (x in res, the factor values in net.lu).
+struct NewtonResult {
+  int32_t iters = 0;
+  double resid = 0.0;
+  std::vector<double> x;
+};
+rh_status device_newton(Network &net, double tol, int32_t max_iter, NewtonResult &res, std::string &err);
+void device_newton_free(Network &net);
 void flows_inject(const Network &net, const std::vector<double> &th, const std::vector<double> &v,
                   std::vector<double> &P, std::vector<double> &Q);
 void unpack_state(const Network &net, const std::vector<double> &x, const std::vector<double> &p,

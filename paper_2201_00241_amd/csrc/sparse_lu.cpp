@@ -692,6 +692,75 @@ Schedule build_schedule(const Sweep &in, int32_t n, const std::vector<int32_t> &
   return out;
 }
 
+namespace {
+// Rows grouped by level (ascending), as {level pointer, rows}.
+void group_levels(const std::vector<int32_t> &level, int32_t n_lev, std::vector<int32_t> &ptr,
+                  std::vector<int32_t> &rows) {
+  ptr.assign(n_lev + 1, 0);
+  for (int32_t l : level) ptr[l + 1]++;
+  for (int32_t l = 0; l < n_lev; ++l) ptr[l + 1] += ptr[l];
+  rows.assign(level.size(), 0);
+  std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+  for (int32_t i = 0; i < (int32_t)level.size(); ++i) rows[fill[level[i]]++] = i;
+}
+}  // namespace
+
+bool lu_device_maps(const LuPlan &lu, const Csr &gx, LuMaps &mp, std::string &err) {
+  const int32_t n = lu.n;
+  mp = LuMaps();
+  mp.row_ptr.assign(n + 1, 0);
+  mp.nl.resize(n);
+  for (int32_t i = 0; i < n; ++i) {
+    mp.nl[i] = (int32_t)lu.lrow[i].size();
+    const int32_t len = mp.nl[i] + (int32_t)lu.urow[i].size();
+    mp.row_ptr[i + 1] = mp.row_ptr[i] + len;
+    mp.maxpat = std::max(mp.maxpat, len);
+    mp.lucol.insert(mp.lucol.end(), lu.lrow[i].begin(), lu.lrow[i].end());
+    mp.lucol.insert(mp.lucol.end(), lu.urow[i].begin(), lu.urow[i].end());
+  }
+  if (mp.maxpat > 65535) {
+    err = "LU row pattern too wide for 16-bit positions";
+    return false;
+  }
+  // position of column c within row i (the L part and the U part are each
+  // ascending, and every L column is below every U column)
+  auto pos_in = [&](int32_t i, int32_t c) -> int32_t {
+    const int32_t *b = mp.lucol.data() + mp.row_ptr[i], *e = mp.lucol.data() + mp.row_ptr[i + 1];
+    const int32_t *p = std::lower_bound(b, e, c);
+    return (p != e && *p == c) ? (int32_t)(p - b) : -1;
+  };
+  mp.a_ptr.assign(n + 1, 0);
+  for (int32_t i = 0; i < n; ++i) {
+    const int32_t r = lu.perm[i];
+    for (int32_t e = gx.ptr[r]; e < gx.ptr[r + 1]; ++e) {
+      const int32_t p = pos_in(i, lu.iperm[gx.col[e]]);
+      if (p < 0) {
+        err = "internal: G_x entry outside the LU pattern";
+        return false;
+      }
+      mp.a_src.push_back(e);
+      mp.a_dst.push_back((uint16_t)p);
+    }
+    mp.a_ptr[i + 1] = (int32_t)mp.a_src.size();
+  }
+  mp.upd_ptr.assign(n + 1, 0);
+  for (int32_t i = 0; i < n; ++i) {
+    for (int32_t k : lu.lrow[i])
+      for (size_t s = 1; s < lu.urow[k].size(); ++s) {
+        const int32_t p = pos_in(i, lu.urow[k][s]);
+        if (p < 0) {
+          err = "internal: fill outside the LU pattern";
+          return false;
+        }
+        mp.tgt.push_back((uint16_t)p);
+      }
+    mp.upd_ptr[i + 1] = (int64_t)mp.tgt.size();
+  }
+  group_levels(lu.level_l, lu.n_levels_l, mp.lev_ptr_l, mp.lev_rows_l);
+  group_levels(lu.level_u, lu.n_levels_u, mp.lev_ptr_u, mp.lev_rows_u);
+  return true;
+}
+
 std::vector<int32_t> etree_parent(const LuPlan &lu) {
   std::vector<int32_t> parent(lu.n, -1);
   for (int32_t k = 0; k < lu.n; ++k)

@@ -97,6 +97,9 @@ _SIGS = {
     "rh_set_initial_state": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
     "rh_solve_powerflow": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32,
                                           _i32p, _f64p]),
+    "rh_solve_powerflow_device": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int32,
+                                                 _i32p, _f64p]),
+    "rh_get_factors": (ctypes.c_int, [ctypes.c_void_p, _f64p, _f64p]),
     "rh_get_state": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
     "rh_objective": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
     "rh_reduced_gradient": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
@@ -283,6 +286,19 @@ def rh_solve_powerflow(net, tol=1e-13, max_iter=30):
     _check(load().rh_solve_powerflow(net, float(tol), int(max_iter), ctypes.byref(it),
                                      ctypes.byref(r)))
     return it.value, r.value
+
+
+def rh_solve_powerflow_device(net, tol=1e-13, max_iter=30):
+    it, r = ctypes.c_int32(), ctypes.c_double()
+    _check(load().rh_solve_powerflow_device(net, float(tol), int(max_iter), ctypes.byref(it),
+                                            ctypes.byref(r)))
+    return it.value, r.value
+
+
+def rh_get_factors(net, nnz_l, nnz_u):
+    lv, uv = np.zeros(nnz_l), np.zeros(nnz_u)
+    _check(load().rh_get_factors(net, _p(lv, _f64p), _p(uv, _f64p)))
+    return lv, uv
 
 
 def rh_get_state(net) -> np.ndarray:
@@ -523,6 +539,12 @@ class Network:
     set_initial_state = lambda self, x0=None: rh_set_initial_state(self.h, x0)  # noqa: E731
     solve = lambda self, tol=1e-13, max_iter=30: rh_solve_powerflow(self.h, tol, max_iter)  # noqa
     state = lambda self: rh_get_state(self.h)  # noqa: E731
+    solve_device = lambda self, tol=1e-13, max_iter=30: rh_solve_powerflow_device(self.h, tol, max_iter)  # noqa
+
+    def factors(self):
+        """(L values, U values) of the solved operating point (see rh_get_factors)."""
+        r = self.report()
+        return rh_get_factors(self.h, r["nnz_l"], r["nnz_u"])
     objective = lambda self: rh_objective(self.h)  # noqa: E731
     reduced_gradient = lambda self: rh_reduced_gradient(self.h)  # noqa: E731
     hvp = lambda self, W, prec=RH_FP64: rh_hvp(self.h, W, prec)  # noqa: E731

@@ -400,6 +400,56 @@ int main(int argc, char **argv) {
                relerr(X, Y), sc.meta.size() / 4, waves, ok ? 1 : 0);
       }
   printf("order_violations %d\n", bad);
+  // the device refactorisation's maps, replayed on the host in the kernel's
+  // order (levels of rows, each row in a buffer: scatter G_x, eliminate with
+  // the L part's rows in ascending order at the mapped positions), against
+  // the host factorisation of the same G_x
+  {
+    LuMaps mp;
+    std::string e2;
+    if (!lu_device_maps(net.lu, net.gx, mp, e2)) {
+      printf("maps error %s\n", e2.c_str());
+      return 1;
+    }
+    const LuPlan &lu = net.lu;
+    std::vector<double> LU(mp.row_ptr[nx], std::nan("")), W(mp.maxpat);
+    std::vector<char> done(nx, 0);
+    int level_bad = 0;
+    for (size_t lev = 0; lev + 1 < mp.lev_ptr_l.size(); ++lev) {
+      for (int32_t idx = mp.lev_ptr_l[lev]; idx < mp.lev_ptr_l[lev + 1]; ++idx) {
+        const int32_t i = mp.lev_rows_l[idx], base = mp.row_ptr[i], len = mp.row_ptr[i + 1] - base;
+        std::fill(W.begin(), W.begin() + len, 0.0);
+        for (int32_t t = mp.a_ptr[i]; t < mp.a_ptr[i + 1]; ++t) W[mp.a_dst[t]] = net.gx.val[mp.a_src[t]];
+        int64_t u = mp.upd_ptr[i];
+        for (int32_t q = 0; q < mp.nl[i]; ++q) {
+          const int32_t k = mp.lucol[base + q];
+          if (!done[k]) ++level_bad;  // row k must be final (an earlier level)
+          const int32_t kb = mp.row_ptr[k] + mp.nl[k], ul = mp.row_ptr[k + 1] - kb;
+          const double l = W[q] / LU[kb];
+          W[q] = l;
+          for (int32_t s2 = 1; s2 < ul; ++s2) W[mp.tgt[u + s2 - 1]] -= l * LU[kb + s2];
+          u += ul - 1;
+        }
+        if (u != mp.upd_ptr[i + 1]) ++level_bad;
+        for (int32_t t = 0; t < len; ++t) LU[base + t] = W[t];
+      }
+      for (int32_t idx = mp.lev_ptr_l[lev]; idx < mp.lev_ptr_l[lev + 1]; ++idx) done[mp.lev_rows_l[idx]] = 1;
+    }
+    double e = 0.0, mx = 0.0;
+    for (int32_t i = 0; i < nx; ++i) {
+      const int32_t base = mp.row_ptr[i];
+      for (size_t q = 0; q < lu.lval[i].size(); ++q) {
+        e = std::max(e, std::fabs(LU[base + q] - lu.lval[i][q]));
+        mx = std::max(mx, std::fabs(lu.lval[i][q]));
+      }
+      for (size_t q = 0; q < lu.uval[i].size(); ++q) {
+        e = std::max(e, std::fabs(LU[base + mp.nl[i] + q] - lu.uval[i][q]));
+        mx = std::max(mx, std::fabs(lu.uval[i][q]));
+      }
+    }
+    printf("max_err device_refactor %.3e\n", e / mx);
+    printf("refactor_level_violations %d\n", level_bad);
+  }
   // the four sweeps compose to the two solves: U^-1 L^-1 (P b) and L^-T U^-T (P b)
   {
     std::vector<double> bb(nx);

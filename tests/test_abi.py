@@ -162,3 +162,10 @@ def test_batch_recording_needs_a_device(ctx):
         rh.rh_batch_create(ctx.h, [net.h], [1], [None], [net.n_p], [None], [net.n_p])
     assert ei.value.status == rh.RH_EDEVICE
     assert rh.load().rh_batch_destroy(None) == rh.RH_OK
+
+
+def test_device_newton_needs_a_device(ctx):
+    net = rh.Network(ctx, gridgen.config_grid("c0", 0))
+    with pytest.raises(rh.RhError) as ei:
+        net.solve_device()
+    assert ei.value.status == rh.RH_EDEVICE

@@ -63,6 +63,8 @@ def test_planner_lu_and_sweep_schedules(driver, tmp_path, name):
         if parts and parts[0] == "max_err":
             errs[parts[1]] = float(parts[2])
     assert "order_violations 0" in res.stdout, res.stdout
+    assert "refactor_level_violations 0" in res.stdout, res.stdout
+    assert "max_err device_refactor" in res.stdout, res.stdout
     assert "order_violations_composed" not in res.stdout
     assert any(k.startswith("sweep_") for k in errs), res.stdout
     if g.n_x <= 400:
