@@ -62,12 +62,14 @@ struct NtArrays {
   const uint16_t *a_dst;         // ... and position in the row
   const int64_t *upd_ptr;        // per row: first target of its updates
   const uint16_t *tgt;           // targets (position in the row) of every update, row by row
+  const int4 *step;              // per L position: {U part of the pivot row: start, length; first target; row}
   const int32_t *lev_ptr_l, *lev_rows_l, *lev_ptr_u, *lev_rows_u;
 };
 
 // Per-solve device vectors.
 struct NtVectors {
   double *x, *p, *Pd, *Qd, *th, *v, *flows, *dG, *g, *gx, *lu, *y;
+  double *rinv;  // 1 / u_ii of every finished row
   double *stat;  // [0] max |g|, [1] non-finite flag, [2] singular pivot row + 1
 };
 
@@ -178,103 +180,167 @@ __global__ void nt_gx(const NtArgs A) {
 
 // P G_x P^T = L U, one elimination level of rows at a time (rows of a level
 // depend only on rows of earlier levels), one wave per row.  A row is
-// scattered into its wave's LDS buffer, then for every entry k of its L part
-// in ascending order: l = w_k / u_kk, and the U part of row k (final: an
-// earlier level) is subtracted, l times, at precomputed positions; then the
-// row is written back.  The next entry's column, the pivot and the U values
-// and targets of the next step are loaded one step ahead.  A pivot below
-// 1e-13 times the row's largest entry (or not finite) marks the row.
-__global__ __launch_bounds__(kNtThreads) void nt_refactor(const NtArgs A) {
+// scattered into the wave's LDS buffer; then, for every entry of its L part
+// in ascending order (pivot row k), l = w_q / u_kk and the U part of row k
+// (final: an earlier level) is subtracted, l times, at precomputed
+// positions; then the row is written back with the reciprocal of its pivot.
+// The elimination steps form the critical path (tens of thousands at the
+// top of the elimination tree), so a step waits for nothing in global memory:
+// the step descriptors are loaded 64 at a time into a lane register and read
+// by readlane, the pivot reciprocal, U values and targets of a step are
+// loaded four steps ahead into a statically indexed ring, and l takes the
+// stored reciprocal instead of a division.  A pivot below 1e-13 times the
+// row's largest entry (or not finite) marks the row.
+struct NtOp {
+  double uv, rk;
+  int32_t tg, ul, kb, us;
+};
+
+__device__ __forceinline__ void nt_factor_row(const NtArgs &A, int32_t i, double *W, int l64) {
+  const NtArrays &a = A.a;
+  double *LU = A.w.lu;
+  const int32_t base = a.row_ptr[i], len = a.row_ptr[i + 1] - base, nl = a.nl[i];
+  for (int32_t t = l64; t < len; t += 64) W[t] = 0.0;
+  double amax = 0.0;
+  for (int32_t t = a.a_ptr[i] + l64; t < a.a_ptr[i + 1]; t += 64) {
+    const double val = A.w.gx[a.a_src[t]];
+    W[a.a_dst[t]] = val;
+    amax = fmax(amax, fabs(val));
+  }
+  for (int off = 32; off >= 1; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off));
+  __builtin_amdgcn_wave_barrier();
+  const int4 *SI = a.step + base;
+  const int4 z4 = make_int4(0, 0, 0, 0);
+  int32_t c = 0;  // first step of the chunk held by `cur`
+  int4 cur = l64 < nl ? SI[l64] : z4, nxt = 64 + l64 < nl ? SI[64 + l64] : z4;
+  auto load_op = [&](int32_t q, NtOp &o) {
+    const int4 &src = q - c < 64 ? cur : nxt;
+    const int j = (q - c) & 63;
+    const bool in = q < nl;
+    o.kb = __builtin_amdgcn_readlane(src.x, j);
+    o.ul = in ? __builtin_amdgcn_readlane(src.y, j) : 0;
+    o.us = __builtin_amdgcn_readlane(src.z, j);
+    const int32_t k = __builtin_amdgcn_readlane(src.w, j);
+    const bool ok = in && 1 + l64 < o.ul;
+    o.uv = ok ? LU[o.kb + 1 + l64] : 0.0;
+    o.tg = ok ? (int32_t)a.tgt[o.us + l64] : 0;
+    o.rk = in ? A.w.rinv[k] : 0.0;
+  };
+  constexpr int kD = 4;
+  NtOp ring[kD];
+#pragma unroll
+  for (int d = 0; d < kD; ++d) load_op(d, ring[d]);
+  for (int32_t q0 = 0; q0 < nl; q0 += kD) {
+#pragma unroll
+    for (int d = 0; d < kD; ++d) {
+      const int32_t q = q0 + d;
+      if (q < nl) {
+        const NtOp &o = ring[d];
+        const double l = W[q] * o.rk;
+        __builtin_amdgcn_wave_barrier();  // every lane has read w_q
+        if (l64 == 0) W[q] = l;
+        if (1 + l64 < o.ul) W[o.tg] -= l * o.uv;
+        for (int32_t s2 = 65 + l64; s2 < o.ul; s2 += 64) W[a.tgt[o.us + s2 - 1]] -= l * LU[o.kb + s2];
+        __builtin_amdgcn_wave_barrier();  // this step's writes before the next step's reads
+      }
+      // the step kD on, into this slot; the descriptors move on by a chunk
+      // once that step leaves the current one
+      if (q + kD == c + 64) {
+        c += 64;
+        cur = nxt;
+        nxt = c + 64 + l64 < nl ? SI[c + 64 + l64] : z4;
+      }
+      load_op(q + kD, ring[d]);
+    }
+  }
+  for (int32_t t = l64; t < len; t += 64) LU[base + t] = W[t];
+  if (l64 == 0) {
+    const double d = W[nl];
+    A.w.rinv[i] = 1.0 / d;
+    if (!isfinite(d) || !(fabs(d) > 1e-13 * amax) || amax == 0.0) A.w.stat[2] = (double)(i + 1);
+  }
+}
+
+// One wide level: a wave per row over many workgroups of four waves.
+constexpr int kNtWideWaves = 4;
+__global__ __launch_bounds__(64 * kNtWideWaves) void nt_refactor_level(const NtArgs A, int32_t lev) {
+  extern __shared__ double s_w[];
+  const int wv = threadIdx.x >> 6, l64 = threadIdx.x & 63;
+  const int32_t idx = A.a.lev_ptr_l[lev] + blockIdx.x * kNtWideWaves + wv;
+  if (idx < A.a.lev_ptr_l[lev + 1]) nt_factor_row(A, A.a.lev_rows_l[idx], s_w + (int64_t)wv * A.a.maxpat, l64);
+}
+
+// Levels lev0 .. lev1 - 1 by one workgroup, a barrier between levels.
+__global__ __launch_bounds__(kNtThreads) void nt_refactor_run(const NtArgs A, int32_t lev0, int32_t lev1) {
   extern __shared__ double s_w[];
   const int wv = threadIdx.x >> 6, l64 = threadIdx.x & 63;
   double *W = s_w + (int64_t)wv * A.a.maxpat;
-  const NtArrays &a = A.a;
-  double *LU = A.w.lu;
-  for (int32_t lev = 0; lev < a.n_lev_l; ++lev) {
-    const int32_t r0 = a.lev_ptr_l[lev], r1 = a.lev_ptr_l[lev + 1];
-    for (int32_t idx = r0 + wv; idx < r1; idx += kNtWaves) {
-      const int32_t i = a.lev_rows_l[idx];
-      const int32_t base = a.row_ptr[i], len = a.row_ptr[i + 1] - base, nl = a.nl[i];
-      for (int32_t t = l64; t < len; t += 64) W[t] = 0.0;
-      double amax = 0.0;
-      for (int32_t t = a.a_ptr[i] + l64; t < a.a_ptr[i + 1]; t += 64) {
-        const double val = A.w.gx[a.a_src[t]];
-        W[a.a_dst[t]] = val;
-        amax = fmax(amax, fabs(val));
-      }
-      for (int off = 32; off >= 1; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off));
-      __builtin_amdgcn_wave_barrier();
-      int64_t u = a.upd_ptr[i];
-      // step q's operands, loaded one step ahead
-      int32_t kb = 0, ul = 0;
-      double ukk = 1.0, uv = 0.0;
-      int32_t tg = 0;
-      auto fetch = [&](int32_t q, int64_t uq, int32_t &kb_, int32_t &ul_, double &ukk_, double &uv_, int32_t &tg_) {
-        if (q >= nl) return;
-        const int32_t k = a.lucol[base + q];
-        kb_ = a.row_ptr[k] + a.nl[k];
-        ul_ = a.row_ptr[k + 1] - kb_;
-        ukk_ = LU[kb_];
-        const int32_t s = 1 + l64;
-        uv_ = s < ul_ ? LU[kb_ + s] : 0.0;
-        tg_ = s < ul_ ? (int32_t)a.tgt[uq + s - 1] : 0;
-      };
-      fetch(0, u, kb, ul, ukk, uv, tg);
-      for (int32_t q = 0; q < nl; ++q) {
-        int32_t kb2 = 0, ul2 = 0, tg2 = 0;
-        double ukk2 = 1.0, uv2 = 0.0;
-        fetch(q + 1, u + (ul - 1), kb2, ul2, ukk2, uv2, tg2);
-        const double l = W[q] / ukk;
-        __builtin_amdgcn_wave_barrier();  // every lane has read w_q
-        if (l64 == 0) W[q] = l;
-        if (1 + l64 < ul) W[tg] -= l * uv;
-        for (int32_t s = 65 + l64; s < ul; s += 64) W[a.tgt[u + s - 1]] -= l * LU[kb + s];  // rows longer than 65
-        __builtin_amdgcn_wave_barrier();  // this step's writes before the next step's reads
-        u += ul - 1;
-        kb = kb2;
-        ul = ul2;
-        ukk = ukk2;
-        uv = uv2;
-        tg = tg2;
-      }
-      for (int32_t t = l64; t < len; t += 64) LU[base + t] = W[t];
-      if (l64 == 0) {
-        const double d = W[nl];
-        if (!isfinite(d) || !(fabs(d) > 1e-13 * amax) || amax == 0.0) A.w.stat[2] = (double)(i + 1);
-      }
-    }
+  for (int32_t lev = lev0; lev < lev1; ++lev) {
+    for (int32_t idx = A.a.lev_ptr_l[lev] + wv; idx < A.a.lev_ptr_l[lev + 1]; idx += kNtWaves)
+      nt_factor_row(A, A.a.lev_rows_l[idx], W, l64);
     __syncthreads();
   }
 }
 
 // ---- Newton step: y = P g; L y; U y; x -= P^T y ---------------------------
-__global__ __launch_bounds__(kNtThreads) void nt_solve(const NtArgs A) {
+// One wave per row: lanes take the row's entries in turn and the wave sums.
+
+__device__ __forceinline__ void nt_lrow(const NtArgs &A, int32_t i, int l64) {
   const NtArrays &a = A.a;
-  const double *LU = A.w.lu;
-  double *y = A.w.y;
-  for (int32_t i = threadIdx.x; i < a.n_x; i += kNtThreads) y[i] = A.w.g[a.perm[i]];
-  __syncthreads();
-  // forward sweep with the unit lower factor, level by level
-  for (int32_t lev = 0; lev < a.n_lev_l; ++lev) {
-    for (int32_t idx = a.lev_ptr_l[lev] + threadIdx.x; idx < a.lev_ptr_l[lev + 1]; idx += kNtThreads) {
-      const int32_t i = a.lev_rows_l[idx], base = a.row_ptr[i], nl = a.nl[i];
-      double s = y[i];
-      for (int32_t q = 0; q < nl; ++q) s -= LU[base + q] * y[a.lucol[base + q]];
-      y[i] = s;
+  const int32_t base = a.row_ptr[i], nl = a.nl[i];
+  double s = 0.0;
+  for (int32_t q = l64; q < nl; q += 64) s += A.w.lu[base + q] * A.w.y[a.lucol[base + q]];
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+  if (l64 == 0) A.w.y[i] -= s;
+}
+
+__device__ __forceinline__ void nt_urow(const NtArgs &A, int32_t i, int l64) {
+  const NtArrays &a = A.a;
+  const int32_t ub = a.row_ptr[i] + a.nl[i], ue = a.row_ptr[i + 1];
+  double s = 0.0;
+  for (int32_t q = ub + 1 + l64; q < ue; q += 64) s += A.w.lu[q] * A.w.y[a.lucol[q]];
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+  if (l64 == 0) A.w.y[i] = (A.w.y[i] - s) / A.w.lu[ub];
+}
+
+__global__ void nt_permute_in(const NtArgs A) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < A.a.n_x) A.w.y[i] = A.w.g[A.a.perm[i]];
+}
+
+__global__ void nt_update_x(const NtArgs A) {
+  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < A.a.n_x) A.w.x[A.a.perm[i]] -= A.w.y[i];
+}
+
+// One wide level of the L (upper = 0) or U (upper = 1) sweep, a wave per row.
+__global__ __launch_bounds__(256) void nt_solve_level(const NtArgs A, int32_t lev, int32_t upper) {
+  const int wv = threadIdx.x >> 6, l64 = threadIdx.x & 63;
+  const int32_t *lp = upper ? A.a.lev_ptr_u : A.a.lev_ptr_l;
+  const int32_t *lr = upper ? A.a.lev_rows_u : A.a.lev_rows_l;
+  const int32_t idx = lp[lev] + blockIdx.x * 4 + wv;
+  if (idx >= lp[lev + 1]) return;
+  if (upper)
+    nt_urow(A, lr[idx], l64);
+  else
+    nt_lrow(A, lr[idx], l64);
+}
+
+// Levels lev0 .. lev1 - 1 of one sweep by one workgroup, a barrier between levels.
+__global__ __launch_bounds__(kNtThreads) void nt_solve_run(const NtArgs A, int32_t lev0, int32_t lev1,
+                                                           int32_t upper) {
+  const int wv = threadIdx.x >> 6, l64 = threadIdx.x & 63;
+  const int32_t *lp = upper ? A.a.lev_ptr_u : A.a.lev_ptr_l;
+  const int32_t *lr = upper ? A.a.lev_rows_u : A.a.lev_rows_l;
+  for (int32_t lev = lev0; lev < lev1; ++lev) {
+    for (int32_t idx = lp[lev] + wv; idx < lp[lev + 1]; idx += kNtWaves) {
+      if (upper)
+        nt_urow(A, lr[idx], l64);
+      else
+        nt_lrow(A, lr[idx], l64);
     }
     __syncthreads();
   }
-  // backward sweep with U (diagonal first in each row)
-  for (int32_t lev = 0; lev < a.n_lev_u; ++lev) {
-    for (int32_t idx = a.lev_ptr_u[lev] + threadIdx.x; idx < a.lev_ptr_u[lev + 1]; idx += kNtThreads) {
-      const int32_t i = a.lev_rows_u[idx], ub = a.row_ptr[i] + a.nl[i], ue = a.row_ptr[i + 1];
-      double s = y[i];
-      for (int32_t q = ub + 1; q < ue; ++q) s -= LU[q] * y[a.lucol[q]];
-      y[i] = s / LU[ub];
-    }
-    __syncthreads();
-  }
-  for (int32_t i = threadIdx.x; i < a.n_x; i += kNtThreads) A.w.x[a.perm[i]] -= y[i];
 }
 
 }  // namespace
@@ -287,7 +353,13 @@ struct DevNewton {
   NtArgs args{};
   size_t lds_bytes = 0;
   std::vector<int32_t> row_ptr;  // host copy (unpacking the factors)
+  // levels with many rows run as launches of their own over many workgroups,
+  // every run of the other levels as one launch of one workgroup
+  std::vector<int32_t> lev_rows_l, lev_rows_u;  // rows per level
 };
+
+// A level is wide with at least this many rows.
+constexpr int32_t kWideRows = 256;
 
 namespace {
 
@@ -380,6 +452,13 @@ rh_status nt_build(Network &net, DevNewton &d, std::string &err) {
     NT_UP(mp.a_dst, a.a_dst);
     NT_UP(mp.upd_ptr, a.upd_ptr);
     NT_UP(mp.tgt, a.tgt);
+    {
+      std::vector<int4> st(mp.step.size() / 4);
+      std::memcpy(st.data(), mp.step.data(), mp.step.size() * sizeof(int32_t));
+      NT_UP(st, a.step);
+    }
+    for (size_t l = 0; l + 1 < mp.lev_ptr_l.size(); ++l) d.lev_rows_l.push_back(mp.lev_ptr_l[l + 1] - mp.lev_ptr_l[l]);
+    for (size_t l = 0; l + 1 < mp.lev_ptr_u.size(); ++l) d.lev_rows_u.push_back(mp.lev_ptr_u[l + 1] - mp.lev_ptr_u[l]);
     d.row_ptr = mp.row_ptr;
     a.n_lev_l = lu.n_levels_l;
     a.n_lev_u = lu.n_levels_u;
@@ -397,9 +476,10 @@ rh_status nt_build(Network &net, DevNewton &d, std::string &err) {
       (s = nt_alloc(d, 4 * (size_t)m, &w.flows, err)) != RH_OK ||
       (s = nt_alloc(d, 16 * (size_t)m, &w.dG, err)) != RH_OK || (s = nt_alloc(d, net.n_x, &w.g, err)) != RH_OK ||
       (s = nt_alloc(d, a.nnz_gx, &w.gx, err)) != RH_OK || (s = nt_alloc(d, a.nnz_lu, &w.lu, err)) != RH_OK ||
-      (s = nt_alloc(d, net.n_x, &w.y, err)) != RH_OK || (s = nt_alloc(d, 4, &w.stat, err)) != RH_OK)
+      (s = nt_alloc(d, net.n_x, &w.y, err)) != RH_OK || (s = nt_alloc(d, 4, &w.stat, err)) != RH_OK ||
+      (s = nt_alloc(d, net.n_x, &w.rinv, err)) != RH_OK)
     return s;
-  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&nt_refactor),
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&nt_refactor_run),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)d.lds_bytes));
   return RH_OK;
 }
@@ -412,8 +492,46 @@ rh_status nt_step_kernels(DevNewton &d, int32_t m, int32_t nb, int32_t nnz_gx, b
   hipLaunchKernelGGL(nt_norm, dim3(1), dim3(kNtThreads), 0, nullptr, d.args);
   if (jacobian) {
     hipLaunchKernelGGL(nt_gx, dim3((nnz_gx + T - 1) / T), dim3(T), 0, nullptr, d.args);
-    hipLaunchKernelGGL(nt_refactor, dim3(1), dim3(kNtThreads), d.lds_bytes, nullptr, d.args);
+    const size_t lds_w = (size_t)d.args.a.maxpat * sizeof(double) * kNtWideWaves;
+    const int32_t nlev = (int32_t)d.lev_rows_l.size();
+    for (int32_t l = 0; l < nlev;) {
+      if (d.lev_rows_l[l] >= kWideRows) {
+        hipLaunchKernelGGL(nt_refactor_level, dim3((d.lev_rows_l[l] + kNtWideWaves - 1) / kNtWideWaves),
+                           dim3(64 * kNtWideWaves), lds_w, nullptr, d.args, l);
+        ++l;
+        continue;
+      }
+      int32_t l1 = l;
+      while (l1 < nlev && d.lev_rows_l[l1] < kWideRows) ++l1;
+      hipLaunchKernelGGL(nt_refactor_run, dim3(1), dim3(kNtThreads), d.lds_bytes, nullptr, d.args, l, l1);
+      l = l1;
+    }
   }
+  HIP_TRY(hipGetLastError());
+  return RH_OK;
+}
+
+// The Newton step: y = P g, the two sweeps, x -= P^T y.
+rh_status nt_solve_kernels(DevNewton &d, std::string &err) {
+  const int T = 256;
+  const int32_t n = d.args.a.n_x;
+  hipLaunchKernelGGL(nt_permute_in, dim3((n + T - 1) / T), dim3(T), 0, nullptr, d.args);
+  for (int upper = 0; upper < 2; ++upper) {
+    const std::vector<int32_t> &rows = upper ? d.lev_rows_u : d.lev_rows_l;
+    const int32_t nlev = (int32_t)rows.size();
+    for (int32_t l = 0; l < nlev;) {
+      if (rows[l] >= kWideRows) {
+        hipLaunchKernelGGL(nt_solve_level, dim3((rows[l] + 3) / 4), dim3(256), 0, nullptr, d.args, l, upper);
+        ++l;
+        continue;
+      }
+      int32_t l1 = l;
+      while (l1 < nlev && rows[l1] < kWideRows) ++l1;
+      hipLaunchKernelGGL(nt_solve_run, dim3(1), dim3(kNtThreads), 0, nullptr, d.args, l, l1, upper);
+      l = l1;
+    }
+  }
+  hipLaunchKernelGGL(nt_update_x, dim3((n + T - 1) / T), dim3(T), 0, nullptr, d.args);
   HIP_TRY(hipGetLastError());
   return RH_OK;
 }
@@ -476,8 +594,7 @@ rh_status device_newton(Network &net, double tol, int32_t max_iter, NewtonResult
       err = "Newton did not reach the tolerance in max_iter steps";
       return RH_ENOCONV;
     }
-    hipLaunchKernelGGL(nt_solve, dim3(1), dim3(kNtThreads), 0, nullptr, d.args);
-    HIP_TRY(hipGetLastError());
+    if ((s = nt_solve_kernels(d, err)) != RH_OK) return s;
   }
   // the accepted state and the factors of G_x there (from the last step's
   // kernels, which ran at this x)

@@ -219,11 +219,15 @@ rh_status network_accept(Network &net, const std::vector<double> &x, int32_t it,
 // positions a_dst[..] of the row; eliminating with row k (every entry of row
 // i's L part in turn) updates the positions tgt[upd_ptr[i] ..] of row i, one
 // per entry of row k's U part after its diagonal; rows grouped by level of
-// the L (and U) sweep.
+// the L (and U) sweep.  Update targets are numbered below 2^31.
 struct LuMaps {
   std::vector<int32_t> row_ptr, nl, lucol, a_ptr, a_src;
   std::vector<uint16_t> a_dst, tgt;
   std::vector<int64_t> upd_ptr;
+  // per L position of a row (the elimination with row k = its column): the
+  // start and length of row k's U part, the first of its update targets,
+  // and k
+  std::vector<int32_t> step;  // 4 per factor position (only L positions used)
   std::vector<int32_t> lev_ptr_l, lev_rows_l, lev_ptr_u, lev_rows_u;
   int32_t maxpat = 0;
 };

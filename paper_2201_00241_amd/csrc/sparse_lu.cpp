@@ -10,6 +10,7 @@
 // triangular factors are then grouped into dependency levels for the device
 // sweeps.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <queue>
 #include <stdexcept>
@@ -744,8 +745,19 @@ bool lu_device_maps(const LuPlan &lu, const Csr &gx, LuMaps &mp, std::string &er
     mp.a_ptr[i + 1] = (int32_t)mp.a_src.size();
   }
   mp.upd_ptr.assign(n + 1, 0);
+  mp.step.assign(4 * (size_t)mp.row_ptr[n], 0);
   for (int32_t i = 0; i < n; ++i) {
-    for (int32_t k : lu.lrow[i])
+    for (size_t q = 0; q < lu.lrow[i].size(); ++q) {
+      const int32_t k = lu.lrow[i][q];
+      int32_t *st = &mp.step[4 * ((size_t)mp.row_ptr[i] + q)];
+      st[0] = mp.row_ptr[k] + (int32_t)lu.lrow[k].size();
+      st[1] = (int32_t)lu.urow[k].size();
+      if (mp.tgt.size() > (size_t)INT32_MAX) {
+        err = "too many factor updates for 32-bit offsets";
+        return false;
+      }
+      st[2] = (int32_t)mp.tgt.size();
+      st[3] = k;
       for (size_t s = 1; s < lu.urow[k].size(); ++s) {
         const int32_t p = pos_in(i, lu.urow[k][s]);
         if (p < 0) {
@@ -754,6 +766,7 @@ bool lu_device_maps(const LuPlan &lu, const Csr &gx, LuMaps &mp, std::string &er
         }
         mp.tgt.push_back((uint16_t)p);
       }
+    }
     mp.upd_ptr[i + 1] = (int64_t)mp.tgt.size();
   }
   group_levels(lu.level_l, lu.n_levels_l, mp.lev_ptr_l, mp.lev_rows_l);
