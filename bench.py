@@ -237,6 +237,7 @@ def run_refined(net, g, H, k, steps, warmup, stream):
     n_p = net.n_p
     sptr = stream.cuda_stream
     H64 = H.clone()
+    tile = net.autotune(prec=rh.RH_FP32_REFINED)
     for _ in range(warmup):
         net.reduced_hessian_device(H, k_block=k, stream=sptr, prec=rh.RH_FP32_REFINED)
     torch.cuda.synchronize()
@@ -263,6 +264,7 @@ def run_refined(net, g, H, k, steps, warmup, stream):
     return {
         "value": n_p / (ms / 1e3), "unit": "HVP/s", "ms_per_step": ms, "k": k,
         "dirs_per_group": rep["dirs_per_group"], "max_rel_dev_from_fp64": dev,
+        "tuned_shape": tile,
         "passes_per_solve": {"z": pz, "psi": pp},
         "corrections_histogram": {"z": np.bincount(fig["steps_z"]).tolist(),
                                   "psi": np.bincount(fig["steps_psi"]).tolist()},
@@ -468,6 +470,12 @@ def main():
     H = torch.empty((n_p, n_p), dtype=torch.float64, device="cuda")
     stream = torch.cuda.current_stream()
     sptr = stream.cuda_stream
+    # launch shape (directions per workgroup, sweep schedule) from the tuner;
+    # the headline keeps k = 256 directions per block
+    t0 = time.perf_counter()
+    tile = net.autotune()
+    tune_s = time.perf_counter() - t0
+    print(f"# tuned shape: {tile} ({tune_s:.1f} s)", file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
         net.reduced_hessian_device(H, k_block=k, stream=sptr)
@@ -493,6 +501,17 @@ def main():
     ms_per_step = total_ms / args.steps
     value = n_p * args.steps / (total_ms / 1e3)
     print(f"# headline: {value:.0f} HVP/s, {ms_per_step:.3f} ms per Hessian", file=sys.stderr, flush=True)
+
+    # the tuner's own launch size (outside the timed region)
+    torch.cuda.synchronize()
+    e_a, e_b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    net.reduced_hessian_device(H, k_block=0, stream=sptr)
+    e_a.record(stream)
+    for _ in range(3):
+        net.reduced_hessian_device(H, k_block=0, stream=sptr)
+    e_b.record(stream)
+    torch.cuda.synchronize()
+    tuned_ms = e_a.elapsed_time(e_b) / 3
 
     # one more step with in-kernel phase stamps (outside the timed region)
     ctx.set_timing(2)
@@ -532,6 +551,8 @@ def main():
             "levels_l": rep["levels_l"], "levels_u": rep["levels_u"],
             "nnz_l": rep["nnz_l"], "nnz_u": rep["nnz_u"],
             "steps_l": rep["steps_l"], "steps_u": rep["steps_u"],
+            "tuned_shape": {**tile, "tune_s": tune_s,
+                            "source": ["defaults", "measured", "cache"][tile["source"]]},
         },
         "phase_us": dict(zip(phase_names, [round(v, 2) for v in prep["phase_us"]])),
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)),
@@ -546,6 +567,8 @@ def main():
         },
         "setup_s": setup_s,
         "wall_s": wall,
+        "tuned_k_full_hessian": {"k": tile["k"], "ms_per_step": tuned_ms, "value": n_p / (tuned_ms / 1e3),
+                                 "what": "the same full Hessian with the tuner's launch size"},
     }
     # per-phase roofline fractions: each phase's algorithmic bytes (k directions)
     # over its mean time per workgroup
