@@ -304,10 +304,10 @@ class Oracle:
 class Solved:
     """An operating point: Newton solution, factorised G_x, lambda, d2 l."""
 
-    def __init__(self, orc: Oracle, p=None, tol=1e-13, max_iter=30):
+    def __init__(self, orc: Oracle, p=None, tol=1e-13, max_iter=30, x0=None):
         self.o = orc
         self.p = orc.p0() if p is None else np.asarray(p, dtype=np.float64)
-        self.x, self.hist, self.ok = orc.newton(self.p, tol=tol, max_iter=max_iter)
+        self.x, self.hist, self.ok = orc.newton(self.p, tol=tol, max_iter=max_iter, x0=x0)
         if not self.ok:
             raise RuntimeError(f"Newton did not converge: {self.hist}")
         self.Gx, self.Gp = orc.jacobians(self.x, self.p)
