@@ -309,6 +309,57 @@ rh_status rh_refinement_report(const rh_network *net, int32_t n, double *berr_z,
 rh_status rh_network_device_bytes(const rh_network *net, rh_precision prec, int64_t *resident,
                                   int64_t *scratch_per_direction);
 
+/* ---- Real-time tracking (Sec. 6.3) ---------------------------------------
+ *
+ * Reduced gradient grad F = grad_p f + G_p^T lambda (eq. (reduced_gradient))
+ * of the solved operating point into the device buffer dgrad (n_p doubles),
+ * enqueued on hip_stream.  lambda and grad_p f are resident since the solve.
+ * RH_ESTATE if the network is not solved. */
+rh_status rh_reduced_gradient_device(rh_network *net, void *dgrad, void *hip_stream);
+
+/* Dense symmetric positive definite solve on the device, FP64: A = L L^T from
+ * the lower triangle of the column-major n x n matrix dA (leading dimension
+ * lda >= n; the strict upper triangle is neither read nor written), the lower
+ * triangle then holding L; then L L^T X = B for the nrhs columns of dB
+ * (ldb >= n), overwritten by X.  This is the dense system of eq. (qp_rto),
+ * factorised by Cholesky as in Sec. 6.3; the trailing updates run on FP64
+ * matrix cores.  Enqueued on hip_stream, then the stream is synchronised.  A
+ * leading minor that is not positive definite gives RH_ESINGULAR with
+ * *failed_col (may be NULL) = its last column (0-based; -1 on success); dA
+ * and dB are then undefined.  The caller owns both buffers. */
+rh_status rh_cholesky_solve_device(rh_context *ctx, int32_t n, void *dA, int64_t lda, void *dB, int64_t ldb,
+                                   int32_t nrhs, void *hip_stream, int32_t *failed_col);
+
+typedef struct {
+  double tau;          /* shift on the diagonal of H_t: 0 is the step of eq. (qp_rto) */
+  int32_t tries;       /* Cholesky factorisations attempted */
+  int32_t pad;
+  double grad_inf;     /* ||g_t||_inf */
+  double step_inf;     /* ||d_t||_inf before the projection */
+  double ms_gradient;  /* device time of g_t */
+  double ms_hessian;   /* device time of H_t (Algorithm 2 over the identity) */
+  double ms_solve;     /* device time of the factorisations and the two solves */
+} rh_tracking_info;
+
+/* One update of the real-time tracking algorithm (Sec. 6.3) on a network
+ * solved at the current loads w_t and control p_t.  Step 1: g_t and H_t into
+ * device workspace owned by the network (H_t in blocks of k_block directions,
+ * 0 = the tuned launch size, FP64).  Step 2: (H_t + tau I) d_t = -g_t by the
+ * dense Cholesky factorisation on the device, tau = shift (>= 0; 0 is the
+ * paper's step) when that factorisation succeeds, else the first success of
+ * tau_0 = -min_i H_ii + beta, tau <- max(2 tau, beta), beta = 1e-3 max_i |H_ii|
+ * (Cholesky with an added multiple of the identity, Nocedal and Wright,
+ * Numerical Optimization, Algorithm 3.3).  Then the network's parameters
+ * become p_t + d_t clipped to |p_{t+1} - p_t| <= ramp, then to lo <= p <= hi
+ * (each an n_p array or NULL), the next power-flow solve starts from the
+ * current state, and the network is no longer solved (set the next loads and
+ * solve again).  dd (device, n_p doubles, may be NULL) receives d_t on
+ * hip_stream.  Synchronises the stream (the shift and d_t are read back);
+ * info (may be NULL) receives the figures.  RH_ESTATE if not solved,
+ * RH_ESINGULAR if no shift succeeds, RH_ENOCONV on non-finite values. */
+rh_status rh_tracking_step_device(rh_network *net, int32_t k_block, double shift, const double *lo, const double *hi,
+                                  const double *ramp, void *dd, void *hip_stream, rh_tracking_info *info);
+
 /* Figures of the network; waits for the timed launches since the previous
  * report, sums their durations, then starts a new timing window. */
 rh_status rh_last_report(const rh_network *net, rh_report *out);

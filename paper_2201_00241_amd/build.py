@@ -12,7 +12,7 @@ OUT = HERE / "librh.so"
 BUILD = HERE.parent / "_build"
 ROCM = Path(os.environ.get("ROCM_PATH", "/opt/rocm"))
 HOST_SOURCES = ["network.cpp", "sparse_lu.cpp", "api.cpp", "tune.cpp"]
-DEVICE_SOURCES = ["device.hip", "newton.hip"]
+DEVICE_SOURCES = ["device.hip", "newton.hip", "dense.hip", "track.hip"]
 # Packed FP32 instructions are disabled for all device code.
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

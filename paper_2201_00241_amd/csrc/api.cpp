@@ -56,6 +56,39 @@ void invalidate(Network &n) {
 
 }  // namespace
 
+namespace rh {
+rh_status reduced_hessian_into(Network &n, double *H, int64_t ldh, int32_t k_block, rh_precision prec,
+                               void *hip_stream, std::string &err) {
+  const int32_t n_p = n.n_p;
+  rh_status s = RH_OK;
+  int32_t k = k_block > n_p ? n_p : k_block;
+  int32_t group = 1;
+  if (k_block == 0) {
+    // the tuned shape: its k is the launch size
+    rh_tile &t = n.tile[prec == RH_FP64 ? 0 : 1];
+    if (t.k == 0) {
+      rh_tile tt{};
+      if ((s = autotune(n, prec, 0, tt, err)) != RH_OK) return s;
+    }
+    k = std::min(t.k, n_p);
+  } else {
+    // consecutive blocks share a launch when one block leaves CUs idle at
+    // the directions per workgroup the network allows (a direction's product
+    // does not depend on the launch it runs in)
+    const int32_t want = device_launch_dirs(n, prec);
+    group = std::max(1, std::min((want + k - 1) / k, (n_p + k - 1) / k));
+  }
+  n.report.last_k = k;
+  for (int32_t j0 = 0; j0 < n_p; j0 += group * k) {
+    const int32_t kb = std::min(group * k, n_p - j0);
+    s = device_hvp(n, kb, nullptr, 0, H + (int64_t)j0 * ldh, ldh, j0, prec, hip_stream, err);
+    if (s != RH_OK) return s;
+  }
+  if (prec == RH_FP32_REFINED) n.refined_cols = n_p;
+  return RH_OK;
+}
+}  // namespace rh
+
 extern "C" {
 
 const char *rh_status_string(rh_status s) {
@@ -141,6 +174,7 @@ rh_status rh_network_create(rh_context *ctx, const rh_network_desc *desc, rh_net
 rh_status rh_network_destroy(rh_network *net) {
   if (!net) return RH_OK;
   device_newton_free(net->n);
+  device_track_free(net->n);
   device_free(net->n);
   delete net;
   return RH_OK;
@@ -363,6 +397,7 @@ rh_status rh_get_tile(const rh_network *net, rh_precision prec, rh_tile *out) {
   return RH_OK;
 }
 
+
 rh_status rh_reduced_hessian_device(rh_network *net, void *dH, int64_t ldh, int32_t k_block,
                                     rh_precision prec, void *hip_stream) {
   GUARD_BEGIN
@@ -373,31 +408,8 @@ rh_status rh_reduced_hessian_device(rh_network *net, void *dH, int64_t ldh, int3
   const int32_t n_p = net->n.n_p;
   if (!dH || ldh < n_p || k_block < 0) return fail(RH_EINVAL, "bad Hessian arguments");
   std::string err;
-  double *H = static_cast<double *>(dH);
-  int32_t k = k_block > n_p ? n_p : k_block;
-  int32_t group = 1;
-  if (k_block == 0) {
-    // the tuned shape: its k is the launch size
-    rh_tile &t = net->n.tile[prec == RH_FP64 ? 0 : 1];
-    if (t.k == 0) {
-      rh_tile tt{};
-      if ((s = autotune(net->n, prec, 0, tt, err)) != RH_OK) return fail(s, err);
-    }
-    k = std::min(t.k, n_p);
-  } else {
-    // consecutive blocks share a launch when one block leaves CUs idle at
-    // the directions per workgroup the network allows (a direction's product
-    // does not depend on the launch it runs in)
-    const int32_t want = device_launch_dirs(net->n, prec);
-    group = std::max(1, std::min((want + k - 1) / k, (n_p + k - 1) / k));
-  }
-  net->n.report.last_k = k;
-  for (int32_t j0 = 0; j0 < n_p; j0 += group * k) {
-    const int32_t kb = std::min(group * k, n_p - j0);
-    s = device_hvp(net->n, kb, nullptr, 0, H + (int64_t)j0 * ldh, ldh, j0, prec, hip_stream, err);
-    if (s != RH_OK) return fail(s, err);
-  }
-  if (prec == RH_FP32_REFINED) net->n.refined_cols = n_p;
+  s = reduced_hessian_into(net->n, static_cast<double *>(dH), ldh, k_block, prec, hip_stream, err);
+  if (s != RH_OK) return fail(s, err);
   return RH_OK;
   GUARD_END
 }
@@ -457,6 +469,61 @@ rh_status rh_reduced_hessian(rh_network *net, double *H, int64_t ldh, int32_t k_
                          n_p, 0, err);
   device_release(dH);
   if (s != RH_OK) return fail(s, err);
+  return RH_OK;
+  GUARD_END
+}
+
+rh_status rh_reduced_gradient_device(rh_network *net, void *dgrad, void *hip_stream) {
+  GUARD_BEGIN
+  rh_status s = need_solved(net);
+  if (s != RH_OK) return s;
+  if ((s = need_device(net)) != RH_OK) return s;
+  if (!dgrad) return fail(RH_EINVAL, "null gradient buffer");
+  std::string err;
+  if ((s = device_reduced_gradient(net->n, static_cast<double *>(dgrad), hip_stream, err)) != RH_OK)
+    return fail(s, err);
+  return RH_OK;
+  GUARD_END
+}
+
+rh_status rh_cholesky_solve_device(rh_context *ctx, int32_t n, void *dA, int64_t lda, void *dB, int64_t ldb,
+                                   int32_t nrhs, void *hip_stream, int32_t *failed_col) {
+  GUARD_BEGIN
+  if (failed_col) *failed_col = -1;
+  if (!ctx) return fail(RH_EINVAL, "null context");
+  if (ctx->c.device < 0) return fail(RH_EDEVICE, "host-only context");
+  if (n < 0 || nrhs < 0 || lda < std::max(1, n) || ldb < std::max(1, n)) return fail(RH_EINVAL, "bad dimensions");
+  if (n > 0 && (!dA || (nrhs > 0 && !dB))) return fail(RH_EINVAL, "null buffer");
+  if (n == 0) return RH_OK;
+  std::string err;
+  int32_t bad = -1;
+  rh_status s = dense_spd_solve(ctx->c.device, n, static_cast<double *>(dA), lda, static_cast<double *>(dB), ldb,
+                                nrhs, hip_stream, bad, err);
+  if (s != RH_OK) return fail(s, err);
+  if (failed_col) *failed_col = bad;
+  if (bad >= 0) return fail(RH_ESINGULAR, "leading minor " + std::to_string(bad + 1) + " is not positive definite");
+  return RH_OK;
+  GUARD_END
+}
+
+rh_status rh_tracking_step_device(rh_network *net, int32_t k_block, double shift, const double *lo, const double *hi,
+                                  const double *ramp, void *dd, void *hip_stream, rh_tracking_info *info) {
+  GUARD_BEGIN
+  rh_status s = need_solved(net);
+  if (s != RH_OK) return s;
+  if ((s = need_device(net)) != RH_OK) return s;
+  const int32_t n_p = net->n.n_p;
+  if (k_block < 0 || !(shift >= 0.0) || !std::isfinite(shift)) return fail(RH_EINVAL, "bad k_block or shift");
+  if ((lo && !finite_n(lo, n_p)) || (hi && !finite_n(hi, n_p)) || (ramp && !finite_n(ramp, n_p)))
+    return fail(RH_EINVAL, "NaN or Inf in bounds or ramp limits");
+  for (int32_t q = 0; q < n_p; ++q)
+    if ((lo && hi && lo[q] > hi[q]) || (ramp && ramp[q] < 0.0)) return fail(RH_EINVAL, "empty bounds or negative ramp");
+  std::string err;
+  rh_tracking_info r{};
+  if ((s = tracking_step(net->n, k_block, shift, lo, hi, ramp, static_cast<double *>(dd), hip_stream, r, err)) !=
+      RH_OK)
+    return fail(s, err);
+  if (info) *info = r;
   return RH_OK;
   GUARD_END
 }

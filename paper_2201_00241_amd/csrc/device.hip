@@ -150,6 +150,9 @@ struct NetDesc {
   // 2 c2 of the generator whose output is parameter q; NaN where parameter q
   // is a voltage magnitude (its Y_p comes from the projection)
   const double *p_c2x2;
+  // first-order adjoint lambda (permuted x order) and grad_p f at the
+  // operating point: the reduced gradient is grad_p f + G_p^T lambda
+  const double *lam, *fp;
   // G_x and G_x^T in permuted numbering (residuals of the refined mode)
   EllMat gx, gxt;
 };
@@ -2118,14 +2121,19 @@ rh_status device_upload(Network &net, std::string &err) {
     }
     std::vector<double> c2(net.n_p, std::numeric_limits<double>::quiet_NaN());
     for (int32_t b : net.pv) c2[net.pg_p[b]] = 2.0 * net.c2[net.gen_of_bus[b]];
+    std::vector<double> lam_p(net.n_x);
+    for (int32_t ip = 0; ip < net.n_x; ++ip) lam_p[ip] = net.lam[lu.perm[ip]];
     Blob bl;
     const int64_t o_ptr = bl.add(tptr), o_col = bl.add(tcol), o_val = bl.add(tval), o_c2 = bl.add(c2);
+    const int64_t o_lam = bl.add(lam_p), o_fp = bl.add(net.fp);
     const char *base = nullptr;
     UP(bl.h, base);
     nd.gpt_ptr = at_off<int32_t>(base, o_ptr);
     nd.gpt_col = at_off<int32_t>(base, o_col);
     nd.gpt_val = at_off<double>(base, o_val);
     nd.p_c2x2 = at_off<double>(base, o_c2);
+    nd.lam = at_off<double>(base, o_lam);
+    nd.fp = at_off<double>(base, o_fp);
   }
   // tangent sources per bus in permuted numbering: theta from X[thx] (-1 at
   // the reference bus); v from X[vs] at PQ buses, else from W[-vs - 1]
@@ -2236,6 +2244,32 @@ rh_status device_upload(Network &net, std::string &err) {
     dn->nd_dev = static_cast<NetDesc *>(p);
   }
   HIP_TRY(hipDeviceSynchronize());
+  return RH_OK;
+}
+
+namespace {
+// grad F = grad_p f + G_p^T lambda (eq. (reduced_gradient)), one parameter
+// per thread over the rows of G_p^T.
+__global__ __launch_bounds__(256) void reduced_gradient_kernel(const NetDesc *nd, double *grad) {
+  const int32_t q = blockIdx.x * 256 + threadIdx.x;
+  if (q >= nd->n_p) return;
+  double acc = nd->fp[q];
+  for (int32_t e = nd->gpt_ptr[q]; e < nd->gpt_ptr[q + 1]; ++e) acc = fma(nd->gpt_val[e], nd->lam[nd->gpt_col[e]], acc);
+  grad[q] = acc;
+}
+}  // namespace
+
+rh_status device_reduced_gradient(Network &net, double *dgrad, void *stream, std::string &err) {
+  if (!net.dev) {
+    err = "the operating point is not on the device";
+    return RH_ESTATE;
+  }
+  HIP_TRY(hipSetDevice(net.ctx->device));
+  const int32_t n_p = net.n_p;
+  if (n_p > 0)
+    hipLaunchKernelGGL(reduced_gradient_kernel, dim3((n_p + 255) / 256), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), (const NetDesc *)net.dev->nd_dev, dgrad);
+  HIP_TRY(hipGetLastError());
   return RH_OK;
 }
 

@@ -594,6 +594,7 @@ rh_status network_accept(Network &net, const std::vector<double> &x, int32_t it,
   // first-order adjoint: G_x^T lambda = -grad_x f^T
   std::vector<double> fx, fp;
   cost_gradient(net, th, v, fx, fp);
+  net.fp = fp;
   net.lam.resize(net.n_x);
   for (int32_t i = 0; i < net.n_x; ++i) net.lam[i] = -fx[i];
   lu_solve_t(net.lu, net.lam);

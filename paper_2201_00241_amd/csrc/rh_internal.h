@@ -142,6 +142,7 @@ struct DeviceNet;  // defined by the device translation unit
 struct DeviceCtx;  // likewise: a context's resources for batched launches
 struct DeviceBatch;  // likewise: a batched launch recorded as a graph
 struct DevNewton;    // the device Newton's arrays (newton.hip)
+struct DevTrack;     // the tracking update's device workspace (track.hip)
 
 struct Context {
   int32_t device = -1;  // -1: host only
@@ -185,6 +186,7 @@ struct Network {
   LuPlan lu;
   // ---- state
   std::vector<double> p, x, lam;
+  std::vector<double> fp;  // grad_p f at the operating point
   std::vector<double> x0;  // Newton start (empty: flat start)
   bool solved = false;
   int32_t newton_iters = 0;
@@ -194,6 +196,7 @@ struct Network {
   rh_report report{};
   DeviceNet *dev = nullptr;
   DevNewton *dnewton = nullptr;  // device Newton arrays (rh_solve_powerflow_device)
+  DevTrack *dtrack = nullptr;    // tracking workspace (rh_tracking_step_device)
   uint64_t dev_gen = 0;  // device uploads so far (a recorded launch checks it is unchanged)
   // launch shape per precision (0 FP64, 1 refined) chosen by the tuner
   // (tune.cpp); k == 0: not chosen, the library's defaults apply
@@ -241,6 +244,31 @@ struct NewtonResult {
 };
 rh_status device_newton(Network &net, double tol, int32_t max_iter, NewtonResult &res, std::string &err);
 void device_newton_free(Network &net);
+
+// ---- dense FP64 Cholesky (dense.hip) and the tracking update (track.hip)
+// A = L L^T in place on the lower triangle (column-major); *dinfo = 0, or
+// the first failed column + 1.  Enqueued on `stream`.
+rh_status dense_cholesky(int32_t n, double *A, int64_t lda, int32_t *dinfo, void *stream, std::string &err);
+// L L^T X = B in place for nrhs columns (nothing if *dinfo != 0).
+rh_status dense_solve(int32_t n, const double *L, int64_t ldl, double *B, int64_t ldb, int32_t nrhs,
+                      const int32_t *dinfo, void *stream, std::string &err);
+// F = lower triangle of A with tau added on the diagonal.
+rh_status dense_shift_copy(int32_t n, const double *A, int64_t lda, double *F, int64_t ldf, double tau, void *stream,
+                           std::string &err);
+rh_status dense_diagonal(int32_t n, const double *A, int64_t lda, double *out, void *stream, std::string &err);
+rh_status dense_negate(int32_t n, const double *a, double *b, void *stream, std::string &err);
+// Factorise and solve, synchronously; failed_col = -1 or the failed column.
+rh_status dense_spd_solve(int device, int32_t n, double *A, int64_t lda, double *B, int64_t ldb, int32_t nrhs,
+                          void *stream, int32_t &failed_col, std::string &err);
+rh_status tracking_step(Network &net, int32_t k_block, double shift, const double *lo, const double *hi,
+                        const double *ramp, double *dd, void *stream, rh_tracking_info &out, std::string &err);
+void device_track_free(Network &net);
+// grad F = grad_p f + G_p^T lambda of the uploaded operating point (device.hip).
+rh_status device_reduced_gradient(Network &net, double *dgrad, void *stream, std::string &err);
+// The full reduced Hessian into device memory in blocks of k_block
+// directions (0: the tuned launch size) (api.cpp).
+rh_status reduced_hessian_into(Network &n, double *H, int64_t ldh, int32_t k_block, rh_precision prec,
+                               void *hip_stream, std::string &err);
 void flows_inject(const Network &net, const std::vector<double> &th, const std::vector<double> &v,
                   std::vector<double> &P, std::vector<double> &Q);
 void unpack_state(const Network &net, const std::vector<double> &x, const std::vector<double> &p,

@@ -71,6 +71,18 @@ class rh_report(ctypes.Structure):
         return d
 
 
+class rh_tracking_info(ctypes.Structure):
+    _fields_ = [
+        ("tau", ctypes.c_double), ("tries", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("grad_inf", ctypes.c_double), ("step_inf", ctypes.c_double),
+        ("ms_gradient", ctypes.c_double), ("ms_hessian", ctypes.c_double),
+        ("ms_solve", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
 class RhError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(f"librh status {status}: {msg}")
@@ -143,6 +155,13 @@ _SIGS = {
     "rh_refinement_report": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _f64p, _i32p, _f64p,
                                             _i32p]),
     "rh_context_report": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(rh_report)]),
+    "rh_reduced_gradient_device": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "rh_cholesky_solve_device": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                                ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                                ctypes.c_int32, ctypes.c_void_p, _i32p]),
+    "rh_tracking_step_device": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_double,
+                                               _f64p, _f64p, _f64p, ctypes.c_void_p, ctypes.c_void_p,
+                                               ctypes.POINTER(rh_tracking_info)]),
     "rh_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "rh_last_error": (ctypes.c_char_p, []),
 }
@@ -438,6 +457,33 @@ def rh_refinement_report(net, n: int) -> dict:
     return {"berr_z": bz, "steps_z": kz, "berr_psi": bp, "steps_psi": kp}
 
 
+def rh_reduced_gradient_device(net, dgrad_ptr, stream=None) -> None:
+    _check(load().rh_reduced_gradient_device(net, dgrad_ptr, stream))
+
+
+def rh_cholesky_solve_device(ctx, n, dA_ptr, lda, dB_ptr, ldb, nrhs, stream=None) -> int:
+    """Returns -1, or raises RhError (RH_ESINGULAR) whose .failed_col is the
+    column whose leading minor is not positive definite."""
+    bad = ctypes.c_int32(-1)
+    s = load().rh_cholesky_solve_device(ctx, int(n), dA_ptr, int(lda), dB_ptr, int(ldb), int(nrhs),
+                                        stream, ctypes.byref(bad))
+    if s != RH_OK:
+        e = RhError(s, _lib.rh_last_error().decode())
+        e.failed_col = bad.value
+        raise e
+    return bad.value
+
+
+def rh_tracking_step_device(net, k_block=0, shift=0.0, lo=None, hi=None, ramp=None, dd_ptr=None,
+                            stream=None) -> dict:
+    arrs = [None if a is None else _f64(a) for a in (lo, hi, ramp)]
+    ptrs = [None if a is None else _p(a, _f64p) for a in arrs]
+    info = rh_tracking_info()
+    _check(load().rh_tracking_step_device(net, int(k_block), float(shift), *ptrs, dd_ptr, stream,
+                                          ctypes.byref(info)))
+    return info.as_dict()
+
+
 def rh_status_string(s: int) -> str:
     return load().rh_status_string(int(s)).decode()
 
@@ -463,6 +509,14 @@ class Context:
 
     def report(self):
         return rh_context_report(self.h)
+
+    def cholesky_solve_device(self, A, B, stream=None):
+        """A: torch float64 CUDA tensor (n, n) whose row j is column j of the
+        matrix (only entries A[j, i] with i >= j are read; they receive L);
+        B: (nrhs, n), row q a right-hand side, overwritten by the solution."""
+        n = A.shape[0]
+        return rh_cholesky_solve_device(self.h, n, A.data_ptr(), _ld(A), B.data_ptr(), _ld(B),
+                                        B.shape[0], stream)
 
     def hvp_batch_device(self, nets, Ws, HWs, stream=None, prec=RH_FP64):
         """nets: Network objects; Ws/HWs: torch float64 CUDA tensors (k_i, n_p_i)."""
@@ -568,3 +622,14 @@ class Network:
     def reduced_hessian_device(self, H, k_block=0, stream=None, prec=RH_FP64):
         """H: torch float64 CUDA tensor (n_p, n_p); row j receives column j of the Hessian."""
         rh_reduced_hessian_device(self.h, H.data_ptr(), _ld(H), k_block, prec, stream)
+
+    def reduced_gradient_device(self, g, stream=None):
+        """g: torch float64 CUDA tensor of n_p values."""
+        rh_reduced_gradient_device(self.h, g.data_ptr(), stream)
+
+    def tracking_step_device(self, k_block=0, shift=0.0, lo=None, hi=None, ramp=None, d=None,
+                             stream=None):
+        """One tracking update; d (optional torch float64 CUDA tensor, n_p)
+        receives the step.  Returns the rh_tracking_info figures."""
+        return rh_tracking_step_device(self.h, k_block, shift, lo, hi, ramp,
+                                       None if d is None else d.data_ptr(), stream)

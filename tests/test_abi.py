@@ -169,3 +169,14 @@ def test_device_newton_needs_a_device(ctx):
     with pytest.raises(rh.RhError) as ei:
         net.solve_device()
     assert ei.value.status == rh.RH_EDEVICE
+
+
+def test_tracking_and_dense_solve_need_a_device(ctx):
+    net = rh.Network(ctx, gridgen.config_grid("c0", 0))
+    assert _status(net.tracking_step_device) == rh.RH_ESTATE  # before a solve
+    net.solve()
+    assert _status(net.tracking_step_device) == rh.RH_EDEVICE
+    assert _status(rh.rh_reduced_gradient_device, net.h, None) == rh.RH_EDEVICE
+    with pytest.raises(rh.RhError) as ei:
+        rh.rh_cholesky_solve_device(ctx.h, 4, None, 4, None, 4, 1)
+    assert ei.value.status == rh.RH_EDEVICE and ei.value.failed_col == -1
