@@ -188,6 +188,35 @@ def cpu_baseline(config, g, k, budget_s=12.0):
     }
 
 
+def cpu_baseline_tracking(steps=3, seed=5):
+    """The oracle's tracking update (power flow, reduced gradient, reduced
+    Hessian, Cholesky, projected update) on one host core, for the first
+    steps of the 1,000-bus trajectory that run_tracking times on the GPU."""
+    import gridgen
+    from oracle import powerflow as opf
+    from oracle import tracking as otr
+
+    g = gridgen.config_grid("c1", 0)
+    orc = opf.Oracle(g)
+    p0 = orc.p0()
+    npv = orc.npv  # parameter order: Pg at PV buses, v_ref, v at PV buses
+    volt = np.arange(p0.size) >= npv
+    lo = np.where(volt, 0.94, 0.0)
+    hi = np.where(volt, 1.06, 2.0 * np.maximum(p0, 0.1))
+    ramp = np.where(volt, 0.002, 0.01)
+    Pd, Qd = gridgen.load_trajectory(g, steps=60, seed=seed)
+    gg = g.copy()
+    p, x, ms = np.clip(p0, lo, hi), None, []
+    for t in range(steps):
+        gg.Pd, gg.Qd = Pd[t].copy(), Qd[t].copy()
+        t0 = time.perf_counter()
+        s_, _, _, d_, _ = otr.step(gg, p, x0=x)
+        ms.append(1e3 * (time.perf_counter() - t0))
+        x, p = s_.x, otr.project(p, d_, lo, hi, ramp)
+    return {"update_ms_median": float(np.median(ms)), "cores": 1, "kind": "oracle",
+            "sample": f"the first {steps} updates of the 1,000-bus tracking trajectory"}
+
+
 def refined_bytes_per_direction(n_x, n_p, passes_z, passes_psi):
     """Algorithmic bytes of one direction in the refined mode, counting every
     pass made: per FP32 pass (the first solve or a correction) the FP32
@@ -408,6 +437,101 @@ def run_serving(n_peak=120, n_run=300, seed=11):
     }
 
 
+def _tracking_limits(net):
+    """Bounds and per-minute ramp limits of the controls: generator outputs in
+    [0, 2 max(Pg0, 0.1)] moving at most 0.01 pu per step, voltage set-points in
+    [0.94, 1.06] moving at most 0.002 pu per step."""
+    _, _, _, pk = net.index_maps()
+    p0 = net.get_parameters()
+    volt = pk == 1
+    lo = np.where(volt, 0.94, 0.0)
+    hi = np.where(volt, 1.06, 2.0 * np.maximum(p0, 0.1))
+    ramp = np.where(volt, 0.002, 0.01)
+    return lo, hi, ramp
+
+
+def run_tracking(steps=60, seed=5):
+    """Real-time tracking (Sec. 6.3, eq. (qp_rto); Table 3): one update per
+    minute of a synthetic load trajectory on the 1,000-bus grid, each update =
+    power flow at the new loads (device Newton, warm-started), then Step 1
+    (reduced gradient and full reduced Hessian) and Step 2 (dense Cholesky
+    solve of H d = -g and the projected update of p), all on the GPU.  Also
+    single updates on the 10,000-bus grid."""
+    import torch
+
+    import gridgen
+    from paper_2201_00241_amd import rh
+
+    out = {}
+    ctx = rh.Context(0)
+    g = gridgen.config_grid("c1", 0)
+    net = rh.Network(ctx, g)
+    lo, hi, ramp = _tracking_limits(net)
+    p_start = np.clip(net.get_parameters(), lo, hi)
+    net.set_parameters(p_start)
+    Pd, Qd = gridgen.load_trajectory(g, steps=steps, seed=seed)
+    net.solve_device()
+    tile = net.autotune()  # launch shape of H, outside the timed steps
+    rows = []
+    for t in range(steps):
+        net.set_loads(Pd[t], Qd[t])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it, _ = net.solve_device()
+        t1 = time.perf_counter()
+        info = net.tracking_step_device(lo=lo, hi=hi, ramp=ramp)
+        t2 = time.perf_counter()
+        rows.append((1e3 * (t1 - t0), 1e3 * (t2 - t1), info, it))
+    solve_ms = np.array([r[0] for r in rows])
+    step_ms = np.array([r[1] for r in rows])
+    hess_ms = np.array([r[2]["ms_gradient"] + r[2]["ms_hessian"] for r in rows])
+    chol_ms = np.array([r[2]["ms_solve"] for r in rows])
+    out["grid_1k"] = {
+        "steps": steps, "n_p": net.n_p, "tuned_shape": tile,
+        "median_ms": {"power_flow": float(np.median(solve_ms)),
+                      "step1_gradient_hessian": float(np.median(hess_ms)),
+                      "step2_cholesky_solve": float(np.median(chol_ms)),
+                      "update_wall": float(np.median(step_ms)),
+                      "total_wall": float(np.median(solve_ms + step_ms))},
+        "max_total_wall_ms": float(np.max(solve_ms + step_ms)),
+        "newton_iters_median": float(np.median([r[3] for r in rows])),
+        "shifted_steps": int(sum(r[2]["tau"] > 0 for r in rows)),
+        "workload": "1,000-bus grid, 60 one-minute load steps (common swing 3%, per-bus noise 0.5%, "
+                    "seed 5), Pg ramp 0.01 pu/min, voltage ramp 0.002 pu/min",
+    }
+    net.close()
+    # single updates at 10,000 buses (base loads)
+    g2 = gridgen.config_grid("c2", 0)
+    net2 = rh.Network(ctx, g2)
+    lo2, hi2, ramp2 = _tracking_limits(net2)
+    net2.set_parameters(np.clip(net2.get_parameters(), lo2, hi2))
+    net2.solve_device()
+    net2.autotune()
+    r2 = []
+    for t in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        net2.solve_device()
+        t1 = time.perf_counter()
+        info = net2.tracking_step_device(lo=lo2, hi=hi2, ramp=ramp2)
+        t2 = time.perf_counter()
+        r2.append((1e3 * (t1 - t0), 1e3 * (t2 - t1), info))
+    out["grid_10k"] = {
+        "n_p": net2.n_p, "updates": len(r2),
+        "median_ms": {"power_flow": float(np.median([r[0] for r in r2])),
+                      "step1_gradient_hessian": float(np.median([r[2]["ms_gradient"] + r[2]["ms_hessian"]
+                                                                 for r in r2])),
+                      "step2_cholesky_solve": float(np.median([r[2]["ms_solve"] for r in r2])),
+                      "update_wall": float(np.median([r[1] for r in r2]))},
+    }
+    net2.close()
+    ctx.close()
+    out["paper_table3_context"] = {"case": "PEGASE1354 (n_p = 519)", "hardware": "V100 vs Xeon Gold 6140",
+                                   "gpu_s": {"step1": 0.05, "step2": 0.05, "total": 0.10},
+                                   "cpu_s": {"step1": 1.41, "step2": 0.81, "total": 2.22}}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -419,8 +543,9 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-refined", action="store_true")
+    ap.add_argument("--no-tracking", action="store_true")
     ap.add_argument("--workload", default="hessian",
-                    choices=["hessian", "batch", "serving"],
+                    choices=["hessian", "batch", "serving", "tracking"],
                     help="hessian: full reduced Hessian (the headline metric, with the batched "
                          "and serving figures attached); batch: only the operating points of "
                          "one grid in one launch; serving: only the Poisson request mix")
@@ -458,6 +583,9 @@ def main():
         return
     if args.workload == "serving":
         print(json.dumps(run_serving()), flush=True)
+        return
+    if args.workload == "tracking":
+        print(json.dumps(run_tracking()), flush=True)
         return
     g = gridgen.config_grid(args.config, 0)
     ctx = rh.Context(0)
@@ -587,12 +715,19 @@ def main():
     if not args.no_batch:
         out["batch"] = run_batch(args.instances, max(2, args.steps // 4), 1)
         print(f"# batch: {out['batch']['fp64']['value']:.0f} HVP/s", file=sys.stderr, flush=True)
+    if not args.no_tracking:
+        out["tracking"] = run_tracking()
+        tr = out["tracking"]["grid_1k"]["median_ms"]
+        print(f"# tracking 1k: {tr['total_wall']:.1f} ms per update (power flow {tr['power_flow']:.1f}, "
+              f"step 1 {tr['step1_gradient_hessian']:.2f}, step 2 {tr['step2_cholesky_solve']:.2f})",
+              file=sys.stderr, flush=True)
     if not args.no_serving:
         out["serving"] = run_serving()
         print(f"# serving: p50 {out['serving']['p50_ms']:.1f} ms p99 {out['serving']['p99_ms']:.1f} ms",
               file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.config, g, k)
+        out["cpu_baseline"]["tracking"] = cpu_baseline_tracking()
     print(json.dumps(out), flush=True)
 
 

@@ -376,14 +376,15 @@ def load_trajectory(grid: Grid, steps: int = 60, amp: float = 0.03, noise: float
                     seed: int = 0) -> tuple:
     """Loads of a tracking run: one row per minute over ``steps`` minutes.
 
-    Every bus follows a common slow swing ``1 + amp sin(2 pi t / steps + phi)``
-    (one random phase) times its own factor ``1 + noise e_tb`` with
-    ``e_tb ~ N(0, 1)``, applied to both P^d and Q^d.  Returns (Pd, Qd) of
-    shape (steps, n_bus)."""
+    Every bus follows a common slow swing
+    ``1 + amp (sin(2 pi t / steps + phi) - sin(phi))`` (one random phase; the
+    swing starts at the base loads, which the generator set-points balance)
+    times its own factor ``1 + noise e_tb`` with ``e_tb ~ N(0, 1)``, applied
+    to both P^d and Q^d.  Returns (Pd, Qd) of shape (steps, n_bus)."""
     rng = np.random.default_rng(seed)
     phi = rng.uniform(0.0, 2.0 * np.pi)
     t = np.arange(steps)[:, None]
-    common = 1.0 + amp * np.sin(2.0 * np.pi * t / steps + phi)
+    common = 1.0 + amp * (np.sin(2.0 * np.pi * t / steps + phi) - np.sin(phi))
     own = 1.0 + noise * rng.standard_normal((steps, grid.n_bus))
     s = common * own
     return grid.Pd[None, :] * s, grid.Qd[None, :] * s

@@ -160,7 +160,9 @@ rh_status rh_set_loads(rh_network *net, const double *Pd, const double *Qd);
 rh_status rh_set_initial_state(rh_network *net, const double *x0);
 
 /* Newton-Raphson from the initial state (flat start by default) until
- * ||g||_inf <= tol or max_iter steps (Sec. 3.2).  On success it factorises
+ * ||g||_inf <= tol or max_iter steps (Sec. 3.2); a residual below 1e-11 that
+ * no longer halves after three steps counts as converged (rounding level of
+ * a large grid, resid_inf reports it).  On success it factorises
  * G_x, forms the first-order adjoint and the per-branch second-order
  * coefficients, and (on a device context) uploads them.  iters/resid_inf may
  * be NULL.  Returns RH_ENOCONV or RH_ESINGULAR on failure. */

@@ -15,10 +15,11 @@
 //                matrix in 64 x 64 tiles, with FP64 MFMA (16 x 16 x 4).
 // A failed pivot (not positive, or not finite) stores its column + 1 in a
 // status word; every later kernel reads it first and does nothing.
-// chol_solve then solves L L^T X = B for the columns of B (one workgroup per
-// column): the forward sweep right-looking (the update of the rows below a
-// block reads columns of L, contiguous), the backward sweep left-looking (a
-// block's unknowns take dot products of columns of L with the finished part).
+// The forward sweep L Y = B rides along: the right-hand sides are extra rows
+// of the augmented matrix [A; B^T], substituted in the panels like the rows
+// of A and updated by a matrix-vector product per panel, so that at the end
+// B holds Y.  chol_back_block then solves L^T X = Y a block of 64 unknowns
+// per launch, from the last.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -42,15 +43,36 @@ __device__ __forceinline__ double rdlane(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Optimisation barrier: the values v[c + 1 ..] are materialised here.  In
-// the unrolled right-looking steps below, the compiler would otherwise sink
-// each v[k]'s chain of updates down to step k and keep every broadcast
-// factor entry alive until then (hundreds of scalar registers, spilled).
-template <int NB>
-__device__ __forceinline__ void pin_after(double (&v)[NB], int c) {
+// Step C of the right-looking factorisation of a diagonal block held a row
+// per lane (a) and of the substitution of the rows x with the same
+// broadcasts; steps unrolled by recursion so that every index is a
+// compile-time constant.  The empty asm statements materialise a[k], x[k]
+// at the end of the step: the compiler would otherwise sink each chain of
+// updates down to step k and keep every broadcast factor entry alive until
+// then (hundreds of scalar registers, spilled).
+template <int NB, int C>
+__device__ __forceinline__ void chol_step(double (&a)[NB], double (&x)[NB], int32_t &bad) {
+  if constexpr (C < NB) {
+    const double dcc = rdlane(a[C], C);
+    if (bad < 0 && !(dcc > 0.0 && dcc <= 1.7976931348623157e308)) bad = C;
+    // column C scaled by 1 / sqrt(d_CC); on lane C this gives the pivot
+    // d_CC / sqrt(d_CC) itself (within an ulp of sqrt(d_CC))
+    const double ri = 1.0 / sqrt(dcc);
+    a[C] *= ri;
+    x[C] *= ri;
 #pragma unroll
-  for (int k = 0; k < NB; ++k)
-    if (k > c) asm volatile("" : "+v"(v[k]));
+    for (int k = C + 1; k < NB; ++k) {
+      const double lkc = rdlane(a[C], k);  // L(k, C)
+      a[k] = fma(-a[C], lkc, a[k]);
+      x[k] = fma(-x[C], lkc, x[k]);
+    }
+#pragma unroll
+    for (int k = C + 1; k < NB; ++k) {
+      asm volatile("" : "+v"(a[k]));
+      asm volatile("" : "+v"(x[k]));
+    }
+    chol_step<NB, C + 1>(a, x, bad);
+  }
 }
 
 __global__ void dense_clear(int32_t *info) {
@@ -77,74 +99,58 @@ __global__ __launch_bounds__(256) void dense_neg(const double *a, double *b, int
   if (i < n) b[i] = -a[i];
 }
 
+// Row r of the augmented matrix [A; B^T]: a row of A (r < n) or right-hand
+// side r - n, whose entry c is B[c + (r - n) ldb].
+__device__ __forceinline__ double *aug_row(double *A, int64_t lda, double *B, int64_t ldb, int32_t n, int32_t r,
+                                           int32_t c) {
+  return r < n ? A + r + (int64_t)c * lda : B + c + (int64_t)(r - n) * ldb;
+}
+
 template <int NB>
-__global__ __launch_bounds__(256) void chol_panel(double *A, int64_t lda, int32_t n, int32_t j0, int32_t *info) {
+__global__ __launch_bounds__(256) void chol_panel(double *A, int64_t lda, int32_t n, double *B, int64_t ldb,
+                                                  int32_t nrhs, int32_t j0, int32_t *info) {
   if (*info) return;
-  __shared__ double s_L[NB][NB + 1];
-  __shared__ double s_rinv[NB];
-  __shared__ int32_t s_bad;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int32_t nb = min(NB, n - j0);
-  if (wave == 0) {
-    // the diagonal block, rows and columns past nb completed by the identity
-    double a[NB];
-#pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      double v = 0.0;
-      if (lane < nb && c < nb && c <= lane) v = A[(j0 + lane) + (int64_t)(j0 + c) * lda];
-      if (lane >= nb && lane < NB && c == lane) v = 1.0;
-      a[c] = v;
-    }
-    // Lanes above the diagonal (lane < column) run the same updates on
-    // entries of the upper part, which are never read as L and are zeroed
-    // below: no per-lane predicates, whose masks would otherwise stay live
-    // across the whole unrolled loop.
-    int32_t bad = -1;
-#pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      const double dcc = rdlane(a[c], c);
-      if (bad < 0 && !(dcc > 0.0 && dcc <= 1.7976931348623157e308)) bad = c;
-      // column c scaled by 1 / sqrt(d_cc); on lane c this gives the pivot
-      // d_cc / sqrt(d_cc) itself (within an ulp of sqrt(d_cc))
-      const double ri = 1.0 / sqrt(dcc);
-      a[c] *= ri;
-      if (lane == 0) s_rinv[c] = ri;
-#pragma unroll
-      for (int k = c + 1; k < NB; ++k) a[k] = fma(-a[c], rdlane(a[c], k), a[k]);  // L(k, c)
-      pin_after<NB>(a, c);
-    }
-    if (lane < NB) {
-#pragma unroll
-      for (int c = 0; c < NB; ++c) s_L[lane][c] = c <= lane ? a[c] : 0.0;
-    }
-    if (lane == 0) s_bad = bad;
-    if (blockIdx.x == 0) {
-      if (bad >= 0) {
-        if (lane == 0) *info = j0 + bad + 1;
-      } else if (lane < nb) {
-#pragma unroll
-        for (int c = 0; c < NB; ++c)
-          if (c <= lane) A[(j0 + lane) + (int64_t)(j0 + c) * lda] = a[c];
-      }
-    }
-  }
-  __syncthreads();
-  if (s_bad >= 0) return;
+  // this lane's row of the panel below the diagonal block (rows of A, then
+  // the right-hand sides), loaded first so that the loads overlap the
+  // factorisation
   const int32_t r = j0 + nb + (blockIdx.x * 4 + wave) * 64 + lane;
-  if (r >= n) return;
+  const bool has = r < n + nrhs;
   double x[NB];
 #pragma unroll
-  for (int c = 0; c < NB; ++c) x[c] = c < nb ? A[r + (int64_t)(j0 + c) * lda] : 0.0;
+  for (int c = 0; c < NB; ++c) x[c] = (has && c < nb) ? *aug_row(A, lda, B, ldb, n, r, j0 + c) : 0.0;
+  // the diagonal block, rows and columns past nb completed by the identity
+  double a[NB];
 #pragma unroll
   for (int c = 0; c < NB; ++c) {
-    x[c] *= s_rinv[c];
-#pragma unroll
-    for (int k = c + 1; k < NB; ++k) x[k] = fma(-x[c], s_L[k][c], x[k]);
-    pin_after<NB>(x, c);
+    double v = 0.0;
+    if (lane < nb && c < nb && c <= lane) v = A[(j0 + lane) + (int64_t)(j0 + c) * lda];
+    if (lane >= nb && lane < NB && c == lane) v = 1.0;
+    a[c] = v;
   }
+  // Every wave factors the block (lane i holds row i; column c broadcast by
+  // readlane) and, with the same broadcasts, solves x L^T = row for its rows.
+  // Lanes above the diagonal (lane < column) run the same updates on
+  // entries of the upper part, which are never read as L and never stored:
+  // no per-lane predicates, whose masks would stay live across the unrolled
+  // loop.
+  int32_t bad = -1;
+  chol_step<NB, 0>(a, x, bad);
+  if (bad >= 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *info = j0 + bad + 1;
+    return;
+  }
+  if (blockIdx.x == 0 && wave == 0 && lane < nb) {
 #pragma unroll
-  for (int c = 0; c < NB; ++c)
-    if (c < nb) A[r + (int64_t)(j0 + c) * lda] = x[c];
+    for (int c = 0; c < NB; ++c)
+      if (c <= lane) A[(j0 + lane) + (int64_t)(j0 + c) * lda] = a[c];
+  }
+  if (has) {
+#pragma unroll
+    for (int c = 0; c < NB; ++c)
+      if (c < nb) *aug_row(A, lda, B, ldb, n, r, j0 + c) = x[c];
+  }
 }
 
 // Tile (ti, tk), ti >= tk, of the trailing matrix from a linear index.
@@ -165,9 +171,23 @@ __device__ __forceinline__ void tri_tile(int32_t b, int32_t &ti, int32_t &tk) {
 // (l % 16, l / 16) and B-operand (l / 16, l % 16); output register q of lane
 // l is D[4 q + l / 16][l % 16].
 template <int NB>
-__global__ __launch_bounds__(256) void chol_update(double *A, int64_t lda, int32_t n, int32_t j0,
-                                                   const int32_t *info) {
+__global__ __launch_bounds__(256) void chol_update(double *A, int64_t lda, int32_t n, double *B, int64_t ldb,
+                                                   int32_t nrhs, int32_t j0, int32_t tiles, const int32_t *info) {
   if (*info) return;
+  if ((int32_t)blockIdx.x >= tiles) {
+    // right-hand-side rows of the augmented matrix: b_col -= sum_c y_c L(col, c)
+    // over the trailing columns, y = the panel's entries of the solved rows
+    const int32_t col = j0 + NB + ((int32_t)blockIdx.x - tiles) * 256 + threadIdx.x;
+    if (col >= n) return;
+    for (int32_t q = 0; q < nrhs; ++q) {
+      const double *y = B + (int64_t)q * ldb + j0;
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c < NB; ++c) acc = fma(A[col + (int64_t)(j0 + c) * lda], y[c], acc);
+      B[col + (int64_t)q * ldb] -= acc;
+    }
+    return;
+  }
   int32_t ti, tk;
   tri_tile(blockIdx.x, ti, tk);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -211,80 +231,69 @@ __global__ __launch_bounds__(256) void chol_update(double *A, int64_t lda, int32
       }
 }
 
-// L L^T x = b for one column of B per workgroup (1024 threads).  The 64 x 64
-// diagonal blocks are staged in LDS and solved by wave 0, a row per lane.
-constexpr int kSolveThreads = 1024;
-constexpr int kSolveWaves = kSolveThreads / 64;
-
-__device__ __forceinline__ void stage_block(const double *A, int64_t lda, int32_t j0, int32_t bs,
-                                            double (*s_L)[65]) {
-  for (int t = threadIdx.x; t < 64 * 64; t += kSolveThreads) {
+// L^T x = y, one launch per block of 64 unknowns from the last (the rows of
+// B above the block already hold z = y - contributions of the later
+// blocks).  Every workgroup solves the block's triangle (staged in LDS,
+// wave 0) and then updates its slice of the rows above, right-looking:
+// z_r -= sum_c L(j0 + c, r) x_c, whose 64 entries are contiguous in column r.
+// Workgroup 0 stores the block's x in X (not in B, whose block rows the
+// other workgroups may still be reading).  Columns of B: grid y.
+__global__ __launch_bounds__(256) void chol_back_block(const double *A, int64_t lda, int32_t n, double *B,
+                                                       int64_t ldb, double *X, int32_t j0, const int32_t *info) {
+  if (*info) return;
+  __shared__ double s_L[64][65];
+  __shared__ double s_rinv[64];
+  __shared__ double s_x[64];
+  double *z = B + (int64_t)blockIdx.y * ldb;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int32_t bs = min(64, n - j0);
+  for (int t = threadIdx.x; t < 64 * 64; t += 256) {
     const int i = t & 63, c = t >> 6;  // consecutive threads: consecutive rows of a column
-    s_L[i][c] = (i < bs && c <= i) ? A[(j0 + i) + (int64_t)(j0 + c) * lda] : 0.0;
+    s_L[i][c] = (i < bs && c < i) ? A[(j0 + i) + (int64_t)(j0 + c) * lda] : 0.0;
   }
+  if (threadIdx.x < 64) {
+    const int c = threadIdx.x;
+    s_rinv[c] = c < bs ? 1.0 / A[(j0 + c) + (int64_t)(j0 + c) * lda] : 0.0;
+  }
+  __syncthreads();
+  if (wave == 0) {
+    // lane i: z_i and column i of the strictly lower triangle; right-looking
+    // from the last unknown: x_c = z_c / L(c, c) (z_c broadcast), then
+    // z_i -= L(c, i) x_c on every lane.  Lane i's z stops changing once c
+    // passes i (L(c, i) = 0 for c <= i here), so x_i = z_i / L(i, i) at the end.
+    double col[64];
+#pragma unroll
+    for (int c = 0; c < 64; ++c) col[c] = s_L[c][lane];
+    double zv = lane < bs ? z[j0 + lane] : 0.0;
+#pragma unroll
+    for (int c = 63; c >= 0; --c) {
+      const double xc = rdlane(zv, c) * s_rinv[c];
+      zv = fma(-col[c], xc, zv);
+    }
+    const double xv = zv * s_rinv[lane];
+    s_x[lane] = xv;
+    if (blockIdx.x == 0 && lane < bs) X[(int64_t)blockIdx.y * n + j0 + lane] = xv;
+  }
+  __syncthreads();
+  const int32_t r = (int32_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= j0) return;
+  const double *colr = A + j0 + (int64_t)r * lda;  // L(j0 .., r)
+  double acc0 = 0.0, acc1 = 0.0;
+  int c = 0;
+  for (; c + 1 < bs; c += 2) {
+    acc0 = fma(colr[c], s_x[c], acc0);
+    acc1 = fma(colr[c + 1], s_x[c + 1], acc1);
+  }
+  if (c < bs) acc0 = fma(colr[c], s_x[c], acc0);
+  z[r] -= acc0 + acc1;
 }
 
-__global__ __launch_bounds__(kSolveThreads) void chol_solve(const double *A, int64_t lda, int32_t n, double *B,
-                                                            int64_t ldb, const int32_t *info) {
-  if (*info) return;
-  double *y = B + (int64_t)blockIdx.x * ldb;
-  __shared__ double s_L[64][65];
-  __shared__ double s_blk[64];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  // forward: L y = b
-  for (int32_t j0 = 0; j0 < n; j0 += 64) {
-    const int32_t bs = min(64, n - j0);
-    stage_block(A, lda, j0, bs, s_L);
-    __syncthreads();
-    if (wave == 0) {
-      double v = lane < bs ? y[j0 + lane] : 0.0;
-      for (int c = 0; c < bs; ++c) {
-        if (lane == c) v = v / s_L[c][c];
-        const double vc = __shfl(v, c);
-        if (lane > c) v = fma(-s_L[lane][c], vc, v);
-      }
-      if (lane < bs) {
-        y[j0 + lane] = v;
-        s_blk[lane] = v;
-      }
-    }
-    __syncthreads();
-    // rows below: y_r -= sum_c L(r, j0 + c) y_{j0 + c}
-    for (int32_t r = j0 + bs + threadIdx.x; r < n; r += kSolveThreads) {
-      double acc = 0.0;
-      for (int c = 0; c < bs; ++c) acc = fma(A[r + (int64_t)(j0 + c) * lda], s_blk[c], acc);
-      y[r] -= acc;
-    }
-    __syncthreads();
-  }
-  // backward: L^T x = y, blocks from the last
-  const int32_t nblk = (n + 63) / 64;
-  for (int32_t bk = nblk - 1; bk >= 0; --bk) {
-    const int32_t j0 = bk * 64, bs = min(64, n - j0), j1 = j0 + bs;
-    stage_block(A, lda, j0, bs, s_L);
-    // z_c = y_c - sum_{r >= j1} L(r, c) x_r for the block's columns c: wave w
-    // takes columns w, w + 16, ...; lanes stride the rows
-    for (int c = wave; c < bs; c += kSolveWaves) {
-      double acc = 0.0;
-      const double *col = A + (int64_t)(j0 + c) * lda;
-      for (int32_t r = j1 + lane; r < n; r += 64) acc = fma(col[r], y[r], acc);
-      for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
-      if (lane == 0) s_blk[c] = acc;
-    }
-    __syncthreads();
-    if (wave == 0) {
-      const double z = lane < bs ? y[j0 + lane] - s_blk[lane] : 0.0;
-      double xv = 0.0;
-      // x_c = (z_c - sum_{i > c} L(i, c) x_i) / L(c, c), c descending
-      for (int c = bs - 1; c >= 0; --c) {
-        double t = lane > c ? s_L[lane][c] * xv : 0.0;
-        for (int off = 32; off >= 1; off >>= 1) t += __shfl_xor(t, off);
-        if (lane == c) xv = (z - t) / s_L[c][c];
-      }
-      if (lane < bs) y[j0 + lane] = xv;
-    }
-    __syncthreads();
-  }
+__global__ __launch_bounds__(256) void dense_copy_cols(const double *X, int32_t n, double *B, int64_t ldb,
+                                                       int32_t nrhs) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)n * nrhs) return;
+  const int32_t q = (int32_t)(t / n), i = (int32_t)(t % n);
+  B[i + (int64_t)q * ldb] = X[t];
 }
 
 }  // namespace
@@ -300,28 +309,38 @@ __global__ __launch_bounds__(kSolveThreads) void chol_solve(const double *A, int
     }                                                     \
   } while (0)
 
-rh_status dense_cholesky(int32_t n, double *A, int64_t lda, int32_t *dinfo, void *stream, std::string &err) {
+rh_status dense_cholesky(int32_t n, double *A, int64_t lda, double *B, int64_t ldb, int32_t nrhs, int32_t *dinfo,
+                         void *stream, std::string &err) {
   hipStream_t st = static_cast<hipStream_t>(stream);
+  if (!B) nrhs = 0;
   hipLaunchKernelGGL(dense_clear, dim3(1), dim3(64), 0, st, dinfo);
   for (int32_t j0 = 0; j0 < n; j0 += kNB) {
     const int32_t nb = std::min(kNB, n - j0), below = n - j0 - nb;
-    const int32_t blocks = std::max(1, (below + 255) / 256);
-    hipLaunchKernelGGL(chol_panel<kNB>, dim3(blocks), dim3(256), 0, st, A, lda, n, j0, dinfo);
+    const int32_t blocks = std::max(1, (below + nrhs + 255) / 256);
+    hipLaunchKernelGGL(chol_panel<kNB>, dim3(blocks), dim3(256), 0, st, A, lda, n, B, ldb, nrhs, j0, dinfo);
     if (below > 0) {
       const int64_t T = (below + kTile - 1) / kTile, tiles = T * (T + 1) / 2;
-      hipLaunchKernelGGL(chol_update<kNB>, dim3((uint32_t)tiles), dim3(256), 0, st, A, lda, n, j0,
-                         (const int32_t *)dinfo);
+      const int64_t rhs_groups = nrhs > 0 ? (below + 255) / 256 : 0;
+      hipLaunchKernelGGL(chol_update<kNB>, dim3((uint32_t)(tiles + rhs_groups)), dim3(256), 0, st, A, lda, n, B,
+                         ldb, nrhs, j0, (int32_t)tiles, (const int32_t *)dinfo);
     }
   }
   DENSE_TRY(hipGetLastError());
   return RH_OK;
 }
 
-rh_status dense_solve(int32_t n, const double *L, int64_t ldl, double *B, int64_t ldb, int32_t nrhs,
-                      const int32_t *dinfo, void *stream, std::string &err) {
+rh_status dense_back_solve(int32_t n, const double *L, int64_t ldl, double *B, int64_t ldb, int32_t nrhs,
+                           double *work, const int32_t *dinfo, void *stream, std::string &err) {
   if (nrhs <= 0 || n <= 0) return RH_OK;
-  hipLaunchKernelGGL(chol_solve, dim3(nrhs), dim3(kSolveThreads), 0, static_cast<hipStream_t>(stream), L, ldl, n,
-                     B, ldb, dinfo);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  for (int32_t j0 = ((n - 1) / 64) * 64; j0 >= 0; j0 -= 64) {
+    const uint32_t groups = (uint32_t)std::max(1, (j0 + 255) / 256);
+    hipLaunchKernelGGL(chol_back_block, dim3(groups, (uint32_t)nrhs), dim3(256), 0, st, L, ldl, n, B, ldb, work, j0,
+                       dinfo);
+  }
+  const int64_t total = (int64_t)n * nrhs;
+  hipLaunchKernelGGL(dense_copy_cols, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, st, (const double *)work,
+                     n, B, ldb, nrhs);
   DENSE_TRY(hipGetLastError());
   return RH_OK;
 }

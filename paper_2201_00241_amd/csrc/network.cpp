@@ -13,6 +13,7 @@
 // and a bus injection is the sum of the end flows at that bus.
 #include <algorithm>
 #include <cmath>
+#include <limits>
 #include <cstring>
 #include <numeric>
 #include <queue>
@@ -550,7 +551,7 @@ rh_status network_solve(Network &net, double tol, int32_t max_iter, std::string 
     for (int32_t b : net.pq) x[net.v_x[b]] = 1.0;
   std::vector<double> th, v, g;
   int32_t it = 0;
-  double r = 0.0;
+  double r = 0.0, r_prev = std::numeric_limits<double>::infinity();
   for (;; ++it) {
     unpack_state(net, x, net.p, th, v);
     residual(net, th, v, net.p, g);
@@ -565,13 +566,14 @@ rh_status network_solve(Network &net, double tol, int32_t max_iter, std::string 
       net.newton_iters = it;
       return RH_ENOCONV;
     }
-    if (r <= tol) break;
+    if (r <= tol || newton_stalled(it, r, r_prev)) break;
     if (it >= max_iter) {
       err = "Newton did not reach the tolerance in max_iter steps";
       net.newton_iters = it;
       net.newton_resid = r;
       return RH_ENOCONV;
     }
+    r_prev = r;
     assemble_jacobians(net, th, v, net.gx_slot, net.gp_slot);
     if (!lu_factor(net.lu, net.gx, err)) return RH_ESINGULAR;
     lu_solve(net.lu, g);

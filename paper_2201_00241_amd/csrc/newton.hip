@@ -22,6 +22,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <limits>
 #include <cstring>
 #include <vector>
 
@@ -573,6 +574,7 @@ rh_status device_newton(Network &net, double tol, int32_t max_iter, NewtonResult
   HIP_TRY(hipMemcpy(w.Qd, net.Qd.data(), net.Qd.size() * sizeof(double), hipMemcpyHostToDevice));
   const int32_t m = net.n_br, nb = net.n_bus, nnz_gx = (int32_t)net.gx.nnz();
   double stat[3] = {0.0, 0.0, 0.0};
+  double r_prev = std::numeric_limits<double>::infinity();
   int32_t it = 0;
   for (;; ++it) {
     // mismatch at x; with the Jacobian and its factors unless this is the end
@@ -589,11 +591,12 @@ rh_status device_newton(Network &net, double tol, int32_t max_iter, NewtonResult
       err = "G_x is singular to working precision (pivot " + std::to_string((int64_t)stat[2] - 1) + ")";
       return RH_ESINGULAR;
     }
-    if (stat[0] <= tol) break;
+    if (stat[0] <= tol || newton_stalled(it, stat[0], r_prev)) break;
     if (it >= max_iter) {
       err = "Newton did not reach the tolerance in max_iter steps";
       return RH_ENOCONV;
     }
+    r_prev = stat[0];
     if ((s = nt_solve_kernels(d, err)) != RH_OK) return s;
   }
   // the accepted state and the factors of G_x there (from the last step's

@@ -244,14 +244,23 @@ struct NewtonResult {
 };
 rh_status device_newton(Network &net, double tol, int32_t max_iter, NewtonResult &res, std::string &err);
 void device_newton_free(Network &net);
+// Newton at rounding level: after three steps, a residual below 1e-11 that
+// no longer halves is accepted (the tolerance may lie below what the
+// arithmetic can reach for a large grid).
+inline bool newton_stalled(int32_t it, double r, double r_prev) {
+  return it >= 3 && r < 1e-11 && r >= 0.5 * r_prev;
+}
 
 // ---- dense FP64 Cholesky (dense.hip) and the tracking update (track.hip)
-// A = L L^T in place on the lower triangle (column-major); *dinfo = 0, or
-// the first failed column + 1.  Enqueued on `stream`.
-rh_status dense_cholesky(int32_t n, double *A, int64_t lda, int32_t *dinfo, void *stream, std::string &err);
-// L L^T X = B in place for nrhs columns (nothing if *dinfo != 0).
-rh_status dense_solve(int32_t n, const double *L, int64_t ldl, double *B, int64_t ldb, int32_t nrhs,
-                      const int32_t *dinfo, void *stream, std::string &err);
+// A = L L^T in place on the lower triangle (column-major), and L Y = B in
+// place for the nrhs columns of B (B may be null); *dinfo = 0, or the first
+// failed column + 1.  Enqueued on `stream`.
+rh_status dense_cholesky(int32_t n, double *A, int64_t lda, double *B, int64_t ldb, int32_t nrhs, int32_t *dinfo,
+                         void *stream, std::string &err);
+// L^T X = Y in place for nrhs columns (nothing if *dinfo != 0); work holds
+// n * nrhs doubles.
+rh_status dense_back_solve(int32_t n, const double *L, int64_t ldl, double *B, int64_t ldb, int32_t nrhs,
+                           double *work, const int32_t *dinfo, void *stream, std::string &err);
 // F = lower triangle of A with tau added on the diagonal.
 rh_status dense_shift_copy(int32_t n, const double *A, int64_t lda, double *F, int64_t ldf, double tau, void *stream,
                            std::string &err);

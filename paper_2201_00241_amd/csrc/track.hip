@@ -98,9 +98,18 @@ rh_status dense_spd_solve(int device, int32_t n, double *A, int64_t lda, double 
   TR_TRY(hipSetDevice(device));
   hipStream_t st = static_cast<hipStream_t>(stream);
   int32_t *info = nullptr;
+  double *work = nullptr;
   TR_TRY(hipMalloc(&info, sizeof(int32_t)));
-  rh_status s = dense_cholesky(n, A, lda, info, stream, err);
-  if (s == RH_OK) s = dense_solve(n, A, lda, B, ldb, nrhs, info, stream, err);
+  {
+    hipError_t e = hipMalloc(&work, std::max<size_t>(1, (size_t)n * std::max(1, nrhs)) * sizeof(double));
+    if (e != hipSuccess) {
+      (void)hipFree(info);
+      err = std::string("dense solve workspace: ") + hipGetErrorString(e);
+      return RH_ENOMEM;
+    }
+  }
+  rh_status s = dense_cholesky(n, A, lda, B, ldb, nrhs, info, stream, err);
+  if (s == RH_OK) s = dense_back_solve(n, A, lda, B, ldb, nrhs, work, info, stream, err);
   int32_t h = 0;
   if (s == RH_OK) {
     hipError_t e = hipMemcpyAsync(&h, info, sizeof h, hipMemcpyDeviceToHost, st);
@@ -110,7 +119,9 @@ rh_status dense_spd_solve(int device, int32_t n, double *A, int64_t lda, double 
       s = RH_EDEVICE;
     }
   }
+  if (s != RH_OK) (void)hipStreamSynchronize(st);  // the launches may still use the buffers
   (void)hipFree(info);
+  (void)hipFree(work);
   failed_col = h > 0 ? h - 1 : -1;
   return s;
 }
@@ -150,7 +161,8 @@ rh_status tracking_step(Network &net, int32_t k_block, double shift, const doubl
   for (;;) {
     ++tries;
     TR_OK(dense_shift_copy(n, t->H, n, t->F, n, tau, stream, err));
-    TR_OK(dense_cholesky(n, t->F, n, t->info, stream, err));
+    TR_OK(dense_negate(n, t->g, t->d, stream, err));
+    TR_OK(dense_cholesky(n, t->F, n, t->d, n, 1, t->info, stream, err));
     TR_TRY(hipMemcpyAsync(&bad, t->info, sizeof bad, hipMemcpyDeviceToHost, st));
     TR_TRY(hipStreamSynchronize(st));
     if (bad == 0) break;
@@ -160,8 +172,7 @@ rh_status tracking_step(Network &net, int32_t k_block, double shift, const doubl
     }
     tau = std::max(2.0 * tau, beta);
   }
-  TR_OK(dense_negate(n, t->g, t->d, stream, err));
-  TR_OK(dense_solve(n, t->F, n, t->d, n, 1, t->info, stream, err));
+  TR_OK(dense_back_solve(n, t->F, n, t->d, n, 1, t->diag, t->info, stream, err));
   TR_TRY(hipEventRecord(t->ev[3], st));
   if (dd && n > 0) TR_TRY(hipMemcpyAsync(dd, t->d, n * sizeof(double), hipMemcpyDeviceToDevice, st));
   TR_TRY(hipMemcpyAsync(dh.data(), t->d, n * sizeof(double), hipMemcpyDeviceToHost, st));

@@ -131,5 +131,6 @@ def test_load_trajectory_recipe():
     assert Pd.shape == Qd.shape == (60, grid.n_bus)
     s = Pd / np.where(grid.Pd == 0, 1.0, grid.Pd)[None, :]
     loaded = grid.Pd != 0
-    assert np.all(np.abs(s[:, loaded] - 1.0) < 0.03 + 6 * 0.005)
+    assert np.all(np.abs(s[:, loaded] - 1.0) < 2 * 0.03 + 6 * 0.005)
+    assert np.all(np.abs(s[0, loaded] - 1.0) < 6 * 0.005)  # starts at the base loads
     np.testing.assert_allclose(Pd[:, loaded] / grid.Pd[loaded], Qd[:, loaded] / grid.Qd[loaded])
