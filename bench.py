@@ -33,13 +33,18 @@ PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = ROOT / "profiles" / "block_kernel_10k_hbm_traffic.txt"
 
 
+# the sources the block kernel's memory traffic depends on: the kernel, the
+# planner that lays out its records, and their shared header
+TRAFFIC_SOURCES = ("device.hip", "rh_internal.h", "sparse_lu.cpp")
+
+
 def sources_digest():
-    """SHA-256 over the library sources (kernels, planner, ABI), in name order."""
+    """SHA-256 over the block kernel's sources (TRAFFIC_SOURCES), in name order."""
     h = hashlib.sha256()
-    for f in sorted((ROOT / "paper_2201_00241_amd" / "csrc").iterdir()):
-        if f.suffix in (".hip", ".cpp", ".h"):
-            h.update(f.name.encode())
-            h.update(f.read_bytes())
+    for name in sorted(TRAFFIC_SOURCES):
+        f = ROOT / "paper_2201_00241_amd" / "csrc" / name
+        h.update(f.name.encode())
+        h.update(f.read_bytes())
     return h.hexdigest()
 
 
