@@ -1829,8 +1829,8 @@ const T *at_off(const char *base, int64_t off) {
 // both precisions), then the FP64 values and block inverses, then their FP32
 // copies, so that each precision's working set is two contiguous ranges.
 rh_status upload_sweep(DeviceNet *dn, const Sweep &s, int32_t n, const std::vector<int32_t> &parent,
-                       bool forward, const ScheduleParams &prm, DevSweep &o, std::string &err) {
-  const Schedule sc = build_schedule(s, n, parent, forward, prm);
+                       bool forward, const ScheduleParams &prm, DevSweep &o, ScheduleCut *cut, std::string &err) {
+  const Schedule sc = build_schedule(s, n, parent, forward, prm, cut);
   Packed pk = pack_schedule(sc, kThreads);
   if (pk.irow.empty()) pk.irow.push_back(0);  // lanes without a row read element 0
   if (!pk.idinv.empty()) {
@@ -2080,10 +2080,16 @@ rh_status device_upload(Network &net, std::string &err) {
   if (net.sched_wave >= 0) prm.wave_mode = net.sched_wave != 0;
   const int32_t n = net.n_x;
   const std::vector<int32_t> parent = etree_parent(lu);
-  if (upload_sweep(dn, sl, n, parent, true, prm, nd.L, err) != RH_OK ||
-      upload_sweep(dn, su, n, parent, false, prm, nd.U, err) != RH_OK ||
-      upload_sweep(dn, sut, n, parent, true, prm, nd.Ut, err) != RH_OK ||
-      upload_sweep(dn, slt, n, parent, false, prm, nd.Lt, err) != RH_OK)
+  // the sweeps' cuts depend on the pattern and these parameters only
+  if (net.cut_params[0] != prm.bmax || net.cut_params[1] != prm.wave_mode) {
+    for (ScheduleCut &c : net.cuts) c = ScheduleCut();
+    net.cut_params[0] = prm.bmax;
+    net.cut_params[1] = prm.wave_mode;
+  }
+  if (upload_sweep(dn, sl, n, parent, true, prm, nd.L, &net.cuts[0], err) != RH_OK ||
+      upload_sweep(dn, su, n, parent, false, prm, nd.U, &net.cuts[1], err) != RH_OK ||
+      upload_sweep(dn, sut, n, parent, true, prm, nd.Ut, &net.cuts[2], err) != RH_OK ||
+      upload_sweep(dn, slt, n, parent, false, prm, nd.Lt, &net.cuts[3], err) != RH_OK)
     return RH_EDEVICE;
   net.report.steps_l = nd.L.n_steps;
   net.report.steps_u = nd.U.n_steps;

@@ -130,6 +130,14 @@ struct Packed {
   std::vector<double> wval;
 };
 
+// The cut of a sweep into a wave step and the steps above it: the wave that
+// owns each row below the cut (-1 above it), or no wave step at all.  It
+// depends only on the sweep's pattern and the schedule parameters, so a
+// network reuses it for every operating point.
+struct ScheduleCut {
+  bool valid = false, plain = false;
+  std::vector<int32_t> owner;
+};
 struct ScheduleParams {
   int bmax = 64;          // rows of a merged block (0: no blocks)
   int block_rows = 64;    // the kernel's block capacity
@@ -203,6 +211,10 @@ struct Network {
   rh_tile tile[2] = {};
   // schedule parameters of the uploaded sweeps (-1: the defaults)
   int32_t sched_bmax = -1, sched_wave = -1;
+  // the cuts of the four sweeps (L, U, U^T, L^T) for the parameters
+  // cut_params = {bmax, wave mode} (reused across operating points)
+  ScheduleCut cuts[4];
+  int32_t cut_params[2] = {-1, -1};
   int32_t refined_cols = -1;    // columns of the last refined product call (-1: none)
 };
 
@@ -294,8 +306,9 @@ void lu_solve_t(const LuPlan &lu, std::vector<double> &b);      // A^T x = b in 
 // Uh^{-T} P b; pivinv = D^{-1} (reciprocal pivots, factor numbering).
 void lu_sweeps(const LuPlan &lu, Sweep &sl, Sweep &su, Sweep &sut, Sweep &slt, std::vector<double> &pivinv);
 int lane_log2(int32_t rows, int32_t longest, int lane_budget);
+// `cut` (may be null): reused if valid, else filled with the cut chosen.
 Schedule build_schedule(const Sweep &in, int32_t n, const std::vector<int32_t> &parent, bool forward,
-                        const ScheduleParams &prm);
+                        const ScheduleParams &prm, ScheduleCut *cut = nullptr);
 std::vector<int32_t> etree_parent(const LuPlan &lu);
 // Pack a schedule into per-lane slots; `lanes` = workgroup size, wave steps use
 // 64 lanes per wave.

@@ -233,25 +233,33 @@ void lu_sweeps(const LuPlan &lu, Sweep &sl, Sweep &su, Sweep &sut, Sweep &slt, s
   // U^{-T} = D^{-1} Uh^{-T}, so every sweep has a unit diagonal and each solve
   // scales by D^{-1} between its two sweeps.
   pivinv.assign(n, 0.0);
-  std::vector<std::vector<double>> uh(n);
+  for (int32_t k = 0; k < n; ++k) pivinv[k] = 1.0 / lu.uval[k][0];
+  // rows of Uh^T and L^T in flat arrays, each row in ascending column order
+  // (rows of U and L visited in ascending order)
+  std::vector<int32_t> tp(n + 1, 0), lp(n + 1, 0);
   for (int32_t k = 0; k < n; ++k) {
-    pivinv[k] = 1.0 / lu.uval[k][0];
-    uh[k].resize(lu.uval[k].size());
-    for (size_t q = 1; q < lu.uval[k].size(); ++q) uh[k][q] = lu.uval[k][q] / lu.uval[k][0];
+    for (size_t q = 1; q < lu.urow[k].size(); ++q) tp[lu.urow[k][q] + 1]++;
+    for (int32_t c : lu.lrow[k]) lp[c + 1]++;
   }
-  // rows of U^T and L^T (the pattern is symmetric: U^T row i = L row i's columns)
-  std::vector<std::vector<int32_t>> utc(n), ltc(n);
-  std::vector<std::vector<double>> utv(n), ltv(n);
-  for (int32_t k = 0; k < n; ++k)
+  for (int32_t i = 0; i < n; ++i) {
+    tp[i + 1] += tp[i];
+    lp[i + 1] += lp[i];
+  }
+  std::vector<int32_t> tc(tp[n]), lc(lp[n]), tf(tp.begin(), tp.end() - 1), lf(lp.begin(), lp.end() - 1);
+  std::vector<double> tv(tp[n]), lv(lp[n]);
+  for (int32_t k = 0; k < n; ++k) {
+    const double d = lu.uval[k][0];
     for (size_t q = 1; q < lu.urow[k].size(); ++q) {
-      utc[lu.urow[k][q]].push_back(k);
-      utv[lu.urow[k][q]].push_back(uh[k][q]);
+      const int32_t e = tf[lu.urow[k][q]]++;
+      tc[e] = k;
+      tv[e] = lu.uval[k][q] / d;
     }
-  for (int32_t j = 0; j < n; ++j)
-    for (size_t q = 0; q < lu.lrow[j].size(); ++q) {
-      ltc[lu.lrow[j][q]].push_back(j);
-      ltv[lu.lrow[j][q]].push_back(lu.lval[j][q]);
+    for (size_t q = 0; q < lu.lrow[k].size(); ++q) {
+      const int32_t e = lf[lu.lrow[k][q]]++;
+      lc[e] = k;
+      lv[e] = lu.lval[k][q];
     }
+  }
   make_sweep(sl, n, lu.level_l, lu.n_levels_l,
              [&](int32_t i, std::vector<int32_t> &c, std::vector<double> &v) {
                c.insert(c.end(), lu.lrow[i].begin(), lu.lrow[i].end());
@@ -261,19 +269,20 @@ void lu_sweeps(const LuPlan &lu, Sweep &sl, Sweep &su, Sweep &sut, Sweep &slt, s
   make_sweep(su, n, lu.level_u, lu.n_levels_u,
              [&](int32_t i, std::vector<int32_t> &c, std::vector<double> &v) {
                c.insert(c.end(), lu.urow[i].begin() + 1, lu.urow[i].end());
-               v.insert(v.end(), uh[i].begin() + 1, uh[i].end());
+               const double d = lu.uval[i][0];
+               for (size_t q = 1; q < lu.uval[i].size(); ++q) v.push_back(lu.uval[i][q] / d);
              },
              nullptr);
   make_sweep(sut, n, lu.level_l, lu.n_levels_l,
              [&](int32_t i, std::vector<int32_t> &c, std::vector<double> &v) {
-               c.insert(c.end(), utc[i].begin(), utc[i].end());
-               v.insert(v.end(), utv[i].begin(), utv[i].end());
+               c.insert(c.end(), tc.begin() + tp[i], tc.begin() + tp[i + 1]);
+               v.insert(v.end(), tv.begin() + tp[i], tv.begin() + tp[i + 1]);
              },
              nullptr);
   make_sweep(slt, n, lu.level_u, lu.n_levels_u,
              [&](int32_t i, std::vector<int32_t> &c, std::vector<double> &v) {
-               c.insert(c.end(), ltc[i].begin(), ltc[i].end());
-               v.insert(v.end(), ltv[i].begin(), ltv[i].end());
+               c.insert(c.end(), lc.begin() + lp[i], lc.begin() + lp[i + 1]);
+               v.insert(v.end(), lv.begin() + lp[i], lv.begin() + lp[i + 1]);
              },
              nullptr);
 }
@@ -376,33 +385,19 @@ int32_t emit_levels(const Sweep &in, const std::vector<int32_t> &order, std::vec
 
 }  // namespace
 
-// Sweep schedule.  Steps are plain levels, dense-inverse blocks of merged
-// narrow levels, or one wave step: the elimination tree is cut into disjoint
-// subtrees (each subtree's rows depend only on the subtree and on rows outside
-// it that are solved before), the subtrees are assigned to the workgroup's
-// waves (longest-processing-time-first, then single-subtree moves that lower
-// the largest number of units on one wave), and every wave walks its
-// subtrees level by level with wave-local ordering only.  The cut is chosen
-// by a small cost model (a workgroup barrier step ~ 5 wave units); the wave
-// step comes first in forward sweeps (leaves first) and last in backward
-// sweeps.
-Schedule build_schedule(const Sweep &in, int32_t n, const std::vector<int32_t> &parent, bool forward,
-                        const ScheduleParams &prm) {
-  const int bmax = std::min(prm.bmax, prm.block_rows);
-  Schedule out;
-  std::vector<int32_t> local(n, -1), lvl(n, -1);
+namespace {
+
+// The cut of a sweep (see build_schedule): for the cut factors f = 1 .. 32,
+// subtrees of at most total / (waves f) work go to the waves by
+// longest-processing-time-first and single-subtree moves, and the cut with
+// the lowest modelled cost wins.  Returns the factor chosen (0: no wave step)
+// and the owner of every row.
+int choose_cut(const Sweep &in, int32_t n, const std::vector<int32_t> &parent, const ScheduleParams &prm, int bmax,
+               std::vector<int32_t> &lvl, std::vector<int32_t> &local, std::vector<int32_t> &owner) {
   const int32_t npos = (int32_t)in.rows.size();
-  std::vector<int32_t> pos_of(n, -1);
-  for (int32_t p = 0; p < npos; ++p) pos_of[in.rows[p]] = p;
+  const int nw = prm.n_waves;
   std::vector<int32_t> all(npos);
   for (int32_t p = 0; p < npos; ++p) all[p] = p;
-
-  out.s.ptr.assign(1, 0);
-  const int nw = prm.n_waves;
-  if (prm.wave_mode == 0 || nw < 2 || (int32_t)parent.size() != n) {
-    emit_levels(in, all, lvl, bmax, prm.lane_budget, local, &out);
-    return out;
-  }
   // subtree work (rows + entries) in the elimination tree (parent > child)
   std::vector<double> wk(n, 0.0), sub(n, 0.0);
   double total = 0.0;
@@ -426,7 +421,6 @@ Schedule build_schedule(const Sweep &in, int32_t n, const std::vector<int32_t> &
   const double plain_cost = kBarrier * emit_levels(in, all, lvl, bmax, prm.lane_budget, local, nullptr);
   double best = plain_cost;
   int best_f = 0;
-  std::vector<int32_t> owner(n, -1);  // wave of a subtree row, -1 = top part
   std::vector<int32_t> best_owner;
   for (int f : {1, 2, 4, 8, 16, 32}) {
     const double target = total / (nw * f);
@@ -578,11 +572,57 @@ Schedule build_schedule(const Sweep &in, int32_t n, const std::vector<int32_t> &
       best_owner = owner;
     }
   }
-  if (best_f == 0) {
+  if (best_f != 0) owner = best_owner;
+  return best_f;
+}
+
+}  // namespace
+
+// Sweep schedule.  Steps are plain levels, dense-inverse blocks of merged
+// narrow levels, or one wave step: the elimination tree is cut into disjoint
+// subtrees (each subtree's rows depend only on the subtree and on rows outside
+// it that are solved before), the subtrees are assigned to the workgroup's
+// waves (longest-processing-time-first, then single-subtree moves that lower
+// the largest number of units on one wave), and every wave walks its
+// subtrees level by level with wave-local ordering only.  The cut is chosen
+// by a small cost model (a workgroup barrier step ~ 5 wave units); the wave
+// step comes first in forward sweeps (leaves first) and last in backward
+// sweeps.
+// The cut (the search above, the costly part) is taken from `cut` when it
+// holds one, and stored there otherwise.
+Schedule build_schedule(const Sweep &in, int32_t n, const std::vector<int32_t> &parent, bool forward,
+                        const ScheduleParams &prm, ScheduleCut *cut) {
+  const int bmax = std::min(prm.bmax, prm.block_rows);
+  Schedule out;
+  std::vector<int32_t> local(n, -1), lvl(n, -1);
+  const int32_t npos = (int32_t)in.rows.size();
+  std::vector<int32_t> pos_of(n, -1);
+  for (int32_t p = 0; p < npos; ++p) pos_of[in.rows[p]] = p;
+  std::vector<int32_t> all(npos);
+  for (int32_t p = 0; p < npos; ++p) all[p] = p;
+
+  out.s.ptr.assign(1, 0);
+  const int nw = prm.n_waves;
+  if (prm.wave_mode == 0 || nw < 2 || (int32_t)parent.size() != n ||
+      (cut && cut->valid && cut->plain)) {
     emit_levels(in, all, lvl, bmax, prm.lane_budget, local, &out);
     return out;
   }
-  owner = best_owner;
+  std::vector<int32_t> owner(n, -1);  // wave of a subtree row, -1 = top part
+  if (cut && cut->valid && (int32_t)cut->owner.size() == n) {
+    owner = cut->owner;
+  } else {
+    int best_f = choose_cut(in, n, parent, prm, bmax, lvl, local, owner);
+    if (cut) {
+      cut->valid = true;
+      cut->plain = best_f == 0;
+      cut->owner = owner;
+    }
+    if (best_f == 0) {
+      emit_levels(in, all, lvl, bmax, prm.lane_budget, local, &out);
+      return out;
+    }
+  }
   std::vector<int32_t> top_order;
   for (int32_t p = 0; p < npos; ++p)
     if (owner[in.rows[p]] < 0) top_order.push_back(p);
