@@ -1,9 +1,8 @@
 """Calibrate the loading factor and loss factor of the synthetic workloads.
 
 Run by hand (``python tests/golden/calibrate_grids.py c2 0 1 2``); it calls
-only the generator and the oracle.  For each instance it
-
-Newton starts from the generator's voltage guess ``v0`` (angles 0).
+only the generator and the oracle; Newton starts from the generator's voltage
+guess ``v0`` (angles 0).  For each instance it
 
 1. solves the power flow at a light loading ``alpha0`` and reads off the
    fraction of the total load that the slack bus supplies (the losses),
@@ -12,7 +11,8 @@ Newton starts from the generator's voltage guess ``v0`` (angles 0).
 3. bisects the largest loading factor for which Newton converges, to 0.01.
 
 The values chosen in ``gridgen.CONFIGS`` keep every listed instance at or
-below 0.8 of its limit; ``tests/test_grids.py`` checks convergence there.
+below 0.8 of its limit; ``tests/test_oracle.py::test_grids_converge_for_the_workloads``
+checks convergence there.
 """
 import json
 import sys
