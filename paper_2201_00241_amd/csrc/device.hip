@@ -79,9 +79,12 @@ struct DevSweep {
   int32_t n_slots, n_irow;  // lengths of the slot and row arrays
   const double *sval, *dense;   // unit diagonal (pivots are applied between sweeps)
   const float *sval32, *dense32;  // FP32 copies (refined mode)
-  // wave units (see Packed): the FP64 and FP32 records
+  // wave units (see Packed): the FP64 and FP32 records, wide (any network)
+  // and compact (null when the padded vector has more than 65,536 rows;
+  // the kernels with X in LDS read these)
   int32_t n_wunits;
   const char *wrec, *wrec32;
+  const char *wrecc, *wrecc32;
 };
 
 template <class T>
@@ -567,6 +570,22 @@ template <>
 __device__ __forceinline__ const char *sw_wrec<double>(const DevSweep AS4 &s) { return s.wrec; }
 template <>
 __device__ __forceinline__ const char *sw_wrec<float>(const DevSweep AS4 &s) { return s.wrec32; }
+template <class T>
+__device__ __forceinline__ const char *sw_wrecc(const DevSweep AS4 &s);
+template <>
+__device__ __forceinline__ const char *sw_wrecc<double>(const DevSweep AS4 &s) { return s.wrecc; }
+template <>
+__device__ __forceinline__ const char *sw_wrecc<float>(const DevSweep AS4 &s) { return s.wrecc32; }
+template <class T>
+struct WaveRecC;
+template <>
+struct WaveRecC<double> {
+  static constexpr int bytes = kWaveRecCompact64;
+};
+template <>
+struct WaveRecC<float> {
+  static constexpr int bytes = kWaveRecCompact32;
+};
 
 // Byte offset of an 8-byte-row offset in a vector whose rows are C values of T.
 template <int C, class T>
@@ -626,6 +645,95 @@ __device__ __forceinline__ void wrec_load(__amdgpu_buffer_rsrc_t R, int32_t soff
     W.val[1] = a.y;
     W.val[2] = a.z;
     W.val[3] = a.w;
+  }
+}
+
+// A compact record (see wave_records): one 16-byte header per lane with the
+// four column rows, the start and write rows (16-bit row indices) and the
+// flags, then the values.  vh, vv0, vv1: per-lane byte offsets of the header
+// and the value pairs (FP32 reads its quad at vv0).
+template <class T>
+struct WRingC {
+  u32x4 hdr;
+  T val[4];
+};
+
+template <class T>
+__device__ __forceinline__ void wrecc_load(__amdgpu_buffer_rsrc_t R, int32_t soff, int vh, int vv0, int vv1,
+                                           WRingC<T> &W) {
+  const int32_t so = __builtin_amdgcn_readfirstlane(soff);
+  W.hdr = __builtin_amdgcn_raw_buffer_load_b128(R, vh, so, 0);
+  if constexpr (sizeof(T) == 8) {
+    const f64x2 a = __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(R, vv0, so, 0));
+    const f64x2 b = __builtin_bit_cast(f64x2, __builtin_amdgcn_raw_buffer_load_b128(R, vv1, so, 0));
+    W.val[0] = a.x;
+    W.val[1] = a.y;
+    W.val[2] = b.x;
+    W.val[3] = b.y;
+  } else {
+    (void)vv1;
+    const f32x4 a = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(R, vv0, so, 0));
+    W.val[0] = a.x;
+    W.val[1] = a.y;
+    W.val[2] = a.z;
+    W.val[3] = a.w;
+  }
+}
+
+// The wave walk on compact records with X in LDS (see wave_walk): the same
+// unit, its header one load instead of the column quad and the row words.
+template <int C, class T>
+__device__ __forceinline__ void wave_walk_c(const DevSweep AS4 &s, int32_t u0, int32_t u1, int l64, T *Xpad) {
+  const int32_t n = u1 - u0;
+  if (n <= 0) return;
+  constexpr int RB = WaveRecC<T>::bytes;
+  const __amdgpu_buffer_rsrc_t R = __builtin_amdgcn_make_buffer_rsrc(
+      (void *)(sw_wrecc<T>(s) + (int64_t)u0 * RB), 0, n * RB, kBufWord3);
+  const int vh = l64 * 16, vv0 = l64 * 16 + 1024, vv1 = l64 * 16 + 2048;
+  WRingC<T> ring[kWaveAhead];
+#pragma unroll
+  for (int d = 0; d < kWaveAhead; ++d) {
+    wrecc_load<T>(R, d * RB, vh, vv0, vv1, ring[d]);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  int32_t soff = kWaveAhead * RB;
+  for (int32_t j = 0; j < n; j += kWaveAhead) {
+#pragma unroll
+    for (int d = 0; d < kWaveAhead; ++d) {
+      const u32x4 h = ring[d].hdr;
+      const uint32_t c0 = (h.x & 0xffffu) << 3, c1 = (h.x >> 16) << 3;
+      const uint32_t c2 = (h.y & 0xffffu) << 3, c3 = (h.y >> 16) << 3;
+      const uint32_t rs = (h.z & 0xffffu) << 3, rw = (h.z >> 16) << 3;
+      const int lg = (int)((uint32_t)__builtin_amdgcn_readfirstlane(h.w) >> 2);
+      // loads of the unit kWaveAhead on
+      const bool nact = h.w & 1u, ntwo = (h.w >> 1) & 1u;
+      const int nv0 = nact ? vv0 : kOffRange, nv1 = ntwo ? vv1 : kOffRange;
+      T xv[4][C], xr[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) {
+        xv[0][c] = xget<C, T, true>(Xpad, c0, c);
+        xv[1][c] = xget<C, T, true>(Xpad, c1, c);
+        xv[2][c] = xget<C, T, true>(Xpad, c2, c);
+        xv[3][c] = xget<C, T, true>(Xpad, c3, c);
+        xr[c] = xget<C, T, true>(Xpad, rs, c);
+      }
+      T part[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) part[c] = T(0);
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int c = 0; c < C; ++c) part[c] = fma(ring[d].val[e], xv[e][c], part[c]);
+      T nv[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) nv[c] = xr[c] - group_sum(part[c], lg);
+      // every lane writes (lanes without a row to their dummy rows)
+#pragma unroll
+      for (int c = 0; c < C; ++c) xput<C, T, true>(Xpad, rw, c, nv[c]);
+      wave_sync<true>();  // this wave's writes before its next unit's reads
+      wrecc_load<T>(R, soff, vh, nv0, nv1, ring[d]);
+      soff += RB;
+    }
   }
 }
 
@@ -750,7 +858,10 @@ __device__ __forceinline__ void sweep(const DevSweep AS4 &s, T *__restrict__ X,
       const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), l64 = tid & 63;
       const int32_t AS4 *wd = (const int32_t AS4 *)s.wdir;
       const int32_t u0 = wd[cur.x + wv], u1 = wd[cur.x + wv + 1];
-      wave_walk<C, T, LDSX>(s, u0, u1, l64, X - kWavePadRows * C);
+      if constexpr (LDSX)
+        wave_walk_c<C, T>(s, u0, u1, l64, X - kWavePadRows * C);
+      else
+        wave_walk<C, T, LDSX>(s, u0, u1, l64, X - kWavePadRows * C);
       prefetch(st, k + 1 < ns);
       step_barrier<LDSX>();
       if (ss && tid == 0 && k + 1 < kMaxStepStamps) ss[k + 1] = wall_clock64();
@@ -1607,7 +1718,8 @@ rh_status plan_launch(const DeviceInfo &info, int32_t refine, std::vector<WorkIt
   pl.refined = refine >= 0;
   const size_t elem = pl.refined ? sizeof(float) : sizeof(double);  // LDS vector element
   pl.pad_rows = max_nx + kWavePadRows;                               // padded working vector
-  pl.lds = (size_t)pl.pad_rows * elem <= info.lds_max && !std::getenv("RH_NO_LDS");
+  // X in LDS also means compact wave records (rows as 16-bit indices)
+  pl.lds = (size_t)pl.pad_rows * elem <= info.lds_max && pl.pad_rows <= 65536 && !std::getenv("RH_NO_LDS");
   const int32_t C = pl.C = choose_c(total_k, info.cus, pl.pad_rows, info.lds_max, pl.lds, elem, force_c);
   for (WorkItem &it : items) {
     it.chunk0 = (int32_t)pl.n_chunks;
@@ -1837,19 +1949,13 @@ rh_status upload_sweep(DeviceNet *dn, const Sweep &s, int32_t n, const std::vect
     err = "internal: device sweeps must have a unit diagonal";
     return RH_EDEVICE;
   }
-  // wave-unit records in both precisions (layout: see WaveRec)
+  // wave-unit records in both precisions, wide and (where the rows fit)
+  // compact (layouts: see wave_records)
   const size_t nwu = pk.wlg.size();
-  std::vector<char> rec64(nwu * WaveRec<double>::bytes), rec32(nwu * WaveRec<float>::bytes);
-  for (size_t u = 0; u < nwu; ++u) {
-    char *r64 = rec64.data() + u * WaveRec<double>::bytes, *r32 = rec32.data() + u * WaveRec<float>::bytes;
-    std::memcpy(r64, pk.wcol.data() + 256 * u, 1024);
-    std::memcpy(r64 + 1024, pk.wrow.data() + 128 * u, 512);
-    std::memcpy(r64 + 1536, pk.wval.data() + 256 * u, 2048);
-    std::memcpy(r32, r64, 1536);
-    float *v32 = reinterpret_cast<float *>(r32 + 1536);
-    for (int l = 0; l < 64; ++l)
-      for (int e = 0; e < 4; ++e) v32[4 * l + e] = (float)pk.wval[256 * u + 128 * (e >> 1) + 2 * l + (e & 1)];
-  }
+  std::vector<char> rec64, rec32, recc64, recc32;
+  (void)wave_records(pk, false, true, rec64);
+  (void)wave_records(pk, false, false, rec32);
+  const bool compact = wave_records(pk, true, true, recc64) && wave_records(pk, true, false, recc32);
   Blob bl;
   const int64_t o_steps = bl.add(pk.steps), o_units = bl.add(pk.units), o_wdir = bl.add(pk.wdir);
   const int64_t o_scol = bl.add(pk.scol), o_irow = bl.add(pk.irow);
@@ -1857,6 +1963,7 @@ rh_status upload_sweep(DeviceNet *dn, const Sweep &s, int32_t n, const std::vect
   const int64_t o_sval32 = bl.add(std::vector<float>(pk.sval.begin(), pk.sval.end()));
   const int64_t o_dense32 = bl.add(std::vector<float>(pk.dense.begin(), pk.dense.end()));
   const int64_t o_wrec32 = bl.add(rec32);
+  const int64_t o_wrecc = compact ? bl.add(recc64) : -1, o_wrecc32 = compact ? bl.add(recc32) : -1;
   if (nwu * WaveRec<double>::bytes >= (size_t)kOffRange) {
     err = "network too large for the wave-unit records";
     return RH_EINVAL;
@@ -1876,6 +1983,8 @@ rh_status upload_sweep(DeviceNet *dn, const Sweep &s, int32_t n, const std::vect
   o.n_wunits = (int32_t)nwu;
   o.wrec = at_off<char>(base, o_wrec);
   o.wrec32 = at_off<char>(base, o_wrec32);
+  o.wrecc = compact ? at_off<char>(base, o_wrecc) : nullptr;
+  o.wrecc32 = compact ? at_off<char>(base, o_wrecc32) : nullptr;
   o.n_slots = (int32_t)pk.scol.size();
   o.n_irow = (int32_t)pk.irow.size();
   dn->sweep_steps.push_back(o.n_steps);

@@ -313,6 +313,23 @@ std::vector<int32_t> etree_parent(const LuPlan &lu);
 // Pack a schedule into per-lane slots; `lanes` = workgroup size, wave steps use
 // 64 lanes per wave.
 Packed pack_schedule(const Schedule &sc, int lanes);
+// Device records of the wave units, one fixed-size record per unit, read
+// by the kernel's wave walk with one 16-byte load per lane for each part.
+//  wide (any network), per lane l:
+//    [16 l]          the four column offsets (u32, as wcol)
+//    [1024 + 8 l]    the start and write words (as wrow)
+//    values          FP64: entries 0-1 at [1536 + 16 l], 2-3 at [2560 + 16 l];
+//                    FP32: entries 0-3 at [1536 + 16 l]
+//  compact (padded vectors of at most 65,536 rows), per lane l:
+//    [16 l]          {col 0 | col 1 << 16, col 2 | col 3 << 16,
+//                     start | write << 16, act | two << 1 | lg << 2}, all
+//                     rows as indices (offset / 8)
+//    values          FP64: entries 0-1 at [1024 + 16 l], 2-3 at [2048 + 16 l];
+//                    FP32: entries 0-3 at [1024 + 16 l]
+// Returns false (and no records) if a compact record cannot hold the rows.
+constexpr int kWaveRecWide64 = 3584, kWaveRecWide32 = 2560;
+constexpr int kWaveRecCompact64 = 3072, kWaveRecCompact32 = 2048;
+bool wave_records(const Packed &pk, bool compact, bool fp64, std::vector<char> &out);
 
 // ---- device path (device.hip)
 rh_status device_upload(Network &net, std::string &err);

@@ -10,6 +10,7 @@
 // triangular factors are then grouped into dependency levels for the device
 // sweeps.
 #include <algorithm>
+#include <cstring>
 #include <climits>
 #include <cmath>
 #include <queue>
@@ -1002,6 +1003,49 @@ Packed pack_schedule(const Schedule &sc, int lanes) {
     }
   }
   return pk;
+}
+
+bool wave_records(const Packed &pk, bool compact, bool fp64, std::vector<char> &out) {
+  const size_t nu = pk.wlg.size();
+  const int rb = compact ? (fp64 ? kWaveRecCompact64 : kWaveRecCompact32) : (fp64 ? kWaveRecWide64 : kWaveRecWide32);
+  out.assign(nu * rb, 0);
+  const int vbase = compact ? 1024 : 1536;
+  for (size_t u = 0; u < nu; ++u) {
+    char *r = out.data() + u * rb;
+    for (int l = 0; l < 64; ++l) {
+      const int32_t *wc = &pk.wcol[256 * u + 4 * l];
+      const uint32_t ws = (uint32_t)pk.wrow[128 * u + 2 * l], ww = (uint32_t)pk.wrow[128 * u + 2 * l + 1];
+      if (compact) {
+        uint32_t rows[6];
+        for (int e = 0; e < 4; ++e) rows[e] = (uint32_t)wc[e] >> 3;
+        rows[4] = (ws & kWaveOffMask) >> 3;
+        rows[5] = (ww & kWaveOffMask) >> 3;
+        for (uint32_t v : rows)
+          if (v > 0xffffu) {
+            out.clear();
+            return false;
+          }
+        const uint32_t h[4] = {rows[0] | rows[1] << 16, rows[2] | rows[3] << 16, rows[4] | rows[5] << 16,
+                               ((ws >> kWaveActBit) & 1u) | ((ws >> kWaveTwoBit) & 1u) << 1 |
+                                   (ww >> kWaveLgShift) << 2};
+        std::memcpy(r + 16 * l, h, 16);
+      } else {
+        std::memcpy(r + 16 * l, wc, 16);
+        const uint32_t w2[2] = {ws, ww};
+        std::memcpy(r + 1024 + 8 * l, w2, 8);
+      }
+      for (int e = 0; e < 4; ++e) {
+        const double v = pk.wval[256 * u + 128 * (e >> 1) + 2 * l + (e & 1)];
+        if (fp64) {
+          std::memcpy(r + vbase + 1024 * (e >> 1) + 16 * l + 8 * (e & 1), &v, 8);
+        } else {
+          const float f = (float)v;
+          std::memcpy(r + vbase + 16 * l + 4 * e, &f, 4);
+        }
+      }
+    }
+  }
+  return true;
 }
 
 }  // namespace rh

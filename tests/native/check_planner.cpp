@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstring>
 #include <random>
 #include <vector>
 
@@ -132,6 +133,52 @@ static bool check_wave_walk(const Packed &pk, int n) {
       prev = u;
     }
   }
+  return true;
+}
+
+// The device records of the wave units (wave_records) decoded back, field by
+// field, against the packed arrays: wide and compact, FP64 and FP32.
+static bool check_records(const Packed &pk) {
+  std::vector<char> w64, w32, c64, c32;
+  if (!wave_records(pk, false, true, w64) || !wave_records(pk, false, false, w32)) return false;
+  if (!wave_records(pk, true, true, c64) || !wave_records(pk, true, false, c32)) return false;
+  const size_t nu = pk.wlg.size();
+  if (w64.size() != nu * kWaveRecWide64 || w32.size() != nu * kWaveRecWide32 ||
+      c64.size() != nu * kWaveRecCompact64 || c32.size() != nu * kWaveRecCompact32)
+    return false;
+  auto u32 = [](const char *p) {
+    uint32_t v;
+    std::memcpy(&v, p, 4);
+    return v;
+  };
+  for (size_t u = 0; u < nu; ++u)
+    for (int l = 0; l < 64; ++l) {
+      const uint32_t ws = (uint32_t)pk.wrow[128 * u + 2 * l], ww = (uint32_t)pk.wrow[128 * u + 2 * l + 1];
+      const char *hw = w64.data() + u * kWaveRecWide64, *hw32 = w32.data() + u * kWaveRecWide32;
+      const char *hc = c64.data() + u * kWaveRecCompact64, *hc32 = c32.data() + u * kWaveRecCompact32;
+      for (int e = 0; e < 4; ++e) {
+        const uint32_t col = (uint32_t)pk.wcol[256 * u + 4 * l + e];
+        if (u32(hw + 16 * l + 4 * e) != col || u32(hw32 + 16 * l + 4 * e) != col) return false;
+        const uint32_t hword = u32(hc + 16 * l + 4 * (e >> 1)), hword32 = u32(hc32 + 16 * l + 4 * (e >> 1));
+        const uint32_t row = (e & 1) ? hword >> 16 : hword & 0xffffu;
+        if (hword != hword32 || row * 8u != col) return false;
+        const double v = pk.wval[256 * u + 128 * (e >> 1) + 2 * l + (e & 1)];
+        double a, b;
+        float f, g;
+        std::memcpy(&a, hw + 1536 + 1024 * (e >> 1) + 16 * l + 8 * (e & 1), 8);
+        std::memcpy(&b, hc + 1024 + 1024 * (e >> 1) + 16 * l + 8 * (e & 1), 8);
+        std::memcpy(&f, hw32 + 1536 + 16 * l + 4 * e, 4);
+        std::memcpy(&g, hc32 + 1024 + 16 * l + 4 * e, 4);
+        if (std::memcmp(&a, &v, 8) || std::memcmp(&b, &v, 8) || f != (float)v || g != (float)v) return false;
+      }
+      if (u32(hw + 1024 + 8 * l) != ws || u32(hw + 1028 + 8 * l) != ww) return false;
+      const uint32_t rows = u32(hc + 16 * l + 8), fl = u32(hc + 16 * l + 12);
+      if ((rows & 0xffffu) * 8u != (ws & kWaveOffMask) || (rows >> 16) * 8u != (ww & kWaveOffMask)) return false;
+      if ((fl & 1u) != ((ws >> kWaveActBit) & 1u) || ((fl >> 1) & 1u) != ((ws >> kWaveTwoBit) & 1u) ||
+          (fl >> 2) != (ww >> kWaveLgShift) || (int)(fl >> 2) != pk.wlg[u])
+        return false;
+      if (rows != u32(hc32 + 16 * l + 8) || fl != u32(hc32 + 16 * l + 12)) return false;
+    }
   return true;
 }
 
@@ -389,6 +436,10 @@ int main(int argc, char **argv) {
           emulate_packed(pk, Xa, pend, okp);
           if (!check_wave_walk(pk, nx)) {
             printf("wave_walk_mismatch %s_w%d_b%d\n", nm[k], wave, bmax);
+            okp = false;
+          }
+          if (!check_records(pk)) {
+            printf("record_mismatch %s_w%d_b%d\n", nm[k], wave, bmax);
             okp = false;
           }
           plain(sw[k], Xb);
