@@ -379,7 +379,7 @@ __device__ __forceinline__ T group_sum(T v, int lg) {
   return v;
 }
 
-// The dense inverse of a block (rows <= kBlockRows, column-major) is applied
+// The dense inverse of a block (rows <= kBlockRows, row-major) is applied
 // by all NT threads: NT / kBlockRows lanes per row, each with E entries
 // (columns j, j + lanes, ...) that it loads a step ahead, then a group sum.
 template <int NT>
@@ -405,7 +405,7 @@ __device__ __forceinline__ DenseRow<T, NT> load_dense(const DevSweep AS4 &s, int
   for (int e = 0; e < D::E; ++e) {
     const int32_t b = j + e * D::lanes;
     const bool ok = a < U.rows && b <= a;
-    R.m[e] = Dz[ok ? off + a + b * U.rows : 0];
+    R.m[e] = Dz[ok ? off + a * U.rows + b : 0];
   }
   R.row = s.irow[a < U.rows ? U.info_base + a : 0];  // written only by j == 0, a < rows
   return R;

@@ -82,7 +82,8 @@ constexpr int32_t kWaveBlockRows = 16;
 // Slot 0 and dense[0] are a zero padding entry (offsets start at 1) that
 // lanes without an entry read.
 // steps: 4 ints each {unit or wave directory offset, 0, kind, dense offset},
-// kind 0 = level, 1 = block (dense inverse at the offset), 2 = wave step
+// kind 0 = level, 1 = block (dense inverse at the offset, rows x rows,
+// row-major), 2 = wave step
 // (its waves' wave-unit ranges are wdir[off + w] .. wdir[off + w + 1]).
 //
 // Wave steps: fixed-shape wave units (one wave, one pass, 64 lanes, four

@@ -1000,6 +1000,13 @@ Packed pack_schedule(const Schedule &sc, int lanes) {
     } else {
       const int32_t u = pack_unit(sc, b, rows, lg, lanes, pk);
       pk.steps.insert(pk.steps.end(), {u, 0, kind >= 0 ? 1 : 0, kind >= 0 ? kind + 1 : 0});
+      if (kind >= 0) {
+        // the block's inverse row-major (the lanes of a row read consecutive
+        // columns: whole cache lines)
+        double *M = pk.dense.data() + kind + 1;
+        for (int32_t a = 0; a < rows; ++a)
+          for (int32_t c = 0; c < a; ++c) std::swap(M[(size_t)a + (size_t)c * rows], M[(size_t)a * rows + c]);
+      }
     }
   }
   return pk;

@@ -296,7 +296,7 @@ static void emulate_packed(const Packed &pk, std::vector<double> &X, std::vector
       const int rows = U[2], info_base = U[1];
       for (int x = 0; x < rows; ++x) {
         double acc = 0;
-        for (int c = 0; c <= x; ++c) acc += pk.dense[off + x + (size_t)c * rows] * r[c];
+        for (int c = 0; c <= x; ++c) acc += pk.dense[off + (size_t)x * rows + c] * r[c];
         X[pk.irow[info_base + x]] = acc;
         pending[pk.irow[info_base + x]] = 0;
       }
