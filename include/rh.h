@@ -188,6 +188,14 @@ rh_status rh_get_factors(const rh_network *net, double *l, double *u);
 /* Converged state x (n_x), objective F(p) = f(x(p), p), reduced gradient (n_p). */
 rh_status rh_get_state(const rh_network *net, double *x);
 rh_status rh_objective(const rh_network *net, double *F);
+/* 1-norm condition estimate of G_x at the solved operating point,
+ * ||G_x||_1 times an estimate of ||G_x^{-1}||_1 from a few solves with the
+ * factors (Hager's method with Higham's refinements, the estimator of
+ * LAPACK's xLACON): a lower bound, usually exact or within a small factor.
+ * The pivots are static (diagonal), so a large value warns of an operating
+ * point near the loading limit, where the factors lose accuracy.  Host-side,
+ * synchronous. */
+rh_status rh_condition_estimate(const rh_network *net, double *cond1);
 rh_status rh_reduced_gradient(rh_network *net, double *grad);
 
 /* k reduced-Hessian-vector products HW = (d2 F) W, host buffers (Algorithm 2:

@@ -323,6 +323,16 @@ rh_status rh_objective(const rh_network *net, double *F) {
   return RH_OK;
 }
 
+rh_status rh_condition_estimate(const rh_network *net, double *cond1) {
+  GUARD_BEGIN
+  rh_status s = need_solved(net);
+  if (s != RH_OK) return s;
+  if (!cond1) return fail(RH_EINVAL, "null cond1");
+  *cond1 = condest_1(net->n);
+  return RH_OK;
+  GUARD_END
+}
+
 rh_status rh_reduced_gradient(rh_network *net, double *grad) {
   GUARD_BEGIN
   rh_status s = need_solved(net);

@@ -608,6 +608,63 @@ rh_status network_accept(Network &net, const std::vector<double> &x, int32_t it,
   return RH_OK;
 }
 
+double condest_1(const Network &net) {
+  const int32_t n = net.n_x;
+  if (n == 0) return 0.0;
+  const Csr &A = net.gx;
+  std::vector<double> colsum(n, 0.0);
+  for (int32_t r = 0; r < A.n_rows; ++r)
+    for (int32_t e = A.ptr[r]; e < A.ptr[r + 1]; ++e) colsum[A.col[e]] += std::fabs(A.val[e]);
+  const double anorm = *std::max_element(colsum.begin(), colsum.end());
+  auto norm1 = [](const std::vector<double> &v) {
+    double t = 0.0;
+    for (double e : v) t += std::fabs(e);
+    return t;
+  };
+  auto sgn = [](double v) { return v >= 0.0 ? 1.0 : -1.0; };
+  auto argmax_abs = [](const std::vector<double> &v) {
+    size_t j = 0;
+    for (size_t i = 1; i < v.size(); ++i)
+      if (std::fabs(v[i]) > std::fabs(v[j])) j = i;
+    return j;
+  };
+  // Hager's method with Higham's refinements (LAPACK's xLACON): a lower
+  // bound of ||A^{-1}||_1 from at most five solves with A and A^T
+  std::vector<double> x(n, 1.0 / n), xi(n), z;
+  lu_solve(net.lu, x);
+  double est = norm1(x);
+  if (n > 1) {
+    for (int32_t i = 0; i < n; ++i) xi[i] = sgn(x[i]);
+    z = xi;
+    lu_solve_t(net.lu, z);
+    size_t j = argmax_abs(z);
+    for (int iter = 2; iter <= 5; ++iter) {
+      std::fill(x.begin(), x.end(), 0.0);
+      x[j] = 1.0;
+      lu_solve(net.lu, x);
+      const double prev = est;
+      est = norm1(x);
+      bool same = true;
+      for (int32_t i = 0; i < n && same; ++i) same = sgn(x[i]) == xi[i];
+      if (same || est <= prev) {
+        est = std::max(est, prev);
+        break;
+      }
+      for (int32_t i = 0; i < n; ++i) xi[i] = sgn(x[i]);
+      z = xi;
+      lu_solve_t(net.lu, z);
+      const size_t jl = j;
+      j = argmax_abs(z);
+      if (std::fabs(z[jl]) == std::fabs(z[j])) break;
+    }
+    // the alternating vector, against cancellation in the estimate above
+    for (int32_t i = 0; i < n; ++i) x[i] = (i % 2 ? -1.0 : 1.0) * (1.0 + (double)i / (double)(n - 1));
+    lu_solve(net.lu, x);
+    est = std::max(est, 2.0 * norm1(x) / (3.0 * n));
+  }
+  return anorm * est;
+}
+
 void reduced_gradient(const Network &net, std::vector<double> &grad) {
   std::vector<double> th, v, fx;
   unpack_state(net, net.x, net.p, th, v);

@@ -296,6 +296,9 @@ void flows_inject(const Network &net, const std::vector<double> &th, const std::
 void unpack_state(const Network &net, const std::vector<double> &x, const std::vector<double> &p,
                   std::vector<double> &th, std::vector<double> &v);
 void reduced_gradient(const Network &net, std::vector<double> &grad);
+// 1-norm condition estimate of G_x from its factors (a lower bound that is
+// usually exact or within a small factor).
+double condest_1(const Network &net);
 
 // ---- sparse LU (sparse_lu.cpp)
 void lu_analyse(LuPlan &lu, const Csr &pattern);

@@ -114,6 +114,7 @@ _SIGS = {
     "rh_get_factors": (ctypes.c_int, [ctypes.c_void_p, _f64p, _f64p]),
     "rh_get_state": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
     "rh_objective": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
+    "rh_condition_estimate": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
     "rh_reduced_gradient": (ctypes.c_int, [ctypes.c_void_p, _f64p]),
     "rh_hvp": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _f64p, ctypes.c_int64, _f64p,
                               ctypes.c_int64, ctypes.c_int]),
@@ -331,6 +332,12 @@ def rh_objective(net) -> float:
     f = ctypes.c_double()
     _check(load().rh_objective(net, ctypes.byref(f)))
     return f.value
+
+
+def rh_condition_estimate(net) -> float:
+    c = ctypes.c_double()
+    _check(load().rh_condition_estimate(net, ctypes.byref(c)))
+    return c.value
 
 
 def rh_reduced_gradient(net) -> np.ndarray:
@@ -600,6 +607,7 @@ class Network:
         r = self.report()
         return rh_get_factors(self.h, r["nnz_l"], r["nnz_u"])
     objective = lambda self: rh_objective(self.h)  # noqa: E731
+    condition_estimate = lambda self: rh_condition_estimate(self.h)  # noqa: E731
     reduced_gradient = lambda self: rh_reduced_gradient(self.h)  # noqa: E731
     hvp = lambda self, W, prec=RH_FP64: rh_hvp(self.h, W, prec)  # noqa: E731
     reduced_hessian = lambda self, k_block=0, prec=RH_FP64: rh_reduced_hessian(self.h, k_block, prec)  # noqa

@@ -180,3 +180,32 @@ def test_tracking_and_dense_solve_need_a_device(ctx):
     with pytest.raises(rh.RhError) as ei:
         rh.rh_cholesky_solve_device(ctx.h, 4, None, 4, None, 4, 1)
     assert ei.value.status == rh.RH_EDEVICE and ei.value.failed_col == -1
+
+
+@pytest.mark.parametrize("name", ["c0", "c1"])
+def test_condition_estimate_against_the_exact_one_norm_condition(ctx, name):
+    """The estimate is a lower bound of ||G_x||_1 ||G_x^{-1}||_1 (exact from a
+    dense inverse of the oracle's G_x), within a factor of three."""
+    g = gridgen.config_grid(name, 0)
+    net = rh.Network(ctx, g)
+    net.solve()
+    est = net.condition_estimate()
+    s = solve(g)
+    G = s.Gx.toarray()
+    exact = np.abs(G).sum(axis=0).max() * np.abs(np.linalg.inv(G)).sum(axis=0).max()
+    assert exact / 3.0 <= est <= exact * (1.0 + 1e-10), (est, exact)
+
+
+def test_condition_estimate_grows_toward_the_loading_limit(ctx):
+    """The 1k grid at loading factors 0.30 (the workload), 0.33 and 0.36
+    (its limit is at least 0.375): the condition of G_x rises."""
+    c = gridgen.CONFIGS["c1"]
+    conds = []
+    for alpha in (0.30, 0.33, 0.36):
+        g = gridgen.geometric(c["n_bus"], c["n_branch"], c["n_gen"], 1000, alpha, kappa=c["kappa"])
+        net = rh.Network(ctx, g)
+        net.solve()
+        conds.append(net.condition_estimate())
+    assert conds[0] < conds[1] < conds[2], conds
+    g = gridgen.config_grid("c0", 0)
+    assert _status(rh.rh_condition_estimate, rh.Network(ctx, g).h) == rh.RH_ESTATE
