@@ -11,9 +11,11 @@
 //      order) and max |g|, the one number the host reads per step;
 //   3. the values of G_x on its fixed pattern (per entry, its branch
 //      partials summed in branch order: no atomics);
-//   4. P G_x P^T = L U, row by row with static diagonal pivots, the rows of
+//   4. P G_x P^T = L U with static diagonal pivots: row by row, the rows of
 //      one elimination level at a time (one wave per row, the row's values
-//      in LDS);
+//      in LDS), except the last rows (the top of the elimination tree, where
+//      the factors are nearly dense), which after their steps with earlier
+//      rows are factored as one dense block in LDS;
 //   5. the Newton step from the two triangular solves, and x -= step.
 // After convergence the state and the factors are copied to the host, which
 // forms the first-order adjoint and the branch coefficients from them (it
@@ -65,12 +67,19 @@ struct NtArrays {
   const uint16_t *tgt;           // targets (position in the row) of every update, row by row
   const int4 *step;              // per L position: {U part of the pivot row: start, length; first target; row}
   const int32_t *lev_ptr_l, *lev_rows_l, *lev_ptr_u, *lev_rows_u;
+  // the dense top block: rows b0 .. n_x - 1 (m_blk of them); levels of the
+  // rows below it; per block row its steps with pivot rows below b0 and the
+  // position of every block column in it (-1: none)
+  int32_t b0, m_blk;
+  const int32_t *lev_ptr_f, *lev_rows_f, *ns, *dmap;
 };
 
 // Per-solve device vectors.
 struct NtVectors {
   double *x, *p, *Pd, *Qd, *th, *v, *flows, *dG, *g, *gx, *lu, *y;
   double *rinv;  // 1 / u_ii of every finished row
+  double *S;     // the dense block after the steps with pivot rows below b0 (m_blk x m_blk, row-major)
+  double *amax;  // largest |G_x entry| of every block row (the pivot test)
   double *stat;  // [0] max |g|, [1] non-finite flag, [2] singular pivot row + 1
 };
 
@@ -197,10 +206,12 @@ struct NtOp {
   int32_t tg, ul, kb, us;
 };
 
-__device__ __forceinline__ void nt_factor_row(const NtArgs &A, int32_t i, double *W, int l64) {
+// Row i scattered into W and its first nl elimination steps taken; returns
+// the largest |entry| of the row before elimination.
+__device__ __forceinline__ double nt_eliminate(const NtArgs &A, int32_t i, int32_t nl, double *W, int l64) {
   const NtArrays &a = A.a;
-  double *LU = A.w.lu;
-  const int32_t base = a.row_ptr[i], len = a.row_ptr[i + 1] - base, nl = a.nl[i];
+  const double *LU = A.w.lu;
+  const int32_t base = a.row_ptr[i], len = a.row_ptr[i + 1] - base;
   for (int32_t t = l64; t < len; t += 64) W[t] = 0.0;
   double amax = 0.0;
   for (int32_t t = a.a_ptr[i] + l64; t < a.a_ptr[i + 1]; t += 64) {
@@ -222,10 +233,14 @@ __device__ __forceinline__ void nt_factor_row(const NtArgs &A, int32_t i, double
     o.ul = in ? __builtin_amdgcn_readlane(src.y, j) : 0;
     o.us = __builtin_amdgcn_readlane(src.z, j);
     const int32_t k = __builtin_amdgcn_readlane(src.w, j);
+    // every lane issues the same three loads on every path (an address of
+    // 0 where it has no entry; such values are never used), so the
+    // compiler's wait before a step counts only that step's own loads
+    // instead of draining the whole ring
     const bool ok = in && 1 + l64 < o.ul;
-    o.uv = ok ? LU[o.kb + 1 + l64] : 0.0;
-    o.tg = ok ? (int32_t)a.tgt[o.us + l64] : 0;
-    o.rk = in ? A.w.rinv[k] : 0.0;
+    o.uv = LU[ok ? o.kb + 1 + l64 : 0];
+    o.tg = a.tgt[ok ? o.us + l64 : 0];
+    o.rk = A.w.rinv[in ? k : 0];
   };
   constexpr int kD = 4;
   NtOp ring[kD];
@@ -254,32 +269,121 @@ __device__ __forceinline__ void nt_factor_row(const NtArgs &A, int32_t i, double
       load_op(q + kD, ring[d]);
     }
   }
-  for (int32_t t = l64; t < len; t += 64) LU[base + t] = W[t];
+  __builtin_amdgcn_wave_barrier();
+  return amax;
+}
+
+// A pivot below 1e-13 times its row's largest entry (or not finite) marks
+// the row as singular.
+__device__ __forceinline__ void nt_check_pivot(const NtArgs &A, int32_t i, double d, double amax) {
+  if (!isfinite(d) || !(fabs(d) > 1e-13 * amax) || amax == 0.0) A.w.stat[2] = (double)(i + 1);
+}
+
+__device__ __forceinline__ void nt_factor_row(const NtArgs &A, int32_t i, double *W, int l64) {
+  const int32_t base = A.a.row_ptr[i], len = A.a.row_ptr[i + 1] - base, nl = A.a.nl[i];
+  const double amax = nt_eliminate(A, i, nl, W, l64);
+  for (int32_t t = l64; t < len; t += 64) A.w.lu[base + t] = W[t];
   if (l64 == 0) {
     const double d = W[nl];
     A.w.rinv[i] = 1.0 / d;
-    if (!isfinite(d) || !(fabs(d) > 1e-13 * amax) || amax == 0.0) A.w.stat[2] = (double)(i + 1);
+    nt_check_pivot(A, i, d, amax);
   }
 }
 
-// One wide level: a wave per row over many workgroups of four waves.
+// Block row r: its steps with pivot rows below b0; the finished L entries
+// go to the factors, the rest (columns b0 and up) into row r of S.
+__device__ __forceinline__ void nt_block_row(const NtArgs &A, int32_t r, double *W, int l64) {
+  const int32_t m = A.a.m_blk, i = A.a.b0 + r, base = A.a.row_ptr[i], ns = A.a.ns[r];
+  const double amax = nt_eliminate(A, i, ns, W, l64);
+  for (int32_t t = l64; t < ns; t += 64) A.w.lu[base + t] = W[t];
+  for (int32_t c = l64; c < m; c += 64) {
+    const int32_t p = A.a.dmap[(int64_t)r * m + c];
+    A.w.S[(int64_t)r * m + c] = p >= 0 ? W[p] : 0.0;
+  }
+  if (l64 == 0) A.w.amax[r] = amax;
+}
+
+// One wide level of the rows below b0: a wave per row over many workgroups
+// of four waves.
 constexpr int kNtWideWaves = 4;
 __global__ __launch_bounds__(64 * kNtWideWaves) void nt_refactor_level(const NtArgs A, int32_t lev) {
   extern __shared__ double s_w[];
   const int wv = threadIdx.x >> 6, l64 = threadIdx.x & 63;
-  const int32_t idx = A.a.lev_ptr_l[lev] + blockIdx.x * kNtWideWaves + wv;
-  if (idx < A.a.lev_ptr_l[lev + 1]) nt_factor_row(A, A.a.lev_rows_l[idx], s_w + (int64_t)wv * A.a.maxpat, l64);
+  const int32_t idx = A.a.lev_ptr_f[lev] + blockIdx.x * kNtWideWaves + wv;
+  if (idx < A.a.lev_ptr_f[lev + 1]) nt_factor_row(A, A.a.lev_rows_f[idx], s_w + (int64_t)wv * A.a.maxpat, l64);
 }
 
-// Levels lev0 .. lev1 - 1 by one workgroup, a barrier between levels.
+// Levels lev0 .. lev1 - 1 of the rows below b0 by one workgroup, a barrier
+// between levels.
 __global__ __launch_bounds__(kNtThreads) void nt_refactor_run(const NtArgs A, int32_t lev0, int32_t lev1) {
   extern __shared__ double s_w[];
   const int wv = threadIdx.x >> 6, l64 = threadIdx.x & 63;
   double *W = s_w + (int64_t)wv * A.a.maxpat;
   for (int32_t lev = lev0; lev < lev1; ++lev) {
-    for (int32_t idx = A.a.lev_ptr_l[lev] + wv; idx < A.a.lev_ptr_l[lev + 1]; idx += kNtWaves)
-      nt_factor_row(A, A.a.lev_rows_l[idx], W, l64);
+    for (int32_t idx = A.a.lev_ptr_f[lev] + wv; idx < A.a.lev_ptr_f[lev + 1]; idx += kNtWaves)
+      nt_factor_row(A, A.a.lev_rows_f[idx], W, l64);
     __syncthreads();
+  }
+}
+
+// The block rows' steps with pivot rows below b0 (all final), a wave per row.
+__global__ __launch_bounds__(64 * kNtWideWaves) void nt_block_rows(const NtArgs A) {
+  extern __shared__ double s_w[];
+  const int wv = threadIdx.x >> 6, l64 = threadIdx.x & 63;
+  const int32_t r = blockIdx.x * kNtWideWaves + wv;
+  if (r < A.a.m_blk) nt_block_row(A, r, s_w + (int64_t)wv * A.a.maxpat, l64);
+}
+
+// The dense block S = L_b U_b in LDS by one workgroup, right-looking with
+// static pivots: at column c, every entry (r, j) with r, j > c loses
+// (s_rc / s_cc) s_cj.  Each entry thus receives its updates in ascending
+// pivot order with l = s_rc * (1 / s_cc), as in the row-by-row elimination,
+// so the factors agree with it.  Column c of L is scaled at the end (the
+// unscaled s_rc stays in place while column c is the pivot column).  The
+// thread that updates the next pivot forms its reciprocal at once, so a
+// column step holds one barrier and no division or global access; the
+// pivots are tested after the last step.  The results go to the factors
+// through dmap, with the pivot reciprocals.
+constexpr int kNtDenseCols = 128;  // threads along a row; kNtThreads / kNtDenseCols row groups
+static_assert(kNtDenseCols >= kNtDenseTop, "one thread per block column");
+__global__ __launch_bounds__(kNtThreads) void nt_dense_lu(const NtArgs A) {
+  extern __shared__ double s_t[];
+  const int32_t m = A.a.m_blk, b0 = A.a.b0, ld = m + 1;
+  double *T = s_t, *R = s_t + (int64_t)m * ld;
+  const int tid = threadIdx.x, j = tid % kNtDenseCols, rg = tid / kNtDenseCols;
+  constexpr int kRg = kNtThreads / kNtDenseCols, kRows = (kNtDenseTop + kRg - 1) / kRg;
+  for (int32_t e = tid; e < m * m; e += kNtThreads) T[(e / m) * ld + e % m] = A.w.S[e];
+  if (tid == 0) R[0] = 1.0 / A.w.S[0];
+  __syncthreads();
+  for (int32_t c = 0; c < m; ++c) {
+    const double rp = R[c];
+    if (j > c && j < m) {
+      // this thread's rows: all loads first, then the updates
+      const double u = T[c * ld + j];
+      double sc[kRows], t[kRows];
+#pragma unroll
+      for (int k = 0; k < kRows; ++k) {
+        const int32_t r = c + 1 + rg + k * kRg;
+        sc[k] = r < m ? T[r * ld + c] : 0.0;
+        t[k] = r < m ? T[r * ld + j] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < kRows; ++k) {
+        const int32_t r = c + 1 + rg + k * kRg;
+        t[k] -= (sc[k] * rp) * u;
+        if (r < m) T[r * ld + j] = t[k];
+      }
+      if (rg == 0 && j == c + 1) R[c + 1] = 1.0 / t[0];  // the next pivot is final now
+    }
+    __syncthreads();
+  }
+  for (int32_t r = tid; r < m; r += kNtThreads) {
+    nt_check_pivot(A, b0 + r, T[r * ld + r], A.w.amax[r]);
+    A.w.rinv[b0 + r] = R[r];
+  }
+  for (int32_t e = tid; e < m * m; e += kNtThreads) {
+    const int32_t r = e / m, c = e % m, p = A.a.dmap[e];
+    if (p >= 0) A.w.lu[A.a.row_ptr[b0 + r] + p] = c < r ? T[r * ld + c] * R[c] : T[r * ld + c];
   }
 }
 
@@ -356,7 +460,9 @@ struct DevNewton {
   std::vector<int32_t> row_ptr;  // host copy (unpacking the factors)
   // levels with many rows run as launches of their own over many workgroups,
   // every run of the other levels as one launch of one workgroup
-  std::vector<int32_t> lev_rows_l, lev_rows_u;  // rows per level
+  std::vector<int32_t> lev_rows_l, lev_rows_u;  // rows per level (the solves)
+  std::vector<int32_t> lev_rows_f;              // rows per level below the dense block
+  size_t lds_dense = 0;
 };
 
 // A level is wide with at least this many rows.
@@ -459,6 +565,7 @@ rh_status nt_build(Network &net, DevNewton &d, std::string &err) {
       NT_UP(st, a.step);
     }
     for (size_t l = 0; l + 1 < mp.lev_ptr_l.size(); ++l) d.lev_rows_l.push_back(mp.lev_ptr_l[l + 1] - mp.lev_ptr_l[l]);
+    for (size_t l = 0; l + 1 < mp.lev_ptr_f.size(); ++l) d.lev_rows_f.push_back(mp.lev_ptr_f[l + 1] - mp.lev_ptr_f[l]);
     for (size_t l = 0; l + 1 < mp.lev_ptr_u.size(); ++l) d.lev_rows_u.push_back(mp.lev_ptr_u[l + 1] - mp.lev_ptr_u[l]);
     d.row_ptr = mp.row_ptr;
     a.n_lev_l = lu.n_levels_l;
@@ -467,7 +574,14 @@ rh_status nt_build(Network &net, DevNewton &d, std::string &err) {
     NT_UP(mp.lev_rows_l, a.lev_rows_l);
     NT_UP(mp.lev_ptr_u, a.lev_ptr_u);
     NT_UP(mp.lev_rows_u, a.lev_rows_u);
+    a.b0 = mp.b0;
+    a.m_blk = n - mp.b0;
+    NT_UP(mp.lev_ptr_f, a.lev_ptr_f);
+    NT_UP(mp.lev_rows_f, a.lev_rows_f);
+    NT_UP(mp.ns, a.ns);
+    NT_UP(mp.dmap, a.dmap);
     d.lds_bytes = (size_t)mp.maxpat * sizeof(double) * kNtWaves;
+    d.lds_dense = ((size_t)a.m_blk * (a.m_blk + 1) + a.m_blk) * sizeof(double);
   }
   NtVectors &w = d.args.w;
   rh_status s;
@@ -478,10 +592,14 @@ rh_status nt_build(Network &net, DevNewton &d, std::string &err) {
       (s = nt_alloc(d, 16 * (size_t)m, &w.dG, err)) != RH_OK || (s = nt_alloc(d, net.n_x, &w.g, err)) != RH_OK ||
       (s = nt_alloc(d, a.nnz_gx, &w.gx, err)) != RH_OK || (s = nt_alloc(d, a.nnz_lu, &w.lu, err)) != RH_OK ||
       (s = nt_alloc(d, net.n_x, &w.y, err)) != RH_OK || (s = nt_alloc(d, 4, &w.stat, err)) != RH_OK ||
-      (s = nt_alloc(d, net.n_x, &w.rinv, err)) != RH_OK)
+      (s = nt_alloc(d, net.n_x, &w.rinv, err)) != RH_OK ||
+      (s = nt_alloc(d, (size_t)a.m_blk * a.m_blk, &w.S, err)) != RH_OK ||
+      (s = nt_alloc(d, a.m_blk, &w.amax, err)) != RH_OK)
     return s;
   HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&nt_refactor_run),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)d.lds_bytes));
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&nt_dense_lu),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)d.lds_dense));
   return RH_OK;
 }
 
@@ -494,18 +612,25 @@ rh_status nt_step_kernels(DevNewton &d, int32_t m, int32_t nb, int32_t nnz_gx, b
   if (jacobian) {
     hipLaunchKernelGGL(nt_gx, dim3((nnz_gx + T - 1) / T), dim3(T), 0, nullptr, d.args);
     const size_t lds_w = (size_t)d.args.a.maxpat * sizeof(double) * kNtWideWaves;
-    const int32_t nlev = (int32_t)d.lev_rows_l.size();
+    const std::vector<int32_t> &rows = d.lev_rows_f;
+    const int32_t nlev = (int32_t)rows.size();
     for (int32_t l = 0; l < nlev;) {
-      if (d.lev_rows_l[l] >= kWideRows) {
-        hipLaunchKernelGGL(nt_refactor_level, dim3((d.lev_rows_l[l] + kNtWideWaves - 1) / kNtWideWaves),
+      if (rows[l] >= kWideRows) {
+        hipLaunchKernelGGL(nt_refactor_level, dim3((rows[l] + kNtWideWaves - 1) / kNtWideWaves),
                            dim3(64 * kNtWideWaves), lds_w, nullptr, d.args, l);
         ++l;
         continue;
       }
       int32_t l1 = l;
-      while (l1 < nlev && d.lev_rows_l[l1] < kWideRows) ++l1;
+      while (l1 < nlev && rows[l1] < kWideRows) ++l1;
       hipLaunchKernelGGL(nt_refactor_run, dim3(1), dim3(kNtThreads), d.lds_bytes, nullptr, d.args, l, l1);
       l = l1;
+    }
+    const int32_t mb = d.args.a.m_blk;
+    if (mb > 0) {
+      hipLaunchKernelGGL(nt_block_rows, dim3((mb + kNtWideWaves - 1) / kNtWideWaves), dim3(64 * kNtWideWaves),
+                         lds_w, nullptr, d.args);
+      hipLaunchKernelGGL(nt_dense_lu, dim3(1), dim3(kNtThreads), d.lds_dense, nullptr, d.args);
     }
   }
   HIP_TRY(hipGetLastError());

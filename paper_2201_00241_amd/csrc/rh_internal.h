@@ -246,7 +246,17 @@ struct LuMaps {
   std::vector<int32_t> step;  // 4 per factor position (only L positions used)
   std::vector<int32_t> lev_ptr_l, lev_rows_l, lev_ptr_u, lev_rows_u;
   int32_t maxpat = 0;
+  // The refactorisation treats the last n - b0 rows (the top of the
+  // elimination tree, nearly dense) as one dense block: rows below b0 are
+  // factored level by level (lev_ptr_f, lev_rows_f: the L levels restricted
+  // to them, empty levels dropped); a block row first takes its ns steps
+  // with pivot rows below b0, then the block is factored densely.  dmap[r m
+  // + c] is the position of column b0 + c in row b0 + r, or -1.
+  int32_t b0 = 0;
+  std::vector<int32_t> lev_ptr_f, lev_rows_f, ns, dmap;
 };
+// Rows in the dense top block of the device refactorisation (at most).
+constexpr int32_t kNtDenseTop = 128;
 bool lu_device_maps(const LuPlan &lu, const Csr &gx, LuMaps &mp, std::string &err);
 // Newton on the device (newton.hip): the state and the factors of G_x at it
 // are returned (x in res, the factor values in net.lu).

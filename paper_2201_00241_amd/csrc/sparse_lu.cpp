@@ -812,6 +812,29 @@ bool lu_device_maps(const LuPlan &lu, const Csr &gx, LuMaps &mp, std::string &er
   }
   group_levels(lu.level_l, lu.n_levels_l, mp.lev_ptr_l, mp.lev_rows_l);
   group_levels(lu.level_u, lu.n_levels_u, mp.lev_ptr_u, mp.lev_rows_u);
+  // the dense top block and the levels of the rows below it (a row below b0
+  // depends only on earlier rows, so its level stands; levels left empty are
+  // dropped)
+  const int32_t b0 = n - std::min<int32_t>(kNtDenseTop, n), mb = n - b0;
+  mp.b0 = b0;
+  {
+    std::vector<int32_t> renum(lu.n_levels_l, -1), lvf(b0);
+    for (int32_t i = 0; i < b0; ++i) renum[lu.level_l[i]] = 0;
+    int32_t nf = 0;
+    for (int32_t l = 0; l < lu.n_levels_l; ++l)
+      if (renum[l] == 0) renum[l] = nf++;
+    for (int32_t i = 0; i < b0; ++i) lvf[i] = renum[lu.level_l[i]];
+    group_levels(lvf, nf, mp.lev_ptr_f, mp.lev_rows_f);
+  }
+  mp.ns.assign(mb, 0);
+  mp.dmap.assign((size_t)mb * mb, -1);
+  for (int32_t r = 0; r < mb; ++r) {
+    const int32_t i = b0 + r, base = mp.row_ptr[i], len = mp.row_ptr[i + 1] - base;
+    int32_t q = 0;
+    while (q < mp.nl[i] && mp.lucol[base + q] < b0) ++q;
+    mp.ns[r] = q;
+    for (; q < len; ++q) mp.dmap[(size_t)r * mb + (mp.lucol[base + q] - b0)] = q;
+  }
   return true;
 }
 

@@ -451,10 +451,12 @@ int main(int argc, char **argv) {
                relerr(X, Y), sc.meta.size() / 4, waves, ok ? 1 : 0);
       }
   printf("order_violations %d\n", bad);
-  // the device refactorisation's maps, replayed on the host in the kernel's
-  // order (levels of rows, each row in a buffer: scatter G_x, eliminate with
-  // the L part's rows in ascending order at the mapped positions), against
-  // the host factorisation of the same G_x
+  // the device refactorisation's maps, replayed on the host in the kernels'
+  // order (levels of the rows below the dense block, each row in a buffer:
+  // scatter G_x, eliminate with the L part's rows in ascending order at the
+  // mapped positions; then the block rows' steps with rows below it into the
+  // dense block; then its dense right-looking LU, written back through the
+  // block's position map), against the host factorisation of the same G_x
   {
     LuMaps mp;
     std::string e2;
@@ -466,26 +468,72 @@ int main(int argc, char **argv) {
     std::vector<double> LU(mp.row_ptr[nx], std::nan("")), W(mp.maxpat);
     std::vector<char> done(nx, 0);
     int level_bad = 0;
-    for (size_t lev = 0; lev + 1 < mp.lev_ptr_l.size(); ++lev) {
-      for (int32_t idx = mp.lev_ptr_l[lev]; idx < mp.lev_ptr_l[lev + 1]; ++idx) {
-        const int32_t i = mp.lev_rows_l[idx], base = mp.row_ptr[i], len = mp.row_ptr[i + 1] - base;
-        std::fill(W.begin(), W.begin() + len, 0.0);
-        for (int32_t t = mp.a_ptr[i]; t < mp.a_ptr[i + 1]; ++t) W[mp.a_dst[t]] = net.gx.val[mp.a_src[t]];
-        int64_t u = mp.upd_ptr[i];
-        for (int32_t q = 0; q < mp.nl[i]; ++q) {
-          const int32_t k = mp.lucol[base + q];
-          if (!done[k]) ++level_bad;  // row k must be final (an earlier level)
-          const int32_t kb = mp.row_ptr[k] + mp.nl[k], ul = mp.row_ptr[k + 1] - kb;
-          const double l = W[q] / LU[kb];
-          W[q] = l;
-          for (int32_t s2 = 1; s2 < ul; ++s2) W[mp.tgt[u + s2 - 1]] -= l * LU[kb + s2];
-          u += ul - 1;
-        }
-        if (u != mp.upd_ptr[i + 1]) ++level_bad;
-        for (int32_t t = 0; t < len; ++t) LU[base + t] = W[t];
+    // row i into W with its first ns steps
+    auto eliminate = [&](int32_t i, int32_t ns) {
+      const int32_t base = mp.row_ptr[i], len = mp.row_ptr[i + 1] - base;
+      std::fill(W.begin(), W.begin() + len, 0.0);
+      for (int32_t t = mp.a_ptr[i]; t < mp.a_ptr[i + 1]; ++t) W[mp.a_dst[t]] = net.gx.val[mp.a_src[t]];
+      int64_t u = mp.upd_ptr[i];
+      for (int32_t q = 0; q < ns; ++q) {
+        const int32_t k = mp.lucol[base + q];
+        if (!done[k]) ++level_bad;  // row k must be final (an earlier level)
+        const int32_t kb = mp.row_ptr[k] + mp.nl[k], ul = mp.row_ptr[k + 1] - kb;
+        const double l = W[q] / LU[kb];
+        W[q] = l;
+        for (int32_t s2 = 1; s2 < ul; ++s2) W[mp.tgt[u + s2 - 1]] -= l * LU[kb + s2];
+        u += ul - 1;
       }
-      for (int32_t idx = mp.lev_ptr_l[lev]; idx < mp.lev_ptr_l[lev + 1]; ++idx) done[mp.lev_rows_l[idx]] = 1;
+      if (ns == mp.nl[i] && u != mp.upd_ptr[i + 1]) ++level_bad;
+    };
+    const int32_t b0 = mp.b0, mb = nx - b0;
+    if (mb < 1 || mb > kNtDenseTop || (int32_t)mp.ns.size() != mb) ++level_bad;
+    int32_t nf = 0;
+    for (size_t lev = 0; lev + 1 < mp.lev_ptr_f.size(); ++lev) {
+      if (mp.lev_ptr_f[lev + 1] == mp.lev_ptr_f[lev]) ++level_bad;  // empty levels are dropped
+      for (int32_t idx = mp.lev_ptr_f[lev]; idx < mp.lev_ptr_f[lev + 1]; ++idx) {
+        const int32_t i = mp.lev_rows_f[idx], base = mp.row_ptr[i], len = mp.row_ptr[i + 1] - base;
+        if (i >= b0 || done[i]) ++level_bad;
+        eliminate(i, mp.nl[i]);
+        for (int32_t t = 0; t < len; ++t) LU[base + t] = W[t];
+        ++nf;
+      }
+      for (int32_t idx = mp.lev_ptr_f[lev]; idx < mp.lev_ptr_f[lev + 1]; ++idx) done[mp.lev_rows_f[idx]] = 1;
     }
+    if (nf != b0) ++level_bad;  // every row below the block exactly once
+    // the block rows: steps with rows below b0, the rest into S
+    std::vector<double> S((size_t)mb * mb, 0.0);
+    for (int32_t r = 0; r < mb; ++r) {
+      const int32_t i = b0 + r, base = mp.row_ptr[i], len = mp.row_ptr[i + 1] - base, ns = mp.ns[r];
+      eliminate(i, ns);
+      for (int32_t t = 0; t < ns; ++t) LU[base + t] = W[t];
+      int32_t mapped = 0;
+      for (int32_t c = 0; c < mb; ++c) {
+        const int32_t q = mp.dmap[(size_t)r * mb + c];
+        if (q < 0) continue;
+        if (q < ns || q >= len || mp.lucol[base + q] != b0 + c) ++level_bad;
+        S[(size_t)r * mb + c] = W[q];
+        ++mapped;
+      }
+      if (mapped != len - ns) ++level_bad;  // the map covers the rest of the row
+      for (int32_t q = ns; q < mp.nl[i]; ++q)
+        if (mp.lucol[base + q] < b0) ++level_bad;
+    }
+    // the dense block, right-looking, then written back
+    for (int32_t c = 0; c < mb; ++c)
+      for (int32_t r = c + 1; r < mb; ++r) {
+        const double l = S[(size_t)r * mb + c] / S[(size_t)c * mb + c];
+        for (int32_t j = c + 1; j < mb; ++j) S[(size_t)r * mb + j] -= l * S[(size_t)c * mb + j];
+      }
+    for (int32_t r = 0; r < mb; ++r)
+      for (int32_t c = 0; c < mb; ++c) {
+        const int32_t q = mp.dmap[(size_t)r * mb + c];
+        const double v = S[(size_t)r * mb + c];
+        if (q < 0) {
+          if (v != 0.0) ++level_bad;  // no fill outside the pattern
+          continue;
+        }
+        LU[mp.row_ptr[b0 + r] + q] = c < r ? v / S[(size_t)c * mb + c] : v;
+      }
     double e = 0.0, mx = 0.0;
     for (int32_t i = 0; i < nx; ++i) {
       const int32_t base = mp.row_ptr[i];
