@@ -334,56 +334,107 @@ __global__ __launch_bounds__(64 * kNtWideWaves) void nt_block_rows(const NtArgs 
   if (r < A.a.m_blk) nt_block_row(A, r, s_w + (int64_t)wv * A.a.maxpat, l64);
 }
 
-// The dense block S = L_b U_b in LDS by one workgroup, right-looking with
-// static pivots: at column c, every entry (r, j) with r, j > c loses
+// The dense block S = L_b U_b by one workgroup, right-looking with static
+// pivots: at column c, every entry (r, j) with r, j > c loses
 // (s_rc / s_cc) s_cj.  Each entry thus receives its updates in ascending
 // pivot order with l = s_rc * (1 / s_cc), as in the row-by-row elimination,
-// so the factors agree with it.  Column c of L is scaled at the end (the
-// unscaled s_rc stays in place while column c is the pivot column).  The
-// thread that updates the next pivot forms its reciprocal at once, so a
-// column step holds one barrier and no division or global access; the
-// pivots are tested after the last step.  The results go to the factors
-// through dmap, with the pivot reciprocals.
-constexpr int kNtDenseCols = 128;  // threads along a row; kNtThreads / kNtDenseCols row groups
+// so the factors agree with it.  The block stays in registers: thread
+// (column j, row group g) holds rows g, g + 8, ..., g + 120 of column j.  Before
+// step c the threads of column c publish its entries below the diagonal,
+// the threads holding row c its entries right of the diagonal and the
+// reciprocal of the pivot, into one of two LDS buffers (zeros elsewhere, so
+// every thread updates all its entries with no test: a zero multiplier or
+// pivot-row entry leaves an entry unchanged); one barrier per step.  Column
+// c of L is scaled at the write-back (the unscaled s_rc is what step c
+// publishes).  The results go to the factors through dmap, with the pivot
+// reciprocals.
+constexpr int kNtDenseCols = 128;                         // threads along a row
+constexpr int kNtDenseGroups = kNtThreads / kNtDenseCols;  // row groups
+constexpr int kNtDenseRows = kNtDenseCols / kNtDenseGroups;  // rows per thread
 static_assert(kNtDenseCols >= kNtDenseTop, "one thread per block column");
+static_assert(kNtDenseCols == 128 && kNtThreads == 1024, "the wave layout below");
+struct NtDenseLds {
+  double col[2][kNtDenseCols];  // pivot column, row g + 8 k at g * kNtDenseRows + k
+  double row[2][kNtDenseCols];  // pivot row, by column
+  double rinv[kNtDenseCols];    // pivot reciprocals
+};
+
+__device__ __forceinline__ void nt_dense_publish(NtDenseLds &L, const double (&t)[kNtDenseRows], int32_t c,
+                                                 int32_t m, int j, int g) {
+  const int b = c & 1;
+  if (j == c) {
+#pragma unroll
+    for (int k = 0; k < kNtDenseRows; ++k) {
+      const int32_t r = g + k * kNtDenseGroups;
+      L.col[b][g * kNtDenseRows + k] = r > c && r < m ? t[k] : 0.0;
+    }
+  }
+  if (g == c % kNtDenseGroups) {
+    const int kc = c / kNtDenseGroups;
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < kNtDenseRows; ++k) v = k == kc ? t[k] : v;
+    L.row[b][j] = j > c && j < m ? v : 0.0;
+    if (j == c) L.rinv[c] = 1.0 / v;
+  }
+}
+
 __global__ __launch_bounds__(kNtThreads) void nt_dense_lu(const NtArgs A) {
-  extern __shared__ double s_t[];
-  const int32_t m = A.a.m_blk, b0 = A.a.b0, ld = m + 1;
-  double *T = s_t, *R = s_t + (int64_t)m * ld;
-  const int tid = threadIdx.x, j = tid % kNtDenseCols, rg = tid / kNtDenseCols;
-  constexpr int kRg = kNtThreads / kNtDenseCols, kRows = (kNtDenseTop + kRg - 1) / kRg;
-  for (int32_t e = tid; e < m * m; e += kNtThreads) T[(e / m) * ld + e % m] = A.w.S[e];
-  if (tid == 0) R[0] = 1.0 / A.w.S[0];
+  __shared__ NtDenseLds L;
+  const int32_t m = A.a.m_blk, b0 = A.a.b0;
+  // Wave w takes the column half (w / 4) mod 2 and the row group
+  // w mod 4 + 4 (w / 8): the four waves that share a SIMD (w mod 4) hold
+  // both halves, so the SIMDs stay evenly loaded once the first half's
+  // columns are finished.  The row group is the same for a whole wave.
+  const int tid = threadIdx.x, w = tid >> 6;
+  const int j = (tid & 63) + 64 * ((w >> 2) & 1);
+  const int g = __builtin_amdgcn_readfirstlane((w & 3) + 4 * (w >> 3));
+  // the block, and (for the write-back, loaded now so that their latency
+  // hides behind the steps) each entry's factor position and the row
+  // maximum of this column's diagonal entry
+  // (every load from a clamped address, so that none waits for another;
+  // the entries outside the block are masked afterwards)
+  double t[kNtDenseRows];
+  int32_t pos[kNtDenseRows], base[kNtDenseRows];
+  uint32_t in = 0;
+#pragma unroll
+  for (int k = 0; k < kNtDenseRows; ++k) {
+    const int32_t r = g + k * kNtDenseGroups;
+    const bool ok = r < m && j < m;
+    in |= (uint32_t)ok << k;
+    const int64_t e = ok ? (int64_t)r * m + j : 0;
+    t[k] = A.w.S[e];
+    pos[k] = A.a.dmap[e];
+    base[k] = A.a.row_ptr[b0 + (r < m ? r : m - 1)];
+  }
+  const double amax = A.w.amax[j < m ? j : 0];
+#pragma unroll
+  for (int k = 0; k < kNtDenseRows; ++k) t[k] = (in >> k) & 1 ? t[k] : 0.0;
+  nt_dense_publish(L, t, 0, m, j, g);
   __syncthreads();
   for (int32_t c = 0; c < m; ++c) {
-    const double rp = R[c];
-    if (j > c && j < m) {
-      // this thread's rows: all loads first, then the updates
-      const double u = T[c * ld + j];
-      double sc[kRows], t[kRows];
+    const int b = c & 1;
+    // a wave whose columns are all finished has nothing to update, nor a
+    // wave's finished rows (tests uniform over the wave)
+    if ((j | 63) > c) {
+      const double rp = L.rinv[c], u = L.row[b][j];
+      const double *cb = &L.col[b][g * kNtDenseRows];
 #pragma unroll
-      for (int k = 0; k < kRows; ++k) {
-        const int32_t r = c + 1 + rg + k * kRg;
-        sc[k] = r < m ? T[r * ld + c] : 0.0;
-        t[k] = r < m ? T[r * ld + j] : 0.0;
-      }
-#pragma unroll
-      for (int k = 0; k < kRows; ++k) {
-        const int32_t r = c + 1 + rg + k * kRg;
-        t[k] -= (sc[k] * rp) * u;
-        if (r < m) T[r * ld + j] = t[k];
-      }
-      if (rg == 0 && j == c + 1) R[c + 1] = 1.0 / t[0];  // the next pivot is final now
+      for (int k = 0; k < kNtDenseRows; ++k)
+        if (g + k * kNtDenseGroups > c) t[k] -= (cb[k] * rp) * u;
     }
+    if (c + 1 < m) nt_dense_publish(L, t, c + 1, m, j, g);
     __syncthreads();
   }
-  for (int32_t r = tid; r < m; r += kNtThreads) {
-    nt_check_pivot(A, b0 + r, T[r * ld + r], A.w.amax[r]);
-    A.w.rinv[b0 + r] = R[r];
-  }
-  for (int32_t e = tid; e < m * m; e += kNtThreads) {
-    const int32_t r = e / m, c = e % m, p = A.a.dmap[e];
-    if (p >= 0) A.w.lu[A.a.row_ptr[b0 + r] + p] = c < r ? T[r * ld + c] * R[c] : T[r * ld + c];
+#pragma unroll
+  for (int k = 0; k < kNtDenseRows; ++k) {
+    const int32_t r = g + k * kNtDenseGroups;
+    if (!((in >> k) & 1)) continue;
+    if (j == r) {
+      nt_check_pivot(A, b0 + r, t[k], amax);
+      A.w.rinv[b0 + r] = L.rinv[r];
+    }
+    if (pos[k] >= 0) A.w.lu[base[k] + pos[k]] = j < r ? t[k] * L.rinv[j] : t[k];
   }
 }
 
@@ -462,7 +513,6 @@ struct DevNewton {
   // every run of the other levels as one launch of one workgroup
   std::vector<int32_t> lev_rows_l, lev_rows_u;  // rows per level (the solves)
   std::vector<int32_t> lev_rows_f;              // rows per level below the dense block
-  size_t lds_dense = 0;
 };
 
 // A level is wide with at least this many rows.
@@ -581,7 +631,6 @@ rh_status nt_build(Network &net, DevNewton &d, std::string &err) {
     NT_UP(mp.ns, a.ns);
     NT_UP(mp.dmap, a.dmap);
     d.lds_bytes = (size_t)mp.maxpat * sizeof(double) * kNtWaves;
-    d.lds_dense = ((size_t)a.m_blk * (a.m_blk + 1) + a.m_blk) * sizeof(double);
   }
   NtVectors &w = d.args.w;
   rh_status s;
@@ -598,8 +647,7 @@ rh_status nt_build(Network &net, DevNewton &d, std::string &err) {
     return s;
   HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&nt_refactor_run),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)d.lds_bytes));
-  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&nt_dense_lu),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)d.lds_dense));
+
   return RH_OK;
 }
 
@@ -630,7 +678,7 @@ rh_status nt_step_kernels(DevNewton &d, int32_t m, int32_t nb, int32_t nnz_gx, b
     if (mb > 0) {
       hipLaunchKernelGGL(nt_block_rows, dim3((mb + kNtWideWaves - 1) / kNtWideWaves), dim3(64 * kNtWideWaves),
                          lds_w, nullptr, d.args);
-      hipLaunchKernelGGL(nt_dense_lu, dim3(1), dim3(kNtThreads), d.lds_dense, nullptr, d.args);
+      hipLaunchKernelGGL(nt_dense_lu, dim3(1), dim3(kNtThreads), 0, nullptr, d.args);
     }
   }
   HIP_TRY(hipGetLastError());
