@@ -38,7 +38,9 @@
 #include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <exception>
 #include <mutex>
+#include <thread>
 
 #include "rh_internal.h"
 
@@ -1940,54 +1942,113 @@ const T *at_off(const char *base, int64_t off) {
 // One sweep in one allocation: the layout and entry columns first (read in
 // both precisions), then the FP64 values and block inverses, then their FP32
 // copies, so that each precision's working set is two contiguous ranges.
-rh_status upload_sweep(DeviceNet *dn, const Sweep &s, int32_t n, const std::vector<int32_t> &parent,
-                       bool forward, const ScheduleParams &prm, DevSweep &o, ScheduleCut *cut, std::string &err) {
+// The host part (schedule, packing, records) is prepare_sweep, which touches
+// nothing shared, so the four sweeps of a network are prepared on threads of
+// their own; commit_sweep uploads.
+struct SweepHost {
+  Blob bl;
+  int64_t o_steps = -1, o_units = -1, o_wdir = -1, o_scol = -1, o_irow = -1, o_sval = -1, o_dense = -1,
+          o_wrec = -1, o_sval32 = -1, o_dense32 = -1, o_wrec32 = -1, o_wrecc = -1, o_wrecc32 = -1;
+  bool compact = false;
+  int32_t n_steps = 0, n_wunits = 0, n_slots = 0, n_irow = 0;
+  rh_status st = RH_OK;
+  std::string err;
+};
+
+void prepare_sweep(const Sweep &s, int32_t n, const std::vector<int32_t> &parent, bool forward,
+                   const ScheduleParams &prm, ScheduleCut *cut, SweepHost &h) {
   const Schedule sc = build_schedule(s, n, parent, forward, prm, cut);
   Packed pk = pack_schedule(sc, kThreads);
   if (pk.irow.empty()) pk.irow.push_back(0);  // lanes without a row read element 0
   if (!pk.idinv.empty()) {
-    err = "internal: device sweeps must have a unit diagonal";
-    return RH_EDEVICE;
+    h.st = RH_EDEVICE;
+    h.err = "internal: device sweeps must have a unit diagonal";
+    return;
   }
   // wave-unit records in both precisions, wide and (where the rows fit)
   // compact (layouts: see wave_records)
   const size_t nwu = pk.wlg.size();
+  if (nwu * WaveRec<double>::bytes >= (size_t)kOffRange) {
+    h.st = RH_EINVAL;
+    h.err = "network too large for the wave-unit records";
+    return;
+  }
   std::vector<char> rec64, rec32, recc64, recc32;
   (void)wave_records(pk, false, true, rec64);
   (void)wave_records(pk, false, false, rec32);
-  const bool compact = wave_records(pk, true, true, recc64) && wave_records(pk, true, false, recc32);
-  Blob bl;
-  const int64_t o_steps = bl.add(pk.steps), o_units = bl.add(pk.units), o_wdir = bl.add(pk.wdir);
-  const int64_t o_scol = bl.add(pk.scol), o_irow = bl.add(pk.irow);
-  const int64_t o_sval = bl.add(pk.sval), o_dense = bl.add(pk.dense), o_wrec = bl.add(rec64);
-  const int64_t o_sval32 = bl.add(std::vector<float>(pk.sval.begin(), pk.sval.end()));
-  const int64_t o_dense32 = bl.add(std::vector<float>(pk.dense.begin(), pk.dense.end()));
-  const int64_t o_wrec32 = bl.add(rec32);
-  const int64_t o_wrecc = compact ? bl.add(recc64) : -1, o_wrecc32 = compact ? bl.add(recc32) : -1;
-  if (nwu * WaveRec<double>::bytes >= (size_t)kOffRange) {
-    err = "network too large for the wave-unit records";
-    return RH_EINVAL;
+  h.compact = wave_records(pk, true, true, recc64) && wave_records(pk, true, false, recc32);
+  Blob &bl = h.bl;
+  h.o_steps = bl.add(pk.steps);
+  h.o_units = bl.add(pk.units);
+  h.o_wdir = bl.add(pk.wdir);
+  h.o_scol = bl.add(pk.scol);
+  h.o_irow = bl.add(pk.irow);
+  h.o_sval = bl.add(pk.sval);
+  h.o_dense = bl.add(pk.dense);
+  h.o_wrec = bl.add(rec64);
+  h.o_sval32 = bl.add(std::vector<float>(pk.sval.begin(), pk.sval.end()));
+  h.o_dense32 = bl.add(std::vector<float>(pk.dense.begin(), pk.dense.end()));
+  h.o_wrec32 = bl.add(rec32);
+  h.o_wrecc = h.compact ? bl.add(recc64) : -1;
+  h.o_wrecc32 = h.compact ? bl.add(recc32) : -1;
+  h.n_steps = (int32_t)(pk.steps.size() / 4);
+  h.n_wunits = (int32_t)nwu;
+  h.n_slots = (int32_t)pk.scol.size();
+  h.n_irow = (int32_t)pk.irow.size();
+}
+
+rh_status commit_sweep(DeviceNet *dn, const SweepHost &h, DevSweep &o, std::string &err) {
+  if (h.st != RH_OK) {
+    err = h.err;
+    return h.st;
   }
   const char *base = nullptr;
-  UP(bl.h, base);
-  o.n_steps = (int32_t)(pk.steps.size() / 4);
-  o.steps = at_off<int4>(base, o_steps);
-  o.units = at_off<int4>(base, o_units);
-  o.wdir = at_off<int32_t>(base, o_wdir);
-  o.scol = at_off<int32_t>(base, o_scol);
-  o.irow = at_off<int32_t>(base, o_irow);
-  o.sval = at_off<double>(base, o_sval);
-  o.dense = at_off<double>(base, o_dense);
-  o.sval32 = at_off<float>(base, o_sval32);
-  o.dense32 = at_off<float>(base, o_dense32);
-  o.n_wunits = (int32_t)nwu;
-  o.wrec = at_off<char>(base, o_wrec);
-  o.wrec32 = at_off<char>(base, o_wrec32);
-  o.wrecc = compact ? at_off<char>(base, o_wrecc) : nullptr;
-  o.wrecc32 = compact ? at_off<char>(base, o_wrecc32) : nullptr;
-  o.n_slots = (int32_t)pk.scol.size();
-  o.n_irow = (int32_t)pk.irow.size();
+  UP(h.bl.h, base);
+  o.n_steps = h.n_steps;
+  o.steps = at_off<int4>(base, h.o_steps);
+  o.units = at_off<int4>(base, h.o_units);
+  o.wdir = at_off<int32_t>(base, h.o_wdir);
+  o.scol = at_off<int32_t>(base, h.o_scol);
+  o.irow = at_off<int32_t>(base, h.o_irow);
+  o.sval = at_off<double>(base, h.o_sval);
+  o.dense = at_off<double>(base, h.o_dense);
+  o.sval32 = at_off<float>(base, h.o_sval32);
+  o.dense32 = at_off<float>(base, h.o_dense32);
+  o.n_wunits = h.n_wunits;
+  o.wrec = at_off<char>(base, h.o_wrec);
+  o.wrec32 = at_off<char>(base, h.o_wrec32);
+  o.wrecc = h.compact ? at_off<char>(base, h.o_wrecc) : nullptr;
+  o.wrecc32 = h.compact ? at_off<char>(base, h.o_wrecc32) : nullptr;
+  o.n_slots = h.n_slots;
+  o.n_irow = h.n_irow;
   dn->sweep_steps.push_back(o.n_steps);
+  return RH_OK;
+}
+
+// The four sweeps (L, U, U^T, L^T) prepared on four threads, then uploaded
+// in order.  An exception on a thread is raised again here.
+rh_status upload_sweeps(DeviceNet *dn, const Sweep *const sw[4], int32_t n, const std::vector<int32_t> &parent,
+                        const ScheduleParams &prm, DevSweep *const out[4], ScheduleCut *cuts, std::string &err) {
+  SweepHost hs[4];
+  std::exception_ptr ex[4];
+  {
+    std::vector<std::thread> th;
+    for (int k = 0; k < 4; ++k)
+      th.emplace_back([&, k] {
+        try {
+          prepare_sweep(*sw[k], n, parent, k % 2 == 0, prm, &cuts[k], hs[k]);
+        } catch (...) {
+          ex[k] = std::current_exception();
+        }
+      });
+    for (std::thread &t : th) t.join();
+  }
+  for (int k = 0; k < 4; ++k)
+    if (ex[k]) std::rethrow_exception(ex[k]);
+  for (int k = 0; k < 4; ++k) {
+    rh_status s = commit_sweep(dn, hs[k], *out[k], err);
+    if (s != RH_OK) return s;
+  }
   return RH_OK;
 }
 
@@ -2195,11 +2256,12 @@ rh_status device_upload(Network &net, std::string &err) {
     net.cut_params[0] = prm.bmax;
     net.cut_params[1] = prm.wave_mode;
   }
-  if (upload_sweep(dn, sl, n, parent, true, prm, nd.L, &net.cuts[0], err) != RH_OK ||
-      upload_sweep(dn, su, n, parent, false, prm, nd.U, &net.cuts[1], err) != RH_OK ||
-      upload_sweep(dn, sut, n, parent, true, prm, nd.Ut, &net.cuts[2], err) != RH_OK ||
-      upload_sweep(dn, slt, n, parent, false, prm, nd.Lt, &net.cuts[3], err) != RH_OK)
-    return RH_EDEVICE;
+  {
+    const Sweep *const sw[4] = {&sl, &su, &sut, &slt};
+    DevSweep *const out[4] = {&nd.L, &nd.U, &nd.Ut, &nd.Lt};
+    const rh_status s = upload_sweeps(dn, sw, n, parent, prm, out, net.cuts, err);
+    if (s != RH_OK) return s;
+  }
   net.report.steps_l = nd.L.n_steps;
   net.report.steps_u = nd.U.n_steps;
 

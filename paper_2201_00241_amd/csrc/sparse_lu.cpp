@@ -14,7 +14,9 @@
 #include <climits>
 #include <cmath>
 #include <queue>
+#include <exception>
 #include <stdexcept>
+#include <thread>
 
 #include "rh_internal.h"
 
@@ -261,31 +263,54 @@ void lu_sweeps(const LuPlan &lu, Sweep &sl, Sweep &su, Sweep &sut, Sweep &slt, s
       lv[e] = lu.lval[k][q];
     }
   }
-  make_sweep(sl, n, lu.level_l, lu.n_levels_l,
-             [&](int32_t i, std::vector<int32_t> &c, std::vector<double> &v) {
-               c.insert(c.end(), lu.lrow[i].begin(), lu.lrow[i].end());
-               v.insert(v.end(), lu.lval[i].begin(), lu.lval[i].end());
-             },
-             nullptr);
-  make_sweep(su, n, lu.level_u, lu.n_levels_u,
-             [&](int32_t i, std::vector<int32_t> &c, std::vector<double> &v) {
-               c.insert(c.end(), lu.urow[i].begin() + 1, lu.urow[i].end());
-               const double d = lu.uval[i][0];
-               for (size_t q = 1; q < lu.uval[i].size(); ++q) v.push_back(lu.uval[i][q] / d);
-             },
-             nullptr);
-  make_sweep(sut, n, lu.level_l, lu.n_levels_l,
-             [&](int32_t i, std::vector<int32_t> &c, std::vector<double> &v) {
-               c.insert(c.end(), tc.begin() + tp[i], tc.begin() + tp[i + 1]);
-               v.insert(v.end(), tv.begin() + tp[i], tv.begin() + tp[i + 1]);
-             },
-             nullptr);
+  // the four sweeps are independent: one thread each (an exception on a
+  // thread is raised again here)
+  std::exception_ptr ex[3];
+  auto guarded = [&](int k, auto body) {
+    return std::thread([&ex, k, body] {
+      try {
+        body();
+      } catch (...) {
+        ex[k] = std::current_exception();
+      }
+    });
+  };
+  std::thread t0 = guarded(0, [&] {
+    make_sweep(sl, n, lu.level_l, lu.n_levels_l,
+               [&](int32_t i, std::vector<int32_t> &c, std::vector<double> &v) {
+                 c.insert(c.end(), lu.lrow[i].begin(), lu.lrow[i].end());
+                 v.insert(v.end(), lu.lval[i].begin(), lu.lval[i].end());
+               },
+               nullptr);
+  });
+  std::thread t1 = guarded(1, [&] {
+    make_sweep(su, n, lu.level_u, lu.n_levels_u,
+               [&](int32_t i, std::vector<int32_t> &c, std::vector<double> &v) {
+                 c.insert(c.end(), lu.urow[i].begin() + 1, lu.urow[i].end());
+                 const double d = lu.uval[i][0];
+                 for (size_t q = 1; q < lu.uval[i].size(); ++q) v.push_back(lu.uval[i][q] / d);
+               },
+               nullptr);
+  });
+  std::thread t2 = guarded(2, [&] {
+    make_sweep(sut, n, lu.level_l, lu.n_levels_l,
+               [&](int32_t i, std::vector<int32_t> &c, std::vector<double> &v) {
+                 c.insert(c.end(), tc.begin() + tp[i], tc.begin() + tp[i + 1]);
+                 v.insert(v.end(), tv.begin() + tp[i], tv.begin() + tp[i + 1]);
+               },
+               nullptr);
+  });
   make_sweep(slt, n, lu.level_u, lu.n_levels_u,
              [&](int32_t i, std::vector<int32_t> &c, std::vector<double> &v) {
                c.insert(c.end(), lc.begin() + lp[i], lc.begin() + lp[i + 1]);
                v.insert(v.end(), lv.begin() + lp[i], lv.begin() + lp[i + 1]);
              },
              nullptr);
+  t0.join();
+  t1.join();
+  t2.join();
+  for (const std::exception_ptr &e : ex)
+    if (e) std::rethrow_exception(e);
 }
 
 // log2 of the lane group per row of a step: about four entries of the
