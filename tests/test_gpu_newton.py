@@ -44,9 +44,23 @@ def _rel(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
-@pytest.mark.parametrize("name,seed", [("c2", 81), ("c1", 82), ("c0", 0)])
+# The refactorisation treats the last min(128, n_x) rows as one dense block:
+# c0 (n_x = 14) and geo60 (113) are one dense block, geo75 (142) has a
+# sparse part of 14 rows, geo150 (284) and the 1k and 10k grids larger ones.
+GRIDS = {
+    "c2": lambda: gridgen.config_grid("c2", 0),
+    "c1": lambda: gridgen.config_grid("c1", 0),
+    "c0": lambda: gridgen.config_grid("c0", 0),
+    "geo60": lambda: gridgen.geometric(60, 81, 6, seed=560, alpha=0.3, kappa=0.0255),
+    "geo75": lambda: gridgen.geometric(75, 101, 7, seed=575, alpha=0.3, kappa=0.0255),
+    "geo150": lambda: gridgen.geometric(150, 202, 15, seed=650, alpha=0.3, kappa=0.0255),
+}
+
+
+@pytest.mark.parametrize("name,seed", [("c2", 81), ("c1", 82), ("c0", 0), ("geo60", 83), ("geo75", 84),
+                                       ("geo150", 85)])
 def test_device_newton_matches_host_and_oracle(ctx, rhmod, name, seed):
-    base = gridgen.config_grid(name, 0)
+    base = GRIDS[name]()
     g = gridgen.perturb_loads(base, seed=seed) if name != "c0" else base
     dev = rhmod.Network(ctx, g)
     host = rhmod.Network(ctx, g)
@@ -89,3 +103,27 @@ def test_device_newton_reports_failures(ctx, rhmod):
     net.solve_device()
     assert np.all(np.isfinite(net.hvp(W)))
     net.close()
+
+
+@pytest.mark.parametrize("name", ["c0", "c1"])
+def test_device_newton_singular_and_non_finite_starts(ctx, rhmod, name):
+    """A zero start makes G_x singular (every flow and partial vanishes at
+    the PQ buses): the device refactorisation must say so, as the host
+    factorisation does (c0 is all one dense block, c1 mostly sparse rows);
+    a start of 1e200 overflows the flows: a non-finite residual."""
+    g = GRIDS[name]()
+    net = rhmod.Network(ctx, g)
+    for x0, status in ((np.zeros(net.n_x), rhmod.RH_ESINGULAR), (np.full(net.n_x, 1e200), rhmod.RH_ENOCONV)):
+        net.set_initial_state(x0)
+        with pytest.raises(rhmod.RhError) as ei:
+            net.solve_device(1e-13, 30)
+        assert ei.value.status == status, str(ei.value)
+        _say(f"{name}: {ei.value}")
+    # a flat start then solves, and matches the host
+    net.set_initial_state(None)
+    host = rhmod.Network(ctx, g)
+    net.solve_device(1e-13, 30)
+    host.solve(1e-13, 30)
+    assert _rel(net.state(), host.state()) <= 1e-12
+    net.close()
+    host.close()

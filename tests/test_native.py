@@ -45,6 +45,8 @@ def _dump(g, path):
 
 GRIDS = {
     "c0": lambda: gridgen.config_grid("c0", 0),
+    "geo60": lambda: gridgen.geometric(60, 81, 6, seed=560, alpha=0.3, kappa=0.0255),
+    "geo75": lambda: gridgen.geometric(75, 101, 7, seed=575, alpha=0.3, kappa=0.0255),
     "geo120": lambda: gridgen.geometric(120, 162, 12, seed=77, alpha=0.3, kappa=0.0255),
     "c1": lambda: gridgen.config_grid("c1", 0),
     "c2": lambda: gridgen.config_grid("c2", 0),
