@@ -49,7 +49,6 @@ constexpr int kNtWaves = kNtThreads / 64;
 // Device arrays of one network (pattern and topology: built once).
 struct NtArrays {
   int32_t n_bus, n_br, n_x, n_p, nnz_gx, nnz_lu, maxpat;
-  int32_t n_lev_l, n_lev_u;
   // branches
   const int32_t *br_f, *br_t;
   const double *gs, *bs, *bsh;
@@ -66,19 +65,20 @@ struct NtArrays {
   const int64_t *upd_ptr;        // per row: first target of its updates
   const uint16_t *tgt;           // targets (position in the row) of every update, row by row
   const int4 *step;              // per L position: {U part of the pivot row: start, length; first target; row}
-  const int32_t *lev_ptr_l, *lev_rows_l, *lev_ptr_u, *lev_rows_u;
   // the dense top block: rows b0 .. n_x - 1 (m_blk of them); levels of the
   // rows below it; per block row its steps with pivot rows below b0 and the
   // position of every block column in it (-1: none)
   int32_t b0, m_blk;
   const int32_t *lev_ptr_f, *lev_rows_f, *ns, *dmap;
+  const int32_t *lev_ptr_uf, *lev_rows_uf;  // U levels of the rows below b0
 };
 
 // Per-solve device vectors.
 struct NtVectors {
   double *x, *p, *Pd, *Qd, *th, *v, *flows, *dG, *g, *gx, *lu, *y;
   double *rinv;  // 1 / u_ii of every finished row
-  double *S;     // the dense block after the steps with pivot rows below b0 (m_blk x m_blk, row-major)
+  double *S;     // the dense block after the steps with pivot rows below b0, then its factors
+                 // (m_blk x m_blk, row-major: L below the diagonal, U on and above)
   double *amax;  // largest |G_x entry| of every block row (the pivot test)
   double *stat;  // [0] max |g|, [1] non-finite flag, [2] singular pivot row + 1
 };
@@ -434,29 +434,32 @@ __global__ __launch_bounds__(kNtThreads) void nt_dense_lu(const NtArgs A) {
       nt_check_pivot(A, b0 + r, t[k], amax);
       A.w.rinv[b0 + r] = L.rinv[r];
     }
-    if (pos[k] >= 0) A.w.lu[base[k] + pos[k]] = j < r ? t[k] * L.rinv[j] : t[k];
+    const double v = j < r ? t[k] * L.rinv[j] : t[k];
+    A.w.S[(int64_t)r * m + j] = v;  // the dense block's factors, for the Newton step's solves
+    if (pos[k] >= 0) A.w.lu[base[k] + pos[k]] = v;
   }
 }
 
 // ---- Newton step: y = P g; L y; U y; x -= P^T y ---------------------------
 // One wave per row: lanes take the row's entries in turn and the wave sums.
+// Y is the vector being solved (global memory, or its copy in LDS).
 
-__device__ __forceinline__ void nt_lrow(const NtArgs &A, int32_t i, int l64) {
+__device__ __forceinline__ void nt_lrow(const NtArgs &A, double *Y, int32_t i, int l64) {
   const NtArrays &a = A.a;
   const int32_t base = a.row_ptr[i], nl = a.nl[i];
   double s = 0.0;
-  for (int32_t q = l64; q < nl; q += 64) s += A.w.lu[base + q] * A.w.y[a.lucol[base + q]];
+  for (int32_t q = l64; q < nl; q += 64) s += A.w.lu[base + q] * Y[a.lucol[base + q]];
   for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
-  if (l64 == 0) A.w.y[i] -= s;
+  if (l64 == 0) Y[i] -= s;
 }
 
-__device__ __forceinline__ void nt_urow(const NtArgs &A, int32_t i, int l64) {
+__device__ __forceinline__ void nt_urow(const NtArgs &A, double *Y, int32_t i, int l64) {
   const NtArrays &a = A.a;
   const int32_t ub = a.row_ptr[i] + a.nl[i], ue = a.row_ptr[i + 1];
   double s = 0.0;
-  for (int32_t q = ub + 1 + l64; q < ue; q += 64) s += A.w.lu[q] * A.w.y[a.lucol[q]];
+  for (int32_t q = ub + 1 + l64; q < ue; q += 64) s += A.w.lu[q] * Y[a.lucol[q]];
   for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
-  if (l64 == 0) A.w.y[i] = (A.w.y[i] - s) / A.w.lu[ub];
+  if (l64 == 0) Y[i] = (Y[i] - s) / A.w.lu[ub];
 }
 
 __global__ void nt_permute_in(const NtArgs A) {
@@ -469,34 +472,103 @@ __global__ void nt_update_x(const NtArgs A) {
   if (i < A.a.n_x) A.w.x[A.a.perm[i]] -= A.w.y[i];
 }
 
-// One wide level of the L (upper = 0) or U (upper = 1) sweep, a wave per row.
+// One wide level of the L (upper = 0) or U (upper = 1) sweep over the rows
+// below the dense block, a wave per row.
 __global__ __launch_bounds__(256) void nt_solve_level(const NtArgs A, int32_t lev, int32_t upper) {
   const int wv = threadIdx.x >> 6, l64 = threadIdx.x & 63;
-  const int32_t *lp = upper ? A.a.lev_ptr_u : A.a.lev_ptr_l;
-  const int32_t *lr = upper ? A.a.lev_rows_u : A.a.lev_rows_l;
+  const int32_t *lp = upper ? A.a.lev_ptr_uf : A.a.lev_ptr_f;
+  const int32_t *lr = upper ? A.a.lev_rows_uf : A.a.lev_rows_f;
   const int32_t idx = lp[lev] + blockIdx.x * 4 + wv;
   if (idx >= lp[lev + 1]) return;
   if (upper)
-    nt_urow(A, lr[idx], l64);
+    nt_urow(A, A.w.y, lr[idx], l64);
   else
-    nt_lrow(A, lr[idx], l64);
+    nt_lrow(A, A.w.y, lr[idx], l64);
 }
 
-// Levels lev0 .. lev1 - 1 of one sweep by one workgroup, a barrier between levels.
+// Levels lev0 .. lev1 - 1 of one sweep over the rows below the dense block by
+// one workgroup, a barrier between levels.  With LDSY the whole vector is
+// copied into LDS first (the rows' reads then wait for LDS instead of the
+// L2), and the rows of these levels are written back at the end.
+template <bool LDSY>
 __global__ __launch_bounds__(kNtThreads) void nt_solve_run(const NtArgs A, int32_t lev0, int32_t lev1,
                                                            int32_t upper) {
+  extern __shared__ double s_y[];
   const int wv = threadIdx.x >> 6, l64 = threadIdx.x & 63;
-  const int32_t *lp = upper ? A.a.lev_ptr_u : A.a.lev_ptr_l;
-  const int32_t *lr = upper ? A.a.lev_rows_u : A.a.lev_rows_l;
+  const int32_t *lp = upper ? A.a.lev_ptr_uf : A.a.lev_ptr_f;
+  const int32_t *lr = upper ? A.a.lev_rows_uf : A.a.lev_rows_f;
+  double *Y = A.w.y;
+  if constexpr (LDSY) {
+    for (int32_t i = threadIdx.x; i < A.a.n_x; i += kNtThreads) s_y[i] = A.w.y[i];
+    __syncthreads();
+    Y = s_y;
+  }
   for (int32_t lev = lev0; lev < lev1; ++lev) {
     for (int32_t idx = lp[lev] + wv; idx < lp[lev + 1]; idx += kNtWaves) {
       if (upper)
-        nt_urow(A, lr[idx], l64);
+        nt_urow(A, Y, lr[idx], l64);
       else
-        nt_lrow(A, lr[idx], l64);
+        nt_lrow(A, Y, lr[idx], l64);
     }
     __syncthreads();
   }
+  if constexpr (LDSY) {
+    for (int32_t idx = lp[lev0] + threadIdx.x; idx < lp[lev1]; idx += kNtThreads) A.w.y[lr[idx]] = s_y[lr[idx]];
+  }
+}
+
+// The L sweep's block rows, their entries with columns below b0 (the first
+// ns of the row; the rest is the dense block's), a wave per row.
+__global__ __launch_bounds__(256) void nt_block_lres(const NtArgs A) {
+  const int wv = threadIdx.x >> 6, l64 = threadIdx.x & 63;
+  const int32_t r = blockIdx.x * 4 + wv;
+  if (r >= A.a.m_blk) return;
+  const int32_t i = A.a.b0 + r, base = A.a.row_ptr[i], ns = A.a.ns[r];
+  double s = 0.0;
+  for (int32_t q = l64; q < ns; q += 64) s += A.w.lu[base + q] * A.w.y[A.a.lucol[base + q]];
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+  if (l64 == 0) A.w.y[i] -= s;
+}
+
+// The dense block's triangular solve: the factors are staged in LDS by the
+// workgroup, then one wave substitutes, lane l holding rows l and l + 64:
+// forward with the unit lower factor (upper = 0), or backward with the
+// upper factor (upper = 1, the diagonal divided out as in the sparse rows).
+// The solved value of each step is broadcast by readlane, so the 128 steps
+// wait for no barrier and no memory.
+static_assert(kNtDenseTop <= 128, "two rows per lane in the dense solve");
+__device__ __forceinline__ double nt_lane_bcast(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+__global__ __launch_bounds__(kNtThreads) void nt_dense_solve(const NtArgs A, int32_t upper) {
+  extern __shared__ double s_t[];
+  const int32_t m = A.a.m_blk, b0 = A.a.b0, ld = m + 1;
+  for (int32_t e = threadIdx.x; e < m * m; e += kNtThreads) s_t[(e / m) * ld + e % m] = A.w.S[e];
+  __syncthreads();
+  if (threadIdx.x >= 64) return;
+  const int l = threadIdx.x;
+  const int32_t r0 = l, r1 = l + 64;
+  double y0 = r0 < m ? A.w.y[b0 + r0] : 0.0, y1 = r1 < m ? A.w.y[b0 + r1] : 0.0;
+  if (!upper) {
+    for (int32_t c = 0; c < m; ++c) {
+      const double yc = nt_lane_bcast(c < 64 ? y0 : y1, c & 63);
+      if (r0 > c && r0 < m) y0 -= s_t[r0 * ld + c] * yc;
+      if (r1 > c && r1 < m) y1 -= s_t[r1 * ld + c] * yc;
+    }
+  } else {
+    for (int32_t c = m - 1; c >= 0; --c) {
+      const double xc = nt_lane_bcast(c < 64 ? y0 : y1, c & 63) / s_t[c * ld + c];
+      if (r0 == c) y0 = xc;
+      if (r1 == c) y1 = xc;
+      if (r0 < c) y0 -= s_t[r0 * ld + c] * xc;
+      if (r1 < c) y1 -= s_t[r1 * ld + c] * xc;
+    }
+  }
+  if (r0 < m) A.w.y[b0 + r0] = y0;
+  if (r1 < m) A.w.y[b0 + r1] = y1;
 }
 
 }  // namespace
@@ -511,12 +583,15 @@ struct DevNewton {
   std::vector<int32_t> row_ptr;  // host copy (unpacking the factors)
   // levels with many rows run as launches of their own over many workgroups,
   // every run of the other levels as one launch of one workgroup
-  std::vector<int32_t> lev_rows_l, lev_rows_u;  // rows per level (the solves)
-  std::vector<int32_t> lev_rows_f;              // rows per level below the dense block
+  std::vector<int32_t> lev_rows_f, lev_rows_uf;  // rows per level below the dense block (L, U)
+  size_t lds_solve = 0;                          // the dense solve's staged block
+  size_t lds_y = 0;  // the vector in LDS for the solves' runs of levels (0: too large, global memory)
 };
 
 // A level is wide with at least this many rows.
 constexpr int32_t kWideRows = 256;
+// Largest vector the solves' runs of levels keep in LDS.
+constexpr size_t kNtLdsY = 156 * 1024;
 
 namespace {
 
@@ -614,22 +689,19 @@ rh_status nt_build(Network &net, DevNewton &d, std::string &err) {
       std::memcpy(st.data(), mp.step.data(), mp.step.size() * sizeof(int32_t));
       NT_UP(st, a.step);
     }
-    for (size_t l = 0; l + 1 < mp.lev_ptr_l.size(); ++l) d.lev_rows_l.push_back(mp.lev_ptr_l[l + 1] - mp.lev_ptr_l[l]);
     for (size_t l = 0; l + 1 < mp.lev_ptr_f.size(); ++l) d.lev_rows_f.push_back(mp.lev_ptr_f[l + 1] - mp.lev_ptr_f[l]);
-    for (size_t l = 0; l + 1 < mp.lev_ptr_u.size(); ++l) d.lev_rows_u.push_back(mp.lev_ptr_u[l + 1] - mp.lev_ptr_u[l]);
+    for (size_t l = 0; l + 1 < mp.lev_ptr_uf.size(); ++l)
+      d.lev_rows_uf.push_back(mp.lev_ptr_uf[l + 1] - mp.lev_ptr_uf[l]);
     d.row_ptr = mp.row_ptr;
-    a.n_lev_l = lu.n_levels_l;
-    a.n_lev_u = lu.n_levels_u;
-    NT_UP(mp.lev_ptr_l, a.lev_ptr_l);
-    NT_UP(mp.lev_rows_l, a.lev_rows_l);
-    NT_UP(mp.lev_ptr_u, a.lev_ptr_u);
-    NT_UP(mp.lev_rows_u, a.lev_rows_u);
     a.b0 = mp.b0;
     a.m_blk = n - mp.b0;
     NT_UP(mp.lev_ptr_f, a.lev_ptr_f);
     NT_UP(mp.lev_rows_f, a.lev_rows_f);
     NT_UP(mp.ns, a.ns);
     NT_UP(mp.dmap, a.dmap);
+    NT_UP(mp.lev_ptr_uf, a.lev_ptr_uf);
+    NT_UP(mp.lev_rows_uf, a.lev_rows_uf);
+    d.lds_solve = (size_t)a.m_blk * (a.m_blk + 1) * sizeof(double);
     d.lds_bytes = (size_t)mp.maxpat * sizeof(double) * kNtWaves;
   }
   NtVectors &w = d.args.w;
@@ -647,6 +719,13 @@ rh_status nt_build(Network &net, DevNewton &d, std::string &err) {
     return s;
   HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&nt_refactor_run),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)d.lds_bytes));
+  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&nt_dense_solve),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)d.lds_solve));
+  if ((size_t)net.n_x * sizeof(double) <= kNtLdsY) {
+    d.lds_y = (size_t)net.n_x * sizeof(double);
+    HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&nt_solve_run<true>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)d.lds_y));
+  }
 
   return RH_OK;
 }
@@ -685,13 +764,14 @@ rh_status nt_step_kernels(DevNewton &d, int32_t m, int32_t nb, int32_t nnz_gx, b
   return RH_OK;
 }
 
-// The Newton step: y = P g, the two sweeps, x -= P^T y.
+// The Newton step: y = P g, the two sweeps, x -= P^T y.  The L sweep takes
+// the rows below the dense block by levels, then the block rows' entries
+// with earlier rows, then the block; the U sweep the block first, then the
+// rows below it by levels.
 rh_status nt_solve_kernels(DevNewton &d, std::string &err) {
   const int T = 256;
-  const int32_t n = d.args.a.n_x;
-  hipLaunchKernelGGL(nt_permute_in, dim3((n + T - 1) / T), dim3(T), 0, nullptr, d.args);
-  for (int upper = 0; upper < 2; ++upper) {
-    const std::vector<int32_t> &rows = upper ? d.lev_rows_u : d.lev_rows_l;
+  const int32_t n = d.args.a.n_x, mb = d.args.a.m_blk;
+  auto levels = [&](const std::vector<int32_t> &rows, int32_t upper) {
     const int32_t nlev = (int32_t)rows.size();
     for (int32_t l = 0; l < nlev;) {
       if (rows[l] >= kWideRows) {
@@ -701,10 +781,21 @@ rh_status nt_solve_kernels(DevNewton &d, std::string &err) {
       }
       int32_t l1 = l;
       while (l1 < nlev && rows[l1] < kWideRows) ++l1;
-      hipLaunchKernelGGL(nt_solve_run, dim3(1), dim3(kNtThreads), 0, nullptr, d.args, l, l1, upper);
+      if (d.lds_y)
+        hipLaunchKernelGGL(nt_solve_run<true>, dim3(1), dim3(kNtThreads), d.lds_y, nullptr, d.args, l, l1, upper);
+      else
+        hipLaunchKernelGGL(nt_solve_run<false>, dim3(1), dim3(kNtThreads), 0, nullptr, d.args, l, l1, upper);
       l = l1;
     }
+  };
+  hipLaunchKernelGGL(nt_permute_in, dim3((n + T - 1) / T), dim3(T), 0, nullptr, d.args);
+  levels(d.lev_rows_f, 0);
+  if (mb > 0) {
+    hipLaunchKernelGGL(nt_block_lres, dim3((mb + 3) / 4), dim3(256), 0, nullptr, d.args);
+    hipLaunchKernelGGL(nt_dense_solve, dim3(1), dim3(kNtThreads), d.lds_solve, nullptr, d.args, 0);
+    hipLaunchKernelGGL(nt_dense_solve, dim3(1), dim3(kNtThreads), d.lds_solve, nullptr, d.args, 1);
   }
+  levels(d.lev_rows_uf, 1);
   hipLaunchKernelGGL(nt_update_x, dim3((n + T - 1) / T), dim3(T), 0, nullptr, d.args);
   HIP_TRY(hipGetLastError());
   return RH_OK;

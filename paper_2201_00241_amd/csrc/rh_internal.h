@@ -234,8 +234,8 @@ rh_status network_accept(Network &net, const std::vector<double> &x, int32_t it,
 // every position; the G_x entries a_src[a_ptr[i] ..] of permuted row i go to
 // positions a_dst[..] of the row; eliminating with row k (every entry of row
 // i's L part in turn) updates the positions tgt[upd_ptr[i] ..] of row i, one
-// per entry of row k's U part after its diagonal; rows grouped by level of
-// the L (and U) sweep.  Update targets are numbered below 2^31.
+// per entry of row k's U part after its diagonal.  Update targets are
+// numbered below 2^31.
 struct LuMaps {
   std::vector<int32_t> row_ptr, nl, lucol, a_ptr, a_src;
   std::vector<uint16_t> a_dst, tgt;
@@ -244,7 +244,6 @@ struct LuMaps {
   // start and length of row k's U part, the first of its update targets,
   // and k
   std::vector<int32_t> step;  // 4 per factor position (only L positions used)
-  std::vector<int32_t> lev_ptr_l, lev_rows_l, lev_ptr_u, lev_rows_u;
   int32_t maxpat = 0;
   // The refactorisation treats the last n - b0 rows (the top of the
   // elimination tree, nearly dense) as one dense block: rows below b0 are
@@ -254,6 +253,9 @@ struct LuMaps {
   // + c] is the position of column b0 + c in row b0 + r, or -1.
   int32_t b0 = 0;
   std::vector<int32_t> lev_ptr_f, lev_rows_f, ns, dmap;
+  // the U levels restricted to the rows below b0 (the backward solve takes
+  // the block first), empty levels dropped
+  std::vector<int32_t> lev_ptr_uf, lev_rows_uf;
 };
 // Rows in the dense top block of the device refactorisation (at most).
 constexpr int32_t kNtDenseTop = 128;

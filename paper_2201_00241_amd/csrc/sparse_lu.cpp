@@ -835,22 +835,23 @@ bool lu_device_maps(const LuPlan &lu, const Csr &gx, LuMaps &mp, std::string &er
     }
     mp.upd_ptr[i + 1] = (int64_t)mp.tgt.size();
   }
-  group_levels(lu.level_l, lu.n_levels_l, mp.lev_ptr_l, mp.lev_rows_l);
-  group_levels(lu.level_u, lu.n_levels_u, mp.lev_ptr_u, mp.lev_rows_u);
   // the dense top block and the levels of the rows below it (a row below b0
   // depends only on earlier rows, so its level stands; levels left empty are
   // dropped)
   const int32_t b0 = n - std::min<int32_t>(kNtDenseTop, n), mb = n - b0;
   mp.b0 = b0;
-  {
-    std::vector<int32_t> renum(lu.n_levels_l, -1), lvf(b0);
-    for (int32_t i = 0; i < b0; ++i) renum[lu.level_l[i]] = 0;
+  auto below = [&](const std::vector<int32_t> &level, int32_t n_levels, std::vector<int32_t> &ptr,
+                   std::vector<int32_t> &rows) {
+    std::vector<int32_t> renum(n_levels, -1), lvf(b0);
+    for (int32_t i = 0; i < b0; ++i) renum[level[i]] = 0;
     int32_t nf = 0;
-    for (int32_t l = 0; l < lu.n_levels_l; ++l)
+    for (int32_t l = 0; l < n_levels; ++l)
       if (renum[l] == 0) renum[l] = nf++;
-    for (int32_t i = 0; i < b0; ++i) lvf[i] = renum[lu.level_l[i]];
-    group_levels(lvf, nf, mp.lev_ptr_f, mp.lev_rows_f);
-  }
+    for (int32_t i = 0; i < b0; ++i) lvf[i] = renum[level[i]];
+    group_levels(lvf, nf, ptr, rows);
+  };
+  below(lu.level_l, lu.n_levels_l, mp.lev_ptr_f, mp.lev_rows_f);
+  below(lu.level_u, lu.n_levels_u, mp.lev_ptr_uf, mp.lev_rows_uf);
   mp.ns.assign(mb, 0);
   mp.dmap.assign((size_t)mb * mb, -1);
   for (int32_t r = 0; r < mb; ++r) {

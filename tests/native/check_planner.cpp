@@ -547,6 +547,64 @@ int main(int argc, char **argv) {
       }
     }
     printf("max_err device_refactor %.3e\n", e / mx);
+    // the Newton step's solve in the kernels' order with these factors: the
+    // L sweep over the rows below the block by levels, the block rows'
+    // entries with earlier rows, the block forward; the block backward, then
+    // the U sweep over the rows below it by levels; against the host solve
+    {
+      std::vector<double> rhs(nx), y(nx), ref(nx);
+      for (auto &v : rhs) v = nd(rng);
+      for (int32_t i = 0; i < nx; ++i) y[i] = rhs[lu.perm[i]];
+      std::vector<char> fin(nx, 0);
+      for (size_t lev = 0; lev + 1 < mp.lev_ptr_f.size(); ++lev) {
+        for (int32_t idx = mp.lev_ptr_f[lev]; idx < mp.lev_ptr_f[lev + 1]; ++idx) {
+          const int32_t i = mp.lev_rows_f[idx], base = mp.row_ptr[i];
+          double acc = 0.0;
+          for (int32_t q = 0; q < mp.nl[i]; ++q) {
+            if (!fin[mp.lucol[base + q]]) ++level_bad;
+            acc += LU[base + q] * y[mp.lucol[base + q]];
+          }
+          y[i] -= acc;
+        }
+        for (int32_t idx = mp.lev_ptr_f[lev]; idx < mp.lev_ptr_f[lev + 1]; ++idx) fin[mp.lev_rows_f[idx]] = 1;
+      }
+      for (int32_t r = 0; r < mb; ++r) {
+        const int32_t i = b0 + r, base = mp.row_ptr[i];
+        for (int32_t q = 0; q < mp.ns[r]; ++q) {
+          if (!fin[mp.lucol[base + q]]) ++level_bad;
+          y[i] -= LU[base + q] * y[mp.lucol[base + q]];
+        }
+      }
+      for (int32_t c = 0; c < mb; ++c)
+        for (int32_t r = c + 1; r < mb; ++r) y[b0 + r] -= S[(size_t)r * mb + c] / S[(size_t)c * mb + c] * y[b0 + c];
+      for (int32_t c = mb - 1; c >= 0; --c) {
+        y[b0 + c] /= S[(size_t)c * mb + c];
+        for (int32_t r = 0; r < c; ++r) y[b0 + r] -= S[(size_t)r * mb + c] * y[b0 + c];
+      }
+      std::fill(fin.begin(), fin.end(), 0);
+      for (int32_t i = b0; i < nx; ++i) fin[i] = 1;
+      int32_t nuf = 0;
+      for (size_t lev = 0; lev + 1 < mp.lev_ptr_uf.size(); ++lev) {
+        for (int32_t idx = mp.lev_ptr_uf[lev]; idx < mp.lev_ptr_uf[lev + 1]; ++idx) {
+          const int32_t i = mp.lev_rows_uf[idx], ub = mp.row_ptr[i] + mp.nl[i], ue = mp.row_ptr[i + 1];
+          if (i >= b0) ++level_bad;
+          double acc = 0.0;
+          for (int32_t q = ub + 1; q < ue; ++q) {
+            if (!fin[mp.lucol[q]]) ++level_bad;
+            acc += LU[q] * y[mp.lucol[q]];
+          }
+          y[i] = (y[i] - acc) / LU[ub];
+          ++nuf;
+        }
+        for (int32_t idx = mp.lev_ptr_uf[lev]; idx < mp.lev_ptr_uf[lev + 1]; ++idx) fin[mp.lev_rows_uf[idx]] = 1;
+      }
+      if (nuf != b0) ++level_bad;
+      std::vector<double> sol(nx);
+      for (int32_t i = 0; i < nx; ++i) sol[lu.perm[i]] = y[i];
+      ref = rhs;
+      lu_solve(net.lu, ref);
+      printf("max_err device_solve %.3e\n", relerr(sol, ref));
+    }
     printf("refactor_level_violations %d\n", level_bad);
   }
   // the four sweeps compose to the two solves: U^-1 L^-1 (P b) and L^-T U^-T (P b)

@@ -67,6 +67,7 @@ def test_planner_lu_and_sweep_schedules(driver, tmp_path, name):
     assert "order_violations 0" in res.stdout, res.stdout
     assert "refactor_level_violations 0" in res.stdout, res.stdout
     assert "max_err device_refactor" in res.stdout, res.stdout
+    assert "max_err device_solve" in res.stdout, res.stdout
     assert "order_violations_composed" not in res.stdout
     assert "record_mismatch" not in res.stdout, res.stdout
     assert any(k.startswith("sweep_") for k in errs), res.stdout
