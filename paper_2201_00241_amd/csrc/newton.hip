@@ -71,6 +71,9 @@ struct NtArrays {
   int32_t b0, m_blk;
   const int32_t *lev_ptr_f, *lev_rows_f, *ns, *dmap;
   const int32_t *lev_ptr_uf, *lev_rows_uf;  // U levels of the rows below b0
+  // per entry of lev_rows_f / lev_rows_uf: {row, first entry, entries, diagonal
+  // position} of the row in the L (U) sweep (entries past the diagonal for U)
+  const int4 *sdesc_l, *sdesc_u;
 };
 
 // Per-solve device vectors.
@@ -487,33 +490,85 @@ __global__ __launch_bounds__(256) void nt_solve_level(const NtArgs A, int32_t le
 }
 
 // Levels lev0 .. lev1 - 1 of one sweep over the rows below the dense block by
-// one workgroup, a barrier between levels.  With LDSY the whole vector is
-// copied into LDS first (the rows' reads then wait for LDS instead of the
-// L2), and the rows of these levels are written back at the end.
+// one workgroup, a barrier between levels.  A row takes a group of eight
+// lanes (lane j of the group its entries j, j + 8, ...; the rows of a level
+// hold few entries), so one pass covers 128 rows of a level.  With LDSY the
+// whole vector is copied into LDS first (the rows' reads then wait for LDS
+// instead of the L2), and the rows of these levels are written back at the
+// end.  A level's rows depend on the vector only through its gathers, so
+// each lane loads the descriptor of its first row two levels ahead and that
+// row's first entry and column (and, for U, its diagonal) one level ahead:
+// every load from a clamped address, so that each level issues the same
+// loads and waits only for loads issued a level before.
+constexpr int kNtGroup = 8;                                   // lanes per row
+constexpr int kNtPassRows = kNtThreads / kNtGroup;            // rows per pass
+struct NtRowPre {
+  int4 d;   // {row, first entry, entries, diagonal}
+  bool ok;  // the lane's group has a row there
+  double v, dg;
+  int32_t c;
+};
+
 template <bool LDSY>
 __global__ __launch_bounds__(kNtThreads) void nt_solve_run(const NtArgs A, int32_t lev0, int32_t lev1,
                                                            int32_t upper) {
   extern __shared__ double s_y[];
-  const int wv = threadIdx.x >> 6, l64 = threadIdx.x & 63;
+  const int tid = threadIdx.x, slot = tid / kNtGroup, j = tid % kNtGroup;
   const int32_t *lp = upper ? A.a.lev_ptr_uf : A.a.lev_ptr_f;
-  const int32_t *lr = upper ? A.a.lev_rows_uf : A.a.lev_rows_f;
+  const int4 *D = upper ? A.a.sdesc_u : A.a.sdesc_l;
   double *Y = A.w.y;
   if constexpr (LDSY) {
-    for (int32_t i = threadIdx.x; i < A.a.n_x; i += kNtThreads) s_y[i] = A.w.y[i];
+    for (int32_t i = tid; i < A.a.n_x; i += kNtThreads) s_y[i] = A.w.y[i];
     __syncthreads();
     Y = s_y;
   }
+  // the group's row at position first + slot of a level: the descriptor
+  auto desc_at = [&](int32_t lev, int32_t first, NtRowPre &p) {
+    const int32_t lc = lev < lev1 ? lev : lev1 - 1;
+    const int32_t idx = lp[lc] + first + slot;
+    p.ok = lev < lev1 && idx < lp[lc + 1];
+    p.d = D[p.ok ? idx : lp[lev0]];
+  };
+  // ... and the lane's first entry (the descriptor loaded before)
+  auto vals_of = [&](NtRowPre &p) {
+    const bool in = p.ok && j < p.d.z;
+    p.v = A.w.lu[in ? p.d.y + j : 0];
+    p.c = A.a.lucol[in ? p.d.y + j : 0];
+    p.dg = A.w.lu[p.ok && upper ? p.d.w : 0];
+  };
+  // one row per group: the lane's first entry, then any further ones, the
+  // group sum, and the group's first lane writes (every lane takes part)
+  auto row = [&](const NtRowPre &p) {
+    const int32_t ne = p.ok ? p.d.z : 0;
+    double s = j < ne ? p.v * Y[p.c] : 0.0;
+    for (int32_t q = kNtGroup + j; q < ne; q += kNtGroup) s += A.w.lu[p.d.y + q] * Y[A.a.lucol[p.d.y + q]];
+#pragma unroll
+    for (int off = kNtGroup / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+    if (j == 0 && p.ok) Y[p.d.x] = upper ? (Y[p.d.x] - s) / p.dg : Y[p.d.x] - s;
+  };
+  NtRowPre cur, nxt, nx2;
+  desc_at(lev0, 0, cur);
+  desc_at(lev0 + 1, 0, nxt);
+  vals_of(cur);
   for (int32_t lev = lev0; lev < lev1; ++lev) {
-    for (int32_t idx = lp[lev] + wv; idx < lp[lev + 1]; idx += kNtWaves) {
-      if (upper)
-        nt_urow(A, Y, lr[idx], l64);
-      else
-        nt_lrow(A, Y, lr[idx], l64);
+    const NtRowPre p = cur;
+    cur = nxt;
+    desc_at(lev + 2, 0, nx2);
+    vals_of(cur);
+    nxt = nx2;
+    row(p);
+    // further passes of a level with more than a pass of rows, not prefetched
+    for (int32_t first = kNtPassRows; lp[lev] + first < lp[lev + 1]; first += kNtPassRows) {
+      NtRowPre q;
+      desc_at(lev, first, q);
+      vals_of(q);
+      row(q);
     }
     __syncthreads();
   }
   if constexpr (LDSY) {
-    for (int32_t idx = lp[lev0] + threadIdx.x; idx < lp[lev1]; idx += kNtThreads) A.w.y[lr[idx]] = s_y[lr[idx]];
+    const int32_t *lr = upper ? A.a.lev_rows_uf : A.a.lev_rows_f;
+    for (int32_t idx = lp[lev0] + tid; idx < lp[lev1]; idx += kNtThreads) A.w.y[lr[idx]] = s_y[lr[idx]];
   }
 }
 
@@ -530,12 +585,12 @@ __global__ __launch_bounds__(256) void nt_block_lres(const NtArgs A) {
   if (l64 == 0) A.w.y[i] -= s;
 }
 
-// The dense block's triangular solve: the factors are staged in LDS by the
-// workgroup, then one wave substitutes, lane l holding rows l and l + 64:
-// forward with the unit lower factor (upper = 0), or backward with the
-// upper factor (upper = 1, the diagonal divided out as in the sparse rows).
-// The solved value of each step is broadcast by readlane, so the 128 steps
-// wait for no barrier and no memory.
+// The dense block's two triangular solves, which follow each other in the
+// Newton step: the factors are staged in LDS by the workgroup, then one wave
+// substitutes, lane l holding rows l and l + 64, forward with the unit lower
+// factor, then backward with the upper factor.  The solved value of each step is broadcast by
+// readlane, so the steps wait for no barrier and no memory; the backward
+// steps multiply by the stored pivot reciprocals.
 static_assert(kNtDenseTop <= 128, "two rows per lane in the dense solve");
 __device__ __forceinline__ double nt_lane_bcast(double v, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
@@ -543,29 +598,31 @@ __device__ __forceinline__ double nt_lane_bcast(double v, int lane) {
   return __hiloint2double(hi, lo);
 }
 
-__global__ __launch_bounds__(kNtThreads) void nt_dense_solve(const NtArgs A, int32_t upper) {
+__global__ __launch_bounds__(kNtThreads) void nt_dense_solve(const NtArgs A) {
   extern __shared__ double s_t[];
   const int32_t m = A.a.m_blk, b0 = A.a.b0, ld = m + 1;
+  double *s_rinv = s_t + (int64_t)m * ld;  // the pivot reciprocals
   for (int32_t e = threadIdx.x; e < m * m; e += kNtThreads) s_t[(e / m) * ld + e % m] = A.w.S[e];
+  for (int32_t r = threadIdx.x; r < m; r += kNtThreads) s_rinv[r] = A.w.rinv[b0 + r];
   __syncthreads();
   if (threadIdx.x >= 64) return;
   const int l = threadIdx.x;
   const int32_t r0 = l, r1 = l + 64;
   double y0 = r0 < m ? A.w.y[b0 + r0] : 0.0, y1 = r1 < m ? A.w.y[b0 + r1] : 0.0;
-  if (!upper) {
-    for (int32_t c = 0; c < m; ++c) {
-      const double yc = nt_lane_bcast(c < 64 ? y0 : y1, c & 63);
-      if (r0 > c && r0 < m) y0 -= s_t[r0 * ld + c] * yc;
-      if (r1 > c && r1 < m) y1 -= s_t[r1 * ld + c] * yc;
-    }
-  } else {
-    for (int32_t c = m - 1; c >= 0; --c) {
-      const double xc = nt_lane_bcast(c < 64 ? y0 : y1, c & 63) / s_t[c * ld + c];
-      if (r0 == c) y0 = xc;
-      if (r1 == c) y1 = xc;
-      if (r0 < c) y0 -= s_t[r0 * ld + c] * xc;
-      if (r1 < c) y1 -= s_t[r1 * ld + c] * xc;
-    }
+  // (unrolled, so that the LDS reads of several steps are in flight together)
+#pragma unroll 8
+  for (int32_t c = 0; c < m; ++c) {
+    const double yc = nt_lane_bcast(c < 64 ? y0 : y1, c & 63);
+    if (r0 > c && r0 < m) y0 -= s_t[r0 * ld + c] * yc;
+    if (r1 > c && r1 < m) y1 -= s_t[r1 * ld + c] * yc;
+  }
+#pragma unroll 8
+  for (int32_t c = m - 1; c >= 0; --c) {
+    const double xc = nt_lane_bcast(c < 64 ? y0 : y1, c & 63) * s_rinv[c];
+    if (r0 == c) y0 = xc;
+    if (r1 == c) y1 = xc;
+    if (r0 < c) y0 -= s_t[r0 * ld + c] * xc;
+    if (r1 < c) y1 -= s_t[r1 * ld + c] * xc;
   }
   if (r0 < m) A.w.y[b0 + r0] = y0;
   if (r1 < m) A.w.y[b0 + r1] = y1;
@@ -701,7 +758,23 @@ rh_status nt_build(Network &net, DevNewton &d, std::string &err) {
     NT_UP(mp.dmap, a.dmap);
     NT_UP(mp.lev_ptr_uf, a.lev_ptr_uf);
     NT_UP(mp.lev_rows_uf, a.lev_rows_uf);
-    d.lds_solve = (size_t)a.m_blk * (a.m_blk + 1) * sizeof(double);
+    {
+      // row descriptors of the solves' levels below the dense block
+      std::vector<int4> dl(mp.lev_rows_f.size()), du(mp.lev_rows_uf.size());
+      for (size_t q = 0; q < dl.size(); ++q) {
+        const int32_t i = mp.lev_rows_f[q];
+        dl[q] = make_int4(i, mp.row_ptr[i], mp.nl[i], 0);
+      }
+      for (size_t q = 0; q < du.size(); ++q) {
+        const int32_t i = mp.lev_rows_uf[q], ub = mp.row_ptr[i] + mp.nl[i];
+        du[q] = make_int4(i, ub + 1, mp.row_ptr[i + 1] - ub - 1, ub);
+      }
+      if (dl.empty()) dl.push_back(make_int4(0, 0, 0, 0));
+      if (du.empty()) du.push_back(make_int4(0, 0, 0, 0));
+      NT_UP(dl, a.sdesc_l);
+      NT_UP(du, a.sdesc_u);
+    }
+    d.lds_solve = ((size_t)a.m_blk * (a.m_blk + 1) + a.m_blk) * sizeof(double);
     d.lds_bytes = (size_t)mp.maxpat * sizeof(double) * kNtWaves;
   }
   NtVectors &w = d.args.w;
@@ -766,8 +839,8 @@ rh_status nt_step_kernels(DevNewton &d, int32_t m, int32_t nb, int32_t nnz_gx, b
 
 // The Newton step: y = P g, the two sweeps, x -= P^T y.  The L sweep takes
 // the rows below the dense block by levels, then the block rows' entries
-// with earlier rows, then the block; the U sweep the block first, then the
-// rows below it by levels.
+// with earlier rows, then the block; the U sweep the block first (one kernel
+// for the block's two solves), then the rows below it by levels.
 rh_status nt_solve_kernels(DevNewton &d, std::string &err) {
   const int T = 256;
   const int32_t n = d.args.a.n_x, mb = d.args.a.m_blk;
@@ -792,8 +865,7 @@ rh_status nt_solve_kernels(DevNewton &d, std::string &err) {
   levels(d.lev_rows_f, 0);
   if (mb > 0) {
     hipLaunchKernelGGL(nt_block_lres, dim3((mb + 3) / 4), dim3(256), 0, nullptr, d.args);
-    hipLaunchKernelGGL(nt_dense_solve, dim3(1), dim3(kNtThreads), d.lds_solve, nullptr, d.args, 0);
-    hipLaunchKernelGGL(nt_dense_solve, dim3(1), dim3(kNtThreads), d.lds_solve, nullptr, d.args, 1);
+    hipLaunchKernelGGL(nt_dense_solve, dim3(1), dim3(kNtThreads), d.lds_solve, nullptr, d.args);
   }
   levels(d.lev_rows_uf, 1);
   hipLaunchKernelGGL(nt_update_x, dim3((n + T - 1) / T), dim3(T), 0, nullptr, d.args);
