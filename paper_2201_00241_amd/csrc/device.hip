@@ -1973,10 +1973,30 @@ void prepare_sweep(const Sweep &s, int32_t n, const std::vector<int32_t> &parent
     h.err = "network too large for the wave-unit records";
     return;
   }
+  // the four layouts are independent: three of them on threads of their own
   std::vector<char> rec64, rec32, recc64, recc32;
+  bool ok64 = false, ok32 = false;
+  std::exception_ptr ex[3];
+  auto guarded = [&](int k, bool compact, bool fp64, std::vector<char> &out, bool *ok) {
+    return std::thread([&, k, compact, fp64, ok] {
+      try {
+        const bool r = wave_records(pk, compact, fp64, out);
+        if (ok) *ok = r;
+      } catch (...) {
+        ex[k] = std::current_exception();
+      }
+    });
+  };
+  std::thread t0 = guarded(0, false, false, rec32, nullptr);
+  std::thread t1 = guarded(1, true, true, recc64, &ok64);
+  std::thread t2 = guarded(2, true, false, recc32, &ok32);
   (void)wave_records(pk, false, true, rec64);
-  (void)wave_records(pk, false, false, rec32);
-  h.compact = wave_records(pk, true, true, recc64) && wave_records(pk, true, false, recc32);
+  t0.join();
+  t1.join();
+  t2.join();
+  for (const std::exception_ptr &e : ex)
+    if (e) std::rethrow_exception(e);
+  h.compact = ok64 && ok32;
   Blob &bl = h.bl;
   h.o_steps = bl.add(pk.steps);
   h.o_units = bl.add(pk.units);
