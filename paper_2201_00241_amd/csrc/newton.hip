@@ -226,15 +226,19 @@ __device__ __forceinline__ double nt_eliminate(const NtArgs &A, int32_t i, int32
   __builtin_amdgcn_wave_barrier();
   const int4 *SI = a.step + base;
   const int4 z4 = make_int4(0, 0, 0, 0);
-  int32_t c = 0;  // first step of the chunk held by `cur`
+  // the descriptors in chunks of 64 steps: lane j of cur holds step c + j,
+  // lane j of nxt step c + 64 + j
   int4 cur = l64 < nl ? SI[l64] : z4, nxt = 64 + l64 < nl ? SI[64 + l64] : z4;
-  auto load_op = [&](int32_t q, NtOp &o) {
-    const int4 &src = q - c < 64 ? cur : nxt;
-    const int j = (q - c) & 63;
+  // the update targets of consecutive steps follow each other (ul - 1 per
+  // step), so only the first step's start is read
+  int32_t us_run = __builtin_amdgcn_readlane(cur.z, 0);
+  // step q's descriptor from lane j of src, its loads into o
+  auto load_op = [&](int32_t q, const int4 &src, int j, NtOp &o) {
     const bool in = q < nl;
     o.kb = __builtin_amdgcn_readlane(src.x, j);
     o.ul = in ? __builtin_amdgcn_readlane(src.y, j) : 0;
-    o.us = __builtin_amdgcn_readlane(src.z, j);
+    o.us = us_run;
+    us_run += in ? o.ul - 1 : 0;
     const int32_t k = __builtin_amdgcn_readlane(src.w, j);
     // every lane issues the same three loads on every path (an address of
     // 0 where it has no entry; such values are never used), so the
@@ -246,31 +250,41 @@ __device__ __forceinline__ double nt_eliminate(const NtArgs &A, int32_t i, int32
     o.rk = A.w.rinv[in ? k : 0];
   };
   constexpr int kD = 4;
+  static_assert(64 % kD == 0, "whole groups of steps per chunk");
   NtOp ring[kD];
 #pragma unroll
-  for (int d = 0; d < kD; ++d) load_op(d, ring[d]);
-  for (int32_t q0 = 0; q0 < nl; q0 += kD) {
+  for (int d = 0; d < kD; ++d) load_op(d, cur, d, ring[d]);
+  auto step = [&](int32_t q, const NtOp &o) {
+    const double l = W[q] * o.rk;
+    __builtin_amdgcn_wave_barrier();  // every lane has read w_q
+    if (l64 == 0) W[q] = l;
+    if (1 + l64 < o.ul) W[o.tg] -= l * o.uv;
+    if (o.ul > 65)  // a pivot row longer than a wave: the rest of it
+      for (int32_t s2 = 65 + l64; s2 < o.ul; s2 += 64) W[a.tgt[o.us + s2 - 1]] -= l * LU[o.kb + s2];
+    __builtin_amdgcn_wave_barrier();  // this step's writes before the next step's reads
+  };
+  for (int32_t c = 0; c < nl; c += 64) {
+    // groups of kD steps; the ring's loads for the steps kD on read this
+    // chunk's descriptors, in the chunk's last group the next chunk's
+    int32_t g = 0;
+    for (; g < 64 - kD && c + g < nl; g += kD) {
 #pragma unroll
-    for (int d = 0; d < kD; ++d) {
-      const int32_t q = q0 + d;
-      if (q < nl) {
-        const NtOp &o = ring[d];
-        const double l = W[q] * o.rk;
-        __builtin_amdgcn_wave_barrier();  // every lane has read w_q
-        if (l64 == 0) W[q] = l;
-        if (1 + l64 < o.ul) W[o.tg] -= l * o.uv;
-        for (int32_t s2 = 65 + l64; s2 < o.ul; s2 += 64) W[a.tgt[o.us + s2 - 1]] -= l * LU[o.kb + s2];
-        __builtin_amdgcn_wave_barrier();  // this step's writes before the next step's reads
+      for (int d = 0; d < kD; ++d) {
+        const int32_t q = c + g + d;
+        if (q < nl) step(q, ring[d]);
+        load_op(q + kD, cur, g + d + kD, ring[d]);
       }
-      // the step kD on, into this slot; the descriptors move on by a chunk
-      // once that step leaves the current one
-      if (q + kD == c + 64) {
-        c += 64;
-        cur = nxt;
-        nxt = c + 64 + l64 < nl ? SI[c + 64 + l64] : z4;
-      }
-      load_op(q + kD, ring[d]);
     }
+    if (c + g < nl) {
+#pragma unroll
+      for (int d = 0; d < kD; ++d) {
+        const int32_t q = c + g + d;
+        if (q < nl) step(q, ring[d]);
+        load_op(q + kD, nxt, g + d + kD - 64, ring[d]);
+      }
+    }
+    cur = nxt;
+    nxt = c + 128 + l64 < nl ? SI[c + 128 + l64] : z4;
   }
   __builtin_amdgcn_wave_barrier();
   return amax;
