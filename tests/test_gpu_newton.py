@@ -47,6 +47,8 @@ def _rel(a, b):
 # The refactorisation treats the last min(128, n_x) rows as one dense block:
 # c0 (n_x = 14) and geo60 (113) are one dense block, geo75 (142) has a
 # sparse part of 14 rows, geo150 (284) and the 1k and 10k grids larger ones.
+# The solves keep the vector in LDS up to n_x = 19,968: geo11k (20,899) takes
+# the global-memory path.
 GRIDS = {
     "c2": lambda: gridgen.config_grid("c2", 0),
     "c1": lambda: gridgen.config_grid("c1", 0),
@@ -54,11 +56,12 @@ GRIDS = {
     "geo60": lambda: gridgen.geometric(60, 81, 6, seed=560, alpha=0.3, kappa=0.0255),
     "geo75": lambda: gridgen.geometric(75, 101, 7, seed=575, alpha=0.3, kappa=0.0255),
     "geo150": lambda: gridgen.geometric(150, 202, 15, seed=650, alpha=0.3, kappa=0.0255),
+    "geo11k": lambda: gridgen.geometric(11000, 14850, 1100, seed=611, alpha=0.22, kappa=0.0187),
 }
 
 
 @pytest.mark.parametrize("name,seed", [("c2", 81), ("c1", 82), ("c0", 0), ("geo60", 83), ("geo75", 84),
-                                       ("geo150", 85)])
+                                       ("geo150", 85), ("geo11k", 86)])
 def test_device_newton_matches_host_and_oracle(ctx, rhmod, name, seed):
     base = GRIDS[name]()
     g = gridgen.perturb_loads(base, seed=seed) if name != "c0" else base
