@@ -75,3 +75,28 @@ def test_planner_lu_and_sweep_schedules(driver, tmp_path, name):
         assert "lu_solve" in errs and "lu_solve_t" in errs
     for k, v in errs.items():
         assert v < 1e-12, (k, v, res.stdout)
+
+
+@pytest.fixture(scope="module")
+def sanitized_driver(tmp_path_factory):
+    """The same driver and planner sources built with AddressSanitizer and
+    UndefinedBehaviorSanitizer (host code only; any report aborts the run)."""
+    out = tmp_path_factory.mktemp("native_san") / "check_planner_san"
+    subprocess.run(["g++", "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined",
+                    "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
+                    str(ROOT / "tests/native/check_planner.cpp"), str(CSRC / "network.cpp"),
+                    str(CSRC / "sparse_lu.cpp"), "-o", str(out)], check=True)
+    return out
+
+
+@pytest.mark.parametrize("name", ["c0", "geo60", "geo75", "geo120", "c1"])
+def test_planner_under_sanitizers(sanitized_driver, tmp_path, name):
+    """Network set-up, Newton, the LU, the four sweep schedules with their
+    packing and records, and the device refactorisation's maps, with every
+    memory access and integer operation checked."""
+    f = tmp_path / "grid.bin"
+    _dump(GRIDS[name](), f)
+    res = subprocess.run([str(sanitized_driver), str(f)], capture_output=True, text=True)
+    assert res.returncode == 0, res.stderr[-4000:]
+    assert "ERROR: AddressSanitizer" not in res.stderr and "runtime error" not in res.stderr, res.stderr[-4000:]
+    assert "order_violations 0" in res.stdout and "refactor_level_violations 0" in res.stdout, res.stdout
