@@ -1873,6 +1873,7 @@ rh_status run_items(const DeviceInfo &info, Runner &r, int32_t timing, int32_t r
 
 struct DeviceNet {
   std::vector<int32_t> sweep_steps;  // barrier steps of the L, U, U^T, L^T sweeps
+  std::mutex up_mu;                  // allocs and bytes, while the upload's threads add to them
   double *rinfo = nullptr;           // per-column refinement figures (4 doubles per column)
   int64_t rinfo_cols = 0;
   int64_t bytes = 0;                 // device bytes of the network's own arrays (allocs)
@@ -1907,8 +1908,11 @@ rh_status upload(DeviceNet &dn, const std::vector<T> &v, const T **out, std::str
   }
   void *p = nullptr;
   HIP_TRY(hipMalloc(&p, v.size() * sizeof(T)));
-  dn.allocs.push_back(p);
-  dn.bytes += (int64_t)(v.size() * sizeof(T));
+  {
+    std::lock_guard<std::mutex> lk(dn.up_mu);
+    dn.allocs.push_back(p);
+    dn.bytes += (int64_t)(v.size() * sizeof(T));
+  }
   HIP_TRY(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
   *out = static_cast<const T *>(p);
   return RH_OK;
@@ -2041,22 +2045,32 @@ rh_status commit_sweep(DeviceNet *dn, const SweepHost &h, DevSweep &o, std::stri
   o.wrecc32 = h.compact ? at_off<char>(base, h.o_wrecc32) : nullptr;
   o.n_slots = h.n_slots;
   o.n_irow = h.n_irow;
-  dn->sweep_steps.push_back(o.n_steps);
   return RH_OK;
 }
 
-// The four sweeps (L, U, U^T, L^T) prepared on four threads, then uploaded
-// in order.  An exception on a thread is raised again here.
-rh_status upload_sweeps(DeviceNet *dn, const Sweep *const sw[4], int32_t n, const std::vector<int32_t> &parent,
-                        const ScheduleParams &prm, DevSweep *const out[4], ScheduleCut *cuts, std::string &err) {
+// The four sweeps (L, U, U^T, L^T), each prepared and uploaded on a thread of
+// its own (the device is current per thread).  An exception on a thread is
+// raised again here.
+rh_status upload_sweeps(DeviceNet *dn, int device, const Sweep *const sw[4], int32_t n,
+                        const std::vector<int32_t> &parent, const ScheduleParams &prm, DevSweep *const out[4],
+                        ScheduleCut *cuts, std::string &err) {
   SweepHost hs[4];
+  rh_status st[4] = {RH_OK, RH_OK, RH_OK, RH_OK};
+  std::string errs[4];
   std::exception_ptr ex[4];
   {
     std::vector<std::thread> th;
     for (int k = 0; k < 4; ++k)
       th.emplace_back([&, k] {
         try {
+          if (hipSetDevice(device) != hipSuccess) {
+            st[k] = RH_EDEVICE;
+            errs[k] = "hipSetDevice failed on an upload thread";
+            return;
+          }
           prepare_sweep(*sw[k], n, parent, k % 2 == 0, prm, &cuts[k], hs[k]);
+          st[k] = commit_sweep(dn, hs[k], *out[k], errs[k]);
+          hs[k].bl.h = std::vector<char>();  // the staging copy is no longer needed
         } catch (...) {
           ex[k] = std::current_exception();
         }
@@ -2065,10 +2079,12 @@ rh_status upload_sweeps(DeviceNet *dn, const Sweep *const sw[4], int32_t n, cons
   }
   for (int k = 0; k < 4; ++k)
     if (ex[k]) std::rethrow_exception(ex[k]);
-  for (int k = 0; k < 4; ++k) {
-    rh_status s = commit_sweep(dn, hs[k], *out[k], err);
-    if (s != RH_OK) return s;
-  }
+  for (int k = 0; k < 4; ++k)
+    if (st[k] != RH_OK) {
+      err = errs[k];
+      return st[k];
+    }
+  for (int k = 0; k < 4; ++k) dn->sweep_steps.push_back(out[k]->n_steps);
   return RH_OK;
 }
 
@@ -2251,6 +2267,43 @@ rh_status device_upload(Network &net, std::string &err) {
   nd.n_p = net.n_p;
   nd.n_bus = net.n_bus;
 
+  // G_x and G_x^T in permuted numbering (residuals of the refined mode), each
+  // built and uploaded on a thread of its own while the sweeps are; the
+  // guard joins them on every way out of this function
+  struct Joiner {
+    std::thread t;
+    ~Joiner() {
+      if (t.joinable()) t.join();
+    }
+  };
+  rh_status ell_st[2] = {RH_OK, RH_OK};
+  std::string ell_err[2];
+  std::exception_ptr ell_ex[2];
+  Joiner ell[2];
+  for (int k = 0; k < 2; ++k)
+    ell[k].t = std::thread([&, k] {
+      try {
+        if (hipSetDevice(net.ctx->device) != hipSuccess) {
+          ell_st[k] = RH_EDEVICE;
+          ell_err[k] = "hipSetDevice failed on an upload thread";
+          return;
+        }
+        const int32_t nx = net.n_x;
+        std::vector<std::vector<std::pair<int32_t, double>>> rows(nx);
+        for (int32_t r = 0; r < nx; ++r)
+          for (int32_t e = net.gx.ptr[r]; e < net.gx.ptr[r + 1]; ++e) {
+            const int32_t ip = lu.iperm[r], jp = lu.iperm[net.gx.col[e]];
+            if (k == 0)
+              rows[ip].push_back({jp, net.gx.val[e]});
+            else
+              rows[jp].push_back({ip, net.gx.val[e]});
+          }
+        ell_st[k] = upload_ell(dn, rows, k == 0 ? nd.gx : nd.gxt, ell_err[k]);
+      } catch (...) {
+        ell_ex[k] = std::current_exception();
+      }
+    });
+
   Sweep sl, su, sut, slt;
   std::vector<double> pivinv;
   lu_sweeps(lu, sl, su, sut, slt, pivinv);
@@ -2279,7 +2332,7 @@ rh_status device_upload(Network &net, std::string &err) {
   {
     const Sweep *const sw[4] = {&sl, &su, &sut, &slt};
     DevSweep *const out[4] = {&nd.L, &nd.U, &nd.Ut, &nd.Lt};
-    const rh_status s = upload_sweeps(dn, sw, n, parent, prm, out, net.cuts, err);
+    const rh_status s = upload_sweeps(dn, net.ctx->device, sw, n, parent, prm, out, net.cuts, err);
     if (s != RH_OK) return s;
   }
   net.report.steps_l = nd.L.n_steps;
@@ -2419,19 +2472,15 @@ rh_status device_upload(Network &net, std::string &err) {
   }
   UP(tp.slack_gth, nd.slack_gth);
   UP(tp.slack_gv, nd.slack_gv);
-  // G_x and G_x^T in permuted numbering (residuals of the refined mode)
-  {
-    const int32_t nx = net.n_x;
-    std::vector<std::vector<std::pair<int32_t, double>>> rows(nx), trows(nx);
-    for (int32_t r = 0; r < nx; ++r)
-      for (int32_t e = net.gx.ptr[r]; e < net.gx.ptr[r + 1]; ++e) {
-        const int32_t ip = lu.iperm[r], jp = lu.iperm[net.gx.col[e]];
-        rows[ip].push_back({jp, net.gx.val[e]});
-        trows[jp].push_back({ip, net.gx.val[e]});
-      }
-    if (upload_ell(dn, rows, nd.gx, err) != RH_OK || upload_ell(dn, trows, nd.gxt, err) != RH_OK)
-      return RH_EDEVICE;
-  }
+  // G_x and G_x^T (built on their threads since the start)
+  for (int k = 0; k < 2; ++k) ell[k].t.join();
+  for (int k = 0; k < 2; ++k)
+    if (ell_ex[k]) std::rethrow_exception(ell_ex[k]);
+  for (int k = 0; k < 2; ++k)
+    if (ell_st[k] != RH_OK) {
+      err = ell_err[k];
+      return ell_st[k];
+    }
   {
     void *p = nullptr;
     HIP_TRY(hipMalloc(&p, sizeof(NetDesc)));

@@ -602,9 +602,9 @@ __global__ __launch_bounds__(256) void nt_block_lres(const NtArgs A) {
 // The dense block's two triangular solves, which follow each other in the
 // Newton step: the factors are staged in LDS by the workgroup, then one wave
 // substitutes, lane l holding rows l and l + 64, forward with the unit lower
-// factor, then backward with the upper factor.  The solved value of each step is broadcast by
-// readlane, so the steps wait for no barrier and no memory; the backward
-// steps multiply by the stored pivot reciprocals.
+// factor, then backward with the upper factor.  The solved value of each
+// step is broadcast by readlane, so the steps wait for no barrier and no
+// memory; the backward steps multiply by the stored pivot reciprocals.
 static_assert(kNtDenseTop <= 128, "two rows per lane in the dense solve");
 __device__ __forceinline__ double nt_lane_bcast(double v, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
@@ -623,14 +623,11 @@ __global__ __launch_bounds__(kNtThreads) void nt_dense_solve(const NtArgs A) {
   const int l = threadIdx.x;
   const int32_t r0 = l, r1 = l + 64;
   double y0 = r0 < m ? A.w.y[b0 + r0] : 0.0, y1 = r1 < m ? A.w.y[b0 + r1] : 0.0;
-  // (unrolled, so that the LDS reads of several steps are in flight together)
-#pragma unroll 8
   for (int32_t c = 0; c < m; ++c) {
     const double yc = nt_lane_bcast(c < 64 ? y0 : y1, c & 63);
     if (r0 > c && r0 < m) y0 -= s_t[r0 * ld + c] * yc;
     if (r1 > c && r1 < m) y1 -= s_t[r1 * ld + c] * yc;
   }
-#pragma unroll 8
   for (int32_t c = m - 1; c >= 0; --c) {
     const double xc = nt_lane_bcast(c < 64 ? y0 : y1, c & 63) * s_rinv[c];
     if (r0 == c) y0 = xc;
