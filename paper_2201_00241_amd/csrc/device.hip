@@ -38,6 +38,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <map>
 #include <exception>
 #include <mutex>
 #include <thread>
@@ -1880,6 +1881,12 @@ struct DeviceNet {
   NetDesc nd{};               // host copy of the descriptor (device pointers)
   NetDesc *nd_dev = nullptr;  // the same descriptor in device memory
   std::vector<void *> allocs;
+  std::vector<size_t> alloc_bytes;  // size of each of allocs
+  // the previous operating point's allocations while this one is uploaded:
+  // the layout depends on the pattern only, so the sizes repeat and each
+  // array takes a block of its size instead of a new allocation (the rest
+  // is freed at the end of the upload)
+  std::multimap<size_t, void *> pool;
   DeviceInfo info;
   Runner run;
 };
@@ -1906,14 +1913,24 @@ rh_status upload(DeviceNet &dn, const std::vector<T> &v, const T **out, std::str
     *out = nullptr;
     return RH_OK;
   }
+  const size_t nb = v.size() * sizeof(T);
   void *p = nullptr;
-  HIP_TRY(hipMalloc(&p, v.size() * sizeof(T)));
+  {
+    std::lock_guard<std::mutex> lk(dn.up_mu);
+    auto it = dn.pool.find(nb);
+    if (it != dn.pool.end()) {
+      p = it->second;
+      dn.pool.erase(it);
+    }
+  }
+  if (!p) HIP_TRY(hipMalloc(&p, nb));
   {
     std::lock_guard<std::mutex> lk(dn.up_mu);
     dn.allocs.push_back(p);
-    dn.bytes += (int64_t)(v.size() * sizeof(T));
+    dn.alloc_bytes.push_back(nb);
+    dn.bytes += (int64_t)nb;
   }
-  HIP_TRY(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(p, v.data(), nb, hipMemcpyHostToDevice));
   *out = static_cast<const T *>(p);
   return RH_OK;
 }
@@ -2193,6 +2210,7 @@ void device_free(Network &net) {
   if (!net.dev) return;
   (void)hipDeviceSynchronize();
   for (void *p : net.dev->allocs) (void)hipFree(p);
+  for (auto &pr : net.dev->pool) (void)hipFree(pr.second);  // an upload that stopped half-way
   if (net.dev->rinfo) (void)hipFree(net.dev->rinfo);
   runner_free(net.dev->run);
   delete net.dev;
@@ -2244,12 +2262,18 @@ rh_status device_upload(Network &net, std::string &err) {
   Runner keep;  // keep the launch resources across operating points
   double *keep_rinfo = nullptr;
   int64_t keep_cols = 0;
+  std::multimap<size_t, void *> pool;  // and the arrays' device memory (see DeviceNet::pool)
   if (net.dev) {
     keep = net.dev->run;
     net.dev->run = Runner();
     keep_rinfo = net.dev->rinfo;
     keep_cols = net.dev->rinfo_cols;
     net.dev->rinfo = nullptr;
+    (void)hipDeviceSynchronize();  // no kernel uses them any more
+    for (size_t q = 0; q < net.dev->allocs.size(); ++q)
+      pool.emplace(net.dev->alloc_bytes[q], net.dev->allocs[q]);
+    net.dev->allocs.clear();
+    net.dev->alloc_bytes.clear();
     device_free(net);
   }
   DeviceNet *dn = new DeviceNet();
@@ -2258,6 +2282,7 @@ rh_status device_upload(Network &net, std::string &err) {
   dn->run = keep;
   dn->rinfo = keep_rinfo;
   dn->rinfo_cols = keep_cols;
+  dn->pool = std::move(pool);
   rh_status qs = query_info(net.ctx->device, dn->info, err);
   if (qs != RH_OK) return qs;
 
@@ -2482,13 +2507,14 @@ rh_status device_upload(Network &net, std::string &err) {
       return ell_st[k];
     }
   {
-    void *p = nullptr;
-    HIP_TRY(hipMalloc(&p, sizeof(NetDesc)));
-    dn->allocs.push_back(p);
-    dn->bytes += (int64_t)sizeof(NetDesc);
-    HIP_TRY(hipMemcpy(p, &dn->nd, sizeof(NetDesc), hipMemcpyHostToDevice));
-    dn->nd_dev = static_cast<NetDesc *>(p);
+    const NetDesc *p = nullptr;
+    const std::vector<NetDesc> one(1, dn->nd);
+    UP(one, p);
+    dn->nd_dev = const_cast<NetDesc *>(p);
   }
+  // what the previous operating point left unused
+  for (auto &pr : dn->pool) (void)hipFree(pr.second);
+  dn->pool.clear();
   HIP_TRY(hipDeviceSynchronize());
   return RH_OK;
 }
