@@ -15,8 +15,10 @@
 //      one elimination level at a time (one wave per row, the row's values
 //      in LDS), except the last rows (the top of the elimination tree, where
 //      the factors are nearly dense), which after their steps with earlier
-//      rows are factored as one dense block in LDS;
-//   5. the Newton step from the two triangular solves, and x -= step.
+//      rows are factored as one dense block by one workgroup, in registers;
+//   5. the Newton step from the two triangular solves (the rows below the
+//      dense block by levels, the block by dense substitution), and
+//      x -= step.
 // After convergence the state and the factors are copied to the host, which
 // forms the first-order adjoint and the branch coefficients from them (it
 // does not factorise) and uploads the product path as after a host solve.
@@ -197,8 +199,8 @@ __global__ void nt_gx(const NtArgs A) {
 // in ascending order (pivot row k), l = w_q / u_kk and the U part of row k
 // (final: an earlier level) is subtracted, l times, at precomputed
 // positions; then the row is written back with the reciprocal of its pivot.
-// The elimination steps form the critical path (tens of thousands at the
-// top of the elimination tree), so a step waits for nothing in global memory:
+// The elimination steps form the critical path (about ten thousand at 10k
+// buses, below the dense block), so a step waits for nothing in global memory:
 // the step descriptors are loaded 64 at a time into a lane register and read
 // by readlane, the pivot reciprocal, U values and targets of a step are
 // loaded four steps ahead into a statically indexed ring, and l takes the
