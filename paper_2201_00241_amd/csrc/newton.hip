@@ -76,6 +76,10 @@ struct NtArrays {
   // per entry of lev_rows_f / lev_rows_uf: {row, first entry, entries, diagonal
   // position} of the row in the L (U) sweep (entries past the diagonal for U)
   const int4 *sdesc_l, *sdesc_u;
+  // per entry of lev_rows_f: {row, first position, positions, L positions}
+  // and {first, end} of its G_x entries (a row's set-up in one load)
+  const int4 *fdesc;
+  const int2 *fdesc_a;
 };
 
 // Per-solve device vectors.
@@ -211,15 +215,25 @@ struct NtOp {
   int32_t tg, ul, kb, us;
 };
 
-// Row i scattered into W and its first nl elimination steps taken; returns
+// A row of the factors: its first position and positions, and the range of
+// its G_x entries.
+struct NtRow {
+  int32_t base, len, a0, a1;
+};
+
+__device__ __forceinline__ NtRow nt_row(const NtArgs &A, int32_t i) {
+  return NtRow{A.a.row_ptr[i], A.a.row_ptr[i + 1] - A.a.row_ptr[i], A.a.a_ptr[i], A.a.a_ptr[i + 1]};
+}
+
+// A row scattered into W and its first nl elimination steps taken; returns
 // the largest |entry| of the row before elimination.
-__device__ __forceinline__ double nt_eliminate(const NtArgs &A, int32_t i, int32_t nl, double *W, int l64) {
+__device__ __forceinline__ double nt_eliminate(const NtArgs &A, const NtRow &R, int32_t nl, double *W, int l64) {
   const NtArrays &a = A.a;
   const double *LU = A.w.lu;
-  const int32_t base = a.row_ptr[i], len = a.row_ptr[i + 1] - base;
+  const int32_t base = R.base, len = R.len;
   for (int32_t t = l64; t < len; t += 64) W[t] = 0.0;
   double amax = 0.0;
-  for (int32_t t = a.a_ptr[i] + l64; t < a.a_ptr[i + 1]; t += 64) {
+  for (int32_t t = R.a0 + l64; t < R.a1; t += 64) {
     const double val = A.w.gx[a.a_src[t]];
     W[a.a_dst[t]] = val;
     amax = fmax(amax, fabs(val));
@@ -298,9 +312,13 @@ __device__ __forceinline__ void nt_check_pivot(const NtArgs &A, int32_t i, doubl
   if (!isfinite(d) || !(fabs(d) > 1e-13 * amax) || amax == 0.0) A.w.stat[2] = (double)(i + 1);
 }
 
-__device__ __forceinline__ void nt_factor_row(const NtArgs &A, int32_t i, double *W, int l64) {
-  const int32_t base = A.a.row_ptr[i], len = A.a.row_ptr[i + 1] - base, nl = A.a.nl[i];
-  const double amax = nt_eliminate(A, i, nl, W, l64);
+// Row idx of the levels below the dense block, its set-up from one
+// descriptor.
+__device__ __forceinline__ void nt_factor_row(const NtArgs &A, int32_t idx, double *W, int l64) {
+  const int4 d = A.a.fdesc[idx];
+  const int2 ar = A.a.fdesc_a[idx];
+  const int32_t i = d.x, base = d.y, len = d.z, nl = d.w;
+  const double amax = nt_eliminate(A, NtRow{base, len, ar.x, ar.y}, nl, W, l64);
   for (int32_t t = l64; t < len; t += 64) A.w.lu[base + t] = W[t];
   if (l64 == 0) {
     const double d = W[nl];
@@ -312,8 +330,10 @@ __device__ __forceinline__ void nt_factor_row(const NtArgs &A, int32_t i, double
 // Block row r: its steps with pivot rows below b0; the finished L entries
 // go to the factors, the rest (columns b0 and up) into row r of S.
 __device__ __forceinline__ void nt_block_row(const NtArgs &A, int32_t r, double *W, int l64) {
-  const int32_t m = A.a.m_blk, i = A.a.b0 + r, base = A.a.row_ptr[i], ns = A.a.ns[r];
-  const double amax = nt_eliminate(A, i, ns, W, l64);
+  const int32_t m = A.a.m_blk, i = A.a.b0 + r, ns = A.a.ns[r];
+  const NtRow R = nt_row(A, i);
+  const int32_t base = R.base;
+  const double amax = nt_eliminate(A, R, ns, W, l64);
   for (int32_t t = l64; t < ns; t += 64) A.w.lu[base + t] = W[t];
   for (int32_t c = l64; c < m; c += 64) {
     const int32_t p = A.a.dmap[(int64_t)r * m + c];
@@ -329,7 +349,7 @@ __global__ __launch_bounds__(64 * kNtWideWaves) void nt_refactor_level(const NtA
   extern __shared__ double s_w[];
   const int wv = threadIdx.x >> 6, l64 = threadIdx.x & 63;
   const int32_t idx = A.a.lev_ptr_f[lev] + blockIdx.x * kNtWideWaves + wv;
-  if (idx < A.a.lev_ptr_f[lev + 1]) nt_factor_row(A, A.a.lev_rows_f[idx], s_w + (int64_t)wv * A.a.maxpat, l64);
+  if (idx < A.a.lev_ptr_f[lev + 1]) nt_factor_row(A, idx, s_w + (int64_t)wv * A.a.maxpat, l64);
 }
 
 // Levels lev0 .. lev1 - 1 of the rows below b0 by one workgroup, a barrier
@@ -340,7 +360,7 @@ __global__ __launch_bounds__(kNtThreads) void nt_refactor_run(const NtArgs A, in
   double *W = s_w + (int64_t)wv * A.a.maxpat;
   for (int32_t lev = lev0; lev < lev1; ++lev) {
     for (int32_t idx = A.a.lev_ptr_f[lev] + wv; idx < A.a.lev_ptr_f[lev + 1]; idx += kNtWaves)
-      nt_factor_row(A, A.a.lev_rows_f[idx], W, l64);
+      nt_factor_row(A, idx, W, l64);
     __syncthreads();
   }
 }
@@ -786,6 +806,20 @@ rh_status nt_build(Network &net, DevNewton &d, std::string &err) {
       if (du.empty()) du.push_back(make_int4(0, 0, 0, 0));
       NT_UP(dl, a.sdesc_l);
       NT_UP(du, a.sdesc_u);
+      // the refactorisation's rows below the dense block
+      std::vector<int4> fd(mp.lev_rows_f.size());
+      std::vector<int2> fa(mp.lev_rows_f.size());
+      for (size_t q = 0; q < fd.size(); ++q) {
+        const int32_t i = mp.lev_rows_f[q];
+        fd[q] = make_int4(i, mp.row_ptr[i], mp.row_ptr[i + 1] - mp.row_ptr[i], mp.nl[i]);
+        fa[q] = make_int2(mp.a_ptr[i], mp.a_ptr[i + 1]);
+      }
+      if (fd.empty()) {
+        fd.push_back(make_int4(0, 0, 0, 0));
+        fa.push_back(make_int2(0, 0));
+      }
+      NT_UP(fd, a.fdesc);
+      NT_UP(fa, a.fdesc_a);
     }
     d.lds_solve = ((size_t)a.m_blk * (a.m_blk + 1) + a.m_blk) * sizeof(double);
     d.lds_bytes = (size_t)mp.maxpat * sizeof(double) * kNtWaves;
