@@ -130,3 +130,25 @@ def test_device_newton_singular_and_non_finite_starts(ctx, rhmod, name):
     assert _rel(net.state(), host.state()) <= 1e-12
     net.close()
     host.close()
+
+
+def test_device_newton_70k_matches_host(ctx, rhmod):
+    """The 70,000-bus grid (n_x = 134,999: the solves' vector in global
+    memory, LU rows of up to 732 positions in the refactorisation's LDS
+    buffers): state and factors of the device solve against the host's."""
+    g = gridgen.perturb_loads(gridgen.config_grid("c3", 0), seed=87)
+    dev = rhmod.Network(ctx, g)
+    host = rhmod.Network(ctx, g)
+    t0 = time.perf_counter()
+    it_d, r_d = dev.solve_device(1e-12, 30)
+    t_dev = time.perf_counter() - t0
+    it_h, r_h = host.solve(1e-12, 30)
+    _say(f"c3: device Newton {it_d} steps ({t_dev * 1e3:.0f} ms), host {it_h} steps, residuals {r_d:.1e} {r_h:.1e}")
+    assert r_d <= 1e-12 and it_d == it_h
+    assert _rel(dev.state(), host.state()) <= 1e-12
+    Ld, Ud = dev.factors()
+    Lh, Uh = host.factors()
+    assert _rel(Ld, Lh) <= 1e-12 and _rel(Ud, Uh) <= 1e-12
+    _say(f"  state vs host {_rel(dev.state(), host.state()):.1e}, L {_rel(Ld, Lh):.1e}, U {_rel(Ud, Uh):.1e}")
+    dev.close()
+    host.close()
