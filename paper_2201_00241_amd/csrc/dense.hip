@@ -12,7 +12,10 @@
 //                rows of the panel below it (one row per lane, the factor's
 //                entries read from LDS at one address per wave);
 //   chol_update: A_ik -= L_i L_k^T on the lower triangle of the trailing
-//                matrix in 64 x 64 tiles, with FP64 MFMA (16 x 16 x 4).
+//                matrix in 64 x 64 tiles, with FP64 MFMA (16 x 16 x 4), in
+//                two launches: the tile column that holds the next panel,
+//                then the rest together with the next panel's factorisation
+//                in workgroups of the same launch (a lookahead of one panel).
 // A failed pivot (not positive, or not finite) stores its column + 1 in a
 // status word; every later kernel reads it first and does nothing.
 // The forward sweep L Y = B rides along: the right-hand sides are extra rows
@@ -56,8 +59,20 @@ __device__ __forceinline__ void chol_step(double (&a)[NB], double (&x)[NB], int3
     const double dcc = rdlane(a[C], C);
     if (bad < 0 && !(dcc > 0.0 && dcc <= 1.7976931348623157e308)) bad = C;
     // column C scaled by 1 / sqrt(d_CC); on lane C this gives the pivot
-    // d_CC / sqrt(d_CC) itself (within an ulp of sqrt(d_CC))
-    const double ri = 1.0 / sqrt(dcc);
+    // d_CC / sqrt(d_CC) itself (within an ulp of sqrt(d_CC)).  The hardware
+    // reciprocal square root refined by two Newton-Raphson steps on
+    // f(r) = 1 / r^2 - d (each squares the relative error) is a shorter
+    // dependency chain than a square root and a division.  Pivots below
+    // 2^-900 are scaled by 2^1000 first (exactly, a power of two) and the
+    // result by 2^500, so that the estimate never sees a denormal.
+    const bool tiny = dcc < 0x1p-900;
+    const double ds = tiny ? dcc * 0x1p+1000 : dcc;
+    double ri = __builtin_amdgcn_rsq(ds);
+    for (int it = 0; it < 2; ++it) {
+      const double h = ds * ri;
+      ri = fma(0.5 * ri, fma(-h, ri, 1.0), ri);
+    }
+    if (tiny) ri *= 0x1p+500;
     a[C] *= ri;
     x[C] *= ri;
 #pragma unroll
@@ -106,16 +121,17 @@ __device__ __forceinline__ double *aug_row(double *A, int64_t lda, double *B, in
   return r < n ? A + r + (int64_t)c * lda : B + c + (int64_t)(r - n) * ldb;
 }
 
+// Panel j0 for workgroup blk of the panel's launch.
 template <int NB>
-__global__ __launch_bounds__(256) void chol_panel(double *A, int64_t lda, int32_t n, double *B, int64_t ldb,
-                                                  int32_t nrhs, int32_t j0, int32_t *info) {
+__device__ __forceinline__ void panel_rows(double *A, int64_t lda, int32_t n, double *B, int64_t ldb, int32_t nrhs,
+                                           int32_t j0, int32_t blk, int32_t *info) {
   if (*info) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int32_t nb = min(NB, n - j0);
   // this lane's row of the panel below the diagonal block (rows of A, then
   // the right-hand sides), loaded first so that the loads overlap the
   // factorisation
-  const int32_t r = j0 + nb + (blockIdx.x * 4 + wave) * 64 + lane;
+  const int32_t r = j0 + nb + (blk * 4 + wave) * 64 + lane;
   const bool has = r < n + nrhs;
   double x[NB];
 #pragma unroll
@@ -138,10 +154,10 @@ __global__ __launch_bounds__(256) void chol_panel(double *A, int64_t lda, int32_
   int32_t bad = -1;
   chol_step<NB, 0>(a, x, bad);
   if (bad >= 0) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *info = j0 + bad + 1;
+    if (blk == 0 && threadIdx.x == 0) *info = j0 + bad + 1;
     return;
   }
-  if (blockIdx.x == 0 && wave == 0 && lane < nb) {
+  if (blk == 0 && wave == 0 && lane < nb) {
 #pragma unroll
     for (int c = 0; c < NB; ++c)
       if (c <= lane) A[(j0 + lane) + (int64_t)(j0 + c) * lda] = a[c];
@@ -170,14 +186,20 @@ __device__ __forceinline__ void tri_tile(int32_t b, int32_t &ti, int32_t &tk) {
 // v_mfma_f64_16x16x4f64 (measured on gfx950): lane l holds A-operand
 // (l % 16, l / 16) and B-operand (l / 16, l % 16); output register q of lane
 // l is D[4 q + l / 16][l % 16].
+// Tiles of workgroup blk: with part kUpdFirst, the first tile column (which
+// holds the next panel) and then the right-hand sides; with kUpdRest, the
+// tiles right of that column.  Each entry gets the same update either way.
+constexpr int kUpdFirst = 1, kUpdRest = 2;
+
 template <int NB>
-__global__ __launch_bounds__(256) void chol_update(double *A, int64_t lda, int32_t n, double *B, int64_t ldb,
-                                                   int32_t nrhs, int32_t j0, int32_t tiles, const int32_t *info) {
+__device__ __forceinline__ void update_tiles(double *A, int64_t lda, int32_t n, double *B, int64_t ldb,
+                                             int32_t nrhs, int32_t j0, int32_t blk, int32_t tiles, int32_t part,
+                                             const int32_t *info) {
   if (*info) return;
-  if ((int32_t)blockIdx.x >= tiles) {
+  if (blk >= tiles) {
     // right-hand-side rows of the augmented matrix: b_col -= sum_c y_c L(col, c)
     // over the trailing columns, y = the panel's entries of the solved rows
-    const int32_t col = j0 + NB + ((int32_t)blockIdx.x - tiles) * 256 + threadIdx.x;
+    const int32_t col = j0 + NB + (blk - tiles) * 256 + threadIdx.x;
     if (col >= n) return;
     for (int32_t q = 0; q < nrhs; ++q) {
       const double *y = B + (int64_t)q * ldb + j0;
@@ -189,7 +211,13 @@ __global__ __launch_bounds__(256) void chol_update(double *A, int64_t lda, int32
     return;
   }
   int32_t ti, tk;
-  tri_tile(blockIdx.x, ti, tk);
+  if (part == kUpdFirst) {
+    ti = blk;
+    tk = 0;
+  } else {
+    tri_tile(blk, ti, tk);
+    ++ti, ++tk;
+  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int qi = wave >> 1, qk = wave & 1;
   if (ti == tk && qk > qi) return;  // above the diagonal
@@ -197,6 +225,18 @@ __global__ __launch_bounds__(256) void chol_update(double *A, int64_t lda, int32
   const int32_t r0 = j1 + ti * kTile + qi * 32, c0 = j1 + tk * kTile + qk * 32;
   if (r0 >= n || c0 >= n) return;
   const int li = lane & 15, lk = lane >> 4;
+  // the entries this lane updates, loaded with the panel so that the two
+  // loads overlap
+  double cur[2][2][4];
+#pragma unroll
+  for (int hk = 0; hk < 2; ++hk)
+#pragma unroll
+    for (int hi = 0; hi < 2; ++hi)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int32_t row = r0 + 16 * hi + li, col = c0 + 16 * hk + 4 * q + lk;
+        cur[hk][hi][q] = (row < n && col < n && row >= col) ? A[row + (int64_t)col * lda] : 0.0;
+      }
   v4d acc[2][2];
 #pragma unroll
   for (int hk = 0; hk < 2; ++hk)
@@ -227,8 +267,35 @@ __global__ __launch_bounds__(256) void chol_update(double *A, int64_t lda, int32
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int32_t row = r0 + 16 * hi + li, col = c0 + 16 * hk + 4 * q + lk;
-        if (row < n && col < n && row >= col) A[row + (int64_t)col * lda] -= acc[hk][hi][q];
+        if (row < n && col < n && row >= col) A[row + (int64_t)col * lda] = cur[hk][hi][q] - acc[hk][hi][q];
       }
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void chol_panel(double *A, int64_t lda, int32_t n, double *B, int64_t ldb,
+                                                  int32_t nrhs, int32_t j0, int32_t *info) {
+  panel_rows<NB>(A, lda, n, B, ldb, nrhs, j0, blockIdx.x, info);
+}
+
+// The first tile column of the update of panel j0 and the right-hand sides.
+template <int NB>
+__global__ __launch_bounds__(256) void chol_update_first(double *A, int64_t lda, int32_t n, double *B, int64_t ldb,
+                                                         int32_t nrhs, int32_t j0, int32_t tiles,
+                                                         const int32_t *info) {
+  update_tiles<NB>(A, lda, n, B, ldb, nrhs, j0, blockIdx.x, tiles, kUpdFirst, info);
+}
+
+// The lookahead: panel j0 + NB (whose columns the first tile column has
+// made final) in the first pblocks workgroups, and the rest of the update
+// of panel j0 in the others, which touch none of its columns.
+template <int NB>
+__global__ __launch_bounds__(256) void chol_panel_update(double *A, int64_t lda, int32_t n, double *B, int64_t ldb,
+                                                         int32_t nrhs, int32_t j0, int32_t pblocks, int32_t tiles,
+                                                         int32_t *info) {
+  if ((int32_t)blockIdx.x < pblocks)
+    panel_rows<NB>(A, lda, n, B, ldb, nrhs, j0 + NB, blockIdx.x, info);
+  else
+    update_tiles<NB>(A, lda, n, B, ldb, nrhs, j0, (int32_t)blockIdx.x - pblocks, tiles, kUpdRest, info);
 }
 
 // L^T x = y, one launch per block of 64 unknowns from the last (the rows of
@@ -309,21 +376,32 @@ __global__ __launch_bounds__(256) void dense_copy_cols(const double *X, int32_t 
     }                                                     \
   } while (0)
 
+// Right-looking with a lookahead of one panel, two launches per panel
+// after the first: the tile column of the trailing update that holds panel
+// j0 + kNB (with the right-hand sides), then that panel together with the
+// rest of the update, so that the panel's latency overlaps the update.
 rh_status dense_cholesky(int32_t n, double *A, int64_t lda, double *B, int64_t ldb, int32_t nrhs, int32_t *dinfo,
                          void *stream, std::string &err) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (!B) nrhs = 0;
+  auto panel_blocks = [&](int32_t j0) {
+    const int32_t below = n - j0 - std::min(kNB, n - j0);
+    return std::max(1, (below + nrhs + 255) / 256);
+  };
   hipLaunchKernelGGL(dense_clear, dim3(1), dim3(64), 0, st, dinfo);
+  if (n > 0)
+    hipLaunchKernelGGL(chol_panel<kNB>, dim3(panel_blocks(0)), dim3(256), 0, st, A, lda, n, B, ldb, nrhs, 0, dinfo);
   for (int32_t j0 = 0; j0 < n; j0 += kNB) {
-    const int32_t nb = std::min(kNB, n - j0), below = n - j0 - nb;
-    const int32_t blocks = std::max(1, (below + nrhs + 255) / 256);
-    hipLaunchKernelGGL(chol_panel<kNB>, dim3(blocks), dim3(256), 0, st, A, lda, n, B, ldb, nrhs, j0, dinfo);
-    if (below > 0) {
-      const int64_t T = (below + kTile - 1) / kTile, tiles = T * (T + 1) / 2;
-      const int64_t rhs_groups = nrhs > 0 ? (below + 255) / 256 : 0;
-      hipLaunchKernelGGL(chol_update<kNB>, dim3((uint32_t)(tiles + rhs_groups)), dim3(256), 0, st, A, lda, n, B,
-                         ldb, nrhs, j0, (int32_t)tiles, (const int32_t *)dinfo);
-    }
+    const int32_t below = n - j0 - std::min(kNB, n - j0);
+    if (below <= 0) break;  // j0 + kNB exists below
+    const int64_t T = (below + kTile - 1) / kTile;
+    const int64_t rhs_groups = nrhs > 0 ? (below + 255) / 256 : 0;
+    hipLaunchKernelGGL(chol_update_first<kNB>, dim3((uint32_t)(T + rhs_groups)), dim3(256), 0, st, A, lda, n, B,
+                       ldb, nrhs, j0, (int32_t)T, (const int32_t *)dinfo);
+    const int32_t pb = panel_blocks(j0 + kNB);
+    const int64_t rest = (T - 1) * T / 2;
+    hipLaunchKernelGGL(chol_panel_update<kNB>, dim3((uint32_t)(pb + rest)), dim3(256), 0, st, A, lda, n, B, ldb,
+                       nrhs, j0, pb, (int32_t)rest, dinfo);
   }
   DENSE_TRY(hipGetLastError());
   return RH_OK;
