@@ -64,6 +64,37 @@ def test_cholesky_solve_matches_oracle(ctx, n, nrhs, pad):
     assert err_L <= 1e-12 and err_X <= 1e-11
 
 
+@pytest.mark.parametrize("n,e", [(70, -1000), (97, 900)])
+def test_cholesky_solve_extreme_scales(ctx, n, e):
+    """A = 2^e M: with e = -1000 every pivot is far below 2^-900, where the
+    pivot is scaled by a power of two before the reciprocal square root;
+    with e = 900 every pivot is far above 1.  L scales by 2^(e/2) and X not
+    at all (B is scaled by 2^e too), so the scaled call must agree with the
+    unscaled one as closely as with the oracle."""
+    print(f"cholesky extreme scale n={n} 2^{e}", flush=True)
+    M = _spd(n, seed=7 * n)
+    B0 = np.random.default_rng(n).standard_normal((n, 1))
+    s = 2.0 ** e
+    A_t, B_t = _dev((s * M).T), _dev((s * B0).T)
+    assert ctx.cholesky_solve_device(A_t, B_t) == -1
+    U_t, C_t = _dev(M.T), _dev(B0.T)
+    assert ctx.cholesky_solve_device(U_t, C_t) == -1
+    L_or, j = tracking.cholesky(s * M)
+    assert j == -1
+    X_or = sla.solve_triangular(L_or.T, sla.solve_triangular(L_or, s * B0, lower=True), lower=False)
+    L_dev = np.tril(A_t.cpu().numpy().T)
+    L_ref = np.tril(U_t.cpu().numpy().T) * 2.0 ** (e // 2)
+    X_dev, X_ref = B_t.cpu().numpy().T, C_t.cpu().numpy().T
+    assert np.all(np.isfinite(L_dev)) and np.all(np.isfinite(X_dev))
+    err_L = np.abs(L_dev - L_or).max() / np.abs(L_or).max()
+    err_X = np.abs(X_dev - X_or).max() / np.abs(X_or).max()
+    d_L = np.abs(L_dev - L_ref).max() / np.abs(L_ref).max()
+    d_X = np.abs(X_dev - X_ref).max() / np.abs(X_ref).max()
+    print(f"  vs oracle L {err_L:.2e} X {err_X:.2e}; vs unscaled L {d_L:.2e} X {d_X:.2e}", flush=True)
+    assert err_L <= 1e-12 and err_X <= 1e-11
+    assert d_L <= 1e-14 and d_X <= 1e-13
+
+
 @pytest.mark.parametrize("n,bad", [(40, 12), (300, 201), (97, 96)])
 def test_cholesky_reports_the_oracle_failing_column(ctx, n, bad):
     print(f"cholesky failure n={n} col={bad}", flush=True)
