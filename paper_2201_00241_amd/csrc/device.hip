@@ -39,6 +39,7 @@
 #include <cstring>
 #include <limits>
 #include <map>
+#include <memory>
 #include <exception>
 #include <mutex>
 #include <thread>
@@ -1960,6 +1961,47 @@ const T *at_off(const char *base, int64_t off) {
   return off < 0 ? nullptr : reinterpret_cast<const T *>(base + off);
 }
 
+// Host arrays of one sweep's packing: the packed schedule, the four record
+// layouts, FP32 copies and the staging buffer.  They are taken from a
+// process-wide pool and given back after the upload, so that the next
+// upload (the next operating point) fills memory that is already mapped
+// instead of faulting in fresh pages; a scratch above kScratchKeep bytes
+// is freed instead of kept.
+struct SweepScratch {
+  Packed pk;
+  std::vector<char> rec[4];
+  std::vector<float> f32;
+  Blob bl;
+  size_t bytes() const {
+    size_t b = bl.h.capacity() + f32.capacity() * sizeof(float);
+    for (const std::vector<char> &r : rec) b += r.capacity();
+    for (const std::vector<int32_t> *v : {&pk.steps, &pk.units, &pk.wdir, &pk.scol, &pk.irow, &pk.wlg, &pk.wcol,
+                                          &pk.wrow})
+      b += v->capacity() * sizeof(int32_t);
+    for (const std::vector<double> *v : {&pk.sval, &pk.idinv, &pk.dense, &pk.wval}) b += v->capacity() * sizeof(double);
+    return b;
+  }
+};
+
+constexpr size_t kScratchKeep = size_t(256) << 20;
+constexpr size_t kScratchPool = 16;
+std::mutex g_scratch_mu;
+std::vector<std::unique_ptr<SweepScratch>> g_scratch;
+
+std::unique_ptr<SweepScratch> scratch_take() {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch.empty()) return std::make_unique<SweepScratch>();
+  std::unique_ptr<SweepScratch> w = std::move(g_scratch.back());
+  g_scratch.pop_back();
+  return w;
+}
+
+void scratch_give(std::unique_ptr<SweepScratch> w) {
+  if (!w || w->bytes() > kScratchKeep) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch.size() < kScratchPool) g_scratch.push_back(std::move(w));
+}
+
 // One sweep in one allocation: the layout and entry columns first (read in
 // both precisions), then the FP64 values and block inverses, then their FP32
 // copies, so that each precision's working set is two contiguous ranges.
@@ -1967,7 +2009,7 @@ const T *at_off(const char *base, int64_t off) {
 // nothing shared, so the four sweeps of a network are prepared on threads of
 // their own; commit_sweep uploads.
 struct SweepHost {
-  Blob bl;
+  SweepScratch *ws = nullptr;
   int64_t o_steps = -1, o_units = -1, o_wdir = -1, o_scol = -1, o_irow = -1, o_sval = -1, o_dense = -1,
           o_wrec = -1, o_sval32 = -1, o_dense32 = -1, o_wrec32 = -1, o_wrecc = -1, o_wrecc32 = -1;
   bool compact = false;
@@ -1979,7 +2021,8 @@ struct SweepHost {
 void prepare_sweep(const Sweep &s, int32_t n, const std::vector<int32_t> &parent, bool forward,
                    const ScheduleParams &prm, ScheduleCut *cut, SweepHost &h) {
   const Schedule sc = build_schedule(s, n, parent, forward, prm, cut);
-  Packed pk = pack_schedule(sc, kThreads);
+  Packed &pk = h.ws->pk;
+  pack_schedule(sc, kThreads, pk);
   if (pk.irow.empty()) pk.irow.push_back(0);  // lanes without a row read element 0
   if (!pk.idinv.empty()) {
     h.st = RH_EDEVICE;
@@ -1995,7 +2038,7 @@ void prepare_sweep(const Sweep &s, int32_t n, const std::vector<int32_t> &parent
     return;
   }
   // the four layouts are independent: three of them on threads of their own
-  std::vector<char> rec64, rec32, recc64, recc32;
+  std::vector<char> &rec64 = h.ws->rec[0], &rec32 = h.ws->rec[1], &recc64 = h.ws->rec[2], &recc32 = h.ws->rec[3];
   bool ok64 = false, ok32 = false;
   std::exception_ptr ex[3];
   auto guarded = [&](int k, bool compact, bool fp64, std::vector<char> &out, bool *ok) {
@@ -2018,7 +2061,9 @@ void prepare_sweep(const Sweep &s, int32_t n, const std::vector<int32_t> &parent
   for (const std::exception_ptr &e : ex)
     if (e) std::rethrow_exception(e);
   h.compact = ok64 && ok32;
-  Blob &bl = h.bl;
+  Blob &bl = h.ws->bl;
+  bl.h.clear();
+  std::vector<float> &f32 = h.ws->f32;
   h.o_steps = bl.add(pk.steps);
   h.o_units = bl.add(pk.units);
   h.o_wdir = bl.add(pk.wdir);
@@ -2027,8 +2072,10 @@ void prepare_sweep(const Sweep &s, int32_t n, const std::vector<int32_t> &parent
   h.o_sval = bl.add(pk.sval);
   h.o_dense = bl.add(pk.dense);
   h.o_wrec = bl.add(rec64);
-  h.o_sval32 = bl.add(std::vector<float>(pk.sval.begin(), pk.sval.end()));
-  h.o_dense32 = bl.add(std::vector<float>(pk.dense.begin(), pk.dense.end()));
+  f32.assign(pk.sval.begin(), pk.sval.end());
+  h.o_sval32 = bl.add(f32);
+  f32.assign(pk.dense.begin(), pk.dense.end());
+  h.o_dense32 = bl.add(f32);
   h.o_wrec32 = bl.add(rec32);
   h.o_wrecc = h.compact ? bl.add(recc64) : -1;
   h.o_wrecc32 = h.compact ? bl.add(recc32) : -1;
@@ -2044,7 +2091,7 @@ rh_status commit_sweep(DeviceNet *dn, const SweepHost &h, DevSweep &o, std::stri
     return h.st;
   }
   const char *base = nullptr;
-  UP(h.bl.h, base);
+  UP(h.ws->bl.h, base);
   o.n_steps = h.n_steps;
   o.steps = at_off<int4>(base, h.o_steps);
   o.units = at_off<int4>(base, h.o_units);
@@ -2072,6 +2119,11 @@ rh_status upload_sweeps(DeviceNet *dn, int device, const Sweep *const sw[4], int
                         const std::vector<int32_t> &parent, const ScheduleParams &prm, DevSweep *const out[4],
                         ScheduleCut *cuts, std::string &err) {
   SweepHost hs[4];
+  std::unique_ptr<SweepScratch> ws[4];
+  for (int k = 0; k < 4; ++k) {
+    ws[k] = scratch_take();
+    hs[k].ws = ws[k].get();
+  }
   rh_status st[4] = {RH_OK, RH_OK, RH_OK, RH_OK};
   std::string errs[4];
   std::exception_ptr ex[4];
@@ -2087,13 +2139,13 @@ rh_status upload_sweeps(DeviceNet *dn, int device, const Sweep *const sw[4], int
           }
           prepare_sweep(*sw[k], n, parent, k % 2 == 0, prm, &cuts[k], hs[k]);
           st[k] = commit_sweep(dn, hs[k], *out[k], errs[k]);
-          hs[k].bl.h = std::vector<char>();  // the staging copy is no longer needed
         } catch (...) {
           ex[k] = std::current_exception();
         }
       });
     for (std::thread &t : th) t.join();
   }
+  for (int k = 0; k < 4; ++k) scratch_give(std::move(ws[k]));
   for (int k = 0; k < 4; ++k)
     if (ex[k]) std::rethrow_exception(ex[k]);
   for (int k = 0; k < 4; ++k)

@@ -327,8 +327,10 @@ Schedule build_schedule(const Sweep &in, int32_t n, const std::vector<int32_t> &
                         const ScheduleParams &prm, ScheduleCut *cut = nullptr);
 std::vector<int32_t> etree_parent(const LuPlan &lu);
 // Pack a schedule into per-lane slots; `lanes` = workgroup size, wave steps use
-// 64 lanes per wave.
+// 64 lanes per wave.  The second form fills `pk` in place, reusing the
+// capacity of its arrays.
 Packed pack_schedule(const Schedule &sc, int lanes);
+void pack_schedule(const Schedule &sc, int lanes, Packed &pk);
 // Device records of the wave units, one fixed-size record per unit, read
 // by the kernel's wave walk with one 16-byte load per lane for each part.
 //  wide (any network), per lane l:

@@ -982,6 +982,13 @@ int wave_lg(int32_t longest) {
 
 Packed pack_schedule(const Schedule &sc, int lanes) {
   Packed pk;
+  pack_schedule(sc, lanes, pk);
+  return pk;
+}
+
+void pack_schedule(const Schedule &sc, int lanes, Packed &pk) {
+  for (std::vector<int32_t> *v : {&pk.steps, &pk.units, &pk.wdir, &pk.irow, &pk.wlg, &pk.wcol, &pk.wrow}) v->clear();
+  for (std::vector<double> *v : {&pk.idinv, &pk.wval}) v->clear();
   // element 0 of the slots and of the block inverses is a zero that lanes
   // without an entry read
   pk.scol.assign(1, 0);
@@ -1058,7 +1065,6 @@ Packed pack_schedule(const Schedule &sc, int lanes) {
       }
     }
   }
-  return pk;
 }
 
 bool wave_records(const Packed &pk, bool compact, bool fp64, std::vector<char> &out) {

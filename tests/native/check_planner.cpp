@@ -405,6 +405,7 @@ int main(int argc, char **argv) {
   const bool fwd[4] = {true, false, true, false};
   const std::vector<int32_t> parent = etree_parent(net.lu);
   int bad = 0;
+  Packed reused;  // packed again in place after every other schedule
   for (int k = 0; k < 4; ++k)
     for (int wave : {0, 1})
       for (int bmax : {0, 16, 64}) {
@@ -424,6 +425,14 @@ int main(int argc, char **argv) {
         // the packed form the kernel reads
         {
           const Packed pk = pack_schedule(sc, 1024);
+          pack_schedule(sc, 1024, reused);
+          if (reused.steps != pk.steps || reused.units != pk.units || reused.wdir != pk.wdir ||
+              reused.scol != pk.scol || reused.irow != pk.irow || reused.sval != pk.sval ||
+              reused.idinv != pk.idinv || reused.dense != pk.dense || reused.wlg != pk.wlg ||
+              reused.wcol != pk.wcol || reused.wrow != pk.wrow || reused.wval != pk.wval) {
+            printf("pack_reuse_mismatch %s_w%d_b%d\n", nm[k], wave, bmax);
+            ++bad;
+          }
           std::vector<double> Xp = Y;
           for (size_t p = 0; p < Xp.size(); ++p) Xp[p] = 0;
           std::vector<double> X0(nx);
