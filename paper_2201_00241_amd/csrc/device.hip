@@ -1983,24 +1983,45 @@ struct SweepScratch {
   }
 };
 
+// The factors' four sweeps and lu_sweeps' work arrays, pooled the same way.
+struct SweepsScratch {
+  Sweep sw[4];
+  LuSweepsWork lw;
+  std::vector<double> pivinv;
+  std::vector<float> p32;
+  size_t bytes() const {
+    size_t b = pivinv.capacity() * sizeof(double) + p32.capacity() * sizeof(float);
+    for (const Sweep &s : sw)
+      b += (s.lev_ptr.capacity() + s.rows.capacity() + s.ptr.capacity() + s.col.capacity()) * sizeof(int32_t) +
+           (s.val.capacity() + s.dinv.capacity()) * sizeof(double);
+    for (const std::vector<int32_t> *v : {&lw.tp, &lw.lp, &lw.tc, &lw.lc, &lw.tf, &lw.lf})
+      b += v->capacity() * sizeof(int32_t);
+    return b + (lw.tv.capacity() + lw.lv.capacity()) * sizeof(double);
+  }
+};
+
 constexpr size_t kScratchKeep = size_t(256) << 20;
 constexpr size_t kScratchPool = 16;
-std::mutex g_scratch_mu;
-std::vector<std::unique_ptr<SweepScratch>> g_scratch;
 
-std::unique_ptr<SweepScratch> scratch_take() {
-  std::lock_guard<std::mutex> lock(g_scratch_mu);
-  if (g_scratch.empty()) return std::make_unique<SweepScratch>();
-  std::unique_ptr<SweepScratch> w = std::move(g_scratch.back());
-  g_scratch.pop_back();
-  return w;
-}
-
-void scratch_give(std::unique_ptr<SweepScratch> w) {
-  if (!w || w->bytes() > kScratchKeep) return;
-  std::lock_guard<std::mutex> lock(g_scratch_mu);
-  if (g_scratch.size() < kScratchPool) g_scratch.push_back(std::move(w));
-}
+template <class T>
+struct ScratchPool {
+  std::mutex mu;
+  std::vector<std::unique_ptr<T>> free;
+  std::unique_ptr<T> take() {
+    std::lock_guard<std::mutex> lock(mu);
+    if (free.empty()) return std::make_unique<T>();
+    std::unique_ptr<T> w = std::move(free.back());
+    free.pop_back();
+    return w;
+  }
+  void give(std::unique_ptr<T> w) {
+    if (!w || w->bytes() > kScratchKeep) return;
+    std::lock_guard<std::mutex> lock(mu);
+    if (free.size() < kScratchPool) free.push_back(std::move(w));
+  }
+};
+ScratchPool<SweepScratch> g_sweep_scratch;
+ScratchPool<SweepsScratch> g_sweeps_scratch;
 
 // One sweep in one allocation: the layout and entry columns first (read in
 // both precisions), then the FP64 values and block inverses, then their FP32
@@ -2121,7 +2142,7 @@ rh_status upload_sweeps(DeviceNet *dn, int device, const Sweep *const sw[4], int
   SweepHost hs[4];
   std::unique_ptr<SweepScratch> ws[4];
   for (int k = 0; k < 4; ++k) {
-    ws[k] = scratch_take();
+    ws[k] = g_sweep_scratch.take();
     hs[k].ws = ws[k].get();
   }
   rh_status st[4] = {RH_OK, RH_OK, RH_OK, RH_OK};
@@ -2145,7 +2166,7 @@ rh_status upload_sweeps(DeviceNet *dn, int device, const Sweep *const sw[4], int
       });
     for (std::thread &t : th) t.join();
   }
-  for (int k = 0; k < 4; ++k) scratch_give(std::move(ws[k]));
+  for (int k = 0; k < 4; ++k) g_sweep_scratch.give(std::move(ws[k]));
   for (int k = 0; k < 4; ++k)
     if (ex[k]) std::rethrow_exception(ex[k]);
   for (int k = 0; k < 4; ++k)
@@ -2381,12 +2402,18 @@ rh_status device_upload(Network &net, std::string &err) {
       }
     });
 
-  Sweep sl, su, sut, slt;
-  std::vector<double> pivinv;
-  lu_sweeps(lu, sl, su, sut, slt, pivinv);
+  // given back to the pool on every way out of this function
+  struct SweepsGuard {
+    std::unique_ptr<SweepsScratch> w = g_sweeps_scratch.take();
+    ~SweepsGuard() { g_sweeps_scratch.give(std::move(w)); }
+  } sg;
+  Sweep &sl = sg.w->sw[0], &su = sg.w->sw[1], &sut = sg.w->sw[2], &slt = sg.w->sw[3];
+  std::vector<double> &pivinv = sg.w->pivinv;
+  lu_sweeps(lu, sl, su, sut, slt, pivinv, &sg.w->lw);
   UP(pivinv, nd.pivinv);
   {
-    const std::vector<float> p32(pivinv.begin(), pivinv.end());
+    std::vector<float> &p32 = sg.w->p32;
+    p32.assign(pivinv.begin(), pivinv.end());
     UP(p32, nd.pivinv32);
   }
   ScheduleParams prm;

@@ -320,7 +320,14 @@ void lu_solve_t(const LuPlan &lu, std::vector<double> &b);      // A^T x = b in 
 // The four unit-diagonal sweeps of the two solves with A = P^T L D Uh P:
 // A^{-1} b = P^T Uh^{-1} D^{-1} L^{-1} P b and A^{-T} b = P^T L^{-T} D^{-1}
 // Uh^{-T} P b; pivinv = D^{-1} (reciprocal pivots, factor numbering).
-void lu_sweeps(const LuPlan &lu, Sweep &sl, Sweep &su, Sweep &sut, Sweep &slt, std::vector<double> &pivinv);
+// `work` (may be null) holds the transposed rows of Uh and L between calls,
+// so that a caller that keeps it (and the four sweeps) reuses their memory.
+struct LuSweepsWork {
+  std::vector<int32_t> tp, lp, tc, lc, tf, lf;
+  std::vector<double> tv, lv;
+};
+void lu_sweeps(const LuPlan &lu, Sweep &sl, Sweep &su, Sweep &sut, Sweep &slt, std::vector<double> &pivinv,
+               LuSweepsWork *work = nullptr);
 int lane_log2(int32_t rows, int32_t longest, int lane_budget);
 // `cut` (may be null): reused if valid, else filled with the cut chosen.
 Schedule build_schedule(const Sweep &in, int32_t n, const std::vector<int32_t> &parent, bool forward,

@@ -230,8 +230,11 @@ void make_sweep(Sweep &s, int32_t n, const std::vector<int32_t> &level, int32_t 
 
 }  // namespace
 
-void lu_sweeps(const LuPlan &lu, Sweep &sl, Sweep &su, Sweep &sut, Sweep &slt, std::vector<double> &pivinv) {
+void lu_sweeps(const LuPlan &lu, Sweep &sl, Sweep &su, Sweep &sut, Sweep &slt, std::vector<double> &pivinv,
+               LuSweepsWork *work) {
   const int32_t n = lu.n;
+  LuSweepsWork local;
+  LuSweepsWork &w = work ? *work : local;
   // U = D Uh with Uh unit upper triangular: U^{-1} = Uh^{-1} D^{-1} and
   // U^{-T} = D^{-1} Uh^{-T}, so every sweep has a unit diagonal and each solve
   // scales by D^{-1} between its two sweeps.
@@ -239,7 +242,10 @@ void lu_sweeps(const LuPlan &lu, Sweep &sl, Sweep &su, Sweep &sut, Sweep &slt, s
   for (int32_t k = 0; k < n; ++k) pivinv[k] = 1.0 / lu.uval[k][0];
   // rows of Uh^T and L^T in flat arrays, each row in ascending column order
   // (rows of U and L visited in ascending order)
-  std::vector<int32_t> tp(n + 1, 0), lp(n + 1, 0);
+  std::vector<int32_t> &tp = w.tp, &lp = w.lp, &tc = w.tc, &lc = w.lc, &tf = w.tf, &lf = w.lf;
+  std::vector<double> &tv = w.tv, &lv = w.lv;
+  tp.assign(n + 1, 0);
+  lp.assign(n + 1, 0);
   for (int32_t k = 0; k < n; ++k) {
     for (size_t q = 1; q < lu.urow[k].size(); ++q) tp[lu.urow[k][q] + 1]++;
     for (int32_t c : lu.lrow[k]) lp[c + 1]++;
@@ -248,8 +254,12 @@ void lu_sweeps(const LuPlan &lu, Sweep &sl, Sweep &su, Sweep &sut, Sweep &slt, s
     tp[i + 1] += tp[i];
     lp[i + 1] += lp[i];
   }
-  std::vector<int32_t> tc(tp[n]), lc(lp[n]), tf(tp.begin(), tp.end() - 1), lf(lp.begin(), lp.end() - 1);
-  std::vector<double> tv(tp[n]), lv(lp[n]);
+  tc.resize(tp[n]);  // every entry is written below
+  lc.resize(lp[n]);
+  tv.resize(tp[n]);
+  lv.resize(lp[n]);
+  tf.assign(tp.begin(), tp.end() - 1);
+  lf.assign(lp.begin(), lp.end() - 1);
   for (int32_t k = 0; k < n; ++k) {
     const double d = lu.uval[k][0];
     for (size_t q = 1; q < lu.urow[k].size(); ++q) {

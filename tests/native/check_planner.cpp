@@ -405,6 +405,21 @@ int main(int argc, char **argv) {
   const bool fwd[4] = {true, false, true, false};
   const std::vector<int32_t> parent = etree_parent(net.lu);
   int bad = 0;
+  {
+    // the sweeps built again into the same objects and work arrays
+    Sweep rs[4];
+    std::vector<double> rp;
+    LuSweepsWork lw;
+    for (int rep = 0; rep < 2; ++rep) lu_sweeps(net.lu, rs[0], rs[1], rs[2], rs[3], rp, &lw);
+    bool same = rp == pivinv;
+    for (int k = 0; k < 4; ++k)
+      same = same && rs[k].lev_ptr == sw[k].lev_ptr && rs[k].rows == sw[k].rows && rs[k].ptr == sw[k].ptr &&
+             rs[k].col == sw[k].col && rs[k].val == sw[k].val && rs[k].dinv == sw[k].dinv;
+    if (!same) {
+      printf("sweeps_reuse_mismatch\n");
+      ++bad;
+    }
+  }
   Packed reused;  // packed again in place after every other schedule
   for (int k = 0; k < 4; ++k)
     for (int wave : {0, 1})

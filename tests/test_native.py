@@ -71,6 +71,7 @@ def test_planner_lu_and_sweep_schedules(driver, tmp_path, name):
     assert "order_violations_composed" not in res.stdout
     assert "record_mismatch" not in res.stdout, res.stdout
     assert "pack_reuse_mismatch" not in res.stdout, res.stdout
+    assert "sweeps_reuse_mismatch" not in res.stdout, res.stdout
     assert any(k.startswith("sweep_") for k in errs), res.stdout
     if g.n_x <= 400:
         assert "lu_solve" in errs and "lu_solve_t" in errs
