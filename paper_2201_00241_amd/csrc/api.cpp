@@ -284,8 +284,10 @@ rh_status rh_solve_powerflow_device(rh_network *net, double tol, int32_t max_ite
   n.newton_iters = res.iters;
   n.newton_resid = res.resid;
   if (s != RH_OK) return fail(s, err);
-  if ((s = network_accept(n, res.x, res.iters, res.resid, true, err)) != RH_OK) return fail(s, err);
-  if ((s = device_upload(n, err)) != RH_OK) {
+  // the host side of the solve (Jacobians, adjoint, tape) runs while the
+  // upload prepares the factors' sweeps
+  s = device_upload(n, err, [&](std::string &e) { return network_accept(n, res.x, res.iters, res.resid, true, e); });
+  if (s != RH_OK) {
     n.solved = false;
     return fail(s, err);
   }

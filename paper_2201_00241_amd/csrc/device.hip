@@ -2330,7 +2330,7 @@ rh_status device_ctx_collect(Context &ctx, rh_report &rep, std::string &err) {
   return RH_OK;
 }
 
-rh_status device_upload(Network &net, std::string &err) {
+rh_status device_upload(Network &net, std::string &err, const std::function<rh_status(std::string &)> &accept) {
   HIP_TRY(hipSetDevice(net.ctx->device));
   Runner keep;  // keep the launch resources across operating points
   double *keep_rinfo = nullptr;
@@ -2365,15 +2365,72 @@ rh_status device_upload(Network &net, std::string &err) {
   nd.n_p = net.n_p;
   nd.n_bus = net.n_bus;
 
-  // G_x and G_x^T in permuted numbering (residuals of the refined mode), each
-  // built and uploaded on a thread of its own while the sweeps are; the
-  // guard joins them on every way out of this function
+  // The factors' sweeps read the factors only: they are prepared and
+  // uploaded on a thread of their own while `accept` finishes the host side
+  // of the solve.  On every way out of this function the guard joins the
+  // thread (it is destroyed first) and the scratch goes back to the pool.
   struct Joiner {
     std::thread t;
     ~Joiner() {
       if (t.joinable()) t.join();
     }
   };
+  struct SweepsGuard {
+    std::unique_ptr<SweepsScratch> w = g_sweeps_scratch.take();
+    ~SweepsGuard() { g_sweeps_scratch.give(std::move(w)); }
+  } sg;
+  ScheduleParams prm;
+  prm.bmax = kBlockRows;
+  prm.block_rows = kBlockRows;
+  prm.lane_budget = kLaneBudget;
+  prm.n_waves = kWaves;
+  if (const char *e = std::getenv("RH_BLOCK_ROWS")) prm.bmax = std::min(kBlockRows, std::max(0, std::atoi(e)));
+  if (const char *e = std::getenv("RH_WAVE_STEPS")) prm.wave_mode = std::atoi(e) != 0;
+  if (net.sched_bmax >= 0) prm.bmax = std::min(kBlockRows, net.sched_bmax);  // the tuner's choice
+  if (net.sched_wave >= 0) prm.wave_mode = net.sched_wave != 0;
+  // the sweeps' cuts depend on the pattern and these parameters only
+  if (net.cut_params[0] != prm.bmax || net.cut_params[1] != prm.wave_mode) {
+    for (ScheduleCut &c : net.cuts) c = ScheduleCut();
+    net.cut_params[0] = prm.bmax;
+    net.cut_params[1] = prm.wave_mode;
+  }
+  rh_status sw_st = RH_OK;
+  std::string sw_err;
+  std::exception_ptr sw_ex;
+  Joiner sweeps;
+  sweeps.t = std::thread([&] {
+    try {
+      if (hipSetDevice(net.ctx->device) != hipSuccess) {
+        sw_st = RH_EDEVICE;
+        sw_err = "hipSetDevice failed on an upload thread";
+        return;
+      }
+      sw_st = [&]() -> rh_status {
+        std::string &err = sw_err;
+        Sweep &sl = sg.w->sw[0], &su = sg.w->sw[1], &sut = sg.w->sw[2], &slt = sg.w->sw[3];
+        std::vector<double> &pivinv = sg.w->pivinv;
+        lu_sweeps(lu, sl, su, sut, slt, pivinv, &sg.w->lw);
+        UP(pivinv, nd.pivinv);
+        std::vector<float> &p32 = sg.w->p32;
+        p32.assign(pivinv.begin(), pivinv.end());
+        UP(p32, nd.pivinv32);
+        const std::vector<int32_t> parent = etree_parent(lu);
+        const Sweep *const sw[4] = {&sl, &su, &sut, &slt};
+        DevSweep *const out[4] = {&nd.L, &nd.U, &nd.Ut, &nd.Lt};
+        return upload_sweeps(dn, net.ctx->device, sw, net.n_x, parent, prm, out, net.cuts, err);
+      }();
+    } catch (...) {
+      sw_ex = std::current_exception();
+    }
+  });
+  if (accept) {
+    const rh_status s = accept(err);
+    if (s != RH_OK) return s;
+  }
+
+  // G_x and G_x^T in permuted numbering (residuals of the refined mode), each
+  // built and uploaded on a thread of its own while the sweeps are; the
+  // guard joins them on every way out of this function
   rh_status ell_st[2] = {RH_OK, RH_OK};
   std::string ell_err[2];
   std::exception_ptr ell_ex[2];
@@ -2401,46 +2458,6 @@ rh_status device_upload(Network &net, std::string &err) {
         ell_ex[k] = std::current_exception();
       }
     });
-
-  // given back to the pool on every way out of this function
-  struct SweepsGuard {
-    std::unique_ptr<SweepsScratch> w = g_sweeps_scratch.take();
-    ~SweepsGuard() { g_sweeps_scratch.give(std::move(w)); }
-  } sg;
-  Sweep &sl = sg.w->sw[0], &su = sg.w->sw[1], &sut = sg.w->sw[2], &slt = sg.w->sw[3];
-  std::vector<double> &pivinv = sg.w->pivinv;
-  lu_sweeps(lu, sl, su, sut, slt, pivinv, &sg.w->lw);
-  UP(pivinv, nd.pivinv);
-  {
-    std::vector<float> &p32 = sg.w->p32;
-    p32.assign(pivinv.begin(), pivinv.end());
-    UP(p32, nd.pivinv32);
-  }
-  ScheduleParams prm;
-  prm.bmax = kBlockRows;
-  prm.block_rows = kBlockRows;
-  prm.lane_budget = kLaneBudget;
-  prm.n_waves = kWaves;
-  if (const char *e = std::getenv("RH_BLOCK_ROWS")) prm.bmax = std::min(kBlockRows, std::max(0, std::atoi(e)));
-  if (const char *e = std::getenv("RH_WAVE_STEPS")) prm.wave_mode = std::atoi(e) != 0;
-  if (net.sched_bmax >= 0) prm.bmax = std::min(kBlockRows, net.sched_bmax);  // the tuner's choice
-  if (net.sched_wave >= 0) prm.wave_mode = net.sched_wave != 0;
-  const int32_t n = net.n_x;
-  const std::vector<int32_t> parent = etree_parent(lu);
-  // the sweeps' cuts depend on the pattern and these parameters only
-  if (net.cut_params[0] != prm.bmax || net.cut_params[1] != prm.wave_mode) {
-    for (ScheduleCut &c : net.cuts) c = ScheduleCut();
-    net.cut_params[0] = prm.bmax;
-    net.cut_params[1] = prm.wave_mode;
-  }
-  {
-    const Sweep *const sw[4] = {&sl, &su, &sut, &slt};
-    DevSweep *const out[4] = {&nd.L, &nd.U, &nd.Ut, &nd.Lt};
-    const rh_status s = upload_sweeps(dn, net.ctx->device, sw, n, parent, prm, out, net.cuts, err);
-    if (s != RH_OK) return s;
-  }
-  net.report.steps_l = nd.L.n_steps;
-  net.report.steps_u = nd.U.n_steps;
 
   // G_p with rows in permuted order, and G_p^T with permuted columns
   {
@@ -2576,7 +2593,15 @@ rh_status device_upload(Network &net, std::string &err) {
   }
   UP(tp.slack_gth, nd.slack_gth);
   UP(tp.slack_gv, nd.slack_gv);
-  // G_x and G_x^T (built on their threads since the start)
+  // the sweeps, then G_x and G_x^T (built on their threads meanwhile)
+  sweeps.t.join();
+  if (sw_ex) std::rethrow_exception(sw_ex);
+  if (sw_st != RH_OK) {
+    err = sw_err;
+    return sw_st;
+  }
+  net.report.steps_l = nd.L.n_steps;
+  net.report.steps_u = nd.U.n_steps;
   for (int k = 0; k < 2; ++k) ell[k].t.join();
   for (int k = 0; k < 2; ++k)
     if (ell_ex[k]) std::rethrow_exception(ell_ex[k]);

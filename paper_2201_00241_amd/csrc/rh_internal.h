@@ -2,6 +2,7 @@
 #pragma once
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -357,7 +358,12 @@ constexpr int kWaveRecCompact64 = 3072, kWaveRecCompact32 = 2048;
 bool wave_records(const Packed &pk, bool compact, bool fp64, std::vector<char> &out);
 
 // ---- device path (device.hip)
-rh_status device_upload(Network &net, std::string &err);
+// Uploads the solved operating point.  `accept` (may be empty) finishes the
+// host side of the solve (network_accept); the upload calls it while the
+// factors' sweeps are prepared on other threads, and reads the Jacobians,
+// adjoint and tape only after it returns.
+rh_status device_upload(Network &net, std::string &err,
+                        const std::function<rh_status(std::string &)> &accept = nullptr);
 void device_free(Network &net);
 void device_ctx_free(Context &ctx);
 // Fill the report's launch count, summed kernel time and phase times of the
