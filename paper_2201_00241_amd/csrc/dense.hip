@@ -6,11 +6,11 @@
 // A is column-major, n x n, leading dimension lda; only its lower triangle
 // (diagonal included) is read and it is overwritten by L with A = L L^T.
 // Right-looking, in panels of kNB columns:
-//   chol_panel:  one wave factors the kNB x kNB diagonal block in registers
-//                (lane i holds row i, the pivot column broadcast by readlane)
-//                into LDS; then every wave solves L_ij L_jj^T = A_ij for 64
-//                rows of the panel below it (one row per lane, the factor's
-//                entries read from LDS at one address per wave);
+//   chol_panel:  every wave factors the kNB x kNB diagonal block in
+//                registers (lanes 0 .. kNB - 1 hold its rows, the pivot
+//                column broadcast by readlane) and, with the same
+//                broadcasts, solves L_ij L_jj^T = A_ij for 64 - kNB rows of
+//                the panel below it (a row on each of the other lanes);
 //   chol_update: A_ik -= L_i L_k^T on the lower triangle of the trailing
 //                matrix in 64 x 64 tiles, with FP64 MFMA (16 x 16 x 4), in
 //                two launches: the tile column that holds the next panel,
@@ -46,47 +46,46 @@ __device__ __forceinline__ double rdlane(double v, int l) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Step C of the right-looking factorisation of a diagonal block held a row
-// per lane (a) and of the substitution of the rows x with the same
-// broadcasts; steps unrolled by recursion so that every index is a
-// compile-time constant.  The empty asm statements materialise a[k], x[k]
-// at the end of the step: the compiler would otherwise sink each chain of
-// updates down to step k and keep every broadcast factor entry alive until
-// then (hundreds of scalar registers, spilled).
+// 1 / sqrt(d) for a pivot d: the hardware reciprocal square root refined by
+// two Newton-Raphson steps on f(r) = 1 / r^2 - d (each squares the relative
+// error), a shorter dependency chain than a square root and a division.
+// Pivots below 2^-900 are scaled by 2^1000 first (exactly, a power of two)
+// and the result by 2^500, so that the estimate never sees a denormal.
+__device__ __forceinline__ double pivot_rsqrt(double d) {
+  const bool tiny = d < 0x1p-900;
+  const double ds = tiny ? d * 0x1p+1000 : d;
+  double ri = __builtin_amdgcn_rsq(ds);
+  for (int it = 0; it < 2; ++it) {
+    const double h = ds * ri;
+    ri = fma(0.5 * ri, fma(-h, ri, 1.0), ri);
+  }
+  return tiny ? ri * 0x1p+500 : ri;
+}
+
+// Step C of the right-looking factorisation of the diagonal block, whose
+// rows lanes 0 .. NB - 1 hold, and of the substitution of the rows the
+// other lanes hold, with the same broadcasts: v[c] is entry c of the lane's
+// row.  Steps unrolled by recursion so that every index is a compile-time
+// constant.  The empty asm statements materialise v[k] at the end of the
+// step: the compiler would otherwise sink each chain of updates down to
+// step k and keep every broadcast factor entry alive until then (hundreds
+// of scalar registers, spilled).
 template <int NB, int C>
-__device__ __forceinline__ void chol_step(double (&a)[NB], double (&x)[NB], int32_t &bad) {
+__device__ __forceinline__ void chol_step(double (&v)[NB], int32_t &bad) {
   if constexpr (C < NB) {
-    const double dcc = rdlane(a[C], C);
+    const double dcc = rdlane(v[C], C);
     if (bad < 0 && !(dcc > 0.0 && dcc <= 1.7976931348623157e308)) bad = C;
     // column C scaled by 1 / sqrt(d_CC); on lane C this gives the pivot
-    // d_CC / sqrt(d_CC) itself (within an ulp of sqrt(d_CC)).  The hardware
-    // reciprocal square root refined by two Newton-Raphson steps on
-    // f(r) = 1 / r^2 - d (each squares the relative error) is a shorter
-    // dependency chain than a square root and a division.  Pivots below
-    // 2^-900 are scaled by 2^1000 first (exactly, a power of two) and the
-    // result by 2^500, so that the estimate never sees a denormal.
-    const bool tiny = dcc < 0x1p-900;
-    const double ds = tiny ? dcc * 0x1p+1000 : dcc;
-    double ri = __builtin_amdgcn_rsq(ds);
-    for (int it = 0; it < 2; ++it) {
-      const double h = ds * ri;
-      ri = fma(0.5 * ri, fma(-h, ri, 1.0), ri);
-    }
-    if (tiny) ri *= 0x1p+500;
-    a[C] *= ri;
-    x[C] *= ri;
+    // d_CC / sqrt(d_CC) itself (within an ulp of sqrt(d_CC))
+    v[C] *= pivot_rsqrt(dcc);
 #pragma unroll
     for (int k = C + 1; k < NB; ++k) {
-      const double lkc = rdlane(a[C], k);  // L(k, C)
-      a[k] = fma(-a[C], lkc, a[k]);
-      x[k] = fma(-x[C], lkc, x[k]);
+      const double lkc = rdlane(v[C], k);  // L(k, C)
+      v[k] = fma(-v[C], lkc, v[k]);
     }
 #pragma unroll
-    for (int k = C + 1; k < NB; ++k) {
-      asm volatile("" : "+v"(a[k]));
-      asm volatile("" : "+v"(x[k]));
-    }
-    chol_step<NB, C + 1>(a, x, bad);
+    for (int k = C + 1; k < NB; ++k) asm volatile("" : "+v"(v[k]));
+    chol_step<NB, C + 1>(v, bad);
   }
 }
 
@@ -121,51 +120,49 @@ __device__ __forceinline__ double *aug_row(double *A, int64_t lda, double *B, in
   return r < n ? A + r + (int64_t)c * lda : B + c + (int64_t)(r - n) * ldb;
 }
 
-// Panel j0 for workgroup blk of the panel's launch.
+// Panel j0 for workgroup blk of the panel's launch: every wave factors the
+// diagonal block and solves x L^T = row for 64 - NB rows below it (rows of
+// A, then the right-hand sides).
 template <int NB>
 __device__ __forceinline__ void panel_rows(double *A, int64_t lda, int32_t n, double *B, int64_t ldb, int32_t nrhs,
                                            int32_t j0, int32_t blk, int32_t *info) {
+  static_assert(NB <= 32, "the diagonal block and the panel rows share a wave");
   if (*info) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int32_t nb = min(NB, n - j0);
-  // this lane's row of the panel below the diagonal block (rows of A, then
-  // the right-hand sides), loaded first so that the loads overlap the
-  // factorisation
-  const int32_t r = j0 + nb + (blk * 4 + wave) * 64 + lane;
-  const bool has = r < n + nrhs;
-  double x[NB];
-#pragma unroll
-  for (int c = 0; c < NB; ++c) x[c] = (has && c < nb) ? *aug_row(A, lda, B, ldb, n, r, j0 + c) : 0.0;
-  // the diagonal block, rows and columns past nb completed by the identity
-  double a[NB];
+  // lanes 0 .. NB - 1: the diagonal block's rows (rows and columns past nb
+  // completed by the identity); the other lanes: rows of the panel below it
+  const bool dg = lane < NB;
+  const int32_t r = j0 + nb + (blk * 4 + wave) * (64 - NB) + (lane - NB);
+  const bool has = !dg && r < n + nrhs;
+  double v[NB];
 #pragma unroll
   for (int c = 0; c < NB; ++c) {
-    double v = 0.0;
-    if (lane < nb && c < nb && c <= lane) v = A[(j0 + lane) + (int64_t)(j0 + c) * lda];
-    if (lane >= nb && lane < NB && c == lane) v = 1.0;
-    a[c] = v;
+    double t = 0.0;
+    if (has && c < nb) t = *aug_row(A, lda, B, ldb, n, r, j0 + c);
+    if (dg && lane < nb && c < nb && c <= lane) t = A[(j0 + lane) + (int64_t)(j0 + c) * lda];
+    if (dg && lane >= nb && c == lane) t = 1.0;
+    v[c] = t;
   }
-  // Every wave factors the block (lane i holds row i; column c broadcast by
-  // readlane) and, with the same broadcasts, solves x L^T = row for its rows.
-  // Lanes above the diagonal (lane < column) run the same updates on
-  // entries of the upper part, which are never read as L and never stored:
-  // no per-lane predicates, whose masks would stay live across the unrolled
-  // loop.
+  // The diagonal lanes above the diagonal (lane < column) run the same
+  // updates on entries of the upper part, which are never read as L and
+  // never stored: no per-lane predicates, whose masks would stay live
+  // across the unrolled loop.
   int32_t bad = -1;
-  chol_step<NB, 0>(a, x, bad);
+  chol_step<NB, 0>(v, bad);
   if (bad >= 0) {
     if (blk == 0 && threadIdx.x == 0) *info = j0 + bad + 1;
     return;
   }
-  if (blk == 0 && wave == 0 && lane < nb) {
+  if (blk == 0 && wave == 0 && dg && lane < nb) {
 #pragma unroll
     for (int c = 0; c < NB; ++c)
-      if (c <= lane) A[(j0 + lane) + (int64_t)(j0 + c) * lda] = a[c];
+      if (c <= lane) A[(j0 + lane) + (int64_t)(j0 + c) * lda] = v[c];
   }
   if (has) {
 #pragma unroll
     for (int c = 0; c < NB; ++c)
-      if (c < nb) *aug_row(A, lda, B, ldb, n, r, j0 + c) = x[c];
+      if (c < nb) *aug_row(A, lda, B, ldb, n, r, j0 + c) = v[c];
   }
 }
 
@@ -384,9 +381,9 @@ rh_status dense_cholesky(int32_t n, double *A, int64_t lda, double *B, int64_t l
                          void *stream, std::string &err) {
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (!B) nrhs = 0;
-  auto panel_blocks = [&](int32_t j0) {
-    const int32_t below = n - j0 - std::min(kNB, n - j0);
-    return std::max(1, (below + nrhs + 255) / 256);
+  auto panel_blocks = [&](int32_t j0) {  // 4 waves of 64 - kNB rows
+    const int32_t below = n - j0 - std::min(kNB, n - j0), per = 4 * (64 - kNB);
+    return std::max(1, (below + nrhs + per - 1) / per);
   };
   hipLaunchKernelGGL(dense_clear, dim3(1), dim3(64), 0, st, dinfo);
   if (n > 0)
