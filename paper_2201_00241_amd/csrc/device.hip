@@ -33,6 +33,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -1598,19 +1599,39 @@ rh_status runner_collect(Runner &r, const DeviceInfo &info, rh_report &rep, std:
 }
 
 // The LDS kernels address the padded vector from LDS address 0, which holds
-// only if they have no static LDS (checked once per kernel).
-rh_status no_static_lds(const void *kernel, int &checked, std::string &err) {
-  if (checked == 0) {
+// only if they have no static LDS (checked once per kernel; threads that
+// race to check it store the same answer).
+rh_status no_static_lds(const void *kernel, std::atomic<int> &checked, std::string &err) {
+  if (checked.load() == 0) {
     hipFuncAttributes fa{};
     HIP_TRY(hipFuncGetAttributes(&fa, kernel));
-    checked = fa.sharedSizeBytes == 0 ? 1 : -1;
+    checked.store(fa.sharedSizeBytes == 0 ? 1 : -1);
   }
-  if (checked < 0) {
+  if (checked.load() < 0) {
     err = "internal: an LDS kernel has static LDS";
     return RH_EDEVICE;
   }
   return RH_OK;
 }
+
+std::mutex g_lds_mu;
+std::map<std::pair<int, const void *>, size_t> g_lds_bound;
+
+}  // namespace
+
+rh_status lds_bound(const void *kernel, size_t bytes, std::string &err) {
+  int device = 0;
+  HIP_TRY(hipGetDevice(&device));
+  std::lock_guard<std::mutex> lock(g_lds_mu);
+  size_t &b = g_lds_bound[{device, kernel}];
+  if (bytes > b) {
+    HIP_TRY(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    b = bytes;
+  }
+  return RH_OK;
+}
+
+namespace {
 
 // Launch the kernel for C directions per workgroup.  The per-kernel attribute
 // calls come first; a launch recorded into a graph makes them beforehand
@@ -1620,7 +1641,7 @@ enum LaunchMode { kAttrsAndLaunch, kAttrsOnly, kLaunchOnly };
 template <int C>
 rh_status launch(bool lds, bool refined, int32_t groups, size_t lds_bytes, hipStream_t s,
                  const LaunchArgs &la, std::string &err, LaunchMode mode = kAttrsAndLaunch) {
-  static int checked_b = 0, checked_r = 0;
+  static std::atomic<int> checked_b{0}, checked_r{0};
   const bool attrs = mode != kLaunchOnly;
   if (mode == kAttrsOnly) {
     if (!lds) return RH_OK;
@@ -1629,7 +1650,8 @@ rh_status launch(bool lds, bool refined, int32_t groups, size_t lds_bytes, hipSt
                               : reinterpret_cast<const void *>(&block_kernel_lds<C>);
       rh_status st = no_static_lds(k, refined ? checked_r : checked_b, err);
       if (st != RH_OK) return st;
-      HIP_TRY(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+      st = lds_bound(k, lds_bytes, err);
+      if (st != RH_OK) return st;
     }
     return RH_OK;
   }
@@ -1639,8 +1661,8 @@ rh_status launch(bool lds, bool refined, int32_t groups, size_t lds_bytes, hipSt
         if (attrs) {
           rh_status st = no_static_lds(reinterpret_cast<const void *>(&refined_kernel_lds<C>), checked_r, err);
           if (st != RH_OK) return st;
-          HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&refined_kernel_lds<C>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+          st = lds_bound(reinterpret_cast<const void *>(&refined_kernel_lds<C>), lds_bytes, err);
+          if (st != RH_OK) return st;
         }
         hipLaunchKernelGGL(refined_kernel_lds<C>, dim3(groups), dim3(kThreadsLds), lds_bytes, s, la);
         HIP_TRY(hipGetLastError());
@@ -1656,8 +1678,8 @@ rh_status launch(bool lds, bool refined, int32_t groups, size_t lds_bytes, hipSt
       if (attrs) {
         rh_status st = no_static_lds(reinterpret_cast<const void *>(&block_kernel_lds<C>), checked_b, err);
         if (st != RH_OK) return st;
-        HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&block_kernel_lds<C>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+        st = lds_bound(reinterpret_cast<const void *>(&block_kernel_lds<C>), lds_bytes, err);
+        if (st != RH_OK) return st;
       }
       hipLaunchKernelGGL(block_kernel_lds<C>, dim3(groups), dim3(kThreadsLds), lds_bytes, s, la);
       HIP_TRY(hipGetLastError());

@@ -837,14 +837,12 @@ rh_status nt_build(Network &net, DevNewton &d, std::string &err) {
       (s = nt_alloc(d, (size_t)a.m_blk * a.m_blk, &w.S, err)) != RH_OK ||
       (s = nt_alloc(d, a.m_blk, &w.amax, err)) != RH_OK)
     return s;
-  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&nt_refactor_run),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)d.lds_bytes));
-  HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&nt_dense_solve),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)d.lds_solve));
+  if ((s = lds_bound(reinterpret_cast<const void *>(&nt_refactor_run), d.lds_bytes, err)) != RH_OK ||
+      (s = lds_bound(reinterpret_cast<const void *>(&nt_dense_solve), d.lds_solve, err)) != RH_OK)
+    return s;
   if ((size_t)net.n_x * sizeof(double) <= kNtLdsY) {
     d.lds_y = (size_t)net.n_x * sizeof(double);
-    HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(&nt_solve_run<true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)d.lds_y));
+    if ((s = lds_bound(reinterpret_cast<const void *>(&nt_solve_run<true>), d.lds_y, err)) != RH_OK) return s;
   }
 
   return RH_OK;

@@ -378,6 +378,11 @@ rh_status device_hvp_batch(Context &ctx, int32_t n, Network *const *nets, const 
                            const int64_t *ldhw, const int32_t *identity_from, rh_precision prec,
                            void *stream, std::string &err);
 rh_status device_set(int32_t device, std::string &err);
+// Raises the dynamic-LDS bound of `kernel` on the current device to `bytes`
+// if it is lower.  The bound belongs to the kernel, not to a network, so it
+// only grows: a network that needs less never cuts the bound another one
+// (on another thread, say) launches with.
+rh_status lds_bound(const void *kernel, size_t bytes, std::string &err);
 // Takes the device address of the fixed scratch array of the allocation-free
 // entry point on `device` (once per device; that device becomes current).
 rh_status device_fixed_scratch_init(int32_t device, std::string &err);

@@ -132,6 +132,54 @@ def test_device_newton_singular_and_non_finite_starts(ctx, rhmod, name):
     host.close()
 
 
+def test_distinct_networks_on_two_threads(ctx, rhmod):
+    """Two networks solved on the device and projected on two host threads at
+    once (the upload's host arrays come from a shared pool; distinct handles
+    may be used from different threads): every state and product equals the
+    same work done one network after the other, bit for bit."""
+    import threading
+
+    grids = [gridgen.perturb_loads(GRIDS["c1"](), seed=91), gridgen.perturb_loads(GRIDS["geo150"](), seed=92)]
+    Ws = [None, None]
+
+    def work(net, i, out):
+        for step in range(3):  # three operating points: loads scaled by 1, 1.01, 1.02
+            Pd, Qd = grids[i].Pd * (1 + 0.01 * step), grids[i].Qd * (1 + 0.01 * step)
+            net.set_loads(Pd, Qd)
+            net.solve_device(1e-13, 30)
+            out.append((net.state(), net.hvp(Ws[i])))
+
+    serial = [[], []]
+    for i in range(2):
+        net = rhmod.Network(ctx, grids[i])
+        Ws[i] = gridgen.directions(net.n_p, min(8, net.n_p), 95 + i)
+        work(net, i, serial[i])
+        net.close()
+    nets = [rhmod.Network(ctx, g) for g in grids]
+    par = [[], []]
+    errs = []
+
+    def run(i):
+        try:
+            work(nets[i], i, par[i])
+        except Exception as e:  # reported below, in the main thread
+            errs.append(e)
+
+    th = [threading.Thread(target=run, args=(i,)) for i in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join(timeout=100)
+    assert not any(t.is_alive() for t in th) and not errs, errs
+    for i in range(2):
+        for (xs, hs), (xp, hp) in zip(serial[i], par[i]):
+            assert np.array_equal(xs, xp) and np.array_equal(hs, hp)
+        assert len(par[i]) == 3
+    _say("two threads: states and products equal to the serial runs")
+    for n in nets:
+        n.close()
+
+
 def test_device_newton_70k_matches_host(ctx, rhmod):
     """The 70,000-bus grid (n_x = 134,999: the solves' vector in global
     memory, LU rows of up to 732 positions in the refactorisation's LDS
