@@ -15,6 +15,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -72,8 +73,12 @@ std::string cache_key(const Network &net, rh_precision prec) {
          (prec == RH_FP32_REFINED ? "refined" : "fp64");
 }
 
+// Networks tuned on several threads read and append the cache one at a time.
+std::mutex g_cache_mu;
+
 // The last line of the cache with this key, if any.
 bool cache_read(const std::string &key, rh_tile &t) {
+  std::lock_guard<std::mutex> lock(g_cache_mu);
   const std::string path = cache_path();
   if (path.empty()) return false;
   std::ifstream f(path);
@@ -95,6 +100,7 @@ bool cache_read(const std::string &key, rh_tile &t) {
 }
 
 void cache_write(const std::string &key, const rh_tile &t) {
+  std::lock_guard<std::mutex> lock(g_cache_mu);
   const std::string path = cache_path();
   if (path.empty()) return;
   // create the directories on the way (best effort: a failure only skips the cache)
