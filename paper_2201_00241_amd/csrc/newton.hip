@@ -678,8 +678,14 @@ struct DevNewton {
   size_t lds_y = 0;  // the vector in LDS for the solves' runs of levels (0: too large, global memory)
 };
 
-// A level is wide with at least this many rows.
-constexpr int32_t kWideRows = 256;
+// A level is wide with at least this many rows: it gets a launch of its own
+// (a wave per row over many workgroups) instead of rounds of the one
+// workgroup's 16 waves, each row a round.  Below that the launch costs more
+// than the rounds: from 64 rows for the refactorisation, whose rows take
+// many elimination steps, from 256 for the solves, whose rows take one
+// short dot product.
+constexpr int32_t kWideRows = 64;
+constexpr int32_t kWideSolveRows = 256;
 // Largest vector the solves' runs of levels keep in LDS.
 constexpr size_t kNtLdsY = 156 * 1024;
 
@@ -892,13 +898,13 @@ rh_status nt_solve_kernels(DevNewton &d, std::string &err) {
   auto levels = [&](const std::vector<int32_t> &rows, int32_t upper) {
     const int32_t nlev = (int32_t)rows.size();
     for (int32_t l = 0; l < nlev;) {
-      if (rows[l] >= kWideRows) {
+      if (rows[l] >= kWideSolveRows) {
         hipLaunchKernelGGL(nt_solve_level, dim3((rows[l] + 3) / 4), dim3(256), 0, nullptr, d.args, l, upper);
         ++l;
         continue;
       }
       int32_t l1 = l;
-      while (l1 < nlev && rows[l1] < kWideRows) ++l1;
+      while (l1 < nlev && rows[l1] < kWideSolveRows) ++l1;
       if (d.lds_y)
         hipLaunchKernelGGL(nt_solve_run<true>, dim3(1), dim3(kNtThreads), d.lds_y, nullptr, d.args, l, l1, upper);
       else
